@@ -1,0 +1,321 @@
+"""Oracle: plain FP64 CPU implementation of the mixed-frame relativistic SHDOM
+source iteration (Tominaga, Shibata & Blinnikov 2015).
+
+TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the CPU
+baseline leg of the benchmark may import this package.  It shares no code with
+the HIP library: its arithmetic lives in ``rrt_oracle.c`` (plain loops, FP64)
+and the iteration control (Lambda iteration, Ng acceleration, the four-stage
+time scheme of Appendix A) is written out below in Python.
+
+A problem is described by the plain dictionary that
+``paper_1507_05141_amd.workloads`` produces (sizes, group edges, fields); the
+oracle derives every table it needs (Gauss-Legendre ordinates, real spherical
+harmonics, group centres, Compton tables) with its own routines.
+"""
+import ctypes
+import math
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rrt_oracle.c")
+_LIB = os.path.join(_HERE, "librrt_oracle.so")
+_lib = None
+
+
+def build(force=True):
+    """Compile the oracle with gcc (FP64, OpenMP over independent loops)."""
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c99", "-o", _LIB, _SRC, "-lm"]
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        subprocess.check_call(cmd)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+            build()
+        _lib = ctypes.CDLL(_LIB)
+    return _lib
+
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class _Problem(ctypes.Structure):
+    _fields_ = [
+        ("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+        ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double),
+        ("nmu", ctypes.c_int), ("nphi", ctypes.c_int), ("lmax", ctypes.c_int),
+        ("ng", ctypes.c_int), ("grey", ctypes.c_int),
+        ("edges", _dp), ("centres", _dp),
+        ("compton", ctypes.c_int), ("kn_s", _dp), ("kn_p", _dp),
+        ("kappa", _dp), ("sigma", _dp), ("bnu", _dp), ("beta", _dp),
+        ("bc_bot", _dp), ("bc_top", _dp),
+        ("mu", _dp), ("wmu", _dp), ("Y", _dp),
+    ]
+
+
+def _ptr(a):
+    if a is None:
+        return ctypes.cast(None, _dp)
+    assert a.dtype == np.float64 and a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a):
+    return None if a is None else np.ascontiguousarray(a, dtype=np.float64)
+
+
+# ---------------------------------------------------------------------------
+# tables
+# ---------------------------------------------------------------------------
+
+def gauss_legendre(n):
+    """Gauss-Legendre nodes (ascending) and weights on [-1, 1]."""
+    x = np.zeros(n)
+    w = np.zeros(n)
+    _load().or_gauss_legendre(n, _ptr(x), _ptr(w))
+    return x, w
+
+
+def sh_eval(lmax, mu, phi):
+    """Real orthonormal spherical harmonics (Eq. 9) at one direction."""
+    Y = np.zeros((lmax + 1) ** 2)
+    _load().or_sh_eval(ctypes.c_int(lmax), ctypes.c_double(mu), ctypes.c_double(phi), _ptr(Y))
+    return Y
+
+
+def group_centres(edges, log_centres):
+    """Geometric centres for logarithmic bins, arithmetic for linear ones."""
+    e = np.asarray(edges, dtype=np.float64)
+    return np.sqrt(e[:-1] * e[1:]) if log_centres else 0.5 * (e[:-1] + e[1:])
+
+
+def compton_cold(edges, centres, mec2, lmax):
+    """Klein-Nishina group-to-group Legendre tables for electrons at rest."""
+    G = len(centres)
+    s = np.zeros(G)
+    p = np.zeros((lmax + 1, G, G))
+    e = _f64(edges)
+    c = _f64(centres)
+    _load().or_compton_cold(G, _ptr(e), _ptr(c), ctypes.c_double(mec2), lmax, _ptr(s), _ptr(p))
+    return s, p
+
+
+# ---------------------------------------------------------------------------
+# problem
+# ---------------------------------------------------------------------------
+
+class Oracle:
+    """FP64 reference solver for one problem description (see module doc)."""
+
+    def __init__(self, spec):
+        self.spec = spec
+        self.nx, self.ny, self.nz = spec["nx"], spec["ny"], spec["nz"]
+        self.P = self.nx * self.ny * self.nz
+        self.nmu, self.nphi, self.lmax = spec["nmu"], spec["nphi"], spec["lmax"]
+        self.K = self.nmu * self.nphi
+        self.NL = (self.lmax + 1) ** 2
+        self.grey = spec.get("edges") is None
+        if self.grey:
+            self.G = 1
+            self.edges = np.array([0.0, 1.0])
+            self.centres = np.array([1.0])
+        else:
+            self.edges = _f64(spec["edges"])
+            self.G = len(self.edges) - 1
+            self.centres = group_centres(self.edges, spec.get("log_centres", True))
+        G, P, K = self.G, self.P, self.K
+        self.compton = spec.get("scatter", "thomson") == "compton"
+        if self.compton:
+            self.kn_s, self.kn_p = compton_cold(self.edges, self.centres, spec["mec2"], self.lmax)
+        else:
+            self.kn_s, self.kn_p = None, None
+        self.mu, self.wmu = gauss_legendre(self.nmu)
+        self.Y = np.zeros((K, self.NL))
+        _load().or_sh_table(self.lmax, self.nmu, self.nphi, _ptr(self.mu), _ptr(self.Y))
+        self.kappa = _f64(np.broadcast_to(spec["kappa"], (P, G)))
+        self.sigma = _f64(np.broadcast_to(spec["sigma"], (P,)))
+        self.bnu = _f64(np.broadcast_to(spec["bnu"], (P, G)))
+        self.beta = _f64(spec.get("beta"))
+        self.bc_bot = _f64(spec.get("bc_bot"))
+        self.bc_top = _f64(spec.get("bc_top"))
+        s = self._s = _Problem()
+        s.nx, s.ny, s.nz = self.nx, self.ny, self.nz
+        s.lx, s.ly, s.lz = spec["lx"], spec["ly"], spec["lz"]
+        s.nmu, s.nphi, s.lmax = self.nmu, self.nphi, self.lmax
+        s.ng, s.grey = G, int(self.grey)
+        s.edges, s.centres = _ptr(self.edges), _ptr(self.centres)
+        s.compton = int(self.compton)
+        s.kn_s, s.kn_p = _ptr(self.kn_s), _ptr(self.kn_p)
+        s.kappa, s.sigma, s.bnu, s.beta = _ptr(self.kappa), _ptr(self.sigma), _ptr(self.bnu), _ptr(self.beta)
+        s.bc_bot, s.bc_top = _ptr(self.bc_bot), _ptr(self.bc_top)
+        s.mu, s.wmu, s.Y = _ptr(self.mu), _ptr(self.wmu), _ptr(self.Y)
+        self._ref = ctypes.byref(s)
+
+    # shapes
+    def sh_shape(self):
+        return (self.P, self.G, self.NL)
+
+    def lab_shape(self):
+        return (self.K, self.G, self.P)
+
+    def co_shape(self):
+        return (self.P, self.G, self.K)
+
+    # --- single steps ------------------------------------------------------
+    def source(self, I_lm):
+        I_lm = _f64(I_lm)
+        S = np.zeros(self.sh_shape())
+        _load().or_source(self._ref, _ptr(I_lm), _ptr(S))
+        return S
+
+    def sh2do(self, S_lm):
+        S_lm = _f64(S_lm)
+        out = np.zeros(self.co_shape())
+        _load().or_sh2do(self._ref, _ptr(S_lm), _ptr(out))
+        return out
+
+    def do2sh(self, I0):
+        I0 = _f64(I0)
+        out = np.zeros(self.sh_shape())
+        _load().or_do2sh(self._ref, _ptr(I0), _ptr(out))
+        return out
+
+    def boost(self, S0, I_prev=None, inv_cdt=0.0):
+        S0 = _f64(S0)
+        I_prev = _f64(I_prev)
+        St = np.zeros(self.lab_shape())
+        Xt = np.zeros(self.lab_shape())
+        _load().or_boost(self._ref, _ptr(S0), _ptr(I_prev), ctypes.c_double(inv_cdt), _ptr(St), _ptr(Xt))
+        return St, Xt
+
+    def trace(self, St, Xt):
+        St, Xt = _f64(St), _f64(Xt)
+        I = np.zeros(self.lab_shape())
+        _load().or_trace(self._ref, _ptr(St), _ptr(Xt), _ptr(I))
+        return I
+
+    def unboost(self, I_lab):
+        I_lab = _f64(I_lab)
+        out = np.zeros(self.co_shape())
+        _load().or_unboost(self._ref, _ptr(I_lab), _ptr(out))
+        return out
+
+    def fold(self, I_lab):
+        return self.do2sh(self.unboost(I_lab))
+
+    def residual(self, S_old, S_new):
+        r = np.zeros(self.G)
+        _load().or_residual(self._ref, _ptr(_f64(S_old)), _ptr(_f64(S_new)), _ptr(r))
+        return r
+
+    def moments_lab(self, I_lab):
+        I_lab = _f64(I_lab)
+        J = np.zeros((self.P, self.G))
+        H = np.zeros((self.P, self.G, 3))
+        Kt = np.zeros((self.P, self.G, 6))
+        _load().or_moments_lab(self._ref, _ptr(I_lab), _ptr(J), _ptr(H), _ptr(Kt))
+        return J, H, Kt
+
+    def moments_comoving(self, I_lm):
+        I_lm = _f64(I_lm)
+        J = np.zeros((self.P, self.G))
+        H = np.zeros((self.P, self.G, 3))
+        Kt = np.zeros((self.P, self.G, 6))
+        _load().or_moments_comoving(self._ref, _ptr(I_lm), _ptr(J), _ptr(H), _ptr(Kt))
+        return J, H, Kt
+
+    def sweep(self, S_lm, I_prev=None, inv_cdt=0.0):
+        """One source iteration: SH->DO, boost + time terms, ray trace, inverse
+        boost, DO->SH, new source, residual.  Returns (I_lab, I_lm, S_new, r)."""
+        S_lm = _f64(S_lm)
+        I_prev = _f64(I_prev)
+        I_lab = np.zeros(self.lab_shape())
+        I_lm = np.zeros(self.sh_shape())
+        S_new = np.zeros(self.sh_shape())
+        r = np.zeros(self.G)
+        rc = _load().or_sweep(self._ref, _ptr(S_lm), _ptr(I_prev), ctypes.c_double(inv_cdt),
+                              _ptr(I_lab), _ptr(I_lm), _ptr(S_new), _ptr(r))
+        if rc != 0:
+            raise MemoryError("oracle sweep could not allocate its work arrays")
+        return I_lab, I_lm, S_new, r
+
+    # --- iteration control -------------------------------------------------
+    def initial_source(self, I_in=None):
+        """Source from the comoving SH moments of a lab intensity (0 -> thermal)."""
+        if I_in is None:
+            return self.source(np.zeros(self.sh_shape()))
+        return self.source(self.fold(I_in))
+
+    @staticmethod
+    def ng_extrapolate(chain):
+        """Ng acceleration in the two-coefficient form of Auer (1987) from the
+        last four members of a chain of Lambda iterates (newest last)."""
+        s3, s2, s1, s0 = chain[-4], chain[-3], chain[-2], chain[-1]
+        d0, d1, d2 = s0 - s1, s1 - s2, s2 - s3
+        q1, q2 = (d0 - d1).ravel(), (d0 - d2).ravel()
+        d0r = d0.ravel()
+        a11, a12, a22 = q1 @ q1, q1 @ q2, q2 @ q2
+        b1, b2 = d0r @ q1, d0r @ q2
+        det = a11 * a22 - a12 * a12
+        if not (det > 1e-14 * a11 * a22) or not np.isfinite(det):
+            return None
+        a = (b1 * a22 - b2 * a12) / det
+        b = (b2 * a11 - b1 * a12) / det
+        return (1.0 - a - b) * s0 + a * s1 + b * s2
+
+    def solve(self, tol=1e-8, max_iter=200, use_ng=True, I_prev=None, inv_cdt=0.0, I_init=None):
+        """Lambda (Picard) iteration of the static problem (Eq. 1, or Eq. 4 with
+        the implicit time terms) to max_g residual < tol.  Returns a dict with
+        the lab intensity of the last sweep, its comoving SH moments, the final
+        source, the iteration count and the residual."""
+        S = self.initial_source(I_init if I_init is not None else I_prev)
+        chain = [S]
+        it = 0
+        r = np.full(self.G, np.inf)
+        I_lab = I_lm = None
+        while it < max_iter:
+            it += 1
+            I_lab, I_lm, S_new, r = self.sweep(S, I_prev, inv_cdt)
+            S = S_new
+            if float(np.max(r)) < tol:
+                break
+            chain.append(S)
+            if use_ng and len(chain) == 4:
+                Sx = self.ng_extrapolate(chain)
+                if Sx is not None:
+                    S = Sx
+                chain = [S]
+        return {"I_lab": I_lab, "I_lm": I_lm, "S": S, "iters": it, "resid": float(np.max(r))}
+
+    def advance(self, I, dt, nsteps=1, scheme="rk4", tol=1e-10, max_iter=200, use_ng=False):
+        """Time steps of length dt (c = 1).  scheme 'rk4': the four implicit
+        stages of Appendix A (Eqs. A1-A8); 'euler': one implicit stage."""
+        I = np.zeros(self.lab_shape()) if I is None else _f64(I).copy()
+        last = None
+        for _ in range(nsteps):
+            if scheme == "euler":
+                last = self.solve(tol, max_iter, use_ng, I_prev=I, inv_cdt=1.0 / dt)
+                I = last["I_lab"].copy()
+                continue
+            acc = np.zeros_like(I)
+            Iin = I
+            for frac, coef in ((1.0 / 6.0, 3.0), (1.0 / 3.0, 1.5), (1.0 / 3.0, 3.0), (1.0 / 6.0, None)):
+                last = self.solve(tol, max_iter, use_ng, I_prev=Iin, inv_cdt=1.0 / (frac * dt))
+                d = last["I_lab"] - Iin
+                acc += d
+                if coef is not None:
+                    Iin = I + coef * d
+            I = I + acc
+        return I, last
+
+
+def kn_total_closed_form(x):
+    """Klein-Nishina total cross-section / sigma_T (Rybicki & Lightman Eq. 7.5)."""
+    return 0.75 * ((1 + x) / x ** 3 * (2 * x * (1 + x) / (1 + 2 * x) - math.log(1 + 2 * x))
+                   + math.log(1 + 2 * x) / (2 * x) - (1 + 3 * x) / (1 + 2 * x) ** 2)

@@ -1,0 +1,771 @@
+/*
+ * Oracle for the mixed-frame relativistic SHDOM source iteration of
+ * Tominaga, Shibata & Blinnikov (2015), "Time-dependent multi-group
+ * multidimensional relativistic radiative transfer code based on SHDOM".
+ *
+ * TEST INFRASTRUCTURE ONLY.  This is a plain, slow, FP64 CPU implementation
+ * written straight from the paper's equations, used to check the HIP library.
+ * Only the test-suite, the smoke check and the CPU-baseline leg of the
+ * benchmark may load it.  It shares no code, header, table or constant
+ * generator with the HIP library.
+ *
+ * Where the paper defers to the SHDOM papers (Evans 1998; Pincus & Evans 2009)
+ * and to de la Cruz Rodriguez & Piskunov (2013) for details it does not print,
+ * the reading followed here is the one documented with the repository's design
+ * notes (grid, ordinates, interpolation, Bezier derivative rule, boundaries).
+ *
+ * Array layouts (point index p = (z*ny + y)*nx + x, ordinate k = a*nphi + b):
+ *   SH arrays            [P][G][NLM]          (q = l*l + l + m)
+ *   comoving DO arrays   [P][G][K]
+ *   lab DO arrays        [K][G][P]
+ *   fields               kappa, bnu [P][G]; sigma [P]; beta [P][3]
+ *   z-boundary inflow    [K][G][ny][nx]
+ *
+ * Functions whose result is not pinned by a test against something other than
+ * this file say so in their comment.
+ */
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+
+#ifndef M_PI
+#define M_PI 3.14159265358979323846
+#endif
+
+typedef struct {
+    /* grid: x, y periodic with nx, ny points; z has nz points on [0, lz] */
+    int nx, ny, nz;
+    double lx, ly, lz;
+    /* angular mesh and spherical-harmonic order */
+    int nmu, nphi, lmax;
+    /* frequency groups */
+    int ng;
+    int grey;               /* 1: one frequency-integrated group */
+    const double *edges;    /* [ng+1] */
+    const double *centres;  /* [ng]   */
+    /* scattering: 0 = Thomson, 1 = Compton on electrons at rest */
+    int compton;
+    const double *kn_s;     /* [ng]  sigma_KN(nu_i) / sigma_T          */
+    const double *kn_p;     /* [lmax+1][ng][ng]  Legendre moment p_l^{i->j} */
+    /* fields */
+    const double *kappa;    /* [P][ng] */
+    const double *sigma;    /* [P]     */
+    const double *bnu;      /* [P][ng] */
+    const double *beta;     /* [P][3] or NULL */
+    const double *bc_bot;   /* [K][ng][ny][nx] or NULL */
+    const double *bc_top;   /* [K][ng][ny][nx] or NULL */
+    /* ordinate tables */
+    const double *mu;       /* [nmu] Gauss-Legendre nodes, ascending */
+    const double *wmu;      /* [nmu] Gauss-Legendre weights          */
+    const double *Y;        /* [K][NLM] real SH at the ordinates     */
+} or_problem;
+
+static int nlm_of(int lmax) { return (lmax + 1) * (lmax + 1); }
+static long npts(const or_problem *pr) { return (long)pr->nx * pr->ny * pr->nz; }
+static int nord(const or_problem *pr) { return pr->nmu * pr->nphi; }
+
+/* ------------------------------------------------------------------------ */
+/* Quadrature and spherical harmonics (Eq. 9: real orthonormal Y_lm)         */
+/* ------------------------------------------------------------------------ */
+
+/* Gauss-Legendre nodes (ascending) and weights on [-1, 1] by Newton iteration
+   on the three-term Legendre recurrence. */
+int or_gauss_legendre(int n, double *x, double *w)
+{
+    if (n < 1) return -1;
+    for (int i = 0; i < n; i++) {
+        double z = cos(M_PI * (i + 0.75) / (n + 0.5));
+        double pn = 0.0, dp = 1.0;
+        for (int it = 0; it < 200; it++) {
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; k++) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            if (n == 1) { p1 = z; p0 = 1.0; }
+            pn = p1;
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+            double dz = pn / dp;
+            z -= dz;
+            if (fabs(dz) < 1e-16) break;
+        }
+        {   /* derivative at the converged root */
+            double p0 = 1.0, p1 = z;
+            for (int k = 2; k <= n; k++) {
+                double p2 = ((2.0 * k - 1.0) * z * p1 - (k - 1.0) * p0) / k;
+                p0 = p1;
+                p1 = p2;
+            }
+            dp = n * (z * p1 - p0) / (z * z - 1.0);
+        }
+        x[n - 1 - i] = z;
+        w[n - 1 - i] = 2.0 / ((1.0 - z * z) * dp * dp);
+    }
+    return 0;
+}
+
+/* Real orthonormal spherical harmonics at (mu, phi), all l <= lmax, index
+   q = l*l + l + m.  Y_lm = N_l^|m| P_l^|m|(mu) * {sqrt2 cos(m phi), 1,
+   sqrt2 sin(|m| phi)} for m > 0, m = 0, m < 0, associated Legendre functions
+   without the Condon-Shortley phase, N_l^m = sqrt((2l+1)/(4 pi) (l-m)!/(l+m)!). */
+void or_sh_eval(int lmax, double mu, double phi, double *Y)
+{
+    int L = lmax;
+    double *P = (double *)malloc(sizeof(double) * (L + 1) * (L + 1));
+    double s = sqrt(fmax(0.0, 1.0 - mu * mu));
+    for (int m = 0; m <= L; m++) {
+        double pmm = 1.0;
+        for (int i = 1; i <= m; i++) pmm *= (2.0 * i - 1.0) * s;
+        P[m * (L + 1) + m] = pmm;
+        if (m + 1 <= L) P[(m + 1) * (L + 1) + m] = (2.0 * m + 1.0) * mu * pmm;
+        for (int l = m + 2; l <= L; l++)
+            P[l * (L + 1) + m] = ((2.0 * l - 1.0) * mu * P[(l - 1) * (L + 1) + m]
+                                  - (l + m - 1.0) * P[(l - 2) * (L + 1) + m]) / (l - m);
+    }
+    for (int l = 0; l <= L; l++) {
+        for (int m = 0; m <= l; m++) {
+            double ratio = 1.0;               /* (l-m)!/(l+m)! */
+            for (int i = l - m + 1; i <= l + m; i++) ratio /= (double)i;
+            double N = sqrt((2.0 * l + 1.0) / (4.0 * M_PI) * ratio);
+            double v = N * P[l * (L + 1) + m];
+            if (m == 0) {
+                Y[l * l + l] = v;
+            } else {
+                Y[l * l + l + m] = v * sqrt(2.0) * cos(m * phi);
+                Y[l * l + l - m] = v * sqrt(2.0) * sin(m * phi);
+            }
+        }
+    }
+    free(P);
+}
+
+/* Y[k][q] at every ordinate k = a*nphi + b, phi_b = 2 pi b / nphi. */
+void or_sh_table(int lmax, int nmu, int nphi, const double *mu, double *Y)
+{
+    int nl = nlm_of(lmax);
+    for (int a = 0; a < nmu; a++)
+        for (int b = 0; b < nphi; b++)
+            or_sh_eval(lmax, mu[a], 2.0 * M_PI * b / nphi, Y + (long)(a * nphi + b) * nl);
+}
+
+static void ordinate_dir(const or_problem *pr, int k, double n[3])
+{
+    int a = k / pr->nphi, b = k % pr->nphi;
+    double mu = pr->mu[a], phi = 2.0 * M_PI * b / pr->nphi;
+    double st = sqrt(fmax(0.0, 1.0 - mu * mu));
+    n[0] = st * cos(phi);
+    n[1] = st * sin(phi);
+    n[2] = mu;
+}
+
+static double ordinate_weight(const or_problem *pr, int k)
+{
+    return pr->wmu[k / pr->nphi] * 2.0 * M_PI / pr->nphi;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Compton tables, Eqs. 13-14 (Klein-Nishina, electrons at rest)             */
+/* ------------------------------------------------------------------------ */
+
+static double legendre_p(int l, double x)
+{
+    if (l == 0) return 1.0;
+    double p0 = 1.0, p1 = x;
+    for (int k = 2; k <= l; k++) {
+        double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+    }
+    return p1;
+}
+
+/* Klein-Nishina differential cross-section in units of r0^2 for a photon of
+   energy x = h nu / (m_e c^2) scattered by angle with cosine mu.  The ratio
+   nu1/nu enters squared (Rybicki & Lightman Eq. 7.4); the single power printed
+   in Eq. 14 does not integrate to the Klein-Nishina total cross-section. */
+static double kn_dsdo(double x, double mu)
+{
+    double eps = 1.0 / (1.0 + x * (1.0 - mu));
+    return 0.5 * eps * eps * (1.0 / eps + eps - (1.0 - mu * mu));
+}
+
+/* integral of f(mu) = kn_dsdo(x,mu) * P_l(mu) over [a, b] by 48-point Gauss-Legendre */
+static double kn_band_integral(double x, int l, double a, double b, const double *gx, const double *gw, int ng)
+{
+    double h = 0.5 * (b - a), c = 0.5 * (b + a), s = 0.0;
+    for (int i = 0; i < ng; i++) {
+        double mu = c + h * gx[i];
+        s += gw[i] * kn_dsdo(x, mu) * legendre_p(l, mu);
+    }
+    return s * h;
+}
+
+/* Group-to-group Compton tables for electrons at rest (multi-group treatment
+   of the Klein-Nishina kernel, with photons at the bin-centre frequency):
+     s[i]        = sigma_KN(nu_i) / sigma_T
+     p[l][i][j]  = (2l+1)/2 * integral over mu of p^{i->j}(mu) P_l(mu),
+     p^{i->j}(mu) = 4 pi (dsigma/dOmega)(nu_i, mu) / sigma_KN(nu_i) when the
+                    scattered frequency nu1(mu) = nu_i / (1 + x (1 - mu)) falls
+                    in bin j, else 0.
+   mec2 is the electron rest energy in the units of the edges. */
+int or_compton_cold(int ng, const double *edges, const double *centres, double mec2,
+                    int lmax, double *s, double *p)
+{
+    const int NQ = 48;
+    double gx[48], gw[48];
+    or_gauss_legendre(NQ, gx, gw);
+    for (int i = 0; i < ng; i++) {
+        double nu = centres[i], x = nu / mec2;
+        /* total cross-section over 8 equal pieces of [-1, 1] */
+        double tot = 0.0;
+        for (int piece = 0; piece < 8; piece++)
+            tot += kn_band_integral(x, 0, -1.0 + piece * 0.25, -1.0 + (piece + 1) * 0.25, gx, gw, NQ);
+        tot *= 2.0 * M_PI;                        /* in r0^2 */
+        s[i] = tot / (8.0 * M_PI / 3.0);
+        for (int j = 0; j < ng; j++) {
+            /* scattering-cosine range mapping into [edges[j], edges[j+1]) */
+            double lo, hi;
+            double e0 = edges[j], e1 = edges[j + 1];
+            lo = (e0 > 0.0) ? 1.0 - (nu / e0 - 1.0) / x : -1.0e300;
+            hi = (e1 > 0.0) ? 1.0 - (nu / e1 - 1.0) / x : -1.0e300;
+            if (lo < -1.0) lo = -1.0;
+            if (hi > 1.0) hi = 1.0;
+            for (int l = 0; l <= lmax; l++) {
+                double v = 0.0;
+                if (hi > lo) {
+                    /* split the band in 4 pieces for accuracy */
+                    for (int piece = 0; piece < 4; piece++) {
+                        double a = lo + (hi - lo) * piece / 4.0, b = lo + (hi - lo) * (piece + 1) / 4.0;
+                        v += kn_band_integral(x, l, a, b, gx, gw, NQ);
+                    }
+                    v *= (2.0 * l + 1.0) / 2.0 * 4.0 * M_PI / tot;
+                }
+                p[((long)l * ng + i) * ng + j] = v;
+            }
+        }
+    }
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* S1: source function in SH space (Eqs. 10-12 and the multi-group kernel)   */
+/* ------------------------------------------------------------------------ */
+
+static double chi0_of(const or_problem *pr, long p, int g)
+{
+    double s = pr->compton ? pr->kn_s[g] : 1.0;
+    return pr->kappa[p * pr->ng + g] + pr->sigma[p] * s;
+}
+
+/* S_lm = omega chi_l/(2l+1) I_lm + T_lm with the Thomson Legendre moments
+   chi_l = (1, 0, 1/2, 0, ...) of 3/4 (1 + cos^2), or, for Compton,
+   S_lm^j = sigma/chi_j sum_i s_i (nu_j dnu_i)/(nu_i dnu_j) p_l^{i->j}/(2l+1) I_lm^i,
+   plus the isotropic thermal term T_00 = sqrt(4 pi) kappa B / chi. */
+void or_source(const or_problem *pr, const double *I_lm, double *S_lm)
+{
+    long P = npts(pr);
+    int G = pr->ng, NL = nlm_of(pr->lmax);
+    #pragma omp parallel for
+    for (long p = 0; p < P; p++) {
+        for (int j = 0; j < G; j++) {
+            double chi = chi0_of(pr, p, j);
+            double *S = S_lm + (p * G + j) * NL;
+            if (chi <= 0.0) {
+                for (int q = 0; q < NL; q++) S[q] = 0.0;
+                continue;
+            }
+            for (int l = 0; l <= pr->lmax; l++) {
+                for (int m = -l; m <= l; m++) {
+                    int q = l * l + l + m;
+                    double v = 0.0;
+                    if (!pr->compton) {
+                        double chil = (l == 0) ? 1.0 : (l == 2 ? 0.5 : 0.0);
+                        v = pr->sigma[p] / chi * chil / (2.0 * l + 1.0) * I_lm[(p * G + j) * NL + q];
+                    } else {
+                        for (int i = 0; i < G; i++) {
+                            double dnu_i = pr->edges[i + 1] - pr->edges[i];
+                            double dnu_j = pr->edges[j + 1] - pr->edges[j];
+                            double w = pr->kn_s[i] * (pr->centres[j] * dnu_i) / (pr->centres[i] * dnu_j)
+                                       * pr->kn_p[((long)l * G + i) * G + j] / (2.0 * l + 1.0);
+                            v += w * I_lm[(p * G + i) * NL + q];
+                        }
+                        v *= pr->sigma[p] / chi;
+                    }
+                    S[q] = v;
+                }
+            }
+            S[0] += sqrt(4.0 * M_PI) * pr->kappa[p * G + j] * pr->bnu[p * G + j] / chi;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* S2 and S6: spherical harmonics <-> discrete ordinates                     */
+/* ------------------------------------------------------------------------ */
+
+/* S0(p, g, j) = sum_q Y[j][q] S_q(p, g) */
+void or_sh2do(const or_problem *pr, const double *S_lm, double *S0)
+{
+    long P = npts(pr);
+    int G = pr->ng, NL = nlm_of(pr->lmax), K = nord(pr);
+    #pragma omp parallel for
+    for (long p = 0; p < P; p++)
+        for (int g = 0; g < G; g++)
+            for (int k = 0; k < K; k++) {
+                double v = 0.0;
+                for (int q = 0; q < NL; q++) v += pr->Y[(long)k * NL + q] * S_lm[(p * G + g) * NL + q];
+                S0[(p * G + g) * K + k] = v;
+            }
+}
+
+/* I_q(p, g) = sum_j w_j Y[j][q] I0(p, g, j) */
+void or_do2sh(const or_problem *pr, const double *I0, double *I_lm)
+{
+    long P = npts(pr);
+    int G = pr->ng, NL = nlm_of(pr->lmax), K = nord(pr);
+    #pragma omp parallel for
+    for (long p = 0; p < P; p++)
+        for (int g = 0; g < G; g++)
+            for (int q = 0; q < NL; q++) {
+                double v = 0.0;
+                for (int k = 0; k < K; k++)
+                    v += ordinate_weight(pr, k) * pr->Y[(long)k * NL + q] * I0[(p * G + g) * K + k];
+                I_lm[(p * G + g) * NL + q] = v;
+            }
+}
+
+/* ------------------------------------------------------------------------ */
+/* Remap between frames (Eqs. 7-8 and the Lorentz invariants I/nu^3, chi nu) */
+/* ------------------------------------------------------------------------ */
+
+/* Bilinear value in (mu, phi) of F given at the ordinates (F[k*stride]).
+   Beyond the outermost mu ring the value goes linearly to a pole value at
+   mu = -1 or +1, equal to the azimuthal mean of that ring. */
+static double angle_interp(const or_problem *pr, const double *F, long stride, const double n[3])
+{
+    int nmu = pr->nmu, nphi = pr->nphi;
+    double mus = n[2];
+    if (mus > 1.0) mus = 1.0;
+    if (mus < -1.0) mus = -1.0;
+    double phis = atan2(n[1], n[0]);
+    if (phis < 0.0) phis += 2.0 * M_PI;
+    double t = phis / (2.0 * M_PI / nphi);
+    double tf = floor(t);
+    double fphi = t - tf;
+    int b0 = ((int)tf) % nphi;
+    if (b0 < 0) b0 += nphi;
+    int b1 = (b0 + 1) % nphi;
+#define RING(a) ((1.0 - fphi) * F[(long)((a) * nphi + b0) * stride] + fphi * F[(long)((a) * nphi + b1) * stride])
+    if (mus < pr->mu[0]) {
+        double pole = 0.0;
+        for (int b = 0; b < nphi; b++) pole += F[(long)b * stride];
+        pole /= nphi;
+        double w = (mus + 1.0) / (pr->mu[0] + 1.0);
+        return (1.0 - w) * pole + w * RING(0);
+    }
+    if (mus > pr->mu[nmu - 1]) {
+        double pole = 0.0;
+        for (int b = 0; b < nphi; b++) pole += F[(long)((nmu - 1) * nphi + b) * stride];
+        pole /= nphi;
+        double w = (mus - pr->mu[nmu - 1]) / (1.0 - pr->mu[nmu - 1]);
+        return (1.0 - w) * RING(nmu - 1) + w * pole;
+    }
+    int a = 0;
+    while (a < nmu - 2 && mus > pr->mu[a + 1]) a++;
+    double w = (mus - pr->mu[a]) / (pr->mu[a + 1] - pr->mu[a]);
+    return (1.0 - w) * RING(a) + w * RING(a + 1);
+#undef RING
+}
+
+/* Linear interpolation in ln(nu) of values v[g] given at the group centres.
+   zero_outside = 1 (intensity invariants): two ghost centres, the mirror images
+   of the outer centres in ln(nu) about the outer edges, carry the value 0 and
+   the value is 0 beyond them (when the lowest edge is 0 the lowest value is held
+   down to nu = 0).  zero_outside = 0 (opacities): the outer values are held. */
+static double freq_interp(const or_problem *pr, const double *v, long stride, double nu, int zero_outside)
+{
+    int G = pr->ng;
+    double x = log(nu);
+    double c0 = log(pr->centres[0]), cN = log(pr->centres[G - 1]);
+    if (!zero_outside) {
+        if (x <= c0) return v[0];
+        if (x >= cN) return v[(long)(G - 1) * stride];
+    } else {
+        if (x < c0) {
+            if (pr->edges[0] <= 0.0) return v[0];
+            double cg = 2.0 * log(pr->edges[0]) - c0;
+            if (x <= cg) return 0.0;
+            return v[0] * (x - cg) / (c0 - cg);
+        }
+        if (x >= cN) {
+            double cg = 2.0 * log(pr->edges[G]) - cN;
+            if (x >= cg) return 0.0;
+            return v[(long)(G - 1) * stride] * (cg - x) / (cg - cN);
+        }
+    }
+    int g = 0;
+    while (g < G - 2 && x >= log(pr->centres[g + 1])) g++;
+    double cl = log(pr->centres[g]), ch = log(pr->centres[g + 1]);
+    double w = (x - cl) / (ch - cl);
+    return (1.0 - w) * v[(long)g * stride] + w * v[(long)(g + 1) * stride];
+}
+
+static int has_motion(const or_problem *pr, long p)
+{
+    if (!pr->beta) return 0;
+    const double *b = pr->beta + 3 * p;
+    return !(b[0] == 0.0 && b[1] == 0.0 && b[2] == 0.0);
+}
+
+/* S3: lab-frame source and extinction on the lab ordinates, plus the implicit
+   time terms of Eqs. 5-6:  chi~ = chi_lab + 1/(c dt),
+   S~ = (chi_lab S_lab + I_prev/(c dt)) / chi~   (c = 1, inv_cdt = 1/(c dt)).
+   Comoving -> lab: nu0 = Gamma nu (1 - beta.n) (Eq. 7), n0 from Eq. 8, and
+   S_lab(nu) = nu^3 [S0/nu0^3](n0, nu/D), chi_lab = chi0(nu/D)/D, D = nu/nu0;
+   a grey (frequency-integrated) group scales as D^4 instead. */
+void or_boost(const or_problem *pr, const double *S0, const double *I_prev, double inv_cdt,
+              double *St, double *Xt)
+{
+    long P = npts(pr);
+    int G = pr->ng, K = nord(pr);
+    #pragma omp parallel
+    {
+        double *A = (double *)malloc(sizeof(double) * G);
+        double *C = (double *)malloc(sizeof(double) * G);
+        #pragma omp for
+        for (long p = 0; p < P; p++) {
+            for (int g = 0; g < G; g++) C[g] = chi0_of(pr, p, g);
+            int moving = has_motion(pr, p);
+            for (int k = 0; k < K; k++) {
+                double n[3];
+                ordinate_dir(pr, k, n);
+                double D = 1.0, n0[3] = {n[0], n[1], n[2]};
+                if (moving) {
+                    const double *b = pr->beta + 3 * p;
+                    double b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+                    double Gam = 1.0 / sqrt(1.0 - b2);
+                    double bn = b[0] * n[0] + b[1] * n[1] + b[2] * n[2];
+                    D = 1.0 / (Gam * (1.0 - bn));
+                    double f = Gam * (1.0 - Gam / (Gam + 1.0) * bn);
+                    for (int c = 0; c < 3; c++) n0[c] = D * (n[c] - f * b[c]);
+                }
+                for (int g = 0; g < G; g++) {
+                    double Slab, chil;
+                    if (!moving) {
+                        Slab = S0[(p * G + g) * K + k];
+                        chil = C[g];
+                    } else if (pr->grey) {
+                        Slab = D * D * D * D * angle_interp(pr, S0 + (p * G + g) * K, 1, n0);
+                        chil = C[g] / D;
+                    } else {
+                        if (g == 0)
+                            for (int gp = 0; gp < G; gp++) {
+                                double nc = pr->centres[gp];
+                                A[gp] = angle_interp(pr, S0 + (p * G + gp) * K, 1, n0) / (nc * nc * nc);
+                            }
+                        double nu = pr->centres[g];
+                        Slab = nu * nu * nu * freq_interp(pr, A, 1, nu / D, 1);
+                        chil = freq_interp(pr, C, 1, nu / D, 0) / D;
+                    }
+                    double ip = I_prev ? I_prev[((long)k * G + g) * P + p] : 0.0;
+                    double xt = chil + inv_cdt;
+                    long o = ((long)k * G + g) * P + p;
+                    Xt[o] = xt;
+                    St[o] = (xt > 0.0) ? (chil * Slab + ip * inv_cdt) / xt : 0.0;
+                }
+            }
+        }
+        free(A);
+        free(C);
+    }
+}
+
+/* S5: lab -> comoving on the comoving ordinates.  For comoving ordinate n0 the
+   lab direction is n = (nu0/nu)[n0 + Gamma beta (1 + Gamma/(Gamma+1) beta.n0)]
+   with nu/nu0 = D' = Gamma (1 + beta.n0), and I0(nu) = nu^3 [I_lab/nu^3](n, D' nu);
+   a grey group scales as D'^-4. */
+void or_unboost(const or_problem *pr, const double *I_lab, double *I0)
+{
+    long P = npts(pr);
+    int G = pr->ng, K = nord(pr);
+    #pragma omp parallel
+    {
+        double *A = (double *)malloc(sizeof(double) * G);
+        #pragma omp for
+        for (long p = 0; p < P; p++) {
+            int moving = has_motion(pr, p);
+            for (int j = 0; j < K; j++) {
+                if (!moving) {
+                    for (int g = 0; g < G; g++) I0[(p * G + g) * K + j] = I_lab[((long)j * G + g) * P + p];
+                    continue;
+                }
+                double n0[3], n[3];
+                ordinate_dir(pr, j, n0);
+                const double *b = pr->beta + 3 * p;
+                double b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+                double Gam = 1.0 / sqrt(1.0 - b2);
+                double bn0 = b[0] * n0[0] + b[1] * n0[1] + b[2] * n0[2];
+                double Dp = Gam * (1.0 + bn0);
+                double f = Gam * (1.0 + Gam / (Gam + 1.0) * bn0);
+                for (int c = 0; c < 3; c++) n[c] = (n0[c] + f * b[c]) / Dp;
+                if (pr->grey) {
+                    I0[(p * G + 0) * K + j] = angle_interp(pr, I_lab + p, (long)G * P, n) / (Dp * Dp * Dp * Dp);
+                    continue;
+                }
+                for (int gp = 0; gp < G; gp++) {
+                    double nc = pr->centres[gp];
+                    A[gp] = angle_interp(pr, I_lab + (long)gp * P + p, (long)G * P, n) / (nc * nc * nc);
+                }
+                for (int g = 0; g < G; g++) {
+                    double nu = pr->centres[g];
+                    I0[(p * G + g) * K + j] = nu * nu * nu * freq_interp(pr, A, 1, Dp * nu, 1);
+                }
+            }
+        }
+        free(A);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* S4: short-characteristic ray trace with the cubic Bezier formal solution  */
+/* ------------------------------------------------------------------------ */
+
+/* periodic bilinear value of a plane F[ny][nx] at (i + ox, j + oy) (cell units) */
+static double plane_interp(const double *F, int nx, int ny, int i, int j, double ox, double oy)
+{
+    double xs = i + ox, ys = j + oy;
+    double x0 = floor(xs), y0 = floor(ys);
+    double fx = xs - x0, fy = ys - y0;
+    long i0 = ((long)x0 % nx + nx) % nx, j0 = ((long)y0 % ny + ny) % ny;
+    long i1 = (i0 + 1) % nx, j1 = (j0 + 1) % ny;
+    return (1.0 - fx) * (1.0 - fy) * F[j0 * nx + i0] + fx * (1.0 - fy) * F[j0 * nx + i1]
+         + (1.0 - fx) * fy * F[j1 * nx + i0] + fx * fy * F[j1 * nx + i1];
+}
+
+/* Fritsch-Butland weighted harmonic mean of the two one-sided slopes around a
+   point, hl and hr being the optical depths of the left and right intervals. */
+static double fb_slope(double dl, double dr, double hl, double hr)
+{
+    if (dl * dr <= 0.0) return 0.0;
+    double alpha = (1.0 + hr / (hl + hr)) / 3.0;
+    return dl * dr / (alpha * dr + (1.0 - alpha) * dl);
+}
+
+static double clampd(double v, double a, double b)
+{
+    double lo = a < b ? a : b, hi = a < b ? b : a;
+    return v < lo ? lo : (v > hi ? hi : v);
+}
+
+/* Weights of the cubic Bezier formal solution over optical depth h:
+   integral_0^h S(t) e^{-(h-t)} dt = w0 S_u + w1 C_u + w2 C_p + w3 S_p, with
+   E_n = h int_0^1 u^n e^{-h u} du.  Series in h for small h. */
+static void bezier_weights(double h, double *ex, double w[4])
+{
+    double E[4];
+    if (h < 0.5) {
+        for (int n = 0; n < 4; n++) {
+            double term = h, sum = 0.0;            /* h * (-h)^m / m! */
+            for (int m = 0; m < 60; m++) {
+                sum += term / (n + m + 1.0);
+                term *= -h / (m + 1.0);
+                if (fabs(term) < 1e-30) break;
+            }
+            E[n] = sum;
+        }
+        *ex = exp(-h);
+    } else {
+        double e = exp(-h);
+        E[0] = 1.0 - e;
+        for (int n = 1; n < 4; n++) E[n] = n / h * E[n - 1] - e;
+        *ex = e;
+    }
+    w[0] = E[3];
+    w[1] = 3.0 * (E[2] - E[3]);
+    w[2] = 3.0 * (E[1] - 2.0 * E[2] + E[3]);
+    w[3] = E[0] - 3.0 * E[1] + 3.0 * E[2] - E[3];
+}
+
+/* For every lab ordinate and group, march the z planes from the inflow face:
+   I_p = I_u e^{-h} + Bezier integral of S~ over the segment from the upwind
+   point u on the previous plane (back-traced a distance dz/|mu| along -n and
+   bilinearly interpolated, periodic in x and y) to the grid point p. */
+void or_trace(const or_problem *pr, const double *St, const double *Xt, double *I)
+{
+    int nx = pr->nx, ny = pr->ny, nz = pr->nz, G = pr->ng, K = nord(pr);
+    long P = npts(pr), PL = (long)nx * ny;
+    double dx = pr->lx / nx, dy = pr->ly / ny, dz = pr->lz / (nz - 1);
+    #pragma omp parallel for collapse(2) schedule(dynamic)
+    for (int k = 0; k < K; k++) {
+        for (int g = 0; g < G; g++) {
+            double n[3];
+            ordinate_dir(pr, k, n);
+            double mu = n[2];
+            double ds = dz / fabs(mu);
+            double ox = -ds * n[0] / dx, oy = -ds * n[1] / dy;
+            long o = ((long)k * G + g) * P;
+            const double *S = St + o, *X = Xt + o;
+            double *Ik = I + o;
+            const double *bc = (mu > 0.0) ? pr->bc_bot : pr->bc_top;
+            for (int t = 0; t < nz; t++) {
+                int m = (mu > 0.0) ? t : nz - 1 - t;
+                int mu_ = (mu > 0.0) ? t - 1 : nz - t;       /* upwind plane          */
+                int muu = (mu > 0.0) ? t - 2 : nz + 1 - t;   /* second upwind plane   */
+                int md = (mu > 0.0) ? t + 1 : nz - 2 - t;    /* downwind plane        */
+                if (t == 0) {
+                    for (long e = 0; e < PL; e++)
+                        Ik[m * PL + e] = bc ? bc[((long)k * G + g) * PL + e] : 0.0;
+                    continue;
+                }
+                for (int j = 0; j < ny; j++) {
+                    for (int i = 0; i < nx; i++) {
+                        long e = (long)j * nx + i;
+                        double Sp = S[m * PL + e], Xp = X[m * PL + e];
+                        double Su = plane_interp(S + mu_ * PL, nx, ny, i, j, ox, oy);
+                        double Xu = plane_interp(X + mu_ * PL, nx, ny, i, j, ox, oy);
+                        double Iu = plane_interp(Ik + mu_ * PL, nx, ny, i, j, ox, oy);
+                        double hu = ds * 0.5 * (Xu + Xp);
+                        double dSp = 0.0, dSu = 0.0;
+                        if (hu > 0.0) {
+                            double d1 = (Sp - Su) / hu;
+                            if (t <= nz - 2) {
+                                double Sd = plane_interp(S + md * PL, nx, ny, i, j, -ox, -oy);
+                                double Xd = plane_interp(X + md * PL, nx, ny, i, j, -ox, -oy);
+                                double hd = ds * 0.5 * (Xp + Xd);
+                                dSp = (hd > 0.0) ? fb_slope(d1, (Sd - Sp) / hd, hu, hd) : 0.0;
+                            } else {
+                                dSp = d1;
+                            }
+                            if (t >= 2) {
+                                double Suu = plane_interp(S + muu * PL, nx, ny, i, j, 2.0 * ox, 2.0 * oy);
+                                double Xuu = plane_interp(X + muu * PL, nx, ny, i, j, 2.0 * ox, 2.0 * oy);
+                                double huu = ds * 0.5 * (Xuu + Xu);
+                                dSu = (huu > 0.0) ? fb_slope((Su - Suu) / huu, d1, huu, hu) : 0.0;
+                            } else {
+                                dSu = d1;
+                            }
+                        }
+                        double Cu = clampd(Su + hu * dSu / 3.0, Su, Sp);
+                        double Cp = clampd(Sp - hu * dSp / 3.0, Su, Sp);
+                        double ex, w[4];
+                        bezier_weights(hu, &ex, w);
+                        Ik[m * PL + e] = Iu * ex + w[0] * Su + w[1] * Cu + w[2] * Cp + w[3] * Sp;
+                    }
+                }
+            }
+        }
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* S7 moments (Eddington tensor), S8 residual                                */
+/* ------------------------------------------------------------------------ */
+
+/* Lab moments by ordinate quadrature: J = sum w I/4pi, H = sum w n I/4pi,
+   K = sum w n n I/4pi, K stored as (xx, yy, zz, xy, xz, yz). */
+void or_moments_lab(const or_problem *pr, const double *I_lab, double *J, double *H, double *Kt)
+{
+    long P = npts(pr);
+    int G = pr->ng, K = nord(pr);
+    #pragma omp parallel for
+    for (long p = 0; p < P; p++)
+        for (int g = 0; g < G; g++) {
+            double j = 0, h[3] = {0, 0, 0}, kk[6] = {0, 0, 0, 0, 0, 0};
+            for (int k = 0; k < K; k++) {
+                double n[3];
+                ordinate_dir(pr, k, n);
+                double v = ordinate_weight(pr, k) * I_lab[((long)k * G + g) * P + p] / (4.0 * M_PI);
+                j += v;
+                for (int c = 0; c < 3; c++) h[c] += v * n[c];
+                kk[0] += v * n[0] * n[0];
+                kk[1] += v * n[1] * n[1];
+                kk[2] += v * n[2] * n[2];
+                kk[3] += v * n[0] * n[1];
+                kk[4] += v * n[0] * n[2];
+                kk[5] += v * n[1] * n[2];
+            }
+            J[p * G + g] = j;
+            for (int c = 0; c < 3; c++) H[(p * G + g) * 3 + c] = h[c];
+            for (int c = 0; c < 6; c++) Kt[(p * G + g) * 6 + c] = kk[c];
+        }
+}
+
+/* Comoving moments from the l <= 2 SH coefficients of the comoving intensity. */
+void or_moments_comoving(const or_problem *pr, const double *I_lm, double *J, double *H, double *Kt)
+{
+    long P = npts(pr);
+    int G = pr->ng, NL = nlm_of(pr->lmax);
+    double f4 = 4.0 * M_PI;
+    for (long p = 0; p < P; p++)
+        for (int g = 0; g < G; g++) {
+            const double *c = I_lm + (p * G + g) * NL;
+            double i0 = sqrt(f4) * c[0];                                  /* int I dOmega         */
+            J[p * G + g] = i0 / f4;
+            double hx = 0, hy = 0, hz = 0;
+            if (pr->lmax >= 1) {
+                hx = sqrt(f4 / 3.0) * c[3];
+                hy = sqrt(f4 / 3.0) * c[1];
+                hz = sqrt(f4 / 3.0) * c[2];
+            }
+            H[(p * G + g) * 3 + 0] = hx / f4;
+            H[(p * G + g) * 3 + 1] = hy / f4;
+            H[(p * G + g) * 3 + 2] = hz / f4;
+            double kxx = i0 / 3.0, kyy = i0 / 3.0, kzz = i0 / 3.0, kxy = 0, kxz = 0, kyz = 0;
+            if (pr->lmax >= 2) {
+                double a20 = sqrt(16.0 * M_PI / 5.0) * c[6];   /* int (3 nz^2 - 1) I  */
+                double a22 = sqrt(16.0 * M_PI / 15.0) * c[8];  /* int (nx^2 - ny^2) I */
+                kzz = (a20 + i0) / 3.0;
+                double sxy = i0 - kzz;                          /* int (nx^2 + ny^2) I */
+                kxx = 0.5 * (sxy + a22);
+                kyy = 0.5 * (sxy - a22);
+                kxy = sqrt(f4 / 15.0) * c[4];
+                kxz = sqrt(f4 / 15.0) * c[7];
+                kyz = sqrt(f4 / 15.0) * c[5];
+            }
+            double *k6 = Kt + (p * G + g) * 6;
+            k6[0] = kxx / f4; k6[1] = kyy / f4; k6[2] = kzz / f4;
+            k6[3] = kxy / f4; k6[4] = kxz / f4; k6[5] = kyz / f4;
+        }
+}
+
+/* per-group ||S_new - S_old||_2 / ||S_new||_2 over (points, SH terms) */
+void or_residual(const or_problem *pr, const double *S_old, const double *S_new, double *r)
+{
+    long P = npts(pr);
+    int G = pr->ng, NL = nlm_of(pr->lmax);
+    for (int g = 0; g < G; g++) {
+        double dn = 0.0, nn = 0.0;
+        for (long p = 0; p < P; p++)
+            for (int q = 0; q < NL; q++) {
+                double a = S_new[(p * G + g) * NL + q], b = S_old[(p * G + g) * NL + q];
+                dn += (a - b) * (a - b);
+                nn += a * a;
+            }
+        r[g] = (nn > 0.0) ? sqrt(dn / nn) : (dn > 0.0 ? INFINITY : 0.0);
+    }
+}
+
+/* ------------------------------------------------------------------------ */
+/* One source iteration: S2, S3, S4, S5, S6, S1, S8                           */
+/* ------------------------------------------------------------------------ */
+
+int or_sweep(const or_problem *pr, const double *S_lm, const double *I_prev, double inv_cdt,
+             double *I_lab, double *I_lm, double *S_new, double *resid)
+{
+    long P = npts(pr);
+    long ndo = P * pr->ng * nord(pr);
+    double *S0 = (double *)malloc(sizeof(double) * ndo);
+    double *Xt = (double *)malloc(sizeof(double) * ndo);
+    double *St = (double *)malloc(sizeof(double) * ndo);
+    if (!S0 || !Xt || !St) { free(S0); free(Xt); free(St); return -2; }
+    or_sh2do(pr, S_lm, S0);
+    or_boost(pr, S0, I_prev, inv_cdt, St, Xt);
+    or_trace(pr, St, Xt, I_lab);
+    or_unboost(pr, I_lab, S0);       /* S0 reused as the comoving intensity I0 */
+    or_do2sh(pr, S0, I_lm);
+    or_source(pr, I_lm, S_new);
+    or_residual(pr, S_lm, S_new, resid);
+    free(S0); free(Xt); free(St);
+    return 0;
+}
