@@ -1,0 +1,159 @@
+"""Benchmark: grid-point x ordinate x group updates per second of the
+source-iteration sweep on one MI355X.
+
+A step is one full sweep (SH -> comoving ordinates, Lorentz transform to the
+lab frame, ray trace, inverse transform, ordinates -> SH, new source function,
+residual) of the 32^3 relativistic Thomson jet (16 log groups, L = 7,
+16 x 32 ordinates, FP32), with every input already resident in HBM.  Prints one
+JSON line with the throughput, the roofline of the dominant kernel (timed
+live with HIP events on the library's stream) and the FP64 oracle's rate on
+the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "grid-pt·ordinate·group updates/s per sweep"
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+KERNELS = ["trace", "sh2do", "boost", "unboost", "do2sh", "source", "reduce"]
+
+
+def algorithmic(kernel, spec, esz):
+    """Algorithmic HBM bytes (or flops) of one launch of each kernel of the sweep:
+    the unavoidable reads and writes of its inputs and outputs, once each."""
+    n = spec["nx"] * spec["ny"] * spec["nz"]
+    G = len(spec["edges"]) - 1 if spec.get("edges") is not None else 1
+    K = spec["nmu"] * spec["nphi"]
+    NL = (spec["lmax"] + 1) ** 2
+    do, sh = n * G * K, n * G * NL
+    table = {
+        # S~ and chi~ read, I written: 3 words per update
+        "trace": ("hbm", 3 * esz * do),
+        # SH read, comoving ordinates written
+        "sh2do": ("hbm", esz * (sh + do)),
+        # comoving ordinates read, S~ and chi~ written
+        "boost": ("hbm", esz * 3 * do),
+        # lab intensity read, comoving ordinates written
+        "unboost": ("hbm", esz * 2 * do),
+        # comoving ordinates read, SH written
+        "do2sh": ("hbm", esz * (do + sh)),
+        # SH read and written (Thomson: diagonal in SH)
+        "source": ("hbm", esz * 2 * sh),
+        "reduce": ("hbm", esz * 2 * sh),
+    }
+    return table[kernel]
+
+
+def traffic_from_profiles(kernel, workload):
+    """Measured HBM bytes per launch from the committed rocprofv3 counter
+    summary, or None when absent or taken on a different kernel source."""
+    path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_1507_05141_amd", "csrc", "rrt_kernels.hip")
+    h = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if rec.get("kernel_source_sha256") != h:
+        return None
+    return rec.get("bytes_per_launch")
+
+
+def cpu_baseline(spec):
+    """The FP64 oracle, as it stands, timed on this host's cores over one full
+    sweep of the same workload."""
+    import oracle
+    o = oracle.Oracle(spec)
+    S = o.initial_source()
+    t0 = time.perf_counter()
+    o.sweep(S)
+    dt = time.perf_counter() - t0
+    updates = o.P * o.G * o.K
+    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return {"value": updates / dt, "unit": "updates/s", "cores": cores, "kind": "oracle",
+            "sample": f"one full FP64 sweep of the same workload ({updates} updates, {dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: the sweep is measured on one MI355X "
+              "(multi-GPU sharding is a design note only).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1507_05141_amd import binding as B
+    from paper_1507_05141_amd import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs the GPU"
+    torch.cuda.set_device(0)
+    spec = W.thomson_jet()
+    workload = "thomson_jet_32c_g16_l7_16x32"
+    prec = B.FP32 if args.precision == "fp32" else B.FP64
+    esz = 4 if prec == B.FP32 else 8
+    stream = torch.cuda.current_stream().cuda_stream
+    pr = B.Problem.from_spec(spec, precision=prec, stream=stream)
+    # the initial source of the solve (thermal emission only), resident on the device
+    nl = (spec["lmax"] + 1) ** 2
+    S0 = np.zeros((pr.P, pr.G, nl))
+    S0[:, :, 0] = np.sqrt(4 * np.pi) * spec["kappa"] * spec["bnu"] / (spec["kappa"] + spec["sigma"][:, None])
+    pr.set_source_sh(S0)
+    for _ in range(args.warmup):
+        pr.sweep()
+    pr.synchronize()
+    torch.cuda.synchronize()
+    pr.set_profiling(True)
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pr.sweep()
+    pr.synchronize()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    kern = {}
+    for k in KERNELS:
+        n, ms = pr.kernel_time(k)
+        if n:
+            kern[k] = {"launches": n, "avg_ms": ms / n}
+    pr.set_profiling(False)
+    updates = pr.P * pr.G * pr.K
+    value = updates * args.steps / elapsed
+    dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
+    bound, alg = algorithmic(dom, spec, esz)
+    achieved = alg / (kern[dom]["avg_ms"] * 1e-3) / 1e9
+    traffic = traffic_from_profiles(dom, workload)
+    roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "algorithmic_bytes_per_launch": alg, "avg_launch_ms": kern[dom]["avg_ms"]}
+    out = {
+        "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == B.FP32 else "f64",
+        "data": "synthetic",
+        "config": {"workload": workload, "grid": [32, 32, 32], "groups": 16, "lmax": 7,
+                   "ordinates": [16, 32], "scatter": "thomson", "gamma_max": 10.0,
+                   "updates_per_sweep": updates},
+        "roofline": roof,
+        "kernels": kern,
+    }
+    pr.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(spec)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,175 @@
+/*
+ * rrt.h -- C ABI of the MI355X mixed-frame relativistic radiative-transfer
+ * library (librrt.so): the source-iteration sweep of the spherical-harmonic
+ * discrete-ordinate method with time dependence, Lorentz transformation and
+ * Thomson / Compton scattering of Tominaga, Shibata & Blinnikov (2015).
+ *
+ * The problem is the static transfer equation n.grad I = -chi I + eta (Eq. 1),
+ * or its implicit time-discretised form with chi~ = chi + 1/(c dt) and
+ * eta~ = eta + I(t)/(c dt) (Eqs. 4-6), solved by Lambda iteration (Sec. 2):
+ * the source function is kept as real spherical harmonics in the comoving
+ * frame (Eqs. 9-11), turned into discrete ordinates, Lorentz transformed to the
+ * laboratory frame (Eqs. 7-8 and the invariants I/nu^3, chi nu), integrated
+ * along rays in the laboratory frame, and folded back into comoving spherical
+ * harmonics.  Units: c = 1 (time in units of length).
+ *
+ * Conventions used by every call
+ *  - Grid: nx x ny x nz points; x_i = i lx/nx and y_j = j ly/ny are periodic,
+ *    z_m = m lz/(nz-1) with the inflow boundaries on the planes z = 0, lz.
+ *    Point index p = (z*ny + y)*nx + x; P = nx*ny*nz.
+ *  - Ordinates: k = a*n_phi + b with mu_a the n_mu Gauss-Legendre nodes in
+ *    ascending order and phi_b = 2 pi b / n_phi; zenith along z, azimuth from
+ *    x towards y.  K = n_mu*n_phi.  n_mu must be even (no mu = 0 ray), and the
+ *    mesh must resolve the SH order: n_mu >= lmax+1, n_phi >= 2*lmax+1.
+ *  - Spherical harmonics: real orthonormal Y_lm, index q = l*l + l + m,
+ *    NLM = (lmax+1)^2.
+ *  - Groups: edges e_0 < ... < e_G; centres sqrt(e_g e_{g+1}) (log_centres=1)
+ *    or (e_g+e_{g+1})/2.  edges == NULL with ngroups == 1 is one grey
+ *    (frequency-integrated) group.
+ *  - Array layouts (all row-major, C order):
+ *      per-point fields     kappa, bnu [P][G]; sigma, kte [P]; beta [P][3]
+ *      lab intensity        [K][G][P]
+ *      z-boundary inflow    [K][G][ny][nx]   (only inflow ordinates are read)
+ *      SH coefficients      [P][G][NLM]
+ *      moments              J [P][G], H [P][G][3], K [P][G][6] (xx,yy,zz,xy,xz,yz)
+ *  - Ownership: host arrays passed in are copied before the call returns; the
+ *    caller keeps them.  The library owns all device memory from rrt_create to
+ *    rrt_destroy.  Output arrays are caller-allocated with the sizes above.
+ *  - Errors: every call returns an rrt_status; on failure rrt_last_error()
+ *    describes it (thread-local, valid until the next call on that thread).
+ *    No call aborts the process.
+ *  - Threads: one problem must not be used from two threads at once; separate
+ *    problems are independent.
+ */
+#ifndef RRT_H
+#define RRT_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    RRT_OK = 0,
+    RRT_E_INVALID = -1,        /* bad argument: sizes, NaN, kappa<0, |beta|>=1, ...   */
+    RRT_E_HOST_OOM = -2,       /* host allocation failed                             */
+    RRT_E_HBM = -3,            /* device memory would not fit / allocation failed    */
+    RRT_E_NOT_CONVERGED = -4,  /* iteration limit reached; the last iterate is kept  */
+    RRT_E_DEVICE = -5,         /* a HIP call failed                                  */
+    RRT_E_STATE = -6           /* call out of order (e.g. solve before set_medium)   */
+} rrt_status;
+
+typedef enum { RRT_FP64 = 0, RRT_FP32 = 1 } rrt_precision;
+typedef enum { RRT_THOMSON = 0, RRT_COMPTON = 1 } rrt_scatter;
+typedef enum { RRT_FRAME_LAB = 0, RRT_FRAME_COMOVING = 1 } rrt_frame;
+typedef enum { RRT_SCHEME_RK4 = 0, RRT_SCHEME_EULER = 1 } rrt_scheme;
+
+typedef struct { int nx, ny, nz; double lx, ly, lz; } rrt_grid;
+typedef struct {
+    int ngroups;
+    const double *edges;   /* ngroups+1 ascending edges, or NULL for one grey group */
+    int log_centres;       /* 1: geometric centres; 0: arithmetic centres           */
+    double mec2;           /* electron rest energy in the units of the edges (Compton) */
+} rrt_groups;
+typedef struct { int lmax, n_mu, n_phi; } rrt_angles;
+typedef struct {
+    int iters;             /* source iterations (sweeps) performed                   */
+    double residual;       /* max over groups of ||S_new - S_old|| / ||S_new||       */
+    double seconds;        /* wall time of the call                                  */
+    long long updates;     /* grid-point x ordinate x group updates performed        */
+} rrt_info;
+
+typedef struct rrt_problem rrt_problem;
+
+/* Create a problem: computes the ordinate set, the SH tables and, for Compton
+   scattering, the Klein-Nishina group-to-group tables for electrons at rest
+   (Eqs. 13-14), and allocates the device arrays.  hip_stream: a hipStream_t on
+   which all work is queued, or NULL for a stream owned by the library.
+   Errors: RRT_E_INVALID (sizes, odd n_mu, mesh too coarse for lmax, bad edges),
+   RRT_E_HBM (device memory), RRT_E_DEVICE. */
+rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_angles *angles,
+                      rrt_scatter scatter, rrt_precision precision, void *hip_stream,
+                      rrt_problem **out);
+
+/* Comoving medium (Eq. 1 with chi = alpha + sigma): absorption kappa [P][G] >= 0,
+   n_e sigma_T [P] >= 0 (scattering coefficient per unit length), thermal source
+   function bnu [P][G] (emission kappa*B), flow velocity beta [P][3] with
+   |beta| < 1 or NULL for a static medium, electron temperature kte [P] which
+   must be NULL (electrons at rest, as in the paper's Compton kernel).
+   Errors: RRT_E_INVALID for NaN/negative/|beta|>=1/non-NULL kte. */
+rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *sigma,
+                          const double *bnu, const double *beta, const double *kte);
+
+/* Inflow intensity on the z = 0 (face 0) or z = lz (face 1) plane in the lab
+   frame, [K][G][ny][nx]; only ordinates entering the domain are used.
+   NULL = vacuum (the default). */
+rrt_status rrt_set_boundary(rrt_problem *pr, int face, const double *I_in);
+
+/* Lab intensity state [K][G][P] (the initial condition of rrt_advance, the
+   previous-time intensity of a time-dependent rrt_sweep, the first guess of
+   rrt_solve); NULL sets it to zero. */
+rrt_status rrt_set_intensity(rrt_problem *pr, const double *I_lab);
+
+/* Comoving SH source S [P][G][NLM] used by the next rrt_sweep. */
+rrt_status rrt_set_source_sh(rrt_problem *pr, const double *S_lm);
+
+/* One source iteration from the current SH source (no Ng): SH -> comoving
+   ordinates, comoving -> lab transform with the time terms of Eqs. 5-6 when
+   dt_stage > 0 (the intensity state is I(t)), ray trace, lab -> comoving,
+   ordinates -> SH, new source, residual.  Afterwards the SH source is the new
+   one and the last lab intensity / comoving SH intensity are readable.
+   Errors: RRT_E_STATE before rrt_set_medium. */
+rrt_status rrt_sweep(rrt_problem *pr, double dt_stage, rrt_info *info);
+
+/* Steady solve: Lambda iteration from the source of the intensity state until
+   residual < tol (Ng acceleration every third iteration of a chain when
+   use_ng).  The intensity state becomes the last lab intensity.
+   Returns RRT_E_NOT_CONVERGED after max_iter sweeps (result still readable). */
+rrt_status rrt_solve(rrt_problem *pr, double tol, int max_iter, int use_ng, rrt_info *info);
+
+/* nsteps time steps of length dt from the intensity state: RRT_SCHEME_RK4 is
+   the four implicit stages of Appendix A (dt/6, dt/3, dt/3, dt/6 and
+   Eq. A1), RRT_SCHEME_EULER one implicit stage.  Each stage is a solve to tol. */
+rrt_status rrt_advance(rrt_problem *pr, double dt, int nsteps, int scheme, double tol,
+                       int max_iter, int use_ng, rrt_info *info);
+
+/* Moments per point and group: lab frame by ordinate quadrature of the
+   intensity state, comoving frame from the l <= 2 SH coefficients of the last
+   comoving intensity: J = int I/4pi, H = int n I/4pi, K = int n n I/4pi; the
+   Eddington tensor is K/J.  Reduced in FP64.  Any output pointer may be NULL. */
+rrt_status rrt_get_moments(rrt_problem *pr, rrt_frame frame, double *J, double *H, double *K);
+
+rrt_status rrt_get_source_sh(rrt_problem *pr, double *S_lm);        /* [P][G][NLM] */
+rrt_status rrt_get_intensity_sh(rrt_problem *pr, double *I_lm);     /* [P][G][NLM] */
+rrt_status rrt_get_intensity(rrt_problem *pr, double *I_lab);       /* [K][G][P] state */
+/* lab intensity produced by the last ray trace (rrt_sweep / solve / stage) */
+rrt_status rrt_get_sweep_intensity(rrt_problem *pr, double *I_lab); /* [K][G][P]   */
+
+/* Ray trace alone (the sweep's transfer step) from given lab S~ and chi~
+   [K][G][P] with the problem's boundaries; result [K][G][P]. */
+rrt_status rrt_ray_trace(rrt_problem *pr, const double *S_tilde, const double *chi_tilde,
+                         double *I_lab);
+
+/* Device bytes the problem needs (0 if the arguments are invalid). */
+size_t rrt_footprint_bytes(const rrt_grid *grid, const rrt_groups *groups, const rrt_angles *angles,
+                           rrt_precision precision, int time_dependent, int use_ng);
+
+/* Kernel timing: when enabled, each launch of the library's kernels is
+   bracketed by HIP events on the problem's stream; rrt_kernel_time returns
+   the number of launches and their summed duration (ms) for one kernel name
+   ("trace", "sh2do", "boost", "unboost", "do2sh", "source", "reduce",
+   "moments", "rk") since the last reset, synchronising the stream. */
+rrt_status rrt_set_profiling(rrt_problem *pr, int enable);
+rrt_status rrt_kernel_time(rrt_problem *pr, const char *kernel, int *launches, double *ms);
+
+/* Synchronise the problem's stream. */
+rrt_status rrt_synchronize(rrt_problem *pr);
+
+void rrt_destroy(rrt_problem *pr);
+const char *rrt_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* RRT_H */

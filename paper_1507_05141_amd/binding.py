@@ -1,0 +1,263 @@
+"""Thin ctypes binding of librrt.so (C ABI in include/rrt.h).
+
+Argument marshalling only: every step of the solver runs in the library's HIP
+kernels.  Host arrays are float64 NumPy arrays in the layouts of rrt.h.  The
+library must have been built (``__graft_entry__.build()``); loading fails
+loudly otherwise.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librrt.so")
+
+RRT_OK, RRT_E_INVALID, RRT_E_HOST_OOM, RRT_E_HBM, RRT_E_NOT_CONVERGED, RRT_E_DEVICE, RRT_E_STATE = 0, -1, -2, -3, -4, -5, -6
+FP64, FP32 = 0, 1
+THOMSON, COMPTON = 0, 1
+FRAME_LAB, FRAME_COMOVING = 0, 1
+SCHEME_RK4, SCHEME_EULER = 0, 1
+STATUS_NAMES = {0: "RRT_OK", -1: "RRT_E_INVALID", -2: "RRT_E_HOST_OOM", -3: "RRT_E_HBM",
+                -4: "RRT_E_NOT_CONVERGED", -5: "RRT_E_DEVICE", -6: "RRT_E_STATE"}
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int),
+                ("lx", ctypes.c_double), ("ly", ctypes.c_double), ("lz", ctypes.c_double)]
+
+
+class Groups(ctypes.Structure):
+    _fields_ = [("ngroups", ctypes.c_int), ("edges", _dp), ("log_centres", ctypes.c_int), ("mec2", ctypes.c_double)]
+
+
+class Angles(ctypes.Structure):
+    _fields_ = [("lmax", ctypes.c_int), ("n_mu", ctypes.c_int), ("n_phi", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("residual", ctypes.c_double), ("seconds", ctypes.c_double),
+                ("updates", ctypes.c_longlong)]
+
+
+class RRTError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load librrt.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: build the HIP library first (__graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        I = ctypes.c_int
+        D = ctypes.c_double
+        sigs = {
+            "rrt_create": [ctypes.POINTER(Grid), ctypes.POINTER(Groups), ctypes.POINTER(Angles), I, I, P, ctypes.POINTER(P)],
+            "rrt_set_medium": [P, _dp, _dp, _dp, _dp, _dp],
+            "rrt_set_boundary": [P, I, _dp],
+            "rrt_set_intensity": [P, _dp],
+            "rrt_set_source_sh": [P, _dp],
+            "rrt_sweep": [P, D, ctypes.POINTER(Info)],
+            "rrt_solve": [P, D, I, I, ctypes.POINTER(Info)],
+            "rrt_advance": [P, D, I, I, D, I, I, ctypes.POINTER(Info)],
+            "rrt_get_moments": [P, I, _dp, _dp, _dp],
+            "rrt_get_source_sh": [P, _dp],
+            "rrt_get_intensity_sh": [P, _dp],
+            "rrt_get_intensity": [P, _dp],
+            "rrt_get_sweep_intensity": [P, _dp],
+            "rrt_ray_trace": [P, _dp, _dp, _dp],
+            "rrt_set_profiling": [P, I],
+            "rrt_kernel_time": [P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(D)],
+            "rrt_synchronize": [P],
+        }
+        for name, args in sigs.items():
+            f = getattr(L, name)
+            f.argtypes = args
+            f.restype = ctypes.c_int
+        L.rrt_destroy.argtypes = [P]
+        L.rrt_destroy.restype = None
+        L.rrt_last_error.argtypes = []
+        L.rrt_last_error.restype = ctypes.c_char_p
+        L.rrt_footprint_bytes.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Groups), ctypes.POINTER(Angles), I, I, I]
+        L.rrt_footprint_bytes.restype = ctypes.c_size_t
+        _lib = L
+    return _lib
+
+
+def _check(status, allow=()):
+    if status != RRT_OK and status not in allow:
+        raise RRTError(status, lib().rrt_last_error().decode())
+    return status
+
+
+def _in(a):
+    if a is None:
+        return None, ctypes.cast(None, _dp)
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return a, a.ctypes.data_as(_dp)
+
+
+def _structs(spec):
+    edges = spec.get("edges")
+    e_arr, e_ptr = _in(edges)
+    G = 1 if edges is None else len(edges) - 1
+    grid = Grid(spec["nx"], spec["ny"], spec["nz"], spec["lx"], spec["ly"], spec["lz"])
+    groups = Groups(G, e_ptr, int(spec.get("log_centres", True)), float(spec.get("mec2", 510.99895)))
+    angles = Angles(spec["lmax"], spec["nmu"], spec["nphi"])
+    return grid, groups, angles, e_arr
+
+
+def footprint_bytes(spec, precision=FP32, time_dependent=False, use_ng=False):
+    grid, groups, angles, keep = _structs(spec)
+    return lib().rrt_footprint_bytes(ctypes.byref(grid), ctypes.byref(groups), ctypes.byref(angles),
+                                     precision, int(time_dependent), int(use_ng))
+
+
+class Problem:
+    """One radiative-transfer problem on the device (see rrt.h for the physics)."""
+
+    def __init__(self, spec, precision=FP32, stream=None):
+        L = lib()
+        self.spec = spec
+        grid, groups, angles, self._edges = _structs(spec)
+        self.nx, self.ny, self.nz = spec["nx"], spec["ny"], spec["nz"]
+        self.P = self.nx * self.ny * self.nz
+        self.G = groups.ngroups
+        self.K = spec["nmu"] * spec["nphi"]
+        self.NL = (spec["lmax"] + 1) ** 2
+        self.precision = precision
+        scatter = COMPTON if spec.get("scatter", "thomson") == "compton" else THOMSON
+        h = ctypes.c_void_p()
+        _check(L.rrt_create(ctypes.byref(grid), ctypes.byref(groups), ctypes.byref(angles), scatter, precision,
+                            ctypes.c_void_p(stream) if stream else None, ctypes.byref(h)))
+        self._h = h
+
+    @classmethod
+    def from_spec(cls, spec, precision=FP32, stream=None):
+        """Create a problem and upload its medium and boundaries from a workload dict."""
+        pr = cls(spec, precision, stream)
+        pr.set_medium(spec["kappa"], spec["sigma"], spec["bnu"], spec.get("beta"), None)
+        if spec.get("bc_bot") is not None:
+            pr.set_boundary(0, spec["bc_bot"])
+        if spec.get("bc_top") is not None:
+            pr.set_boundary(1, spec["bc_top"])
+        return pr
+
+    # shapes
+    def lab_shape(self):
+        return (self.K, self.G, self.P)
+
+    def sh_shape(self):
+        return (self.P, self.G, self.NL)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib().rrt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # inputs
+    def set_medium(self, kappa, sigma, bnu, beta=None, kte=None):
+        P, G = self.P, self.G
+        k, kp = _in(np.broadcast_to(kappa, (P, G)))
+        s, sp = _in(np.broadcast_to(sigma, (P,)))
+        b, bp = _in(np.broadcast_to(bnu, (P, G)))
+        v, vp = _in(beta)
+        t, tp = _in(kte)
+        _check(lib().rrt_set_medium(self._h, kp, sp, bp, vp, tp))
+
+    def set_boundary(self, face, I_in):
+        a, p = _in(I_in)
+        _check(lib().rrt_set_boundary(self._h, face, p))
+
+    def set_intensity(self, I_lab):
+        a, p = _in(I_lab)
+        _check(lib().rrt_set_intensity(self._h, p))
+
+    def set_source_sh(self, S):
+        a, p = _in(S)
+        _check(lib().rrt_set_source_sh(self._h, p))
+
+    # steps
+    @staticmethod
+    def _info(i):
+        return {"iters": i.iters, "residual": i.residual, "seconds": i.seconds, "updates": i.updates}
+
+    def sweep(self, dt_stage=0.0):
+        i = Info()
+        _check(lib().rrt_sweep(self._h, float(dt_stage), ctypes.byref(i)))
+        return self._info(i)
+
+    def solve(self, tol=1e-8, max_iter=200, use_ng=True, allow_not_converged=False):
+        i = Info()
+        st = _check(lib().rrt_solve(self._h, float(tol), int(max_iter), int(use_ng), ctypes.byref(i)),
+                    allow=(RRT_E_NOT_CONVERGED,) if allow_not_converged else ())
+        d = self._info(i)
+        d["converged"] = st == RRT_OK
+        return d
+
+    def advance(self, dt, nsteps=1, scheme=SCHEME_RK4, tol=1e-8, max_iter=200, use_ng=False):
+        i = Info()
+        _check(lib().rrt_advance(self._h, float(dt), int(nsteps), int(scheme), float(tol), int(max_iter), int(use_ng),
+                                 ctypes.byref(i)))
+        return self._info(i)
+
+    # outputs
+    def moments(self, frame=FRAME_LAB):
+        J = np.zeros((self.P, self.G))
+        H = np.zeros((self.P, self.G, 3))
+        K = np.zeros((self.P, self.G, 6))
+        _check(lib().rrt_get_moments(self._h, frame, J.ctypes.data_as(_dp), H.ctypes.data_as(_dp), K.ctypes.data_as(_dp)))
+        return J, H, K
+
+    def _get(self, fn, shape):
+        out = np.zeros(shape)
+        _check(fn(self._h, out.ctypes.data_as(_dp)))
+        return out
+
+    def source_sh(self):
+        return self._get(lib().rrt_get_source_sh, self.sh_shape())
+
+    def intensity_sh(self):
+        return self._get(lib().rrt_get_intensity_sh, self.sh_shape())
+
+    def intensity(self):
+        return self._get(lib().rrt_get_intensity, self.lab_shape())
+
+    def sweep_intensity(self):
+        return self._get(lib().rrt_get_sweep_intensity, self.lab_shape())
+
+    def ray_trace(self, S_tilde, chi_tilde):
+        s, sp = _in(S_tilde)
+        x, xp = _in(chi_tilde)
+        out = np.zeros(self.lab_shape())
+        _check(lib().rrt_ray_trace(self._h, sp, xp, out.ctypes.data_as(_dp)))
+        return out
+
+    # timing
+    def set_profiling(self, enable=True):
+        _check(lib().rrt_set_profiling(self._h, int(enable)))
+
+    def kernel_time(self, name):
+        n = ctypes.c_int()
+        ms = ctypes.c_double()
+        _check(lib().rrt_kernel_time(self._h, name.encode(), ctypes.byref(n), ctypes.byref(ms)))
+        return n.value, ms.value
+
+    def synchronize(self):
+        _check(lib().rrt_synchronize(self._h))

@@ -1,0 +1,911 @@
+// Host driver and C ABI of librrt (see include/rrt.h): problem set-up, device
+// memory, the Lambda iteration with Ng acceleration, the four-stage implicit
+// time scheme, and kernel timing.  Every step of the sweep runs in the HIP
+// kernels of rrt_kernels.hip; the host only sequences them.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <new>
+#include <cmath>
+#include <cstring>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "rrt.h"
+#include "rrt_internal.h"
+#include "rrt_kernels.h"
+
+namespace {
+
+thread_local std::string g_err;
+
+rrt_status fail(rrt_status s, const std::string &m)
+{
+    g_err = m;
+    return s;
+}
+
+#define HIPCHK(call)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (call);                                                             \
+        if (e_ != hipSuccess)                                                               \
+            return fail(RRT_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));  \
+    } while (0)
+
+enum KId { KI_TRACE, KI_SH2DO, KI_BOOST, KI_UNBOOST, KI_DO2SH, KI_SOURCE, KI_REDUCE, KI_MOMENTS, KI_RK, KI_N };
+const char *kNames[KI_N] = {"trace", "sh2do", "boost", "unboost", "do2sh", "source", "reduce", "moments", "rk"};
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr size_t kMaxTraceLds = 160 * 1024;
+
+}  // namespace
+
+struct rrt_problem {
+    // sizes
+    int nx = 0, ny = 0, nz = 0;
+    double lx = 0, ly = 0, lz = 0;
+    long P = 0;
+    int G = 1, grey = 1, log_centres = 1;
+    double mec2 = 0;
+    int lmax = 0, NL = 0, nmu = 0, nphi = 0, K = 0;
+    rrt_scatter scatter = RRT_THOMSON;
+    rrt_precision prec = RRT_FP32;
+    size_t esz = 4;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    // host tables
+    std::vector<double> mu, wmu, edges, centres, Y, dir;
+    std::vector<double> kn_s, kn_A, kn_p;
+    // device tables
+    double *d_dir = nullptr, *d_mu = nullptr, *d_lnc = nullptr, *d_nu3 = nullptr, *d_inv_nu3 = nullptr;
+    rrt::OrdGeom *d_geo = nullptr;
+    void *d_Yt = nullptr, *d_WY = nullptr, *d_A = nullptr, *d_sg = nullptr;
+    rrt::FreqInfo fi{};
+    // fields
+    void *d_kappa = nullptr, *d_sigma = nullptr, *d_bnu = nullptr, *d_beta = nullptr, *d_chi0 = nullptr;
+    void *d_bc[2] = {nullptr, nullptr};
+    // state and work arrays
+    void *d_S = nullptr, *d_Snew = nullptr, *d_Ilm = nullptr;
+    void *d_co = nullptr, *d_St = nullptr, *d_Xt = nullptr, *d_Ilab = nullptr, *d_I = nullptr;
+    void *d_Iin = nullptr, *d_acc = nullptr;
+    void *d_chain[4] = {nullptr, nullptr, nullptr, nullptr};
+    double *d_partial = nullptr, *d_red = nullptr;
+    int nblk_red = 0;
+    bool medium_set = false;
+    // kernel timing
+    bool prof = false;
+    std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[KI_N];
+    std::vector<hipEvent_t> pool;
+    double ms[KI_N] = {0};
+    int calls[KI_N] = {0};
+};
+
+namespace {
+
+size_t sh_elems(const rrt_problem *p) { return (size_t)p->P * p->G * p->NL; }
+size_t do_elems(const rrt_problem *p) { return (size_t)p->P * p->G * p->K; }
+
+rrt_status dev_alloc(void **ptr, size_t bytes)
+{
+    if (*ptr) return RRT_OK;
+    hipError_t e = hipMalloc(ptr, bytes ? bytes : 1);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        return fail(RRT_E_HBM, std::string("hipMalloc of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
+    }
+    return RRT_OK;
+}
+
+void dev_free(void *&p)
+{
+    if (p) (void)hipFree(p);
+    p = nullptr;
+}
+
+// upload host doubles converted to the working precision
+rrt_status upload_real(rrt_problem *pr, void *dst, const double *src, size_t n)
+{
+    if (pr->prec == RRT_FP64) {
+        HIPCHK(hipMemcpyAsync(dst, src, n * 8, hipMemcpyHostToDevice, pr->stream));
+        HIPCHK(hipStreamSynchronize(pr->stream));
+        return RRT_OK;
+    }
+    std::vector<float> tmp(n);
+    for (size_t i = 0; i < n; ++i) tmp[i] = (float)src[i];
+    HIPCHK(hipMemcpyAsync(dst, tmp.data(), n * 4, hipMemcpyHostToDevice, pr->stream));
+    HIPCHK(hipStreamSynchronize(pr->stream));
+    return RRT_OK;
+}
+
+rrt_status download_real(rrt_problem *pr, double *dst, const void *src, size_t n)
+{
+    if (pr->prec == RRT_FP64) {
+        HIPCHK(hipMemcpyAsync(dst, src, n * 8, hipMemcpyDeviceToHost, pr->stream));
+        HIPCHK(hipStreamSynchronize(pr->stream));
+        return RRT_OK;
+    }
+    std::vector<float> tmp(n);
+    HIPCHK(hipMemcpyAsync(tmp.data(), src, n * 4, hipMemcpyDeviceToHost, pr->stream));
+    HIPCHK(hipStreamSynchronize(pr->stream));
+    for (size_t i = 0; i < n; ++i) dst[i] = tmp[i];
+    return RRT_OK;
+}
+
+rrt_status upload_double(rrt_problem *pr, void **dst, const std::vector<double> &v)
+{
+    rrt_status s = dev_alloc(dst, v.size() * 8);
+    if (s) return s;
+    HIPCHK(hipMemcpyAsync(*dst, v.data(), v.size() * 8, hipMemcpyHostToDevice, pr->stream));
+    HIPCHK(hipStreamSynchronize(pr->stream));
+    return RRT_OK;
+}
+
+rrt_status alloc_upload_real(rrt_problem *pr, void **dst, const std::vector<double> &v)
+{
+    rrt_status s = dev_alloc(dst, v.size() * pr->esz);
+    if (s) return s;
+    return upload_real(pr, *dst, v.data(), v.size());
+}
+
+// --- kernel timing ---------------------------------------------------------
+void prof_begin(rrt_problem *pr, int id)
+{
+    if (!pr->prof) return;
+    hipEvent_t a, b;
+    if (pr->pool.size() >= 2) {
+        a = pr->pool.back(); pr->pool.pop_back();
+        b = pr->pool.back(); pr->pool.pop_back();
+    } else {
+        (void)hipEventCreate(&a);
+        (void)hipEventCreate(&b);
+    }
+    (void)hipEventRecord(a, pr->stream);
+    pr->pending[id].push_back({a, b});
+}
+
+void prof_end(rrt_problem *pr, int id)
+{
+    if (!pr->prof) return;
+    (void)hipEventRecord(pr->pending[id].back().second, pr->stream);
+}
+
+void prof_collect(rrt_problem *pr)
+{
+    (void)hipStreamSynchronize(pr->stream);
+    for (int i = 0; i < KI_N; ++i) {
+        for (auto &e : pr->pending[i]) {
+            float t = 0;
+            if (hipEventElapsedTime(&t, e.first, e.second) == hipSuccess) {
+                pr->ms[i] += t;
+                pr->calls[i] += 1;
+            }
+            pr->pool.push_back(e.first);
+            pr->pool.push_back(e.second);
+        }
+        pr->pending[i].clear();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// the sweep, templated on the working precision
+// ---------------------------------------------------------------------------
+template <typename real>
+struct Engine {
+    rrt_problem *pr;
+
+    real *R(void *p) const { return static_cast<real *>(p); }
+
+    rrt_status check_launch()
+    {
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return fail(RRT_E_DEVICE, std::string("kernel launch: ") + hipGetErrorString(e));
+        return RRT_OK;
+    }
+
+    // S2 + S3: comoving SH source -> lab S~, chi~
+    void to_lab(const void *S, const void *Iprev, double inv_cdt)
+    {
+        const long PG = pr->P * pr->G;
+        prof_begin(pr, KI_SH2DO);
+        rrt::launch_sh2do<real>(PG, pr->K, pr->NL, R(pr->d_Yt), static_cast<const real *>(S), R(pr->d_co), pr->stream);
+        prof_end(pr, KI_SH2DO);
+        rrt::BoostArgs<real> b;
+        b.P = pr->P; b.K = pr->K; b.nmu = pr->nmu; b.nphi = pr->nphi; b.fi = pr->fi;
+        b.dir = pr->d_dir; b.mu = pr->d_mu; b.S0 = R(pr->d_co); b.Iprev = static_cast<const real *>(Iprev);
+        b.inv_cdt = (real)inv_cdt; b.chi0 = R(pr->d_chi0); b.beta = R(pr->d_beta);
+        b.St = R(pr->d_St); b.Xt = R(pr->d_Xt);
+        prof_begin(pr, KI_BOOST);
+        rrt::launch_boost<real>(b, pr->stream);
+        prof_end(pr, KI_BOOST);
+    }
+
+    // S4
+    void trace(const void *St, const void *Xt, void *I)
+    {
+        rrt::TraceArgs<real> t;
+        t.nx = pr->nx; t.ny = pr->ny; t.nz = pr->nz; t.G = pr->G; t.K = pr->K; t.P = pr->P;
+        t.geo = pr->d_geo; t.St = static_cast<const real *>(St); t.Xt = static_cast<const real *>(Xt);
+        t.bc_bot = R(pr->d_bc[0]); t.bc_top = R(pr->d_bc[1]); t.I = R(I);
+        prof_begin(pr, KI_TRACE);
+        rrt::launch_trace<real>(t, pr->stream);
+        prof_end(pr, KI_TRACE);
+    }
+
+    // S5 + S6: lab intensity -> comoving SH intensity (into d_Ilm)
+    void fold(const void *Ilab)
+    {
+        rrt::UnboostArgs<real> u;
+        u.P = pr->P; u.K = pr->K; u.nmu = pr->nmu; u.nphi = pr->nphi; u.fi = pr->fi;
+        u.dir = pr->d_dir; u.mu = pr->d_mu; u.Ilab = static_cast<const real *>(Ilab); u.beta = R(pr->d_beta);
+        u.I0 = R(pr->d_co);
+        prof_begin(pr, KI_UNBOOST);
+        rrt::launch_unboost<real>(u, pr->stream);
+        prof_end(pr, KI_UNBOOST);
+        prof_begin(pr, KI_DO2SH);
+        rrt::launch_do2sh<real>(pr->P * pr->G, pr->K, pr->NL, R(pr->d_WY), R(pr->d_co), R(pr->d_Ilm), pr->stream);
+        prof_end(pr, KI_DO2SH);
+    }
+
+    // S1: source from d_Ilm into S
+    void source(void *S)
+    {
+        rrt::SourceArgs<real> s;
+        s.P = pr->P; s.G = pr->G; s.NL = pr->NL; s.compton = pr->scatter == RRT_COMPTON;
+        s.chi0 = R(pr->d_chi0); s.sigma = R(pr->d_sigma); s.kappa = R(pr->d_kappa); s.bnu = R(pr->d_bnu);
+        s.A = R(pr->d_A); s.Ilm = R(pr->d_Ilm); s.S = R(S);
+        prof_begin(pr, KI_SOURCE);
+        rrt::launch_source<real>(s, pr->stream);
+        prof_end(pr, KI_SOURCE);
+    }
+
+    // S8: max over groups of ||a - b|| / ||a||
+    rrt_status residual(const void *a, const void *b, double *r)
+    {
+        prof_begin(pr, KI_REDUCE);
+        rrt::launch_resid<real>(pr->P, pr->G, pr->NL, static_cast<const real *>(a), static_cast<const real *>(b),
+                                pr->d_partial, pr->nblk_red, pr->d_red, pr->stream);
+        prof_end(pr, KI_REDUCE);
+        rrt_status s = check_launch();
+        if (s) return s;
+        std::vector<double> h(2 * pr->G);
+        HIPCHK(hipMemcpyAsync(h.data(), pr->d_red, h.size() * 8, hipMemcpyDeviceToHost, pr->stream));
+        HIPCHK(hipStreamSynchronize(pr->stream));
+        double m = 0.0;
+        for (int g = 0; g < pr->G; ++g) {
+            const double dd = h[2 * g], aa = h[2 * g + 1];
+            const double rg = (aa > 0.0) ? std::sqrt(dd / aa) : (dd > 0.0 ? INFINITY : 0.0);
+            if (!(rg <= m)) m = rg;
+        }
+        *r = m;
+        return RRT_OK;
+    }
+
+    // one source iteration from d_S (Iprev/inv_cdt: implicit time terms)
+    rrt_status sweep(const void *Iprev, double inv_cdt, double *resid)
+    {
+        to_lab(pr->d_S, Iprev, inv_cdt);
+        trace(pr->d_St, pr->d_Xt, pr->d_Ilab);
+        fold(pr->d_Ilab);
+        source(pr->d_Snew);
+        rrt_status s = check_launch();
+        if (s) return s;
+        s = residual(pr->d_Snew, pr->d_S, resid);
+        if (s) return s;
+        std::swap(pr->d_S, pr->d_Snew);
+        return RRT_OK;
+    }
+
+    // initial source: S = source(fold(I)) (thermal only when I = 0)
+    rrt_status initial_source(const void *I)
+    {
+        fold(I);
+        source(pr->d_S);
+        return check_launch();
+    }
+
+    rrt_status ng_step(double *ok)
+    {
+        const size_t n = sh_elems(pr);
+        // chain[3] newest ... chain[0] oldest
+        prof_begin(pr, KI_REDUCE);
+        rrt::launch_ng_dots<real>((long)n, R(pr->d_chain[3]), R(pr->d_chain[2]), R(pr->d_chain[1]), R(pr->d_chain[0]),
+                                  pr->d_partial, pr->nblk_red, pr->d_red, pr->stream);
+        prof_end(pr, KI_REDUCE);
+        rrt_status s = check_launch();
+        if (s) return s;
+        double h[5];
+        HIPCHK(hipMemcpyAsync(h, pr->d_red, sizeof(h), hipMemcpyDeviceToHost, pr->stream));
+        HIPCHK(hipStreamSynchronize(pr->stream));
+        const double a11 = h[0], a12 = h[1], a22 = h[2], b1 = h[3], b2 = h[4];
+        const double det = a11 * a22 - a12 * a12;
+        *ok = 0;
+        if (!(det > 1e-14 * a11 * a22) || !std::isfinite(det)) return RRT_OK;
+        const double a = (b1 * a22 - b2 * a12) / det;
+        const double b = (b2 * a11 - b1 * a12) / det;
+        rrt::launch_combine3<real>((long)n, 1.0 - a - b, R(pr->d_chain[3]), a, R(pr->d_chain[2]), b, R(pr->d_chain[1]),
+                                   R(pr->d_S), pr->stream);
+        *ok = 1;
+        return check_launch();
+    }
+
+    // Lambda iteration; the lab intensity of the last sweep is left in d_Ilab
+    rrt_status solve(const void *Iprev, double inv_cdt, const void *Iinit, double tol, int max_iter, int use_ng,
+                     int *iters, double *res)
+    {
+        const size_t shb = sh_elems(pr) * pr->esz;
+        rrt_status s = initial_source(Iinit);
+        if (s) return s;
+        if (use_ng) {
+            for (int c = 0; c < 4; ++c)
+                if ((s = dev_alloc(&pr->d_chain[c], shb))) return s;
+        }
+        int clen = 0;
+        if (use_ng) {
+            HIPCHK(hipMemcpyAsync(pr->d_chain[0], pr->d_S, shb, hipMemcpyDeviceToDevice, pr->stream));
+            clen = 1;
+        }
+        double r = INFINITY;
+        int it = 0;
+        while (it < max_iter) {
+            ++it;
+            if ((s = sweep(Iprev, inv_cdt, &r))) return s;
+            if (r < tol) break;
+            if (use_ng) {
+                HIPCHK(hipMemcpyAsync(pr->d_chain[clen], pr->d_S, shb, hipMemcpyDeviceToDevice, pr->stream));
+                ++clen;
+                if (clen == 4) {
+                    double ok = 0;
+                    if ((s = ng_step(&ok))) return s;
+                    HIPCHK(hipMemcpyAsync(pr->d_chain[0], pr->d_S, shb, hipMemcpyDeviceToDevice, pr->stream));
+                    clen = 1;
+                }
+            }
+        }
+        *iters = it;
+        *res = r;
+        return (r < tol) ? RRT_OK : RRT_E_NOT_CONVERGED;
+    }
+
+    rrt_status moments(rrt_frame frame, double *J, double *H, double *Kt)
+    {
+        const size_t pg = (size_t)pr->P * pr->G;
+        double *dJ = nullptr, *dH = nullptr, *dK = nullptr;
+        rrt_status s;
+        if ((s = dev_alloc((void **)&dJ, pg * 8)) || (s = dev_alloc((void **)&dH, pg * 24)) ||
+            (s = dev_alloc((void **)&dK, pg * 48))) {
+            if (dJ) (void)hipFree(dJ);
+            if (dH) (void)hipFree(dH);
+            return s;
+        }
+        prof_begin(pr, KI_MOMENTS);
+        if (frame == RRT_FRAME_LAB)
+            rrt::launch_moments_lab<real>(pr->P, pr->G, pr->K, pr->d_dir, R(pr->d_I), dJ, dH, dK, pr->stream);
+        else
+            rrt::launch_moments_co<real>((long)pg, pr->NL, pr->lmax, R(pr->d_Ilm), dJ, dH, dK, pr->stream);
+        prof_end(pr, KI_MOMENTS);
+        s = check_launch();
+        if (!s) {
+            hipError_t e = hipSuccess;
+            if (J && e == hipSuccess) e = hipMemcpyAsync(J, dJ, pg * 8, hipMemcpyDeviceToHost, pr->stream);
+            if (H && e == hipSuccess) e = hipMemcpyAsync(H, dH, pg * 24, hipMemcpyDeviceToHost, pr->stream);
+            if (Kt && e == hipSuccess) e = hipMemcpyAsync(Kt, dK, pg * 48, hipMemcpyDeviceToHost, pr->stream);
+            if (e == hipSuccess) e = hipStreamSynchronize(pr->stream);
+            if (e != hipSuccess) s = fail(RRT_E_DEVICE, std::string("moments download: ") + hipGetErrorString(e));
+        }
+        (void)hipFree(dJ);
+        (void)hipFree(dH);
+        (void)hipFree(dK);
+        return s;
+    }
+
+    rrt_status advance(double dt, int nsteps, int scheme, double tol, int max_iter, int use_ng, int *iters, double *res)
+    {
+        const size_t n = do_elems(pr);
+        const size_t b = n * pr->esz;
+        rrt_status s;
+        if ((s = dev_alloc(&pr->d_Iin, b)) || (s = dev_alloc(&pr->d_acc, b))) return s;
+        int total = 0;
+        double rmax = 0;
+        for (int step = 0; step < nsteps; ++step) {
+            if (scheme == RRT_SCHEME_EULER) {
+                int it = 0;
+                double r = 0;
+                s = solve(pr->d_I, 1.0 / dt, pr->d_I, tol, max_iter, use_ng, &it, &r);
+                total += it;
+                rmax = std::fmax(rmax, r);
+                if (s && s != RRT_E_NOT_CONVERGED) return s;
+                HIPCHK(hipMemcpyAsync(pr->d_I, pr->d_Ilab, b, hipMemcpyDeviceToDevice, pr->stream));
+                if (s) return s;
+                continue;
+            }
+            HIPCHK(hipMemcpyAsync(pr->d_Iin, pr->d_I, b, hipMemcpyDeviceToDevice, pr->stream));
+            const double frac[4] = {1.0 / 6.0, 1.0 / 3.0, 1.0 / 3.0, 1.0 / 6.0};
+            const double coef[4] = {3.0, 1.5, 3.0, 0.0};
+            for (int st = 0; st < 4; ++st) {
+                int it = 0;
+                double r = 0;
+                s = solve(pr->d_Iin, 1.0 / (frac[st] * dt), pr->d_Iin, tol, max_iter, use_ng, &it, &r);
+                total += it;
+                rmax = std::fmax(rmax, r);
+                if (s && s != RRT_E_NOT_CONVERGED) return s;
+                if (s) return s;
+                prof_begin(pr, KI_RK);
+                rrt::launch_rk_stage<real>((long)n, R(pr->d_Ilab), R(pr->d_Iin), R(pr->d_acc), R(pr->d_I), st == 0,
+                                           st == 3, (real)coef[st], pr->stream);
+                prof_end(pr, KI_RK);
+                if ((s = check_launch())) return s;
+            }
+        }
+        // comoving SH intensity of the final state, for the comoving moments
+        fold(pr->d_I);
+        *iters = total;
+        *res = rmax;
+        return check_launch();
+    }
+};
+
+template <typename F>
+rrt_status dispatch(rrt_problem *pr, F &&f)
+{
+    if (pr->prec == RRT_FP64) {
+        Engine<double> e{pr};
+        return f(e);
+    }
+    Engine<float> e{pr};
+    return f(e);
+}
+
+rrt_status check_sizes(const rrt_grid *g, const rrt_groups *gr, const rrt_angles *a, rrt_scatter sc, int prec)
+{
+    if (!g || !gr || !a) return fail(RRT_E_INVALID, "NULL grid/groups/angles");
+    if (g->nx < 1 || g->ny < 1 || g->nz < 2) return fail(RRT_E_INVALID, "grid needs nx, ny >= 1 and nz >= 2");
+    if (!(g->lx > 0) || !(g->ly > 0) || !(g->lz > 0)) return fail(RRT_E_INVALID, "domain lengths must be > 0");
+    if (a->lmax < 0 || a->n_mu < 2 || a->n_phi < 1) return fail(RRT_E_INVALID, "bad angular sizes");
+    if (a->n_mu % 2) return fail(RRT_E_INVALID, "n_mu must be even (no horizontal ordinate)");
+    if (a->n_mu < a->lmax + 1 || a->n_phi < 2 * a->lmax + 1)
+        return fail(RRT_E_INVALID, "ordinate mesh too coarse for lmax (need n_mu >= lmax+1, n_phi >= 2 lmax+1)");
+    if (prec != RRT_FP64 && prec != RRT_FP32) return fail(RRT_E_INVALID, "unknown precision");
+    if (sc != RRT_THOMSON && sc != RRT_COMPTON) return fail(RRT_E_INVALID, "unknown scattering kernel");
+    if (!gr->edges) {
+        if (gr->ngroups != 1) return fail(RRT_E_INVALID, "a grey problem has exactly one group");
+        if (sc == RRT_COMPTON) return fail(RRT_E_INVALID, "Compton scattering needs frequency groups");
+    } else {
+        if (gr->ngroups < 1) return fail(RRT_E_INVALID, "ngroups must be >= 1");
+        for (int i = 0; i <= gr->ngroups; ++i)
+            if (!std::isfinite(gr->edges[i]) || gr->edges[i] < 0) return fail(RRT_E_INVALID, "edges must be finite and >= 0");
+        for (int i = 0; i < gr->ngroups; ++i)
+            if (!(gr->edges[i + 1] > gr->edges[i])) return fail(RRT_E_INVALID, "edges must ascend");
+        if (gr->log_centres && !(gr->edges[0] > 0)) return fail(RRT_E_INVALID, "log centres need edges > 0");
+        if (sc == RRT_COMPTON && !(gr->mec2 > 0)) return fail(RRT_E_INVALID, "Compton scattering needs mec2 > 0");
+    }
+    const size_t esz = prec == RRT_FP64 ? 8 : 4;
+    if (2 * esz * (size_t)g->nx * g->ny > kMaxTraceLds)
+        return fail(RRT_E_INVALID, "an x-y plane is too large for the ray-trace kernel's LDS");
+    return RRT_OK;
+}
+
+size_t footprint(const rrt_grid *g, const rrt_groups *gr, const rrt_angles *a, int prec, int time_dep, int use_ng)
+{
+    const size_t esz = prec == RRT_FP64 ? 8 : 4;
+    const size_t P = (size_t)g->nx * g->ny * g->nz, G = gr->ngroups, K = (size_t)a->n_mu * a->n_phi;
+    const size_t NL = (size_t)(a->lmax + 1) * (a->lmax + 1);
+    size_t sh = P * G * NL * esz, dob = P * G * K * esz;
+    size_t total = 3 * sh + 5 * dob;                 // S, Snew, Ilm; co, St, Xt, Ilab, I
+    if (time_dep) total += 2 * dob;                  // stage input, accumulator
+    if (use_ng) total += 4 * sh;                     // Ng chain
+    total += P * (2 * G + 4) * esz + P * G * esz;    // fields + chi0
+    total += 2 * (size_t)g->nx * g->ny * K * G * esz;  // boundaries
+    total += 1 << 20;                                // tables and reductions
+    return total;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *rrt_last_error(void) { return g_err.c_str(); }
+
+size_t rrt_footprint_bytes(const rrt_grid *grid, const rrt_groups *groups, const rrt_angles *angles,
+                           rrt_precision precision, int time_dependent, int use_ng)
+{
+    if (check_sizes(grid, groups, angles, RRT_THOMSON, precision) != RRT_OK) return 0;
+    return footprint(grid, groups, angles, precision, time_dependent, use_ng);
+}
+
+void rrt_destroy(rrt_problem *pr)
+{
+    if (!pr) return;
+    if (pr->stream) (void)hipStreamSynchronize(pr->stream);
+    void *bufs[] = {pr->d_dir, pr->d_mu, pr->d_lnc, pr->d_nu3, pr->d_inv_nu3, pr->d_geo, pr->d_Yt, pr->d_WY, pr->d_A,
+                    pr->d_sg, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_chi0, pr->d_bc[0], pr->d_bc[1],
+                    pr->d_S, pr->d_Snew, pr->d_Ilm, pr->d_co, pr->d_St, pr->d_Xt, pr->d_Ilab, pr->d_I, pr->d_Iin,
+                    pr->d_acc, pr->d_chain[0], pr->d_chain[1], pr->d_chain[2], pr->d_chain[3], pr->d_partial, pr->d_red};
+    for (void *b : bufs)
+        if (b) (void)hipFree(b);
+    for (int i = 0; i < KI_N; ++i)
+        for (auto &e : pr->pending[i]) {
+            (void)hipEventDestroy(e.first);
+            (void)hipEventDestroy(e.second);
+        }
+    for (auto e : pr->pool) (void)hipEventDestroy(e);
+    if (pr->own_stream && pr->stream) (void)hipStreamDestroy(pr->stream);
+    delete pr;
+}
+
+rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_angles *angles, rrt_scatter scatter,
+                      rrt_precision precision, void *hip_stream, rrt_problem **out)
+{
+    if (!out) return fail(RRT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    rrt_status s = check_sizes(grid, groups, angles, scatter, precision);
+    if (s) return s;
+    rrt_problem *pr = new (std::nothrow) rrt_problem();
+    if (!pr) return fail(RRT_E_HOST_OOM, "problem allocation");
+    pr->nx = grid->nx; pr->ny = grid->ny; pr->nz = grid->nz;
+    pr->lx = grid->lx; pr->ly = grid->ly; pr->lz = grid->lz;
+    pr->P = (long)pr->nx * pr->ny * pr->nz;
+    pr->grey = groups->edges == nullptr;
+    pr->G = groups->ngroups;
+    pr->log_centres = groups->log_centres;
+    pr->mec2 = groups->mec2;
+    pr->lmax = angles->lmax; pr->NL = (pr->lmax + 1) * (pr->lmax + 1);
+    pr->nmu = angles->n_mu; pr->nphi = angles->n_phi; pr->K = pr->nmu * pr->nphi;
+    pr->scatter = scatter;
+    pr->prec = precision;
+    pr->esz = precision == RRT_FP64 ? 8 : 4;
+    auto bail = [&](rrt_status st) { rrt_destroy(pr); return st; };
+    if (hip_stream) {
+        pr->stream = static_cast<hipStream_t>(hip_stream);
+    } else {
+        hipError_t e = hipStreamCreateWithFlags(&pr->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) return bail(fail(RRT_E_DEVICE, std::string("hipStreamCreate: ") + hipGetErrorString(e)));
+        pr->own_stream = true;
+    }
+    {
+        int dev = 0, lds = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+        if (e == hipSuccess) e = rrt::upload_bezier_coefficients();
+        const size_t lim = std::min(kMaxTraceLds, (size_t)lds);
+        if (e == hipSuccess) e = rrt::set_trace_lds_limit(lim);
+        if (e != hipSuccess) return bail(fail(RRT_E_DEVICE, std::string("kernel set-up: ") + hipGetErrorString(e)));
+        if (2 * pr->esz * (size_t)pr->nx * pr->ny > lim)
+            return bail(fail(RRT_E_INVALID, "an x-y plane is too large for the ray-trace kernel's LDS on this device"));
+    }
+    // ordinates and SH tables
+    rrt::gauss_legendre(pr->nmu, pr->mu, pr->wmu);
+    const int K = pr->K, NL = pr->NL;
+    pr->dir.resize(4 * (size_t)K);
+    pr->Y.resize((size_t)K * NL);
+    for (int a = 0; a < pr->nmu; ++a)
+        for (int b = 0; b < pr->nphi; ++b) {
+            const int k = a * pr->nphi + b;
+            const double m = pr->mu[a], ph = 2.0 * kPi * b / pr->nphi, st = std::sqrt(std::fmax(0.0, 1.0 - m * m));
+            pr->dir[4 * k] = st * std::cos(ph);
+            pr->dir[4 * k + 1] = st * std::sin(ph);
+            pr->dir[4 * k + 2] = m;
+            pr->dir[4 * k + 3] = pr->wmu[a] * 2.0 * kPi / pr->nphi;
+            rrt::real_sh(pr->lmax, m, ph, &pr->Y[(size_t)k * NL]);
+        }
+    std::vector<double> Yt((size_t)NL * K), WY((size_t)K * NL);
+    for (int k = 0; k < K; ++k)
+        for (int q = 0; q < NL; ++q) {
+            Yt[(size_t)q * K + k] = pr->Y[(size_t)k * NL + q];
+            WY[(size_t)k * NL + q] = pr->dir[4 * k + 3] * pr->Y[(size_t)k * NL + q];
+        }
+    if ((s = upload_double(pr, (void **)&pr->d_dir, pr->dir)) || (s = upload_double(pr, (void **)&pr->d_mu, pr->mu)) ||
+        (s = alloc_upload_real(pr, &pr->d_Yt, Yt)) || (s = alloc_upload_real(pr, &pr->d_WY, WY)))
+        return bail(s);
+    // ray-trace geometry per ordinate
+    {
+        const double dx = pr->lx / pr->nx, dy = pr->ly / pr->ny, dz = pr->lz / (pr->nz - 1);
+        std::vector<rrt::OrdGeom> geo(K);
+        for (int k = 0; k < K; ++k) {
+            const double *n = &pr->dir[4 * k];
+            rrt::OrdGeom &gm = geo[k];
+            gm.ds = dz / std::fabs(n[2]);
+            gm.up = n[2] > 0 ? 1 : 0;
+            const double ox = -gm.ds * n[0] / dx, oy = -gm.ds * n[1] / dy;
+            const double sh[3] = {2.0, 1.0, -1.0};
+            for (int c = 0; c < 3; ++c) {
+                const double sx = sh[c] * ox, sy = sh[c] * oy;
+                const double fx0 = std::floor(sx), fy0 = std::floor(sy);
+                gm.fx[c] = sx - fx0;
+                gm.fy[c] = sy - fy0;
+                long ix = (long)fx0 % pr->nx, iy = (long)fy0 % pr->ny;
+                if (ix < 0) ix += pr->nx;
+                if (iy < 0) iy += pr->ny;
+                gm.ix[c] = (int)ix;
+                gm.iy[c] = (int)iy;
+            }
+        }
+        s = dev_alloc((void **)&pr->d_geo, sizeof(rrt::OrdGeom) * K);
+        if (s) return bail(s);
+        hipError_t e = hipMemcpy(pr->d_geo, geo.data(), sizeof(rrt::OrdGeom) * K, hipMemcpyHostToDevice);
+        if (e != hipSuccess) return bail(fail(RRT_E_DEVICE, "geometry upload"));
+    }
+    // groups
+    const int G = pr->G;
+    if (pr->grey) {
+        pr->edges = {0.0, 1.0};
+        pr->centres = {1.0};
+    } else {
+        pr->edges.assign(groups->edges, groups->edges + G + 1);
+        pr->centres.resize(G);
+        for (int g = 0; g < G; ++g)
+            pr->centres[g] = pr->log_centres ? std::sqrt(pr->edges[g] * pr->edges[g + 1]) : 0.5 * (pr->edges[g] + pr->edges[g + 1]);
+    }
+    {
+        std::vector<double> lnc(G), nu3(G), inu3(G);
+        for (int g = 0; g < G; ++g) {
+            lnc[g] = std::log(pr->centres[g]);
+            nu3[g] = pr->centres[g] * pr->centres[g] * pr->centres[g];
+            inu3[g] = 1.0 / nu3[g];
+        }
+        if ((s = upload_double(pr, (void **)&pr->d_lnc, lnc)) || (s = upload_double(pr, (void **)&pr->d_nu3, nu3)) ||
+            (s = upload_double(pr, (void **)&pr->d_inv_nu3, inu3)))
+            return bail(s);
+        pr->fi.G = G;
+        pr->fi.grey = pr->grey;
+        pr->fi.has_lo_ghost = pr->edges[0] > 0.0;
+        pr->fi.ghost_lo = pr->edges[0] > 0.0 ? 2.0 * std::log(pr->edges[0]) - lnc[0] : -INFINITY;
+        pr->fi.ghost_hi = 2.0 * std::log(pr->edges[G]) - lnc[G - 1];
+        pr->fi.lnc = pr->d_lnc;
+        pr->fi.nu3 = pr->d_nu3;
+        pr->fi.inv_nu3 = pr->d_inv_nu3;
+    }
+    if (scatter == RRT_COMPTON) {
+        rrt::compton_tables(G, pr->edges.data(), pr->centres.data(), pr->mec2, pr->lmax, pr->kn_s, pr->kn_A, pr->kn_p);
+        if ((s = alloc_upload_real(pr, &pr->d_A, pr->kn_A)) || (s = alloc_upload_real(pr, &pr->d_sg, pr->kn_s)))
+            return bail(s);
+    }
+    // state arrays
+    const size_t shb = sh_elems(pr) * pr->esz, dob = do_elems(pr) * pr->esz;
+    if ((s = dev_alloc(&pr->d_S, shb)) || (s = dev_alloc(&pr->d_Snew, shb)) || (s = dev_alloc(&pr->d_Ilm, shb)) ||
+        (s = dev_alloc(&pr->d_co, dob)) || (s = dev_alloc(&pr->d_St, dob)) || (s = dev_alloc(&pr->d_Xt, dob)) ||
+        (s = dev_alloc(&pr->d_Ilab, dob)) || (s = dev_alloc(&pr->d_I, dob)))
+        return bail(s);
+    {
+        hipError_t e = hipMemsetAsync(pr->d_I, 0, dob, pr->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(pr->d_S, 0, shb, pr->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(pr->d_Ilm, 0, shb, pr->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(pr->d_Ilab, 0, dob, pr->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(pr->stream);
+        if (e != hipSuccess) return bail(fail(RRT_E_DEVICE, "initial clear"));
+    }
+    pr->nblk_red = 1024;
+    if ((s = dev_alloc((void **)&pr->d_partial, (size_t)pr->nblk_red * std::max(2 * G, 5) * 8)) ||
+        (s = dev_alloc((void **)&pr->d_red, (size_t)std::max(2 * G, 5) * 8)))
+        return bail(s);
+    *out = pr;
+    g_err.clear();
+    return RRT_OK;
+}
+
+rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *sigma, const double *bnu,
+                          const double *beta, const double *kte)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    if (!kappa || !sigma || !bnu) return fail(RRT_E_INVALID, "kappa, sigma and bnu are required");
+    if (kte) return fail(RRT_E_INVALID, "electron temperature fields are not supported: electrons at rest only");
+    const size_t P = pr->P, G = pr->G;
+    for (size_t i = 0; i < P * G; ++i) {
+        if (!std::isfinite(kappa[i]) || kappa[i] < 0) return fail(RRT_E_INVALID, "kappa must be finite and >= 0");
+        if (!std::isfinite(bnu[i])) return fail(RRT_E_INVALID, "bnu must be finite");
+    }
+    for (size_t i = 0; i < P; ++i)
+        if (!std::isfinite(sigma[i]) || sigma[i] < 0) return fail(RRT_E_INVALID, "sigma must be finite and >= 0");
+    if (beta)
+        for (size_t i = 0; i < P; ++i) {
+            const double b2 = beta[3 * i] * beta[3 * i] + beta[3 * i + 1] * beta[3 * i + 1] + beta[3 * i + 2] * beta[3 * i + 2];
+            if (!std::isfinite(b2) || !(b2 < 1.0)) return fail(RRT_E_INVALID, "|beta| must be < 1");
+        }
+    rrt_status s;
+    if ((s = dev_alloc(&pr->d_kappa, P * G * pr->esz)) || (s = dev_alloc(&pr->d_sigma, P * pr->esz)) ||
+        (s = dev_alloc(&pr->d_bnu, P * G * pr->esz)) || (s = dev_alloc(&pr->d_chi0, P * G * pr->esz)))
+        return s;
+    if ((s = upload_real(pr, pr->d_kappa, kappa, P * G)) || (s = upload_real(pr, pr->d_sigma, sigma, P)) ||
+        (s = upload_real(pr, pr->d_bnu, bnu, P * G)))
+        return s;
+    if (beta) {
+        if ((s = dev_alloc(&pr->d_beta, P * 3 * pr->esz))) return s;
+        if ((s = upload_real(pr, pr->d_beta, beta, P * 3))) return s;
+    } else {
+        dev_free(pr->d_beta);
+    }
+    if (pr->prec == RRT_FP64)
+        rrt::launch_chi0<double>((long)P, (int)G, (const double *)pr->d_kappa, (const double *)pr->d_sigma,
+                                 (const double *)pr->d_sg, (double *)pr->d_chi0, pr->stream);
+    else
+        rrt::launch_chi0<float>((long)P, (int)G, (const float *)pr->d_kappa, (const float *)pr->d_sigma,
+                                (const float *)pr->d_sg, (float *)pr->d_chi0, pr->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(pr->stream));
+    pr->medium_set = true;
+    return RRT_OK;
+}
+
+rrt_status rrt_set_boundary(rrt_problem *pr, int face, const double *I_in)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    if (face != 0 && face != 1) return fail(RRT_E_INVALID, "face must be 0 (z = 0) or 1 (z = lz)");
+    if (!I_in) {
+        dev_free(pr->d_bc[face]);
+        return RRT_OK;
+    }
+    const size_t n = (size_t)pr->K * pr->G * pr->nx * pr->ny;
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(I_in[i])) return fail(RRT_E_INVALID, "boundary intensity must be finite");
+    rrt_status s = dev_alloc(&pr->d_bc[face], n * pr->esz);
+    if (s) return s;
+    return upload_real(pr, pr->d_bc[face], I_in, n);
+}
+
+rrt_status rrt_set_intensity(rrt_problem *pr, const double *I_lab)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    const size_t n = do_elems(pr);
+    if (!I_lab) {
+        HIPCHK(hipMemsetAsync(pr->d_I, 0, n * pr->esz, pr->stream));
+        HIPCHK(hipStreamSynchronize(pr->stream));
+        return RRT_OK;
+    }
+    return upload_real(pr, pr->d_I, I_lab, n);
+}
+
+rrt_status rrt_set_source_sh(rrt_problem *pr, const double *S_lm)
+{
+    if (!pr || !S_lm) return fail(RRT_E_INVALID, "NULL argument");
+    return upload_real(pr, pr->d_S, S_lm, sh_elems(pr));
+}
+
+rrt_status rrt_sweep(rrt_problem *pr, double dt_stage, rrt_info *info)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    if (!pr->medium_set) return fail(RRT_E_STATE, "rrt_set_medium must come first");
+    if (!(dt_stage >= 0) || !std::isfinite(dt_stage)) return fail(RRT_E_INVALID, "dt_stage must be >= 0");
+    auto t0 = std::chrono::steady_clock::now();
+    double r = 0;
+    rrt_status s = dispatch(pr, [&](auto &e) {
+        return e.sweep(dt_stage > 0 ? pr->d_I : nullptr, dt_stage > 0 ? 1.0 / dt_stage : 0.0, &r);
+    });
+    if (info) {
+        info->iters = 1;
+        info->residual = r;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->updates = (long long)do_elems(pr);
+    }
+    return s;
+}
+
+rrt_status rrt_solve(rrt_problem *pr, double tol, int max_iter, int use_ng, rrt_info *info)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    if (!pr->medium_set) return fail(RRT_E_STATE, "rrt_set_medium must come first");
+    if (max_iter < 1 || !(tol >= 0)) return fail(RRT_E_INVALID, "need max_iter >= 1 and tol >= 0");
+    auto t0 = std::chrono::steady_clock::now();
+    int it = 0;
+    double r = 0;
+    rrt_status s = dispatch(pr, [&](auto &e) { return e.solve(nullptr, 0.0, pr->d_I, tol, max_iter, use_ng, &it, &r); });
+    if (s == RRT_OK || s == RRT_E_NOT_CONVERGED) {
+        hipError_t e = hipMemcpyAsync(pr->d_I, pr->d_Ilab, do_elems(pr) * pr->esz, hipMemcpyDeviceToDevice, pr->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(pr->stream);
+        if (e != hipSuccess) s = fail(RRT_E_DEVICE, "state copy");
+        if (s == RRT_E_NOT_CONVERGED) fail(s, "source iteration did not converge within max_iter");
+    }
+    if (info) {
+        info->iters = it;
+        info->residual = r;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->updates = (long long)it * (long long)do_elems(pr);
+    }
+    return s;
+}
+
+rrt_status rrt_advance(rrt_problem *pr, double dt, int nsteps, int scheme, double tol, int max_iter, int use_ng,
+                       rrt_info *info)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    if (!pr->medium_set) return fail(RRT_E_STATE, "rrt_set_medium must come first");
+    if (!(dt > 0) || nsteps < 0 || max_iter < 1 || !(tol >= 0)) return fail(RRT_E_INVALID, "bad time-step arguments");
+    if (scheme != RRT_SCHEME_RK4 && scheme != RRT_SCHEME_EULER) return fail(RRT_E_INVALID, "unknown scheme");
+    auto t0 = std::chrono::steady_clock::now();
+    int it = 0;
+    double r = 0;
+    rrt_status s = dispatch(pr, [&](auto &e) { return e.advance(dt, nsteps, scheme, tol, max_iter, use_ng, &it, &r); });
+    if (s == RRT_E_NOT_CONVERGED) fail(s, "a stage did not converge within max_iter");
+    if (info) {
+        info->iters = it;
+        info->residual = r;
+        info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        info->updates = (long long)it * (long long)do_elems(pr);
+    }
+    return s;
+}
+
+rrt_status rrt_get_moments(rrt_problem *pr, rrt_frame frame, double *J, double *H, double *K)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    if (frame != RRT_FRAME_LAB && frame != RRT_FRAME_COMOVING) return fail(RRT_E_INVALID, "unknown frame");
+    return dispatch(pr, [&](auto &e) { return e.moments(frame, J, H, K); });
+}
+
+rrt_status rrt_get_source_sh(rrt_problem *pr, double *S_lm)
+{
+    if (!pr || !S_lm) return fail(RRT_E_INVALID, "NULL argument");
+    return download_real(pr, S_lm, pr->d_S, sh_elems(pr));
+}
+
+rrt_status rrt_get_intensity_sh(rrt_problem *pr, double *I_lm)
+{
+    if (!pr || !I_lm) return fail(RRT_E_INVALID, "NULL argument");
+    return download_real(pr, I_lm, pr->d_Ilm, sh_elems(pr));
+}
+
+rrt_status rrt_get_intensity(rrt_problem *pr, double *I_lab)
+{
+    if (!pr || !I_lab) return fail(RRT_E_INVALID, "NULL argument");
+    return download_real(pr, I_lab, pr->d_I, do_elems(pr));
+}
+
+rrt_status rrt_get_sweep_intensity(rrt_problem *pr, double *I_lab)
+{
+    if (!pr || !I_lab) return fail(RRT_E_INVALID, "NULL argument");
+    return download_real(pr, I_lab, pr->d_Ilab, do_elems(pr));
+}
+
+rrt_status rrt_ray_trace(rrt_problem *pr, const double *S_tilde, const double *chi_tilde, double *I_lab)
+{
+    if (!pr || !S_tilde || !chi_tilde || !I_lab) return fail(RRT_E_INVALID, "NULL argument");
+    const size_t n = do_elems(pr);
+    for (size_t i = 0; i < n; ++i)
+        if (!std::isfinite(S_tilde[i]) || !std::isfinite(chi_tilde[i]) || chi_tilde[i] < 0)
+            return fail(RRT_E_INVALID, "S~ must be finite and chi~ finite and >= 0");
+    rrt_status s;
+    if ((s = upload_real(pr, pr->d_St, S_tilde, n)) || (s = upload_real(pr, pr->d_Xt, chi_tilde, n))) return s;
+    s = dispatch(pr, [&](auto &e) {
+        e.trace(pr->d_St, pr->d_Xt, pr->d_Ilab);
+        return e.check_launch();
+    });
+    if (s) return s;
+    return download_real(pr, I_lab, pr->d_Ilab, n);
+}
+
+rrt_status rrt_set_profiling(rrt_problem *pr, int enable)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    prof_collect(pr);
+    for (int i = 0; i < KI_N; ++i) {
+        pr->ms[i] = 0;
+        pr->calls[i] = 0;
+    }
+    pr->prof = enable != 0;
+    return RRT_OK;
+}
+
+rrt_status rrt_kernel_time(rrt_problem *pr, const char *kernel, int *launches, double *ms)
+{
+    if (!pr || !kernel) return fail(RRT_E_INVALID, "NULL argument");
+    prof_collect(pr);
+    for (int i = 0; i < KI_N; ++i)
+        if (std::strcmp(kernel, kNames[i]) == 0) {
+            if (launches) *launches = pr->calls[i];
+            if (ms) *ms = pr->ms[i];
+            return RRT_OK;
+        }
+    return fail(RRT_E_INVALID, std::string("unknown kernel name ") + kernel);
+}
+
+rrt_status rrt_synchronize(rrt_problem *pr)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    HIPCHK(hipStreamSynchronize(pr->stream));
+    return RRT_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,85 @@
+// Argument blocks and launchers of the library's HIP kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace rrt {
+
+constexpr int kBezTerms64 = 18;   // series terms of the Bezier weights, h < 0.5 (FP64)
+constexpr int kBezTerms32 = 12;   // series terms of the Bezier weights, h < 1   (FP32)
+
+// Per-ordinate geometry of the plane-to-plane short characteristic: path
+// length ds = dz/|mu| between planes, march direction, and the horizontal
+// back-trace offsets in cells for the second-upwind (2 * off), upwind (off)
+// and downwind (-off) planes: integer part (reduced modulo nx, ny) + fraction.
+struct OrdGeom {
+    double ds;
+    int up;
+    int ix[3], iy[3];
+    double fx[3], fy[3];
+};
+
+// Group centres for the ln(nu) interpolation of the frame transforms.
+struct FreqInfo {
+    int G;
+    int grey;
+    int has_lo_ghost;        // lowest edge > 0: a zero-valued ghost centre below
+    double ghost_lo, ghost_hi;
+    const double *lnc;       // [G] ln(centre)
+    const double *nu3;       // [G] centre^3
+    const double *inv_nu3;   // [G] 1/centre^3
+};
+
+template <typename real> struct TraceArgs {
+    int nx, ny, nz, G, K;
+    long P;
+    const OrdGeom *geo;
+    const real *St, *Xt, *bc_bot, *bc_top;
+    real *I;
+};
+
+template <typename real> struct BoostArgs {
+    long P;
+    int K, nmu, nphi;
+    FreqInfo fi;
+    const double *dir, *mu;
+    const real *S0, *Iprev;
+    real inv_cdt;
+    const real *chi0, *beta;
+    real *St, *Xt;
+};
+
+template <typename real> struct UnboostArgs {
+    long P;
+    int K, nmu, nphi;
+    FreqInfo fi;
+    const double *dir, *mu;
+    const real *Ilab, *beta;
+    real *I0;
+};
+
+template <typename real> struct SourceArgs {
+    long P;
+    int G, NL, compton;
+    const real *chi0, *sigma, *kappa, *bnu, *A, *Ilm;
+    real *S;
+};
+
+hipError_t upload_bezier_coefficients();
+
+template <typename real> void launch_trace(const TraceArgs<real> &a, hipStream_t st);
+template <typename real> void launch_boost(const BoostArgs<real> &a, hipStream_t st);
+template <typename real> void launch_unboost(const UnboostArgs<real> &a, hipStream_t st);
+template <typename real> void launch_sh2do(long PG, int K, int NL, const real *Yt, const real *S, real *S0, hipStream_t st);
+template <typename real> void launch_do2sh(long PG, int K, int NL, const real *WY, const real *I0, real *Ilm, hipStream_t st);
+template <typename real> void launch_source(const SourceArgs<real> &a, hipStream_t st);
+template <typename real> void launch_chi0(long P, int G, const real *kappa, const real *sigma, const real *sg, real *chi0, hipStream_t st);
+template <typename real> void launch_moments_lab(long P, int G, int K, const double *dir, const real *I, double *J, double *H, double *Kt, hipStream_t st);
+template <typename real> void launch_moments_co(long PG, int NL, int lmax, const real *Ilm, double *J, double *H, double *Kt, hipStream_t st);
+template <typename real> void launch_resid(long P, int G, int NL, const real *a, const real *b, double *partial, int nblk, double *out, hipStream_t st);
+template <typename real> void launch_ng_dots(long n, const real *s0, const real *s1, const real *s2, const real *s3, double *partial, int nblk, double *out, hipStream_t st);
+template <typename real> void launch_combine3(long n, double c0, const real *x0, double c1, const real *x1, double c2, const real *x2, real *out, hipStream_t st);
+template <typename real> void launch_rk_stage(long n, const real *R, real *Iin, real *acc, real *In, int first, int last, real coef, hipStream_t st);
+
+hipError_t set_trace_lds_limit(size_t bytes);
+
+}  // namespace rrt

@@ -1,0 +1,200 @@
+"""Parity of the HIP library (through its C ABI) with the FP64 oracle.
+
+Every case runs the same seeded inputs through both and compares element by
+element: 1e-11 relative (to the per-group maximum) for the FP64 device path,
+1e-5 for FP32.  Sizes are chosen so the oracle finishes in seconds while the
+kernels still see several tiles and ragged edges; the last case runs one full
+sweep of the 32^3 x 16-group x 512-ordinate relativistic Thomson jet.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1507_05141_amd import binding as B
+from paper_1507_05141_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = {B.FP64: 1e-11, B.FP32: 1e-5}
+PREC_IDS = {B.FP64: "fp64", B.FP32: "fp32"}
+
+
+def close_by_group(got, ref, rtol, gaxis, what=""):
+    g = np.moveaxis(got, gaxis, 0).reshape(got.shape[gaxis], -1)
+    r = np.moveaxis(ref, gaxis, 0).reshape(ref.shape[gaxis], -1)
+    for i in range(r.shape[0]):
+        scale = np.max(np.abs(r[i]))
+        err = np.max(np.abs(g[i] - r[i]))
+        assert err <= rtol * scale + 1e-300, f"{what} group {i}: max err {err:.3e} vs scale {scale:.3e}"
+
+
+def custom_spec(nx, ny, nz, G=3, lmax=3, nmu=4, nphi=8, seed=0, scatter="thomson", gamma_max=4.0,
+                edges=None, log_centres=True, grey=False, with_bc=True, mec2=None):
+    rs = np.random.default_rng(seed)
+    P = nx * ny * nz
+    if grey:
+        edges, G = None, 1
+    elif edges is None:
+        edges = 10.0 ** np.linspace(-1, 1, G + 1) if log_centres else np.linspace(0.0, 1.1, G + 1)
+    else:
+        G = len(edges) - 1
+    K = nmu * nphi
+    bmax = math.sqrt(1 - 1 / gamma_max ** 2)
+    d = rs.normal(size=(P, 3))
+    d /= np.linalg.norm(d, axis=1, keepdims=True)
+    beta = d * bmax * rs.uniform(0, 1, (P, 1)) ** 0.5
+    beta[rs.uniform(size=P) < 0.25] = 0.0                  # part of the medium at rest
+    return dict(nx=nx, ny=ny, nz=nz, lx=1.0, ly=0.8, lz=1.1, nmu=nmu, nphi=nphi, lmax=lmax,
+                edges=edges, log_centres=log_centres, scatter=scatter,
+                mec2=mec2 if mec2 is not None else (1.0 if scatter == "compton" else W.MEC2_KEV),
+                kappa=rs.uniform(0.1, 2.0, (P, G)), sigma=10 ** rs.uniform(-1, 1, P),
+                bnu=rs.uniform(0.2, 2.0, (P, G)), beta=beta, kte=None,
+                bc_bot=rs.uniform(0, 1, (K, G, ny, nx)) if with_bc else None,
+                bc_top=rs.uniform(0, 1, (K, G, ny, nx)) if with_bc else None)
+
+
+CASES = {
+    "thomson_log": dict(nx=9, ny=7, nz=6, G=3, seed=1),
+    "thomson_grey": dict(nx=6, ny=6, nz=5, grey=True, seed=2, nmu=8, nphi=16),
+    "compton_linear_bins": dict(nx=5, ny=4, nz=4, G=6, scatter="compton", log_centres=False, seed=3, lmax=3),
+    "compton_log_keV": dict(nx=4, ny=5, nz=5, G=5, scatter="compton", seed=4,
+                            edges=np.exp(np.linspace(np.log(20.0), np.log(2000.0), 6)), mec2=W.MEC2_KEV),
+    "lmax0_min_z": dict(nx=3, ny=3, nz=2, G=2, lmax=0, nmu=2, nphi=4, seed=5),
+    "high_gamma_L7": dict(nx=5, ny=5, nz=4, G=4, lmax=7, nmu=8, nphi=16, gamma_max=20.0, seed=6),
+    "vacuum_boundaries": dict(nx=6, ny=6, nz=6, G=2, with_bc=False, seed=7),
+}
+
+
+def _both(spec, prec):
+    o = oracle.Oracle(spec)
+    print(f"case nx={spec['nx']} ny={spec['ny']} nz={spec['nz']} G={o.G} L={spec['lmax']} "
+          f"K={o.K} {spec['scatter']} prec={PREC_IDS[prec]}", flush=True)
+    g = B.Problem.from_spec(spec, precision=prec)
+    return o, g
+
+
+@pytest.mark.parametrize("prec", [B.FP64, B.FP32], ids=["fp64", "fp32"])
+def test_ray_trace_parity(prec):
+    spec = custom_spec(11, 7, 9, G=3, seed=10)
+    o, g = _both(spec, prec)
+    rs = np.random.default_rng(11)
+    St = rs.uniform(0.0, 2.0, o.lab_shape())
+    Xt = 10 ** rs.uniform(-1.5, 1.5, o.lab_shape())
+    Xt[:, :, : spec["nx"]] = 0.0                            # a vacuum row: h = 0 branches
+    ref = o.trace(St, Xt)
+    got = g.ray_trace(St, Xt)
+    close_by_group(got, ref, TOL[prec], 1, "I")
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [B.FP64, B.FP32], ids=["fp64", "fp32"])
+@pytest.mark.parametrize("case", list(CASES))
+def test_sweep_parity(case, prec):
+    spec = custom_spec(**CASES[case])
+    o, g = _both(spec, prec)
+    rs = np.random.default_rng(99)
+    S = o.initial_source() + 0.3 * rs.normal(size=o.sh_shape()) * np.abs(o.initial_source()[..., :1]).mean()
+    ref_I, ref_Ilm, ref_S, ref_r = o.sweep(S)
+    g.set_source_sh(S)
+    info = g.sweep()
+    close_by_group(g.sweep_intensity(), ref_I, TOL[prec], 1, "I_lab")
+    close_by_group(g.intensity_sh(), ref_Ilm, TOL[prec], 1, "I_lm")
+    close_by_group(g.source_sh(), ref_S, TOL[prec], 1, "S_new")
+    assert abs(info["residual"] - ref_r.max()) <= 10 * TOL[prec] * max(1.0, ref_r.max())
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [B.FP64, B.FP32], ids=["fp64", "fp32"])
+def test_time_dependent_sweep_parity(prec):
+    spec = custom_spec(7, 6, 5, G=4, seed=12)
+    o, g = _both(spec, prec)
+    rs = np.random.default_rng(13)
+    I_prev = rs.uniform(0, 1.5, o.lab_shape())
+    S = o.initial_source(I_prev)
+    dt = 0.5 / 7 / 6
+    ref_I, ref_Ilm, ref_S, ref_r = o.sweep(S, I_prev, 1.0 / dt)
+    g.set_intensity(I_prev)
+    g.set_source_sh(S)
+    g.sweep(dt)
+    close_by_group(g.sweep_intensity(), ref_I, TOL[prec], 1, "I_lab")
+    close_by_group(g.source_sh(), ref_S, TOL[prec], 1, "S_new")
+    g.close()
+
+
+def _close_moments(got, ref, rtol, what):
+    J, H, K = got
+    Jr, Hr, Kr = ref
+    for gi in range(Jr.shape[1]):
+        jr = Jr[:, gi]
+        assert np.all(np.abs(J[:, gi] - jr) <= rtol * np.abs(jr)), f"{what} J group {gi}"
+        for arr, ar, nm in ((H, Hr, "H"), (K, Kr, "K")):
+            scale = np.max(np.abs(ar[:, gi]))
+            assert np.max(np.abs(arr[:, gi] - ar[:, gi])) <= rtol * scale + 1e-300, f"{what} {nm} group {gi}"
+
+
+def test_uniform_slab_solve_parity_fp64():
+    """The plain-method slab at its full size: 16^3, grey, L = 3, 8 x 16, FP64,
+    residual < 1e-8; J, H and the Eddington tensor at every point, both frames."""
+    spec = W.uniform_slab()
+    o, g = _both(spec, B.FP64)
+    ref = o.solve(tol=1e-8, max_iter=300, use_ng=True)
+    info = g.solve(tol=1e-8, max_iter=300, use_ng=True)
+    assert info["iters"] == ref["iters"]
+    _close_moments(g.moments(B.FRAME_LAB), o.moments_lab(ref["I_lab"]), 1e-10, "lab")
+    _close_moments(g.moments(B.FRAME_COMOVING), o.moments_comoving(ref["I_lm"]), 1e-10, "comoving")
+    g.close()
+
+
+@pytest.mark.parametrize("prec", [B.FP64, B.FP32], ids=["fp64", "fp32"])
+def test_small_jet_time_steps_parity(prec):
+    """Two four-stage time steps of a reduced relativistic Thomson jet."""
+    spec = W.thomson_jet(n=8, ng=4, lmax=3, nmu=4, nphi=8, seed=2)
+    o, g = _both(spec, prec)
+    dt = 0.5 / 8
+    tol = 1e-12 if prec == B.FP64 else 1e-7
+    I_ref, last = o.advance(None, dt, nsteps=2, scheme="rk4", tol=1e-12, max_iter=100)
+    g.advance(dt, nsteps=2, scheme=B.SCHEME_RK4, tol=tol, max_iter=100)
+    rt = 1e-10 if prec == B.FP64 else 1e-5
+    close_by_group(g.intensity(), I_ref, rt, 1, "I")
+    _close_moments(g.moments(B.FRAME_LAB), o.moments_lab(I_ref), rt, "lab")
+    _close_moments(g.moments(B.FRAME_COMOVING), o.moments_comoving(o.fold(I_ref)), rt, "comoving")
+    g.close()
+
+
+def test_full_size_thomson_jet_sweep_fp32():
+    """One full sweep of the 32^3, 16-group, L = 7, 16 x 32 relativistic jet
+    (the benchmarked workload) against the oracle, every output element."""
+    spec = W.thomson_jet()
+    o, g = _both(spec, B.FP32)
+    S = o.initial_source()
+    I_prev = None
+    ref_I, ref_Ilm, ref_S, _ = o.sweep(S, I_prev, 0.0)
+    g.set_source_sh(S)
+    g.sweep()
+    close_by_group(g.sweep_intensity(), ref_I, 1e-5, 1, "I_lab")
+    close_by_group(g.intensity_sh(), ref_Ilm, 1e-5, 1, "I_lm")
+    close_by_group(g.source_sh(), ref_S, 1e-5, 1, "S_new")
+    g.close()
+
+
+def test_invalid_inputs_are_rejected():
+    spec = custom_spec(3, 3, 3, G=2, seed=20)
+    g = B.Problem(spec, precision=B.FP32)
+    bad = spec["kappa"].copy()
+    bad[0, 0] = -1.0
+    with pytest.raises(B.RRTError) as e:
+        g.set_medium(bad, spec["sigma"], spec["bnu"], spec["beta"])
+    assert e.value.status == B.RRT_E_INVALID
+    with pytest.raises(B.RRTError) as e:
+        g.sweep()
+    assert e.value.status == B.RRT_E_STATE
+    b2 = spec["beta"].copy()
+    b2[0] = [0.0, 0.0, 1.0]
+    with pytest.raises(B.RRTError):
+        g.set_medium(spec["kappa"], spec["sigma"], spec["bnu"], b2)
+    g.set_medium(spec["kappa"], spec["sigma"], spec["bnu"], spec["beta"])
+    info = g.solve(tol=1e-30, max_iter=2, use_ng=False, allow_not_converged=True)
+    assert not info["converged"] and info["iters"] == 2
+    g.close()
