@@ -34,15 +34,15 @@ def algorithmic(kernel, spec, esz):
     NL = (spec["lmax"] + 1) ** 2
     do, sh = n * G * K, n * G * NL
     table = {
-        # S~ and chi~ read, I written: 3 words per update
-        "trace": ("hbm", 3 * esz * do),
-        # SH read, comoving ordinates written
+        # S~ read, I written (chi~ is rebuilt from the per-point medium)
+        "trace": ("hbm", 2 * esz * do),
+        # SH source read, comoving ordinate values written
         "sh2do": ("hbm", esz * (sh + do)),
-        # comoving ordinates read, S~ and chi~ written
-        "boost": ("hbm", esz * 3 * do),
-        # lab intensity read, comoving ordinates written
-        "unboost": ("hbm", esz * 2 * do),
-        # comoving ordinates read, SH written
+        # comoving ordinate values read, S~ written
+        "boost": ("hbm", 2 * esz * do),
+        # lab intensity read, comoving ordinate values written
+        "unboost": ("hbm", 2 * esz * do),
+        # comoving ordinate values read, SH intensity written
         "do2sh": ("hbm", esz * (do + sh)),
         # SH read and written (Thomson: diagonal in SH)
         "source": ("hbm", esz * 2 * sh),
@@ -87,6 +87,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="first run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on exactly one GPU: the sweep is measured on one MI355X "
@@ -101,6 +103,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     spec = W.thomson_jet()
     workload = "thomson_jet_32c_g16_l7_16x32"
     prec = B.FP32 if args.precision == "fp32" else B.FP64

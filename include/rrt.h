@@ -28,8 +28,8 @@
  *    (frequency-integrated) group.
  *  - Array layouts (all row-major, C order):
  *      per-point fields     kappa, bnu [P][G]; sigma, kte [P]; beta [P][3]
- *      lab intensity        [K][G][P]
- *      z-boundary inflow    [K][G][ny][nx]   (only inflow ordinates are read)
+ *      lab intensity        [K][P][G]        (ordinate, point, group innermost)
+ *      z-boundary inflow    [K][ny][nx][G]   (only inflow ordinates are read)
  *      SH coefficients      [P][G][NLM]
  *      moments              J [P][G], H [P][G][3], K [P][G][6] (xx,yy,zz,xy,xz,yz)
  *  - Ownership: host arrays passed in are copied before the call returns; the
@@ -102,11 +102,11 @@ rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *si
                           const double *bnu, const double *beta, const double *kte);
 
 /* Inflow intensity on the z = 0 (face 0) or z = lz (face 1) plane in the lab
-   frame, [K][G][ny][nx]; only ordinates entering the domain are used.
+   frame, [K][ny][nx][G]; only ordinates entering the domain are used.
    NULL = vacuum (the default). */
 rrt_status rrt_set_boundary(rrt_problem *pr, int face, const double *I_in);
 
-/* Lab intensity state [K][G][P] (the initial condition of rrt_advance, the
+/* Lab intensity state [K][P][G] (the initial condition of rrt_advance, the
    previous-time intensity of a time-dependent rrt_sweep, the first guess of
    rrt_solve); NULL sets it to zero. */
 rrt_status rrt_set_intensity(rrt_problem *pr, const double *I_lab);
@@ -142,12 +142,12 @@ rrt_status rrt_get_moments(rrt_problem *pr, rrt_frame frame, double *J, double *
 
 rrt_status rrt_get_source_sh(rrt_problem *pr, double *S_lm);        /* [P][G][NLM] */
 rrt_status rrt_get_intensity_sh(rrt_problem *pr, double *I_lm);     /* [P][G][NLM] */
-rrt_status rrt_get_intensity(rrt_problem *pr, double *I_lab);       /* [K][G][P] state */
+rrt_status rrt_get_intensity(rrt_problem *pr, double *I_lab);       /* [K][P][G] state */
 /* lab intensity produced by the last ray trace (rrt_sweep / solve / stage) */
-rrt_status rrt_get_sweep_intensity(rrt_problem *pr, double *I_lab); /* [K][G][P]   */
+rrt_status rrt_get_sweep_intensity(rrt_problem *pr, double *I_lab); /* [K][P][G]   */
 
 /* Ray trace alone (the sweep's transfer step) from given lab S~ and chi~
-   [K][G][P] with the problem's boundaries; result [K][G][P]. */
+   [K][P][G] with the problem's boundaries; result [K][P][G]. */
 rrt_status rrt_ray_trace(rrt_problem *pr, const double *S_tilde, const double *chi_tilde,
                          double *I_lab);
 

@@ -11,6 +11,10 @@ A problem is described by the plain dictionary that
 ``paper_1507_05141_amd.workloads`` produces (sizes, group edges, fields); the
 oracle derives every table it needs (Gauss-Legendre ordinates, real spherical
 harmonics, group centres, Compton tables) with its own routines.
+
+Array layouts at this Python interface are those of the library's C ABI: lab
+intensities [K][P][G], boundaries [K][ny][nx][G], SH [P][G][NLM]; comoving
+ordinate arrays are [P][G][K].  The C code keeps lab arrays as [K][G][P].
 """
 import ctypes
 import math
@@ -142,8 +146,8 @@ class Oracle:
         self.sigma = _f64(np.broadcast_to(spec["sigma"], (P,)))
         self.bnu = _f64(np.broadcast_to(spec["bnu"], (P, G)))
         self.beta = _f64(spec.get("beta"))
-        self.bc_bot = _f64(spec.get("bc_bot"))
-        self.bc_top = _f64(spec.get("bc_top"))
+        self.bc_bot = self._bc(spec.get("bc_bot"))
+        self.bc_top = self._bc(spec.get("bc_top"))
         s = self._s = _Problem()
         s.nx, s.ny, s.nz = self.nx, self.ny, self.nz
         s.lx, s.ly, s.lz = spec["lx"], spec["ly"], spec["lz"]
@@ -157,11 +161,29 @@ class Oracle:
         s.mu, s.wmu, s.Y = _ptr(self.mu), _ptr(self.wmu), _ptr(self.Y)
         self._ref = ctypes.byref(s)
 
+    def _bc(self, a):
+        if a is None:
+            return None
+        a = np.asarray(a, dtype=np.float64).reshape(self.K, self.ny, self.nx, self.G)
+        return np.ascontiguousarray(a.transpose(0, 3, 1, 2))
+
+    def _to_c(self, a):
+        """lab array [K][P][G] -> the C layout [K][G][P]"""
+        if a is None:
+            return None
+        return np.ascontiguousarray(np.asarray(a, dtype=np.float64).reshape(self.K, self.P, self.G).transpose(0, 2, 1))
+
+    def _from_c(self, a):
+        return np.ascontiguousarray(a.transpose(0, 2, 1))
+
     # shapes
     def sh_shape(self):
         return (self.P, self.G, self.NL)
 
     def lab_shape(self):
+        return (self.K, self.P, self.G)
+
+    def _c_lab_shape(self):
         return (self.K, self.G, self.P)
 
     def co_shape(self):
@@ -188,20 +210,20 @@ class Oracle:
 
     def boost(self, S0, I_prev=None, inv_cdt=0.0):
         S0 = _f64(S0)
-        I_prev = _f64(I_prev)
-        St = np.zeros(self.lab_shape())
-        Xt = np.zeros(self.lab_shape())
+        I_prev = self._to_c(I_prev)
+        St = np.zeros(self._c_lab_shape())
+        Xt = np.zeros(self._c_lab_shape())
         _load().or_boost(self._ref, _ptr(S0), _ptr(I_prev), ctypes.c_double(inv_cdt), _ptr(St), _ptr(Xt))
-        return St, Xt
+        return self._from_c(St), self._from_c(Xt)
 
     def trace(self, St, Xt):
-        St, Xt = _f64(St), _f64(Xt)
-        I = np.zeros(self.lab_shape())
+        St, Xt = self._to_c(St), self._to_c(Xt)
+        I = np.zeros(self._c_lab_shape())
         _load().or_trace(self._ref, _ptr(St), _ptr(Xt), _ptr(I))
-        return I
+        return self._from_c(I)
 
     def unboost(self, I_lab):
-        I_lab = _f64(I_lab)
+        I_lab = self._to_c(I_lab)
         out = np.zeros(self.co_shape())
         _load().or_unboost(self._ref, _ptr(I_lab), _ptr(out))
         return out
@@ -215,7 +237,7 @@ class Oracle:
         return r
 
     def moments_lab(self, I_lab):
-        I_lab = _f64(I_lab)
+        I_lab = self._to_c(I_lab)
         J = np.zeros((self.P, self.G))
         H = np.zeros((self.P, self.G, 3))
         Kt = np.zeros((self.P, self.G, 6))
@@ -234,8 +256,8 @@ class Oracle:
         """One source iteration: SH->DO, boost + time terms, ray trace, inverse
         boost, DO->SH, new source, residual.  Returns (I_lab, I_lm, S_new, r)."""
         S_lm = _f64(S_lm)
-        I_prev = _f64(I_prev)
-        I_lab = np.zeros(self.lab_shape())
+        I_prev = self._to_c(I_prev)
+        I_lab = np.zeros(self._c_lab_shape())
         I_lm = np.zeros(self.sh_shape())
         S_new = np.zeros(self.sh_shape())
         r = np.zeros(self.G)
@@ -243,7 +265,7 @@ class Oracle:
                               _ptr(I_lab), _ptr(I_lm), _ptr(S_new), _ptr(r))
         if rc != 0:
             raise MemoryError("oracle sweep could not allocate its work arrays")
-        return I_lab, I_lm, S_new, r
+        return self._from_c(I_lab), I_lm, S_new, r
 
     # --- iteration control -------------------------------------------------
     def initial_source(self, I_in=None):

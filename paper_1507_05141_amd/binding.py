@@ -1,7 +1,8 @@
 """Thin ctypes binding of librrt.so (C ABI in include/rrt.h).
 
 Argument marshalling only: every step of the solver runs in the library's HIP
-kernels.  Host arrays are float64 NumPy arrays in the layouts of rrt.h.  The
+kernels.  Host arrays are float64 NumPy arrays in the layouts of rrt.h (lab
+intensities [K][P][G], boundaries [K][ny][nx][G]).  The
 library must have been built (``__graft_entry__.build()``); loading fails
 loudly otherwise.
 """
@@ -155,7 +156,7 @@ class Problem:
 
     # shapes
     def lab_shape(self):
-        return (self.K, self.G, self.P)
+        return (self.K, self.P, self.G)
 
     def sh_shape(self):
         return (self.P, self.G, self.NL)

@@ -3,11 +3,13 @@
 // time scheme, and kernel timing.  Every step of the sweep runs in the HIP
 // kernels of rrt_kernels.hip; the host only sequences them.
 #include <hip/hip_runtime.h>
+#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
 #include <new>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <string>
 #include <utility>
@@ -38,7 +40,7 @@ enum KId { KI_TRACE, KI_SH2DO, KI_BOOST, KI_UNBOOST, KI_DO2SH, KI_SOURCE, KI_RED
 const char *kNames[KI_N] = {"trace", "sh2do", "boost", "unboost", "do2sh", "source", "reduce", "moments", "rk"};
 
 constexpr double kPi = 3.14159265358979323846;
-constexpr size_t kMaxTraceLds = 160 * 1024;
+constexpr size_t kMaxLds = 160 * 1024;
 
 }  // namespace
 
@@ -59,12 +61,18 @@ struct rrt_problem {
     std::vector<double> mu, wmu, edges, centres, Y, dir;
     std::vector<double> kn_s, kn_A, kn_p;
     // device tables
-    double *d_dir = nullptr, *d_mu = nullptr, *d_lnc = nullptr, *d_nu3 = nullptr, *d_inv_nu3 = nullptr;
+    double *d_dir = nullptr, *d_mu = nullptr, *d_lnc = nullptr, *d_nu3 = nullptr, *d_inv_nu3 = nullptr,
+           *d_inv_dc = nullptr;
+    rocblas_handle blas = nullptr;
+    int Gc = 1;
     rrt::OrdGeom *d_geo = nullptr;
     void *d_Yt = nullptr, *d_WY = nullptr, *d_A = nullptr, *d_sg = nullptr;
     rrt::FreqInfo fi{};
     // fields
-    void *d_kappa = nullptr, *d_sigma = nullptr, *d_bnu = nullptr, *d_beta = nullptr, *d_chi0 = nullptr;
+    void *d_kappa = nullptr, *d_sigma = nullptr, *d_bnu = nullptr, *d_chi0 = nullptr;
+    double *d_beta = nullptr, *d_gam = nullptr;
+    void *d_chilab = nullptr;
+    int grey_chi = 0;
     void *d_bc[2] = {nullptr, nullptr};
     // state and work arrays
     void *d_S = nullptr, *d_Snew = nullptr, *d_Ilm = nullptr;
@@ -204,48 +212,76 @@ struct Engine {
         return RRT_OK;
     }
 
-    // S2 + S3: comoving SH source -> lab S~, chi~
-    void to_lab(const void *S, const void *Iprev, double inv_cdt)
+    // row-major C[M][N] = A[M][Kd] . B[Kd][N] with rocBLAS (column-major C^T = B^T A^T),
+    // split along M so that no matrix exceeds 2^31 elements
+    rrt_status gemm(long M, int N, int Kd, const real *A, const real *Bm, real *C)
     {
-        const long PG = pr->P * pr->G;
+        const real one = 1, zero = 0;
+        const long maxrows = std::max(1L, (long)((1L << 31) - 1) / std::max(N, Kd));
+        for (long r0 = 0; r0 < M; r0 += maxrows) {
+            const int rows = (int)std::min(maxrows, M - r0);
+            rocblas_status st;
+            if (sizeof(real) == 8)
+                st = rocblas_dgemm(pr->blas, rocblas_operation_none, rocblas_operation_none, N, rows, Kd,
+                                   (const double *)&one, (const double *)Bm, N, (const double *)(A + r0 * Kd), Kd,
+                                   (const double *)&zero, (double *)(C + r0 * N), N);
+            else
+                st = rocblas_sgemm(pr->blas, rocblas_operation_none, rocblas_operation_none, N, rows, Kd,
+                                   (const float *)&one, (const float *)Bm, N, (const float *)(A + r0 * Kd), Kd,
+                                   (const float *)&zero, (float *)(C + r0 * N), N);
+            if (st != rocblas_status_success)
+                return fail(RRT_E_DEVICE, std::string("rocBLAS gemm: ") + rocblas_status_to_string(st));
+        }
+        return RRT_OK;
+    }
+
+    // S2 + S3: comoving SH source -> comoving ordinates -> lab S~ (with the implicit time terms)
+    rrt_status to_lab(const void *S, const void *Iprev, double inv_cdt)
+    {
         prof_begin(pr, KI_SH2DO);
-        rrt::launch_sh2do<real>(PG, pr->K, pr->NL, R(pr->d_Yt), static_cast<const real *>(S), R(pr->d_co), pr->stream);
+        rrt_status s = gemm(pr->P * pr->G, pr->K, pr->NL, static_cast<const real *>(S), R(pr->d_Yt), R(pr->d_co));
         prof_end(pr, KI_SH2DO);
+        if (s) return s;
         rrt::BoostArgs<real> b;
         b.P = pr->P; b.K = pr->K; b.nmu = pr->nmu; b.nphi = pr->nphi; b.fi = pr->fi;
         b.dir = pr->d_dir; b.mu = pr->d_mu; b.S0 = R(pr->d_co); b.Iprev = static_cast<const real *>(Iprev);
-        b.inv_cdt = (real)inv_cdt; b.chi0 = R(pr->d_chi0); b.beta = R(pr->d_beta);
-        b.St = R(pr->d_St); b.Xt = R(pr->d_Xt);
+        b.inv_cdt = (real)inv_cdt; b.chilab = R(pr->d_chilab); b.chi_grey = pr->grey_chi;
+        b.beta = pr->d_beta; b.gam = pr->d_gam; b.St = R(pr->d_St);
         prof_begin(pr, KI_BOOST);
         rrt::launch_boost<real>(b, pr->stream);
         prof_end(pr, KI_BOOST);
+        return check_launch();
     }
 
-    // S4
-    void trace(const void *St, const void *Xt, void *I)
+    // S4 (chi~ from the medium, or from d_Xt when chi_array)
+    void trace(const void *St, void *I, double inv_cdt, bool chi_array)
     {
         rrt::TraceArgs<real> t;
-        t.nx = pr->nx; t.ny = pr->ny; t.nz = pr->nz; t.G = pr->G; t.K = pr->K; t.P = pr->P;
-        t.geo = pr->d_geo; t.St = static_cast<const real *>(St); t.Xt = static_cast<const real *>(Xt);
-        t.bc_bot = R(pr->d_bc[0]); t.bc_top = R(pr->d_bc[1]); t.I = R(I);
+        t.nx = pr->nx; t.ny = pr->ny; t.nz = pr->nz; t.G = pr->G; t.K = pr->K; t.Gc = pr->Gc; t.P = pr->P;
+        t.geo = pr->d_geo; t.dir = pr->d_dir; t.St = static_cast<const real *>(St); t.Xt = R(pr->d_Xt);
+        t.chilab = R(pr->d_chilab); t.chi_grey = pr->grey_chi;
+        t.inv_cdt = (real)inv_cdt; t.bc_bot = R(pr->d_bc[0]); t.bc_top = R(pr->d_bc[1]); t.I = R(I);
         prof_begin(pr, KI_TRACE);
-        rrt::launch_trace<real>(t, pr->stream);
+        rrt::launch_trace<real>(t, chi_array, pr->stream);
         prof_end(pr, KI_TRACE);
     }
 
-    // S5 + S6: lab intensity -> comoving SH intensity (into d_Ilm)
-    void fold(const void *Ilab)
+    // S5 + S6: lab intensity -> comoving ordinates -> comoving SH intensity (into d_Ilm)
+    rrt_status fold(const void *Ilab)
     {
         rrt::UnboostArgs<real> u;
         u.P = pr->P; u.K = pr->K; u.nmu = pr->nmu; u.nphi = pr->nphi; u.fi = pr->fi;
-        u.dir = pr->d_dir; u.mu = pr->d_mu; u.Ilab = static_cast<const real *>(Ilab); u.beta = R(pr->d_beta);
-        u.I0 = R(pr->d_co);
+        u.dir = pr->d_dir; u.mu = pr->d_mu; u.Ilab = static_cast<const real *>(Ilab);
+        u.beta = pr->d_beta; u.gam = pr->d_gam; u.I0 = R(pr->d_co);
         prof_begin(pr, KI_UNBOOST);
         rrt::launch_unboost<real>(u, pr->stream);
         prof_end(pr, KI_UNBOOST);
+        rrt_status s = check_launch();
+        if (s) return s;
         prof_begin(pr, KI_DO2SH);
-        rrt::launch_do2sh<real>(pr->P * pr->G, pr->K, pr->NL, R(pr->d_WY), R(pr->d_co), R(pr->d_Ilm), pr->stream);
+        s = gemm(pr->P * pr->G, pr->NL, pr->K, R(pr->d_co), R(pr->d_WY), R(pr->d_Ilm));
         prof_end(pr, KI_DO2SH);
+        return s;
     }
 
     // S1: source from d_Ilm into S
@@ -285,12 +321,12 @@ struct Engine {
     // one source iteration from d_S (Iprev/inv_cdt: implicit time terms)
     rrt_status sweep(const void *Iprev, double inv_cdt, double *resid)
     {
-        to_lab(pr->d_S, Iprev, inv_cdt);
-        trace(pr->d_St, pr->d_Xt, pr->d_Ilab);
-        fold(pr->d_Ilab);
-        source(pr->d_Snew);
-        rrt_status s = check_launch();
+        rrt_status s = to_lab(pr->d_S, Iprev, inv_cdt);
         if (s) return s;
+        trace(pr->d_St, pr->d_Ilab, inv_cdt, false);
+        if ((s = fold(pr->d_Ilab))) return s;
+        source(pr->d_Snew);
+        if ((s = check_launch())) return s;
         s = residual(pr->d_Snew, pr->d_S, resid);
         if (s) return s;
         std::swap(pr->d_S, pr->d_Snew);
@@ -300,7 +336,8 @@ struct Engine {
     // initial source: S = source(fold(I)) (thermal only when I = 0)
     rrt_status initial_source(const void *I)
     {
-        fold(I);
+        rrt_status s = fold(I);
+        if (s) return s;
         source(pr->d_S);
         return check_launch();
     }
@@ -439,7 +476,7 @@ struct Engine {
             }
         }
         // comoving SH intensity of the final state, for the comoving moments
-        fold(pr->d_I);
+        if ((s = fold(pr->d_I))) return s;
         *iters = total;
         *res = rmax;
         return check_launch();
@@ -464,6 +501,7 @@ rrt_status check_sizes(const rrt_grid *g, const rrt_groups *gr, const rrt_angles
     if (!(g->lx > 0) || !(g->ly > 0) || !(g->lz > 0)) return fail(RRT_E_INVALID, "domain lengths must be > 0");
     if (a->lmax < 0 || a->n_mu < 2 || a->n_phi < 1) return fail(RRT_E_INVALID, "bad angular sizes");
     if (a->n_mu % 2) return fail(RRT_E_INVALID, "n_mu must be even (no horizontal ordinate)");
+    if ((long)a->n_mu * a->n_phi > 65535) return fail(RRT_E_INVALID, "at most 65535 ordinates");
     if (a->n_mu < a->lmax + 1 || a->n_phi < 2 * a->lmax + 1)
         return fail(RRT_E_INVALID, "ordinate mesh too coarse for lmax (need n_mu >= lmax+1, n_phi >= 2 lmax+1)");
     if (prec != RRT_FP64 && prec != RRT_FP32) return fail(RRT_E_INVALID, "unknown precision");
@@ -480,9 +518,7 @@ rrt_status check_sizes(const rrt_grid *g, const rrt_groups *gr, const rrt_angles
         if (gr->log_centres && !(gr->edges[0] > 0)) return fail(RRT_E_INVALID, "log centres need edges > 0");
         if (sc == RRT_COMPTON && !(gr->mec2 > 0)) return fail(RRT_E_INVALID, "Compton scattering needs mec2 > 0");
     }
-    const size_t esz = prec == RRT_FP64 ? 8 : 4;
-    if (2 * esz * (size_t)g->nx * g->ny > kMaxTraceLds)
-        return fail(RRT_E_INVALID, "an x-y plane is too large for the ray-trace kernel's LDS");
+    (void)prec;
     return RRT_OK;
 }
 
@@ -492,10 +528,11 @@ size_t footprint(const rrt_grid *g, const rrt_groups *gr, const rrt_angles *a, i
     const size_t P = (size_t)g->nx * g->ny * g->nz, G = gr->ngroups, K = (size_t)a->n_mu * a->n_phi;
     const size_t NL = (size_t)(a->lmax + 1) * (a->lmax + 1);
     size_t sh = P * G * NL * esz, dob = P * G * K * esz;
-    size_t total = 3 * sh + 5 * dob;                 // S, Snew, Ilm; co, St, Xt, Ilab, I
+    size_t total = 3 * sh + 4 * dob;                 // S, Snew, Ilm; comoving ordinates, St, Ilab, I
+    total += P * K * esz;                            // lab extinction (one group; G times more if non-grey)
     if (time_dep) total += 2 * dob;                  // stage input, accumulator
     if (use_ng) total += 4 * sh;                     // Ng chain
-    total += P * (2 * G + 4) * esz + P * G * esz;    // fields + chi0
+    total += P * (3 * G + 1) * esz + 4 * P * 8;     // fields, chi0, beta, Gamma
     total += 2 * (size_t)g->nx * g->ny * K * G * esz;  // boundaries
     total += 1 << 20;                                // tables and reductions
     return total;
@@ -521,8 +558,9 @@ void rrt_destroy(rrt_problem *pr)
 {
     if (!pr) return;
     if (pr->stream) (void)hipStreamSynchronize(pr->stream);
-    void *bufs[] = {pr->d_dir, pr->d_mu, pr->d_lnc, pr->d_nu3, pr->d_inv_nu3, pr->d_geo, pr->d_Yt, pr->d_WY, pr->d_A,
-                    pr->d_sg, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_chi0, pr->d_bc[0], pr->d_bc[1],
+    if (pr->blas) (void)rocblas_destroy_handle(pr->blas);
+    void *bufs[] = {pr->d_dir, pr->d_mu, pr->d_lnc, pr->d_nu3, pr->d_inv_nu3, pr->d_inv_dc, pr->d_geo, pr->d_Yt, pr->d_WY,
+                    pr->d_A, pr->d_sg, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_gam, pr->d_chi0, pr->d_chilab, pr->d_bc[0], pr->d_bc[1],
                     pr->d_S, pr->d_Snew, pr->d_Ilm, pr->d_co, pr->d_St, pr->d_Xt, pr->d_Ilab, pr->d_I, pr->d_Iin,
                     pr->d_acc, pr->d_chain[0], pr->d_chain[1], pr->d_chain[2], pr->d_chain[3], pr->d_partial, pr->d_red};
     for (void *b : bufs)
@@ -571,11 +609,33 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
         if (e == hipSuccess) e = rrt::upload_bezier_coefficients();
-        const size_t lim = std::min(kMaxTraceLds, (size_t)lds);
-        if (e == hipSuccess) e = rrt::set_trace_lds_limit(lim);
+        const size_t lim = std::min(kMaxLds, (size_t)lds);
+        if (e == hipSuccess) e = rrt::set_lds_limits(lim);
         if (e != hipSuccess) return bail(fail(RRT_E_DEVICE, std::string("kernel set-up: ") + hipGetErrorString(e)));
-        if (2 * pr->esz * (size_t)pr->nx * pr->ny > lim)
-            return bail(fail(RRT_E_INVALID, "an x-y plane is too large for the ray-trace kernel's LDS on this device"));
+        // sized for a chi~ per group, which also covers the grey and stand-alone cases
+        auto tl = [&](int gc) {
+            return pr->prec == RRT_FP64 ? rrt::trace_lds<double>(pr->nx, pr->ny, gc, 0)
+                                        : rrt::trace_lds<float>(pr->nx, pr->ny, gc, 0);
+        };
+        // groups per ray-trace workgroup: the largest of 4, 2, 1 dividing G that leaves
+        // room for two workgroups per CU, else the largest that fits at all
+        pr->Gc = 0;
+        const char *env = std::getenv("RRT_TRACE_GC");
+        const int want = env ? std::atoi(env) : 0;
+        if ((want == 1 || want == 2) && pr->G % want == 0 && tl(want) <= lim) pr->Gc = want;
+        // one group per workgroup measured fastest on the 32^3 x 16-group jet (MI355X)
+        if (!pr->Gc && tl(1) <= lim) pr->Gc = 1;
+        const size_t need_boost = pr->prec == RRT_FP64 ? rrt::boost_lds<double>(pr->K, pr->G)
+                                                       : rrt::boost_lds<float>(pr->K, pr->G);
+        if (!pr->Gc || (long)pr->nx * pr->ny > (long)rrt::kTraceThreads * rrt::kTraceMaxPts)
+            return bail(fail(RRT_E_INVALID, "an x-y plane is too large for the ray-trace kernel on this device"));
+        if (need_boost > lim)
+            return bail(fail(RRT_E_INVALID, "ordinates x groups per point too large for the frame-transform "
+                                            "kernels' LDS in this precision"));
+        rocblas_status bs = rocblas_create_handle(&pr->blas);
+        if (bs == rocblas_status_success) bs = rocblas_set_stream(pr->blas, pr->stream);
+        if (bs != rocblas_status_success)
+            return bail(fail(RRT_E_DEVICE, std::string("rocBLAS handle: ") + rocblas_status_to_string(bs)));
     }
     // ordinates and SH tables
     rrt::gauss_legendre(pr->nmu, pr->mu, pr->wmu);
@@ -641,20 +701,24 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
             pr->centres[g] = pr->log_centres ? std::sqrt(pr->edges[g] * pr->edges[g + 1]) : 0.5 * (pr->edges[g] + pr->edges[g + 1]);
     }
     {
-        std::vector<double> lnc(G), nu3(G), inu3(G);
+        std::vector<double> lnc(G), nu3(G), inu3(G), idc(std::max(1, G - 1), 0.0);
         for (int g = 0; g < G; ++g) {
             lnc[g] = std::log(pr->centres[g]);
             nu3[g] = pr->centres[g] * pr->centres[g] * pr->centres[g];
             inu3[g] = 1.0 / nu3[g];
         }
+        for (int g = 0; g + 1 < G; ++g) idc[g] = 1.0 / (lnc[g + 1] - lnc[g]);
         if ((s = upload_double(pr, (void **)&pr->d_lnc, lnc)) || (s = upload_double(pr, (void **)&pr->d_nu3, nu3)) ||
-            (s = upload_double(pr, (void **)&pr->d_inv_nu3, inu3)))
+            (s = upload_double(pr, (void **)&pr->d_inv_nu3, inu3)) || (s = upload_double(pr, (void **)&pr->d_inv_dc, idc)))
             return bail(s);
         pr->fi.G = G;
         pr->fi.grey = pr->grey;
         pr->fi.has_lo_ghost = pr->edges[0] > 0.0;
         pr->fi.ghost_lo = pr->edges[0] > 0.0 ? 2.0 * std::log(pr->edges[0]) - lnc[0] : -INFINITY;
         pr->fi.ghost_hi = 2.0 * std::log(pr->edges[G]) - lnc[G - 1];
+        pr->fi.inv_lo = pr->edges[0] > 0.0 ? 1.0 / (lnc[0] - pr->fi.ghost_lo) : 0.0;
+        pr->fi.inv_hi = 1.0 / (pr->fi.ghost_hi - lnc[G - 1]);
+        pr->fi.inv_dc = pr->d_inv_dc;
         pr->fi.lnc = pr->d_lnc;
         pr->fi.nu3 = pr->d_nu3;
         pr->fi.inv_nu3 = pr->d_inv_nu3;
@@ -667,8 +731,8 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
     // state arrays
     const size_t shb = sh_elems(pr) * pr->esz, dob = do_elems(pr) * pr->esz;
     if ((s = dev_alloc(&pr->d_S, shb)) || (s = dev_alloc(&pr->d_Snew, shb)) || (s = dev_alloc(&pr->d_Ilm, shb)) ||
-        (s = dev_alloc(&pr->d_co, dob)) || (s = dev_alloc(&pr->d_St, dob)) || (s = dev_alloc(&pr->d_Xt, dob)) ||
-        (s = dev_alloc(&pr->d_Ilab, dob)) || (s = dev_alloc(&pr->d_I, dob)))
+        (s = dev_alloc(&pr->d_co, dob)) || (s = dev_alloc(&pr->d_St, dob)) || (s = dev_alloc(&pr->d_Ilab, dob)) ||
+        (s = dev_alloc(&pr->d_I, dob)))
         return bail(s);
     {
         hipError_t e = hipMemsetAsync(pr->d_I, 0, dob, pr->stream);
@@ -713,17 +777,47 @@ rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *si
         (s = upload_real(pr, pr->d_bnu, bnu, P * G)))
         return s;
     if (beta) {
-        if ((s = dev_alloc(&pr->d_beta, P * 3 * pr->esz))) return s;
-        if ((s = upload_real(pr, pr->d_beta, beta, P * 3))) return s;
+        std::vector<double> gam(P);
+        for (size_t i = 0; i < P; ++i) {
+            const double b2 = beta[3 * i] * beta[3 * i] + beta[3 * i + 1] * beta[3 * i + 1] + beta[3 * i + 2] * beta[3 * i + 2];
+            gam[i] = 1.0 / std::sqrt(1.0 - b2);
+        }
+        if ((s = dev_alloc((void **)&pr->d_beta, P * 3 * 8)) || (s = dev_alloc((void **)&pr->d_gam, P * 8))) return s;
+        HIPCHK(hipMemcpyAsync(pr->d_beta, beta, P * 3 * 8, hipMemcpyHostToDevice, pr->stream));
+        HIPCHK(hipMemcpyAsync(pr->d_gam, gam.data(), P * 8, hipMemcpyHostToDevice, pr->stream));
+        HIPCHK(hipStreamSynchronize(pr->stream));
     } else {
-        dev_free(pr->d_beta);
+        void *b = pr->d_beta;
+        dev_free(b);
+        pr->d_beta = nullptr;
+        void *gm = pr->d_gam;
+        dev_free(gm);
+        pr->d_gam = nullptr;
     }
-    if (pr->prec == RRT_FP64)
-        rrt::launch_chi0<double>((long)P, (int)G, (const double *)pr->d_kappa, (const double *)pr->d_sigma,
-                                 (const double *)pr->d_sg, (double *)pr->d_chi0, pr->stream);
-    else
-        rrt::launch_chi0<float>((long)P, (int)G, (const float *)pr->d_kappa, (const float *)pr->d_sigma,
-                                (const float *)pr->d_sg, (float *)pr->d_chi0, pr->stream);
+    // extinction independent of frequency: Thomson with the same kappa in every group
+    pr->grey_chi = 1;
+    if (pr->scatter == RRT_COMPTON) pr->grey_chi = 0;
+    for (size_t p = 0; p < P && pr->grey_chi; ++p)
+        for (size_t g = 1; g < G; ++g)
+            if (kappa[p * G + g] != kappa[p * G]) { pr->grey_chi = 0; break; }
+    // lab extinction per (ordinate, point[, group]) of this medium
+    {
+        const size_t nchi = (size_t)pr->K * P * (pr->grey_chi ? 1 : G);
+        void *c = pr->d_chilab;
+        dev_free(c);
+        pr->d_chilab = nullptr;
+        if ((s = dev_alloc(&pr->d_chilab, nchi * pr->esz))) return s;
+    }
+    auto chilab = [&](auto tag) {
+        using real = decltype(tag);
+        rrt::launch_chi0<real>((long)P, (int)G, (const real *)pr->d_kappa, (const real *)pr->d_sigma,
+                               (const real *)pr->d_sg, (real *)pr->d_chi0, pr->stream);
+        rrt::ChiLabArgs<real> c;
+        c.P = (long)P; c.K = pr->K; c.fi = pr->fi; c.chi_grey = pr->grey_chi; c.dir = pr->d_dir;
+        c.chi0 = (const real *)pr->d_chi0; c.beta = pr->d_beta; c.gam = pr->d_gam; c.out = (real *)pr->d_chilab;
+        rrt::launch_chilab<real>(c, pr->stream);
+    };
+    if (pr->prec == RRT_FP64) chilab(0.0); else chilab(0.0f);
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(pr->stream));
     pr->medium_set = true;
@@ -867,9 +961,10 @@ rrt_status rrt_ray_trace(rrt_problem *pr, const double *S_tilde, const double *c
         if (!std::isfinite(S_tilde[i]) || !std::isfinite(chi_tilde[i]) || chi_tilde[i] < 0)
             return fail(RRT_E_INVALID, "S~ must be finite and chi~ finite and >= 0");
     rrt_status s;
+    if ((s = dev_alloc(&pr->d_Xt, n * pr->esz))) return s;
     if ((s = upload_real(pr, pr->d_St, S_tilde, n)) || (s = upload_real(pr, pr->d_Xt, chi_tilde, n))) return s;
     s = dispatch(pr, [&](auto &e) {
-        e.trace(pr->d_St, pr->d_Xt, pr->d_Ilab);
+        e.trace(pr->d_St, pr->d_Ilab, 0.0, true);
         return e.check_launch();
     });
     if (s) return s;

@@ -6,6 +6,8 @@ namespace rrt {
 
 constexpr int kBezTerms64 = 18;   // series terms of the Bezier weights, h < 0.5 (FP64)
 constexpr int kBezTerms32 = 12;   // series terms of the Bezier weights, h < 1   (FP32)
+constexpr int kTraceThreads = 256;  // threads per ray-trace workgroup
+constexpr int kTraceMaxPts = 16;    // grid points of a plane per ray-trace thread (at most)
 
 // Per-ordinate geometry of the plane-to-plane short characteristic: path
 // length ds = dz/|mu| between planes, march direction, and the horizontal
@@ -24,17 +26,27 @@ struct FreqInfo {
     int grey;
     int has_lo_ghost;        // lowest edge > 0: a zero-valued ghost centre below
     double ghost_lo, ghost_hi;
+    double inv_lo, inv_hi;   // 1/(lnc[0]-ghost_lo), 1/(ghost_hi-lnc[G-1])
     const double *lnc;       // [G] ln(centre)
+    const double *inv_dc;    // [G-1] 1/(lnc[g+1]-lnc[g])
     const double *nu3;       // [G] centre^3
     const double *inv_nu3;   // [G] 1/centre^3
 };
 
+// Lab-frame arrays (S~, I, stage inputs) are laid out [k][p][g]: ordinate,
+// point, group innermost.  Comoving ordinate arrays are [p][g][j].
 template <typename real> struct TraceArgs {
-    int nx, ny, nz, G, K;
+    int nx, ny, nz, G, K, Gc;   // Gc groups per workgroup (divides G)
     long P;
     const OrdGeom *geo;
-    const real *St, *Xt, *bc_bot, *bc_top;
-    real *I;
+    const double *dir;          // [K][4]
+    const real *St;             // S~ [k][p][g]
+    const real *Xt;             // chi~ [k][p][g] (stand-alone trace only)
+    const real *chilab;         // lab extinction [k][p] (chi_grey) or [k][p][g]
+    int chi_grey;
+    real inv_cdt;               // 1/(c dt) of the implicit time step, 0 when steady
+    const real *bc_bot, *bc_top;  // [k][ny][nx][g] or NULL
+    real *I;                    // [k][p][g]
 };
 
 template <typename real> struct BoostArgs {
@@ -42,10 +54,24 @@ template <typename real> struct BoostArgs {
     int K, nmu, nphi;
     FreqInfo fi;
     const double *dir, *mu;
-    const real *S0, *Iprev;
+    const real *S0;             // comoving source on the ordinates [p][g][j]
+    const real *Iprev;          // [k][p][g] or NULL
     real inv_cdt;
-    const real *chi0, *beta;
-    real *St, *Xt;
+    const real *chilab;         // [k][p] (chi_grey) or [k][p][g]
+    int chi_grey;
+    const double *beta, *gam;
+    real *St;                   // [k][p][g]
+};
+
+template <typename real> struct ChiLabArgs {
+    long P;
+    int K;
+    FreqInfo fi;
+    int chi_grey;               // chi0 the same for every group: output [k][p]
+    const double *dir;
+    const real *chi0;           // [p][g]
+    const double *beta, *gam;
+    real *out;
 };
 
 template <typename real> struct UnboostArgs {
@@ -53,8 +79,9 @@ template <typename real> struct UnboostArgs {
     int K, nmu, nphi;
     FreqInfo fi;
     const double *dir, *mu;
-    const real *Ilab, *beta;
-    real *I0;
+    const real *Ilab;           // [k][p][g]
+    const double *beta, *gam;
+    real *I0;                   // [p][g][j]
 };
 
 template <typename real> struct SourceArgs {
@@ -66,11 +93,12 @@ template <typename real> struct SourceArgs {
 
 hipError_t upload_bezier_coefficients();
 
-template <typename real> void launch_trace(const TraceArgs<real> &a, hipStream_t st);
+template <typename real> void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st);
 template <typename real> void launch_boost(const BoostArgs<real> &a, hipStream_t st);
 template <typename real> void launch_unboost(const UnboostArgs<real> &a, hipStream_t st);
-template <typename real> void launch_sh2do(long PG, int K, int NL, const real *Yt, const real *S, real *S0, hipStream_t st);
-template <typename real> void launch_do2sh(long PG, int K, int NL, const real *WY, const real *I0, real *Ilm, hipStream_t st);
+template <typename real> size_t trace_lds(int nx, int ny, int Gc, int chi_per_point);
+template <typename real> size_t boost_lds(int K, int G);
+template <typename real> void launch_chilab(const ChiLabArgs<real> &a, hipStream_t st);
 template <typename real> void launch_source(const SourceArgs<real> &a, hipStream_t st);
 template <typename real> void launch_chi0(long P, int G, const real *kappa, const real *sigma, const real *sg, real *chi0, hipStream_t st);
 template <typename real> void launch_moments_lab(long P, int G, int K, const double *dir, const real *I, double *J, double *H, double *Kt, hipStream_t st);
@@ -80,6 +108,6 @@ template <typename real> void launch_ng_dots(long n, const real *s0, const real 
 template <typename real> void launch_combine3(long n, double c0, const real *x0, double c1, const real *x1, double c2, const real *x2, real *out, hipStream_t st);
 template <typename real> void launch_rk_stage(long n, const real *R, real *Iin, real *acc, real *In, int first, int last, real coef, hipStream_t st);
 
-hipError_t set_trace_lds_limit(size_t bytes);
+hipError_t set_lds_limits(size_t bytes);
 
 }  // namespace rrt

@@ -3,6 +3,8 @@
 // evaluated in double, reductions are accumulated in double.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "rrt_kernels.h"
 
 namespace rrt {
@@ -44,6 +46,10 @@ hipError_t upload_bezier_coefficients()
     return hipMemcpyToSymbol(HIP_SYMBOL(c_bez32), c32, sizeof(c32));
 }
 
+// reciprocal: the hardware v_rcp_f32 (1 ulp) in FP32, exact division in FP64
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
+
 template <typename real> struct BezTraits;
 template <> struct BezTraits<double> {
     static constexpr double hs = 0.5;
@@ -55,7 +61,7 @@ template <> struct BezTraits<float> {
     static constexpr float hs = 1.0f;
     static constexpr int nt = kBezTerms32;
     __device__ static float c(int i, int m) { return c_bez32[i][m]; }
-    __device__ static float ex(float h) { return expf(-h); }
+    __device__ static float ex(float h) { return __expf(-h); }
 };
 
 // integral over optical depth [0, h] of the Bezier source times e^{-(h - t)}
@@ -76,7 +82,7 @@ __device__ __forceinline__ void bezier_weights(real h, real &ex, real &w0, real 
         }
         w0 = h * a0; w1 = h * a1; w2 = h * a2; w3 = h * a3;
     } else {
-        const real ih = real(1) / h;
+        const real ih = fast_rcp(h);
         const real E0 = real(1) - ex;
         const real E1 = E0 * ih - ex;
         const real E2 = real(2) * E1 * ih - ex;
@@ -94,8 +100,8 @@ template <typename real>
 __device__ __forceinline__ real fb_slope(real dl, real dr, real hl, real hr)
 {
     if (dl * dr <= real(0)) return real(0);
-    const real al = (real(1) + hr / (hl + hr)) * real(1.0 / 3.0);
-    return dl * dr / (al * dr + (real(1) - al) * dl);
+    const real al = (real(1) + hr * fast_rcp(hl + hr)) * real(1.0 / 3.0);
+    return dl * dr * fast_rcp(al * dr + (real(1) - al) * dl);
 }
 
 template <typename real>
@@ -105,98 +111,36 @@ __device__ __forceinline__ real clamp_between(real v, real a, real b)
     return fmin(fmax(v, lo), hi);
 }
 
-// periodic bilinear value of plane F[ny][nx] at point (i, j) shifted by
+// periodic bilinear value of a plane stored F[(y * nx + x) * ge] (ge values
+// per point, F already offset to the wanted one) at point (i, j) shifted by
 // (ix + fx, iy + fy) cells; ix, iy already reduced into [0, nx), [0, ny)
 template <typename real>
-__device__ __forceinline__ real shifted(const real *__restrict__ F, int i, int j, int nx, int ny,
+__device__ __forceinline__ real shifted(const real *__restrict__ F, int i, int j, int nx, int ny, int ge, int row,
                                         int ix, int iy, real fx, real fy)
 {
     int i0 = i + ix; if (i0 >= nx) i0 -= nx;
     int j0 = j + iy; if (j0 >= ny) j0 -= ny;
     const int i1 = (i0 + 1 == nx) ? 0 : i0 + 1;
     const int j1 = (j0 + 1 == ny) ? 0 : j0 + 1;
-    const real a = F[j0 * nx + i0], b = F[j0 * nx + i1], c = F[j1 * nx + i0], d = F[j1 * nx + i1];
+    const real a = F[j0 * row + i0 * ge], b = F[j0 * row + i1 * ge], c = F[j1 * row + i0 * ge], d = F[j1 * row + i1 * ge];
     return (real(1) - fy) * ((real(1) - fx) * a + fx * b) + fy * ((real(1) - fx) * c + fx * d);
 }
 
 // ---------------------------------------------------------------------------
-// S4: ray trace.  One workgroup per (ordinate, group) marches the z planes
-// from the inflow face; the previous I plane is kept in LDS.
+// launch-order helpers
 // ---------------------------------------------------------------------------
-template <typename real>
-__global__ void __launch_bounds__(256) k_trace(TraceArgs<real> a)
+
+// Workgroups are dispatched round-robin over the 8 XCDs (block b runs on XCD
+// b % 8).  Give each XCD a contiguous range of work items so that neighbours
+// (adjacent points, or the groups of one ordinate) share that XCD's L2.
+__device__ __forceinline__ long xcd_item(long nitems)
 {
-    extern __shared__ unsigned char smem_raw[];
-    real *Ish = reinterpret_cast<real *>(smem_raw);
-    const int kg = blockIdx.x;
-    const int k = kg / a.G;
-    const OrdGeom gm = a.geo[k];
-    const int nx = a.nx, ny = a.ny, nz = a.nz, PL = nx * ny;
-    const long base = (long)kg * a.P;
-    const real *__restrict__ S = a.St + base;
-    const real *__restrict__ X = a.Xt + base;
-    real *__restrict__ Io = a.I + base;
-    const real *__restrict__ bc = gm.up ? a.bc_bot : a.bc_top;
-    const real ds = (real)gm.ds;
-    const real fxu = (real)gm.fx[1], fyu = (real)gm.fy[1];
-    const real fxuu = (real)gm.fx[0], fyuu = (real)gm.fy[0];
-    const real fxd = (real)gm.fx[2], fyd = (real)gm.fy[2];
-    int cur = 0;
-    for (int t = 0; t < nz; ++t) {
-        const int m = gm.up ? t : nz - 1 - t;
-        const int mu_ = gm.up ? t - 1 : nz - t;
-        const int muu = gm.up ? t - 2 : nz + 1 - t;
-        const int md = gm.up ? t + 1 : nz - 2 - t;
-        real *Icur = Ish + cur * PL;
-        const real *Iprv = Ish + (1 - cur) * PL;
-        for (int e = threadIdx.x; e < PL; e += blockDim.x) {
-            real v;
-            if (t == 0) {
-                v = bc ? bc[(long)kg * PL + e] : real(0);
-            } else {
-                const int i = e % nx, j = e / nx;
-                const real Sp = S[(long)m * PL + e], Xp = X[(long)m * PL + e];
-                const real *Su_pl = S + (long)mu_ * PL, *Xu_pl = X + (long)mu_ * PL;
-                const real Su = shifted(Su_pl, i, j, nx, ny, gm.ix[1], gm.iy[1], fxu, fyu);
-                const real Xu = shifted(Xu_pl, i, j, nx, ny, gm.ix[1], gm.iy[1], fxu, fyu);
-                const real Iu = shifted(Iprv, i, j, nx, ny, gm.ix[1], gm.iy[1], fxu, fyu);
-                const real hu = ds * real(0.5) * (Xu + Xp);
-                real dSp = 0, dSu = 0;
-                if (hu > real(0)) {
-                    const real d1 = (Sp - Su) / hu;
-                    if (t <= nz - 2) {
-                        const real Sd = shifted(S + (long)md * PL, i, j, nx, ny, gm.ix[2], gm.iy[2], fxd, fyd);
-                        const real Xd = shifted(X + (long)md * PL, i, j, nx, ny, gm.ix[2], gm.iy[2], fxd, fyd);
-                        const real hd = ds * real(0.5) * (Xp + Xd);
-                        dSp = (hd > real(0)) ? fb_slope(d1, (Sd - Sp) / hd, hu, hd) : real(0);
-                    } else {
-                        dSp = d1;
-                    }
-                    if (t >= 2) {
-                        const real Suu = shifted(S + (long)muu * PL, i, j, nx, ny, gm.ix[0], gm.iy[0], fxuu, fyuu);
-                        const real Xuu = shifted(X + (long)muu * PL, i, j, nx, ny, gm.ix[0], gm.iy[0], fxuu, fyuu);
-                        const real huu = ds * real(0.5) * (Xuu + Xu);
-                        dSu = (huu > real(0)) ? fb_slope((Su - Suu) / huu, d1, huu, hu) : real(0);
-                    } else {
-                        dSu = d1;
-                    }
-                }
-                const real Cu = clamp_between(Su + hu * dSu * real(1.0 / 3.0), Su, Sp);
-                const real Cp = clamp_between(Sp - hu * dSp * real(1.0 / 3.0), Su, Sp);
-                real ex, w0, w1, w2, w3;
-                bezier_weights(hu, ex, w0, w1, w2, w3);
-                v = Iu * ex + w0 * Su + w1 * Cu + w2 * Cp + w3 * Sp;
-            }
-            Icur[e] = v;
-            Io[(long)m * PL + e] = v;
-        }
-        __syncthreads();
-        cur ^= 1;
-    }
+    const long per = (nitems + 7) / 8;
+    return (long)(blockIdx.x % 8) * per + blockIdx.x / 8;
 }
 
 // ---------------------------------------------------------------------------
-// frame transforms
+// frame transforms: shared geometry
 // ---------------------------------------------------------------------------
 
 struct AngleTaps {
@@ -237,28 +181,38 @@ __device__ __forceinline__ AngleTaps angle_taps(const double *__restrict__ mu, i
     return t;
 }
 
-// value of F (F[k * stride], k = a*nphi + b) at the taps
+// taps as kept in LDS, weights in the working precision
+template <typename real> struct TapL {
+    int a0, a1, b0, b1;
+    real wmu, wphi;
+};
+
+// value at the taps of a field F[k * sk + g * sg] (k = ordinate) held in LDS;
+// pole[g] / pole[G + g] are the azimuthal means of the lowest / highest ring
 template <typename real>
-__device__ __forceinline__ real angle_value(const real *__restrict__ F, long stride, int nmu, int nphi, const AngleTaps &t)
+__device__ __forceinline__ real tap_value(const real *F, int sk, int sg, int G, int g, int nmu, int nphi,
+                                          const TapL<real> &t, const real *pole)
 {
     auto ring = [&](int a) -> real {
-        if (a < 0 || a >= nmu) {
-            const int ar = (a < 0) ? 0 : nmu - 1;
-            real s = 0;
-            for (int b = 0; b < nphi; ++b) s += F[(long)(ar * nphi + b) * stride];
-            return s / real(nphi);
-        }
-        const real wp = (real)t.wphi;
-        return (real(1) - wp) * F[(long)(a * nphi + t.b0) * stride] + wp * F[(long)(a * nphi + t.b1) * stride];
+        if (a < 0) return pole[g];
+        if (a >= nmu) return pole[G + g];
+        return (real(1) - t.wphi) * F[(a * nphi + t.b0) * sk + g * sg] + t.wphi * F[(a * nphi + t.b1) * sk + g * sg];
     };
-    const real wm = (real)t.wmu;
-    return (real(1) - wm) * ring(t.a0) + wm * ring(t.a1);
+    return (real(1) - t.wmu) * ring(t.a0) + t.wmu * ring(t.a1);
 }
 
 // frequency bracket in ln(nu): value = wl * v[gl] + wh * v[gh]; gl/gh = -1 means 0
 struct FreqTaps { int gl, gh; double wl, wh; };
 
-__device__ __forceinline__ int centre_bracket(const double *__restrict__ lnc, int G, double x)
+// Group-centre tables staged in LDS.
+struct FreqL {
+    const double *lnc;      // [G] ln(centre)
+    const double *inv_dc;   // [G-1] 1/(lnc[g+1]-lnc[g])
+    const double *nu3;      // [G] centre^3
+    const double *inv_nu3;  // [G] 1/centre^3
+};
+
+__device__ __forceinline__ int centre_bracket(const double *lnc, int G, double x)
 {
     int lo = 0, hi = G - 1;                   // lnc[lo] <= x < lnc[hi]
     while (hi - lo > 1) {
@@ -269,183 +223,460 @@ __device__ __forceinline__ int centre_bracket(const double *__restrict__ lnc, in
 }
 
 // intensity invariants: zero-valued ghost centres beyond the outer edges
-__device__ __forceinline__ FreqTaps freq_taps_zero(const FreqInfo &f, double x)
+__device__ __forceinline__ FreqTaps freq_taps_zero(const FreqInfo &f, const FreqL &l, double x)
 {
     FreqTaps r{-1, -1, 0.0, 0.0};
     const int G = f.G;
-    const double c0 = f.lnc[0], cN = f.lnc[G - 1];
+    const double c0 = l.lnc[0], cN = l.lnc[G - 1];
     if (x < c0) {
         if (!f.has_lo_ghost) { r.gl = 0; r.wl = 1.0; return r; }
         if (x <= f.ghost_lo) return r;
-        r.gl = 0; r.wl = (x - f.ghost_lo) / (c0 - f.ghost_lo);
+        r.gl = 0; r.wl = (x - f.ghost_lo) * f.inv_lo;
         return r;
     }
     if (x >= cN) {
         if (x >= f.ghost_hi) return r;
-        r.gl = G - 1; r.wl = (f.ghost_hi - x) / (f.ghost_hi - cN);
+        r.gl = G - 1; r.wl = (f.ghost_hi - x) * f.inv_hi;
         return r;
     }
-    const int g = centre_bracket(f.lnc, G, x);
-    const double w = (x - f.lnc[g]) / (f.lnc[g + 1] - f.lnc[g]);
+    const int g = centre_bracket(l.lnc, G, x);
+    const double w = (x - l.lnc[g]) * l.inv_dc[g];
     r.gl = g; r.wl = 1.0 - w; r.gh = g + 1; r.wh = w;
     return r;
 }
 
 // opacities: outer values held
-__device__ __forceinline__ FreqTaps freq_taps_hold(const FreqInfo &f, double x)
+__device__ __forceinline__ FreqTaps freq_taps_hold(const FreqInfo &f, const FreqL &l, double x)
 {
     FreqTaps r{-1, -1, 0.0, 0.0};
     const int G = f.G;
-    if (x <= f.lnc[0]) { r.gl = 0; r.wl = 1.0; return r; }
-    if (x >= f.lnc[G - 1]) { r.gl = G - 1; r.wl = 1.0; return r; }
-    const int g = centre_bracket(f.lnc, G, x);
-    const double w = (x - f.lnc[g]) / (f.lnc[g + 1] - f.lnc[g]);
+    if (x <= l.lnc[0]) { r.gl = 0; r.wl = 1.0; return r; }
+    if (x >= l.lnc[G - 1]) { r.gl = G - 1; r.wl = 1.0; return r; }
+    const int g = centre_bracket(l.lnc, G, x);
+    const double w = (x - l.lnc[g]) * l.inv_dc[g];
     r.gl = g; r.wl = 1.0 - w; r.gh = g + 1; r.wh = w;
     return r;
 }
 
-template <typename real>
-__device__ __forceinline__ bool load_beta(const real *__restrict__ beta, long p, double b[3])
+// copy the group-centre tables into LDS (4 G doubles)
+__device__ __forceinline__ FreqL stage_freq(const FreqInfo &fi, double *buf)
+{
+    const int G = fi.G;
+    for (int g = threadIdx.x; g < G; g += blockDim.x) {
+        buf[g] = fi.lnc[g];
+        if (g + 1 < G) buf[G + g] = fi.inv_dc[g];
+        buf[2 * G + g] = fi.nu3[g];
+        buf[3 * G + g] = fi.inv_nu3[g];
+    }
+    return FreqL{buf, buf + G, buf + 2 * G, buf + 3 * G};
+}
+
+__device__ __forceinline__ bool load_beta(const double *__restrict__ beta, long p, double b[3])
 {
     if (!beta) return false;
-    b[0] = (double)beta[3 * p]; b[1] = (double)beta[3 * p + 1]; b[2] = (double)beta[3 * p + 2];
+    b[0] = beta[3 * p]; b[1] = beta[3 * p + 1]; b[2] = beta[3 * p + 2];
     return !(b[0] == 0.0 && b[1] == 0.0 && b[2] == 0.0);
 }
 
-// S3: comoving ordinates -> lab ordinates (Eqs. 7-8, invariants S/nu^3 and
-// chi nu), plus the implicit time terms (Eqs. 5-6).  Thread per (point, k).
+// lab extinction chi_lab = chi0(nu/D)/D (chi nu invariant), with
+// 1/D = nu0/nu = Gamma (1 - beta.n) (Eq. 7); chi0 linear in ln(nu) between
+// centres with the outer values held
+template <typename real>
+__device__ __forceinline__ real chi_lab_of(const real *__restrict__ chi0, long p, int g, const FreqInfo &fi,
+                                           const FreqL &fl, int grey_chi, bool moving, double invD)
+{
+    const int G = fi.G;
+    if (!moving) return chi0[p * G + g];
+    if (grey_chi || fi.grey) return (real)((double)chi0[p * G + g] * invD);
+    const FreqTaps fc = freq_taps_hold(fi, fl, fl.lnc[g] + log(invD));
+    double c = fc.wl * (double)chi0[p * G + fc.gl];
+    if (fc.gh >= 0) c += fc.wh * (double)chi0[p * G + fc.gh];
+    return (real)(c * invD);
+}
+
+__device__ __forceinline__ double inv_doppler(const double b[3], double gam, const double n[3])
+{
+    return gam * (1.0 - (b[0] * n[0] + b[1] * n[1] + b[2] * n[2]));
+}
+
+// ---------------------------------------------------------------------------
+// S4: ray trace.  One workgroup of kTraceThreads per (ordinate, chunk of GC
+// groups) marches the z planes from the inflow face; each thread owns up to
+// kTraceMaxPts grid points of the plane with all GC groups.  The source S~ and
+// extinction chi~ of the four planes a step touches (second upwind, upwind,
+// current, downwind) sit in an LDS ring, the previous intensity plane in LDS;
+// the next plane is fetched into registers while the current one is computed.
+// chi~ = chi_lab + 1/(c dt) with chi_lab precomputed per medium (one value per
+// point when it is grey) or read from an array for the stand-alone entry
+// point.  Lab arrays are [k][p][g]; an LDS plane is [point][group-in-chunk].
+// ---------------------------------------------------------------------------
+template <typename real, bool CHI_ARRAY, int GC, int MAXPT>
+struct PlaneRegs {
+    real s[MAXPT][GC], x[MAXPT][GC];
+};
+
+// global -> registers: S~ and chi~ of plane t for this thread's points
+template <typename real, bool CHI_ARRAY, int GC, int MAXPT>
+__device__ __forceinline__ void trace_fetch(PlaneRegs<real, CHI_ARRAY, GC, MAXPT> &r, const TraceArgs<real> &a,
+                                            const OrdGeom &gm, int k, int g0, int t, bool xg)
+{
+    const int PL = a.nx * a.ny, G = a.G;
+    const int m = gm.up ? t : a.nz - 1 - t;
+#pragma unroll
+    for (int c = 0; c < MAXPT; ++c) {
+        const int pe = threadIdx.x + c * kTraceThreads;
+        if (pe < PL) {
+            const long pidx = (long)m * PL + pe;
+            const long o = ((long)k * a.P + pidx) * G + g0;
+#pragma unroll
+            for (int gi = 0; gi < GC; ++gi) r.s[c][gi] = a.St[o + gi];
+            if (CHI_ARRAY) {
+#pragma unroll
+                for (int gi = 0; gi < GC; ++gi) r.x[c][gi] = a.Xt[o + gi];
+            } else if (xg) {
+                r.x[c][0] = a.chilab[(long)k * a.P + pidx] + a.inv_cdt;
+            } else {
+#pragma unroll
+                for (int gi = 0; gi < GC; ++gi) r.x[c][gi] = a.chilab[o + gi] + a.inv_cdt;
+            }
+        }
+    }
+}
+
+// registers -> the LDS ring slot of plane t
+template <typename real, bool CHI_ARRAY, int GC, int MAXPT>
+__device__ __forceinline__ void trace_store(const PlaneRegs<real, CHI_ARRAY, GC, MAXPT> &r, real *Sr, real *Xr,
+                                            int PL, int t, bool xg)
+{
+    const int NE = PL * GC, XE = xg ? PL : NE;
+    real *Sd = Sr + (t & 3) * NE, *Xd = Xr + (t & 3) * XE;
+#pragma unroll
+    for (int c = 0; c < MAXPT; ++c) {
+        const int pe = threadIdx.x + c * kTraceThreads;
+        if (pe < PL) {
+#pragma unroll
+            for (int gi = 0; gi < GC; ++gi) Sd[pe * GC + gi] = r.s[c][gi];
+            if (xg) {
+                Xd[pe] = r.x[c][0];
+            } else {
+#pragma unroll
+                for (int gi = 0; gi < GC; ++gi) Xd[pe * GC + gi] = r.x[c][gi];
+            }
+        }
+    }
+}
+
+template <typename real, bool CHI_ARRAY, int GC, int MAXPT>
+__global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
+{
+    constexpr int T = kTraceThreads;
+    extern __shared__ unsigned char smem_raw[];
+    const int nx = a.nx, ny = a.ny, nz = a.nz, PL = nx * ny, G = a.G;
+    const int nch = G / GC;
+    const long item = xcd_item((long)a.K * nch);
+    if (item >= (long)a.K * nch) return;
+    const int k = (int)(item / nch), g0 = (int)(item - (long)k * nch) * GC;
+    const int NE = PL * GC;
+    const bool xg = !CHI_ARRAY && a.chi_grey;        // one chi~ per point
+    const int XE = xg ? PL : NE, xge = xg ? 1 : GC;
+    real *Sr = reinterpret_cast<real *>(smem_raw);
+    real *Xr = Sr + 4 * NE;
+    real *Ir = Xr + 4 * XE;
+    const OrdGeom gm = a.geo[k];
+    const long P = a.P;
+    const int tid = threadIdx.x;
+    PlaneRegs<real, CHI_ARRAY, GC, MAXPT> rg;
+
+    for (int t = 0; t < nz && t < 3; ++t) {
+        trace_fetch(rg, a, gm, k, g0, t, xg);
+        trace_store(rg, Sr, Xr, PL, t, xg);
+    }
+    {
+        const int m0 = gm.up ? 0 : nz - 1;
+        const real *__restrict__ bc = gm.up ? a.bc_bot : a.bc_top;
+        for (int pe = tid; pe < PL; pe += T)
+#pragma unroll
+            for (int gi = 0; gi < GC; ++gi) {
+                const real v = bc ? bc[((long)k * PL + pe) * G + g0 + gi] : real(0);
+                Ir[pe * GC + gi] = v;
+                a.I[((long)k * P + (long)m0 * PL + pe) * G + g0 + gi] = v;
+            }
+    }
+    __syncthreads();
+    const real ds = (real)gm.ds;
+    const real fxu = (real)gm.fx[1], fyu = (real)gm.fy[1];
+    const real fxuu = (real)gm.fx[0], fyuu = (real)gm.fy[0];
+    const real fxd = (real)gm.fx[2], fyd = (real)gm.fy[2];
+    const int rowS = nx * GC, rowX = nx * xge;
+    for (int t = 1; t < nz; ++t) {
+        if (t + 2 < nz) trace_fetch(rg, a, gm, k, g0, t + 2, xg);   // in flight while plane t is computed
+        const int m = gm.up ? t : nz - 1 - t;
+        const bool has_d = t <= nz - 2, has_uu = t >= 2;
+        const real *Spl = Sr + (t & 3) * NE, *Xpl = Xr + (t & 3) * XE;
+        const real *Sul = Sr + ((t - 1) & 3) * NE, *Xul = Xr + ((t - 1) & 3) * XE;
+        const real *Suul = Sr + ((t - 2) & 3) * NE, *Xuul = Xr + ((t - 2) & 3) * XE;
+        const real *Sdl = Sr + ((t + 1) & 3) * NE, *Xdl = Xr + ((t + 1) & 3) * XE;
+        const real *Iprv = Ir + ((t - 1) & 1) * NE;
+        real *Icur = Ir + (t & 1) * NE;
+#pragma unroll 1
+        for (int c = 0; c < MAXPT; ++c) {
+            const int pe = tid + c * T;
+            if (pe >= PL) break;
+            const int i = pe % nx, j = pe / nx;
+            real Xp = 0, Xu = 0, Xd = 0, Xuu = 0;
+            if (xg) {
+                Xp = Xpl[pe];
+                Xu = shifted(Xul, i, j, nx, ny, 1, rowX, gm.ix[1], gm.iy[1], fxu, fyu);
+                if (has_d) Xd = shifted(Xdl, i, j, nx, ny, 1, rowX, gm.ix[2], gm.iy[2], fxd, fyd);
+                if (has_uu) Xuu = shifted(Xuul, i, j, nx, ny, 1, rowX, gm.ix[0], gm.iy[0], fxuu, fyuu);
+            }
+            const long og = ((long)k * P + (long)m * PL + pe) * G + g0;
+#pragma unroll
+            for (int gi = 0; gi < GC; ++gi) {
+                if (!xg) {
+                    Xp = Xpl[pe * GC + gi];
+                    Xu = shifted(Xul + gi, i, j, nx, ny, GC, rowX, gm.ix[1], gm.iy[1], fxu, fyu);
+                    if (has_d) Xd = shifted(Xdl + gi, i, j, nx, ny, GC, rowX, gm.ix[2], gm.iy[2], fxd, fyd);
+                    if (has_uu) Xuu = shifted(Xuul + gi, i, j, nx, ny, GC, rowX, gm.ix[0], gm.iy[0], fxuu, fyuu);
+                }
+                const real Sp = Spl[pe * GC + gi];
+                const real Su = shifted(Sul + gi, i, j, nx, ny, GC, rowS, gm.ix[1], gm.iy[1], fxu, fyu);
+                const real Iu = shifted(Iprv + gi, i, j, nx, ny, GC, rowS, gm.ix[1], gm.iy[1], fxu, fyu);
+                const real hu = ds * real(0.5) * (Xu + Xp);
+                real dSp = 0, dSu = 0;
+                if (hu > real(0)) {
+                    const real rhu = fast_rcp(hu);
+                    const real d1 = (Sp - Su) * rhu;
+                    if (has_d) {
+                        const real Sd = shifted(Sdl + gi, i, j, nx, ny, GC, rowS, gm.ix[2], gm.iy[2], fxd, fyd);
+                        const real hd = ds * real(0.5) * (Xp + Xd);
+                        dSp = (hd > real(0)) ? fb_slope(d1, (Sd - Sp) * fast_rcp(hd), hu, hd) : real(0);
+                    } else {
+                        dSp = d1;
+                    }
+                    if (has_uu) {
+                        const real Suu = shifted(Suul + gi, i, j, nx, ny, GC, rowS, gm.ix[0], gm.iy[0], fxuu, fyuu);
+                        const real huu = ds * real(0.5) * (Xuu + Xu);
+                        dSu = (huu > real(0)) ? fb_slope((Su - Suu) * fast_rcp(huu), d1, huu, hu) : real(0);
+                    } else {
+                        dSu = d1;
+                    }
+                }
+                const real Cu = clamp_between(Su + hu * dSu * real(1.0 / 3.0), Su, Sp);
+                const real Cp = clamp_between(Sp - hu * dSp * real(1.0 / 3.0), Su, Sp);
+                real ex, w0, w1, w2, w3;
+                bezier_weights(hu, ex, w0, w1, w2, w3);
+                const real v = Iu * ex + w0 * Su + w1 * Cu + w2 * Cp + w3 * Sp;
+                Icur[pe * GC + gi] = v;
+                a.I[og + gi] = v;
+            }
+        }
+        __syncthreads();
+        if (t + 2 < nz) trace_store(rg, Sr, Xr, PL, t + 2, xg);     // the slot of plane t - 2 is free now
+        __syncthreads();
+    }
+}
+
+// Monotone walk of the centre bracket: x increases with g for a fixed ray, so
+// the bracket of group g + 1 is found by advancing from that of group g.
+struct FreqWalk {
+    int lo;
+};
+
+// intensity invariants: zero-valued ghost centres beyond the outer edges
+__device__ __forceinline__ FreqTaps freq_taps_zero_walk(const FreqInfo &f, const FreqL &l, double x, FreqWalk &w)
+{
+    FreqTaps r{-1, -1, 0.0, 0.0};
+    const int G = f.G;
+    const double c0 = l.lnc[0], cN = l.lnc[G - 1];
+    if (x < c0) {
+        if (!f.has_lo_ghost) { r.gl = 0; r.wl = 1.0; return r; }
+        if (x <= f.ghost_lo) return r;
+        r.gl = 0; r.wl = (x - f.ghost_lo) * f.inv_lo;
+        return r;
+    }
+    if (x >= cN) {
+        if (x >= f.ghost_hi) return r;
+        r.gl = G - 1; r.wl = (f.ghost_hi - x) * f.inv_hi;
+        return r;
+    }
+    int g = w.lo;
+    while (g + 2 < G && x >= l.lnc[g + 1]) ++g;
+    w.lo = g;
+    const double wt = (x - l.lnc[g]) * l.inv_dc[g];
+    r.gl = g; r.wl = 1.0 - wt; r.gh = g + 1; r.wh = wt;
+    return r;
+}
+
+// ---------------------------------------------------------------------------
+// S3: comoving ordinates -> lab ordinates, one workgroup per grid point, one
+// thread per lab ordinate (all groups).  The point's comoving source S0[g][j]
+// (from the SH -> ordinate product) is staged in LDS; the lab source of
+// ordinate k is the bilinear (angle) x linear in ln(nu) remap of the invariant
+// S0/nu^3 at the comoving direction n0 (Eq. 8) and frequency nu/D (Eq. 7) of
+// that ray, times nu^3; then the implicit time terms of Eqs. 5-6 with the lab
+// extinction chi_lab precomputed per medium.  Output S~[k][p][g].
+// ---------------------------------------------------------------------------
 template <typename real>
 __global__ void __launch_bounds__(256) k_boost(BoostArgs<real> a)
 {
-    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int k = blockIdx.y;
+    extern __shared__ unsigned char smem_raw[];
+    const long p = xcd_item(a.P);
     if (p >= a.P) return;
-    const int G = a.fi.G, K = a.K;
-    double n[3] = {a.dir[4 * k], a.dir[4 * k + 1], a.dir[4 * k + 2]};
+    const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x;
+    double *fbuf = reinterpret_cast<double *>(smem_raw);                // [4G]
+    real *sS0 = reinterpret_cast<real *>(fbuf + 4 * G);                 // [G][K]
+    real *sPole = sS0 + G * K;                                          // [2][G]
+
+    const FreqL fl = stage_freq(a.fi, fbuf);
     double b[3];
     const bool moving = load_beta(a.beta, p, b);
-    const real *__restrict__ S0p = a.S0 + (long)p * G * K;
-    const real icdt = a.inv_cdt;
-    if (!moving) {
-        for (int g = 0; g < G; ++g) {
-            const real Sl = S0p[(long)g * K + k];
-            const real chil = a.chi0[p * G + g];
-            const long o = ((long)k * G + g) * a.P + p;
-            const real ip = a.Iprev ? a.Iprev[o] : real(0);
-            const real xt = chil + icdt;
-            a.Xt[o] = xt;
-            a.St[o] = (xt > real(0)) ? (chil * Sl + ip * icdt) / xt : real(0);
+    const real *__restrict__ src = a.S0 + (long)p * G * K;
+    for (int i = tid; i < G * K; i += T) sS0[i] = src[i];
+    __syncthreads();
+    if (moving) {
+        for (int i = tid; i < 2 * G; i += T) {
+            const int g = i % G, ring = (i < G) ? 0 : a.nmu - 1;
+            real s = 0;
+            for (int bb = 0; bb < a.nphi; ++bb) s += sS0[g * K + ring * a.nphi + bb];
+            sPole[i] = s / real(a.nphi);
         }
-        return;
+        __syncthreads();
     }
-    const double b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
-    const double gam = 1.0 / sqrt(1.0 - b2);
-    const double bn = b[0] * n[0] + b[1] * n[1] + b[2] * n[2];
-    const double D = 1.0 / (gam * (1.0 - bn));
-    const double f = gam * (1.0 - gam / (gam + 1.0) * bn);
-    double n0[3];
-    for (int c = 0; c < 3; ++c) n0[c] = D * (n[c] - f * b[c]);
-    const AngleTaps at = angle_taps(a.mu, a.nmu, a.nphi, n0);
-    const double lnD = log(D);
-    for (int g = 0; g < G; ++g) {
-        real Sl, chil;
-        if (a.fi.grey) {
-            const double D2 = D * D;
-            Sl = (real)(D2 * D2) * angle_value(S0p, 1, a.nmu, a.nphi, at);
-            chil = (real)((double)a.chi0[p * G] / D);
-        } else {
-            const double x = a.fi.lnc[g] - lnD;
-            const FreqTaps ft = freq_taps_zero(a.fi, x);
-            double v = 0.0;
-            if (ft.gl >= 0) v += ft.wl * (double)angle_value(S0p + (long)ft.gl * K, 1, a.nmu, a.nphi, at) * a.fi.inv_nu3[ft.gl];
-            if (ft.gh >= 0) v += ft.wh * (double)angle_value(S0p + (long)ft.gh * K, 1, a.nmu, a.nphi, at) * a.fi.inv_nu3[ft.gh];
-            Sl = (real)(a.fi.nu3[g] * v);
-            const FreqTaps fc = freq_taps_hold(a.fi, x);
-            double c = fc.wl * (double)a.chi0[p * G + fc.gl];
-            if (fc.gh >= 0) c += fc.wh * (double)a.chi0[p * G + fc.gh];
-            chil = (real)(c / D);
+    const real icdt = a.inv_cdt;
+    const double gam = moving ? a.gam[p] : 1.0;
+    for (int k = tid; k < K; k += T) {
+        const long o0 = ((long)k * a.P + p) * G;
+        TapL<real> tp{0, 0, 0, 0, 0, 0};
+        double D = 1.0, lnD = 0.0;
+        if (moving) {
+            const double n[3] = {a.dir[4 * k], a.dir[4 * k + 1], a.dir[4 * k + 2]};
+            const double bn = b[0] * n[0] + b[1] * n[1] + b[2] * n[2];
+            D = 1.0 / inv_doppler(b, gam, n);
+            const double f = gam * (1.0 - gam / (gam + 1.0) * bn);
+            double n0[3];
+            for (int c = 0; c < 3; ++c) n0[c] = D * (n[c] - f * b[c]);
+            const AngleTaps at = angle_taps(a.mu, a.nmu, a.nphi, n0);
+            tp = TapL<real>{at.a0, at.a1, at.b0, at.b1, (real)at.wmu, (real)at.wphi};
+            lnD = log(D);
         }
-        const long o = ((long)k * G + g) * a.P + p;
-        const real ip = a.Iprev ? a.Iprev[o] : real(0);
-        const real xt = chil + icdt;
-        a.Xt[o] = xt;
-        a.St[o] = (xt > real(0)) ? (chil * Sl + ip * icdt) / xt : real(0);
+        FreqWalk fw{0};
+        if (moving && !a.fi.grey && G > 2) fw.lo = centre_bracket(fl.lnc, G, fl.lnc[0] - lnD);
+        const real chig = a.chi_grey ? a.chilab[(long)k * a.P + p] : real(0);
+        for (int g = 0; g < G; ++g) {
+            real Sl;
+            if (!moving) {
+                Sl = sS0[g * K + k];
+            } else if (a.fi.grey) {
+                const double D2 = D * D;
+                Sl = (real)(D2 * D2) * tap_value(sS0, 1, K, G, g, a.nmu, a.nphi, tp, sPole);
+            } else {
+                const FreqTaps ft = freq_taps_zero_walk(a.fi, fl, fl.lnc[g] - lnD, fw);
+                double v = 0.0;
+                if (ft.gl >= 0) v += ft.wl * (double)tap_value(sS0, 1, K, G, ft.gl, a.nmu, a.nphi, tp, sPole) * fl.inv_nu3[ft.gl];
+                if (ft.gh >= 0) v += ft.wh * (double)tap_value(sS0, 1, K, G, ft.gh, a.nmu, a.nphi, tp, sPole) * fl.inv_nu3[ft.gh];
+                Sl = (real)(fl.nu3[g] * v);
+            }
+            const real chil = a.chi_grey ? chig : a.chilab[o0 + g];
+            const real ip = a.Iprev ? a.Iprev[o0 + g] : real(0);
+            const real xt = chil + icdt;
+            a.St[o0 + g] = (xt > real(0)) ? (chil * Sl + ip * icdt) / xt : real(0);
+        }
     }
 }
 
-// S5: lab ordinates -> comoving ordinates.  Thread per (point, comoving j).
+// ---------------------------------------------------------------------------
+// S5: lab ordinates -> comoving ordinates, one workgroup per grid point, one
+// thread per comoving ordinate.  The point's lab intensities I[k][g] are
+// staged in LDS; the comoving value of ordinate j is the remap of the
+// invariant I/nu^3 at the lab direction and frequency D' nu of that comoving
+// ray.  Output I0[p][g][j].
+// ---------------------------------------------------------------------------
 template <typename real>
 __global__ void __launch_bounds__(256) k_unboost(UnboostArgs<real> a)
 {
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    const int K = a.K, G = a.fi.G;
-    if (idx >= a.P * K) return;
-    const long p = idx / K;
-    const int j = (int)(idx - p * K);
+    extern __shared__ unsigned char smem_raw[];
+    const long p = xcd_item(a.P);
+    if (p >= a.P) return;
+    const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x;
+    double *fbuf = reinterpret_cast<double *>(smem_raw);                // [4G]
+    real *sI = reinterpret_cast<real *>(fbuf + 4 * G);                  // [K][G] lab
+    real *sPole = sI + K * G;                                           // [2][G]
+
+    const FreqL fl = stage_freq(a.fi, fbuf);
     double b[3];
     const bool moving = load_beta(a.beta, p, b);
+    for (int idx = tid; idx < K * G; idx += T) {
+        const int k = idx / G, g = idx - k * G;
+        sI[idx] = a.Ilab[((long)k * a.P + p) * G + g];
+    }
+    __syncthreads();
     real *__restrict__ out = a.I0 + (long)p * G * K;
-    const long stride = (long)G * a.P;
     if (!moving) {
-        for (int g = 0; g < G; ++g) out[(long)g * K + j] = a.Ilab[((long)j * G + g) * a.P + p];
+        for (int idx = tid; idx < K * G; idx += T) {
+            const int g = idx / K, j = idx - g * K;
+            out[idx] = sI[j * G + g];
+        }
         return;
     }
-    const double n0[3] = {a.dir[4 * j], a.dir[4 * j + 1], a.dir[4 * j + 2]};
-    const double b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
-    const double gam = 1.0 / sqrt(1.0 - b2);
-    const double bn0 = b[0] * n0[0] + b[1] * n0[1] + b[2] * n0[2];
-    const double Dp = gam * (1.0 + bn0);
-    const double f = gam * (1.0 + gam / (gam + 1.0) * bn0);
-    double n[3];
-    for (int c = 0; c < 3; ++c) n[c] = (n0[c] + f * b[c]) / Dp;
-    const AngleTaps at = angle_taps(a.mu, a.nmu, a.nphi, n);
-    if (a.fi.grey) {
-        const double D2 = Dp * Dp;
-        out[j] = (real)((double)angle_value(a.Ilab + p, stride, a.nmu, a.nphi, at) / (D2 * D2));
-        return;
+    for (int i = tid; i < 2 * G; i += T) {
+        const int g = i % G, ring = (i < G) ? 0 : a.nmu - 1;
+        real s = 0;
+        for (int bb = 0; bb < a.nphi; ++bb) s += sI[(ring * a.nphi + bb) * G + g];
+        sPole[i] = s / real(a.nphi);
     }
-    const double lnD = log(Dp);
-    for (int g = 0; g < G; ++g) {
-        const FreqTaps ft = freq_taps_zero(a.fi, a.fi.lnc[g] + lnD);
-        double v = 0.0;
-        if (ft.gl >= 0) v += ft.wl * (double)angle_value(a.Ilab + (long)ft.gl * a.P + p, stride, a.nmu, a.nphi, at) * a.fi.inv_nu3[ft.gl];
-        if (ft.gh >= 0) v += ft.wh * (double)angle_value(a.Ilab + (long)ft.gh * a.P + p, stride, a.nmu, a.nphi, at) * a.fi.inv_nu3[ft.gh];
-        out[(long)g * K + j] = (real)(a.fi.nu3[g] * v);
+    __syncthreads();
+    const double gam = a.gam[p];
+    for (int j = tid; j < K; j += T) {
+        const double n0[3] = {a.dir[4 * j], a.dir[4 * j + 1], a.dir[4 * j + 2]};
+        const double bn0 = b[0] * n0[0] + b[1] * n0[1] + b[2] * n0[2];
+        const double Dp = gam * (1.0 + bn0);
+        const double f = gam * (1.0 + gam / (gam + 1.0) * bn0);
+        double n[3];
+        for (int c = 0; c < 3; ++c) n[c] = (n0[c] + f * b[c]) / Dp;
+        const AngleTaps at = angle_taps(a.mu, a.nmu, a.nphi, n);
+        const TapL<real> tp{at.a0, at.a1, at.b0, at.b1, (real)at.wmu, (real)at.wphi};
+        const double lnD = log(Dp);
+        FreqWalk fw{0};
+        if (!a.fi.grey && G > 2) fw.lo = centre_bracket(fl.lnc, G, fl.lnc[0] + lnD);
+        for (int g = 0; g < G; ++g) {
+            real v;
+            if (a.fi.grey) {
+                const double D2 = Dp * Dp;
+                v = (real)((double)tap_value(sI, G, 1, G, g, a.nmu, a.nphi, tp, sPole) / (D2 * D2));
+            } else {
+                const FreqTaps ft = freq_taps_zero_walk(a.fi, fl, fl.lnc[g] + lnD, fw);
+                double s = 0.0;
+                if (ft.gl >= 0) s += ft.wl * (double)tap_value(sI, G, 1, G, ft.gl, a.nmu, a.nphi, tp, sPole) * fl.inv_nu3[ft.gl];
+                if (ft.gh >= 0) s += ft.wh * (double)tap_value(sI, G, 1, G, ft.gh, a.nmu, a.nphi, tp, sPole) * fl.inv_nu3[ft.gh];
+                v = (real)(fl.nu3[g] * s);
+            }
+            out[(long)g * K + j] = v;
+        }
     }
 }
 
-// ---------------------------------------------------------------------------
-// S2, S6: SH <-> ordinates
-// ---------------------------------------------------------------------------
-
-// S0[p][g][k] = sum_q Y[k][q] S[p][g][q]   (Yt stored [q][k])
+// lab extinction chi_lab(k, p[, g]) of the medium (stored [k][p] when chi0 is
+// the same for every group, else [k][p][g])
 template <typename real>
-__global__ void __launch_bounds__(256) k_sh2do(long PG, int K, int NL, const real *__restrict__ Yt,
-                                               const real *__restrict__ S, real *__restrict__ S0)
+__global__ void __launch_bounds__(256) k_chilab(ChiLabArgs<real> a)
 {
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= PG * K) return;
-    const long pg = idx / K;
-    const int k = (int)(idx - pg * K);
-    const real *s = S + pg * NL;
-    real v = 0;
-    for (int q = 0; q < NL; ++q) v += Yt[(long)q * K + k] * s[q];
-    S0[idx] = v;
-}
-
-// I[p][g][q] = sum_k w_k Y[k][q] I0[p][g][k]   (WY stored [k][q])
-template <typename real>
-__global__ void __launch_bounds__(256) k_do2sh(long PG, int K, int NL, const real *__restrict__ WY,
-                                               const real *__restrict__ I0, real *__restrict__ Ilm)
-{
-    const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= PG * NL) return;
-    const long pg = idx / NL;
-    const int q = (int)(idx - pg * NL);
-    const real *x = I0 + pg * K;
-    real v = 0;
-    for (int k = 0; k < K; ++k) v += WY[(long)k * NL + q] * x[k];
-    Ilm[idx] = v;
+    extern __shared__ unsigned char smem_raw[];
+    double *fbuf = reinterpret_cast<double *>(smem_raw);
+    const FreqL fl = stage_freq(a.fi, fbuf);
+    __syncthreads();
+    const int Gn = a.chi_grey ? 1 : a.fi.G;
+    const long n = a.P * Gn;
+    const int k = blockIdx.y;
+    const double nk[3] = {a.dir[4 * k], a.dir[4 * k + 1], a.dir[4 * k + 2]};
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const long p = i / Gn;
+        const int g = (int)(i - p * Gn);
+        double b[3];
+        const bool moving = load_beta(a.beta, p, b);
+        const double invD = moving ? inv_doppler(b, a.gam[p], nk) : 1.0;
+        a.out[(long)k * n + i] = chi_lab_of(a.chi0, p, g, a.fi, fl, a.chi_grey, moving, invD);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -503,12 +734,12 @@ __global__ void __launch_bounds__(256) k_moments_lab(long P, int G, int K, const
 {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= P * G) return;
-    const int g = (int)(idx / P);
-    const long p = idx - (long)g * P;
+    const long p = idx / G;
+    const int g = (int)(idx - p * G);
     double j = 0, h0 = 0, h1 = 0, h2 = 0, k0 = 0, k1 = 0, k2 = 0, k3 = 0, k4 = 0, k5 = 0;
     for (int k = 0; k < K; ++k) {
         const double nx = dir[4 * k], ny = dir[4 * k + 1], nz = dir[4 * k + 2], w = dir[4 * k + 3];
-        const double v = w * (double)I[((long)k * G + g) * P + p];
+        const double v = w * (double)I[(long)k * P * G + idx];
         j += v; h0 += v * nx; h1 += v * ny; h2 += v * nz;
         k0 += v * nx * nx; k1 += v * ny * ny; k2 += v * nz * nz;
         k3 += v * nx * ny; k4 += v * nx * nz; k5 += v * ny * nz;
@@ -667,30 +898,54 @@ __global__ void k_rk_stage(long n, const real *__restrict__ R, real *__restrict_
 static inline unsigned blocks_for(long n, int bs) { return (unsigned)((n + bs - 1) / bs); }
 
 template <typename real>
-void launch_trace(const TraceArgs<real> &a, hipStream_t st)
+size_t trace_lds(int nx, int ny, int Gc, int chi_per_point)
 {
-    const size_t sm = 2 * sizeof(real) * (size_t)a.nx * a.ny;
-    hipLaunchKernelGGL(k_trace<real>, dim3(a.K * a.G), dim3(256), sm, st, a);
+    return sizeof(real) * (size_t)nx * ny * (6 * (size_t)Gc + 4 * (chi_per_point ? 1 : (size_t)Gc));
+}
+template <typename real>
+void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st)
+{
+    const size_t sm = trace_lds<real>(a.nx, a.ny, a.Gc, !chi_array && a.chi_grey);
+    const long items = (long)a.K * (a.G / a.Gc);
+    const dim3 grid((unsigned)(8 * ((items + 7) / 8))), block(kTraceThreads);
+    const int npt = (a.nx * a.ny + kTraceThreads - 1) / kTraceThreads;
+#define RRT_TRACE_CASE(GC, MP)                                                                     \
+    if (a.Gc == GC && npt <= MP) {                                                                 \
+        if (chi_array) hipLaunchKernelGGL((k_trace<real, true, GC, MP>), grid, block, sm, st, a);  \
+        else hipLaunchKernelGGL((k_trace<real, false, GC, MP>), grid, block, sm, st, a);           \
+        return;                                                                                    \
+    }
+    RRT_TRACE_CASE(1, 1)
+    RRT_TRACE_CASE(1, 4)
+    RRT_TRACE_CASE(1, 16)
+    RRT_TRACE_CASE(2, 1)
+    RRT_TRACE_CASE(2, 4)
+    RRT_TRACE_CASE(2, 16)
+#undef RRT_TRACE_CASE
+}
+template <typename real>
+size_t boost_lds(int K, int G)
+{
+    return 4 * sizeof(double) * G + sizeof(real) * ((size_t)K * G + 2 * G);
+}
+template <typename real>
+void launch_chilab(const ChiLabArgs<real> &a, hipStream_t st)
+{
+    const long n = a.P * (a.chi_grey ? 1 : a.fi.G);
+    const unsigned nb = (unsigned)std::min<long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_chilab<real>, dim3(nb, a.K), dim3(256), 4 * sizeof(double) * a.fi.G, st, a);
 }
 template <typename real>
 void launch_boost(const BoostArgs<real> &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_boost<real>, dim3(blocks_for(a.P, 256), a.K), dim3(256), 0, st, a);
+    const unsigned nb = (unsigned)(8 * ((a.P + 7) / 8));
+    hipLaunchKernelGGL(k_boost<real>, dim3(nb), dim3(256), boost_lds<real>(a.K, a.fi.G), st, a);
 }
 template <typename real>
 void launch_unboost(const UnboostArgs<real> &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_unboost<real>, dim3(blocks_for(a.P * a.K, 256)), dim3(256), 0, st, a);
-}
-template <typename real>
-void launch_sh2do(long PG, int K, int NL, const real *Yt, const real *S, real *S0, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_sh2do<real>, dim3(blocks_for(PG * K, 256)), dim3(256), 0, st, PG, K, NL, Yt, S, S0);
-}
-template <typename real>
-void launch_do2sh(long PG, int K, int NL, const real *WY, const real *I0, real *Ilm, hipStream_t st)
-{
-    hipLaunchKernelGGL(k_do2sh<real>, dim3(blocks_for(PG * NL, 256)), dim3(256), 0, st, PG, K, NL, WY, I0, Ilm);
+    const unsigned nb = (unsigned)(8 * ((a.P + 7) / 8));
+    hipLaunchKernelGGL(k_unboost<real>, dim3(nb), dim3(256), boost_lds<real>(a.K, a.fi.G), st, a);
 }
 template <typename real>
 void launch_source(const SourceArgs<real> &a, hipStream_t st)
@@ -737,21 +992,50 @@ void launch_rk_stage(long n, const real *R, real *Iin, real *acc, real *In, int 
     hipLaunchKernelGGL(k_rk_stage<real>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, R, Iin, acc, In, first, last, coef);
 }
 
-hipError_t set_trace_lds_limit(size_t bytes)
+hipError_t set_lds_limits(size_t bytes)
 {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(&k_trace<float>),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
-    if (e != hipSuccess) return e;
-    return hipFuncSetAttribute(reinterpret_cast<const void *>(&k_trace<double>),
-                               hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+    const void *fns[] = {reinterpret_cast<const void *>(&k_trace<float, true, 1, 1>),
+                         reinterpret_cast<const void *>(&k_trace<float, true, 1, 4>),
+                         reinterpret_cast<const void *>(&k_trace<float, true, 1, 16>),
+                         reinterpret_cast<const void *>(&k_trace<float, true, 2, 1>),
+                         reinterpret_cast<const void *>(&k_trace<float, true, 2, 4>),
+                         reinterpret_cast<const void *>(&k_trace<float, true, 2, 16>),
+                         reinterpret_cast<const void *>(&k_trace<float, false, 1, 1>),
+                         reinterpret_cast<const void *>(&k_trace<float, false, 1, 4>),
+                         reinterpret_cast<const void *>(&k_trace<float, false, 1, 16>),
+                         reinterpret_cast<const void *>(&k_trace<float, false, 2, 1>),
+                         reinterpret_cast<const void *>(&k_trace<float, false, 2, 4>),
+                         reinterpret_cast<const void *>(&k_trace<float, false, 2, 16>),
+                         reinterpret_cast<const void *>(&k_trace<double, true, 1, 1>),
+                         reinterpret_cast<const void *>(&k_trace<double, true, 1, 4>),
+                         reinterpret_cast<const void *>(&k_trace<double, true, 1, 16>),
+                         reinterpret_cast<const void *>(&k_trace<double, true, 2, 1>),
+                         reinterpret_cast<const void *>(&k_trace<double, true, 2, 4>),
+                         reinterpret_cast<const void *>(&k_trace<double, true, 2, 16>),
+                         reinterpret_cast<const void *>(&k_trace<double, false, 1, 1>),
+                         reinterpret_cast<const void *>(&k_trace<double, false, 1, 4>),
+                         reinterpret_cast<const void *>(&k_trace<double, false, 1, 16>),
+                         reinterpret_cast<const void *>(&k_trace<double, false, 2, 1>),
+                         reinterpret_cast<const void *>(&k_trace<double, false, 2, 4>),
+                         reinterpret_cast<const void *>(&k_trace<double, false, 2, 16>),
+                         reinterpret_cast<const void *>(&k_boost<float>),
+                         reinterpret_cast<const void *>(&k_boost<double>),
+                         reinterpret_cast<const void *>(&k_unboost<float>),
+                         reinterpret_cast<const void *>(&k_unboost<double>)};
+    for (const void *f : fns) {
+        hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 #define RRT_INSTANTIATE(real)                                                                                  \
-    template void launch_trace<real>(const TraceArgs<real> &, hipStream_t);                                     \
+    template void launch_trace<real>(const TraceArgs<real> &, bool, hipStream_t);                              \
     template void launch_boost<real>(const BoostArgs<real> &, hipStream_t);                                     \
     template void launch_unboost<real>(const UnboostArgs<real> &, hipStream_t);                                 \
-    template void launch_sh2do<real>(long, int, int, const real *, const real *, real *, hipStream_t);          \
-    template void launch_do2sh<real>(long, int, int, const real *, const real *, real *, hipStream_t);          \
+    template size_t trace_lds<real>(int, int, int, int);                                                       \
+    template size_t boost_lds<real>(int, int);                                                                 \
+    template void launch_chilab<real>(const ChiLabArgs<real> &, hipStream_t);                                   \
     template void launch_source<real>(const SourceArgs<real> &, hipStream_t);                                   \
     template void launch_chi0<real>(long, int, const real *, const real *, const real *, real *, hipStream_t);  \
     template void launch_moments_lab<real>(long, int, int, const double *, const real *, double *, double *,    \

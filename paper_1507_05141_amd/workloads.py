@@ -19,7 +19,7 @@ A problem description is a plain dict:
   beta   (P, 3) or None      flow velocity v/c
   kte    (P,) or None        electron temperature (same units as the edges)
   bc_bot, bc_top             incoming lab intensity on z = 0 / z = lz,
-                             (K, G, ny, nx) or None for vacuum
+                             (K, ny, nx, G) or None for vacuum
 with the point index p = (z*ny + y)*nx + x.
 
 Workloads (the paper's own test problems are two-dimensional; these are the
@@ -161,6 +161,6 @@ def random_medium(n=8, nz=None, ng=4, lmax=3, nmu=4, nphi=8, seed=11, scatter="t
                 mec2=1.0 if not log_centres else MEC2_KEV,
                 kappa=gen.uniform(0.2, 2.0, (P, ng)), sigma=10.0 ** gen.uniform(-1, 1, P),
                 bnu=gen.uniform(0.5, 2.0, (P, ng)), beta=beta, kte=None,
-                bc_bot=gen.uniform(0.0, 1.0, (K, ng, n, n)) if with_bc else None,
-                bc_top=gen.uniform(0.0, 1.0, (K, ng, n, n)) if with_bc else None)
+                bc_bot=gen.uniform(0.0, 1.0, (K, n, n, ng)) if with_bc else None,
+                bc_top=gen.uniform(0.0, 1.0, (K, n, n, ng)) if with_bc else None)
     return spec

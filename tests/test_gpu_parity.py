@@ -51,8 +51,8 @@ def custom_spec(nx, ny, nz, G=3, lmax=3, nmu=4, nphi=8, seed=0, scatter="thomson
                 mec2=mec2 if mec2 is not None else (1.0 if scatter == "compton" else W.MEC2_KEV),
                 kappa=rs.uniform(0.1, 2.0, (P, G)), sigma=10 ** rs.uniform(-1, 1, P),
                 bnu=rs.uniform(0.2, 2.0, (P, G)), beta=beta, kte=None,
-                bc_bot=rs.uniform(0, 1, (K, G, ny, nx)) if with_bc else None,
-                bc_top=rs.uniform(0, 1, (K, G, ny, nx)) if with_bc else None)
+                bc_bot=rs.uniform(0, 1, (K, ny, nx, G)) if with_bc else None,
+                bc_top=rs.uniform(0, 1, (K, ny, nx, G)) if with_bc else None)
 
 
 CASES = {
@@ -82,10 +82,10 @@ def test_ray_trace_parity(prec):
     rs = np.random.default_rng(11)
     St = rs.uniform(0.0, 2.0, o.lab_shape())
     Xt = 10 ** rs.uniform(-1.5, 1.5, o.lab_shape())
-    Xt[:, :, : spec["nx"]] = 0.0                            # a vacuum row: h = 0 branches
+    Xt[:, : spec["nx"], :] = 0.0                            # a vacuum row: h = 0 branches
     ref = o.trace(St, Xt)
     got = g.ray_trace(St, Xt)
-    close_by_group(got, ref, TOL[prec], 1, "I")
+    close_by_group(got, ref, TOL[prec], 2, "I")
     g.close()
 
 
@@ -99,7 +99,7 @@ def test_sweep_parity(case, prec):
     ref_I, ref_Ilm, ref_S, ref_r = o.sweep(S)
     g.set_source_sh(S)
     info = g.sweep()
-    close_by_group(g.sweep_intensity(), ref_I, TOL[prec], 1, "I_lab")
+    close_by_group(g.sweep_intensity(), ref_I, TOL[prec], 2, "I_lab")
     close_by_group(g.intensity_sh(), ref_Ilm, TOL[prec], 1, "I_lm")
     close_by_group(g.source_sh(), ref_S, TOL[prec], 1, "S_new")
     assert abs(info["residual"] - ref_r.max()) <= 10 * TOL[prec] * max(1.0, ref_r.max())
@@ -118,7 +118,7 @@ def test_time_dependent_sweep_parity(prec):
     g.set_intensity(I_prev)
     g.set_source_sh(S)
     g.sweep(dt)
-    close_by_group(g.sweep_intensity(), ref_I, TOL[prec], 1, "I_lab")
+    close_by_group(g.sweep_intensity(), ref_I, TOL[prec], 2, "I_lab")
     close_by_group(g.source_sh(), ref_S, TOL[prec], 1, "S_new")
     g.close()
 
@@ -157,7 +157,7 @@ def test_small_jet_time_steps_parity(prec):
     I_ref, last = o.advance(None, dt, nsteps=2, scheme="rk4", tol=1e-12, max_iter=100)
     g.advance(dt, nsteps=2, scheme=B.SCHEME_RK4, tol=tol, max_iter=100)
     rt = 1e-10 if prec == B.FP64 else 1e-5
-    close_by_group(g.intensity(), I_ref, rt, 1, "I")
+    close_by_group(g.intensity(), I_ref, rt, 2, "I")
     _close_moments(g.moments(B.FRAME_LAB), o.moments_lab(I_ref), rt, "lab")
     _close_moments(g.moments(B.FRAME_COMOVING), o.moments_comoving(o.fold(I_ref)), rt, "comoving")
     g.close()
@@ -173,7 +173,7 @@ def test_full_size_thomson_jet_sweep_fp32():
     ref_I, ref_Ilm, ref_S, _ = o.sweep(S, I_prev, 0.0)
     g.set_source_sh(S)
     g.sweep()
-    close_by_group(g.sweep_intensity(), ref_I, 1e-5, 1, "I_lab")
+    close_by_group(g.sweep_intensity(), ref_I, 1e-5, 2, "I_lab")
     close_by_group(g.intensity_sh(), ref_Ilm, 1e-5, 1, "I_lm")
     close_by_group(g.source_sh(), ref_S, 1e-5, 1, "S_new")
     g.close()

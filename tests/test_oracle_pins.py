@@ -301,9 +301,9 @@ def test_isotropic_boost_is_exact_for_an_invariant_linear_in_log_nu():
             ok = (x >= lo) & (x <= hi)
             s_lab = nu[g] ** 3 * (a + b * x)
             chi_lab = chi0 / D
-            ref = (chi_lab * s_lab + I_prev[:, g, p] * icdt) / (chi_lab + icdt)
-            assert np.allclose(Xt[ok, g, p], (chi_lab + icdt)[ok], rtol=1e-13, atol=0)
-            assert np.allclose(St[ok, g, p], ref[ok], rtol=1e-12, atol=0)
+            ref = (chi_lab * s_lab + I_prev[:, p, g] * icdt) / (chi_lab + icdt)
+            assert np.allclose(Xt[ok, p, g], (chi_lab + icdt)[ok], rtol=1e-13, atol=0)
+            assert np.allclose(St[ok, p, g], ref[ok], rtol=1e-12, atol=0)
             checked += ok.sum()
     assert checked > 1000
 
@@ -340,7 +340,7 @@ def test_grey_unboost_inverse_map():
     o = oracle.Oracle(spec_uniform(n=2, nz=2, nmu=8, nphi=16, lmax=3, beta=[0, 0, bv]))
     dirs, mu, _ = ordinate_dirs(o)
     I_lab = np.zeros(o.lab_shape())
-    I_lab[:, 0, :] = (a + b * mu)[:, None]
+    I_lab[:, :, 0] = (a + b * mu)[:, None]
     I0 = o.unboost(I_lab)
     gam = 1 / math.sqrt(1 - bv * bv)
     mu_lab = (mu + bv) / (1 + bv * mu)             # lab direction of each comoving ordinate
@@ -399,17 +399,17 @@ def test_free_streaming_translates_the_inflow_pattern():
     lx = n * dz * tan                 # one cell of horizontal travel per plane
     K = nmu * nphi
     rs = np.random.default_rng(7)
-    bc = np.zeros((K, 1, n, n))
+    bc = np.zeros((K, n, n, 1))
     k = a * nphi
-    bc[k, 0] = rs.uniform(0, 1, (n, n))
+    bc[k, :, :, 0] = rs.uniform(0, 1, (n, n))
     o = oracle.Oracle(spec_uniform(n=n, nz=nz, nmu=nmu, nphi=nphi, lmax=3, kappa=0.0, lx=lx, lz=lz,
                                    bc_bot=bc))
     St = np.zeros(o.lab_shape())
     I = o.trace(St, np.zeros(o.lab_shape()))
-    planes = I[k, 0].reshape(nz, n, n)
+    planes = I[k, :, 0].reshape(nz, n, n)
     for m in range(nz):
-        assert np.allclose(planes[m], np.roll(bc[k, 0], m, axis=1), atol=1e-12)
-    others = np.delete(I[:, 0], k, axis=0)
+        assert np.allclose(planes[m], np.roll(bc[k, :, :, 0], m, axis=1), atol=1e-12)
+    others = np.delete(I[:, :, 0], k, axis=0)
     assert np.abs(others).max() == 0.0
 
 
@@ -417,7 +417,7 @@ def test_pure_absorption_attenuation():
     n, nz, alpha = 3, 7, 1.7
     nmu, nphi = 4, 8
     K = nmu * nphi
-    bc = np.ones((K, 1, n, n))
+    bc = np.ones((K, n, n, 1))
     o = oracle.Oracle(spec_uniform(n=n, nz=nz, nmu=nmu, nphi=nphi, kappa=alpha, bc_bot=bc, bc_top=bc))
     res = o.solve(tol=1e-14, max_iter=5)
     I = res["I_lab"].reshape(K, nz, n, n)
@@ -455,7 +455,7 @@ def test_short_characteristics_equal_long_characteristics_for_linear_source():
     a0, a1, chi = 0.3, 1.4, 2.2
     z = np.arange(n) / (n - 1)
     St = np.zeros(o.lab_shape())
-    St[:] = np.repeat(a0 + a1 * z, n * n)[None, None, :]
+    St[:] = np.repeat(a0 + a1 * z, n * n)[None, :, None]
     Xt = np.full(o.lab_shape(), chi)
     I = o.trace(St, Xt)
     dirs, mu, _ = ordinate_dirs(o)
@@ -464,7 +464,7 @@ def test_short_characteristics_equal_long_characteristics_for_linear_source():
             p = np.array([0.25, 0.5, z[m] if mu[k] > 0 else z[n - 1 - m]])
             ref = _lc_ray_integral(p, dirs[k], lambda r: a0 + a1 * r[2], lambda r: chi, lambda r: 0.0, 1.0)
             idx = ((m if mu[k] > 0 else n - 1 - m) * n + 2) * n + 1
-            assert abs(I[k, 0, idx] - ref) < 1e-11 * max(1.0, abs(ref)), (k, m)
+            assert abs(I[k, idx, 0] - ref) < 1e-11 * max(1.0, abs(ref)), (k, m)
 
 
 @pytest.mark.slow
@@ -484,8 +484,8 @@ def test_short_characteristics_converge_to_long_characteristics_3d():
         X, Yc, Z = W.grid_coords(n)
         s_pts = np.array([S_fun(r) for r in zip(X, Yc, Z)])
         x_pts = np.array([X_fun(r) for r in zip(X, Yc, Z)])
-        St = np.broadcast_to(s_pts, o.lab_shape()).copy()
-        Xt = np.broadcast_to(x_pts, o.lab_shape()).copy()
+        St = np.broadcast_to(s_pts[:, None], o.lab_shape()).copy()
+        Xt = np.broadcast_to(x_pts[:, None], o.lab_shape()).copy()
         I = o.trace(St, Xt)
         dirs, mu, _ = ordinate_dirs(o)
         e = 0.0
@@ -494,7 +494,7 @@ def test_short_characteristics_converge_to_long_characteristics_3d():
                 i, j, m = int(round(t[0] * n)), int(round(t[1] * n)), int(round(t[2] * (n - 1)))
                 p = np.array([i / n, j / n, m / (n - 1)])
                 ref = _lc_ray_integral(p, dirs[k], S_fun, X_fun, lambda r: 0.0, 1.0)
-                e = max(e, abs(I[k, 0, (m * n + j) * n + i] - ref))
+                e = max(e, abs(I[k, (m * n + j) * n + i, 0] - ref))
         errs.append(e)
     assert errs[1] < 0.7 * errs[0] and errs[2] < 0.7 * errs[1], errs
 
@@ -503,7 +503,7 @@ def test_isotropic_field_has_eddington_factor_one_third():
     n, nmu, nphi = 5, 8, 16
     K = nmu * nphi
     B = 1.7
-    bc = np.full((K, 1, n, n), B)
+    bc = np.full((K, n, n, 1), B)
     o = oracle.Oracle(spec_uniform(n=n, nmu=nmu, nphi=nphi, lmax=3, kappa=0.6, sigma=1.3, B=B,
                                    bc_bot=bc, bc_top=bc))
     res = o.solve(tol=1e-14, max_iter=100)
@@ -654,8 +654,8 @@ def test_backward_euler_front_moves_at_c():
     nsteps = 24
     out = {}
     for alpha in (0.0, 0.8):
-        bc = np.zeros((K, 1, n, n))
-        bc[(nmu - 1) * nphi, 0] = 1.0
+        bc = np.zeros((K, n, n, 1))
+        bc[(nmu - 1) * nphi] = 1.0
         o = oracle.Oracle(spec_uniform(n=n, nz=nz, nmu=nmu, nphi=nphi, lmax=3, kappa=alpha, bc_bot=bc))
         I, _ = o.advance(None, dt, nsteps=nsteps, scheme="euler", tol=1e-14, max_iter=3)
         k = (nmu - 1) * nphi
