@@ -719,6 +719,20 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
         pr->fi.inv_lo = pr->edges[0] > 0.0 ? 1.0 / (lnc[0] - pr->fi.ghost_lo) : 0.0;
         pr->fi.inv_hi = 1.0 / (pr->fi.ghost_hi - lnc[G - 1]);
         pr->fi.inv_dc = pr->d_inv_dc;
+        // groups uniform in ln(nu): constant ln spacing of the edges (then the ghost
+        // centres sit one spacing beyond the outer centres)
+        pr->fi.uniform = 0;
+        if (!pr->grey && G >= 2 && pr->log_centres && pr->edges[0] > 0.0) {
+            const double d = std::log(pr->edges[1] / pr->edges[0]);
+            bool uni = d > 0.0;
+            for (int g = 1; g < G && uni; ++g)
+                if (std::fabs(std::log(pr->edges[g + 1] / pr->edges[g]) - d) > 1e-12 * d) uni = false;
+            if (uni) {
+                pr->fi.uniform = 1;
+                pr->fi.delta = d;
+                pr->fi.inv_delta = 1.0 / d;
+            }
+        }
         pr->fi.lnc = pr->d_lnc;
         pr->fi.nu3 = pr->d_nu3;
         pr->fi.inv_nu3 = pr->d_inv_nu3;

@@ -27,6 +27,8 @@ struct FreqInfo {
     int has_lo_ghost;        // lowest edge > 0: a zero-valued ghost centre below
     double ghost_lo, ghost_hi;
     double inv_lo, inv_hi;   // 1/(lnc[0]-ghost_lo), 1/(ghost_hi-lnc[G-1])
+    int uniform;             // centres uniform in ln(nu) with the ghosts one spacing out
+    double delta, inv_delta; // that spacing and its reciprocal
     const double *lnc;       // [G] ln(centre)
     const double *inv_dc;    // [G-1] 1/(lnc[g+1]-lnc[g])
     const double *nu3;       // [G] centre^3

@@ -302,68 +302,103 @@ __device__ __forceinline__ double inv_doppler(const double b[3], double gam, con
 // ---------------------------------------------------------------------------
 // S4: ray trace.  One workgroup of kTraceThreads per (ordinate, chunk of GC
 // groups) marches the z planes from the inflow face; each thread owns up to
-// kTraceMaxPts grid points of the plane with all GC groups.  The source S~ and
+// MAXPT grid points of the plane with all GC groups.  The source S~ and
 // extinction chi~ of the four planes a step touches (second upwind, upwind,
 // current, downwind) sit in an LDS ring, the previous intensity plane in LDS;
 // the next plane is fetched into registers while the current one is computed.
-// chi~ = chi_lab + 1/(c dt) with chi_lab precomputed per medium (one value per
-// point when it is grey) or read from an array for the stand-alone entry
-// point.  Lab arrays are [k][p][g]; an LDS plane is [point][group-in-chunk].
+// LDS planes carry a one-column and one-row periodic halo (row stride nx + 1)
+// so that the bilinear taps need no wrap.  chi~ = chi_lab + 1/(c dt) with
+// chi_lab precomputed per medium (one value per point when it is grey) or read
+// from an array for the stand-alone entry point.  Lab arrays are [k][p][g].
 // ---------------------------------------------------------------------------
 template <typename real, bool CHI_ARRAY, int GC, int MAXPT>
 struct PlaneRegs {
     real s[MAXPT][GC], x[MAXPT][GC];
 };
 
+// (i, j) of plane point pe without an integer division: (pe + 1/2)/nx in FP32
+// is within 1e-3 of its exact value for planes up to 2^12 points, far from the
+// next integer
+__device__ __forceinline__ void plane_ij(int pe, int nx, float rnx, int &i, int &j)
+{
+    j = (int)(((float)pe + 0.5f) * rnx);
+    i = pe - j * nx;
+}
+
+struct TraceIdx {
+    int nx, ny, PL, RS, PS;     // plane sizes; LDS row stride and plane size (with halo)
+    float rnx;                  // 1/nx
+};
+
 // global -> registers: S~ and chi~ of plane t for this thread's points
 template <typename real, bool CHI_ARRAY, int GC, int MAXPT>
-__device__ __forceinline__ void trace_fetch(PlaneRegs<real, CHI_ARRAY, GC, MAXPT> &r, const TraceArgs<real> &a,
-                                            const OrdGeom &gm, int k, int g0, int t, bool xg)
+__device__ __forceinline__ void trace_fetch(PlaneRegs<real, CHI_ARRAY, GC, MAXPT> &r, const real *__restrict__ Sk,
+                                            const real *__restrict__ Xk, const real *__restrict__ Ck, int G, int PL,
+                                            int m, real icdt, bool xg)
 {
-    const int PL = a.nx * a.ny, G = a.G;
-    const int m = gm.up ? t : a.nz - 1 - t;
 #pragma unroll
     for (int c = 0; c < MAXPT; ++c) {
         const int pe = threadIdx.x + c * kTraceThreads;
         if (pe < PL) {
-            const long pidx = (long)m * PL + pe;
-            const long o = ((long)k * a.P + pidx) * G + g0;
+            const int pidx = m * PL + pe;
+            const int o = pidx * G;
 #pragma unroll
-            for (int gi = 0; gi < GC; ++gi) r.s[c][gi] = a.St[o + gi];
+            for (int gi = 0; gi < GC; ++gi) r.s[c][gi] = Sk[o + gi];
             if (CHI_ARRAY) {
 #pragma unroll
-                for (int gi = 0; gi < GC; ++gi) r.x[c][gi] = a.Xt[o + gi];
+                for (int gi = 0; gi < GC; ++gi) r.x[c][gi] = Xk[o + gi];
             } else if (xg) {
-                r.x[c][0] = a.chilab[(long)k * a.P + pidx] + a.inv_cdt;
+                r.x[c][0] = Ck[pidx] + icdt;
             } else {
 #pragma unroll
-                for (int gi = 0; gi < GC; ++gi) r.x[c][gi] = a.chilab[o + gi] + a.inv_cdt;
+                for (int gi = 0; gi < GC; ++gi) r.x[c][gi] = Xk[o + gi] + icdt;
             }
         }
+    }
+}
+
+// write value v of point (i, j) into an LDS plane with its periodic halo
+template <typename real>
+__device__ __forceinline__ void lds_put(real *pl, const TraceIdx &q, int i, int j, int ge, int gi, real v)
+{
+    pl[(j * q.RS + i) * ge + gi] = v;
+    if (i == 0) pl[(j * q.RS + q.nx) * ge + gi] = v;
+    if (j == 0) {
+        pl[(q.ny * q.RS + i) * ge + gi] = v;
+        if (i == 0) pl[(q.ny * q.RS + q.nx) * ge + gi] = v;
     }
 }
 
 // registers -> the LDS ring slot of plane t
 template <typename real, bool CHI_ARRAY, int GC, int MAXPT>
 __device__ __forceinline__ void trace_store(const PlaneRegs<real, CHI_ARRAY, GC, MAXPT> &r, real *Sr, real *Xr,
-                                            int PL, int t, bool xg)
+                                            const TraceIdx &q, int t, bool xg)
 {
-    const int NE = PL * GC, XE = xg ? PL : NE;
-    real *Sd = Sr + (t & 3) * NE, *Xd = Xr + (t & 3) * XE;
+    const int xge = xg ? 1 : GC;
+    real *Sd = Sr + (t & 3) * q.PS * GC, *Xd = Xr + (t & 3) * q.PS * xge;
 #pragma unroll
     for (int c = 0; c < MAXPT; ++c) {
         const int pe = threadIdx.x + c * kTraceThreads;
-        if (pe < PL) {
+        if (pe < q.PL) {
+            int i, j;
+            plane_ij(pe, q.nx, q.rnx, i, j);
 #pragma unroll
-            for (int gi = 0; gi < GC; ++gi) Sd[pe * GC + gi] = r.s[c][gi];
+            for (int gi = 0; gi < GC; ++gi) lds_put(Sd, q, i, j, GC, gi, r.s[c][gi]);
             if (xg) {
-                Xd[pe] = r.x[c][0];
+                lds_put(Xd, q, i, j, 1, 0, r.x[c][0]);
             } else {
 #pragma unroll
-                for (int gi = 0; gi < GC; ++gi) Xd[pe * GC + gi] = r.x[c][gi];
+                for (int gi = 0; gi < GC; ++gi) lds_put(Xd, q, i, j, GC, gi, r.x[c][gi]);
             }
         }
     }
+}
+
+// bilinear value from an LDS plane with halo: base = tap (i0, j0), weights w
+template <typename real>
+__device__ __forceinline__ real bil(const real *pl, int base, int dx, int dy, const real w[4])
+{
+    return w[0] * pl[base] + w[1] * pl[base + dx] + w[2] * pl[base + dy] + w[3] * pl[base + dx + dy];
 }
 
 template <typename real, bool CHI_ARRAY, int GC, int MAXPT>
@@ -376,40 +411,57 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
     const long item = xcd_item((long)a.K * nch);
     if (item >= (long)a.K * nch) return;
     const int k = (int)(item / nch), g0 = (int)(item - (long)k * nch) * GC;
-    const int NE = PL * GC;
+    const TraceIdx q{nx, ny, PL, nx + 1, (nx + 1) * (ny + 1), 1.0f / (float)nx};
+    const int NE = q.PS * GC;
     const bool xg = !CHI_ARRAY && a.chi_grey;        // one chi~ per point
-    const int XE = xg ? PL : NE, xge = xg ? 1 : GC;
+    const int xge = xg ? 1 : GC, XE = q.PS * xge;
     real *Sr = reinterpret_cast<real *>(smem_raw);
     real *Xr = Sr + 4 * NE;
     real *Ir = Xr + 4 * XE;
     const OrdGeom gm = a.geo[k];
-    const long P = a.P;
+    const long slab = (long)k * a.P * G + g0;        // start of this ordinate's lab slab (+ chunk)
+    const real *__restrict__ Sk = a.St + slab;
+    const real *__restrict__ Xk = CHI_ARRAY ? a.Xt + slab : (xg ? nullptr : a.chilab + slab);
+    const real *__restrict__ Ck = xg ? a.chilab + (long)k * a.P : nullptr;
+    real *__restrict__ Ik = a.I + slab;
     const int tid = threadIdx.x;
     PlaneRegs<real, CHI_ARRAY, GC, MAXPT> rg;
 
     for (int t = 0; t < nz && t < 3; ++t) {
-        trace_fetch(rg, a, gm, k, g0, t, xg);
-        trace_store(rg, Sr, Xr, PL, t, xg);
+        trace_fetch(rg, Sk, Xk, Ck, G, PL, gm.up ? t : nz - 1 - t, a.inv_cdt, xg);
+        trace_store(rg, Sr, Xr, q, t, xg);
     }
     {
         const int m0 = gm.up ? 0 : nz - 1;
         const real *__restrict__ bc = gm.up ? a.bc_bot : a.bc_top;
-        for (int pe = tid; pe < PL; pe += T)
+#pragma unroll
+        for (int c = 0; c < MAXPT; ++c) {
+            const int pe = tid + c * T;
+            if (pe >= PL) break;
+            int i, j;
+            plane_ij(pe, nx, q.rnx, i, j);
 #pragma unroll
             for (int gi = 0; gi < GC; ++gi) {
                 const real v = bc ? bc[((long)k * PL + pe) * G + g0 + gi] : real(0);
-                Ir[pe * GC + gi] = v;
-                a.I[((long)k * P + (long)m0 * PL + pe) * G + g0 + gi] = v;
+                lds_put(Ir, q, i, j, GC, gi, v);
+                Ik[(m0 * PL + pe) * G + gi] = v;
             }
+        }
     }
     __syncthreads();
     const real ds = (real)gm.ds;
-    const real fxu = (real)gm.fx[1], fyu = (real)gm.fy[1];
-    const real fxuu = (real)gm.fx[0], fyuu = (real)gm.fy[0];
-    const real fxd = (real)gm.fx[2], fyd = (real)gm.fy[2];
-    const int rowS = nx * GC, rowX = nx * xge;
+    real wts[3][4];
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const real fx = (real)gm.fx[s], fy = (real)gm.fy[s];
+        wts[s][0] = (real(1) - fx) * (real(1) - fy);
+        wts[s][1] = fx * (real(1) - fy);
+        wts[s][2] = (real(1) - fx) * fy;
+        wts[s][3] = fx * fy;
+    }
+    const int dxS = GC, dyS = q.RS * GC, dxX = xge, dyX = q.RS * xge;
     for (int t = 1; t < nz; ++t) {
-        if (t + 2 < nz) trace_fetch(rg, a, gm, k, g0, t + 2, xg);   // in flight while plane t is computed
+        if (t + 2 < nz) trace_fetch(rg, Sk, Xk, Ck, G, PL, gm.up ? t + 2 : nz - 3 - t, a.inv_cdt, xg);
         const int m = gm.up ? t : nz - 1 - t;
         const bool has_d = t <= nz - 2, has_uu = t >= 2;
         const real *Spl = Sr + (t & 3) * NE, *Xpl = Xr + (t & 3) * XE;
@@ -422,40 +474,49 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
         for (int c = 0; c < MAXPT; ++c) {
             const int pe = tid + c * T;
             if (pe >= PL) break;
-            const int i = pe % nx, j = pe / nx;
+            int i, j;
+            plane_ij(pe, nx, q.rnx, i, j);
+            // tap cells of the three shifted points (second upwind, upwind, downwind)
+            int cell[3];
+#pragma unroll
+            for (int s = 0; s < 3; ++s) {
+                int i0 = i + gm.ix[s]; if (i0 >= nx) i0 -= nx;
+                int j0 = j + gm.iy[s]; if (j0 >= ny) j0 -= ny;
+                cell[s] = j0 * q.RS + i0;
+            }
+            const int self = j * q.RS + i;
             real Xp = 0, Xu = 0, Xd = 0, Xuu = 0;
             if (xg) {
-                Xp = Xpl[pe];
-                Xu = shifted(Xul, i, j, nx, ny, 1, rowX, gm.ix[1], gm.iy[1], fxu, fyu);
-                if (has_d) Xd = shifted(Xdl, i, j, nx, ny, 1, rowX, gm.ix[2], gm.iy[2], fxd, fyd);
-                if (has_uu) Xuu = shifted(Xuul, i, j, nx, ny, 1, rowX, gm.ix[0], gm.iy[0], fxuu, fyuu);
+                Xp = Xpl[self];
+                Xu = bil(Xul, cell[1], dxX, dyX, wts[1]);
+                if (has_d) Xd = bil(Xdl, cell[2], dxX, dyX, wts[2]);
+                if (has_uu) Xuu = bil(Xuul, cell[0], dxX, dyX, wts[0]);
             }
-            const long og = ((long)k * P + (long)m * PL + pe) * G + g0;
+            const int og = (m * PL + pe) * G;
 #pragma unroll
             for (int gi = 0; gi < GC; ++gi) {
                 if (!xg) {
-                    Xp = Xpl[pe * GC + gi];
-                    Xu = shifted(Xul + gi, i, j, nx, ny, GC, rowX, gm.ix[1], gm.iy[1], fxu, fyu);
-                    if (has_d) Xd = shifted(Xdl + gi, i, j, nx, ny, GC, rowX, gm.ix[2], gm.iy[2], fxd, fyd);
-                    if (has_uu) Xuu = shifted(Xuul + gi, i, j, nx, ny, GC, rowX, gm.ix[0], gm.iy[0], fxuu, fyuu);
+                    Xp = Xpl[self * GC + gi];
+                    Xu = bil(Xul + gi, cell[1] * GC, dxX, dyX, wts[1]);
+                    if (has_d) Xd = bil(Xdl + gi, cell[2] * GC, dxX, dyX, wts[2]);
+                    if (has_uu) Xuu = bil(Xuul + gi, cell[0] * GC, dxX, dyX, wts[0]);
                 }
-                const real Sp = Spl[pe * GC + gi];
-                const real Su = shifted(Sul + gi, i, j, nx, ny, GC, rowS, gm.ix[1], gm.iy[1], fxu, fyu);
-                const real Iu = shifted(Iprv + gi, i, j, nx, ny, GC, rowS, gm.ix[1], gm.iy[1], fxu, fyu);
+                const real Sp = Spl[self * GC + gi];
+                const real Su = bil(Sul + gi, cell[1] * GC, dxS, dyS, wts[1]);
+                const real Iu = bil(Iprv + gi, cell[1] * GC, dxS, dyS, wts[1]);
                 const real hu = ds * real(0.5) * (Xu + Xp);
                 real dSp = 0, dSu = 0;
                 if (hu > real(0)) {
-                    const real rhu = fast_rcp(hu);
-                    const real d1 = (Sp - Su) * rhu;
+                    const real d1 = (Sp - Su) * fast_rcp(hu);
                     if (has_d) {
-                        const real Sd = shifted(Sdl + gi, i, j, nx, ny, GC, rowS, gm.ix[2], gm.iy[2], fxd, fyd);
+                        const real Sd = bil(Sdl + gi, cell[2] * GC, dxS, dyS, wts[2]);
                         const real hd = ds * real(0.5) * (Xp + Xd);
                         dSp = (hd > real(0)) ? fb_slope(d1, (Sd - Sp) * fast_rcp(hd), hu, hd) : real(0);
                     } else {
                         dSp = d1;
                     }
                     if (has_uu) {
-                        const real Suu = shifted(Suul + gi, i, j, nx, ny, GC, rowS, gm.ix[0], gm.iy[0], fxuu, fyuu);
+                        const real Suu = bil(Suul + gi, cell[0] * GC, dxS, dyS, wts[0]);
                         const real huu = ds * real(0.5) * (Xuu + Xu);
                         dSu = (huu > real(0)) ? fb_slope((Su - Suu) * fast_rcp(huu), d1, huu, hu) : real(0);
                     } else {
@@ -467,12 +528,12 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
                 real ex, w0, w1, w2, w3;
                 bezier_weights(hu, ex, w0, w1, w2, w3);
                 const real v = Iu * ex + w0 * Su + w1 * Cu + w2 * Cp + w3 * Sp;
-                Icur[pe * GC + gi] = v;
-                a.I[og + gi] = v;
+                lds_put(Icur, q, i, j, GC, gi, v);
+                Ik[og + gi] = v;
             }
         }
         __syncthreads();
-        if (t + 2 < nz) trace_store(rg, Sr, Xr, PL, t + 2, xg);     // the slot of plane t - 2 is free now
+        if (t + 2 < nz) trace_store(rg, Sr, Xr, q, t + 2, xg);     // the slot of plane t - 2 is free now
         __syncthreads();
     }
 }
@@ -508,6 +569,33 @@ __device__ __forceinline__ FreqTaps freq_taps_zero_walk(const FreqInfo &f, const
     return r;
 }
 
+// Frequency remap for groups uniform in ln(nu) (spacing delta): the target
+// frequency of group g sits at fractional group position g + y for every g, so
+// the invariant F/nu^3 is interpolated between groups g + s and g + s + 1
+// (s = floor y, weight f = y - s), groups -1 and G being the zero-valued ghost
+// centres, and nu_g^3 / nu_{g'}^3 = exp(3 delta (g - g')).  A[g'] are the
+// angular remaps of F at the taps; out[g] receives the lab (or comoving) value.
+template <typename real>
+__device__ __forceinline__ void uniform_remap(const real *F, int sk, int sg, int G, int nmu, int nphi,
+                                              const TapL<real> &tp, const real *pole, double y, double delta,
+                                              real *out, long ostride = 1)
+{
+    const double sf = floor(y);
+    const double f = y - sf;
+    const int s = (int)sf;
+    const real clo = (real)((1.0 - f) * exp(-3.0 * delta * sf));
+    const real chi = (real)(f * exp(-3.0 * delta * (sf + 1.0)));
+    auto A = [&](int gp) -> real {
+        return (gp >= 0 && gp < G) ? tap_value(F, sk, sg, G, gp, nmu, nphi, tp, pole) : real(0);
+    };
+    real acur = A(s);
+    for (int g = 0; g < G; ++g) {
+        const real anext = A(g + s + 1);
+        out[g * ostride] = clo * acur + chi * anext;
+        acur = anext;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // S3: comoving ordinates -> lab ordinates, one workgroup per grid point, one
 // thread per lab ordinate (all groups).  The point's comoving source S0[g][j]
@@ -523,10 +611,11 @@ __global__ void __launch_bounds__(256) k_boost(BoostArgs<real> a)
     extern __shared__ unsigned char smem_raw[];
     const long p = xcd_item(a.P);
     if (p >= a.P) return;
-    const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x;
+    const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x, Gp = G + 1;
     double *fbuf = reinterpret_cast<double *>(smem_raw);                // [4G]
     real *sS0 = reinterpret_cast<real *>(fbuf + 4 * G);                 // [G][K]
     real *sPole = sS0 + G * K;                                          // [2][G]
+    real *sOut = sPole + 2 * G;                                         // [T][G+1] lab values of a chunk of ordinates
 
     const FreqL fl = stage_freq(a.fi, fbuf);
     double b[3];
@@ -545,43 +634,55 @@ __global__ void __launch_bounds__(256) k_boost(BoostArgs<real> a)
     }
     const real icdt = a.inv_cdt;
     const double gam = moving ? a.gam[p] : 1.0;
-    for (int k = tid; k < K; k += T) {
-        const long o0 = ((long)k * a.P + p) * G;
-        TapL<real> tp{0, 0, 0, 0, 0, 0};
-        double D = 1.0, lnD = 0.0;
-        if (moving) {
-            const double n[3] = {a.dir[4 * k], a.dir[4 * k + 1], a.dir[4 * k + 2]};
-            const double bn = b[0] * n[0] + b[1] * n[1] + b[2] * n[2];
-            D = 1.0 / inv_doppler(b, gam, n);
-            const double f = gam * (1.0 - gam / (gam + 1.0) * bn);
-            double n0[3];
-            for (int c = 0; c < 3; ++c) n0[c] = D * (n[c] - f * b[c]);
-            const AngleTaps at = angle_taps(a.mu, a.nmu, a.nphi, n0);
-            tp = TapL<real>{at.a0, at.a1, at.b0, at.b1, (real)at.wmu, (real)at.wphi};
-            lnD = log(D);
-        }
-        FreqWalk fw{0};
-        if (moving && !a.fi.grey && G > 2) fw.lo = centre_bracket(fl.lnc, G, fl.lnc[0] - lnD);
-        const real chig = a.chi_grey ? a.chilab[(long)k * a.P + p] : real(0);
-        for (int g = 0; g < G; ++g) {
-            real Sl;
+    for (int k0 = 0; k0 < K; k0 += T) {
+        // lab source of ordinate k = k0 + tid, all groups, into the tile
+        const int k = k0 + tid;
+        if (k < K) {
+            real *outk = sOut + tid * Gp;
             if (!moving) {
-                Sl = sS0[g * K + k];
-            } else if (a.fi.grey) {
-                const double D2 = D * D;
-                Sl = (real)(D2 * D2) * tap_value(sS0, 1, K, G, g, a.nmu, a.nphi, tp, sPole);
+                for (int g = 0; g < G; ++g) outk[g] = sS0[g * K + k];
             } else {
-                const FreqTaps ft = freq_taps_zero_walk(a.fi, fl, fl.lnc[g] - lnD, fw);
-                double v = 0.0;
-                if (ft.gl >= 0) v += ft.wl * (double)tap_value(sS0, 1, K, G, ft.gl, a.nmu, a.nphi, tp, sPole) * fl.inv_nu3[ft.gl];
-                if (ft.gh >= 0) v += ft.wh * (double)tap_value(sS0, 1, K, G, ft.gh, a.nmu, a.nphi, tp, sPole) * fl.inv_nu3[ft.gh];
-                Sl = (real)(fl.nu3[g] * v);
+                const double n[3] = {a.dir[4 * k], a.dir[4 * k + 1], a.dir[4 * k + 2]};
+                const double bn = b[0] * n[0] + b[1] * n[1] + b[2] * n[2];
+                const double D = 1.0 / inv_doppler(b, gam, n);
+                const double f = gam * (1.0 - gam / (gam + 1.0) * bn);
+                double n0[3];
+                for (int c = 0; c < 3; ++c) n0[c] = D * (n[c] - f * b[c]);
+                const AngleTaps at = angle_taps(a.mu, a.nmu, a.nphi, n0);
+                const TapL<real> tp{at.a0, at.a1, at.b0, at.b1, (real)at.wmu, (real)at.wphi};
+                if (a.fi.grey) {
+                    const double D2 = D * D;
+                    outk[0] = (real)(D2 * D2) * tap_value(sS0, 1, K, G, 0, a.nmu, a.nphi, tp, sPole);
+                } else if (a.fi.uniform) {
+                    uniform_remap(sS0, 1, K, G, a.nmu, a.nphi, tp, sPole, -log(D) * a.fi.inv_delta, a.fi.delta, outk);
+                } else {
+                    const double lnD = log(D);
+                    FreqWalk fw{0};
+                    if (G > 2) fw.lo = centre_bracket(fl.lnc, G, fl.lnc[0] - lnD);
+                    for (int g = 0; g < G; ++g) {
+                        const FreqTaps ft = freq_taps_zero_walk(a.fi, fl, fl.lnc[g] - lnD, fw);
+                        double v = 0.0;
+                        if (ft.gl >= 0) v += ft.wl * (double)tap_value(sS0, 1, K, G, ft.gl, a.nmu, a.nphi, tp, sPole) * fl.inv_nu3[ft.gl];
+                        if (ft.gh >= 0) v += ft.wh * (double)tap_value(sS0, 1, K, G, ft.gh, a.nmu, a.nphi, tp, sPole) * fl.inv_nu3[ft.gh];
+                        outk[g] = (real)(fl.nu3[g] * v);
+                    }
+                }
             }
-            const real chil = a.chi_grey ? chig : a.chilab[o0 + g];
-            const real ip = a.Iprev ? a.Iprev[o0 + g] : real(0);
-            const real xt = chil + icdt;
-            a.St[o0 + g] = (xt > real(0)) ? (chil * Sl + ip * icdt) / xt : real(0);
         }
+        __syncthreads();
+        // implicit time terms and a coalesced write of the chunk: runs of G values per ordinate
+        const int nk = min(T, K - k0);
+        const float rG = 1.0f / (float)G;
+        for (int idx = tid; idx < nk * G; idx += T) {
+            const int kk = (int)(((float)idx + 0.5f) * rG), g = idx - kk * G;
+            const long o = ((long)(k0 + kk) * a.P + p) * G + g;
+            const real Sl = sOut[kk * Gp + g];
+            const real chil = a.chi_grey ? a.chilab[(long)(k0 + kk) * a.P + p] : a.chilab[o];
+            const real ip = a.Iprev ? a.Iprev[o] : real(0);
+            const real xt = chil + icdt;
+            a.St[o] = (xt > real(0)) ? (chil * Sl + ip * icdt) / xt : real(0);
+        }
+        __syncthreads();
     }
 }
 
@@ -598,31 +699,32 @@ __global__ void __launch_bounds__(256) k_unboost(UnboostArgs<real> a)
     extern __shared__ unsigned char smem_raw[];
     const long p = xcd_item(a.P);
     if (p >= a.P) return;
-    const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x;
+    const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x, Gp = G + 1;
     double *fbuf = reinterpret_cast<double *>(smem_raw);                // [4G]
-    real *sI = reinterpret_cast<real *>(fbuf + 4 * G);                  // [K][G] lab
-    real *sPole = sI + K * G;                                           // [2][G]
+    real *sI = reinterpret_cast<real *>(fbuf + 4 * G);                  // [K][G+1] lab (padded rows)
+    real *sPole = sI + K * Gp;                                          // [2][G]
 
     const FreqL fl = stage_freq(a.fi, fbuf);
     double b[3];
     const bool moving = load_beta(a.beta, p, b);
+    const float rG = 1.0f / (float)G, rK = 1.0f / (float)K;
     for (int idx = tid; idx < K * G; idx += T) {
-        const int k = idx / G, g = idx - k * G;
-        sI[idx] = a.Ilab[((long)k * a.P + p) * G + g];
+        const int k = (int)(((float)idx + 0.5f) * rG), g = idx - k * G;
+        sI[k * Gp + g] = a.Ilab[((long)k * a.P + p) * G + g];
     }
     __syncthreads();
     real *__restrict__ out = a.I0 + (long)p * G * K;
     if (!moving) {
         for (int idx = tid; idx < K * G; idx += T) {
-            const int g = idx / K, j = idx - g * K;
-            out[idx] = sI[j * G + g];
+            const int g = (int)(((float)idx + 0.5f) * rK), j = idx - g * K;
+            out[idx] = sI[j * Gp + g];
         }
         return;
     }
     for (int i = tid; i < 2 * G; i += T) {
         const int g = i % G, ring = (i < G) ? 0 : a.nmu - 1;
         real s = 0;
-        for (int bb = 0; bb < a.nphi; ++bb) s += sI[(ring * a.nphi + bb) * G + g];
+        for (int bb = 0; bb < a.nphi; ++bb) s += sI[(ring * a.nphi + bb) * Gp + g];
         sPole[i] = s / real(a.nphi);
     }
     __syncthreads();
@@ -637,18 +739,22 @@ __global__ void __launch_bounds__(256) k_unboost(UnboostArgs<real> a)
         const AngleTaps at = angle_taps(a.mu, a.nmu, a.nphi, n);
         const TapL<real> tp{at.a0, at.a1, at.b0, at.b1, (real)at.wmu, (real)at.wphi};
         const double lnD = log(Dp);
+        if (!a.fi.grey && a.fi.uniform) {
+            uniform_remap(sI, Gp, 1, G, a.nmu, a.nphi, tp, sPole, lnD * a.fi.inv_delta, a.fi.delta, out + j, K);
+            continue;
+        }
         FreqWalk fw{0};
         if (!a.fi.grey && G > 2) fw.lo = centre_bracket(fl.lnc, G, fl.lnc[0] + lnD);
         for (int g = 0; g < G; ++g) {
             real v;
             if (a.fi.grey) {
                 const double D2 = Dp * Dp;
-                v = (real)((double)tap_value(sI, G, 1, G, g, a.nmu, a.nphi, tp, sPole) / (D2 * D2));
+                v = (real)((double)tap_value(sI, Gp, 1, G, g, a.nmu, a.nphi, tp, sPole) / (D2 * D2));
             } else {
                 const FreqTaps ft = freq_taps_zero_walk(a.fi, fl, fl.lnc[g] + lnD, fw);
                 double s = 0.0;
-                if (ft.gl >= 0) s += ft.wl * (double)tap_value(sI, G, 1, G, ft.gl, a.nmu, a.nphi, tp, sPole) * fl.inv_nu3[ft.gl];
-                if (ft.gh >= 0) s += ft.wh * (double)tap_value(sI, G, 1, G, ft.gh, a.nmu, a.nphi, tp, sPole) * fl.inv_nu3[ft.gh];
+                if (ft.gl >= 0) s += ft.wl * (double)tap_value(sI, Gp, 1, G, ft.gl, a.nmu, a.nphi, tp, sPole) * fl.inv_nu3[ft.gl];
+                if (ft.gh >= 0) s += ft.wh * (double)tap_value(sI, Gp, 1, G, ft.gh, a.nmu, a.nphi, tp, sPole) * fl.inv_nu3[ft.gh];
                 v = (real)(fl.nu3[g] * s);
             }
             out[(long)g * K + j] = v;
@@ -900,7 +1006,7 @@ static inline unsigned blocks_for(long n, int bs) { return (unsigned)((n + bs - 
 template <typename real>
 size_t trace_lds(int nx, int ny, int Gc, int chi_per_point)
 {
-    return sizeof(real) * (size_t)nx * ny * (6 * (size_t)Gc + 4 * (chi_per_point ? 1 : (size_t)Gc));
+    return sizeof(real) * (size_t)(nx + 1) * (ny + 1) * (6 * (size_t)Gc + 4 * (chi_per_point ? 1 : (size_t)Gc));
 }
 template <typename real>
 void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st)
@@ -926,7 +1032,7 @@ void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st)
 template <typename real>
 size_t boost_lds(int K, int G)
 {
-    return 4 * sizeof(double) * G + sizeof(real) * ((size_t)K * G + 2 * G);
+    return 4 * sizeof(double) * G + sizeof(real) * ((size_t)K * (G + 1) + 2 * G + 256 * (size_t)(G + 1));
 }
 template <typename real>
 void launch_chilab(const ChiLabArgs<real> &a, hipStream_t st)
