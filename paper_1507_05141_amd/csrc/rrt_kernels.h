@@ -6,8 +6,8 @@ namespace rrt {
 
 constexpr int kBezTerms64 = 18;   // series terms of the Bezier weights, h < 0.5 (FP64)
 constexpr int kBezTerms32 = 12;   // series terms of the Bezier weights, h < 1   (FP32)
-constexpr int kTraceThreads = 256;  // threads per ray-trace workgroup
-constexpr int kTraceMaxPts = 16;    // grid points of a plane per ray-trace thread (at most)
+constexpr int kTraceThreads = 512;  // threads per ray-trace workgroup
+constexpr int kTraceMaxPts = 8;     // grid points of a plane per ray-trace thread (at most)
 
 // Per-ordinate geometry of the plane-to-plane short characteristic: path
 // length ds = dz/|mu| between planes, march direction, and the horizontal

@@ -470,7 +470,7 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
         const real *Sdl = Sr + ((t + 1) & 3) * NE, *Xdl = Xr + ((t + 1) & 3) * XE;
         const real *Iprv = Ir + ((t - 1) & 1) * NE;
         real *Icur = Ir + (t & 1) * NE;
-#pragma unroll 1
+#pragma unroll 2
         for (int c = 0; c < MAXPT; ++c) {
             const int pe = tid + c * T;
             if (pe >= PL) break;
@@ -1022,11 +1022,11 @@ void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st)
         return;                                                                                    \
     }
     RRT_TRACE_CASE(1, 1)
-    RRT_TRACE_CASE(1, 4)
-    RRT_TRACE_CASE(1, 16)
+    RRT_TRACE_CASE(1, 2)
+    RRT_TRACE_CASE(1, 8)
     RRT_TRACE_CASE(2, 1)
-    RRT_TRACE_CASE(2, 4)
-    RRT_TRACE_CASE(2, 16)
+    RRT_TRACE_CASE(2, 2)
+    RRT_TRACE_CASE(2, 8)
 #undef RRT_TRACE_CASE
 }
 template <typename real>
@@ -1101,29 +1101,29 @@ void launch_rk_stage(long n, const real *R, real *Iin, real *acc, real *In, int 
 hipError_t set_lds_limits(size_t bytes)
 {
     const void *fns[] = {reinterpret_cast<const void *>(&k_trace<float, true, 1, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, true, 1, 4>),
-                         reinterpret_cast<const void *>(&k_trace<float, true, 1, 16>),
+                         reinterpret_cast<const void *>(&k_trace<float, true, 1, 2>),
+                         reinterpret_cast<const void *>(&k_trace<float, true, 1, 8>),
                          reinterpret_cast<const void *>(&k_trace<float, true, 2, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, true, 2, 4>),
-                         reinterpret_cast<const void *>(&k_trace<float, true, 2, 16>),
+                         reinterpret_cast<const void *>(&k_trace<float, true, 2, 2>),
+                         reinterpret_cast<const void *>(&k_trace<float, true, 2, 8>),
                          reinterpret_cast<const void *>(&k_trace<float, false, 1, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, false, 1, 4>),
-                         reinterpret_cast<const void *>(&k_trace<float, false, 1, 16>),
+                         reinterpret_cast<const void *>(&k_trace<float, false, 1, 2>),
+                         reinterpret_cast<const void *>(&k_trace<float, false, 1, 8>),
                          reinterpret_cast<const void *>(&k_trace<float, false, 2, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, false, 2, 4>),
-                         reinterpret_cast<const void *>(&k_trace<float, false, 2, 16>),
+                         reinterpret_cast<const void *>(&k_trace<float, false, 2, 2>),
+                         reinterpret_cast<const void *>(&k_trace<float, false, 2, 8>),
                          reinterpret_cast<const void *>(&k_trace<double, true, 1, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, true, 1, 4>),
-                         reinterpret_cast<const void *>(&k_trace<double, true, 1, 16>),
+                         reinterpret_cast<const void *>(&k_trace<double, true, 1, 2>),
+                         reinterpret_cast<const void *>(&k_trace<double, true, 1, 8>),
                          reinterpret_cast<const void *>(&k_trace<double, true, 2, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, true, 2, 4>),
-                         reinterpret_cast<const void *>(&k_trace<double, true, 2, 16>),
+                         reinterpret_cast<const void *>(&k_trace<double, true, 2, 2>),
+                         reinterpret_cast<const void *>(&k_trace<double, true, 2, 8>),
                          reinterpret_cast<const void *>(&k_trace<double, false, 1, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, false, 1, 4>),
-                         reinterpret_cast<const void *>(&k_trace<double, false, 1, 16>),
+                         reinterpret_cast<const void *>(&k_trace<double, false, 1, 2>),
+                         reinterpret_cast<const void *>(&k_trace<double, false, 1, 8>),
                          reinterpret_cast<const void *>(&k_trace<double, false, 2, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, false, 2, 4>),
-                         reinterpret_cast<const void *>(&k_trace<double, false, 2, 16>),
+                         reinterpret_cast<const void *>(&k_trace<double, false, 2, 2>),
+                         reinterpret_cast<const void *>(&k_trace<double, false, 2, 8>),
                          reinterpret_cast<const void *>(&k_boost<float>),
                          reinterpret_cast<const void *>(&k_boost<double>),
                          reinterpret_cast<const void *>(&k_unboost<float>),
