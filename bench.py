@@ -86,6 +86,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--workload", choices=["thomson_jet", "compton_jet"], default="thomson_jet",
+                    help="thomson_jet: 32^3, 16 groups, L=7 (default); compton_jet: 64^3, 32 groups, L=15, "
+                         "electrons at rest")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
@@ -110,8 +113,13 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-    spec = W.thomson_jet()
-    workload = "thomson_jet_32c_g16_l7_16x32"
+    if args.workload == "thomson_jet":
+        spec = W.thomson_jet()
+        workload = "thomson_jet_32c_g16_l7_16x32"
+    else:
+        spec = W.compton_jet()
+        spec["kte"] = None
+        workload = "compton_jet_64c_g32_l15_16x32"
     prec = B.FP32 if args.precision == "fp32" else B.FP64
     esz = 4 if prec == B.FP32 else 8
     stream = torch.cuda.current_stream().cuda_stream
@@ -152,15 +160,15 @@ def main():
         "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == B.FP32 else "f64",
         "data": "synthetic",
-        "config": {"workload": workload, "grid": [32, 32, 32], "groups": 16, "lmax": 7,
-                   "ordinates": [16, 32], "scatter": "thomson", "gamma_max": 10.0,
-                   "updates_per_sweep": updates},
+        "config": {"workload": workload, "grid": [spec["nx"], spec["ny"], spec["nz"]], "groups": pr.G,
+                   "lmax": spec["lmax"], "ordinates": [spec["nmu"], spec["nphi"]], "scatter": spec["scatter"],
+                   "gamma_max": 10.0, "updates_per_sweep": updates},
         "roofline": roof,
         "kernels": kern,
     }
     pr.close()
-    if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(spec)
+    if not args.no_cpu_baseline and args.workload == "thomson_jet":
+        out["cpu_baseline"] = cpu_baseline(W.thomson_jet())
     print(json.dumps(out), flush=True)
 
 

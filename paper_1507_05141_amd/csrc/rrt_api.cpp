@@ -534,7 +534,7 @@ size_t footprint(const rrt_grid *g, const rrt_groups *gr, const rrt_angles *a, i
     if (use_ng) total += 4 * sh;                     // Ng chain
     total += P * (3 * G + 1) * esz + 4 * P * 8;     // fields, chi0, beta, Gamma
     total += 2 * (size_t)g->nx * g->ny * K * G * esz;  // boundaries
-    total += 1 << 20;                                // tables and reductions
+    total += 16 * P * G + (1 << 20);                 // residual partial sums, tables
     return total;
 }
 
@@ -629,6 +629,8 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
                                                        : rrt::boost_lds<float>(pr->K, pr->G);
         if (!pr->Gc || (long)pr->nx * pr->ny > (long)rrt::kTraceThreads * rrt::kTraceMaxPts)
             return bail(fail(RRT_E_INVALID, "an x-y plane is too large for the ray-trace kernel on this device"));
+        if (scatter == RRT_COMPTON && pr->esz * (size_t)pr->G * pr->NL > lim)
+            return bail(fail(RRT_E_INVALID, "groups x SH terms per point too large for the Compton source kernel"));
         if (need_boost > lim)
             return bail(fail(RRT_E_INVALID, "ordinates x groups per point too large for the frame-transform "
                                             "kernels' LDS in this precision"));
@@ -757,7 +759,8 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
         if (e != hipSuccess) return bail(fail(RRT_E_DEVICE, "initial clear"));
     }
     pr->nblk_red = 1024;
-    if ((s = dev_alloc((void **)&pr->d_partial, (size_t)pr->nblk_red * std::max(2 * G, 5) * 8)) ||
+    if ((s = dev_alloc((void **)&pr->d_partial,
+                       std::max((size_t)pr->nblk_red * std::max(2 * G, 5), 2 * (size_t)pr->P * G) * 8)) ||
         (s = dev_alloc((void **)&pr->d_red, (size_t)std::max(2 * G, 5) * 8)))
         return bail(s);
     *out = pr;

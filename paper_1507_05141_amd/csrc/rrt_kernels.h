@@ -8,6 +8,7 @@ constexpr int kBezTerms64 = 18;   // series terms of the Bezier weights, h < 0.5
 constexpr int kBezTerms32 = 12;   // series terms of the Bezier weights, h < 1   (FP32)
 constexpr int kTraceThreads = 512;  // threads per ray-trace workgroup
 constexpr int kTraceMaxPts = 8;     // grid points of a plane per ray-trace thread (at most)
+constexpr int kRemapThreads = 512;  // threads per frame-transform workgroup (one lab ordinate each)
 
 // Per-ordinate geometry of the plane-to-plane short characteristic: path
 // length ds = dz/|mu| between planes, march direction, and the horizontal

@@ -304,8 +304,9 @@ __device__ __forceinline__ double inv_doppler(const double b[3], double gam, con
 // groups) marches the z planes from the inflow face; each thread owns up to
 // MAXPT grid points of the plane with all GC groups.  The source S~ and
 // extinction chi~ of the four planes a step touches (second upwind, upwind,
-// current, downwind) sit in an LDS ring, the previous intensity plane in LDS;
-// the next plane is fetched into registers while the current one is computed.
+// current, downwind) sit in an LDS ring, the previous intensity plane in LDS
+// (overwritten by the new one once every thread has read it); the next plane
+// is fetched into registers while the current one is computed.
 // LDS planes carry a one-column and one-row periodic halo (row stride nx + 1)
 // so that the bilinear taps need no wrap.  chi~ = chi_lab + 1/(c dt) with
 // chi_lab precomputed per medium (one value per point when it is grey) or read
@@ -402,7 +403,7 @@ __device__ __forceinline__ real bil(const real *pl, int base, int dx, int dy, co
 }
 
 template <typename real, bool CHI_ARRAY, int GC, int MAXPT>
-__global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
+__global__ void __launch_bounds__(kTraceThreads, (MAXPT <= 2 && sizeof(real) == 4) ? 8 : 1) k_trace(TraceArgs<real> a)
 {
     constexpr int T = kTraceThreads;
     extern __shared__ unsigned char smem_raw[];
@@ -468,9 +469,9 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
         const real *Sul = Sr + ((t - 1) & 3) * NE, *Xul = Xr + ((t - 1) & 3) * XE;
         const real *Suul = Sr + ((t - 2) & 3) * NE, *Xuul = Xr + ((t - 2) & 3) * XE;
         const real *Sdl = Sr + ((t + 1) & 3) * NE, *Xdl = Xr + ((t + 1) & 3) * XE;
-        const real *Iprv = Ir + ((t - 1) & 1) * NE;
-        real *Icur = Ir + (t & 1) * NE;
-#pragma unroll 2
+        const real *Iprv = Ir;
+        real res[MAXPT][GC];
+#pragma unroll
         for (int c = 0; c < MAXPT; ++c) {
             const int pe = tid + c * T;
             if (pe >= PL) break;
@@ -528,12 +529,23 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
                 real ex, w0, w1, w2, w3;
                 bezier_weights(hu, ex, w0, w1, w2, w3);
                 const real v = Iu * ex + w0 * Su + w1 * Cu + w2 * Cp + w3 * Sp;
-                lds_put(Icur, q, i, j, GC, gi, v);
+                res[c][gi] = v;
                 Ik[og + gi] = v;
             }
         }
         __syncthreads();
-        if (t + 2 < nz) trace_store(rg, Sr, Xr, q, t + 2, xg);     // the slot of plane t - 2 is free now
+        // every read of plane t - 1 is done: the intensity plane and the slot of
+        // plane t - 2 can be overwritten
+#pragma unroll
+        for (int c = 0; c < MAXPT; ++c) {
+            const int pe = tid + c * T;
+            if (pe >= PL) break;
+            int i, j;
+            plane_ij(pe, nx, q.rnx, i, j);
+#pragma unroll
+            for (int gi = 0; gi < GC; ++gi) lds_put(Ir, q, i, j, GC, gi, res[c][gi]);
+        }
+        if (t + 2 < nz) trace_store(rg, Sr, Xr, q, t + 2, xg);
         __syncthreads();
     }
 }
@@ -606,7 +618,7 @@ __device__ __forceinline__ void uniform_remap(const real *F, int sk, int sg, int
 // extinction chi_lab precomputed per medium.  Output S~[k][p][g].
 // ---------------------------------------------------------------------------
 template <typename real>
-__global__ void __launch_bounds__(256) k_boost(BoostArgs<real> a)
+__global__ void __launch_bounds__(kRemapThreads) k_boost(BoostArgs<real> a)
 {
     extern __shared__ unsigned char smem_raw[];
     const long p = xcd_item(a.P);
@@ -694,7 +706,7 @@ __global__ void __launch_bounds__(256) k_boost(BoostArgs<real> a)
 // ray.  Output I0[p][g][j].
 // ---------------------------------------------------------------------------
 template <typename real>
-__global__ void __launch_bounds__(256) k_unboost(UnboostArgs<real> a)
+__global__ void __launch_bounds__(kRemapThreads) k_unboost(UnboostArgs<real> a)
 {
     extern __shared__ unsigned char smem_raw[];
     const long p = xcd_item(a.P);
@@ -796,27 +808,49 @@ __global__ void __launch_bounds__(256) k_source(SourceArgs<real> a)
     if (idx >= a.P * G * NL) return;
     const int q = (int)(idx % NL);
     const long pj = idx / NL;
-    const int j = (int)(pj % G);
     const long p = pj / G;
     const real chi = a.chi0[pj];
     if (!(chi > real(0))) { a.S[idx] = 0; return; }
     int l = (int)sqrtf((float)q);
     while (l * l > q) --l;
     while ((l + 1) * (l + 1) <= q) ++l;
-    const real om = a.sigma[p] / chi;
-    real v;
-    if (!a.compton) {
-        const real cl = (l == 0) ? real(1) : (l == 2 ? real(0.1) : real(0));   // chi_l/(2l+1)
-        v = om * cl * a.Ilm[idx];
-    } else {
-        const real *__restrict__ Arow = a.A + ((long)l * G + j) * G;
-        const real *__restrict__ Ip = a.Ilm + (long)p * G * NL + q;
-        real s = 0;
-        for (int i = 0; i < G; ++i) s += Arow[i] * Ip[(long)i * NL];
-        v = om * s;
-    }
+    const real cl = (l == 0) ? real(1) : (l == 2 ? real(0.1) : real(0));   // chi_l/(2l+1), Thomson
+    real v = a.sigma[p] / chi * cl * a.Ilm[idx];
     if (q == 0) v += real(3.5449077018110318) * a.kappa[pj] * a.bnu[pj] / chi;   // sqrt(4 pi) kappa B / chi
     a.S[idx] = v;
+}
+
+// Compton: one workgroup per point; its SH intensities I[i][q] (all groups) are
+// staged in LDS and S[j][q] = sigma/chi_j sum_i A_l(q)[j][i] I[i][q] + T_q
+template <typename real>
+__global__ void __launch_bounds__(256) k_source_compton(SourceArgs<real> a)
+{
+    extern __shared__ unsigned char smem_raw[];
+    real *sI = reinterpret_cast<real *>(smem_raw);
+    const long p = xcd_item(a.P);
+    if (p >= a.P) return;
+    const int G = a.G, NL = a.NL, T = blockDim.x;
+    const real *__restrict__ Ip = a.Ilm + p * G * NL;
+    for (int i = threadIdx.x; i < G * NL; i += T) sI[i] = Ip[i];
+    __syncthreads();
+    const real sig = a.sigma[p];
+    const float rNL = 1.0f / (float)NL;
+    for (int o = threadIdx.x; o < G * NL; o += T) {
+        const int j = (int)(((float)o + 0.5f) * rNL), q = o - j * NL;
+        int l = (int)sqrtf((float)q);
+        while (l * l > q) --l;
+        while ((l + 1) * (l + 1) <= q) ++l;
+        const real chi = a.chi0[p * G + j];
+        real v = 0;
+        if (chi > real(0)) {
+            const real *__restrict__ Arow = a.A + ((long)l * G + j) * G;
+            real acc = 0;
+            for (int i = 0; i < G; ++i) acc += Arow[i] * sI[i * NL + q];
+            v = sig / chi * acc;
+            if (q == 0) v += real(3.5449077018110318) * a.kappa[p * G + j] * a.bnu[p * G + j] / chi;
+        }
+        a.S[p * G * NL + o] = v;
+    }
 }
 
 // chi0 = kappa + sigma * s_g
@@ -908,31 +942,44 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
     return r;
 }
 
-// per block and group: sum (a-b)^2 and sum a^2 over the block's points
+// per (point, group) row of NL SH terms: sum (a-b)^2 and sum a^2; one wave per
+// row (lanes stride the row, then a shuffle reduction), rows strided over waves
 template <typename real>
-__global__ void __launch_bounds__(256) k_resid_partial(long P, int G, int NL, const real *__restrict__ a,
-                                                       const real *__restrict__ b, double *partial)
+__global__ void __launch_bounds__(256) k_resid_rows(long PG, int NL, const real *__restrict__ a,
+                                                    const real *__restrict__ b, double *rows)
 {
-    __shared__ double sh[256];
-    const long nthreads = (long)gridDim.x * blockDim.x;
-    const long tid = (long)blockIdx.x * blockDim.x + threadIdx.x;
-    for (int g = 0; g < G; ++g) {
+    const int lane = threadIdx.x & 63;
+    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long nwaves = ((long)gridDim.x * blockDim.x) >> 6;
+    for (long r = wave; r < PG; r += nwaves) {
+        const real *x = a + r * NL, *y = b + r * NL;
         double dd = 0, aa = 0;
-        for (long p = tid; p < P; p += nthreads) {
-            const real *x = a + (p * G + g) * NL, *y = b + (p * G + g) * NL;
-            for (int q = 0; q < NL; ++q) {
-                const double u = (double)x[q], d = u - (double)y[q];
-                dd += d * d;
-                aa += u * u;
-            }
+        for (int q = lane; q < NL; q += 64) {
+            const double u = (double)x[q], d = u - (double)y[q];
+            dd += d * d;
+            aa += u * u;
         }
-        dd = block_sum(dd, sh);
-        aa = block_sum(aa, sh);
-        if (threadIdx.x == 0) {
-            partial[((long)blockIdx.x * G + g) * 2] = dd;
-            partial[((long)blockIdx.x * G + g) * 2 + 1] = aa;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            dd += __shfl_xor(dd, off, 64);
+            aa += __shfl_xor(aa, off, 64);
+        }
+        if (lane == 0) {
+            rows[2 * r] = dd;
+            rows[2 * r + 1] = aa;
         }
     }
+}
+
+// out[2g + c] = sum over points of rows[2 (p G + g) + c]; one block per (g, c)
+__global__ void __launch_bounds__(256) k_resid_groups(long P, int G, const double *__restrict__ rows, double *out)
+{
+    __shared__ double sh[256];
+    const int g = blockIdx.x >> 1, c = blockIdx.x & 1;
+    double v = 0;
+    for (long p = threadIdx.x; p < P; p += blockDim.x) v += rows[2 * (p * G + g) + c];
+    v = block_sum(v, sh);
+    if (threadIdx.x == 0) out[2 * g + c] = v;
 }
 
 // five dot products for the Ng extrapolation from the chain s3 (oldest) .. s0
@@ -1006,7 +1053,7 @@ static inline unsigned blocks_for(long n, int bs) { return (unsigned)((n + bs - 
 template <typename real>
 size_t trace_lds(int nx, int ny, int Gc, int chi_per_point)
 {
-    return sizeof(real) * (size_t)(nx + 1) * (ny + 1) * (6 * (size_t)Gc + 4 * (chi_per_point ? 1 : (size_t)Gc));
+    return sizeof(real) * (size_t)(nx + 1) * (ny + 1) * (5 * (size_t)Gc + 4 * (chi_per_point ? 1 : (size_t)Gc));
 }
 template <typename real>
 void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st)
@@ -1032,7 +1079,7 @@ void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st)
 template <typename real>
 size_t boost_lds(int K, int G)
 {
-    return 4 * sizeof(double) * G + sizeof(real) * ((size_t)K * (G + 1) + 2 * G + 256 * (size_t)(G + 1));
+    return 4 * sizeof(double) * G + sizeof(real) * ((size_t)K * (G + 1) + 2 * G + kRemapThreads * (size_t)(G + 1));
 }
 template <typename real>
 void launch_chilab(const ChiLabArgs<real> &a, hipStream_t st)
@@ -1045,18 +1092,23 @@ template <typename real>
 void launch_boost(const BoostArgs<real> &a, hipStream_t st)
 {
     const unsigned nb = (unsigned)(8 * ((a.P + 7) / 8));
-    hipLaunchKernelGGL(k_boost<real>, dim3(nb), dim3(256), boost_lds<real>(a.K, a.fi.G), st, a);
+    hipLaunchKernelGGL(k_boost<real>, dim3(nb), dim3(kRemapThreads), boost_lds<real>(a.K, a.fi.G), st, a);
 }
 template <typename real>
 void launch_unboost(const UnboostArgs<real> &a, hipStream_t st)
 {
     const unsigned nb = (unsigned)(8 * ((a.P + 7) / 8));
-    hipLaunchKernelGGL(k_unboost<real>, dim3(nb), dim3(256), boost_lds<real>(a.K, a.fi.G), st, a);
+    hipLaunchKernelGGL(k_unboost<real>, dim3(nb), dim3(kRemapThreads), boost_lds<real>(a.K, a.fi.G), st, a);
 }
 template <typename real>
 void launch_source(const SourceArgs<real> &a, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_source<real>, dim3(blocks_for(a.P * a.G * a.NL, 256)), dim3(256), 0, st, a);
+    if (a.compton) {
+        const unsigned nb = (unsigned)(8 * ((a.P + 7) / 8));
+        hipLaunchKernelGGL(k_source_compton<real>, dim3(nb), dim3(256), sizeof(real) * (size_t)a.G * a.NL, st, a);
+    } else {
+        hipLaunchKernelGGL(k_source<real>, dim3(blocks_for(a.P * a.G * a.NL, 256)), dim3(256), 0, st, a);
+    }
 }
 template <typename real>
 void launch_chi0(long P, int G, const real *kappa, const real *sigma, const real *sg, real *chi0, hipStream_t st)
@@ -1074,10 +1126,12 @@ void launch_moments_co(long PG, int NL, int lmax, const real *Ilm, double *J, do
     hipLaunchKernelGGL(k_moments_co<real>, dim3(blocks_for(PG, 256)), dim3(256), 0, st, PG, NL, lmax, Ilm, J, H, Kt);
 }
 template <typename real>
-void launch_resid(long P, int G, int NL, const real *a, const real *b, double *partial, int nblk, double *out, hipStream_t st)
+void launch_resid(long P, int G, int NL, const real *a, const real *b, double *rows, int nblk, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_resid_partial<real>, dim3(nblk), dim3(256), 0, st, P, G, NL, a, b, partial);
-    hipLaunchKernelGGL(k_sum_columns, dim3(2 * G), dim3(256), 0, st, nblk, 2 * G, partial, out);
+    (void)nblk;
+    const unsigned nb = (unsigned)std::min<long>((P * G + 3) / 4, 8192);   // 4 waves per block, one row each
+    hipLaunchKernelGGL(k_resid_rows<real>, dim3(nb), dim3(256), 0, st, P * G, NL, a, b, rows);
+    hipLaunchKernelGGL(k_resid_groups, dim3(2 * G), dim3(256), 0, st, P, G, rows, out);
 }
 template <typename real>
 void launch_ng_dots(long n, const real *s0, const real *s1, const real *s2, const real *s3, double *partial, int nblk,
@@ -1127,7 +1181,9 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_boost<float>),
                          reinterpret_cast<const void *>(&k_boost<double>),
                          reinterpret_cast<const void *>(&k_unboost<float>),
-                         reinterpret_cast<const void *>(&k_unboost<double>)};
+                         reinterpret_cast<const void *>(&k_unboost<double>),
+                         reinterpret_cast<const void *>(&k_source_compton<float>),
+                         reinterpret_cast<const void *>(&k_source_compton<double>)};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
         if (e != hipSuccess) return e;

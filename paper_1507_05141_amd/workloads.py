@@ -79,8 +79,12 @@ def jet_beta(n, nz, gamma_max, r_jet=0.5, width2=0.02):
 
 
 def planck(nu, kt):
-    """2 nu^3 / (exp(nu/kT) - 1) in units h = c = 1."""
-    return 2.0 * nu ** 3 / np.expm1(nu / kt)
+    """2 nu^3 / (exp(nu/kT) - 1) in units h = c = 1 (0 where exp overflows)."""
+    x = np.asarray(nu, dtype=np.float64) / kt
+    out = np.zeros_like(x)
+    ok = x < 700.0
+    out[ok] = 2.0 * np.asarray(nu, dtype=np.float64)[ok] ** 3 / np.expm1(x[ok])
+    return out
 
 
 def _centres_for_input(edges, log_centres):
