@@ -608,7 +608,6 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
         int dev = 0, lds = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
-        if (e == hipSuccess) e = rrt::upload_bezier_coefficients();
         const size_t lim = std::min(kMaxLds, (size_t)lds);
         if (e == hipSuccess) e = rrt::set_lds_limits(lim);
         if (e != hipSuccess) return bail(fail(RRT_E_DEVICE, std::string("kernel set-up: ") + hipGetErrorString(e)));
@@ -617,17 +616,20 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
             return pr->prec == RRT_FP64 ? rrt::trace_lds<double>(pr->nx, pr->ny, gc, 0)
                                         : rrt::trace_lds<float>(pr->nx, pr->ny, gc, 0);
         };
-        // groups per ray-trace workgroup: the largest of 4, 2, 1 dividing G that leaves
-        // room for two workgroups per CU, else the largest that fits at all
+        // groups per ray-trace workgroup: the largest of 4, 2, 1 that divides G and
+        // fits the LDS (a thread reads and writes the groups of a point as one
+        // vector, and shares the tap addresses and a grey extinction among them)
+        const long plane = (long)pr->nx * pr->ny;
+        auto fits = [&](int gc) { return gc >= 1 && pr->G % gc == 0 && tl(gc) <= lim; };
         pr->Gc = 0;
         const char *env = std::getenv("RRT_TRACE_GC");
         const int want = env ? std::atoi(env) : 0;
-        if ((want == 1 || want == 2) && pr->G % want == 0 && tl(want) <= lim) pr->Gc = want;
-        // one group per workgroup measured fastest on the 32^3 x 16-group jet (MI355X)
-        if (!pr->Gc && tl(1) <= lim) pr->Gc = 1;
+        if ((want == 1 || want == 2 || want == 4) && fits(want)) pr->Gc = want;
+        for (int gc = 4; !pr->Gc && gc >= 1; gc /= 2)
+            if (fits(gc)) pr->Gc = gc;
         const size_t need_boost = pr->prec == RRT_FP64 ? rrt::boost_lds<double>(pr->K, pr->G)
                                                        : rrt::boost_lds<float>(pr->K, pr->G);
-        if (!pr->Gc || (long)pr->nx * pr->ny > (long)rrt::kTraceThreads * rrt::kTraceMaxPts)
+        if (!pr->Gc || plane > rrt::kTraceMaxPlane)
             return bail(fail(RRT_E_INVALID, "an x-y plane is too large for the ray-trace kernel on this device"));
         if (scatter == RRT_COMPTON && pr->esz * (size_t)pr->G * pr->NL > lim)
             return bail(fail(RRT_E_INVALID, "groups x SH terms per point too large for the Compton source kernel"));

@@ -4,10 +4,8 @@
 
 namespace rrt {
 
-constexpr int kBezTerms64 = 18;   // series terms of the Bezier weights, h < 0.5 (FP64)
-constexpr int kBezTerms32 = 12;   // series terms of the Bezier weights, h < 1   (FP32)
-constexpr int kTraceThreads = 512;  // threads per ray-trace workgroup
-constexpr int kTraceMaxPts = 8;     // grid points of a plane per ray-trace thread (at most)
+constexpr int kTraceThreads = 1024;    // threads per ray-trace workgroup
+constexpr int kTraceMaxPlane = 4096;   // grid points of an x-y plane (at most): four per ray-trace thread
 constexpr int kRemapThreads = 512;  // threads per frame-transform workgroup (one lab ordinate each)
 
 // Per-ordinate geometry of the plane-to-plane short characteristic: path
@@ -93,8 +91,6 @@ template <typename real> struct SourceArgs {
     const real *chi0, *sigma, *kappa, *bnu, *A, *Ilm;
     real *S;
 };
-
-hipError_t upload_bezier_coefficients();
 
 template <typename real> void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st);
 template <typename real> void launch_boost(const BoostArgs<real> &a, hipStream_t st);

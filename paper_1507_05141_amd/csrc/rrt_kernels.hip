@@ -15,100 +15,117 @@ static constexpr double kPiD = 3.14159265358979323846;
 // cubic Bezier formal-solution weights
 // ---------------------------------------------------------------------------
 
-// Series coefficients of the four weights as functions of the optical depth h:
-// w_i(h) = h sum_m bez_c[i][m] h^m, bez_c[i][m] = (-1)^m/m! * int_0^1 b_i(u) u^m du
-// with b_0 = u^3, b_1 = 3u^2(1-u), b_2 = 3u(1-u)^2, b_3 = (1-u)^3.
-__constant__ double c_bez64[4][kBezTerms64];
-__constant__ float c_bez32[4][kBezTerms32];
-
-void bezier_series_coefficients(double (*c64)[kBezTerms64], float (*c32)[kBezTerms32])
-{
-    double fact = 1.0;
-    for (int m = 0; m < kBezTerms64; ++m) {
-        if (m > 0) fact *= m;
-        const double sgn = (m % 2) ? -1.0 : 1.0;
-        const double a = m + 1.0, b = m + 2.0, c = m + 3.0, d = m + 4.0;
-        const double v[4] = {1.0 / d, 3.0 / (c * d), 6.0 / (b * c * d), 6.0 / (a * b * c * d)};
-        for (int i = 0; i < 4; ++i) {
-            c64[i][m] = sgn / fact * v[i];
-            if (m < kBezTerms32) c32[i][m] = (float)(sgn / fact * v[i]);
-        }
-    }
-}
-
-hipError_t upload_bezier_coefficients()
-{
-    double c64[4][kBezTerms64];
-    float c32[4][kBezTerms32];
-    bezier_series_coefficients(c64, c32);
-    hipError_t e = hipMemcpyToSymbol(HIP_SYMBOL(c_bez64), c64, sizeof(c64));
-    if (e != hipSuccess) return e;
-    return hipMemcpyToSymbol(HIP_SYMBOL(c_bez32), c32, sizeof(c32));
-}
-
 // reciprocal: the hardware v_rcp_f32 (1 ulp) in FP32, exact division in FP64
 __device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
 __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 
+// With E_n(h) = int_0^h (u/h)^n e^{-u} du (u = optical distance back from the
+// downwind point), the downward recurrence E_{n-1} = (h/n)(E_n + e^{-h}) adds
+// positive terms only and is stable for every h.  It starts from
+// E_3 = (6/h^3) P(4, h), P the regularised lower incomplete gamma function:
+// for h < hs by its positive series P(4, h) = h^4 e^{-h} sum_k h^k/(k+4)!, else
+// as 1 - e^{-h}(1 + h + h^2/2 + h^3/6) (at most ~4 bits of cancellation).
+// Both branches are evaluated and selected, so a wave never diverges.
 template <typename real> struct BezTraits;
 template <> struct BezTraits<double> {
-    static constexpr double hs = 0.5;
-    static constexpr int nt = kBezTerms64;
-    __device__ static double c(int i, int m) { return c_bez64[i][m]; }
+    static constexpr double hs = 1.5;
+    static constexpr int nt = 18;      // last term < 1e-16 of the first at h = hs
     __device__ static double ex(double h) { return exp(-h); }
 };
 template <> struct BezTraits<float> {
-    static constexpr float hs = 1.0f;
-    static constexpr int nt = kBezTerms32;
-    __device__ static float c(int i, int m) { return c_bez32[i][m]; }
+    static constexpr float hs = 1.5f;
+    static constexpr int nt = 10;      // last term < 4e-8 of the first at h = hs
     __device__ static float ex(float h) { return __expf(-h); }
 };
 
-// integral over optical depth [0, h] of the Bezier source times e^{-(h - t)}
-// = w0 S_u + w1 C_u + w2 C_p + w3 S_p; ex = e^{-h}
+// 1/n! as a compile-time constant, and sum_{k=K}^{NT-1} h^(k-K)/(k+4)! by Horner's rule
+template <int N> struct InvFact { static constexpr double v = InvFact<N - 1>::v / N; };
+template <> struct InvFact<0> { static constexpr double v = 1.0; };
+template <typename real, int K, int NT> struct GammaSeries {
+    __device__ static real eval(real h) { return real(InvFact<K + 4>::v) + h * GammaSeries<real, K + 1, NT>::eval(h); }
+};
+template <typename real, int NT> struct GammaSeries<real, NT, NT> {
+    __device__ static real eval(real) { return real(0); }
+};
+
+// ex = e^{-h} and the moments E_0..E_3 over optical depth [0, h].  The
+// integral of the cubic Bezier source (control values S_u, C_u, C_p, S_p)
+// times e^{-u} is sum_i w_i S_i with Bernstein weights w_0 = E_3,
+// w_1 = 3(E_2 - E_3), w_2 = 3(E_1 - 2E_2 + E_3), w_3 = E_0 - 3E_1 + 3E_2 - E_3;
+// bezier_integral regroups it by moments (forward differences of the
+// control polygon).
 template <typename real>
-__device__ __forceinline__ void bezier_weights(real h, real &ex, real &w0, real &w1, real &w2, real &w3)
+__device__ __forceinline__ void bezier_moments(real h, real &ex, real &E0, real &E1, real &E2, real &E3)
 {
     using T = BezTraits<real>;
     ex = T::ex(h);
-    if (h < T::hs) {
-        real a0 = 0, a1 = 0, a2 = 0, a3 = 0;
-#pragma unroll
-        for (int m = T::nt - 1; m >= 0; --m) {
-            a0 = a0 * h + T::c(0, m);
-            a1 = a1 * h + T::c(1, m);
-            a2 = a2 * h + T::c(2, m);
-            a3 = a3 * h + T::c(3, m);
-        }
-        w0 = h * a0; w1 = h * a1; w2 = h * a2; w3 = h * a3;
-    } else {
-        const real ih = fast_rcp(h);
-        const real E0 = real(1) - ex;
-        const real E1 = E0 * ih - ex;
-        const real E2 = real(2) * E1 * ih - ex;
-        const real E3 = real(3) * E2 * ih - ex;
-        w0 = E3;
-        w1 = real(3) * (E2 - E3);
-        w2 = real(3) * (E1 - real(2) * E2 + E3);
-        w3 = E0 - real(3) * E1 + real(3) * E2 - E3;
+    const real e3s = real(6) * h * ex * GammaSeries<real, 0, T::nt>::eval(h);
+    const real ih = fast_rcp(h);
+    const real poly = ((h * real(1.0 / 6.0) + real(0.5)) * h + real(1)) * h + real(1);
+    const real e3l = real(6) * (real(1) - ex * poly) * (ih * ih * ih);
+    E3 = (h < T::hs) ? e3s : e3l;
+    E2 = h * real(1.0 / 3.0) * (E3 + ex);
+    E1 = h * real(0.5) * (E2 + ex);
+    E0 = h * (E1 + ex);
+}
+
+template <typename real>
+__device__ __forceinline__ real bezier_integral(real E0, real E1, real E2, real E3, real Su, real Cu, real Cp, real Sp)
+{
+    const real d1 = Cp - Sp, d2 = (Cu - Cp) - d1, d3 = (Su - Cu) - real(2) * (Cu - Cp) + d1;
+    return E0 * Sp + real(3) * (E1 * d1 + E2 * d2) + E3 * d3;
+}
+
+// Optical-depth part of one step u -> p, shared by every group with the same
+// extinction.  The Fritsch-Butland weighted harmonic-mean slope at a point
+// between a left segment (source change dl over optical depth hl) and a right
+// one (dr over hr), with alpha = (1 + hr/(hl + hr))/3, is
+// (dl/hl)(dr/hr) / (alpha dr/hr + (1 - alpha) dl/hl); times the step depth h it
+// equals n dl dr / (a dr + b dl) with a = hl (hl + 2 hr), b = hr (2 hl + hr),
+// n = 3 h (hl + hr), and is zero unless dl dr > 0 and hl, hr > 0.
+template <typename real>
+struct StepDepth {
+    real hu;                    // optical depth of the step
+    real ap, bp, np;            // slope at p: left = the step, right = p -> d
+    real au, bu, nu;            // slope at u: left = uu -> u, right = the step
+    bool okp, oku;
+    real ex, E0, E1, E2, E3;    // e^{-hu} and the Bezier moments
+};
+
+template <typename real>
+__device__ __forceinline__ StepDepth<real> step_depth(real hds, real Xuu, real Xu, real Xp, real Xd, bool has_d,
+                                                     bool has_uu)
+{
+    StepDepth<real> g;
+    const real hu = hds * (Xu + Xp);
+    g.hu = hu;
+    g.ap = g.bp = g.np = g.au = g.bu = g.nu = real(0);
+    g.okp = g.oku = false;
+    if (has_d) {
+        const real hd = hds * (Xp + Xd);
+        g.ap = hu * (hu + real(2) * hd);
+        g.bp = hd * (real(2) * hu + hd);
+        g.np = real(3) * hu * (hu + hd);
+        g.okp = hu > real(0) && hd > real(0);
     }
+    if (has_uu) {
+        const real huu = hds * (Xuu + Xu);
+        g.au = huu * (huu + real(2) * hu);
+        g.bu = hu * (real(2) * huu + hu);
+        g.nu = real(3) * hu * (huu + hu);
+        g.oku = huu > real(0) && hu > real(0);
+    }
+    bezier_moments(hu, g.ex, g.E0, g.E1, g.E2, g.E3);
+    return g;
 }
 
-// Fritsch-Butland weighted harmonic mean of the slopes on the left (dl, over
-// optical depth hl) and right (dr, hr) of a point.
+// step depth times the Fritsch-Butland slope from the source changes dl, dr
 template <typename real>
-__device__ __forceinline__ real fb_slope(real dl, real dr, real hl, real hr)
+__device__ __forceinline__ real fb_slope(real n, real a, real b, bool ok, real dl, real dr)
 {
-    if (dl * dr <= real(0)) return real(0);
-    const real al = (real(1) + hr * fast_rcp(hl + hr)) * real(1.0 / 3.0);
-    return dl * dr * fast_rcp(al * dr + (real(1) - al) * dl);
-}
-
-template <typename real>
-__device__ __forceinline__ real clamp_between(real v, real a, real b)
-{
-    const real lo = fmin(a, b), hi = fmax(a, b);
-    return fmin(fmax(v, lo), hi);
+    const real prod = dl * dr;
+    const real v = n * prod * fast_rcp(a * dr + b * dl);
+    return (ok && prod > real(0)) ? v : real(0);
 }
 
 // periodic bilinear value of a plane stored F[(y * nx + x) * ge] (ge values
@@ -302,19 +319,30 @@ __device__ __forceinline__ double inv_doppler(const double b[3], double gam, con
 // ---------------------------------------------------------------------------
 // S4: ray trace.  One workgroup of kTraceThreads per (ordinate, chunk of GC
 // groups) marches the z planes from the inflow face; each thread owns up to
-// MAXPT grid points of the plane with all GC groups.  The source S~ and
-// extinction chi~ of the four planes a step touches (second upwind, upwind,
-// current, downwind) sit in an LDS ring, the previous intensity plane in LDS
+// MAXPT grid points of the plane with their GC groups, which it reads and
+// writes as one vector (lab arrays are [k][p][g]), so the tap addresses and a
+// grey extinction are shared by the groups.  The source S~ and extinction
+// chi~ of the four planes a step touches (second upwind, upwind, current,
+// downwind) sit in an LDS ring, the previous intensity plane in LDS
 // (overwritten by the new one once every thread has read it); the next plane
 // is fetched into registers while the current one is computed.
 // LDS planes carry a one-column and one-row periodic halo (row stride nx + 1)
 // so that the bilinear taps need no wrap.  chi~ = chi_lab + 1/(c dt) with
 // chi_lab precomputed per medium (one value per point when it is grey) or read
-// from an array for the stand-alone entry point.  Lab arrays are [k][p][g].
+// from an array for the stand-alone entry point (XMODE: kChiGrey, kChiGroup,
+// kChiArray).  With a grey chi~ the optical depths, slope coefficients and
+// Bezier moments of a point are computed once for its GC groups.
 // ---------------------------------------------------------------------------
-template <typename real, bool CHI_ARRAY, int GC, int MAXPT>
+constexpr int kChiGrey = 0, kChiGroup = 1, kChiArray = 2;
+
+template <typename real, int N>
+struct alignas(sizeof(real) * N) Pack {
+    real v[N];
+};
+
+template <typename real, int GC, int MAXPT>
 struct PlaneRegs {
-    real s[MAXPT][GC], x[MAXPT][GC];
+    Pack<real, GC> s[MAXPT], x[MAXPT];      // x[c].v[0] only when chi~ is grey
 };
 
 // (i, j) of plane point pe without an integer division: (pe + 1/2)/nx in FP32
@@ -331,106 +359,121 @@ struct TraceIdx {
     float rnx;                  // 1/nx
 };
 
-// global -> registers: S~ and chi~ of plane t for this thread's points
-template <typename real, bool CHI_ARRAY, int GC, int MAXPT>
-__device__ __forceinline__ void trace_fetch(PlaneRegs<real, CHI_ARRAY, GC, MAXPT> &r, const real *__restrict__ Sk,
-                                            const real *__restrict__ Xk, const real *__restrict__ Ck, int G, int PL,
-                                            int m, real icdt, bool xg)
+// global -> registers: S~ and chi (raw) of plane m for this thread's points.
+// Threads past the end of the plane load its last point (never stored), so
+// the loads are unconditional and stay in flight until the values are stored.
+template <typename real, int XMODE, int GC, int MAXPT>
+__device__ __forceinline__ void trace_fetch(PlaneRegs<real, GC, MAXPT> &r, const real *__restrict__ Sk,
+                                            const real *__restrict__ Xk, int G, int PL, int m)
 {
+    using P = Pack<real, GC>;
 #pragma unroll
     for (int c = 0; c < MAXPT; ++c) {
-        const int pe = threadIdx.x + c * kTraceThreads;
-        if (pe < PL) {
-            const int pidx = m * PL + pe;
-            const int o = pidx * G;
-#pragma unroll
-            for (int gi = 0; gi < GC; ++gi) r.s[c][gi] = Sk[o + gi];
-            if (CHI_ARRAY) {
-#pragma unroll
-                for (int gi = 0; gi < GC; ++gi) r.x[c][gi] = Xk[o + gi];
-            } else if (xg) {
-                r.x[c][0] = Ck[pidx] + icdt;
-            } else {
-#pragma unroll
-                for (int gi = 0; gi < GC; ++gi) r.x[c][gi] = Xk[o + gi] + icdt;
-            }
-        }
+        const int pidx = m * PL + min((int)threadIdx.x + c * kTraceThreads, PL - 1), o = pidx * G;
+        r.s[c] = *reinterpret_cast<const P *>(Sk + o);
+        if (XMODE == kChiGrey) r.x[c].v[0] = Xk[pidx];
+        else r.x[c] = *reinterpret_cast<const P *>(Xk + o);
     }
 }
 
 // write value v of point (i, j) into an LDS plane with its periodic halo
-template <typename real>
-__device__ __forceinline__ void lds_put(real *pl, const TraceIdx &q, int i, int j, int ge, int gi, real v)
+template <typename T>
+__device__ __forceinline__ void lds_put(T *pl, const TraceIdx &q, int i, int j, const T &v)
 {
-    pl[(j * q.RS + i) * ge + gi] = v;
-    if (i == 0) pl[(j * q.RS + q.nx) * ge + gi] = v;
+    pl[j * q.RS + i] = v;
+    if (i == 0) pl[j * q.RS + q.nx] = v;
     if (j == 0) {
-        pl[(q.ny * q.RS + i) * ge + gi] = v;
-        if (i == 0) pl[(q.ny * q.RS + q.nx) * ge + gi] = v;
+        pl[q.ny * q.RS + i] = v;
+        if (i == 0) pl[q.ny * q.RS + q.nx] = v;
     }
 }
 
-// registers -> the LDS ring slot of plane t
-template <typename real, bool CHI_ARRAY, int GC, int MAXPT>
-__device__ __forceinline__ void trace_store(const PlaneRegs<real, CHI_ARRAY, GC, MAXPT> &r, real *Sr, real *Xr,
-                                            const TraceIdx &q, int t, bool xg)
+// registers -> the LDS ring slot of plane t; chi~ = chi + add (the time term)
+template <typename real, int XMODE, int GC, int MAXPT>
+__device__ __forceinline__ void trace_store(const PlaneRegs<real, GC, MAXPT> &r, real *Sr, real *Xr,
+                                            const TraceIdx &q, int t, real add)
 {
-    const int xge = xg ? 1 : GC;
-    real *Sd = Sr + (t & 3) * q.PS * GC, *Xd = Xr + (t & 3) * q.PS * xge;
+    constexpr bool xg = XMODE == kChiGrey;
+    using P = Pack<real, GC>;
+    P *Sd = reinterpret_cast<P *>(Sr + (t & 3) * q.PS * GC);
 #pragma unroll
     for (int c = 0; c < MAXPT; ++c) {
         const int pe = threadIdx.x + c * kTraceThreads;
         if (pe < q.PL) {
             int i, j;
             plane_ij(pe, q.nx, q.rnx, i, j);
-#pragma unroll
-            for (int gi = 0; gi < GC; ++gi) lds_put(Sd, q, i, j, GC, gi, r.s[c][gi]);
+            lds_put(Sd, q, i, j, r.s[c]);
             if (xg) {
-                lds_put(Xd, q, i, j, 1, 0, r.x[c][0]);
+                lds_put(Xr + (t & 3) * q.PS, q, i, j, r.x[c].v[0] + add);
             } else {
+                P x = r.x[c];
 #pragma unroll
-                for (int gi = 0; gi < GC; ++gi) lds_put(Xd, q, i, j, GC, gi, r.x[c][gi]);
+                for (int n = 0; n < GC; ++n) x.v[n] += add;
+                lds_put(reinterpret_cast<P *>(Xr + (t & 3) * q.PS * GC), q, i, j, x);
             }
         }
     }
 }
 
-// bilinear value from an LDS plane with halo: base = tap (i0, j0), weights w
-template <typename real>
-__device__ __forceinline__ real bil(const real *pl, int base, int dx, int dy, const real w[4])
+// bilinear value of GC groups from an LDS plane with halo: tap cell, row stride RS
+template <typename real, int N>
+__device__ __forceinline__ Pack<real, N> bil(const Pack<real, N> *pl, int cell, int RS, const real w[4])
 {
-    return w[0] * pl[base] + w[1] * pl[base + dx] + w[2] * pl[base + dy] + w[3] * pl[base + dx + dy];
+    const Pack<real, N> a = pl[cell], b = pl[cell + 1], c = pl[cell + RS], d = pl[cell + RS + 1];
+    Pack<real, N> r;
+#pragma unroll
+    for (int n = 0; n < N; ++n) r.v[n] = w[0] * a.v[n] + w[1] * b.v[n] + w[2] * c.v[n] + w[3] * d.v[n];
+    return r;
 }
 
-template <typename real, bool CHI_ARRAY, int GC, int MAXPT>
-__global__ void __launch_bounds__(kTraceThreads, (MAXPT <= 2 && sizeof(real) == 4) ? 8 : 1) k_trace(TraceArgs<real> a)
+template <typename real, int XMODE, int GC, int MAXPT>
+__global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
 {
+    using P = Pack<real, GC>;
+    using PX = Pack<real, XMODE == kChiGrey ? 1 : GC>;
     constexpr int T = kTraceThreads;
+    constexpr bool xg = XMODE == kChiGrey;
+    constexpr int XG = xg ? 1 : GC;
     extern __shared__ unsigned char smem_raw[];
     const int nx = a.nx, ny = a.ny, nz = a.nz, PL = nx * ny, G = a.G;
     const int nch = G / GC;
-    const long item = xcd_item((long)a.K * nch);
-    if (item >= (long)a.K * nch) return;
-    const int k = (int)(item / nch), g0 = (int)(item - (long)k * nch) * GC;
+    const long wi = xcd_item((long)a.K * nch);
+    if (wi >= (long)a.K * nch) return;
+    const int k = (int)(wi / nch), g0 = (int)(wi - (long)k * nch) * GC;
     const TraceIdx q{nx, ny, PL, nx + 1, (nx + 1) * (ny + 1), 1.0f / (float)nx};
-    const int NE = q.PS * GC;
-    const bool xg = !CHI_ARRAY && a.chi_grey;        // one chi~ per point
-    const int xge = xg ? 1 : GC, XE = q.PS * xge;
+    const int XE = q.PS * XG;
     real *Sr = reinterpret_cast<real *>(smem_raw);
-    real *Xr = Sr + 4 * NE;
-    real *Ir = Xr + 4 * XE;
+    real *Xr = Sr + 4 * q.PS * GC;
+    P *Ir = reinterpret_cast<P *>(Xr + 4 * XE);
     const OrdGeom gm = a.geo[k];
     const long slab = (long)k * a.P * G + g0;        // start of this ordinate's lab slab (+ chunk)
     const real *__restrict__ Sk = a.St + slab;
-    const real *__restrict__ Xk = CHI_ARRAY ? a.Xt + slab : (xg ? nullptr : a.chilab + slab);
-    const real *__restrict__ Ck = xg ? a.chilab + (long)k * a.P : nullptr;
+    const real *__restrict__ Xk = XMODE == kChiArray ? a.Xt + slab
+                                : (XMODE == kChiGrey ? a.chilab + (long)k * a.P : a.chilab + slab);
     real *__restrict__ Ik = a.I + slab;
     const int tid = threadIdx.x;
-    PlaneRegs<real, CHI_ARRAY, GC, MAXPT> rg;
+    PlaneRegs<real, GC, MAXPT> rg;
 
+    // LDS cell of each point and of its three bilinear tap cells (second
+    // upwind, upwind, downwind): the same on every plane
+    int self[MAXPT], cell[MAXPT][3];
+#pragma unroll
+    for (int c = 0; c < MAXPT; ++c) {
+        int i, j;
+        plane_ij(min(tid + c * T, PL - 1), nx, q.rnx, i, j);
+        self[c] = j * q.RS + i;
+#pragma unroll
+        for (int s = 0; s < 3; ++s) {
+            int i0 = i + gm.ix[s]; if (i0 >= nx) i0 -= nx;
+            int j0 = j + gm.iy[s]; if (j0 >= ny) j0 -= ny;
+            cell[c][s] = j0 * q.RS + i0;
+        }
+    }
+
+    const real add = XMODE == kChiArray ? real(0) : a.inv_cdt;   // the stand-alone chi~ already holds it
     for (int t = 0; t < nz && t < 3; ++t) {
-        trace_fetch(rg, Sk, Xk, Ck, G, PL, gm.up ? t : nz - 1 - t, a.inv_cdt, xg);
-        trace_store(rg, Sr, Xr, q, t, xg);
+        trace_fetch<real, XMODE, GC, MAXPT>(rg, Sk, Xk, G, PL, gm.up ? t : nz - 1 - t);
+        trace_store<real, XMODE, GC, MAXPT>(rg, Sr, Xr, q, t, add);
     }
     {
         const int m0 = gm.up ? 0 : nz - 1;
@@ -441,16 +484,19 @@ __global__ void __launch_bounds__(kTraceThreads, (MAXPT <= 2 && sizeof(real) == 
             if (pe >= PL) break;
             int i, j;
             plane_ij(pe, nx, q.rnx, i, j);
+            P v;
+            if (bc) {
+                v = *reinterpret_cast<const P *>(bc + ((long)k * PL + pe) * G + g0);
+            } else {
 #pragma unroll
-            for (int gi = 0; gi < GC; ++gi) {
-                const real v = bc ? bc[((long)k * PL + pe) * G + g0 + gi] : real(0);
-                lds_put(Ir, q, i, j, GC, gi, v);
-                Ik[(m0 * PL + pe) * G + gi] = v;
+                for (int n = 0; n < GC; ++n) v.v[n] = real(0);
             }
+            lds_put(Ir, q, i, j, v);
+            *reinterpret_cast<P *>(Ik + (m0 * PL + pe) * G) = v;
         }
     }
     __syncthreads();
-    const real ds = (real)gm.ds;
+    const real hds = real(0.5) * (real)gm.ds;
     real wts[3][4];
 #pragma unroll
     for (int s = 0; s < 3; ++s) {
@@ -460,78 +506,51 @@ __global__ void __launch_bounds__(kTraceThreads, (MAXPT <= 2 && sizeof(real) == 
         wts[s][2] = (real(1) - fx) * fy;
         wts[s][3] = fx * fy;
     }
-    const int dxS = GC, dyS = q.RS * GC, dxX = xge, dyX = q.RS * xge;
+    const int RS = q.RS;
     for (int t = 1; t < nz; ++t) {
-        if (t + 2 < nz) trace_fetch(rg, Sk, Xk, Ck, G, PL, gm.up ? t + 2 : nz - 3 - t, a.inv_cdt, xg);
+        if (t + 2 < nz) trace_fetch<real, XMODE, GC, MAXPT>(rg, Sk, Xk, G, PL, gm.up ? t + 2 : nz - 3 - t);
         const int m = gm.up ? t : nz - 1 - t;
         const bool has_d = t <= nz - 2, has_uu = t >= 2;
-        const real *Spl = Sr + (t & 3) * NE, *Xpl = Xr + (t & 3) * XE;
-        const real *Sul = Sr + ((t - 1) & 3) * NE, *Xul = Xr + ((t - 1) & 3) * XE;
-        const real *Suul = Sr + ((t - 2) & 3) * NE, *Xuul = Xr + ((t - 2) & 3) * XE;
-        const real *Sdl = Sr + ((t + 1) & 3) * NE, *Xdl = Xr + ((t + 1) & 3) * XE;
-        const real *Iprv = Ir;
-        real res[MAXPT][GC];
+        const P *Spl = reinterpret_cast<const P *>(Sr + (t & 3) * q.PS * GC);
+        const P *Sul = reinterpret_cast<const P *>(Sr + ((t - 1) & 3) * q.PS * GC);
+        const P *Suul = reinterpret_cast<const P *>(Sr + ((t - 2) & 3) * q.PS * GC);
+        const P *Sdl = reinterpret_cast<const P *>(Sr + ((t + 1) & 3) * q.PS * GC);
+        const PX *Xpl = reinterpret_cast<const PX *>(Xr + (t & 3) * XE);
+        const PX *Xul = reinterpret_cast<const PX *>(Xr + ((t - 1) & 3) * XE);
+        const PX *Xuul = reinterpret_cast<const PX *>(Xr + ((t - 2) & 3) * XE);
+        const PX *Xdl = reinterpret_cast<const PX *>(Xr + ((t + 1) & 3) * XE);
+        P res[MAXPT];
 #pragma unroll
         for (int c = 0; c < MAXPT; ++c) {
-            const int pe = tid + c * T;
-            if (pe >= PL) break;
-            int i, j;
-            plane_ij(pe, nx, q.rnx, i, j);
-            // tap cells of the three shifted points (second upwind, upwind, downwind)
-            int cell[3];
+            const int cp = self[c], cu = cell[c][1], cd = cell[c][2], cuu = cell[c][0];
+            const P Sp = Spl[cp], Su = bil(Sul, cu, RS, wts[1]), Iu = bil(Ir, cu, RS, wts[1]);
+            P Sd, Suu;
+            PX Xd, Xuu;
+            const PX Xp = Xpl[cp], Xu = bil(Xul, cu, RS, wts[1]);
+            if (has_d) {
+                Sd = bil(Sdl, cd, RS, wts[2]);
+                Xd = bil(Xdl, cd, RS, wts[2]);
+            }
+            if (has_uu) {
+                Suu = bil(Suul, cuu, RS, wts[0]);
+                Xuu = bil(Xuul, cuu, RS, wts[0]);
+            }
+            StepDepth<real> gd;
+            if (xg) gd = step_depth(hds, Xuu.v[0], Xu.v[0], Xp.v[0], Xd.v[0], has_d, has_uu);
 #pragma unroll
-            for (int s = 0; s < 3; ++s) {
-                int i0 = i + gm.ix[s]; if (i0 >= nx) i0 -= nx;
-                int j0 = j + gm.iy[s]; if (j0 >= ny) j0 -= ny;
-                cell[s] = j0 * q.RS + i0;
+            for (int n = 0; n < GC; ++n) {
+                if (!xg) gd = step_depth(hds, Xuu.v[n % XG], Xu.v[n % XG], Xp.v[n % XG], Xd.v[n % XG], has_d, has_uu);
+                const real sp = Sp.v[n], su = Su.v[n];
+                const real dl = sp - su;
+                // step depth times the slopes at p and at u (secant where the outer neighbour is missing)
+                const real tp = has_d ? fb_slope(gd.np, gd.ap, gd.bp, gd.okp, dl, Sd.v[n] - sp) : dl;
+                const real tu = has_uu ? fb_slope(gd.nu, gd.au, gd.bu, gd.oku, su - Suu.v[n], dl) : dl;
+                const real lo = fmin(su, sp), hi = fmax(su, sp);
+                const real Cu = fmin(fmax(su + tu * real(1.0 / 3.0), lo), hi);
+                const real Cp = fmin(fmax(sp - tp * real(1.0 / 3.0), lo), hi);
+                res[c].v[n] = Iu.v[n] * gd.ex + bezier_integral(gd.E0, gd.E1, gd.E2, gd.E3, su, Cu, Cp, sp);
             }
-            const int self = j * q.RS + i;
-            real Xp = 0, Xu = 0, Xd = 0, Xuu = 0;
-            if (xg) {
-                Xp = Xpl[self];
-                Xu = bil(Xul, cell[1], dxX, dyX, wts[1]);
-                if (has_d) Xd = bil(Xdl, cell[2], dxX, dyX, wts[2]);
-                if (has_uu) Xuu = bil(Xuul, cell[0], dxX, dyX, wts[0]);
-            }
-            const int og = (m * PL + pe) * G;
-#pragma unroll
-            for (int gi = 0; gi < GC; ++gi) {
-                if (!xg) {
-                    Xp = Xpl[self * GC + gi];
-                    Xu = bil(Xul + gi, cell[1] * GC, dxX, dyX, wts[1]);
-                    if (has_d) Xd = bil(Xdl + gi, cell[2] * GC, dxX, dyX, wts[2]);
-                    if (has_uu) Xuu = bil(Xuul + gi, cell[0] * GC, dxX, dyX, wts[0]);
-                }
-                const real Sp = Spl[self * GC + gi];
-                const real Su = bil(Sul + gi, cell[1] * GC, dxS, dyS, wts[1]);
-                const real Iu = bil(Iprv + gi, cell[1] * GC, dxS, dyS, wts[1]);
-                const real hu = ds * real(0.5) * (Xu + Xp);
-                real dSp = 0, dSu = 0;
-                if (hu > real(0)) {
-                    const real d1 = (Sp - Su) * fast_rcp(hu);
-                    if (has_d) {
-                        const real Sd = bil(Sdl + gi, cell[2] * GC, dxS, dyS, wts[2]);
-                        const real hd = ds * real(0.5) * (Xp + Xd);
-                        dSp = (hd > real(0)) ? fb_slope(d1, (Sd - Sp) * fast_rcp(hd), hu, hd) : real(0);
-                    } else {
-                        dSp = d1;
-                    }
-                    if (has_uu) {
-                        const real Suu = bil(Suul + gi, cell[0] * GC, dxS, dyS, wts[0]);
-                        const real huu = ds * real(0.5) * (Xuu + Xu);
-                        dSu = (huu > real(0)) ? fb_slope((Su - Suu) * fast_rcp(huu), d1, huu, hu) : real(0);
-                    } else {
-                        dSu = d1;
-                    }
-                }
-                const real Cu = clamp_between(Su + hu * dSu * real(1.0 / 3.0), Su, Sp);
-                const real Cp = clamp_between(Sp - hu * dSp * real(1.0 / 3.0), Su, Sp);
-                real ex, w0, w1, w2, w3;
-                bezier_weights(hu, ex, w0, w1, w2, w3);
-                const real v = Iu * ex + w0 * Su + w1 * Cu + w2 * Cp + w3 * Sp;
-                res[c][gi] = v;
-                Ik[og + gi] = v;
-            }
+            if (tid + c * T < PL) *reinterpret_cast<P *>(Ik + (m * PL + tid + c * T) * G) = res[c];
         }
         __syncthreads();
         // every read of plane t - 1 is done: the intensity plane and the slot of
@@ -542,10 +561,9 @@ __global__ void __launch_bounds__(kTraceThreads, (MAXPT <= 2 && sizeof(real) == 
             if (pe >= PL) break;
             int i, j;
             plane_ij(pe, nx, q.rnx, i, j);
-#pragma unroll
-            for (int gi = 0; gi < GC; ++gi) lds_put(Ir, q, i, j, GC, gi, res[c][gi]);
+            lds_put(Ir, q, i, j, res[c]);
         }
-        if (t + 2 < nz) trace_store(rg, Sr, Xr, q, t + 2, xg);
+        if (t + 2 < nz) trace_store<real, XMODE, GC, MAXPT>(rg, Sr, Xr, q, t + 2, add);
         __syncthreads();
     }
 }
@@ -1062,18 +1080,22 @@ void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st)
     const long items = (long)a.K * (a.G / a.Gc);
     const dim3 grid((unsigned)(8 * ((items + 7) / 8))), block(kTraceThreads);
     const int npt = (a.nx * a.ny + kTraceThreads - 1) / kTraceThreads;
-#define RRT_TRACE_CASE(GC, MP)                                                                     \
-    if (a.Gc == GC && npt <= MP) {                                                                 \
-        if (chi_array) hipLaunchKernelGGL((k_trace<real, true, GC, MP>), grid, block, sm, st, a);  \
-        else hipLaunchKernelGGL((k_trace<real, false, GC, MP>), grid, block, sm, st, a);           \
-        return;                                                                                    \
+#define RRT_TRACE_CASE(GC, MP)                                                                       \
+    if (a.Gc == GC && npt <= MP) {                                                                   \
+        if (chi_array) hipLaunchKernelGGL((k_trace<real, kChiArray, GC, MP>), grid, block, sm, st, a); \
+        else if (a.chi_grey) hipLaunchKernelGGL((k_trace<real, kChiGrey, GC, MP>), grid, block, sm, st, a); \
+        else hipLaunchKernelGGL((k_trace<real, kChiGroup, GC, MP>), grid, block, sm, st, a);          \
+        return;                                                                                      \
     }
     RRT_TRACE_CASE(1, 1)
     RRT_TRACE_CASE(1, 2)
-    RRT_TRACE_CASE(1, 8)
+    RRT_TRACE_CASE(1, 4)
     RRT_TRACE_CASE(2, 1)
     RRT_TRACE_CASE(2, 2)
-    RRT_TRACE_CASE(2, 8)
+    RRT_TRACE_CASE(2, 4)
+    RRT_TRACE_CASE(4, 1)
+    RRT_TRACE_CASE(4, 2)
+    RRT_TRACE_CASE(4, 4)
 #undef RRT_TRACE_CASE
 }
 template <typename real>
@@ -1154,30 +1176,60 @@ void launch_rk_stage(long n, const real *R, real *Iin, real *acc, real *In, int 
 
 hipError_t set_lds_limits(size_t bytes)
 {
-    const void *fns[] = {reinterpret_cast<const void *>(&k_trace<float, true, 1, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, true, 1, 2>),
-                         reinterpret_cast<const void *>(&k_trace<float, true, 1, 8>),
-                         reinterpret_cast<const void *>(&k_trace<float, true, 2, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, true, 2, 2>),
-                         reinterpret_cast<const void *>(&k_trace<float, true, 2, 8>),
-                         reinterpret_cast<const void *>(&k_trace<float, false, 1, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, false, 1, 2>),
-                         reinterpret_cast<const void *>(&k_trace<float, false, 1, 8>),
-                         reinterpret_cast<const void *>(&k_trace<float, false, 2, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, false, 2, 2>),
-                         reinterpret_cast<const void *>(&k_trace<float, false, 2, 8>),
-                         reinterpret_cast<const void *>(&k_trace<double, true, 1, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, true, 1, 2>),
-                         reinterpret_cast<const void *>(&k_trace<double, true, 1, 8>),
-                         reinterpret_cast<const void *>(&k_trace<double, true, 2, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, true, 2, 2>),
-                         reinterpret_cast<const void *>(&k_trace<double, true, 2, 8>),
-                         reinterpret_cast<const void *>(&k_trace<double, false, 1, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, false, 1, 2>),
-                         reinterpret_cast<const void *>(&k_trace<double, false, 1, 8>),
-                         reinterpret_cast<const void *>(&k_trace<double, false, 2, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, false, 2, 2>),
-                         reinterpret_cast<const void *>(&k_trace<double, false, 2, 8>),
+    const void *fns[] = {reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 1, 1>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 1, 2>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 1, 4>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 2, 1>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 2, 2>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 2, 4>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 4, 1>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 4, 2>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 4, 4>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 1, 1>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 1, 2>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 1, 4>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 2, 1>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 2, 2>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 2, 4>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 4, 1>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 4, 2>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 4, 4>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 1, 1>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 1, 2>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 1, 4>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 2, 1>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 2, 2>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 2, 4>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 4, 1>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 4, 2>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 4, 4>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 1, 1>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 1, 2>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 1, 4>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 2, 1>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 2, 2>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 2, 4>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 4, 1>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 4, 2>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 4, 4>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 1, 1>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 1, 2>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 1, 4>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 2, 1>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 2, 2>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 2, 4>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 4, 1>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 4, 2>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 4, 4>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 1, 1>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 1, 2>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 1, 4>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 2, 1>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 2, 2>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 2, 4>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 4, 1>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 4, 2>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 4, 4>),
                          reinterpret_cast<const void *>(&k_boost<float>),
                          reinterpret_cast<const void *>(&k_boost<double>),
                          reinterpret_cast<const void *>(&k_unboost<float>),
