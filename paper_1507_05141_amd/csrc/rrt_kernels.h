@@ -97,6 +97,7 @@ template <typename real> void launch_boost(const BoostArgs<real> &a, hipStream_t
 template <typename real> void launch_unboost(const UnboostArgs<real> &a, hipStream_t st);
 template <typename real> size_t trace_lds(int nx, int ny, int Gc, int chi_per_point);
 template <typename real> size_t boost_lds(int K, int G);
+template <typename real> size_t unboost_lds(int K, int G);
 template <typename real> void launch_chilab(const ChiLabArgs<real> &a, hipStream_t st);
 template <typename real> void launch_source(const SourceArgs<real> &a, hipStream_t st);
 template <typename real> void launch_chi0(long P, int G, const real *kappa, const real *sigma, const real *sg, real *chi0, hipStream_t st);

@@ -166,56 +166,43 @@ struct AngleTaps {
     double wmu, wphi;
 };
 
-// bilinear taps of direction n on the Gauss-Legendre x uniform-azimuth mesh
+// bilinear taps of direction n on the Gauss-Legendre x uniform-azimuth mesh,
+// located in precision T (the working precision: the direction itself comes
+// from double-precision Lorentz maps)
+template <typename T>
 __device__ __forceinline__ AngleTaps angle_taps(const double *__restrict__ mu, int nmu, int nphi, const double n[3])
 {
+    constexpr T two_pi = T(2.0 * kPiD);
     AngleTaps t;
-    double ms = fmin(1.0, fmax(-1.0, n[2]));
-    double ph = atan2(n[1], n[0]);
-    if (ph < 0.0) ph += 2.0 * kPiD;
-    const double s = ph * (nphi / (2.0 * kPiD));
-    const double sf = floor(s);
-    t.wphi = s - sf;
-    int b0 = (int)sf % nphi;
+    const T ms = fmin(T(1), fmax(T(-1), (T)n[2]));
+    T ph = atan2((T)n[1], (T)n[0]);
+    if (ph < T(0)) ph += two_pi;
+    const T s = ph * ((T)nphi / two_pi);
+    const T sf = floor(s);
+    t.wphi = (double)(s - sf);
+    int b0 = (int)sf;
+    if (b0 >= nphi) b0 -= nphi;
     if (b0 < 0) b0 += nphi;
     t.b0 = b0;
     t.b1 = (b0 + 1 == nphi) ? 0 : b0 + 1;
-    if (ms < mu[0]) {
+    const T mlo = (T)mu[0], mhi = (T)mu[nmu - 1];
+    if (ms < mlo) {
         t.a0 = -1; t.a1 = 0;
-        t.wmu = (ms + 1.0) / (mu[0] + 1.0);
-    } else if (ms > mu[nmu - 1]) {
+        t.wmu = (double)((ms + T(1)) / (mlo + T(1)));
+    } else if (ms > mhi) {
         t.a0 = nmu - 1; t.a1 = nmu;
-        t.wmu = (ms - mu[nmu - 1]) / (1.0 - mu[nmu - 1]);
+        t.wmu = (double)((ms - mhi) / (T(1) - mhi));
     } else {
         int lo = 0, hi = nmu - 1;          // mu[lo] <= ms <= mu[hi]
         while (hi - lo > 1) {
             const int mid = (lo + hi) >> 1;
-            if (ms > mu[mid]) lo = mid; else hi = mid;
+            if (ms > (T)mu[mid]) lo = mid; else hi = mid;
         }
         t.a0 = lo; t.a1 = lo + 1;
-        t.wmu = (ms - mu[lo]) / (mu[lo + 1] - mu[lo]);
+        const T m0 = (T)mu[lo];
+        t.wmu = (double)((ms - m0) / ((T)mu[lo + 1] - m0));
     }
     return t;
-}
-
-// taps as kept in LDS, weights in the working precision
-template <typename real> struct TapL {
-    int a0, a1, b0, b1;
-    real wmu, wphi;
-};
-
-// value at the taps of a field F[k * sk + g * sg] (k = ordinate) held in LDS;
-// pole[g] / pole[G + g] are the azimuthal means of the lowest / highest ring
-template <typename real>
-__device__ __forceinline__ real tap_value(const real *F, int sk, int sg, int G, int g, int nmu, int nphi,
-                                          const TapL<real> &t, const real *pole)
-{
-    auto ring = [&](int a) -> real {
-        if (a < 0) return pole[g];
-        if (a >= nmu) return pole[G + g];
-        return (real(1) - t.wphi) * F[(a * nphi + t.b0) * sk + g * sg] + t.wphi * F[(a * nphi + t.b1) * sk + g * sg];
-    };
-    return (real(1) - t.wmu) * ring(t.a0) + t.wmu * ring(t.a1);
 }
 
 // frequency bracket in ln(nu): value = wl * v[gl] + wh * v[gh]; gl/gh = -1 means 0
@@ -599,25 +586,88 @@ __device__ __forceinline__ FreqTaps freq_taps_zero_walk(const FreqInfo &f, const
     return r;
 }
 
+// ---------------------------------------------------------------------------
+// Frame transforms (S3, S5).  One workgroup per grid point stages that point's
+// values in an LDS table F[r][c]: row r = g + 1 for group g, rows 0 and G + 1
+// zero (the ghost centres beyond the outer edges); column c < K an ordinate,
+// c = K / K + 1 the azimuthal mean of the lowest / highest polar ring (the
+// pole values); row stride KS = (K + 2) | 1, odd, so that writing a column
+// hits distinct banks.  A direction's bilinear taps become four columns with
+// combined weights, the same for every group.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int table_stride(int K) { return (K + 2) | 1; }
+
+template <typename real> struct Taps4 {
+    int c[4];
+    real w[4];
+};
+
+template <typename real>
+__device__ __forceinline__ Taps4<real> taps4(const AngleTaps &t, int K, int nmu, int nphi)
+{
+    auto col = [&](int ring, int b) { return ring < 0 ? K : (ring >= nmu ? K + 1 : ring * nphi + b); };
+    Taps4<real> r;
+    r.c[0] = col(t.a0, t.b0); r.c[1] = col(t.a0, t.b1);
+    r.c[2] = col(t.a1, t.b0); r.c[3] = col(t.a1, t.b1);
+    const double um = 1.0 - t.wmu, up = 1.0 - t.wphi;
+    r.w[0] = (real)(um * up); r.w[1] = (real)(um * t.wphi);
+    r.w[2] = (real)(t.wmu * up); r.w[3] = (real)(t.wmu * t.wphi);
+    return r;
+}
+
+template <typename real>
+__device__ __forceinline__ real tap_row(const real *row, const Taps4<real> &t)
+{
+    return t.w[0] * row[t.c[0]] + t.w[1] * row[t.c[1]] + t.w[2] * row[t.c[2]] + t.w[3] * row[t.c[3]];
+}
+
+// pole columns of rows 1..G: azimuthal means of the lowest and highest ring
+template <typename real>
+__device__ __forceinline__ void table_poles(real *F, int G, int K, int KS, int nmu, int nphi)
+{
+    for (int i = threadIdx.x; i < 2 * G; i += blockDim.x) {
+        const int g = i >> 1, top = i & 1;
+        const real *row = F + (g + 1) * KS + (top ? (nmu - 1) * nphi : 0);
+        real s = 0;
+        for (int b = 0; b < nphi; ++b) s += row[b];
+        F[(g + 1) * KS + K + top] = s / real(nphi);
+    }
+}
+
+// zero the ghost rows 0 and G + 1
+template <typename real>
+__device__ __forceinline__ void table_ghosts(real *F, int G, int KS)
+{
+    for (int i = threadIdx.x; i < KS; i += blockDim.x) {
+        F[i] = real(0);
+        F[(G + 1) * KS + i] = real(0);
+    }
+}
+
 // Frequency remap for groups uniform in ln(nu) (spacing delta): the target
 // frequency of group g sits at fractional group position g + y for every g, so
 // the invariant F/nu^3 is interpolated between groups g + s and g + s + 1
-// (s = floor y, weight f = y - s), groups -1 and G being the zero-valued ghost
-// centres, and nu_g^3 / nu_{g'}^3 = exp(3 delta (g - g')).  A[g'] are the
-// angular remaps of F at the taps; out[g] receives the lab (or comoving) value.
+// (s = floor y, weight f = y - s), positions beyond the groups reading the
+// zero ghost rows, and nu_g^3 / nu_{g'}^3 = exp(3 delta (g - g')).
+// out[g * ostride] receives the remapped (lab or comoving) value.  In FP32 the
+// exponent is capped at 80 so that a factor multiplying a ghost stays finite
+// (only a group set spanning more than ~12 decades reaches the cap).
 template <typename real>
-__device__ __forceinline__ void uniform_remap(const real *F, int sk, int sg, int G, int nmu, int nphi,
-                                              const TapL<real> &tp, const real *pole, double y, double delta,
-                                              real *out, long ostride = 1)
+__device__ __forceinline__ void uniform_remap(const real *F, int KS, int G, const Taps4<real> &tp, double y,
+                                              double delta, real *out, long ostride)
 {
     const double sf = floor(y);
-    const double f = y - sf;
+    if (sf <= -(double)(G + 1) || sf >= (double)G) {      // every position beyond the groups
+        for (int g = 0; g < G; ++g) out[g * ostride] = real(0);
+        return;
+    }
+    const real f = (real)(y - sf);
     const int s = (int)sf;
-    const real clo = (real)((1.0 - f) * exp(-3.0 * delta * sf));
-    const real chi = (real)(f * exp(-3.0 * delta * (sf + 1.0)));
-    auto A = [&](int gp) -> real {
-        return (gp >= 0 && gp < G) ? tap_value(F, sk, sg, G, gp, nmu, nphi, tp, pole) : real(0);
-    };
+    const real cap = sizeof(real) == 4 ? real(80) : real(700);
+    const real e3 = real(-3.0 * delta);
+    const real clo = (real(1) - f) * exp(fmin(e3 * (real)sf, cap));
+    const real chi = f * exp(fmin(e3 * (real)(sf + 1.0), cap));
+    auto A = [&](int gp) -> real { return tap_row(F + (min(max(gp, -1), G) + 1) * KS, tp); };
     real acur = A(s);
     for (int g = 0; g < G; ++g) {
         const real anext = A(g + s + 1);
@@ -626,14 +676,47 @@ __device__ __forceinline__ void uniform_remap(const real *F, int sk, int sg, int
     }
 }
 
+// remap of every group for non-uniform groups: frequency x = ln(nu_g) + lnD
+// bracketed by a monotone walk, invariants F/nu^3 linear in ln(nu)
+template <typename real>
+__device__ __forceinline__ void general_remap(const real *F, int KS, const FreqInfo &fi, const FreqL &fl,
+                                              const Taps4<real> &tp, double lnD, real *out, long ostride)
+{
+    const int G = fi.G;
+    FreqWalk fw{0};
+    if (G > 2) fw.lo = centre_bracket(fl.lnc, G, fl.lnc[0] + lnD);
+    for (int g = 0; g < G; ++g) {
+        const FreqTaps ft = freq_taps_zero_walk(fi, fl, fl.lnc[g] + lnD, fw);
+        double v = 0.0;
+        if (ft.gl >= 0) v += ft.wl * (double)tap_row(F + (ft.gl + 1) * KS, tp) * fl.inv_nu3[ft.gl];
+        if (ft.gh >= 0) v += ft.wh * (double)tap_row(F + (ft.gh + 1) * KS, tp) * fl.inv_nu3[ft.gh];
+        out[g * ostride] = (real)(fl.nu3[g] * v);
+    }
+}
+
+// S~ = (chi S + I_prev/(c dt)) / (chi + 1/(c dt)); in steady state S (or 0 where chi = 0)
+__device__ __forceinline__ float time_terms(float chi, float S, float ip, float icdt)
+{
+    if (icdt == 0.0f) return chi > 0.0f ? S : 0.0f;
+    const float xt = chi + icdt;
+    return xt > 0.0f ? (chi * S + ip * icdt) * __builtin_amdgcn_rcpf(xt) : 0.0f;
+}
+__device__ __forceinline__ double time_terms(double chi, double S, double ip, double icdt)
+{
+    if (icdt == 0.0) return chi > 0.0 ? S : 0.0;
+    const double xt = chi + icdt;
+    return xt > 0.0 ? (chi * S + ip * icdt) / xt : 0.0;
+}
+
 // ---------------------------------------------------------------------------
-// S3: comoving ordinates -> lab ordinates, one workgroup per grid point, one
-// thread per lab ordinate (all groups).  The point's comoving source S0[g][j]
-// (from the SH -> ordinate product) is staged in LDS; the lab source of
-// ordinate k is the bilinear (angle) x linear in ln(nu) remap of the invariant
-// S0/nu^3 at the comoving direction n0 (Eq. 8) and frequency nu/D (Eq. 7) of
-// that ray, times nu^3; then the implicit time terms of Eqs. 5-6 with the lab
-// extinction chi_lab precomputed per medium.  Output S~[k][p][g].
+// S3: comoving ordinates -> lab ordinates, one thread per lab ordinate (all
+// groups).  The point's comoving source S0[g][j] (from the SH -> ordinate
+// product) is staged in the table; the lab source of ordinate k is the
+// bilinear (angle) x linear in ln(nu) remap of the invariant S0/nu^3 at the
+// comoving direction n0 (Eq. 8) and frequency nu/D (Eq. 7) of that ray, times
+// nu^3; then the implicit time terms of Eqs. 5-6 with the lab extinction
+// chi_lab precomputed per medium.  Output S~[k][p][g], written through an LDS
+// tile in runs of G values.
 // ---------------------------------------------------------------------------
 template <typename real>
 __global__ void __launch_bounds__(kRemapThreads) k_boost(BoostArgs<real> a)
@@ -641,25 +724,21 @@ __global__ void __launch_bounds__(kRemapThreads) k_boost(BoostArgs<real> a)
     extern __shared__ unsigned char smem_raw[];
     const long p = xcd_item(a.P);
     if (p >= a.P) return;
-    const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x, Gp = G + 1;
+    const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x, Gp = G + 1, KS = table_stride(K);
     double *fbuf = reinterpret_cast<double *>(smem_raw);                // [4G]
-    real *sS0 = reinterpret_cast<real *>(fbuf + 4 * G);                 // [G][K]
-    real *sPole = sS0 + G * K;                                          // [2][G]
-    real *sOut = sPole + 2 * G;                                         // [T][G+1] lab values of a chunk of ordinates
+    real *F = reinterpret_cast<real *>(fbuf + 4 * G);                   // [G+2][KS]
+    real *sOut = F + (G + 2) * KS;                                      // [T][G+1] lab values of a chunk of ordinates
 
     const FreqL fl = stage_freq(a.fi, fbuf);
     double b[3];
     const bool moving = load_beta(a.beta, p, b);
     const real *__restrict__ src = a.S0 + (long)p * G * K;
-    for (int i = tid; i < G * K; i += T) sS0[i] = src[i];
+    for (int g = 0; g < G; ++g)
+        for (int j = tid; j < K; j += T) F[(g + 1) * KS + j] = src[g * K + j];
+    if (moving) table_ghosts(F, G, KS);
     __syncthreads();
     if (moving) {
-        for (int i = tid; i < 2 * G; i += T) {
-            const int g = i % G, ring = (i < G) ? 0 : a.nmu - 1;
-            real s = 0;
-            for (int bb = 0; bb < a.nphi; ++bb) s += sS0[g * K + ring * a.nphi + bb];
-            sPole[i] = s / real(a.nphi);
-        }
+        table_poles(F, G, K, KS, a.nmu, a.nphi);
         __syncthreads();
     }
     const real icdt = a.inv_cdt;
@@ -670,7 +749,7 @@ __global__ void __launch_bounds__(kRemapThreads) k_boost(BoostArgs<real> a)
         if (k < K) {
             real *outk = sOut + tid * Gp;
             if (!moving) {
-                for (int g = 0; g < G; ++g) outk[g] = sS0[g * K + k];
+                for (int g = 0; g < G; ++g) outk[g] = F[(g + 1) * KS + k];
             } else {
                 const double n[3] = {a.dir[4 * k], a.dir[4 * k + 1], a.dir[4 * k + 2]};
                 const double bn = b[0] * n[0] + b[1] * n[1] + b[2] * n[2];
@@ -678,24 +757,14 @@ __global__ void __launch_bounds__(kRemapThreads) k_boost(BoostArgs<real> a)
                 const double f = gam * (1.0 - gam / (gam + 1.0) * bn);
                 double n0[3];
                 for (int c = 0; c < 3; ++c) n0[c] = D * (n[c] - f * b[c]);
-                const AngleTaps at = angle_taps(a.mu, a.nmu, a.nphi, n0);
-                const TapL<real> tp{at.a0, at.a1, at.b0, at.b1, (real)at.wmu, (real)at.wphi};
+                const Taps4<real> tp = taps4<real>(angle_taps<real>(a.mu, a.nmu, a.nphi, n0), K, a.nmu, a.nphi);
                 if (a.fi.grey) {
                     const double D2 = D * D;
-                    outk[0] = (real)(D2 * D2) * tap_value(sS0, 1, K, G, 0, a.nmu, a.nphi, tp, sPole);
+                    outk[0] = (real)(D2 * D2) * tap_row(F + KS, tp);
                 } else if (a.fi.uniform) {
-                    uniform_remap(sS0, 1, K, G, a.nmu, a.nphi, tp, sPole, -log(D) * a.fi.inv_delta, a.fi.delta, outk);
+                    uniform_remap(F, KS, G, tp, -(double)log((real)D) * a.fi.inv_delta, a.fi.delta, outk, 1);
                 } else {
-                    const double lnD = log(D);
-                    FreqWalk fw{0};
-                    if (G > 2) fw.lo = centre_bracket(fl.lnc, G, fl.lnc[0] - lnD);
-                    for (int g = 0; g < G; ++g) {
-                        const FreqTaps ft = freq_taps_zero_walk(a.fi, fl, fl.lnc[g] - lnD, fw);
-                        double v = 0.0;
-                        if (ft.gl >= 0) v += ft.wl * (double)tap_value(sS0, 1, K, G, ft.gl, a.nmu, a.nphi, tp, sPole) * fl.inv_nu3[ft.gl];
-                        if (ft.gh >= 0) v += ft.wh * (double)tap_value(sS0, 1, K, G, ft.gh, a.nmu, a.nphi, tp, sPole) * fl.inv_nu3[ft.gh];
-                        outk[g] = (real)(fl.nu3[g] * v);
-                    }
+                    general_remap(F, KS, a.fi, fl, tp, -log(D), outk, 1);
                 }
             }
         }
@@ -706,57 +775,48 @@ __global__ void __launch_bounds__(kRemapThreads) k_boost(BoostArgs<real> a)
         for (int idx = tid; idx < nk * G; idx += T) {
             const int kk = (int)(((float)idx + 0.5f) * rG), g = idx - kk * G;
             const long o = ((long)(k0 + kk) * a.P + p) * G + g;
-            const real Sl = sOut[kk * Gp + g];
             const real chil = a.chi_grey ? a.chilab[(long)(k0 + kk) * a.P + p] : a.chilab[o];
             const real ip = a.Iprev ? a.Iprev[o] : real(0);
-            const real xt = chil + icdt;
-            a.St[o] = (xt > real(0)) ? (chil * Sl + ip * icdt) / xt : real(0);
+            a.St[o] = time_terms(chil, sOut[kk * Gp + g], ip, icdt);
         }
         __syncthreads();
     }
 }
 
 // ---------------------------------------------------------------------------
-// S5: lab ordinates -> comoving ordinates, one workgroup per grid point, one
-// thread per comoving ordinate.  The point's lab intensities I[k][g] are
-// staged in LDS; the comoving value of ordinate j is the remap of the
-// invariant I/nu^3 at the lab direction and frequency D' nu of that comoving
-// ray.  Output I0[p][g][j].
+// S5: lab ordinates -> comoving ordinates, one thread per comoving ordinate.
+// The point's lab intensities I[k][g] are staged in the table (transposed);
+// the comoving value of ordinate j is the remap of the invariant I/nu^3 at the
+// lab direction and frequency D' nu of that comoving ray.  Output I0[p][g][j].
 // ---------------------------------------------------------------------------
 template <typename real>
-__global__ void __launch_bounds__(kRemapThreads) k_unboost(UnboostArgs<real> a)
+__global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_unboost(UnboostArgs<real> a)
 {
     extern __shared__ unsigned char smem_raw[];
     const long p = xcd_item(a.P);
     if (p >= a.P) return;
-    const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x, Gp = G + 1;
+    const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x, KS = table_stride(K);
     double *fbuf = reinterpret_cast<double *>(smem_raw);                // [4G]
-    real *sI = reinterpret_cast<real *>(fbuf + 4 * G);                  // [K][G+1] lab (padded rows)
-    real *sPole = sI + K * Gp;                                          // [2][G]
+    real *F = reinterpret_cast<real *>(fbuf + 4 * G);                   // [G+2][KS]
 
     const FreqL fl = stage_freq(a.fi, fbuf);
     double b[3];
     const bool moving = load_beta(a.beta, p, b);
-    const float rG = 1.0f / (float)G, rK = 1.0f / (float)K;
+    const float rG = 1.0f / (float)G;
     for (int idx = tid; idx < K * G; idx += T) {
         const int k = (int)(((float)idx + 0.5f) * rG), g = idx - k * G;
-        sI[k * Gp + g] = a.Ilab[((long)k * a.P + p) * G + g];
+        F[(g + 1) * KS + k] = a.Ilab[((long)k * a.P + p) * G + g];
     }
-    __syncthreads();
     real *__restrict__ out = a.I0 + (long)p * G * K;
     if (!moving) {
-        for (int idx = tid; idx < K * G; idx += T) {
-            const int g = (int)(((float)idx + 0.5f) * rK), j = idx - g * K;
-            out[idx] = sI[j * Gp + g];
-        }
+        __syncthreads();
+        for (int g = 0; g < G; ++g)
+            for (int j = tid; j < K; j += T) out[g * K + j] = F[(g + 1) * KS + j];
         return;
     }
-    for (int i = tid; i < 2 * G; i += T) {
-        const int g = i % G, ring = (i < G) ? 0 : a.nmu - 1;
-        real s = 0;
-        for (int bb = 0; bb < a.nphi; ++bb) s += sI[(ring * a.nphi + bb) * Gp + g];
-        sPole[i] = s / real(a.nphi);
-    }
+    table_ghosts(F, G, KS);
+    __syncthreads();
+    table_poles(F, G, K, KS, a.nmu, a.nphi);
     __syncthreads();
     const double gam = a.gam[p];
     for (int j = tid; j < K; j += T) {
@@ -766,28 +826,14 @@ __global__ void __launch_bounds__(kRemapThreads) k_unboost(UnboostArgs<real> a)
         const double f = gam * (1.0 + gam / (gam + 1.0) * bn0);
         double n[3];
         for (int c = 0; c < 3; ++c) n[c] = (n0[c] + f * b[c]) / Dp;
-        const AngleTaps at = angle_taps(a.mu, a.nmu, a.nphi, n);
-        const TapL<real> tp{at.a0, at.a1, at.b0, at.b1, (real)at.wmu, (real)at.wphi};
-        const double lnD = log(Dp);
-        if (!a.fi.grey && a.fi.uniform) {
-            uniform_remap(sI, Gp, 1, G, a.nmu, a.nphi, tp, sPole, lnD * a.fi.inv_delta, a.fi.delta, out + j, K);
-            continue;
-        }
-        FreqWalk fw{0};
-        if (!a.fi.grey && G > 2) fw.lo = centre_bracket(fl.lnc, G, fl.lnc[0] + lnD);
-        for (int g = 0; g < G; ++g) {
-            real v;
-            if (a.fi.grey) {
-                const double D2 = Dp * Dp;
-                v = (real)((double)tap_value(sI, Gp, 1, G, g, a.nmu, a.nphi, tp, sPole) / (D2 * D2));
-            } else {
-                const FreqTaps ft = freq_taps_zero_walk(a.fi, fl, fl.lnc[g] + lnD, fw);
-                double s = 0.0;
-                if (ft.gl >= 0) s += ft.wl * (double)tap_value(sI, Gp, 1, G, ft.gl, a.nmu, a.nphi, tp, sPole) * fl.inv_nu3[ft.gl];
-                if (ft.gh >= 0) s += ft.wh * (double)tap_value(sI, Gp, 1, G, ft.gh, a.nmu, a.nphi, tp, sPole) * fl.inv_nu3[ft.gh];
-                v = (real)(fl.nu3[g] * s);
-            }
-            out[(long)g * K + j] = v;
+        const Taps4<real> tp = taps4<real>(angle_taps<real>(a.mu, a.nmu, a.nphi, n), K, a.nmu, a.nphi);
+        if (a.fi.grey) {
+            const double D2 = Dp * Dp;
+            out[j] = (real)((double)tap_row(F + KS, tp) / (D2 * D2));
+        } else if (a.fi.uniform) {
+            uniform_remap(F, KS, G, tp, (double)log((real)Dp) * a.fi.inv_delta, a.fi.delta, out + j, K);
+        } else {
+            general_remap(F, KS, a.fi, fl, tp, log(Dp), out + j, K);
         }
     }
 }
@@ -1101,7 +1147,13 @@ void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st)
 template <typename real>
 size_t boost_lds(int K, int G)
 {
-    return 4 * sizeof(double) * G + sizeof(real) * ((size_t)K * (G + 1) + 2 * G + kRemapThreads * (size_t)(G + 1));
+    const size_t ks = (size_t)((K + 2) | 1);
+    return 4 * sizeof(double) * G + sizeof(real) * ((G + 2) * ks + kRemapThreads * (size_t)(G + 1));
+}
+template <typename real>
+size_t unboost_lds(int K, int G)
+{
+    return 4 * sizeof(double) * G + sizeof(real) * (G + 2) * (size_t)((K + 2) | 1);
 }
 template <typename real>
 void launch_chilab(const ChiLabArgs<real> &a, hipStream_t st)
@@ -1120,7 +1172,7 @@ template <typename real>
 void launch_unboost(const UnboostArgs<real> &a, hipStream_t st)
 {
     const unsigned nb = (unsigned)(8 * ((a.P + 7) / 8));
-    hipLaunchKernelGGL(k_unboost<real>, dim3(nb), dim3(kRemapThreads), boost_lds<real>(a.K, a.fi.G), st, a);
+    hipLaunchKernelGGL(k_unboost<real>, dim3(nb), dim3(kRemapThreads), unboost_lds<real>(a.K, a.fi.G), st, a);
 }
 template <typename real>
 void launch_source(const SourceArgs<real> &a, hipStream_t st)
@@ -1249,6 +1301,7 @@ hipError_t set_lds_limits(size_t bytes)
     template void launch_unboost<real>(const UnboostArgs<real> &, hipStream_t);                                 \
     template size_t trace_lds<real>(int, int, int, int);                                                       \
     template size_t boost_lds<real>(int, int);                                                                 \
+    template size_t unboost_lds<real>(int, int);                                                               \
     template void launch_chilab<real>(const ChiLabArgs<real> &, hipStream_t);                                   \
     template void launch_source<real>(const SourceArgs<real> &, hipStream_t);                                   \
     template void launch_chi0<real>(long, int, const real *, const real *, const real *, real *, hipStream_t);  \

@@ -38,7 +38,7 @@ def close_by_group(got, ref, rtol, gaxis, what="", decades=None):
 
 
 def custom_spec(nx, ny, nz, G=3, lmax=3, nmu=4, nphi=8, seed=0, scatter="thomson", gamma_max=4.0,
-                edges=None, log_centres=True, grey=False, with_bc=True, mec2=None):
+                edges=None, log_centres=True, grey=False, with_bc=True, mec2=None, grey_kappa=False):
     rs = np.random.default_rng(seed)
     P = nx * ny * nz
     if grey:
@@ -56,7 +56,9 @@ def custom_spec(nx, ny, nz, G=3, lmax=3, nmu=4, nphi=8, seed=0, scatter="thomson
     return dict(nx=nx, ny=ny, nz=nz, lx=1.0, ly=0.8, lz=1.1, nmu=nmu, nphi=nphi, lmax=lmax,
                 edges=edges, log_centres=log_centres, scatter=scatter,
                 mec2=mec2 if mec2 is not None else (1.0 if scatter == "compton" else W.MEC2_KEV),
-                kappa=rs.uniform(0.1, 2.0, (P, G)), sigma=10 ** rs.uniform(-1, 1, P),
+                kappa=(np.repeat(rs.uniform(0.1, 2.0, (P, 1)), G, axis=1) if grey_kappa
+                       else rs.uniform(0.1, 2.0, (P, G))),
+                sigma=10 ** rs.uniform(-1, 1, P),
                 bnu=rs.uniform(0.2, 2.0, (P, G)), beta=beta, kte=None,
                 bc_bot=rs.uniform(0, 1, (K, ny, nx, G)) if with_bc else None,
                 bc_top=rs.uniform(0, 1, (K, ny, nx, G)) if with_bc else None)
@@ -71,6 +73,7 @@ CASES = {
     "lmax0_min_z": dict(nx=3, ny=3, nz=2, G=2, lmax=0, nmu=2, nphi=4, seed=5),
     "high_gamma_L7": dict(nx=5, ny=5, nz=4, G=4, lmax=7, nmu=8, nphi=16, gamma_max=20.0, seed=6),
     "vacuum_boundaries": dict(nx=6, ny=6, nz=6, G=2, with_bc=False, seed=7),
+    "grey_extinction_8g": dict(nx=7, ny=6, nz=7, G=8, grey_kappa=True, seed=8, gamma_max=10.0),
 }
 
 
@@ -110,6 +113,30 @@ def test_sweep_parity(case, prec):
     close_by_group(g.intensity_sh(), ref_Ilm, TOL[prec], 1, "I_lm")
     close_by_group(g.source_sh(), ref_S, TOL[prec], 1, "S_new")
     assert abs(info["residual"] - ref_r.max()) <= 10 * TOL[prec] * max(1.0, ref_r.max())
+    g.close()
+
+
+@pytest.mark.parametrize("gc", [1, 2, 4], ids=["gc1", "gc2", "gc4"])
+@pytest.mark.parametrize("grey_kappa", [True, False], ids=["grey_chi", "group_chi"])
+def test_ray_trace_variants_parity(gc, grey_kappa, monkeypatch):
+    """Every ray-trace variant (groups per workgroup; grey, per-group or given
+    extinction) on one time-dependent problem."""
+    variant = f"gc{gc}"
+    monkeypatch.setenv("RRT_TRACE_GC", str(gc))
+    spec = custom_spec(9, 5, 7, G=4, seed=21, grey_kappa=grey_kappa, gamma_max=8.0)
+    o, g = _both(spec, B.FP32)
+    rs = np.random.default_rng(22)
+    S = o.initial_source() * (1 + 0.2 * rs.uniform(size=o.sh_shape()))
+    Iprev = rs.uniform(0.0, 1.0, o.lab_shape())
+    ref_I = o.sweep(S, I_prev=Iprev, inv_cdt=3.0)[0]
+    g.set_source_sh(S)
+    g.set_intensity(Iprev)
+    g.sweep(dt_stage=1.0 / 3.0)
+    close_by_group(g.sweep_intensity(), ref_I, TOL[B.FP32], 2, f"I_lab {variant}")
+    # the stand-alone entry point: chi~ given per ordinate and group
+    St = rs.uniform(0.0, 2.0, o.lab_shape())
+    Xt = 10 ** rs.uniform(-1.5, 1.5, o.lab_shape())
+    close_by_group(g.ray_trace(St, Xt), o.trace(St, Xt), TOL[B.FP32], 2, f"ray trace {variant}")
     g.close()
 
 
