@@ -709,25 +709,54 @@ __device__ __forceinline__ double time_terms(double chi, double S, double ip, do
 }
 
 // ---------------------------------------------------------------------------
-// S3: comoving ordinates -> lab ordinates, one thread per lab ordinate (all
-// groups).  The point's comoving source S0[g][j] (from the SH -> ordinate
-// product) is staged in the table; the lab source of ordinate k is the
-// bilinear (angle) x linear in ln(nu) remap of the invariant S0/nu^3 at the
-// comoving direction n0 (Eq. 8) and frequency nu/D (Eq. 7) of that ray, times
-// nu^3; then the implicit time terms of Eqs. 5-6 with the lab extinction
-// chi_lab precomputed per medium.  Output S~[k][p][g], written through an LDS
-// tile in runs of G values.
+// S3: comoving ordinates -> lab ordinates.  The point's comoving source
+// S0[g][j] (from the SH -> ordinate product) is staged in the table; the lab
+// source of ordinate k is the bilinear (angle) x linear in ln(nu) remap of the
+// invariant S0/nu^3 at the comoving direction n0 (Eq. 8) and frequency nu/D
+// (Eq. 7) of that ray, times nu^3; then the implicit time terms of Eqs. 5-6
+// with the lab extinction chi_lab precomputed per medium.  Output S~[k][p][g].
+// Each wave takes 64 ordinates: every lane first sets up the remap of one
+// ordinate (taps, Doppler shift), then the lanes run over (ordinate, run of W
+// groups) pairs, W = 4 when G allows 16-byte runs, fetching the set-up of
+// their ordinate from the lane that made it; consecutive lanes so write
+// consecutive groups of one ordinate.
 // ---------------------------------------------------------------------------
+template <typename real> struct OrdRemap {
+    int c[4];
+    real w[4];
+    int s;              // uniform groups: position shift (kAllGhost: every position beyond the groups)
+    real clo, chi;      // uniform groups: weights with the nu^3 ratios
+    double x;           // grey: D^4; general groups: ln(nu0/nu) = -ln D
+};
+constexpr int kAllGhost = -(1 << 30);
+
 template <typename real>
-__global__ void __launch_bounds__(kRemapThreads) k_boost(BoostArgs<real> a)
+__device__ __forceinline__ OrdRemap<real> shfl_remap(const OrdRemap<real> &r, int src)
 {
+    OrdRemap<real> o;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        o.c[i] = __shfl(r.c[i], src, 64);
+        o.w[i] = __shfl(r.w[i], src, 64);
+    }
+    o.s = __shfl(r.s, src, 64);
+    o.clo = __shfl(r.clo, src, 64);
+    o.chi = __shfl(r.chi, src, 64);
+    o.x = __shfl(r.x, src, 64);
+    return o;
+}
+
+template <typename real>
+__global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_boost(BoostArgs<real> a)
+{
+    using P4 = Pack<real, 4>;
     extern __shared__ unsigned char smem_raw[];
     const long p = xcd_item(a.P);
     if (p >= a.P) return;
-    const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x, Gp = G + 1, KS = table_stride(K);
+    const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x, KS = table_stride(K);
+    const int lane = tid & 63, wave = tid >> 6;
     double *fbuf = reinterpret_cast<double *>(smem_raw);                // [4G]
     real *F = reinterpret_cast<real *>(fbuf + 4 * G);                   // [G+2][KS]
-    real *sOut = F + (G + 2) * KS;                                      // [T][G+1] lab values of a chunk of ordinates
 
     const FreqL fl = stage_freq(a.fi, fbuf);
     double b[3];
@@ -742,44 +771,108 @@ __global__ void __launch_bounds__(kRemapThreads) k_boost(BoostArgs<real> a)
         __syncthreads();
     }
     const real icdt = a.inv_cdt;
+    const int W = (G & 3) == 0 ? 4 : 1;                // groups per lane item
+    const int NC = G / W;                               // items per ordinate
+    const float rNC = 1.0f / (float)NC;
     const double gam = moving ? a.gam[p] : 1.0;
-    for (int k0 = 0; k0 < K; k0 += T) {
-        // lab source of ordinate k = k0 + tid, all groups, into the tile
-        const int k = k0 + tid;
-        if (k < K) {
-            real *outk = sOut + tid * Gp;
-            if (!moving) {
-                for (int g = 0; g < G; ++g) outk[g] = F[(g + 1) * KS + k];
-            } else {
-                const double n[3] = {a.dir[4 * k], a.dir[4 * k + 1], a.dir[4 * k + 2]};
-                const double bn = b[0] * n[0] + b[1] * n[1] + b[2] * n[2];
-                const double D = 1.0 / inv_doppler(b, gam, n);
-                const double f = gam * (1.0 - gam / (gam + 1.0) * bn);
-                double n0[3];
-                for (int c = 0; c < 3; ++c) n0[c] = D * (n[c] - f * b[c]);
-                const Taps4<real> tp = taps4<real>(angle_taps<real>(a.mu, a.nmu, a.nphi, n0), K, a.nmu, a.nphi);
-                if (a.fi.grey) {
-                    const double D2 = D * D;
-                    outk[0] = (real)(D2 * D2) * tap_row(F + KS, tp);
-                } else if (a.fi.uniform) {
-                    uniform_remap(F, KS, G, tp, -(double)log((real)D) * a.fi.inv_delta, a.fi.delta, outk, 1);
+    for (int kb = wave * 64; kb < K; kb += T) {
+        // set-up of ordinate kb + lane
+        OrdRemap<real> mine{};
+        const int km = kb + lane;
+        if (moving && km < K) {
+            const double n[3] = {a.dir[4 * km], a.dir[4 * km + 1], a.dir[4 * km + 2]};
+            const double bn = b[0] * n[0] + b[1] * n[1] + b[2] * n[2];
+            const double D = 1.0 / inv_doppler(b, gam, n);
+            const double f = gam * (1.0 - gam / (gam + 1.0) * bn);
+            double n0[3];
+            for (int c = 0; c < 3; ++c) n0[c] = D * (n[c] - f * b[c]);
+            const Taps4<real> tp = taps4<real>(angle_taps<real>(a.mu, a.nmu, a.nphi, n0), K, a.nmu, a.nphi);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { mine.c[i] = tp.c[i]; mine.w[i] = tp.w[i]; }
+            if (a.fi.grey) {
+                const double D2 = D * D;
+                mine.x = D2 * D2;
+            } else if (a.fi.uniform) {
+                const double y = -(double)log((real)D) * a.fi.inv_delta;
+                const double sf = floor(y);
+                if (sf <= -(double)(G + 1) || sf >= (double)G) {
+                    mine.s = kAllGhost;
                 } else {
-                    general_remap(F, KS, a.fi, fl, tp, -log(D), outk, 1);
+                    const real fr = (real)(y - sf);
+                    const real cap = sizeof(real) == 4 ? real(80) : real(700);
+                    const real e3 = real(-3.0 * a.fi.delta);
+                    mine.s = (int)sf;
+                    mine.clo = (real(1) - fr) * exp(fmin(e3 * (real)sf, cap));
+                    mine.chi = fr * exp(fmin(e3 * (real)(sf + 1.0), cap));
                 }
+            } else {
+                mine.x = -log(D);
             }
         }
-        __syncthreads();
-        // implicit time terms and a coalesced write of the chunk: runs of G values per ordinate
-        const int nk = min(T, K - k0);
-        const float rG = 1.0f / (float)G;
-        for (int idx = tid; idx < nk * G; idx += T) {
-            const int kk = (int)(((float)idx + 0.5f) * rG), g = idx - kk * G;
-            const long o = ((long)(k0 + kk) * a.P + p) * G + g;
-            const real chil = a.chi_grey ? a.chilab[(long)(k0 + kk) * a.P + p] : a.chilab[o];
-            const real ip = a.Iprev ? a.Iprev[o] : real(0);
-            a.St[o] = time_terms(chil, sOut[kk * Gp + g], ip, icdt);
+        const int nk = min(64, K - kb);
+        for (int item = lane; item < nk * NC; item += 64) {
+            const int kk = (int)(((float)item + 0.5f) * rNC), g0 = (item - kk * NC) * W;
+            const int k = kb + kk;
+            const OrdRemap<real> r = shfl_remap(mine, kk);
+            const long o = ((long)k * a.P + p) * G + g0;
+            // time-term inputs first: their loads overlap the remap below
+            real ip[4] = {0, 0, 0, 0}, out[4] = {0, 0, 0, 0};
+            if (a.Iprev) {
+                if (W == 4) {
+                    const P4 v = *reinterpret_cast<const P4 *>(a.Iprev + o);
+                    ip[0] = v.v[0]; ip[1] = v.v[1]; ip[2] = v.v[2]; ip[3] = v.v[3];
+                } else {
+                    ip[0] = a.Iprev[o];
+                }
+            }
+            const real chig = a.chi_grey ? a.chilab[(long)k * a.P + p] : real(0);
+            const Taps4<real> tp{{r.c[0], r.c[1], r.c[2], r.c[3]}, {r.w[0], r.w[1], r.w[2], r.w[3]}};
+            if (!moving) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i)
+                    if (i < W) out[i] = F[(g0 + i + 1) * KS + k];
+            } else if (a.fi.grey) {
+                out[0] = (real)r.x * tap_row(F + KS, tp);
+            } else if (a.fi.uniform) {
+                if (r.s != kAllGhost) {
+                    auto A = [&](int gp) -> real { return tap_row(F + (min(max(gp, -1), G) + 1) * KS, tp); };
+                    real acur = A(g0 + r.s);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        if (i < W) {
+                            const real anext = A(g0 + i + r.s + 1);
+                            out[i] = r.clo * acur + r.chi * anext;
+                            acur = anext;
+                        }
+                    }
+                }
+            } else {
+                FreqWalk fw{0};
+                if (G > 2) fw.lo = centre_bracket(fl.lnc, G, fl.lnc[g0] + r.x);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    if (i < W) {
+                        const int g = g0 + i;
+                        const FreqTaps ft = freq_taps_zero_walk(a.fi, fl, fl.lnc[g] + r.x, fw);
+                        double v = 0.0;
+                        if (ft.gl >= 0) v += ft.wl * (double)tap_row(F + (ft.gl + 1) * KS, tp) * fl.inv_nu3[ft.gl];
+                        if (ft.gh >= 0) v += ft.wh * (double)tap_row(F + (ft.gh + 1) * KS, tp) * fl.inv_nu3[ft.gh];
+                        out[i] = (real)(fl.nu3[g] * v);
+                    }
+                }
+            }
+            // implicit time terms and the store
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                if (i < W) out[i] = time_terms(a.chi_grey ? chig : a.chilab[o + i], out[i], ip[i], icdt);
+            if (W == 4) {
+                P4 v;
+                v.v[0] = out[0]; v.v[1] = out[1]; v.v[2] = out[2]; v.v[3] = out[3];
+                *reinterpret_cast<P4 *>(a.St + o) = v;
+            } else {
+                a.St[o] = out[0];
+            }
         }
-        __syncthreads();
     }
 }
 
@@ -1147,8 +1240,7 @@ void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st)
 template <typename real>
 size_t boost_lds(int K, int G)
 {
-    const size_t ks = (size_t)((K + 2) | 1);
-    return 4 * sizeof(double) * G + sizeof(real) * ((G + 2) * ks + kRemapThreads * (size_t)(G + 1));
+    return 4 * sizeof(double) * G + sizeof(real) * (G + 2) * (size_t)((K + 2) | 1);
 }
 template <typename real>
 size_t unboost_lds(int K, int G)
