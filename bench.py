@@ -27,21 +27,22 @@ FP32_PEAK_TFLOPS = 157.3
 KERNELS = ["trace", "sh2do", "boost", "unboost", "do2sh", "source", "reduce"]
 
 
-def algorithmic(kernel, spec, esz):
-    """Algorithmic HBM bytes (or flops) of one launch of each kernel of the sweep:
-    the unavoidable reads and writes of its inputs and outputs, once each."""
+def algorithmic(kernel, spec, esz, time_dependent):
+    """Algorithmic HBM bytes of one launch of each kernel of the sweep: the
+    unavoidable reads and writes of its inputs and outputs, once each (the lab
+    extinction, recomputable from the per-point medium, is not counted)."""
     n = spec["nx"] * spec["ny"] * spec["nz"]
     G = len(spec["edges"]) - 1 if spec.get("edges") is not None else 1
     K = spec["nmu"] * spec["nphi"]
     NL = (spec["lmax"] + 1) ** 2
     do, sh = n * G * K, n * G * NL
     table = {
-        # S~ read, I written (chi~ is rebuilt from the per-point medium)
+        # S~ read, I written
         "trace": ("hbm", 2 * esz * do),
         # SH source read, comoving ordinate values written
         "sh2do": ("hbm", esz * (sh + do)),
-        # comoving ordinate values read, S~ written
-        "boost": ("hbm", 2 * esz * do),
+        # comoving ordinate values read (and the stage's starting intensity), S~ written
+        "boost": ("hbm", (3 if time_dependent else 2) * esz * do),
         # lab intensity read, comoving ordinate values written
         "unboost": ("hbm", 2 * esz * do),
         # comoving ordinate values read, SH intensity written
@@ -53,13 +54,16 @@ def algorithmic(kernel, spec, esz):
     return table[kernel]
 
 
-def traffic_from_profiles(kernel, workload):
+def traffic_from_profiles(kernel, workload, time_dependent, precision):
     """Measured HBM bytes per launch from the committed rocprofv3 counter
-    summary, or None when absent or taken on a different kernel source."""
+    summary, or None when absent or taken on a different kernel source, stage
+    kind or precision."""
     path = os.path.join(ROOT, "profiles", f"{kernel}_{workload}_traffic.json")
     if not os.path.exists(path):
         return None
     rec = json.load(open(path))
+    if rec.get("time_dependent") != time_dependent or rec.get("precision") != precision:
+        return None
     src = os.path.join(ROOT, "paper_1507_05141_amd", "csrc", "rrt_kernels.hip")
     h = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if rec.get("kernel_source_sha256") != h:
@@ -166,9 +170,9 @@ def main():
     updates = pr.P * pr.G * pr.K
     value = updates * args.steps / elapsed
     dom = max(kern, key=lambda k: kern[k]["avg_ms"] * kern[k]["launches"])
-    bound, alg = algorithmic(dom, spec, esz)
+    bound, alg = algorithmic(dom, spec, esz, bool(dt_stage))
     achieved = alg / (kern[dom]["avg_ms"] * 1e-3) / 1e9
-    traffic = traffic_from_profiles(dom, workload)
+    traffic = traffic_from_profiles(dom, workload, bool(dt_stage), args.precision)
     roof = {"kernel": dom, "bound": bound, "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
             "algorithmic_bytes_per_launch": alg, "avg_launch_ms": kern[dom]["avg_ms"]}
