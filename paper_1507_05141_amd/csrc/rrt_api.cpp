@@ -279,7 +279,11 @@ struct Engine {
         rrt_status s = check_launch();
         if (s) return s;
         prof_begin(pr, KI_DO2SH);
-        s = gemm(pr->P * pr->G, pr->NL, pr->K, R(pr->d_co), R(pr->d_WY), R(pr->d_Ilm));
+        if (sizeof(real) == 4 && rrt::launch_do2sh_f32(pr->P * pr->G, pr->K, pr->NL, (const float *)pr->d_co,
+                                                       (const float *)pr->d_WY, (float *)pr->d_Ilm, pr->stream))
+            s = check_launch();
+        else
+            s = gemm(pr->P * pr->G, pr->NL, pr->K, R(pr->d_co), R(pr->d_WY), R(pr->d_Ilm));
         prof_end(pr, KI_DO2SH);
         return s;
     }

@@ -99,6 +99,9 @@ template <typename real> size_t trace_lds(int nx, int ny, int Gc, int chi_per_po
 template <typename real> size_t boost_lds(int K, int G);
 template <typename real> size_t unboost_lds(int K, int G);
 template <typename real> void launch_chilab(const ChiLabArgs<real> &a, hipStream_t st);
+// S6 on the matrix cores (FP32) for NL <= 64; false when the shape is not covered (then use a library product)
+bool launch_do2sh_f32(long R, int K, int NL, const float *A, const float *B, float *C, hipStream_t st);
+size_t do2sh_lds(int NL);
 template <typename real> void launch_source(const SourceArgs<real> &a, hipStream_t st);
 template <typename real> void launch_chi0(long P, int G, const real *kappa, const real *sigma, const real *sg, real *chi0, hipStream_t st);
 template <typename real> void launch_moments_lab(long P, int G, int K, const double *dir, const real *I, double *J, double *H, double *Kt, hipStream_t st);

@@ -955,6 +955,75 @@ __global__ void __launch_bounds__(256) k_chilab(ChiLabArgs<real> a)
 }
 
 // ---------------------------------------------------------------------------
+// S6: comoving ordinates -> SH, Ilm[r][q] = sum_j I0[r][j] (w_j Y_q(n_j)) for
+// the R = P G rows (point, group), FP32 on the matrix cores
+// (v_mfma_f32_16x16x4f32, FP32 accumulation).  A wave owns 16 rows and all NL
+// columns (NT tiles of 16); the weight table is staged in LDS per chunk of 64
+// ordinates (rows padded by 4 so the B operand reads are conflict-free); the
+// rows stream from HBM as 16-byte vectors.  Within a 16-ordinate block lane
+// group lg = lane/16 holds ordinates 4 lg .. 4 lg + 3 of its row, and the four
+// matrix-core steps take them in that order (the reduction order over j is
+// free); the B operand follows the same order.
+// ---------------------------------------------------------------------------
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+template <int NT>
+__global__ void __launch_bounds__(256) k_do2sh_f32(long R, int K, int NL, const float *__restrict__ A,
+                                                   const float *__restrict__ B, float *__restrict__ C)
+{
+    constexpr int KC = 64, NC = NT * 16, NLP = NC + 4;
+    extern __shared__ unsigned char smem_raw[];
+    float *Bs = reinterpret_cast<float *>(smem_raw);                   // [KC][NLP]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
+    const long r0 = (long)xcd_item(gridDim.x) * 64 + wave * 16;
+    const float *__restrict__ Arow = A + min(r0 + lr, R - 1) * (long)K;
+    const bool vec = (K & 3) == 0;
+    f32x4 acc[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < K; kc += KC) {
+        float a[4][4];
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = kc + 16 * t + 4 * lg;
+            if (vec && k + 3 < K) {
+                const f32x4 v = *reinterpret_cast<const f32x4 *>(Arow + k);
+                a[t][0] = v.x; a[t][1] = v.y; a[t][2] = v.z; a[t][3] = v.w;
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[t][i] = (k + i < K) ? Arow[k + i] : 0.f;
+            }
+        }
+        __syncthreads();                                                // the previous chunk's B reads are done
+        for (int i = threadIdx.x; i < KC * NC; i += blockDim.x) {
+            const int kk = i / NC, c = i - kk * NC;
+            Bs[kk * NLP + c] = (kc + kk < K && c < NL) ? B[(long)(kc + kk) * NL + c] : 0.f;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const float *brow = Bs + (16 * t + 4 * lg + s) * NLP + lr;
+#pragma unroll
+                for (int c = 0; c < NT; ++c)
+                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][s], brow[16 * c], acc[c], 0, 0, 0);
+            }
+        }
+    }
+    // lane holds rows 4 lg + i, column 16 c + lr of each tile
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+        const int col = 16 * c + lr;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const long r = r0 + 4 * lg + i;
+            if (r < R && col < NL) C[r * NL + col] = acc[c][i];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // S1: source function in SH space
 // ---------------------------------------------------------------------------
 template <typename real>
@@ -1266,6 +1335,21 @@ void launch_unboost(const UnboostArgs<real> &a, hipStream_t st)
     const unsigned nb = (unsigned)(8 * ((a.P + 7) / 8));
     hipLaunchKernelGGL(k_unboost<real>, dim3(nb), dim3(kRemapThreads), unboost_lds<real>(a.K, a.fi.G), st, a);
 }
+size_t do2sh_lds(int NL) { return sizeof(float) * 64 * (size_t)(((NL + 15) / 16) * 16 + 4); }
+
+bool launch_do2sh_f32(long R, int K, int NL, const float *A, const float *B, float *C, hipStream_t st)
+{
+    const long nb = (R + 63) / 64;
+    if (nb > 0x7fffffffL) return false;
+    const dim3 grid((unsigned)(8 * ((nb + 7) / 8))), block(256);
+    const size_t sm = do2sh_lds(NL);
+    // NL up to 64 (L <= 7); at L = 15 the library product is faster (measured on MI355X)
+    if (NL <= 16) hipLaunchKernelGGL(k_do2sh_f32<1>, grid, block, sm, st, R, K, NL, A, B, C);
+    else if (NL <= 64) hipLaunchKernelGGL(k_do2sh_f32<4>, grid, block, sm, st, R, K, NL, A, B, C);
+    else return false;
+    return true;
+}
+
 template <typename real>
 void launch_source(const SourceArgs<real> &a, hipStream_t st)
 {
@@ -1379,6 +1463,8 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_unboost<float>),
                          reinterpret_cast<const void *>(&k_unboost<double>),
                          reinterpret_cast<const void *>(&k_source_compton<float>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32<1>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32<4>),
                          reinterpret_cast<const void *>(&k_source_compton<double>)};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
