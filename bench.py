@@ -99,7 +99,8 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp32", "fp64"], default="fp32")
+    ap.add_argument("--precision", choices=["fp32", "fp64", "mixed"], default="fp32",
+                    help="mixed: FP32 with the SH <-> ordinate products on FP16 matrix cores")
     ap.add_argument("--workload", choices=["thomson_jet", "compton_jet"], default="thomson_jet",
                     help="thomson_jet: 32^3, 16 groups, L=7 (default); compton_jet: 64^3, 32 groups, L=15, "
                          "electrons at rest")
@@ -135,8 +136,8 @@ def main():
         spec = W.compton_jet()
         spec["kte"] = None
         workload = "compton_jet_64c_g32_l15_16x32"
-    prec = B.FP32 if args.precision == "fp32" else B.FP64
-    esz = 4 if prec == B.FP32 else 8
+    prec = {"fp32": B.FP32, "fp64": B.FP64, "mixed": B.MIXED}[args.precision]
+    esz = 8 if prec == B.FP64 else 4
     stream = torch.cuda.current_stream().cuda_stream
     pr = B.Problem.from_spec(spec, precision=prec, stream=stream)
     # time step of half a cell light-crossing time, first stage (dt/6) of the
@@ -179,7 +180,7 @@ def main():
     out = {
         "metric": METRIC, "value": value, "unit": "updates/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "f32" if prec == B.FP32 else "f64",
+        "scaling": "weak", "vs_baseline": None, "dtype": {"fp32": "f32", "fp64": "f64", "mixed": "f32+f16mfma"}[args.precision],
         "data": "synthetic",
         "config": {"workload": workload, "grid": [spec["nx"], spec["ny"], spec["nz"]], "groups": pr.G,
                    "lmax": spec["lmax"], "ordinates": [spec["nmu"], spec["nphi"]], "scatter": spec["scatter"],

@@ -60,7 +60,13 @@ typedef enum {
     RRT_E_STATE = -6           /* call out of order (e.g. solve before set_medium)   */
 } rrt_status;
 
-typedef enum { RRT_FP64 = 0, RRT_FP32 = 1 } rrt_precision;
+/* Working precision.  RRT_MIXED computes in FP32 like RRT_FP32 except the two
+   SH <-> ordinate products of every sweep (Eq. 9, forward and backward), which
+   run on FP16 matrix cores with FP32 accumulation: the data operand is scaled
+   by powers of two per (point, group) row (per row and block of 32 ordinates
+   in the backward product) and the SH tables are rounded to FP16.  Needs
+   (lmax + 1)^2 <= 256.  Reductions stay FP64 in every mode. */
+typedef enum { RRT_FP64 = 0, RRT_FP32 = 1, RRT_MIXED = 2 } rrt_precision;
 typedef enum { RRT_THOMSON = 0, RRT_COMPTON = 1 } rrt_scatter;
 typedef enum { RRT_FRAME_LAB = 0, RRT_FRAME_COMOVING = 1 } rrt_frame;
 typedef enum { RRT_SCHEME_RK4 = 0, RRT_SCHEME_EULER = 1 } rrt_scheme;

@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "librrt.so")
 
 RRT_OK, RRT_E_INVALID, RRT_E_HOST_OOM, RRT_E_HBM, RRT_E_NOT_CONVERGED, RRT_E_DEVICE, RRT_E_STATE = 0, -1, -2, -3, -4, -5, -6
-FP64, FP32 = 0, 1
+FP64, FP32, MIXED = 0, 1, 2
 THOMSON, COMPTON = 0, 1
 FRAME_LAB, FRAME_COMOVING = 0, 1
 SCHEME_RK4, SCHEME_EULER = 0, 1

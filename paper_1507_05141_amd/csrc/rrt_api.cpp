@@ -67,6 +67,8 @@ struct rrt_problem {
     int Gc = 1;
     rrt::OrdGeom *d_geo = nullptr;
     void *d_Yt = nullptr, *d_WY = nullptr, *d_A = nullptr, *d_sg = nullptr;
+    void *d_Y16 = nullptr, *d_WYt16 = nullptr;     // RRT_MIXED: FP16 SH tables, hi then lo part (zero padded)
+    size_t y16_n = 0, wyt16_n = 0;                  // elements per part
     rrt::FreqInfo fi{};
     // fields
     void *d_kappa = nullptr, *d_sigma = nullptr, *d_bnu = nullptr, *d_chi0 = nullptr;
@@ -239,7 +241,13 @@ struct Engine {
     rrt_status to_lab(const void *S, const void *Iprev, double inv_cdt)
     {
         prof_begin(pr, KI_SH2DO);
-        rrt_status s = gemm(pr->P * pr->G, pr->K, pr->NL, static_cast<const real *>(S), R(pr->d_Yt), R(pr->d_co));
+        rrt_status s;
+        const _Float16 *y16 = (const _Float16 *)pr->d_Y16;
+        if (pr->prec == RRT_MIXED && rrt::launch_sh2do_f16(pr->P * pr->G, pr->K, pr->NL, (const float *)S, y16,
+                                                           y16 + pr->y16_n, (float *)pr->d_co, pr->stream))
+            s = check_launch();
+        else
+            s = gemm(pr->P * pr->G, pr->K, pr->NL, static_cast<const real *>(S), R(pr->d_Yt), R(pr->d_co));
         prof_end(pr, KI_SH2DO);
         if (s) return s;
         rrt::BoostArgs<real> b;
@@ -279,8 +287,12 @@ struct Engine {
         rrt_status s = check_launch();
         if (s) return s;
         prof_begin(pr, KI_DO2SH);
-        if (sizeof(real) == 4 && rrt::launch_do2sh_f32(pr->P * pr->G, pr->K, pr->NL, (const float *)pr->d_co,
-                                                       (const float *)pr->d_WY, (float *)pr->d_Ilm, pr->stream))
+        const _Float16 *wy16 = (const _Float16 *)pr->d_WYt16;
+        if (pr->prec == RRT_MIXED && rrt::launch_do2sh_f16(pr->P * pr->G, pr->K, pr->NL, (const float *)pr->d_co, wy16,
+                                                           wy16 + pr->wyt16_n, (float *)pr->d_Ilm, pr->stream))
+            s = check_launch();
+        else if (sizeof(real) == 4 && rrt::launch_do2sh_f32(pr->P * pr->G, pr->K, pr->NL, (const float *)pr->d_co,
+                                                            (const float *)pr->d_WY, (float *)pr->d_Ilm, pr->stream))
             s = check_launch();
         else
             s = gemm(pr->P * pr->G, pr->NL, pr->K, R(pr->d_co), R(pr->d_WY), R(pr->d_Ilm));
@@ -508,7 +520,9 @@ rrt_status check_sizes(const rrt_grid *g, const rrt_groups *gr, const rrt_angles
     if ((long)a->n_mu * a->n_phi > 65535) return fail(RRT_E_INVALID, "at most 65535 ordinates");
     if (a->n_mu < a->lmax + 1 || a->n_phi < 2 * a->lmax + 1)
         return fail(RRT_E_INVALID, "ordinate mesh too coarse for lmax (need n_mu >= lmax+1, n_phi >= 2 lmax+1)");
-    if (prec != RRT_FP64 && prec != RRT_FP32) return fail(RRT_E_INVALID, "unknown precision");
+    if (prec != RRT_FP64 && prec != RRT_FP32 && prec != RRT_MIXED) return fail(RRT_E_INVALID, "unknown precision");
+    if (prec == RRT_MIXED && (a->lmax + 1) * (a->lmax + 1) > 256)
+        return fail(RRT_E_INVALID, "mixed precision supports (lmax + 1)^2 <= 256");
     if (sc != RRT_THOMSON && sc != RRT_COMPTON) return fail(RRT_E_INVALID, "unknown scattering kernel");
     if (!gr->edges) {
         if (gr->ngroups != 1) return fail(RRT_E_INVALID, "a grey problem has exactly one group");
@@ -564,6 +578,7 @@ void rrt_destroy(rrt_problem *pr)
     if (pr->stream) (void)hipStreamSynchronize(pr->stream);
     if (pr->blas) (void)rocblas_destroy_handle(pr->blas);
     void *bufs[] = {pr->d_dir, pr->d_mu, pr->d_lnc, pr->d_nu3, pr->d_inv_nu3, pr->d_inv_dc, pr->d_geo, pr->d_Yt, pr->d_WY,
+                    pr->d_Y16, pr->d_WYt16,
                     pr->d_A, pr->d_sg, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_gam, pr->d_chi0, pr->d_chilab, pr->d_bc[0], pr->d_bc[1],
                     pr->d_S, pr->d_Snew, pr->d_Ilm, pr->d_co, pr->d_St, pr->d_Xt, pr->d_Ilab, pr->d_I, pr->d_Iin,
                     pr->d_acc, pr->d_chain[0], pr->d_chain[1], pr->d_chain[2], pr->d_chain[3], pr->d_partial, pr->d_red};
@@ -669,6 +684,29 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
     if ((s = upload_double(pr, (void **)&pr->d_dir, pr->dir)) || (s = upload_double(pr, (void **)&pr->d_mu, pr->mu)) ||
         (s = alloc_upload_real(pr, &pr->d_Yt, Yt)) || (s = alloc_upload_real(pr, &pr->d_WY, WY)))
         return bail(s);
+    if (pr->prec == RRT_MIXED) {
+        // FP16 hi + lo tables in the layouts of the matrix-core operands: Y16[K up to 16][NL up
+        // to 32] (forward product) and WYt16[NL up to 16][K up to 32] (backward), zero padded
+        const int Kt = (K + 15) / 16 * 16, NLp = (NL + 31) / 32 * 32, NLr = (NL + 15) / 16 * 16, Kp = (K + 31) / 32 * 32;
+        pr->y16_n = (size_t)Kt * NLp;
+        pr->wyt16_n = (size_t)NLr * Kp;
+        std::vector<_Float16> y16(2 * pr->y16_n, (_Float16)0.0f), wyt16(2 * pr->wyt16_n, (_Float16)0.0f);
+        auto put = [](std::vector<_Float16> &t, size_t n, size_t i, double v) {
+            const _Float16 h = (_Float16)v;
+            t[i] = h;
+            t[n + i] = (_Float16)(v - (double)h);
+        };
+        for (int k = 0; k < K; ++k)
+            for (int q = 0; q < NL; ++q) {
+                put(y16, pr->y16_n, (size_t)k * NLp + q, pr->Y[(size_t)k * NL + q]);
+                put(wyt16, pr->wyt16_n, (size_t)q * Kp + k, WY[(size_t)k * NL + q]);
+            }
+        hipError_t e = hipMalloc(&pr->d_Y16, y16.size() * sizeof(_Float16));
+        if (e == hipSuccess) e = hipMalloc(&pr->d_WYt16, wyt16.size() * sizeof(_Float16));
+        if (e == hipSuccess) e = hipMemcpy(pr->d_Y16, y16.data(), y16.size() * sizeof(_Float16), hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(pr->d_WYt16, wyt16.data(), wyt16.size() * sizeof(_Float16), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return bail(fail(RRT_E_HBM, std::string("mixed-precision tables: ") + hipGetErrorString(e)));
+    }
     // ray-trace geometry per ordinate
     {
         const double dx = pr->lx / pr->nx, dy = pr->ly / pr->ny, dz = pr->lz / (pr->nz - 1);

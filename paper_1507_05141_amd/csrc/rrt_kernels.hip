@@ -1024,6 +1024,211 @@ __global__ void __launch_bounds__(256) k_do2sh_f32(long R, int K, int NL, const 
 }
 
 // ---------------------------------------------------------------------------
+// Mixed precision: the two SH <-> ordinate products on FP16 matrix cores
+// (v_mfma_f32_16x16x32_f16) with FP32 accumulation.  Both operands are split
+// into FP16 pairs x = hi + lo (lo the FP16 rounding of the remainder) and a
+// block product is hi.hi + lo.hi + hi.lo, about 22 significant bits.  The data
+// operand is first brought into FP16 range by a power of two (exact): per row
+// (point, group) for the short SH rows of S2, per row and block of 32
+// ordinates for S6, whose row maximum is not known before the row has
+// streamed by; each block's product is rescaled into the accumulator.  The
+// tables (w_j) Y_q(n_j) are stored as FP16 pairs, rows padded by zeros to
+// whole 32-element blocks, and staged in LDS per chunk.  Operand layout of the
+// 16 x 16 x 32 product: lane group lg = lane/16 holds elements 8 lg .. 8 lg + 7
+// of the reduction block for row / column lane % 16 (A and B in the same
+// order).
+// ---------------------------------------------------------------------------
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+
+// power of two s taking m > 0 into [2^14, 2^15) (FP16 keeps full precision
+// down to 2^-28 m); m = 0 or tiny gives a bounded scale
+__device__ __forceinline__ void fp16_scale(float m, float &s, float &inv)
+{
+    const int e = max(((__float_as_int(m) >> 23) & 0xff) - 127, -100);
+    s = ldexpf(1.0f, 14 - e);
+    inv = ldexpf(1.0f, e - 14);
+}
+
+// hi + lo FP16 pair of v * s
+__device__ __forceinline__ void split_f16x8(const float v[8], float s, f16x8 &hi, f16x8 &lo)
+{
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+        const float x = v[i] * s;
+        const _Float16 h = (_Float16)x;
+        hi[i] = h;
+        lo[i] = (_Float16)(x - (float)h);
+    }
+}
+
+__device__ __forceinline__ f32x4 mfma3(const f16x8 &ah, const f16x8 &al, const f16x8 &bh, const f16x8 &bl, f32x4 c)
+{
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x32_f16(al, bh, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x32_f16(ah, bl, c, 0, 0, 0);
+}
+
+__device__ __forceinline__ float quad_max(float m)
+{
+    m = fmaxf(m, __shfl_xor(m, 16, 64));
+    return fmaxf(m, __shfl_xor(m, 32, 64));
+}
+
+// S6 mixed: Ilm[r][q] = sum_j I0[r][j] WYt[q][j]; WYt = hi, lo FP16 tables [NT*16][Kp], Kp = K up to 32.
+// A workgroup of 4 waves takes 64 RT rows (a wave RT tiles of 16 rows); the table is
+// staged in LDS per chunk of 64 ordinates ([NT*16][64 + 8] per part).
+template <int NT, int RT>
+__global__ void __launch_bounds__(256) k_do2sh_f16(long R, int K, int Kp, int NL, const float *__restrict__ A,
+                                                   const _Float16 *__restrict__ WYh, const _Float16 *__restrict__ WYl,
+                                                   float *__restrict__ C)
+{
+    constexpr int KC = 64, LS = KC + 8, NC = NT * 16;
+    extern __shared__ unsigned char smem_raw[];
+    _Float16 *Th = reinterpret_cast<_Float16 *>(smem_raw), *Tl = Th + NC * LS;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
+    const long r0 = (long)xcd_item(gridDim.x) * (64 * RT) + wave * (16 * RT);
+    const bool vec = (K & 3) == 0;
+    const float *Arow[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) Arow[t] = A + min(r0 + 16 * t + lr, R - 1) * (long)K;
+    f32x4 acc[RT][NT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int kc = 0; kc < Kp; kc += KC) {
+        __syncthreads();
+        // table chunk: columns kc .. kc + 63 of both parts (zero past Kp)
+        for (int i = threadIdx.x; i < NC * (KC / 8); i += blockDim.x) {
+            const int row = i / (KC / 8), k8 = (i - row * (KC / 8)) * 8;
+            f16x8 h = {}, l = {};
+            if (kc + k8 < Kp) {
+                h = *reinterpret_cast<const f16x8 *>(WYh + (long)row * Kp + kc + k8);
+                l = *reinterpret_cast<const f16x8 *>(WYl + (long)row * Kp + kc + k8);
+            }
+            *reinterpret_cast<f16x8 *>(Th + row * LS + k8) = h;
+            *reinterpret_cast<f16x8 *>(Tl + row * LS + k8) = l;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int kb = 0; kb < KC; kb += 32) {
+            if (kc + kb >= Kp) break;
+            const int k = kc + kb + 8 * lg;
+#pragma unroll
+            for (int t = 0; t < RT; ++t) {
+                float v[8];
+                if (vec && k + 7 < K) {
+                    const f32x4 x = *reinterpret_cast<const f32x4 *>(Arow[t] + k);
+                    const f32x4 y = *reinterpret_cast<const f32x4 *>(Arow[t] + k + 4);
+                    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w; v[4] = y.x; v[5] = y.y; v[6] = y.z; v[7] = y.w;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 8; ++i) v[i] = (k + i < K) ? Arow[t][k + i] : 0.f;
+                }
+                float m = 0.f;
+#pragma unroll
+                for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(v[i]));
+                float sc, inv;
+                fp16_scale(quad_max(m), sc, inv);
+                f16x8 ah, al;
+                split_f16x8(v, sc, ah, al);
+                // inverse scales of the output rows 4 lg + i of this tile
+                float ri[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) ri[i] = __shfl(inv, 4 * lg + i, 64);
+#pragma unroll
+                for (int c = 0; c < NT; ++c) {
+                    const int o = (16 * c + lr) * LS + kb + 8 * lg;
+                    const f32x4 p = mfma3(ah, al, *reinterpret_cast<const f16x8 *>(Th + o),
+                                          *reinterpret_cast<const f16x8 *>(Tl + o), f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) acc[t][c][i] += p[i] * ri[i];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            const int col = 16 * c + lr;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long r = r0 + 16 * t + 4 * lg + i;
+                if (r < R && col < NL) C[r * NL + col] = acc[t][c][i];
+            }
+        }
+}
+
+// S2 mixed: S0[r][j] = sum_q S[r][q] Y[j][q]; Y = hi, lo FP16 tables [Kt][NLp] (Kt = K up to 16,
+// NLp = NL up to 32, NB = NLp / 32 blocks); one scale per row.  A workgroup of 4 waves takes 64
+// rows; the table is staged in LDS per chunk of 64 ordinates ([64][NLp + 8] per part).
+template <int NB>
+__global__ void __launch_bounds__(256) k_sh2do_f16(long R, int K, int NL, const float *__restrict__ S,
+                                                   const _Float16 *__restrict__ Yh, const _Float16 *__restrict__ Yl,
+                                                   float *__restrict__ C)
+{
+    constexpr int NLp = NB * 32, LS = NLp + 8, JC = 64;
+    extern __shared__ unsigned char smem_raw[];
+    _Float16 *Th = reinterpret_cast<_Float16 *>(smem_raw), *Tl = Th + JC * LS;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
+    const long r0 = (long)xcd_item(gridDim.x) * 64 + wave * 16;
+    const int Kt = (K + 15) / 16 * 16;
+    const float *__restrict__ Srow = S + min(r0 + lr, R - 1) * (long)NL;
+    float v[NB][8];
+    float m = 0.f;
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) {
+            const int q = 32 * b + 8 * lg + i;
+            v[b][i] = q < NL ? Srow[q] : 0.f;
+            m = fmaxf(m, fabsf(v[b][i]));
+        }
+    }
+    float sc, inv;
+    fp16_scale(quad_max(m), sc, inv);
+    f16x8 ah[NB], al[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) split_f16x8(v[b], sc, ah[b], al[b]);
+    float ri[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ri[i] = __shfl(inv, 4 * lg + i, 64);
+    for (int jc = 0; jc < Kt; jc += JC) {
+        __syncthreads();
+        for (int i = threadIdx.x; i < JC * (NLp / 8); i += blockDim.x) {
+            const int row = i / (NLp / 8), q8 = (i - row * (NLp / 8)) * 8;
+            f16x8 h = {}, l = {};
+            if (jc + row < Kt) {
+                h = *reinterpret_cast<const f16x8 *>(Yh + (long)(jc + row) * NLp + q8);
+                l = *reinterpret_cast<const f16x8 *>(Yl + (long)(jc + row) * NLp + q8);
+            }
+            *reinterpret_cast<f16x8 *>(Th + row * LS + q8) = h;
+            *reinterpret_cast<f16x8 *>(Tl + row * LS + q8) = l;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int c = 0; c < JC / 16; ++c) {
+            const int j0 = jc + 16 * c;
+            if (j0 >= Kt) break;
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int o = (16 * c + lr) * LS + 32 * b + 8 * lg;
+                acc = mfma3(ah[b], al[b], *reinterpret_cast<const f16x8 *>(Th + o), *reinterpret_cast<const f16x8 *>(Tl + o),
+                            acc);
+            }
+            const int col = j0 + lr;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long r = r0 + 4 * lg + i;
+                if (r < R && col < K) C[r * K + col] = acc[i] * ri[i];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // S1: source function in SH space
 // ---------------------------------------------------------------------------
 template <typename real>
@@ -1350,6 +1555,42 @@ bool launch_do2sh_f32(long R, int K, int NL, const float *A, const float *B, flo
     return true;
 }
 
+bool launch_do2sh_f16(long R, int K, int NL, const float *A, const _Float16 *WYh, const _Float16 *WYl, float *C,
+                      hipStream_t st)
+{
+    const int Kp = (K + 31) / 32 * 32;
+    const dim3 block(256);
+#define RRT_DO2SH16(NT, RT)                                                                                  \
+    {                                                                                                        \
+        const long nb = (R + 64 * RT - 1) / (64 * RT);                                                       \
+        if (nb > 0x7fffffffL) return false;                                                                 \
+        const size_t sm = 2 * sizeof(_Float16) * (size_t)(NT * 16) * 72;                                    \
+        hipLaunchKernelGGL((k_do2sh_f16<NT, RT>), dim3((unsigned)(8 * ((nb + 7) / 8))), block, sm, st, R, K, Kp, \
+                           NL, A, WYh, WYl, C);                                                             \
+        return true;                                                                                         \
+    }
+    if (NL <= 16) RRT_DO2SH16(1, 4)
+    if (NL <= 64) RRT_DO2SH16(4, 2)
+    if (NL <= 256) RRT_DO2SH16(16, 1)
+#undef RRT_DO2SH16
+    return false;
+}
+
+bool launch_sh2do_f16(long R, int K, int NL, const float *S, const _Float16 *Yh, const _Float16 *Yl, float *C,
+                      hipStream_t st)
+{
+    const long nb = (R + 63) / 64;
+    if (nb > 0x7fffffffL) return false;
+    const dim3 grid((unsigned)(8 * ((nb + 7) / 8))), block(256);
+    auto sm = [](int NB) { return 2 * sizeof(_Float16) * 64 * (size_t)(NB * 32 + 8); };
+    if (NL <= 32) hipLaunchKernelGGL(k_sh2do_f16<1>, grid, block, sm(1), st, R, K, NL, S, Yh, Yl, C);
+    else if (NL <= 64) hipLaunchKernelGGL(k_sh2do_f16<2>, grid, block, sm(2), st, R, K, NL, S, Yh, Yl, C);
+    else if (NL <= 128) hipLaunchKernelGGL(k_sh2do_f16<4>, grid, block, sm(4), st, R, K, NL, S, Yh, Yl, C);
+    else if (NL <= 256) hipLaunchKernelGGL(k_sh2do_f16<8>, grid, block, sm(8), st, R, K, NL, S, Yh, Yl, C);
+    else return false;
+    return true;
+}
+
 template <typename real>
 void launch_source(const SourceArgs<real> &a, hipStream_t st)
 {
@@ -1463,6 +1704,13 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_unboost<float>),
                          reinterpret_cast<const void *>(&k_unboost<double>),
                          reinterpret_cast<const void *>(&k_source_compton<float>),
+                         reinterpret_cast<const void *>(&k_do2sh_f16<1, 4>),
+                         reinterpret_cast<const void *>(&k_do2sh_f16<4, 2>),
+                         reinterpret_cast<const void *>(&k_do2sh_f16<16, 1>),
+                         reinterpret_cast<const void *>(&k_sh2do_f16<1>),
+                         reinterpret_cast<const void *>(&k_sh2do_f16<2>),
+                         reinterpret_cast<const void *>(&k_sh2do_f16<4>),
+                         reinterpret_cast<const void *>(&k_sh2do_f16<8>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<1>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<4>),
                          reinterpret_cast<const void *>(&k_source_compton<double>)};

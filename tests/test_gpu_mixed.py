@@ -1,0 +1,98 @@
+"""Mixed precision (FP16 matrix-core SH <-> ordinate products, FP32 elsewhere)
+against the FP64 oracle, through the C ABI.
+
+Target: 1e-3 on J, H and the Eddington tensor of converged solves, with the
+error definitions J: per-point relative; H and K: max-norm error relative to
+the max-norm of the reference, per group; f = K/J: absolute, over points with
+J > 1e-6 max J.  One sweep is compared element by element to the per-group
+maximum.  Every test prints the errors it measured.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1507_05141_amd import binding as B
+from paper_1507_05141_amd import workloads as W
+from test_gpu_parity import CASES, custom_spec
+
+pytestmark = pytest.mark.gpu
+
+TARGET = 1e-3
+
+
+def _group_err(got, ref, gaxis):
+    g = np.moveaxis(got, gaxis, 0).reshape(got.shape[gaxis], -1)
+    r = np.moveaxis(ref, gaxis, 0).reshape(ref.shape[gaxis], -1)
+    return max(np.max(np.abs(g[i] - r[i])) / max(np.max(np.abs(r[i])), 1e-300) for i in range(r.shape[0]))
+
+
+def moment_errors(got, ref, decades=None):
+    """Errors of (J, H, K) against the reference; with `decades`, only groups whose
+    largest J is within that many decades of the largest group's count (FP32 carries
+    no relative accuracy further down a steep spectrum)."""
+    J, H, K = got
+    Jr, Hr, Kr = ref
+    if decades is not None:
+        keep = Jr.max(axis=0) >= Jr.max() * 10.0 ** -decades
+        J, H, K, Jr, Hr, Kr = J[:, keep], H[:, keep], K[:, keep], Jr[:, keep], Hr[:, keep], Kr[:, keep]
+    e = {"J": float(np.max(np.abs(J - Jr) / np.maximum(np.abs(Jr), 1e-300)))}
+    for nm, a, ar in (("H", H, Hr), ("K", K, Kr)):
+        e[nm] = max(float(np.max(np.abs(a[:, g] - ar[:, g])) / max(np.max(np.abs(ar[:, g])), 1e-300))
+                    for g in range(Jr.shape[1]))
+    mask = Jr > 1e-6 * Jr.max(axis=0, keepdims=True)
+    f, fr = K / np.where(mask, J, 1.0)[..., None], Kr / np.where(mask, Jr, 1.0)[..., None]
+    e["f"] = float(np.max(np.abs(f - fr)[mask]))
+    return e
+
+
+@pytest.mark.parametrize("case", ["thomson_log", "high_gamma_L7", "grey_extinction_8g", "compton_log_keV",
+                                  "lmax0_min_z"])
+def test_mixed_sweep_against_oracle(case):
+    spec = custom_spec(**CASES[case])
+    o = oracle.Oracle(spec)
+    print(f"case {case} mixed", flush=True)
+    g = B.Problem.from_spec(spec, precision=B.MIXED)
+    rs = np.random.default_rng(99)
+    S = o.initial_source() + 0.3 * rs.normal(size=o.sh_shape()) * np.abs(o.initial_source()[..., :1]).mean()
+    ref_I, ref_Ilm, ref_S, _ = o.sweep(S)
+    g.set_source_sh(S)
+    g.sweep()
+    errs = {"I_lab": _group_err(g.sweep_intensity(), ref_I, 2), "I_lm": _group_err(g.intensity_sh(), ref_Ilm, 1),
+            "S": _group_err(g.source_sh(), ref_S, 1)}
+    print(case, {k: f"{v:.2e}" for k, v in errs.items()}, flush=True)
+    g.close()
+    for k, v in errs.items():
+        assert v <= TARGET, f"{case} {k}: {v:.3e}"
+
+
+def _solve_both(spec, tol_mixed=1e-6, decades=None):
+    o = oracle.Oracle(spec)
+    ref = o.solve(tol=1e-10, max_iter=500, use_ng=True)
+    g = B.Problem.from_spec(spec, precision=B.MIXED)
+    # a spectrum spanning more decades than FP32 resolves stalls above tol in its deepest groups
+    g.solve(tol=tol_mixed, max_iter=300, use_ng=True, allow_not_converged=decades is not None)
+    lab = moment_errors(g.moments(B.FRAME_LAB), o.moments_lab(ref["I_lab"]), decades)
+    co = moment_errors(g.moments(B.FRAME_COMOVING), o.moments_comoving(ref["I_lm"]), decades)
+    g.close()
+    return lab, co
+
+
+@pytest.mark.parametrize("name", ["uniform_slab", "small_jet", "small_compton_jet"])
+def test_mixed_converged_moments(name):
+    if name == "uniform_slab":
+        spec = W.uniform_slab()
+    elif name == "small_jet":
+        spec = W.thomson_jet(n=8, ng=4, lmax=3, nmu=4, nphi=8, seed=2)
+    else:
+        # groups up to 200 keV: with L = 3 the truncated Klein-Nishina redistribution of
+        # MeV photons is not a positive kernel and the Lambda iteration does not converge,
+        # in the oracle either
+        spec = W.compton_jet(n=8, ng=8, lmax=3, nmu=4, nphi=8, e_hi=200.0)
+        spec["kte"] = None
+    print(f"converged {name} mixed", flush=True)
+    lab, co = _solve_both(spec)
+    print(name, "lab", {k: f"{v:.2e}" for k, v in lab.items()}, "comoving", {k: f"{v:.2e}" for k, v in co.items()},
+          flush=True)
+    for frame, e in (("lab", lab), ("comoving", co)):
+        for k in ("J", "H", "K", "f"):
+            assert e[k] <= TARGET, f"{name} {frame} {k}: {e[k]:.3e}"
