@@ -94,6 +94,33 @@ def cpu_baseline(spec, inv_cdt):
             "sample": f"one full FP64 sweep of the same workload ({updates} updates, {dt:.1f} s)"}
 
 
+def serving_bench(args):
+    """Solve requests drawn from the mix (grids 16^3-32^3, 4-16 groups, L = 3 or 7,
+    Thomson or Compton) arriving as a Poisson stream: first all at once in FP32 to
+    measure the capacity, then at 0.8 x that rate in FP32 and in mixed precision,
+    each solve to a residual below 1e-6 with Ng acceleration."""
+    from paper_1507_05141_amd import binding as B
+    from paper_1507_05141_amd import serving as SV
+    budget = 64 << 30
+    burst = SV.poisson_requests(args.requests, rate=0.0, seed=5)
+    recs, wall = SV.serve(burst, precision=B.FP32, budget_bytes=budget)
+    cap = SV.summary(recs, wall)["solves_per_s"]
+    rate = 0.8 * cap
+    stream = SV.poisson_requests(args.requests, rate=rate, seed=5)
+    res = {}
+    for name, prec in (("fp32", B.FP32), ("mixed", B.MIXED)):
+        recs, wall = SV.serve(stream, precision=prec, budget_bytes=budget)
+        res[name] = SV.summary(recs, wall)
+    return {"metric": "solves/s (continuous batching of a request stream)", "value": res["mixed"]["solves_per_s"],
+            "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
+            "dtype": "f32+f16mfma", "data": "synthetic",
+            "p50_ms": res["mixed"]["p50_ms"], "p99_ms": res["mixed"]["p99_ms"],
+            "config": {"workload": "request mix: n in {16,24,32}, G in {4,8,16}, L in {3,7}, Thomson/Compton",
+                       "requests": args.requests, "arrival_rate_per_s": rate, "fp32_capacity_solves_per_s": cap,
+                       "tol": 1e-6, "hbm_budget_bytes": budget},
+            "fp32": res["fp32"], "mixed": res["mixed"]}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -105,6 +132,9 @@ def main():
                     help="thomson_jet: 32^3, 16 groups, L=7 (default); compton_jet: 64^3, 32 groups, L=15, "
                          "electrons at rest")
     ap.add_argument("--steady", action="store_true", help="time steady-state sweeps instead of a time-step stage")
+    ap.add_argument("--serving", action="store_true",
+                    help="continuous batching of a stream of solve requests instead of sweeps: solves/s, p50/p99 latency")
+    ap.add_argument("--requests", type=int, default=48, help="requests in the --serving stream")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
@@ -122,6 +152,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs the GPU"
     torch.cuda.set_device(0)
+    if args.serving:
+        print(json.dumps(serving_bench(args)), flush=True)
+        return
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

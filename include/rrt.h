@@ -172,8 +172,52 @@ rrt_status rrt_kernel_time(rrt_problem *pr, const char *kernel, int *launches, d
 /* Synchronise the problem's stream. */
 rrt_status rrt_synchronize(rrt_problem *pr);
 
+/* Destroy a problem (removing it from its batch first) and free its memory. */
 void rrt_destroy(rrt_problem *pr);
 const char *rrt_last_error(void);
+
+/* Device memory the problem holds now, in bytes (grows when Ng chains or
+   time-stepping arrays are first needed). */
+size_t rrt_device_bytes(const rrt_problem *pr);
+
+/* ---------------------------------------------------------------------------
+   Batches: steady-state solves of independent problems sharing the GPU.
+   Each admitted problem runs the Lambda iteration with Ng acceleration of
+   rrt_solve (Sec. 2), kept on the device between calls; rrt_batch_step
+   advances every running solve by one iteration per round, queuing all of
+   them (each problem on its own stream) before waiting, so their kernels
+   overlap.  A solve runs exactly the iterations rrt_solve would, so its
+   result is the same alone and in a batch.  A batch keeps pointers to its
+   problems but owns none of them.
+   ------------------------------------------------------------------------- */
+typedef struct rrt_batch rrt_batch;
+
+/* A batch whose admitted problems may hold at most max_hbm_bytes of device
+   memory (rrt_device_bytes, counted at admission). */
+rrt_status rrt_batch_create(size_t max_hbm_bytes, rrt_batch **out);
+
+/* Admit a problem (medium set, not in a batch) and start its solve from its
+   current intensity state (0 after rrt_create), as rrt_solve(tol, max_iter,
+   use_ng).  RRT_E_HBM when the budget has no room (the batch is unchanged),
+   RRT_E_STATE / RRT_E_INVALID for bad state or arguments. */
+rrt_status rrt_batch_admit(rrt_batch *b, rrt_problem *pr, double tol, int max_iter, int use_ng);
+
+/* Advance every running solve by up to `rounds` iterations; *active (may be
+   NULL) receives the number still running. */
+rrt_status rrt_batch_step(rrt_batch *b, int rounds, int *active);
+
+/* *done = 1 once the problem's solve has finished; info (may be NULL) as for
+   rrt_solve, seconds measured from admission.  Returns the finished solve's
+   status (RRT_OK, RRT_E_NOT_CONVERGED, or a device error), RRT_OK while it
+   runs.  A finished problem's results are read with the usual getters. */
+rrt_status rrt_batch_poll(rrt_batch *b, const rrt_problem *pr, int *done, rrt_info *info);
+
+/* Take a problem (finished or not) out of the batch, returning its share of
+   the budget; the problem itself stays valid. */
+rrt_status rrt_batch_remove(rrt_batch *b, rrt_problem *pr);
+
+/* Remove every problem and free the batch. */
+void rrt_batch_destroy(rrt_batch *b);
 
 #ifdef __cplusplus
 }

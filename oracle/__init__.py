@@ -274,16 +274,37 @@ class Oracle:
             return self.source(np.zeros(self.sh_shape()))
         return self.source(self.fold(I_in))
 
-    @staticmethod
-    def ng_extrapolate(chain):
+    # groups whose source norm is below this fraction of the largest group's are
+    # measured against that floor in the convergence test (their relative change
+    # carries no weight and is not resolved in single precision)
+    RESIDUAL_FLOOR = 1e-20
+
+    @classmethod
+    def floored_residual(cls, S_old, S_new):
+        """Per-group residual ||S_new,g - S_old,g|| / max(||S_new,g||, floor * max_g' ||S_new,g'||)
+        (norms over points and SH terms)."""
+        S_old, S_new = np.asarray(S_old), np.asarray(S_new)
+        dn = np.sum((S_new - S_old) ** 2, axis=(0, 2))
+        nn = np.sum(S_new ** 2, axis=(0, 2))
+        den = np.maximum(nn, cls.RESIDUAL_FLOOR ** 2 * nn.max())
+        with np.errstate(divide="ignore", invalid="ignore"):
+            return np.where(den > 0, np.sqrt(dn / np.where(den > 0, den, 1.0)), np.where(dn > 0, np.inf, 0.0))
+
+    @classmethod
+    def ng_extrapolate(cls, chain):
         """Ng acceleration in the two-coefficient form of Auer (1987) from the
-        last four members of a chain of Lambda iterates (newest last)."""
+        last four members of a chain of Lambda iterates (newest last).  The dot
+        products weight each group by 1/||S_g||^2 of the newest member (floored
+        as in the residual), so that every group counts by its relative change,
+        as in the convergence test."""
         s3, s2, s1, s0 = chain[-4], chain[-3], chain[-2], chain[-1]
+        nn = np.sum(np.asarray(s0) ** 2, axis=(0, 2))
+        den = np.maximum(nn, cls.RESIDUAL_FLOOR ** 2 * nn.max())
+        w = np.where(den > 0, 1.0 / np.where(den > 0, den, 1.0), 1.0)[None, :, None]
         d0, d1, d2 = s0 - s1, s1 - s2, s2 - s3
-        q1, q2 = (d0 - d1).ravel(), (d0 - d2).ravel()
-        d0r = d0.ravel()
-        a11, a12, a22 = q1 @ q1, q1 @ q2, q2 @ q2
-        b1, b2 = d0r @ q1, d0r @ q2
+        q1, q2 = d0 - d1, d0 - d2
+        a11, a12, a22 = np.sum(w * q1 * q1), np.sum(w * q1 * q2), np.sum(w * q2 * q2)
+        b1, b2 = np.sum(w * d0 * q1), np.sum(w * d0 * q2)
         det = a11 * a22 - a12 * a12
         if not (det > 1e-14 * a11 * a22) or not np.isfinite(det):
             return None
@@ -304,6 +325,7 @@ class Oracle:
         while it < max_iter:
             it += 1
             I_lab, I_lm, S_new, r = self.sweep(S, I_prev, inv_cdt)
+            r = self.floored_residual(S, S_new)
             S = S_new
             if float(np.max(r)) < tol:
                 break

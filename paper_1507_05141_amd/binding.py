@@ -80,6 +80,11 @@ def lib():
             "rrt_set_profiling": [P, I],
             "rrt_kernel_time": [P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(D)],
             "rrt_synchronize": [P],
+            "rrt_batch_create": [ctypes.c_size_t, ctypes.POINTER(P)],
+            "rrt_batch_admit": [P, P, D, I, I],
+            "rrt_batch_step": [P, I, ctypes.POINTER(I)],
+            "rrt_batch_poll": [P, P, ctypes.POINTER(I), ctypes.POINTER(Info)],
+            "rrt_batch_remove": [P, P],
         }
         for name, args in sigs.items():
             f = getattr(L, name)
@@ -91,6 +96,10 @@ def lib():
         L.rrt_last_error.restype = ctypes.c_char_p
         L.rrt_footprint_bytes.argtypes = [ctypes.POINTER(Grid), ctypes.POINTER(Groups), ctypes.POINTER(Angles), I, I, I]
         L.rrt_footprint_bytes.restype = ctypes.c_size_t
+        L.rrt_device_bytes.argtypes = [P]
+        L.rrt_device_bytes.restype = ctypes.c_size_t
+        L.rrt_batch_destroy.argtypes = [P]
+        L.rrt_batch_destroy.restype = None
         _lib = L
     return _lib
 
@@ -262,3 +271,55 @@ class Problem:
 
     def synchronize(self):
         _check(lib().rrt_synchronize(self._h))
+
+    def device_bytes(self):
+        return lib().rrt_device_bytes(self._h)
+
+
+class Batch:
+    """Steady-state solves of independent problems sharing the GPU (rrt_batch_*):
+    admission against a device-memory budget, rounds of one iteration per running
+    solve, polling and removal.  The batch does not own its problems."""
+
+    def __init__(self, max_hbm_bytes):
+        h = ctypes.c_void_p()
+        _check(lib().rrt_batch_create(int(max_hbm_bytes), ctypes.byref(h)))
+        self._h = h
+
+    def admit(self, problem, tol=1e-6, max_iter=200, use_ng=True):
+        """True when admitted, False when the budget has no room."""
+        st = lib().rrt_batch_admit(self._h, problem._h, float(tol), int(max_iter), int(use_ng))
+        if st == RRT_E_HBM:
+            return False
+        _check(st)
+        return True
+
+    def step(self, rounds=1):
+        n = ctypes.c_int()
+        _check(lib().rrt_batch_step(self._h, int(rounds), ctypes.byref(n)))
+        return n.value
+
+    def poll(self, problem):
+        """(done, info dict with "converged" once done)."""
+        d = ctypes.c_int()
+        i = Info()
+        st = _check(lib().rrt_batch_poll(self._h, problem._h, ctypes.byref(d), ctypes.byref(i)),
+                    allow=(RRT_E_NOT_CONVERGED,))
+        info = Problem._info(i)
+        if d.value:
+            info["converged"] = st == RRT_OK
+        return bool(d.value), info
+
+    def remove(self, problem):
+        _check(lib().rrt_batch_remove(self._h, problem._h))
+
+    def close(self):
+        if self._h:
+            lib().rrt_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -41,6 +41,7 @@ const char *kNames[KI_N] = {"trace", "sh2do", "boost", "unboost", "do2sh", "sour
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kMaxLds = 160 * 1024;
+constexpr double kResidualFloor = 1e-20;    // of the largest group's source norm
 
 }  // namespace
 
@@ -82,8 +83,21 @@ struct rrt_problem {
     void *d_Iin = nullptr, *d_acc = nullptr;
     void *d_chain[4] = {nullptr, nullptr, nullptr, nullptr};
     double *d_partial = nullptr, *d_red = nullptr;
+    double *h_red = nullptr;                        // pinned host copy of the per-group residual sums
     int nblk_red = 0;
     bool medium_set = false;
+    size_t dev_bytes = 0;                           // device memory held by the problem
+    // a Lambda iteration in progress: one sweep per round, Ng every fourth chain member
+    struct Solve {
+        const void *Iprev = nullptr;
+        double inv_cdt = 0, tol = 0, r = INFINITY;
+        int max_iter = 0, use_ng = 0, it = 0, clen = 0;
+        int phase = 0;                              // 0 idle, 1 running, 2 finished
+        rrt_status st = RRT_OK;
+        std::chrono::steady_clock::time_point t0;
+        double seconds = 0;                         // begin to finish
+    } sv;
+    rrt_batch *batch = nullptr;
     // kernel timing
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[KI_N];
@@ -112,6 +126,15 @@ void dev_free(void *&p)
 {
     if (p) (void)hipFree(p);
     p = nullptr;
+}
+
+// allocation owned by the problem (counted in dev_bytes)
+rrt_status pr_alloc(rrt_problem *pr, void **ptr, size_t bytes)
+{
+    if (*ptr) return RRT_OK;
+    rrt_status s = dev_alloc(ptr, bytes);
+    if (!s) pr->dev_bytes += bytes ? bytes : 1;
+    return s;
 }
 
 // upload host doubles converted to the working precision
@@ -145,7 +168,7 @@ rrt_status download_real(rrt_problem *pr, double *dst, const void *src, size_t n
 
 rrt_status upload_double(rrt_problem *pr, void **dst, const std::vector<double> &v)
 {
-    rrt_status s = dev_alloc(dst, v.size() * 8);
+    rrt_status s = pr_alloc(pr, dst, v.size() * 8);
     if (s) return s;
     HIPCHK(hipMemcpyAsync(*dst, v.data(), v.size() * 8, hipMemcpyHostToDevice, pr->stream));
     HIPCHK(hipStreamSynchronize(pr->stream));
@@ -154,7 +177,7 @@ rrt_status upload_double(rrt_problem *pr, void **dst, const std::vector<double> 
 
 rrt_status alloc_upload_real(rrt_problem *pr, void **dst, const std::vector<double> &v)
 {
-    rrt_status s = dev_alloc(dst, v.size() * pr->esz);
+    rrt_status s = pr_alloc(pr, dst, v.size() * pr->esz);
     if (s) return s;
     return upload_real(pr, *dst, v.data(), v.size());
 }
@@ -313,7 +336,8 @@ struct Engine {
     }
 
     // S8: max over groups of ||a - b|| / ||a||
-    rrt_status residual(const void *a, const void *b, double *r)
+    // S8, queued: per-group sums into the pinned host buffer (read after the stream is synchronized)
+    rrt_status residual_launch(const void *a, const void *b)
     {
         prof_begin(pr, KI_REDUCE);
         rrt::launch_resid<real>(pr->P, pr->G, pr->NL, static_cast<const real *>(a), static_cast<const real *>(b),
@@ -321,21 +345,37 @@ struct Engine {
         prof_end(pr, KI_REDUCE);
         rrt_status s = check_launch();
         if (s) return s;
-        std::vector<double> h(2 * pr->G);
-        HIPCHK(hipMemcpyAsync(h.data(), pr->d_red, h.size() * 8, hipMemcpyDeviceToHost, pr->stream));
-        HIPCHK(hipStreamSynchronize(pr->stream));
+        HIPCHK(hipMemcpyAsync(pr->h_red, pr->d_red, 2 * (size_t)pr->G * 8, hipMemcpyDeviceToHost, pr->stream));
+        return RRT_OK;
+    }
+    // max over groups of ||a - b|| / ||a|| from the downloaded sums, a group's norm floored
+    // at kResidualFloor of the largest group's (relative changes that far down the
+    // spectrum carry no weight and are not resolved in single precision)
+    double residual_value() const
+    {
+        double amax = 0.0;
+        for (int g = 0; g < pr->G; ++g) amax = std::fmax(amax, pr->h_red[2 * g + 1]);
+        const double floor2 = kResidualFloor * kResidualFloor * amax;
         double m = 0.0;
         for (int g = 0; g < pr->G; ++g) {
-            const double dd = h[2 * g], aa = h[2 * g + 1];
+            const double dd = pr->h_red[2 * g], aa = std::fmax(pr->h_red[2 * g + 1], floor2);
             const double rg = (aa > 0.0) ? std::sqrt(dd / aa) : (dd > 0.0 ? INFINITY : 0.0);
             if (!(rg <= m)) m = rg;
         }
-        *r = m;
+        return m;
+    }
+    rrt_status residual(const void *a, const void *b, double *r)
+    {
+        rrt_status s = residual_launch(a, b);
+        if (s) return s;
+        HIPCHK(hipStreamSynchronize(pr->stream));
+        *r = residual_value();
         return RRT_OK;
     }
 
-    // one source iteration from d_S (Iprev/inv_cdt: implicit time terms)
-    rrt_status sweep(const void *Iprev, double inv_cdt, double *resid)
+    // one source iteration from d_S (Iprev/inv_cdt: implicit time terms), queued on the
+    // stream; the residual sums arrive in h_red
+    rrt_status sweep_launch(const void *Iprev, double inv_cdt)
     {
         rrt_status s = to_lab(pr->d_S, Iprev, inv_cdt);
         if (s) return s;
@@ -343,9 +383,17 @@ struct Engine {
         if ((s = fold(pr->d_Ilab))) return s;
         source(pr->d_Snew);
         if ((s = check_launch())) return s;
-        s = residual(pr->d_Snew, pr->d_S, resid);
+        s = residual_launch(pr->d_Snew, pr->d_S);
         if (s) return s;
         std::swap(pr->d_S, pr->d_Snew);
+        return RRT_OK;
+    }
+    rrt_status sweep(const void *Iprev, double inv_cdt, double *resid)
+    {
+        rrt_status s = sweep_launch(Iprev, inv_cdt);
+        if (s) return s;
+        HIPCHK(hipStreamSynchronize(pr->stream));
+        *resid = residual_value();
         return RRT_OK;
     }
 
@@ -358,67 +406,90 @@ struct Engine {
         return check_launch();
     }
 
-    rrt_status ng_step(double *ok)
+    // Ng extrapolation of the chain (chain[3] newest) into d_S, queued (coefficients on the device);
+    // the dot products weight each group by the inverse square of its norm in chain[3]
+    rrt_status ng_step()
     {
         const size_t n = sh_elems(pr);
-        // chain[3] newest ... chain[0] oldest
         prof_begin(pr, KI_REDUCE);
-        rrt::launch_ng_dots<real>((long)n, R(pr->d_chain[3]), R(pr->d_chain[2]), R(pr->d_chain[1]), R(pr->d_chain[0]),
+        // d_red still holds the last residual's per-group sums, ||chain[3]_g||^2 among them
+        rrt::launch_ng_dots<real>((long)n, pr->G, pr->NL, pr->d_red, kResidualFloor * kResidualFloor,
+                                  R(pr->d_chain[3]), R(pr->d_chain[2]), R(pr->d_chain[1]), R(pr->d_chain[0]),
                                   pr->d_partial, pr->nblk_red, pr->d_red, pr->stream);
+        rrt::launch_ng_extrapolate<real>((long)n, pr->d_red, R(pr->d_chain[3]), R(pr->d_chain[2]), R(pr->d_chain[1]),
+                                         R(pr->d_S), pr->stream);
         prof_end(pr, KI_REDUCE);
-        rrt_status s = check_launch();
-        if (s) return s;
-        double h[5];
-        HIPCHK(hipMemcpyAsync(h, pr->d_red, sizeof(h), hipMemcpyDeviceToHost, pr->stream));
-        HIPCHK(hipStreamSynchronize(pr->stream));
-        const double a11 = h[0], a12 = h[1], a22 = h[2], b1 = h[3], b2 = h[4];
-        const double det = a11 * a22 - a12 * a12;
-        *ok = 0;
-        if (!(det > 1e-14 * a11 * a22) || !std::isfinite(det)) return RRT_OK;
-        const double a = (b1 * a22 - b2 * a12) / det;
-        const double b = (b2 * a11 - b1 * a12) / det;
-        rrt::launch_combine3<real>((long)n, 1.0 - a - b, R(pr->d_chain[3]), a, R(pr->d_chain[2]), b, R(pr->d_chain[1]),
-                                   R(pr->d_S), pr->stream);
-        *ok = 1;
         return check_launch();
     }
 
-    // Lambda iteration; the lab intensity of the last sweep is left in d_Ilab
-    rrt_status solve(const void *Iprev, double inv_cdt, const void *Iinit, double tol, int max_iter, int use_ng,
-                     int *iters, double *res)
+    // Lambda iteration in rounds: solve_begin queues the initial source; each round
+    // queues one sweep (round_launch) and, once the stream has been synchronized,
+    // reads its residual and queues the Ng bookkeeping (round_finish).  The lab
+    // intensity of the last sweep is left in d_Ilab.
+    rrt_status solve_begin(const void *Iprev, double inv_cdt, const void *Iinit, double tol, int max_iter, int use_ng)
     {
+        auto &v = pr->sv;
+        v = rrt_problem::Solve{};
+        v.Iprev = Iprev; v.inv_cdt = inv_cdt; v.tol = tol; v.max_iter = max_iter; v.use_ng = use_ng;
+        v.t0 = std::chrono::steady_clock::now();
         const size_t shb = sh_elems(pr) * pr->esz;
         rrt_status s = initial_source(Iinit);
         if (s) return s;
         if (use_ng) {
             for (int c = 0; c < 4; ++c)
-                if ((s = dev_alloc(&pr->d_chain[c], shb))) return s;
-        }
-        int clen = 0;
-        if (use_ng) {
+                if ((s = pr_alloc(pr, &pr->d_chain[c], shb))) return s;
             HIPCHK(hipMemcpyAsync(pr->d_chain[0], pr->d_S, shb, hipMemcpyDeviceToDevice, pr->stream));
-            clen = 1;
+            v.clen = 1;
         }
-        double r = INFINITY;
-        int it = 0;
-        while (it < max_iter) {
-            ++it;
-            if ((s = sweep(Iprev, inv_cdt, &r))) return s;
-            if (r < tol) break;
-            if (use_ng) {
-                HIPCHK(hipMemcpyAsync(pr->d_chain[clen], pr->d_S, shb, hipMemcpyDeviceToDevice, pr->stream));
-                ++clen;
-                if (clen == 4) {
-                    double ok = 0;
-                    if ((s = ng_step(&ok))) return s;
-                    HIPCHK(hipMemcpyAsync(pr->d_chain[0], pr->d_S, shb, hipMemcpyDeviceToDevice, pr->stream));
-                    clen = 1;
-                }
+        v.phase = 1;
+        return RRT_OK;
+    }
+    rrt_status round_launch()
+    {
+        ++pr->sv.it;
+        return sweep_launch(pr->sv.Iprev, pr->sv.inv_cdt);
+    }
+    rrt_status round_finish()
+    {
+        auto &v = pr->sv;
+        v.r = residual_value();
+        if (v.r < v.tol) {
+            v.phase = 2;
+            v.st = RRT_OK;
+            return RRT_OK;
+        }
+        if (v.use_ng) {
+            const size_t shb = sh_elems(pr) * pr->esz;
+            HIPCHK(hipMemcpyAsync(pr->d_chain[v.clen], pr->d_S, shb, hipMemcpyDeviceToDevice, pr->stream));
+            if (++v.clen == 4) {
+                rrt_status s = ng_step();
+                if (s) return s;
+                HIPCHK(hipMemcpyAsync(pr->d_chain[0], pr->d_S, shb, hipMemcpyDeviceToDevice, pr->stream));
+                v.clen = 1;
             }
         }
-        *iters = it;
-        *res = r;
-        return (r < tol) ? RRT_OK : RRT_E_NOT_CONVERGED;
+        if (v.it >= v.max_iter) {
+            v.phase = 2;
+            v.st = RRT_E_NOT_CONVERGED;
+        }
+        return RRT_OK;
+    }
+    rrt_status solve(const void *Iprev, double inv_cdt, const void *Iinit, double tol, int max_iter, int use_ng,
+                     int *iters, double *res)
+    {
+        rrt_status s = solve_begin(Iprev, inv_cdt, Iinit, tol, max_iter, use_ng);
+        while (!s && pr->sv.phase == 1) {
+            if ((s = round_launch())) break;
+            if (hipStreamSynchronize(pr->stream) != hipSuccess) {
+                s = fail(RRT_E_DEVICE, "stream synchronize");
+                break;
+            }
+            s = round_finish();
+        }
+        pr->sv.phase = 0;
+        *iters = pr->sv.it;
+        *res = pr->sv.r;
+        return s ? s : pr->sv.st;
     }
 
     rrt_status moments(rrt_frame frame, double *J, double *H, double *Kt)
@@ -458,7 +529,7 @@ struct Engine {
         const size_t n = do_elems(pr);
         const size_t b = n * pr->esz;
         rrt_status s;
-        if ((s = dev_alloc(&pr->d_Iin, b)) || (s = dev_alloc(&pr->d_acc, b))) return s;
+        if ((s = pr_alloc(pr, &pr->d_Iin, b)) || (s = pr_alloc(pr, &pr->d_acc, b))) return s;
         int total = 0;
         double rmax = 0;
         for (int step = 0; step < nsteps; ++step) {
@@ -575,7 +646,9 @@ size_t rrt_footprint_bytes(const rrt_grid *grid, const rrt_groups *groups, const
 void rrt_destroy(rrt_problem *pr)
 {
     if (!pr) return;
+    if (pr->batch) (void)rrt_batch_remove(pr->batch, pr);
     if (pr->stream) (void)hipStreamSynchronize(pr->stream);
+    if (pr->h_red) (void)hipHostFree(pr->h_red);
     if (pr->blas) (void)rocblas_destroy_handle(pr->blas);
     void *bufs[] = {pr->d_dir, pr->d_mu, pr->d_lnc, pr->d_nu3, pr->d_inv_nu3, pr->d_inv_dc, pr->d_geo, pr->d_Yt, pr->d_WY,
                     pr->d_Y16, pr->d_WYt16,
@@ -730,7 +803,7 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
                 gm.iy[c] = (int)iy;
             }
         }
-        s = dev_alloc((void **)&pr->d_geo, sizeof(rrt::OrdGeom) * K);
+        s = pr_alloc(pr, (void **)&pr->d_geo, sizeof(rrt::OrdGeom) * K);
         if (s) return bail(s);
         hipError_t e = hipMemcpy(pr->d_geo, geo.data(), sizeof(rrt::OrdGeom) * K, hipMemcpyHostToDevice);
         if (e != hipSuccess) return bail(fail(RRT_E_DEVICE, "geometry upload"));
@@ -790,9 +863,9 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
     }
     // state arrays
     const size_t shb = sh_elems(pr) * pr->esz, dob = do_elems(pr) * pr->esz;
-    if ((s = dev_alloc(&pr->d_S, shb)) || (s = dev_alloc(&pr->d_Snew, shb)) || (s = dev_alloc(&pr->d_Ilm, shb)) ||
-        (s = dev_alloc(&pr->d_co, dob)) || (s = dev_alloc(&pr->d_St, dob)) || (s = dev_alloc(&pr->d_Ilab, dob)) ||
-        (s = dev_alloc(&pr->d_I, dob)))
+    if ((s = pr_alloc(pr, &pr->d_S, shb)) || (s = pr_alloc(pr, &pr->d_Snew, shb)) || (s = pr_alloc(pr, &pr->d_Ilm, shb)) ||
+        (s = pr_alloc(pr, &pr->d_co, dob)) || (s = pr_alloc(pr, &pr->d_St, dob)) || (s = pr_alloc(pr, &pr->d_Ilab, dob)) ||
+        (s = pr_alloc(pr, &pr->d_I, dob)))
         return bail(s);
     {
         hipError_t e = hipMemsetAsync(pr->d_I, 0, dob, pr->stream);
@@ -803,10 +876,14 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
         if (e != hipSuccess) return bail(fail(RRT_E_DEVICE, "initial clear"));
     }
     pr->nblk_red = 1024;
-    if ((s = dev_alloc((void **)&pr->d_partial,
+    if ((s = pr_alloc(pr, (void **)&pr->d_partial,
                        std::max((size_t)pr->nblk_red * std::max(2 * G, 5), 2 * (size_t)pr->P * G) * 8)) ||
-        (s = dev_alloc((void **)&pr->d_red, (size_t)std::max(2 * G, 5) * 8)))
+        (s = pr_alloc(pr, (void **)&pr->d_red, (size_t)std::max(2 * G, 5) * 8)))
         return bail(s);
+    if (hipHostMalloc((void **)&pr->h_red, (size_t)std::max(2 * G, 5) * 8, hipHostMallocDefault) != hipSuccess) {
+        pr->h_red = nullptr;
+        return bail(fail(RRT_E_HOST_OOM, "pinned residual buffer"));
+    }
     *out = pr;
     g_err.clear();
     return RRT_OK;
@@ -831,8 +908,8 @@ rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *si
             if (!std::isfinite(b2) || !(b2 < 1.0)) return fail(RRT_E_INVALID, "|beta| must be < 1");
         }
     rrt_status s;
-    if ((s = dev_alloc(&pr->d_kappa, P * G * pr->esz)) || (s = dev_alloc(&pr->d_sigma, P * pr->esz)) ||
-        (s = dev_alloc(&pr->d_bnu, P * G * pr->esz)) || (s = dev_alloc(&pr->d_chi0, P * G * pr->esz)))
+    if ((s = pr_alloc(pr, &pr->d_kappa, P * G * pr->esz)) || (s = pr_alloc(pr, &pr->d_sigma, P * pr->esz)) ||
+        (s = pr_alloc(pr, &pr->d_bnu, P * G * pr->esz)) || (s = pr_alloc(pr, &pr->d_chi0, P * G * pr->esz)))
         return s;
     if ((s = upload_real(pr, pr->d_kappa, kappa, P * G)) || (s = upload_real(pr, pr->d_sigma, sigma, P)) ||
         (s = upload_real(pr, pr->d_bnu, bnu, P * G)))
@@ -843,7 +920,7 @@ rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *si
             const double b2 = beta[3 * i] * beta[3 * i] + beta[3 * i + 1] * beta[3 * i + 1] + beta[3 * i + 2] * beta[3 * i + 2];
             gam[i] = 1.0 / std::sqrt(1.0 - b2);
         }
-        if ((s = dev_alloc((void **)&pr->d_beta, P * 3 * 8)) || (s = dev_alloc((void **)&pr->d_gam, P * 8))) return s;
+        if ((s = pr_alloc(pr, (void **)&pr->d_beta, P * 3 * 8)) || (s = pr_alloc(pr, (void **)&pr->d_gam, P * 8))) return s;
         HIPCHK(hipMemcpyAsync(pr->d_beta, beta, P * 3 * 8, hipMemcpyHostToDevice, pr->stream));
         HIPCHK(hipMemcpyAsync(pr->d_gam, gam.data(), P * 8, hipMemcpyHostToDevice, pr->stream));
         HIPCHK(hipStreamSynchronize(pr->stream));
@@ -867,7 +944,7 @@ rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *si
         void *c = pr->d_chilab;
         dev_free(c);
         pr->d_chilab = nullptr;
-        if ((s = dev_alloc(&pr->d_chilab, nchi * pr->esz))) return s;
+        if ((s = pr_alloc(pr, &pr->d_chilab, nchi * pr->esz))) return s;
     }
     auto chilab = [&](auto tag) {
         using real = decltype(tag);
@@ -896,7 +973,7 @@ rrt_status rrt_set_boundary(rrt_problem *pr, int face, const double *I_in)
     const size_t n = (size_t)pr->K * pr->G * pr->nx * pr->ny;
     for (size_t i = 0; i < n; ++i)
         if (!std::isfinite(I_in[i])) return fail(RRT_E_INVALID, "boundary intensity must be finite");
-    rrt_status s = dev_alloc(&pr->d_bc[face], n * pr->esz);
+    rrt_status s = pr_alloc(pr, &pr->d_bc[face], n * pr->esz);
     if (s) return s;
     return upload_real(pr, pr->d_bc[face], I_in, n);
 }
@@ -941,6 +1018,7 @@ rrt_status rrt_sweep(rrt_problem *pr, double dt_stage, rrt_info *info)
 rrt_status rrt_solve(rrt_problem *pr, double tol, int max_iter, int use_ng, rrt_info *info)
 {
     if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    if (pr->batch) return fail(RRT_E_STATE, "the problem is in a batch: remove it first");
     if (!pr->medium_set) return fail(RRT_E_STATE, "rrt_set_medium must come first");
     if (max_iter < 1 || !(tol >= 0)) return fail(RRT_E_INVALID, "need max_iter >= 1 and tol >= 0");
     auto t0 = std::chrono::steady_clock::now();
@@ -966,6 +1044,7 @@ rrt_status rrt_advance(rrt_problem *pr, double dt, int nsteps, int scheme, doubl
                        rrt_info *info)
 {
     if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    if (pr->batch) return fail(RRT_E_STATE, "the problem is in a batch: remove it first");
     if (!pr->medium_set) return fail(RRT_E_STATE, "rrt_set_medium must come first");
     if (!(dt > 0) || nsteps < 0 || max_iter < 1 || !(tol >= 0)) return fail(RRT_E_INVALID, "bad time-step arguments");
     if (scheme != RRT_SCHEME_RK4 && scheme != RRT_SCHEME_EULER) return fail(RRT_E_INVALID, "unknown scheme");
@@ -1022,7 +1101,7 @@ rrt_status rrt_ray_trace(rrt_problem *pr, const double *S_tilde, const double *c
         if (!std::isfinite(S_tilde[i]) || !std::isfinite(chi_tilde[i]) || chi_tilde[i] < 0)
             return fail(RRT_E_INVALID, "S~ must be finite and chi~ finite and >= 0");
     rrt_status s;
-    if ((s = dev_alloc(&pr->d_Xt, n * pr->esz))) return s;
+    if ((s = pr_alloc(pr, &pr->d_Xt, n * pr->esz))) return s;
     if ((s = upload_real(pr, pr->d_St, S_tilde, n)) || (s = upload_real(pr, pr->d_Xt, chi_tilde, n))) return s;
     s = dispatch(pr, [&](auto &e) {
         e.trace(pr->d_St, pr->d_Ilab, 0.0, true);
@@ -1062,6 +1141,151 @@ rrt_status rrt_synchronize(rrt_problem *pr)
     if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
     HIPCHK(hipStreamSynchronize(pr->stream));
     return RRT_OK;
+}
+
+
+// ---------------------------------------------------------------------------
+// Batches: concurrent steady-state solves of independent problems
+// ---------------------------------------------------------------------------
+}  // extern "C"
+
+struct rrt_batch {
+    size_t budget = 0, used = 0;
+    std::vector<rrt_problem *> items;
+    std::vector<size_t> share;                      // bytes each admitted problem counts against the budget
+};
+
+namespace {
+
+// a finished solve leaves its lab intensity as the problem's state, as rrt_solve does
+void batch_finish(rrt_problem *pr)
+{
+    auto &v = pr->sv;
+    v.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - v.t0).count();
+    if (v.st == RRT_OK || v.st == RRT_E_NOT_CONVERGED) {
+        hipError_t e = hipMemcpyAsync(pr->d_I, pr->d_Ilab, do_elems(pr) * pr->esz, hipMemcpyDeviceToDevice, pr->stream);
+        if (e != hipSuccess) v.st = RRT_E_DEVICE;
+    }
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t rrt_device_bytes(const rrt_problem *pr) { return pr ? pr->dev_bytes : 0; }
+
+rrt_status rrt_batch_create(size_t max_hbm_bytes, rrt_batch **out)
+{
+    if (!out) return fail(RRT_E_INVALID, "out is NULL");
+    *out = nullptr;
+    rrt_batch *b = new (std::nothrow) rrt_batch();
+    if (!b) return fail(RRT_E_HOST_OOM, "batch allocation");
+    b->budget = max_hbm_bytes;
+    *out = b;
+    return RRT_OK;
+}
+
+rrt_status rrt_batch_admit(rrt_batch *b, rrt_problem *pr, double tol, int max_iter, int use_ng)
+{
+    if (!b || !pr) return fail(RRT_E_INVALID, "batch or problem is NULL");
+    if (!pr->medium_set) return fail(RRT_E_STATE, "rrt_set_medium must come first");
+    if (pr->batch) return fail(RRT_E_STATE, "the problem is already in a batch");
+    if (max_iter < 1 || !(tol >= 0)) return fail(RRT_E_INVALID, "need max_iter >= 1 and tol >= 0");
+    const size_t shb = sh_elems(pr) * pr->esz;
+    const size_t need = pr->dev_bytes + ((use_ng && !pr->d_chain[0]) ? 4 * shb : 0);
+    if (b->used + need > b->budget)
+        return fail(RRT_E_HBM, "the batch's device-memory budget has no room for this problem");
+    rrt_status s = dispatch(pr, [&](auto &e) { return e.solve_begin(nullptr, 0.0, pr->d_I, tol, max_iter, use_ng); });
+    if (s) {
+        pr->sv.phase = 0;
+        return s;
+    }
+    pr->batch = b;
+    b->items.push_back(pr);
+    b->share.push_back(pr->dev_bytes);
+    b->used += pr->dev_bytes;
+    return RRT_OK;
+}
+
+rrt_status rrt_batch_step(rrt_batch *b, int rounds, int *active)
+{
+    if (!b || rounds < 0) return fail(RRT_E_INVALID, "batch is NULL or rounds < 0");
+    for (int r = 0; r < rounds; ++r) {
+        int n = 0;
+        // queue one iteration of every running solve on its own stream, then collect them
+        for (rrt_problem *pr : b->items) {
+            if (pr->sv.phase != 1) continue;
+            rrt_status s = dispatch(pr, [&](auto &e) { return e.round_launch(); });
+            if (s) {
+                pr->sv.st = s;
+                pr->sv.phase = 2;
+                batch_finish(pr);
+            } else {
+                ++n;
+            }
+        }
+        if (!n) break;
+        for (rrt_problem *pr : b->items) {
+            if (pr->sv.phase != 1) continue;
+            rrt_status s = hipStreamSynchronize(pr->stream) == hipSuccess
+                               ? dispatch(pr, [&](auto &e) { return e.round_finish(); })
+                               : fail(RRT_E_DEVICE, "stream synchronize");
+            if (s) {
+                pr->sv.st = s;
+                pr->sv.phase = 2;
+            }
+            if (pr->sv.phase == 2) batch_finish(pr);
+        }
+    }
+    if (active) {
+        int n = 0;
+        for (rrt_problem *pr : b->items) n += pr->sv.phase == 1;
+        *active = n;
+    }
+    return RRT_OK;
+}
+
+rrt_status rrt_batch_poll(rrt_batch *b, const rrt_problem *pr, int *done, rrt_info *info)
+{
+    if (!b || !pr || !done) return fail(RRT_E_INVALID, "batch, problem or done is NULL");
+    if (pr->batch != b) return fail(RRT_E_STATE, "the problem is not in this batch");
+    const auto &v = pr->sv;
+    *done = v.phase == 2;
+    if (info) {
+        info->iters = v.it;
+        info->residual = v.r;
+        info->seconds = v.phase == 2 ? v.seconds
+                                     : std::chrono::duration<double>(std::chrono::steady_clock::now() - v.t0).count();
+        info->updates = (long long)v.it * (long long)do_elems(pr);
+    }
+    if (v.phase == 2 && v.st != RRT_OK) {
+        if (v.st == RRT_E_NOT_CONVERGED) fail(v.st, "source iteration did not converge within max_iter");
+        return v.st;
+    }
+    return RRT_OK;
+}
+
+rrt_status rrt_batch_remove(rrt_batch *b, rrt_problem *pr)
+{
+    if (!b || !pr) return fail(RRT_E_INVALID, "batch or problem is NULL");
+    for (size_t i = 0; i < b->items.size(); ++i) {
+        if (b->items[i] != pr) continue;
+        if (hipStreamSynchronize(pr->stream) != hipSuccess) return fail(RRT_E_DEVICE, "stream synchronize");
+        b->used -= b->share[i];
+        b->items.erase(b->items.begin() + i);
+        b->share.erase(b->share.begin() + i);
+        pr->batch = nullptr;
+        pr->sv.phase = 0;
+        return RRT_OK;
+    }
+    return fail(RRT_E_STATE, "the problem is not in this batch");
+}
+
+void rrt_batch_destroy(rrt_batch *b)
+{
+    if (!b) return;
+    while (!b->items.empty()) (void)rrt_batch_remove(b, b->items.back());
+    delete b;
 }
 
 }  // extern "C"

@@ -115,7 +115,12 @@ template <typename real> void launch_chi0(long P, int G, const real *kappa, cons
 template <typename real> void launch_moments_lab(long P, int G, int K, const double *dir, const real *I, double *J, double *H, double *Kt, hipStream_t st);
 template <typename real> void launch_moments_co(long PG, int NL, int lmax, const real *Ilm, double *J, double *H, double *Kt, hipStream_t st);
 template <typename real> void launch_resid(long P, int G, int NL, const real *a, const real *b, double *partial, int nblk, double *out, hipStream_t st);
-template <typename real> void launch_ng_dots(long n, const real *s0, const real *s1, const real *s2, const real *s3, double *partial, int nblk, double *out, hipStream_t st);
+// Ng dot products, each group weighted by 1/||s0_g||^2 from the residual sums red (floor2 as there)
+template <typename real> void launch_ng_dots(long n, int G, int NL, const double *red, double floor2, const real *s0,
+                                             const real *s1, const real *s2, const real *s3, double *partial, int nblk,
+                                             double *out, hipStream_t st);
+template <typename real> void launch_ng_extrapolate(long n, const double *dots, const real *s3, const real *s2,
+                                                    const real *s1, real *out, hipStream_t st);
 template <typename real> void launch_combine3(long n, double c0, const real *x0, double c1, const real *x1, double c2, const real *x2, real *out, hipStream_t st);
 template <typename real> void launch_rk_stage(long n, const real *R, real *Iin, real *acc, real *In, int first, int last, real coef, hipStream_t st);
 

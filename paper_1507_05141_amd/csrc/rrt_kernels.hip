@@ -1414,17 +1414,31 @@ __global__ void __launch_bounds__(256) k_resid_groups(long P, int G, const doubl
 }
 
 // five dot products for the Ng extrapolation from the chain s3 (oldest) .. s0
+// (arrays [P][G][NL]), each group weighted by 1/||s0_g||^2 taken from the
+// per-group sums red[2 g + 1] that the last residual left (floored at floor2
+// times the largest, as in the convergence test)
 template <typename real>
-__global__ void __launch_bounds__(256) k_ng_partial(long n, const real *__restrict__ s0, const real *__restrict__ s1,
+__global__ void __launch_bounds__(256) k_ng_partial(long n, int G, int NL, const double *__restrict__ red, double floor2,
+                                                    const real *__restrict__ s0, const real *__restrict__ s1,
                                                     const real *__restrict__ s2, const real *__restrict__ s3, double *partial)
 {
+    extern __shared__ unsigned char smem_raw[];
+    double *w = reinterpret_cast<double *>(smem_raw);               // [G]
     __shared__ double sh[256];
+    double amax = 0;
+    for (int g = 0; g < G; ++g) amax = fmax(amax, red[2 * g + 1]);
+    for (int g = threadIdx.x; g < G; g += blockDim.x) {
+        const double d = fmax(red[2 * g + 1], floor2 * amax);
+        w[g] = d > 0 ? 1.0 / d : 1.0;
+    }
+    __syncthreads();
     double a11 = 0, a12 = 0, a22 = 0, b1 = 0, b2 = 0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double wg = w[(i / NL) % G];
         const double x0 = s0[i], x1 = s1[i], x2 = s2[i], x3 = s3[i];
         const double d0 = x0 - x1, d1 = x1 - x2, d2 = x2 - x3;
         const double q1 = d0 - d1, q2 = d0 - d2;
-        a11 += q1 * q1; a12 += q1 * q2; a22 += q2 * q2; b1 += d0 * q1; b2 += d0 * q2;
+        a11 += wg * q1 * q1; a12 += wg * q1 * q2; a22 += wg * q2 * q2; b1 += wg * d0 * q1; b2 += wg * d0 * q2;
     }
     a11 = block_sum(a11, sh); a12 = block_sum(a12, sh); a22 = block_sum(a22, sh);
     b1 = block_sum(b1, sh); b2 = block_sum(b2, sh);
@@ -1453,6 +1467,24 @@ __global__ void k_combine3(long n, double c0, const real *__restrict__ x0, doubl
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     out[i] = (real)(c0 * (double)x0[i] + c1 * (double)x1[i] + c2 * (double)x2[i]);
+}
+
+// Ng extrapolation from the FP64 dot products d = (a11, a12, a22, b1, b2) of
+// the differences of the last four iterates: (a, b) solve the 2 x 2 normal
+// equations and out = (1 - a - b) s3 + a s2 + b s1; nothing is written when
+// the system is singular.  Every thread forms the same coefficients, so no
+// host round trip is needed.
+template <typename real>
+__global__ void k_ng_extrapolate(long n, const double *__restrict__ d, const real *__restrict__ s3,
+                                 const real *__restrict__ s2, const real *__restrict__ s1, real *__restrict__ out)
+{
+    const double a11 = d[0], a12 = d[1], a22 = d[2], b1 = d[3], b2 = d[4];
+    const double det = a11 * a22 - a12 * a12;
+    if (!(det > 1e-14 * a11 * a22) || !isfinite(det)) return;
+    const double a = (b1 * a22 - b2 * a12) / det, b = (b2 * a11 - b1 * a12) / det;
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    out[i] = (real)((1.0 - a - b) * (double)s3[i] + a * (double)s2[i] + b * (double)s1[i]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1625,11 +1657,18 @@ void launch_resid(long P, int G, int NL, const real *a, const real *b, double *r
     hipLaunchKernelGGL(k_resid_groups, dim3(2 * G), dim3(256), 0, st, P, G, rows, out);
 }
 template <typename real>
-void launch_ng_dots(long n, const real *s0, const real *s1, const real *s2, const real *s3, double *partial, int nblk,
-                    double *out, hipStream_t st)
+void launch_ng_dots(long n, int G, int NL, const double *red, double floor2, const real *s0, const real *s1,
+                    const real *s2, const real *s3, double *partial, int nblk, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_ng_partial<real>, dim3(nblk), dim3(256), 0, st, n, s0, s1, s2, s3, partial);
+    hipLaunchKernelGGL(k_ng_partial<real>, dim3(nblk), dim3(256), sizeof(double) * G, st, n, G, NL, red, floor2, s0,
+                       s1, s2, s3, partial);
     hipLaunchKernelGGL(k_sum_columns, dim3(5), dim3(256), 0, st, nblk, 5, partial, out);
+}
+template <typename real>
+void launch_ng_extrapolate(long n, const double *dots, const real *s3, const real *s2, const real *s1, real *out,
+                           hipStream_t st)
+{
+    hipLaunchKernelGGL(k_ng_extrapolate<real>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, dots, s3, s2, s1, out);
 }
 template <typename real>
 void launch_combine3(long n, double c0, const real *x0, double c1, const real *x1, double c2, const real *x2, real *out,
@@ -1737,8 +1776,10 @@ hipError_t set_lds_limits(size_t bytes)
                                           hipStream_t);                                                         \
     template void launch_resid<real>(long, int, int, const real *, const real *, double *, int, double *,       \
                                      hipStream_t);                                                              \
-    template void launch_ng_dots<real>(long, const real *, const real *, const real *, const real *, double *,  \
-                                       int, double *, hipStream_t);                                             \
+    template void launch_ng_dots<real>(long, int, int, const double *, double, const real *, const real *,     \
+                                       const real *, const real *, double *, int, double *, hipStream_t);       \
+    template void launch_ng_extrapolate<real>(long, const double *, const real *, const real *, const real *,      \
+                                              real *, hipStream_t);                                              \
     template void launch_combine3<real>(long, double, const real *, double, const real *, double, const real *, \
                                         real *, hipStream_t);                                                   \
     template void launch_rk_stage<real>(long, const real *, real *, real *, real *, int, int, real, hipStream_t);

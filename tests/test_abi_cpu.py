@@ -50,3 +50,12 @@ def test_null_problem_is_an_error(lib):
     assert lib.rrt_sweep(None, 0.0, None) == B.RRT_E_INVALID
     assert lib.rrt_synchronize(None) == B.RRT_E_INVALID
     lib.rrt_destroy(None)
+
+
+def test_batch_calls_validate_arguments(lib):
+    assert lib.rrt_batch_create(1 << 20, None) == B.RRT_E_INVALID
+    assert lib.rrt_batch_step(None, 1, None) == B.RRT_E_INVALID
+    assert lib.rrt_batch_admit(None, None, 1e-6, 10, 1) == B.RRT_E_INVALID
+    assert lib.rrt_batch_remove(None, None) == B.RRT_E_INVALID
+    lib.rrt_batch_destroy(None)
+    assert lib.rrt_device_bytes(None) == 0

@@ -677,16 +677,34 @@ def test_backward_euler_front_moves_at_c():
 # ---------------------------------------------------------------------------
 
 def test_ng_is_exact_for_a_rank_two_linear_iteration():
+    """Ng2 recovers the fixed point of x -> A x + b exactly when the error lies in
+    a two-dimensional invariant subspace, whatever the (per-group) weighting:
+    here on [points][groups][terms] arrays whose groups differ by 6 decades."""
     rs = np.random.default_rng(8)
-    U = np.linalg.qr(rs.normal(size=(30, 2)))[0]
-    A = U @ np.diag([0.9, -0.5]) @ U.T
-    b = rs.normal(size=30)
-    fixed = np.linalg.solve(np.eye(30) - A, b)
-    chain = [A @ rs.normal(size=30) + b]          # error already inside the range of A
+    shape = (5, 3, 2)
+    n = int(np.prod(shape))
+    scale = np.broadcast_to(np.array([1.0, 1e-3, 1e-6])[None, :, None], shape).ravel()
+    U = np.linalg.qr(rs.normal(size=(n, 2)))[0]
+    A = np.diag(scale) @ U @ np.diag([0.9, -0.5]) @ U.T @ np.diag(1 / scale)
+    b = rs.normal(size=n) * scale
+    fixed = np.linalg.solve(np.eye(n) - A, b)
+    chain = [A @ (rs.normal(size=n) * scale) + b]    # error already inside the range of A
     for _ in range(3):
         chain.append(A @ chain[-1] + b)
-    S = oracle.Oracle.ng_extrapolate(chain)
-    assert np.allclose(S, fixed, atol=1e-10)
+    S = oracle.Oracle.ng_extrapolate([c.reshape(shape) for c in chain])
+    assert np.allclose(S.ravel(), fixed, rtol=1e-9, atol=1e-15)
+
+
+def test_ng_weighting_is_invariant_to_group_scale():
+    """Each group enters the Ng dot products by its relative change: rescaling one
+    group of every chain member rescales that group of the result and leaves the
+    others unchanged."""
+    rs = np.random.default_rng(9)
+    chain = [rs.normal(size=(6, 3, 4)) + 3.0 for _ in range(4)]
+    c = np.array([1.0, 1e-8, 1.0])[None, :, None]
+    a = oracle.Oracle.ng_extrapolate(chain)
+    b = oracle.Oracle.ng_extrapolate([x * c for x in chain])
+    assert np.allclose(b, a * c, rtol=1e-10)
 
 
 def test_ng_reaches_the_plain_fixed_point():
@@ -696,3 +714,24 @@ def test_ng_reaches_the_plain_fixed_point():
     b = o.solve(tol=1e-12, max_iter=400, use_ng=True)
     assert b["iters"] <= a["iters"]
     assert np.allclose(a["I_lab"], b["I_lab"], rtol=1e-9, atol=1e-11)
+
+
+def test_floored_residual_only_changes_negligible_groups():
+    """The convergence test's per-group norm is floored at 1e-20 of the largest
+    group's.  Ordinary groups keep the plain relative residual that the C sweep
+    reports; a group 30 decades down, or one that underflowed to zero, is
+    measured against the floor."""
+    o = oracle.Oracle(W.random_medium(n=4, ng=3, lmax=2, nmu=4, nphi=8, seed=4))
+    S = o.initial_source()
+    _, _, S_new, r = o.sweep(S)
+    assert np.allclose(oracle.Oracle.floored_residual(S, S_new), r, rtol=1e-12)
+    rs = np.random.default_rng(3)
+    S_new = rs.uniform(0.5, 1.0, (5, 4, 9))
+    S_new[:, 2] *= 1e-30
+    S_new[:, 3] = 0.0
+    S_old = S_new * (1 + 1e-3 * rs.normal(size=S_new.shape))
+    S_old[:, 3] = 1e-40
+    out = oracle.Oracle.floored_residual(S_old, S_new)
+    floor = 1e-20 * np.sqrt(np.sum(S_new[:, :2] ** 2, axis=(0, 2)).max())
+    assert np.isclose(out[2], np.sqrt(np.sum((S_new[:, 2] - S_old[:, 2]) ** 2)) / floor, rtol=1e-12)
+    assert np.isclose(out[3], np.sqrt(np.sum(S_old[:, 3] ** 2)) / floor, rtol=1e-12)
