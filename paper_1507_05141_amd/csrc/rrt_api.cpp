@@ -719,8 +719,8 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
         if ((want == 1 || want == 2 || want == 4) && fits(want)) pr->Gc = want;
         for (int gc = 4; !pr->Gc && gc >= 1; gc /= 2)
             if (fits(gc)) pr->Gc = gc;
-        const size_t need_boost = pr->prec == RRT_FP64 ? rrt::boost_lds<double>(pr->K, pr->G)
-                                                       : rrt::boost_lds<float>(pr->K, pr->G);
+        const size_t need_boost = pr->prec == RRT_FP64 ? rrt::boost_lds<double>(pr->K, pr->G, pr->nmu)
+                                                       : rrt::boost_lds<float>(pr->K, pr->G, pr->nmu);
         if (!pr->Gc || plane > rrt::kTraceMaxPlane)
             return bail(fail(RRT_E_INVALID, "an x-y plane is too large for the ray-trace kernel on this device"));
         if (scatter == RRT_COMPTON && pr->esz * (size_t)pr->G * pr->NL > lim)

@@ -96,8 +96,8 @@ template <typename real> void launch_trace(const TraceArgs<real> &a, bool chi_ar
 template <typename real> void launch_boost(const BoostArgs<real> &a, hipStream_t st);
 template <typename real> void launch_unboost(const UnboostArgs<real> &a, hipStream_t st);
 template <typename real> size_t trace_lds(int nx, int ny, int Gc, int chi_per_point);
-template <typename real> size_t boost_lds(int K, int G);
-template <typename real> size_t unboost_lds(int K, int G);
+template <typename real> size_t boost_lds(int K, int G, int nmu);
+template <typename real> size_t unboost_lds(int K, int G, int nmu);
 template <typename real> void launch_chilab(const ChiLabArgs<real> &a, hipStream_t st);
 // S6 on the matrix cores (FP32) for NL <= 64; false when the shape is not covered (then use a library product)
 bool launch_do2sh_f32(long R, int K, int NL, const float *A, const float *B, float *C, hipStream_t st);

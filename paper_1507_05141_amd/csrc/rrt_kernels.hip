@@ -756,9 +756,11 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_bo
     const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x, KS = table_stride(K);
     const int lane = tid & 63, wave = tid >> 6;
     double *fbuf = reinterpret_cast<double *>(smem_raw);                // [4G]
-    real *F = reinterpret_cast<real *>(fbuf + 4 * G);                   // [G+2][KS]
+    double *smu = fbuf + 4 * G;                                         // [nmu] polar nodes
+    real *F = reinterpret_cast<real *>(smu + a.nmu);                    // [G+2][KS]
 
     const FreqL fl = stage_freq(a.fi, fbuf);
+    for (int i = tid; i < a.nmu; i += T) smu[i] = a.mu[i];
     double b[3];
     const bool moving = load_beta(a.beta, p, b);
     const real *__restrict__ src = a.S0 + (long)p * G * K;
@@ -786,7 +788,7 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_bo
             const double f = gam * (1.0 - gam / (gam + 1.0) * bn);
             double n0[3];
             for (int c = 0; c < 3; ++c) n0[c] = D * (n[c] - f * b[c]);
-            const Taps4<real> tp = taps4<real>(angle_taps<real>(a.mu, a.nmu, a.nphi, n0), K, a.nmu, a.nphi);
+            const Taps4<real> tp = taps4<real>(angle_taps<real>(smu, a.nmu, a.nphi, n0), K, a.nmu, a.nphi);
 #pragma unroll
             for (int i = 0; i < 4; ++i) { mine.c[i] = tp.c[i]; mine.w[i] = tp.w[i]; }
             if (a.fi.grey) {
@@ -890,9 +892,11 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_un
     if (p >= a.P) return;
     const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x, KS = table_stride(K);
     double *fbuf = reinterpret_cast<double *>(smem_raw);                // [4G]
-    real *F = reinterpret_cast<real *>(fbuf + 4 * G);                   // [G+2][KS]
+    double *smu = fbuf + 4 * G;                                         // [nmu] polar nodes
+    real *F = reinterpret_cast<real *>(smu + a.nmu);                    // [G+2][KS]
 
     const FreqL fl = stage_freq(a.fi, fbuf);
+    for (int i = tid; i < a.nmu; i += T) smu[i] = a.mu[i];
     double b[3];
     const bool moving = load_beta(a.beta, p, b);
     const float rG = 1.0f / (float)G;
@@ -919,7 +923,7 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_un
         const double f = gam * (1.0 + gam / (gam + 1.0) * bn0);
         double n[3];
         for (int c = 0; c < 3; ++c) n[c] = (n0[c] + f * b[c]) / Dp;
-        const Taps4<real> tp = taps4<real>(angle_taps<real>(a.mu, a.nmu, a.nphi, n), K, a.nmu, a.nphi);
+        const Taps4<real> tp = taps4<real>(angle_taps<real>(smu, a.nmu, a.nphi, n), K, a.nmu, a.nphi);
         if (a.fi.grey) {
             const double D2 = Dp * Dp;
             out[j] = (real)((double)tap_row(F + KS, tp) / (D2 * D2));
@@ -1544,14 +1548,14 @@ void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st)
 #undef RRT_TRACE_CASE
 }
 template <typename real>
-size_t boost_lds(int K, int G)
+size_t boost_lds(int K, int G, int nmu)
 {
-    return 4 * sizeof(double) * G + sizeof(real) * (G + 2) * (size_t)((K + 2) | 1);
+    return sizeof(double) * (4 * (size_t)G + nmu) + sizeof(real) * (G + 2) * (size_t)((K + 2) | 1);
 }
 template <typename real>
-size_t unboost_lds(int K, int G)
+size_t unboost_lds(int K, int G, int nmu)
 {
-    return 4 * sizeof(double) * G + sizeof(real) * (G + 2) * (size_t)((K + 2) | 1);
+    return sizeof(double) * (4 * (size_t)G + nmu) + sizeof(real) * (G + 2) * (size_t)((K + 2) | 1);
 }
 template <typename real>
 void launch_chilab(const ChiLabArgs<real> &a, hipStream_t st)
@@ -1564,13 +1568,13 @@ template <typename real>
 void launch_boost(const BoostArgs<real> &a, hipStream_t st)
 {
     const unsigned nb = (unsigned)(8 * ((a.P + 7) / 8));
-    hipLaunchKernelGGL(k_boost<real>, dim3(nb), dim3(kRemapThreads), boost_lds<real>(a.K, a.fi.G), st, a);
+    hipLaunchKernelGGL(k_boost<real>, dim3(nb), dim3(kRemapThreads), boost_lds<real>(a.K, a.fi.G, a.nmu), st, a);
 }
 template <typename real>
 void launch_unboost(const UnboostArgs<real> &a, hipStream_t st)
 {
     const unsigned nb = (unsigned)(8 * ((a.P + 7) / 8));
-    hipLaunchKernelGGL(k_unboost<real>, dim3(nb), dim3(kRemapThreads), unboost_lds<real>(a.K, a.fi.G), st, a);
+    hipLaunchKernelGGL(k_unboost<real>, dim3(nb), dim3(kRemapThreads), unboost_lds<real>(a.K, a.fi.G, a.nmu), st, a);
 }
 size_t do2sh_lds(int NL) { return sizeof(float) * 64 * (size_t)(((NL + 15) / 16) * 16 + 4); }
 
@@ -1765,8 +1769,8 @@ hipError_t set_lds_limits(size_t bytes)
     template void launch_boost<real>(const BoostArgs<real> &, hipStream_t);                                     \
     template void launch_unboost<real>(const UnboostArgs<real> &, hipStream_t);                                 \
     template size_t trace_lds<real>(int, int, int, int);                                                       \
-    template size_t boost_lds<real>(int, int);                                                                 \
-    template size_t unboost_lds<real>(int, int);                                                               \
+    template size_t boost_lds<real>(int, int, int);                                                                 \
+    template size_t unboost_lds<real>(int, int, int);                                                               \
     template void launch_chilab<real>(const ChiLabArgs<real> &, hipStream_t);                                   \
     template void launch_source<real>(const SourceArgs<real> &, hipStream_t);                                   \
     template void launch_chi0<real>(long, int, const real *, const real *, const real *, real *, hipStream_t);  \
