@@ -971,7 +971,7 @@ __global__ void __launch_bounds__(256) k_chilab(ChiLabArgs<real> a)
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <int NT>
+template <int NT, int RT>
 __global__ void __launch_bounds__(256) k_do2sh_f32(long R, int K, int NL, const float *__restrict__ A,
                                                    const float *__restrict__ B, float *__restrict__ C)
 {
@@ -979,25 +979,31 @@ __global__ void __launch_bounds__(256) k_do2sh_f32(long R, int K, int NL, const 
     extern __shared__ unsigned char smem_raw[];
     float *Bs = reinterpret_cast<float *>(smem_raw);                   // [KC][NLP]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
-    const long r0 = (long)xcd_item(gridDim.x) * 64 + wave * 16;
-    const float *__restrict__ Arow = A + min(r0 + lr, R - 1) * (long)K;
+    const long r0 = (long)xcd_item(gridDim.x) * (64 * RT) + wave * (16 * RT);
+    const float *Arow[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t) Arow[t] = A + min(r0 + 16 * t + lr, R - 1) * (long)K;
     const bool vec = (K & 3) == 0;
-    f32x4 acc[NT];
+    f32x4 acc[RT][NT];
 #pragma unroll
-    for (int c = 0; c < NT; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    for (int t = 0; t < RT; ++t)
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
     for (int kc = 0; kc < K; kc += KC) {
-        float a[4][4];
+        float a[RT][4][4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int k = kc + 16 * t + 4 * lg;
-            if (vec && k + 3 < K) {
-                const f32x4 v = *reinterpret_cast<const f32x4 *>(Arow + k);
-                a[t][0] = v.x; a[t][1] = v.y; a[t][2] = v.z; a[t][3] = v.w;
-            } else {
+        for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-                for (int i = 0; i < 4; ++i) a[t][i] = (k + i < K) ? Arow[k + i] : 0.f;
+            for (int t = 0; t < 4; ++t) {
+                const int k = kc + 16 * t + 4 * lg;
+                if (vec && k + 3 < K) {
+                    const f32x4 v = *reinterpret_cast<const f32x4 *>(Arow[rt] + k);
+                    a[rt][t][0] = v.x; a[rt][t][1] = v.y; a[rt][t][2] = v.z; a[rt][t][3] = v.w;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) a[rt][t][i] = (k + i < K) ? Arow[rt][k + i] : 0.f;
+                }
             }
-        }
         __syncthreads();                                                // the previous chunk's B reads are done
         for (int i = threadIdx.x; i < KC * NC; i += blockDim.x) {
             const int kk = i / NC, c = i - kk * NC;
@@ -1010,21 +1016,27 @@ __global__ void __launch_bounds__(256) k_do2sh_f32(long R, int K, int NL, const 
             for (int s = 0; s < 4; ++s) {
                 const float *brow = Bs + (16 * t + 4 * lg + s) * NLP + lr;
 #pragma unroll
-                for (int c = 0; c < NT; ++c)
-                    acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[t][s], brow[16 * c], acc[c], 0, 0, 0);
+                for (int c = 0; c < NT; ++c) {
+                    const float bv = brow[16 * c];
+#pragma unroll
+                    for (int rt = 0; rt < RT; ++rt)
+                        acc[rt][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][t][s], bv, acc[rt][c], 0, 0, 0);
+                }
             }
         }
     }
     // lane holds rows 4 lg + i, column 16 c + lr of each tile
 #pragma unroll
-    for (int c = 0; c < NT; ++c) {
-        const int col = 16 * c + lr;
+    for (int rt = 0; rt < RT; ++rt)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const long r = r0 + 4 * lg + i;
-            if (r < R && col < NL) C[r * NL + col] = acc[c][i];
+        for (int c = 0; c < NT; ++c) {
+            const int col = 16 * c + lr;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const long r = r0 + 16 * rt + 4 * lg + i;
+                if (r < R && col < NL) C[r * NL + col] = acc[rt][c][i];
+            }
         }
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1580,15 +1592,21 @@ size_t do2sh_lds(int NL) { return sizeof(float) * 64 * (size_t)(((NL + 15) / 16)
 
 bool launch_do2sh_f32(long R, int K, int NL, const float *A, const float *B, float *C, hipStream_t st)
 {
-    const long nb = (R + 63) / 64;
-    if (nb > 0x7fffffffL) return false;
-    const dim3 grid((unsigned)(8 * ((nb + 7) / 8))), block(256);
+    const dim3 block(256);
     const size_t sm = do2sh_lds(NL);
     // NL up to 64 (L <= 7); at L = 15 the library product is faster (measured on MI355X)
-    if (NL <= 16) hipLaunchKernelGGL(k_do2sh_f32<1>, grid, block, sm, st, R, K, NL, A, B, C);
-    else if (NL <= 64) hipLaunchKernelGGL(k_do2sh_f32<4>, grid, block, sm, st, R, K, NL, A, B, C);
-    else return false;
-    return true;
+#define RRT_DO2SH32(NT, RT)                                                                                   \
+    {                                                                                                         \
+        const long nb = (R + 64 * RT - 1) / (64 * RT);                                                        \
+        if (nb > 0x7fffffffL) return false;                                                                  \
+        hipLaunchKernelGGL((k_do2sh_f32<NT, RT>), dim3((unsigned)(8 * ((nb + 7) / 8))), block, sm, st, R, K, NL, A, B, \
+                           C);                                                                               \
+        return true;                                                                                          \
+    }
+    if (NL <= 16) RRT_DO2SH32(1, 4)
+    if (NL <= 64) RRT_DO2SH32(4, 2)
+#undef RRT_DO2SH32
+    return false;
 }
 
 bool launch_do2sh_f16(long R, int K, int NL, const float *A, const _Float16 *WYh, const _Float16 *WYl, float *C,
@@ -1754,8 +1772,8 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_sh2do_f16<2>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<4>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<8>),
-                         reinterpret_cast<const void *>(&k_do2sh_f32<1>),
-                         reinterpret_cast<const void *>(&k_do2sh_f32<4>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32<1, 4>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32<4, 2>),
                          reinterpret_cast<const void *>(&k_source_compton<double>)};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
