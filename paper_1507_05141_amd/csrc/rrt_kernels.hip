@@ -764,8 +764,20 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_bo
     double b[3];
     const bool moving = load_beta(a.beta, p, b);
     const real *__restrict__ src = a.S0 + (long)p * G * K;
-    for (int g = 0; g < G; ++g)
-        for (int j = tid; j < K; j += T) F[(g + 1) * KS + j] = src[g * K + j];
+    if ((K & 3) == 0) {
+        // 16-byte loads: four ordinates of one group per lane
+        using P4 = Pack<real, 4>;
+        const int K4 = K >> 2;
+        for (int i = tid; i < G * K4; i += T) {
+            const int g = i / K4, j = (i - g * K4) * 4;
+            const P4 v = *reinterpret_cast<const P4 *>(src + (long)g * K + j);
+            real *row = F + (g + 1) * KS + j;
+            row[0] = v.v[0]; row[1] = v.v[1]; row[2] = v.v[2]; row[3] = v.v[3];
+        }
+    } else {
+        for (int g = 0; g < G; ++g)
+            for (int j = tid; j < K; j += T) F[(g + 1) * KS + j] = src[g * K + j];
+    }
     if (moving) table_ghosts(F, G, KS);
     __syncthreads();
     if (moving) {
@@ -899,10 +911,25 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_un
     for (int i = tid; i < a.nmu; i += T) smu[i] = a.mu[i];
     double b[3];
     const bool moving = load_beta(a.beta, p, b);
-    const float rG = 1.0f / (float)G;
-    for (int idx = tid; idx < K * G; idx += T) {
-        const int k = (int)(((float)idx + 0.5f) * rG), g = idx - k * G;
-        F[(g + 1) * KS + k] = a.Ilab[((long)k * a.P + p) * G + g];
+    if ((G & 3) == 0) {
+        // 16-byte loads: four groups of one ordinate per lane, written down a table column
+        using P4 = Pack<real, 4>;
+        const int G4 = G >> 2;
+        const float rG4 = 1.0f / (float)G4;
+        for (int idx = tid; idx < K * G4; idx += T) {
+            const int k = (int)(((float)idx + 0.5f) * rG4), g = (idx - k * G4) * 4;
+            const P4 v = *reinterpret_cast<const P4 *>(a.Ilab + ((long)k * a.P + p) * G + g);
+            F[(g + 1) * KS + k] = v.v[0];
+            F[(g + 2) * KS + k] = v.v[1];
+            F[(g + 3) * KS + k] = v.v[2];
+            F[(g + 4) * KS + k] = v.v[3];
+        }
+    } else {
+        const float rG = 1.0f / (float)G;
+        for (int idx = tid; idx < K * G; idx += T) {
+            const int k = (int)(((float)idx + 0.5f) * rG), g = idx - k * G;
+            F[(g + 1) * KS + k] = a.Ilab[((long)k * a.P + p) * G + g];
+        }
     }
     real *__restrict__ out = a.I0 + (long)p * G * K;
     if (!moving) {
