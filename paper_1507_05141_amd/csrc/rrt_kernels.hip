@@ -727,6 +727,7 @@ template <typename real> struct OrdRemap {
     int s;              // uniform groups: position shift (kAllGhost: every position beyond the groups)
     real clo, chi;      // uniform groups: weights with the nu^3 ratios
     double x;           // grey: D^4; general groups: ln(nu0/nu) = -ln D
+    real kap;           // lab extinction of the ordinate when it is the same for every group
 };
 constexpr int kAllGhost = -(1 << 30);
 
@@ -743,6 +744,7 @@ __device__ __forceinline__ OrdRemap<real> shfl_remap(const OrdRemap<real> &r, in
     o.clo = __shfl(r.clo, src, 64);
     o.chi = __shfl(r.chi, src, 64);
     o.x = __shfl(r.x, src, 64);
+    o.kap = __shfl(r.kap, src, 64);
     return o;
 }
 
@@ -793,6 +795,7 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_bo
         // set-up of ordinate kb + lane
         OrdRemap<real> mine{};
         const int km = kb + lane;
+        if (a.chi_grey && km < K) mine.kap = a.chilab[(long)km * a.P + p];
         if (moving && km < K) {
             const double n[3] = {a.dir[4 * km], a.dir[4 * km + 1], a.dir[4 * km + 2]};
             const double bn = b[0] * n[0] + b[1] * n[1] + b[2] * n[2];
@@ -839,7 +842,7 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_bo
                     ip[0] = a.Iprev[o];
                 }
             }
-            const real chig = a.chi_grey ? a.chilab[(long)k * a.P + p] : real(0);
+            const real chig = r.kap;
             const Taps4<real> tp{{r.c[0], r.c[1], r.c[2], r.c[3]}, {r.w[0], r.w[1], r.w[2], r.w[3]}};
             if (!moving) {
 #pragma unroll
