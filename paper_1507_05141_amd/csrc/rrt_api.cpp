@@ -75,6 +75,7 @@ struct rrt_problem {
     void *d_kappa = nullptr, *d_sigma = nullptr, *d_bnu = nullptr, *d_chi0 = nullptr;
     double *d_beta = nullptr, *d_gam = nullptr;
     void *d_chilab = nullptr;
+    void *d_plan = nullptr;                         // remap entries: [p][k] boost, then [p][j] inverse
     int grey_chi = 0;
     void *d_bc[2] = {nullptr, nullptr};
     // state and work arrays
@@ -275,13 +276,20 @@ struct Engine {
         if (s) return s;
         rrt::BoostArgs<real> b;
         b.P = pr->P; b.K = pr->K; b.nmu = pr->nmu; b.nphi = pr->nphi; b.fi = pr->fi;
-        b.dir = pr->d_dir; b.mu = pr->d_mu; b.S0 = R(pr->d_co); b.Iprev = static_cast<const real *>(Iprev);
+        b.dir = pr->d_dir; b.mu = pr->d_mu; b.plan = plan(0); b.S0 = R(pr->d_co); b.Iprev = static_cast<const real *>(Iprev);
         b.inv_cdt = (real)inv_cdt; b.chilab = R(pr->d_chilab); b.chi_grey = pr->grey_chi;
         b.beta = pr->d_beta; b.gam = pr->d_gam; b.St = R(pr->d_St);
         prof_begin(pr, KI_BOOST);
         rrt::launch_boost<real>(b, pr->stream);
         prof_end(pr, KI_BOOST);
         return check_launch();
+    }
+
+    // remap entries of the boost (0) or of the inverse map (1)
+    const rrt::RemapEntry<real> *plan(int which) const
+    {
+        const auto *e = static_cast<const rrt::RemapEntry<real> *>(pr->d_plan);
+        return e ? e + (size_t)which * pr->P * pr->K : nullptr;
     }
 
     // S4 (chi~ from the medium, or from d_Xt when chi_array)
@@ -302,7 +310,7 @@ struct Engine {
     {
         rrt::UnboostArgs<real> u;
         u.P = pr->P; u.K = pr->K; u.nmu = pr->nmu; u.nphi = pr->nphi; u.fi = pr->fi;
-        u.dir = pr->d_dir; u.mu = pr->d_mu; u.Ilab = static_cast<const real *>(Ilab);
+        u.dir = pr->d_dir; u.mu = pr->d_mu; u.plan = plan(1); u.Ilab = static_cast<const real *>(Ilab);
         u.beta = pr->d_beta; u.gam = pr->d_gam; u.I0 = R(pr->d_co);
         prof_begin(pr, KI_UNBOOST);
         rrt::launch_unboost<real>(u, pr->stream);
@@ -622,6 +630,7 @@ size_t footprint(const rrt_grid *g, const rrt_groups *gr, const rrt_angles *a, i
     if (time_dep) total += 2 * dob;                  // stage input, accumulator
     if (use_ng) total += 4 * sh;                     // Ng chain
     total += P * (3 * G + 1) * esz + 4 * P * 8;     // fields, chi0, beta, Gamma
+    total += 2 * P * K * 8 * esz;                    // remap plan of a moving medium (two entries per point and ordinate)
     total += 2 * (size_t)g->nx * g->ny * K * G * esz;  // boundaries
     total += 16 * P * G + (1 << 20);                 // residual partial sums, tables
     return total;
@@ -652,7 +661,7 @@ void rrt_destroy(rrt_problem *pr)
     if (pr->blas) (void)rocblas_destroy_handle(pr->blas);
     void *bufs[] = {pr->d_dir, pr->d_mu, pr->d_lnc, pr->d_nu3, pr->d_inv_nu3, pr->d_inv_dc, pr->d_geo, pr->d_Yt, pr->d_WY,
                     pr->d_Y16, pr->d_WYt16,
-                    pr->d_A, pr->d_sg, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_gam, pr->d_chi0, pr->d_chilab, pr->d_bc[0], pr->d_bc[1],
+                    pr->d_A, pr->d_sg, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_gam, pr->d_chi0, pr->d_chilab, pr->d_plan, pr->d_bc[0], pr->d_bc[1],
                     pr->d_S, pr->d_Snew, pr->d_Ilm, pr->d_co, pr->d_St, pr->d_Xt, pr->d_Ilab, pr->d_I, pr->d_Iin,
                     pr->d_acc, pr->d_chain[0], pr->d_chain[1], pr->d_chain[2], pr->d_chain[3], pr->d_partial, pr->d_red};
     for (void *b : bufs)
@@ -719,8 +728,8 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
         if ((want == 1 || want == 2 || want == 4) && fits(want)) pr->Gc = want;
         for (int gc = 4; !pr->Gc && gc >= 1; gc /= 2)
             if (fits(gc)) pr->Gc = gc;
-        const size_t need_boost = pr->prec == RRT_FP64 ? rrt::boost_lds<double>(pr->K, pr->G, pr->nmu)
-                                                       : rrt::boost_lds<float>(pr->K, pr->G, pr->nmu);
+        const size_t need_boost = pr->prec == RRT_FP64 ? rrt::boost_lds<double>(pr->K, pr->G)
+                                                       : rrt::boost_lds<float>(pr->K, pr->G);
         if (!pr->Gc || plane > rrt::kTraceMaxPlane)
             return bail(fail(RRT_E_INVALID, "an x-y plane is too large for the ray-trace kernel on this device"));
         if (scatter == RRT_COMPTON && pr->esz * (size_t)pr->G * pr->NL > lim)
@@ -956,6 +965,21 @@ rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *si
         rrt::launch_chilab<real>(c, pr->stream);
     };
     if (pr->prec == RRT_FP64) chilab(0.0); else chilab(0.0f);
+    // remap plan of the velocity field
+    if (beta) {
+        const size_t esz = pr->prec == RRT_FP64 ? sizeof(rrt::RemapEntry<double>) : sizeof(rrt::RemapEntry<float>);
+        if ((s = pr_alloc(pr, &pr->d_plan, 2 * P * pr->K * esz))) return s;
+        auto plan = [&](auto tag) {
+            using real = decltype(tag);
+            rrt::PlanArgs<real> a;
+            a.P = (long)P; a.K = pr->K; a.nmu = pr->nmu; a.nphi = pr->nphi; a.fi = pr->fi;
+            a.dir = pr->d_dir; a.mu = pr->d_mu; a.beta = pr->d_beta; a.gam = pr->d_gam;
+            a.boost = static_cast<rrt::RemapEntry<real> *>(pr->d_plan);
+            a.unboost = a.boost + P * pr->K;
+            rrt::launch_remap_plan<real>(a, pr->stream);
+        };
+        if (pr->prec == RRT_FP64) plan(0.0); else plan(0.0f);
+    }
     HIPCHK(hipGetLastError());
     HIPCHK(hipStreamSynchronize(pr->stream));
     pr->medium_set = true;

@@ -50,11 +50,38 @@ template <typename real> struct TraceArgs {
     real *I;                    // [k][p][g]
 };
 
+// Remap of one ordinate at one moving point, fixed by the medium (velocity
+// field) and computed once per medium: the four bilinear angle taps of the
+// direction in the other frame (ring a0 = (ab & 0xffff) - 1 with a1 = a0 + 1,
+// azimuth b0 = ab >> 16 with b1 = b0 + 1 mod nphi; rings -1 and nmu are the
+// poles) with their weights w, and the frequency shift: for a single group
+// u = D^4 (to the lab) or D'^-4 (to the comoving frame); for groups uniform in
+// ln(nu), position shift s and the two weights u, v with the nu^3 ratios
+// (s = kAllGhost when every target lies beyond the groups); otherwise the
+// ln(nu) shift u + v split into a high and a low part.
+template <typename real> struct alignas(16) RemapEntry {
+    int ab, s;
+    real w[4];
+    real u, v;
+};
+constexpr int kAllGhost = -(1 << 30);
+
+template <typename real> struct PlanArgs {
+    long P;
+    int K, nmu, nphi;
+    FreqInfo fi;
+    const double *dir, *mu;      // [K][4], [nmu]
+    const double *beta, *gam;    // [P][3], [P]
+    RemapEntry<real> *boost;     // [p][k]: comoving taps of lab ordinate k
+    RemapEntry<real> *unboost;   // [p][j]: lab taps of comoving ordinate j
+};
+
 template <typename real> struct BoostArgs {
     long P;
     int K, nmu, nphi;
     FreqInfo fi;
     const double *dir, *mu;
+    const RemapEntry<real> *plan;  // [p][k]
     const real *S0;             // comoving source on the ordinates [p][g][j]
     const real *Iprev;          // [k][p][g] or NULL
     real inv_cdt;
@@ -80,6 +107,7 @@ template <typename real> struct UnboostArgs {
     int K, nmu, nphi;
     FreqInfo fi;
     const double *dir, *mu;
+    const RemapEntry<real> *plan;  // [p][j]
     const real *Ilab;           // [k][p][g]
     const double *beta, *gam;
     real *I0;                   // [p][g][j]
@@ -96,8 +124,9 @@ template <typename real> void launch_trace(const TraceArgs<real> &a, bool chi_ar
 template <typename real> void launch_boost(const BoostArgs<real> &a, hipStream_t st);
 template <typename real> void launch_unboost(const UnboostArgs<real> &a, hipStream_t st);
 template <typename real> size_t trace_lds(int nx, int ny, int Gc, int chi_per_point);
-template <typename real> size_t boost_lds(int K, int G, int nmu);
-template <typename real> size_t unboost_lds(int K, int G, int nmu);
+template <typename real> size_t boost_lds(int K, int G);
+template <typename real> size_t unboost_lds(int K, int G);
+template <typename real> void launch_remap_plan(const PlanArgs<real> &a, hipStream_t st);
 template <typename real> void launch_chilab(const ChiLabArgs<real> &a, hipStream_t st);
 // S6 on the matrix cores (FP32) for NL <= 64; false when the shape is not covered (then use a library product)
 bool launch_do2sh_f32(long R, int K, int NL, const float *A, const float *B, float *C, hipStream_t st);

@@ -648,32 +648,24 @@ __device__ __forceinline__ void table_ghosts(real *F, int G, int KS)
 // frequency of group g sits at fractional group position g + y for every g, so
 // the invariant F/nu^3 is interpolated between groups g + s and g + s + 1
 // (s = floor y, weight f = y - s), positions beyond the groups reading the
-// zero ghost rows, and nu_g^3 / nu_{g'}^3 = exp(3 delta (g - g')).
-// out[g * ostride] receives the remapped (lab or comoving) value.  In FP32 the
-// exponent is capped at 80 so that a factor multiplying a ghost stays finite
-// (only a group set spanning more than ~12 decades reaches the cap).
+// zero ghost rows, and nu_g^3 / nu_{g'}^3 = exp(3 delta (g - g')): the value of
+// group g is clo A(g + s) + chi A(g + s + 1), A the angle remap of a table row.
+// In FP32 the exponent is capped at 80 so that a factor multiplying a ghost
+// stays finite (only a group set spanning more than ~12 decades reaches the cap).
 template <typename real>
-__device__ __forceinline__ void uniform_remap(const real *F, int KS, int G, const Taps4<real> &tp, double y,
-                                              double delta, real *out, long ostride)
+__device__ __forceinline__ void uniform_shift(double y, double delta, int G, int &s, real &clo, real &chi)
 {
     const double sf = floor(y);
     if (sf <= -(double)(G + 1) || sf >= (double)G) {      // every position beyond the groups
-        for (int g = 0; g < G; ++g) out[g * ostride] = real(0);
+        s = kAllGhost; clo = real(0); chi = real(0);
         return;
     }
     const real f = (real)(y - sf);
-    const int s = (int)sf;
     const real cap = sizeof(real) == 4 ? real(80) : real(700);
     const real e3 = real(-3.0 * delta);
-    const real clo = (real(1) - f) * exp(fmin(e3 * (real)sf, cap));
-    const real chi = f * exp(fmin(e3 * (real)(sf + 1.0), cap));
-    auto A = [&](int gp) -> real { return tap_row(F + (min(max(gp, -1), G) + 1) * KS, tp); };
-    real acur = A(s);
-    for (int g = 0; g < G; ++g) {
-        const real anext = A(g + s + 1);
-        out[g * ostride] = clo * acur + chi * anext;
-        acur = anext;
-    }
+    s = (int)sf;
+    clo = (real(1) - f) * exp(fmin(e3 * (real)sf, cap));
+    chi = f * exp(fmin(e3 * (real)(sf + 1.0), cap));
 }
 
 // remap of every group for non-uniform groups: frequency x = ln(nu_g) + lnD
@@ -709,47 +701,134 @@ __device__ __forceinline__ double time_terms(double chi, double S, double ip, do
 }
 
 // ---------------------------------------------------------------------------
+// Remap plan of a medium: for every (point, ordinate) the taps and frequency
+// shift of the boost (lab ordinate k -> comoving direction n0 of Eq. 8 and
+// frequency nu/D of Eq. 7) and of the inverse map (comoving ordinate j -> lab
+// direction and frequency D' nu, D' = Gamma (1 + beta.n0)).  They depend on
+// the velocity field only, so they are computed once per medium.
+// ---------------------------------------------------------------------------
+template <typename real>
+__device__ __forceinline__ RemapEntry<real> remap_entry(const double *mu, int nmu, int nphi, const double nt[3])
+{
+    const AngleTaps t = angle_taps<real>(mu, nmu, nphi, nt);
+    RemapEntry<real> e{};
+    e.ab = (t.a0 + 1) | (t.b0 << 16);
+    const double um = 1.0 - t.wmu, up = 1.0 - t.wphi;
+    e.w[0] = (real)(um * up); e.w[1] = (real)(um * t.wphi);
+    e.w[2] = (real)(t.wmu * up); e.w[3] = (real)(t.wmu * t.wphi);
+    return e;
+}
+
+template <typename real>
+__device__ __forceinline__ void entry_freq(RemapEntry<real> &e, const FreqInfo &fi, double D, bool inverse)
+{
+    if (fi.grey) {
+        const double D2 = D * D;
+        e.u = (real)(inverse ? 1.0 / (D2 * D2) : D2 * D2);
+    } else if (fi.uniform) {
+        // positions of the target frequencies nu/D (boost) or D' nu (inverse)
+        const double lr = (double)log((real)D) * fi.inv_delta;
+        uniform_shift<real>(inverse ? lr : -lr, fi.delta, fi.G, e.s, e.u, e.v);
+    } else {
+        const double x = inverse ? log(D) : -log(D);
+        e.u = (real)x;
+        e.v = (real)(x - (double)e.u);
+    }
+}
+
+template <typename real>
+__global__ void __launch_bounds__(256) k_remap_plan(PlanArgs<real> a)
+{
+    const long n = a.P * a.K;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const long p = i / a.K;
+        const int k = (int)(i - p * a.K);
+        double b[3];
+        if (!load_beta(a.beta, p, b)) continue;
+        const double gam = a.gam[p];
+        const double n[3] = {a.dir[4 * k], a.dir[4 * k + 1], a.dir[4 * k + 2]};
+        const double bn = b[0] * n[0] + b[1] * n[1] + b[2] * n[2];
+        {
+            // lab ordinate k seen from the comoving frame (Eqs. 7-8)
+            const double D = 1.0 / inv_doppler(b, gam, n);
+            const double f = gam * (1.0 - gam / (gam + 1.0) * bn);
+            double n0[3];
+            for (int c = 0; c < 3; ++c) n0[c] = D * (n[c] - f * b[c]);
+            RemapEntry<real> e = remap_entry<real>(a.mu, a.nmu, a.nphi, n0);
+            entry_freq(e, a.fi, D, false);
+            a.boost[i] = e;
+        }
+        {
+            // comoving ordinate k seen from the lab frame (the inverse maps)
+            const double Dp = gam * (1.0 + bn);
+            const double f = gam * (1.0 + gam / (gam + 1.0) * bn);
+            double nl[3];
+            for (int c = 0; c < 3; ++c) nl[c] = (n[c] + f * b[c]) / Dp;
+            RemapEntry<real> e = remap_entry<real>(a.mu, a.nmu, a.nphi, nl);
+            entry_freq(e, a.fi, Dp, true);
+            a.unboost[i] = e;
+        }
+    }
+}
+
+// the four table columns of an entry's angle taps
+template <typename real>
+__device__ __forceinline__ Taps4<real> entry_taps(int ab, const real w[4], int K, int nmu, int nphi)
+{
+    const int a0 = (ab & 0xffff) - 1, b0 = ab >> 16;
+    const int b1 = b0 + 1 == nphi ? 0 : b0 + 1;
+    auto col = [&](int ring, int b) { return ring < 0 ? K : (ring >= nmu ? K + 1 : ring * nphi + b); };
+    Taps4<real> t;
+    t.c[0] = col(a0, b0); t.c[1] = col(a0, b1); t.c[2] = col(a0 + 1, b0); t.c[3] = col(a0 + 1, b1);
+    t.w[0] = w[0]; t.w[1] = w[1]; t.w[2] = w[2]; t.w[3] = w[3];
+    return t;
+}
+
+// stage rows [g][j] of a point's ordinate values (n4 runs of four values,
+// K4 runs per row) into the table, four 16-byte loads per lane in flight
+template <typename real>
+__device__ __forceinline__ void stage_rows(const real *__restrict__ src, real *F, int G, int K, int KS)
+{
+    using P4 = Pack<real, 4>;
+    const int T = blockDim.x, tid = threadIdx.x, K4 = K >> 2, n4 = G * K4;
+    for (int i0 = tid; i0 < n4; i0 += 4 * T) {
+        P4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * T;
+            if (i < n4) {
+                const int g = i / K4, j = (i - g * K4) * 4;
+                v[u] = *reinterpret_cast<const P4 *>(src + (long)g * K + j);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int i = i0 + u * T;
+            if (i < n4) {
+                const int g = i / K4, j = (i - g * K4) * 4;
+                real *row = F + (g + 1) * KS + j;
+                row[0] = v[u].v[0]; row[1] = v[u].v[1]; row[2] = v[u].v[2]; row[3] = v[u].v[3];
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // S3: comoving ordinates -> lab ordinates.  The point's comoving source
 // S0[g][j] (from the SH -> ordinate product) is staged in the table; the lab
 // source of ordinate k is the bilinear (angle) x linear in ln(nu) remap of the
 // invariant S0/nu^3 at the comoving direction n0 (Eq. 8) and frequency nu/D
 // (Eq. 7) of that ray, times nu^3; then the implicit time terms of Eqs. 5-6
 // with the lab extinction chi_lab precomputed per medium.  Output S~[k][p][g].
-// Each wave takes 64 ordinates: every lane first sets up the remap of one
-// ordinate (taps, Doppler shift), then the lanes run over (ordinate, run of W
-// groups) pairs, W = 4 when G allows 16-byte runs, fetching the set-up of
-// their ordinate from the lane that made it; consecutive lanes so write
-// consecutive groups of one ordinate.
+// Each wave takes 64 ordinates: lane l loads the remap entry of ordinate
+// kb + l, then the lanes run over (ordinate, run of W groups) items, W = 4 when
+// G allows 16-byte runs, fetching their ordinate's entry from the lane that
+// loaded it; consecutive lanes so write consecutive groups of one ordinate.
+// The entries and the time-term inputs of a lane's first four items are
+// loaded before the table is staged.
 // ---------------------------------------------------------------------------
-template <typename real> struct OrdRemap {
-    int c[4];
-    real w[4];
-    int s;              // uniform groups: position shift (kAllGhost: every position beyond the groups)
-    real clo, chi;      // uniform groups: weights with the nu^3 ratios
-    double x;           // grey: D^4; general groups: ln(nu0/nu) = -ln D
-    real kap;           // lab extinction of the ordinate when it is the same for every group
-};
-constexpr int kAllGhost = -(1 << 30);
-
 template <typename real>
-__device__ __forceinline__ OrdRemap<real> shfl_remap(const OrdRemap<real> &r, int src)
-{
-    OrdRemap<real> o;
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-        o.c[i] = __shfl(r.c[i], src, 64);
-        o.w[i] = __shfl(r.w[i], src, 64);
-    }
-    o.s = __shfl(r.s, src, 64);
-    o.clo = __shfl(r.clo, src, 64);
-    o.chi = __shfl(r.chi, src, 64);
-    o.x = __shfl(r.x, src, 64);
-    o.kap = __shfl(r.kap, src, 64);
-    return o;
-}
-
-template <typename real>
-__global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_boost(BoostArgs<real> a)
+__global__ void __launch_bounds__(kRemapThreads, 4) k_boost(BoostArgs<real> a)
 {
     using P4 = Pack<real, 4>;
     extern __shared__ unsigned char smem_raw[];
@@ -758,24 +837,47 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_bo
     const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x, KS = table_stride(K);
     const int lane = tid & 63, wave = tid >> 6;
     double *fbuf = reinterpret_cast<double *>(smem_raw);                // [4G]
-    double *smu = fbuf + 4 * G;                                         // [nmu] polar nodes
-    real *F = reinterpret_cast<real *>(smu + a.nmu);                    // [G+2][KS]
+    real *F = reinterpret_cast<real *>(fbuf + 4 * G);                   // [G+2][KS]
 
     const FreqL fl = stage_freq(a.fi, fbuf);
-    for (int i = tid; i < a.nmu; i += T) smu[i] = a.mu[i];
     double b[3];
     const bool moving = load_beta(a.beta, p, b);
+    const int W = (G & 3) == 0 ? 4 : 1;                // groups per lane item
+    const int NC = G / W;                               // items per ordinate
+    const float rNC = 1.0f / (float)NC;
+    const int kb0 = wave * 64;
+
+    RemapEntry<real> e{};
+    real kap = 0;
+    P4 pre[4];
+    auto fetch_ordinates = [&](int kb) {
+        const int km = kb + lane;
+        if (km < K) {
+            if (moving) e = a.plan[p * K + km];
+            if (a.chi_grey) kap = a.chilab[(long)km * a.P + p];
+        }
+    };
+    auto fetch_inputs = [&](int kb, int nit, int base) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int item = base + 64 * u + lane;
+            pre[u] = P4{};
+            if (a.Iprev && item < nit) {
+                const int kk = (int)(((float)item + 0.5f) * rNC), g0 = (item - kk * NC) * W;
+                const long o = ((long)(kb + kk) * a.P + p) * G + g0;
+                if (W == 4) pre[u] = *reinterpret_cast<const P4 *>(a.Iprev + o);
+                else pre[u].v[0] = a.Iprev[o];
+            }
+        }
+    };
+    if (kb0 < K) {
+        fetch_ordinates(kb0);
+        fetch_inputs(kb0, min(64, K - kb0) * NC, 0);
+    }
+
     const real *__restrict__ src = a.S0 + (long)p * G * K;
     if ((K & 3) == 0) {
-        // 16-byte loads: four ordinates of one group per lane
-        using P4 = Pack<real, 4>;
-        const int K4 = K >> 2;
-        for (int i = tid; i < G * K4; i += T) {
-            const int g = i / K4, j = (i - g * K4) * 4;
-            const P4 v = *reinterpret_cast<const P4 *>(src + (long)g * K + j);
-            real *row = F + (g + 1) * KS + j;
-            row[0] = v.v[0]; row[1] = v.v[1]; row[2] = v.v[2]; row[3] = v.v[3];
-        }
+        stage_rows(src, F, G, K, KS);
     } else {
         for (int g = 0; g < G; ++g)
             for (int j = tid; j < K; j += T) F[(g + 1) * KS + j] = src[g * K + j];
@@ -787,107 +889,80 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_bo
         __syncthreads();
     }
     const real icdt = a.inv_cdt;
-    const int W = (G & 3) == 0 ? 4 : 1;                // groups per lane item
-    const int NC = G / W;                               // items per ordinate
-    const float rNC = 1.0f / (float)NC;
-    const double gam = moving ? a.gam[p] : 1.0;
-    for (int kb = wave * 64; kb < K; kb += T) {
-        // set-up of ordinate kb + lane
-        OrdRemap<real> mine{};
-        const int km = kb + lane;
-        if (a.chi_grey && km < K) mine.kap = a.chilab[(long)km * a.P + p];
-        if (moving && km < K) {
-            const double n[3] = {a.dir[4 * km], a.dir[4 * km + 1], a.dir[4 * km + 2]};
-            const double bn = b[0] * n[0] + b[1] * n[1] + b[2] * n[2];
-            const double D = 1.0 / inv_doppler(b, gam, n);
-            const double f = gam * (1.0 - gam / (gam + 1.0) * bn);
-            double n0[3];
-            for (int c = 0; c < 3; ++c) n0[c] = D * (n[c] - f * b[c]);
-            const Taps4<real> tp = taps4<real>(angle_taps<real>(smu, a.nmu, a.nphi, n0), K, a.nmu, a.nphi);
+    for (int kb = kb0; kb < K; kb += T) {
+        const int nk = min(64, K - kb), nit = nk * NC;
+        if (kb != kb0) fetch_ordinates(kb);
+        for (int base = 0; base < nit; base += 256) {
+            if (kb != kb0 || base != 0) fetch_inputs(kb, nit, base);
 #pragma unroll
-            for (int i = 0; i < 4; ++i) { mine.c[i] = tp.c[i]; mine.w[i] = tp.w[i]; }
-            if (a.fi.grey) {
-                const double D2 = D * D;
-                mine.x = D2 * D2;
-            } else if (a.fi.uniform) {
-                const double y = -(double)log((real)D) * a.fi.inv_delta;
-                const double sf = floor(y);
-                if (sf <= -(double)(G + 1) || sf >= (double)G) {
-                    mine.s = kAllGhost;
-                } else {
-                    const real fr = (real)(y - sf);
-                    const real cap = sizeof(real) == 4 ? real(80) : real(700);
-                    const real e3 = real(-3.0 * a.fi.delta);
-                    mine.s = (int)sf;
-                    mine.clo = (real(1) - fr) * exp(fmin(e3 * (real)sf, cap));
-                    mine.chi = fr * exp(fmin(e3 * (real)(sf + 1.0), cap));
+            for (int u = 0; u < 4; ++u) {
+                const int item = base + 64 * u + lane;
+                // every lane takes part in the shuffles (their source lanes are all active)
+                const int kk = min((int)(((float)item + 0.5f) * rNC), nk - 1), g0 = (item - kk * NC) * W;
+                const real kp = __shfl(kap, kk, 64);
+                int ab = 0, sh = 0;
+                real w[4] = {0, 0, 0, 0}, eu = 0, ev = 0;
+                if (moving) {
+                    ab = __shfl(e.ab, kk, 64);
+                    sh = __shfl(e.s, kk, 64);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) w[i] = __shfl(e.w[i], kk, 64);
+                    eu = __shfl(e.u, kk, 64);
+                    ev = __shfl(e.v, kk, 64);
                 }
-            } else {
-                mine.x = -log(D);
-            }
-        }
-        const int nk = min(64, K - kb);
-        for (int item = lane; item < nk * NC; item += 64) {
-            const int kk = (int)(((float)item + 0.5f) * rNC), g0 = (item - kk * NC) * W;
-            const int k = kb + kk;
-            const OrdRemap<real> r = shfl_remap(mine, kk);
-            const long o = ((long)k * a.P + p) * G + g0;
-            // time-term inputs first: their loads overlap the remap below
-            real ip[4] = {0, 0, 0, 0}, out[4] = {0, 0, 0, 0};
-            if (a.Iprev) {
-                if (W == 4) {
-                    const P4 v = *reinterpret_cast<const P4 *>(a.Iprev + o);
-                    ip[0] = v.v[0]; ip[1] = v.v[1]; ip[2] = v.v[2]; ip[3] = v.v[3];
+                if (item >= nit) continue;
+                const int k = kb + kk;
+                const long o = ((long)k * a.P + p) * G + g0;
+                real out[4] = {0, 0, 0, 0};
+                if (!moving) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (i < W) out[i] = F[(g0 + i + 1) * KS + k];
                 } else {
-                    ip[0] = a.Iprev[o];
-                }
-            }
-            const real chig = r.kap;
-            const Taps4<real> tp{{r.c[0], r.c[1], r.c[2], r.c[3]}, {r.w[0], r.w[1], r.w[2], r.w[3]}};
-            if (!moving) {
+                    const Taps4<real> tp = entry_taps(ab, w, K, a.nmu, a.nphi);
+                    if (a.fi.grey) {
+                        out[0] = eu * tap_row(F + KS, tp);
+                    } else if (a.fi.uniform) {
+                        if (sh != kAllGhost) {
+                            auto A = [&](int gp) -> real { return tap_row(F + (min(max(gp, -1), G) + 1) * KS, tp); };
+                            real acur = A(g0 + sh);
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (i < W) out[i] = F[(g0 + i + 1) * KS + k];
-            } else if (a.fi.grey) {
-                out[0] = (real)r.x * tap_row(F + KS, tp);
-            } else if (a.fi.uniform) {
-                if (r.s != kAllGhost) {
-                    auto A = [&](int gp) -> real { return tap_row(F + (min(max(gp, -1), G) + 1) * KS, tp); };
-                    real acur = A(g0 + r.s);
+                            for (int i = 0; i < 4; ++i) {
+                                if (i < W) {
+                                    const real anext = A(g0 + i + sh + 1);
+                                    out[i] = eu * acur + ev * anext;
+                                    acur = anext;
+                                }
+                            }
+                        }
+                    } else {
+                        const double x = (double)eu + (double)ev;
+                        FreqWalk fw{0};
+                        if (G > 2) fw.lo = centre_bracket(fl.lnc, G, fl.lnc[g0] + x);
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        if (i < W) {
-                            const real anext = A(g0 + i + r.s + 1);
-                            out[i] = r.clo * acur + r.chi * anext;
-                            acur = anext;
+                        for (int i = 0; i < 4; ++i) {
+                            if (i < W) {
+                                const int g = g0 + i;
+                                const FreqTaps ft = freq_taps_zero_walk(a.fi, fl, fl.lnc[g] + x, fw);
+                                double v = 0.0;
+                                if (ft.gl >= 0) v += ft.wl * (double)tap_row(F + (ft.gl + 1) * KS, tp) * fl.inv_nu3[ft.gl];
+                                if (ft.gh >= 0) v += ft.wh * (double)tap_row(F + (ft.gh + 1) * KS, tp) * fl.inv_nu3[ft.gh];
+                                out[i] = (real)(fl.nu3[g] * v);
+                            }
                         }
                     }
                 }
-            } else {
-                FreqWalk fw{0};
-                if (G > 2) fw.lo = centre_bracket(fl.lnc, G, fl.lnc[g0] + r.x);
+                // implicit time terms and the store
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    if (i < W) {
-                        const int g = g0 + i;
-                        const FreqTaps ft = freq_taps_zero_walk(a.fi, fl, fl.lnc[g] + r.x, fw);
-                        double v = 0.0;
-                        if (ft.gl >= 0) v += ft.wl * (double)tap_row(F + (ft.gl + 1) * KS, tp) * fl.inv_nu3[ft.gl];
-                        if (ft.gh >= 0) v += ft.wh * (double)tap_row(F + (ft.gh + 1) * KS, tp) * fl.inv_nu3[ft.gh];
-                        out[i] = (real)(fl.nu3[g] * v);
-                    }
+                for (int i = 0; i < 4; ++i)
+                    if (i < W) out[i] = time_terms(a.chi_grey ? kp : a.chilab[o + i], out[i], pre[u].v[i], icdt);
+                if (W == 4) {
+                    P4 v;
+                    v.v[0] = out[0]; v.v[1] = out[1]; v.v[2] = out[2]; v.v[3] = out[3];
+                    *reinterpret_cast<P4 *>(a.St + o) = v;
+                } else {
+                    a.St[o] = out[0];
                 }
-            }
-            // implicit time terms and the store
-#pragma unroll
-            for (int i = 0; i < 4; ++i)
-                if (i < W) out[i] = time_terms(a.chi_grey ? chig : a.chilab[o + i], out[i], ip[i], icdt);
-            if (W == 4) {
-                P4 v;
-                v.v[0] = out[0]; v.v[1] = out[1]; v.v[2] = out[2]; v.v[3] = out[3];
-                *reinterpret_cast<P4 *>(a.St + o) = v;
-            } else {
-                a.St[o] = out[0];
             }
         }
     }
@@ -907,25 +982,40 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_un
     if (p >= a.P) return;
     const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x, KS = table_stride(K);
     double *fbuf = reinterpret_cast<double *>(smem_raw);                // [4G]
-    double *smu = fbuf + 4 * G;                                         // [nmu] polar nodes
-    real *F = reinterpret_cast<real *>(smu + a.nmu);                    // [G+2][KS]
+    real *F = reinterpret_cast<real *>(fbuf + 4 * G);                   // [G+2][KS]
 
     const FreqL fl = stage_freq(a.fi, fbuf);
-    for (int i = tid; i < a.nmu; i += T) smu[i] = a.mu[i];
     double b[3];
     const bool moving = load_beta(a.beta, p, b);
+    RemapEntry<real> e{};
+    if (moving && tid < K) e = a.plan[p * K + tid];     // the first ordinate's entry, before staging
     if ((G & 3) == 0) {
-        // 16-byte loads: four groups of one ordinate per lane, written down a table column
+        // 16-byte loads, four groups of one ordinate per lane, written down a
+        // table column; four loads per lane in flight
         using P4 = Pack<real, 4>;
-        const int G4 = G >> 2;
+        const int G4 = G >> 2, n4 = K * G4;
         const float rG4 = 1.0f / (float)G4;
-        for (int idx = tid; idx < K * G4; idx += T) {
-            const int k = (int)(((float)idx + 0.5f) * rG4), g = (idx - k * G4) * 4;
-            const P4 v = *reinterpret_cast<const P4 *>(a.Ilab + ((long)k * a.P + p) * G + g);
-            F[(g + 1) * KS + k] = v.v[0];
-            F[(g + 2) * KS + k] = v.v[1];
-            F[(g + 3) * KS + k] = v.v[2];
-            F[(g + 4) * KS + k] = v.v[3];
+        for (int i0 = tid; i0 < n4; i0 += 4 * T) {
+            P4 v[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = i0 + u * T;
+                if (idx < n4) {
+                    const int k = (int)(((float)idx + 0.5f) * rG4), g = (idx - k * G4) * 4;
+                    v[u] = *reinterpret_cast<const P4 *>(a.Ilab + ((long)k * a.P + p) * G + g);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int idx = i0 + u * T;
+                if (idx < n4) {
+                    const int k = (int)(((float)idx + 0.5f) * rG4), g = (idx - k * G4) * 4;
+                    F[(g + 1) * KS + k] = v[u].v[0];
+                    F[(g + 2) * KS + k] = v[u].v[1];
+                    F[(g + 3) * KS + k] = v[u].v[2];
+                    F[(g + 4) * KS + k] = v[u].v[3];
+                }
+            }
         }
     } else {
         const float rG = 1.0f / (float)G;
@@ -945,22 +1035,25 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_un
     __syncthreads();
     table_poles(F, G, K, KS, a.nmu, a.nphi);
     __syncthreads();
-    const double gam = a.gam[p];
     for (int j = tid; j < K; j += T) {
-        const double n0[3] = {a.dir[4 * j], a.dir[4 * j + 1], a.dir[4 * j + 2]};
-        const double bn0 = b[0] * n0[0] + b[1] * n0[1] + b[2] * n0[2];
-        const double Dp = gam * (1.0 + bn0);
-        const double f = gam * (1.0 + gam / (gam + 1.0) * bn0);
-        double n[3];
-        for (int c = 0; c < 3; ++c) n[c] = (n0[c] + f * b[c]) / Dp;
-        const Taps4<real> tp = taps4<real>(angle_taps<real>(smu, a.nmu, a.nphi, n), K, a.nmu, a.nphi);
+        if (j != tid) e = a.plan[p * K + j];
+        const Taps4<real> tp = entry_taps(e.ab, e.w, K, a.nmu, a.nphi);
         if (a.fi.grey) {
-            const double D2 = Dp * Dp;
-            out[j] = (real)((double)tap_row(F + KS, tp) / (D2 * D2));
+            out[j] = tap_row(F + KS, tp) * e.u;
         } else if (a.fi.uniform) {
-            uniform_remap(F, KS, G, tp, (double)log((real)Dp) * a.fi.inv_delta, a.fi.delta, out + j, K);
+            if (e.s == kAllGhost) {
+                for (int g = 0; g < G; ++g) out[g * K + j] = real(0);
+            } else {
+                auto A = [&](int gp) -> real { return tap_row(F + (min(max(gp, -1), G) + 1) * KS, tp); };
+                real acur = A(e.s);
+                for (int g = 0; g < G; ++g) {
+                    const real anext = A(g + e.s + 1);
+                    out[g * K + j] = e.u * acur + e.v * anext;
+                    acur = anext;
+                }
+            }
         } else {
-            general_remap(F, KS, a.fi, fl, tp, log(Dp), out + j, K);
+            general_remap(F, KS, a.fi, fl, tp, (double)e.u + (double)e.v, out + j, K);
         }
     }
 }
@@ -1590,14 +1683,21 @@ void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st)
 #undef RRT_TRACE_CASE
 }
 template <typename real>
-size_t boost_lds(int K, int G, int nmu)
+size_t boost_lds(int K, int G)
 {
-    return sizeof(double) * (4 * (size_t)G + nmu) + sizeof(real) * (G + 2) * (size_t)((K + 2) | 1);
+    return sizeof(double) * 4 * (size_t)G + sizeof(real) * (G + 2) * (size_t)((K + 2) | 1);
 }
 template <typename real>
-size_t unboost_lds(int K, int G, int nmu)
+size_t unboost_lds(int K, int G)
 {
-    return sizeof(double) * (4 * (size_t)G + nmu) + sizeof(real) * (G + 2) * (size_t)((K + 2) | 1);
+    return sizeof(double) * 4 * (size_t)G + sizeof(real) * (G + 2) * (size_t)((K + 2) | 1);
+}
+template <typename real>
+void launch_remap_plan(const PlanArgs<real> &a, hipStream_t st)
+{
+    const long n = a.P * a.K;
+    const unsigned nb = (unsigned)std::min<long>((n + 255) / 256, 16384);
+    hipLaunchKernelGGL(k_remap_plan<real>, dim3(nb), dim3(256), 0, st, a);
 }
 template <typename real>
 void launch_chilab(const ChiLabArgs<real> &a, hipStream_t st)
@@ -1610,13 +1710,13 @@ template <typename real>
 void launch_boost(const BoostArgs<real> &a, hipStream_t st)
 {
     const unsigned nb = (unsigned)(8 * ((a.P + 7) / 8));
-    hipLaunchKernelGGL(k_boost<real>, dim3(nb), dim3(kRemapThreads), boost_lds<real>(a.K, a.fi.G, a.nmu), st, a);
+    hipLaunchKernelGGL(k_boost<real>, dim3(nb), dim3(kRemapThreads), boost_lds<real>(a.K, a.fi.G), st, a);
 }
 template <typename real>
 void launch_unboost(const UnboostArgs<real> &a, hipStream_t st)
 {
     const unsigned nb = (unsigned)(8 * ((a.P + 7) / 8));
-    hipLaunchKernelGGL(k_unboost<real>, dim3(nb), dim3(kRemapThreads), unboost_lds<real>(a.K, a.fi.G, a.nmu), st, a);
+    hipLaunchKernelGGL(k_unboost<real>, dim3(nb), dim3(kRemapThreads), unboost_lds<real>(a.K, a.fi.G), st, a);
 }
 size_t do2sh_lds(int NL) { return sizeof(float) * 64 * (size_t)(((NL + 15) / 16) * 16 + 4); }
 
@@ -1817,9 +1917,10 @@ hipError_t set_lds_limits(size_t bytes)
     template void launch_boost<real>(const BoostArgs<real> &, hipStream_t);                                     \
     template void launch_unboost<real>(const UnboostArgs<real> &, hipStream_t);                                 \
     template size_t trace_lds<real>(int, int, int, int);                                                       \
-    template size_t boost_lds<real>(int, int, int);                                                                 \
-    template size_t unboost_lds<real>(int, int, int);                                                               \
+    template size_t boost_lds<real>(int, int);                                                                 \
+    template size_t unboost_lds<real>(int, int);                                                               \
     template void launch_chilab<real>(const ChiLabArgs<real> &, hipStream_t);                                   \
+    template void launch_remap_plan<real>(const PlanArgs<real> &, hipStream_t);                                   \
     template void launch_source<real>(const SourceArgs<real> &, hipStream_t);                                   \
     template void launch_chi0<real>(long, int, const real *, const real *, const real *, real *, hipStream_t);  \
     template void launch_moments_lab<real>(long, int, int, const double *, const real *, double *, double *,    \
