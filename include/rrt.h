@@ -161,6 +161,18 @@ rrt_status rrt_ray_trace(rrt_problem *pr, const double *S_tilde, const double *c
 size_t rrt_footprint_bytes(const rrt_grid *grid, const rrt_groups *groups, const rrt_angles *angles,
                            rrt_precision precision, int time_dependent, int use_ng);
 
+/* Captured sweeps.  With graphs enabled (the default) a sweep whose source
+   buffer, stage input and 1/(c dt) have already been run eagerly is captured
+   once into a HIP graph on the problem's stream and replayed from then on:
+   the same kernels in the same order, so results are bit-identical to eager
+   sweeps; only the host launch cost changes.  Graphs are not used while kernel
+   timing is on.  Disabling drops the captured graphs.  Setting the medium or a
+   boundary drops them too (their buffers may change).  If the runtime refuses
+   a capture the problem runs eagerly from then on.  rrt_graph_count returns
+   the number of captured sweeps held, or -1 after a refused capture. */
+rrt_status rrt_set_graphs(rrt_problem *pr, int enable);
+rrt_status rrt_graph_count(const rrt_problem *pr, int *count);
+
 /* Kernel timing: when enabled, each launch of the library's kernels is
    bracketed by HIP events on the problem's stream; rrt_kernel_time returns
    the number of launches and their summed duration (ms) for one kernel name

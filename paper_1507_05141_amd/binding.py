@@ -78,6 +78,8 @@ def lib():
             "rrt_get_sweep_intensity": [P, _dp],
             "rrt_ray_trace": [P, _dp, _dp, _dp],
             "rrt_set_profiling": [P, I],
+            "rrt_set_graphs": [P, I],
+            "rrt_graph_count": [P, ctypes.POINTER(I)],
             "rrt_kernel_time": [P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(D)],
             "rrt_synchronize": [P],
             "rrt_batch_create": [ctypes.c_size_t, ctypes.POINTER(P)],
@@ -258,6 +260,15 @@ class Problem:
         out = np.zeros(self.lab_shape())
         _check(lib().rrt_ray_trace(self._h, sp, xp, out.ctypes.data_as(_dp)))
         return out
+
+    # captured sweeps
+    def set_graphs(self, enable=True):
+        _check(lib().rrt_set_graphs(self._h, int(enable)))
+
+    def graph_count(self):
+        n = ctypes.c_int()
+        _check(lib().rrt_graph_count(self._h, ctypes.byref(n)))
+        return n.value
 
     # timing
     def set_profiling(self, enable=True):

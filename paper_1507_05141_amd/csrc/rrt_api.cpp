@@ -42,6 +42,7 @@ const char *kNames[KI_N] = {"trace", "sh2do", "boost", "unboost", "do2sh", "sour
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kMaxLds = 160 * 1024;
 constexpr double kResidualFloor = 1e-20;    // of the largest group's source norm
+constexpr size_t kMaxGraphs = 16;           // captured sweeps kept per problem
 
 }  // namespace
 
@@ -99,6 +100,18 @@ struct rrt_problem {
         double seconds = 0;                         // begin to finish
     } sv;
     rrt_batch *batch = nullptr;
+    // sweeps captured as HIP graphs, keyed by the source buffer (the two SH
+    // buffers alternate), the stage input and 1/(c dt); a key is captured the
+    // first time it recurs after two eager sweeps
+    struct Captured {
+        const void *S, *Iprev;
+        double inv_cdt;
+        hipGraphExec_t exec;
+    };
+    std::vector<Captured> graphs;
+    bool use_graphs = true;
+    bool graphs_failed = false;                     // capture or instantiation refused: eager from then on
+    int eager_sweeps = 0;
     // kernel timing
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[KI_N];
@@ -181,6 +194,15 @@ rrt_status alloc_upload_real(rrt_problem *pr, void **dst, const std::vector<doub
     rrt_status s = pr_alloc(pr, dst, v.size() * pr->esz);
     if (s) return s;
     return upload_real(pr, *dst, v.data(), v.size());
+}
+
+// drop the captured sweeps (their buffers or kernel choices are about to change)
+void clear_graphs(rrt_problem *pr)
+{
+    if (!pr->graphs.empty() && pr->stream) (void)hipStreamSynchronize(pr->stream);
+    for (auto &g : pr->graphs) (void)hipGraphExecDestroy(g.exec);
+    pr->graphs.clear();
+    pr->eager_sweeps = 0;
 }
 
 // --- kernel timing ---------------------------------------------------------
@@ -382,8 +404,54 @@ struct Engine {
     }
 
     // one source iteration from d_S (Iprev/inv_cdt: implicit time terms), queued on the
-    // stream; the residual sums arrive in h_red
+    // stream; the residual sums arrive in h_red.  Once a (source buffer, stage input,
+    // 1/(c dt)) key has run eagerly, later sweeps with that key replay a captured graph.
     rrt_status sweep_launch(const void *Iprev, double inv_cdt)
+    {
+        const bool graphs = pr->use_graphs && !pr->graphs_failed && !pr->prof;
+        if (graphs) {
+            for (const auto &g : pr->graphs)
+                if (g.S == pr->d_S && g.Iprev == Iprev && g.inv_cdt == inv_cdt) {
+                    HIPCHK(hipGraphLaunch(g.exec, pr->stream));
+                    std::swap(pr->d_S, pr->d_Snew);
+                    return RRT_OK;
+                }
+            if (pr->eager_sweeps >= 2 && pr->graphs.size() < kMaxGraphs) {
+                rrt_status s = capture_sweep(Iprev, inv_cdt);
+                if (s != RRT_E_STATE) return s;
+            }
+        }
+        ++pr->eager_sweeps;
+        return sweep_queue(Iprev, inv_cdt);
+    }
+    // capture one sweep into a graph and launch it; RRT_E_STATE when the runtime
+    // refuses (nothing queued then: the caller runs the sweep eagerly)
+    rrt_status capture_sweep(const void *Iprev, double inv_cdt)
+    {
+        const void *S0 = pr->d_S;
+        auto refuse = [&]() {
+            (void)hipGetLastError();
+            if (pr->d_S != S0) std::swap(pr->d_S, pr->d_Snew);
+            pr->graphs_failed = true;
+            return RRT_E_STATE;
+        };
+        if (hipStreamBeginCapture(pr->stream, hipStreamCaptureModeThreadLocal) != hipSuccess) return refuse();
+        rrt_status s = sweep_queue(Iprev, inv_cdt);
+        hipGraph_t graph = nullptr;
+        const hipError_t e = hipStreamEndCapture(pr->stream, &graph);
+        if (s || e != hipSuccess || !graph) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return refuse();
+        }
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess || !exec) return refuse();
+        pr->graphs.push_back({S0, Iprev, inv_cdt, exec});
+        HIPCHK(hipGraphLaunch(exec, pr->stream));
+        return RRT_OK;
+    }
+    rrt_status sweep_queue(const void *Iprev, double inv_cdt)
     {
         rrt_status s = to_lab(pr->d_S, Iprev, inv_cdt);
         if (s) return s;
@@ -657,6 +725,7 @@ void rrt_destroy(rrt_problem *pr)
     if (!pr) return;
     if (pr->batch) (void)rrt_batch_remove(pr->batch, pr);
     if (pr->stream) (void)hipStreamSynchronize(pr->stream);
+    clear_graphs(pr);
     if (pr->h_red) (void)hipHostFree(pr->h_red);
     if (pr->blas) (void)rocblas_destroy_handle(pr->blas);
     void *bufs[] = {pr->d_dir, pr->d_mu, pr->d_lnc, pr->d_nu3, pr->d_inv_nu3, pr->d_inv_dc, pr->d_geo, pr->d_Yt, pr->d_WY,
@@ -904,6 +973,7 @@ rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *si
     if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
     if (!kappa || !sigma || !bnu) return fail(RRT_E_INVALID, "kappa, sigma and bnu are required");
     if (kte) return fail(RRT_E_INVALID, "electron temperature fields are not supported: electrons at rest only");
+    clear_graphs(pr);
     const size_t P = pr->P, G = pr->G;
     for (size_t i = 0; i < P * G; ++i) {
         if (!std::isfinite(kappa[i]) || kappa[i] < 0) return fail(RRT_E_INVALID, "kappa must be finite and >= 0");
@@ -990,6 +1060,7 @@ rrt_status rrt_set_boundary(rrt_problem *pr, int face, const double *I_in)
 {
     if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
     if (face != 0 && face != 1) return fail(RRT_E_INVALID, "face must be 0 (z = 0) or 1 (z = lz)");
+    clear_graphs(pr);
     if (!I_in) {
         dev_free(pr->d_bc[face]);
         return RRT_OK;
@@ -1133,6 +1204,21 @@ rrt_status rrt_ray_trace(rrt_problem *pr, const double *S_tilde, const double *c
     });
     if (s) return s;
     return download_real(pr, I_lab, pr->d_Ilab, n);
+}
+
+rrt_status rrt_set_graphs(rrt_problem *pr, int enable)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    if (!enable) clear_graphs(pr);
+    pr->use_graphs = enable != 0;
+    return RRT_OK;
+}
+
+rrt_status rrt_graph_count(const rrt_problem *pr, int *count)
+{
+    if (!pr || !count) return fail(RRT_E_INVALID, "problem and count are required");
+    *count = pr->graphs_failed ? -1 : (int)pr->graphs.size();
+    return RRT_OK;
 }
 
 rrt_status rrt_set_profiling(rrt_problem *pr, int enable)

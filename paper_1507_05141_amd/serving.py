@@ -63,11 +63,13 @@ def poisson_requests(count, rate, seed, **mix):
     return out
 
 
-def serve(requests, precision=B.FP32, budget_bytes=64 << 30, tol=1e-6, max_iter=300, use_ng=True, keep=None):
+def serve(requests, precision=B.FP32, budget_bytes=64 << 30, tol=1e-6, max_iter=300, use_ng=True, keep=None,
+          graphs=True):
     """Run the request stream; returns per-request records and the run's wall time.
 
     keep(i, problem) -> dict, if given, is called on each finished problem
-    before it is destroyed (e.g. to read its moments)."""
+    before it is destroyed (e.g. to read its moments).  graphs=False runs every
+    sweep eagerly instead of replaying captured sweeps."""
     batch = B.Batch(budget_bytes)
     pending = list(range(len(requests)))           # not yet admitted, in arrival order
     running = {}                                    # request -> Problem
@@ -87,6 +89,8 @@ def serve(requests, precision=B.FP32, budget_bytes=64 << 30, tol=1e-6, max_iter=
                     break
                 t_adm = now()
                 pr = B.Problem.from_spec(spec, precision=precision)
+                if not graphs:
+                    pr.set_graphs(False)
                 if not batch.admit(pr, tol=tol, max_iter=max_iter, use_ng=use_ng):
                     pr.close()
                     if running:
