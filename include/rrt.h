@@ -161,6 +161,23 @@ rrt_status rrt_ray_trace(rrt_problem *pr, const double *S_tilde, const double *c
 size_t rrt_footprint_bytes(const rrt_grid *grid, const rrt_groups *groups, const rrt_angles *angles,
                            rrt_precision precision, int time_dependent, int use_ng);
 
+/* Kernel variants.  Two choices of the sweep have several correct kernels:
+   the groups per ray-trace workgroup (1, 2 or 4: those dividing G whose
+   planes fit the LDS) and the ordinate -> SH product (S6; -1 the default for
+   the shape, 0 the library product (FP32 only), 1, 2 or 4 the matrix-core
+   kernel with that many 16-row tiles per wave, for (L+1)^2 <= 64 in FP32 and
+   mixed precision).  With autotuning on (the default) each candidate is timed
+   on the problem's own buffers at the start of its second sweep and the
+   fastest kept; the choice is remembered per problem shape for the rest of
+   the process.  The first sweep always uses the defaults.  Variants differ
+   only in the order of floating-point sums.  rrt_set_variants fixes them
+   (trace_groups 0 keeps the current one) and turns autotuning off; it
+   returns RRT_E_INVALID for a variant the shape or precision does not have.
+   RRT_TRACE_GC in the environment at creation fixes the groups per workgroup. */
+rrt_status rrt_set_autotune(rrt_problem *pr, int enable);
+rrt_status rrt_set_variants(rrt_problem *pr, int trace_groups, int s6_variant);
+rrt_status rrt_get_variants(const rrt_problem *pr, int *trace_groups, int *s6_variant, int *tuned);
+
 /* Captured sweeps.  With graphs enabled (the default) a sweep whose source
    buffer, stage input and 1/(c dt) have already been run eagerly is captured
    once into a HIP graph on the problem's stream and replayed from then on:

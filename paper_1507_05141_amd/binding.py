@@ -79,6 +79,9 @@ def lib():
             "rrt_ray_trace": [P, _dp, _dp, _dp],
             "rrt_set_profiling": [P, I],
             "rrt_set_graphs": [P, I],
+            "rrt_set_autotune": [P, I],
+            "rrt_set_variants": [P, I, I],
+            "rrt_get_variants": [P, ctypes.POINTER(I), ctypes.POINTER(I), ctypes.POINTER(I)],
             "rrt_graph_count": [P, ctypes.POINTER(I)],
             "rrt_kernel_time": [P, ctypes.c_char_p, ctypes.POINTER(I), ctypes.POINTER(D)],
             "rrt_synchronize": [P],
@@ -260,6 +263,22 @@ class Problem:
         out = np.zeros(self.lab_shape())
         _check(lib().rrt_ray_trace(self._h, sp, xp, out.ctypes.data_as(_dp)))
         return out
+
+    # kernel variants
+    def set_autotune(self, enable=True):
+        _check(lib().rrt_set_autotune(self._h, int(enable)))
+
+    def set_variants(self, trace_groups=0, s6=-1):
+        """Fix the kernel variants (turns autotuning off): trace_groups groups per
+        ray-trace workgroup (0 keeps the current), s6 the ordinate -> SH product
+        (-1 the default for the shape, 0 the library product, 1/2/4 the
+        matrix-core kernel with that many 16-row tiles per wave)."""
+        _check(lib().rrt_set_variants(self._h, int(trace_groups), int(s6)))
+
+    def variants(self):
+        gc, s6, tuned = ctypes.c_int(), ctypes.c_int(), ctypes.c_int()
+        _check(lib().rrt_get_variants(self._h, ctypes.byref(gc), ctypes.byref(s6), ctypes.byref(tuned)))
+        return {"trace_groups": gc.value, "s6": s6.value, "tuned": bool(tuned.value)}
 
     # captured sweeps
     def set_graphs(self, enable=True):

@@ -11,6 +11,8 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <string>
 #include <utility>
 #include <vector>
@@ -43,6 +45,9 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kMaxLds = 160 * 1024;
 constexpr double kResidualFloor = 1e-20;    // of the largest group's source norm
 constexpr size_t kMaxGraphs = 16;           // captured sweeps kept per problem
+// kernel variants chosen by timing, per problem shape: (groups per trace workgroup, S6 variant)
+std::mutex g_tune_mu;
+std::map<std::string, std::pair<int, int>> g_tuned;
 
 }  // namespace
 
@@ -112,6 +117,13 @@ struct rrt_problem {
     bool use_graphs = true;
     bool graphs_failed = false;                     // capture or instantiation refused: eager from then on
     int eager_sweeps = 0;
+    // kernel variants: groups per ray-trace workgroup (Gc above) and the S6 product
+    // (-1 the default for the shape, 0 the library product, 1/2/4 the matrix-core
+    // kernel with that many 16-row tiles per wave); autotuned at the second sweep
+    int s6 = -1;
+    bool autotune = true, tuned = false;
+    bool gc_forced = false;                         // groups per workgroup fixed by the environment
+    size_t lds_lim = 0;
     // kernel timing
     bool prof = false;
     std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[KI_N];
@@ -317,14 +329,18 @@ struct Engine {
     // S4 (chi~ from the medium, or from d_Xt when chi_array)
     void trace(const void *St, void *I, double inv_cdt, bool chi_array)
     {
+        prof_begin(pr, KI_TRACE);
+        trace_launch(St, I, inv_cdt, chi_array);
+        prof_end(pr, KI_TRACE);
+    }
+    void trace_launch(const void *St, void *I, double inv_cdt, bool chi_array)
+    {
         rrt::TraceArgs<real> t;
         t.nx = pr->nx; t.ny = pr->ny; t.nz = pr->nz; t.G = pr->G; t.K = pr->K; t.Gc = pr->Gc; t.P = pr->P;
         t.geo = pr->d_geo; t.dir = pr->d_dir; t.St = static_cast<const real *>(St); t.Xt = R(pr->d_Xt);
         t.chilab = R(pr->d_chilab); t.chi_grey = pr->grey_chi;
         t.inv_cdt = (real)inv_cdt; t.bc_bot = R(pr->d_bc[0]); t.bc_top = R(pr->d_bc[1]); t.I = R(I);
-        prof_begin(pr, KI_TRACE);
         rrt::launch_trace<real>(t, chi_array, pr->stream);
-        prof_end(pr, KI_TRACE);
     }
 
     // S5 + S6: lab intensity -> comoving ordinates -> comoving SH intensity (into d_Ilm)
@@ -340,17 +356,109 @@ struct Engine {
         rrt_status s = check_launch();
         if (s) return s;
         prof_begin(pr, KI_DO2SH);
-        const _Float16 *wy16 = (const _Float16 *)pr->d_WYt16;
-        if (pr->prec == RRT_MIXED && rrt::launch_do2sh_f16(pr->P * pr->G, pr->K, pr->NL, (const float *)pr->d_co, wy16,
-                                                           wy16 + pr->wyt16_n, (float *)pr->d_Ilm, pr->stream))
-            s = check_launch();
-        else if (sizeof(real) == 4 && rrt::launch_do2sh_f32(pr->P * pr->G, pr->K, pr->NL, (const float *)pr->d_co,
-                                                            (const float *)pr->d_WY, (float *)pr->d_Ilm, pr->stream))
-            s = check_launch();
-        else
-            s = gemm(pr->P * pr->G, pr->NL, pr->K, R(pr->d_co), R(pr->d_WY), R(pr->d_Ilm));
+        s = do2sh(pr->s6);
         prof_end(pr, KI_DO2SH);
         return s;
+    }
+    // S6 with variant v (as rrt_problem::s6)
+    rrt_status do2sh(int v)
+    {
+        const int rt = v > 0 ? v : 0;
+        const _Float16 *wy16 = (const _Float16 *)pr->d_WYt16;
+        if (pr->prec == RRT_MIXED && rrt::launch_do2sh_f16(pr->P * pr->G, pr->K, pr->NL, (const float *)pr->d_co, wy16,
+                                                           wy16 + pr->wyt16_n, (float *)pr->d_Ilm, pr->stream, rt))
+            return check_launch();
+        if (sizeof(real) == 4 && pr->prec != RRT_MIXED && v != 0 &&
+            rrt::launch_do2sh_f32(pr->P * pr->G, pr->K, pr->NL, (const float *)pr->d_co, (const float *)pr->d_WY,
+                                  (float *)pr->d_Ilm, pr->stream, rt))
+            return check_launch();
+        return gemm(pr->P * pr->G, pr->NL, pr->K, R(pr->d_co), R(pr->d_WY), R(pr->d_Ilm));
+    }
+
+    // --- autotuning of the kernel variants ---------------------------------
+    // Candidates are timed on the problem's own buffers at the start of its second
+    // sweep (the first sweep has filled them); the choice is kept per shape for the
+    // process, so later problems of the same shape take it without timing.
+    std::string tune_key(double inv_cdt) const
+    {
+        char b[256];
+        std::snprintf(b, sizeof b, "%d %d %d %d %d %d %d %d %d %d", pr->nx, pr->ny, pr->nz, pr->G, pr->K, pr->NL,
+                      (int)pr->prec, pr->grey_chi, inv_cdt != 0.0, (int)pr->scatter);
+        return b;
+    }
+    // average time (ms) of n launches of f after one untimed launch
+    template <class F> float time_ms(F f, int n = 2)
+    {
+        hipEvent_t a, b;
+        if (hipEventCreate(&a) != hipSuccess) return INFINITY;
+        if (hipEventCreate(&b) != hipSuccess) { (void)hipEventDestroy(a); return INFINITY; }
+        f();
+        (void)hipEventRecord(a, pr->stream);
+        for (int i = 0; i < n; ++i) f();
+        (void)hipEventRecord(b, pr->stream);
+        float t = INFINITY;
+        if (hipEventSynchronize(b) != hipSuccess || hipEventElapsedTime(&t, a, b) != hipSuccess) t = INFINITY;
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return t / n;
+    }
+    std::vector<int> gc_candidates() const
+    {
+        std::vector<int> c;
+        for (int gc = 4; gc >= 1; gc /= 2) {
+            const size_t need = pr->prec == RRT_FP64 ? rrt::trace_lds<double>(pr->nx, pr->ny, gc, 0)
+                                                     : rrt::trace_lds<float>(pr->nx, pr->ny, gc, 0);
+            if (pr->G % gc == 0 && need <= pr->lds_lim) c.push_back(gc);
+        }
+        return c;
+    }
+    std::vector<int> s6_candidates() const
+    {
+        std::vector<int> c;
+        if (pr->prec == RRT_FP64) return c;
+        if (pr->NL <= 64) c = {1, 2, 4};
+        if (pr->prec == RRT_FP32) c.push_back(0);
+        return c;
+    }
+    rrt_status autotune(double inv_cdt)
+    {
+        pr->tuned = true;
+        const std::string key = tune_key(inv_cdt);
+        {
+            std::lock_guard<std::mutex> lk(g_tune_mu);
+            auto it = g_tuned.find(key);
+            if (it != g_tuned.end()) {
+                if (!pr->gc_forced) pr->Gc = it->second.first;
+                pr->s6 = it->second.second;
+                return RRT_OK;
+            }
+        }
+        if (!pr->gc_forced) {
+            const auto c = gc_candidates();
+            float best = INFINITY;
+            int pick = pr->Gc;
+            for (int gc : c) {
+                pr->Gc = gc;
+                const float t = time_ms([&] { trace_launch(pr->d_St, pr->d_Ilab, inv_cdt, false); });
+                if (t < best) { best = t; pick = gc; }
+            }
+            pr->Gc = pick;
+        }
+        {
+            const auto c = s6_candidates();
+            float best = INFINITY;
+            int pick = pr->s6;
+            for (int v : c) {
+                const float t = time_ms([&] { (void)do2sh(v); });
+                if (t < best) { best = t; pick = v; }
+            }
+            pr->s6 = pick;
+        }
+        rrt_status s = check_launch();
+        if (s) return s;
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        g_tuned[key] = {pr->Gc, pr->s6};
+        return RRT_OK;
     }
 
     // S1: source from d_Ilm into S
@@ -420,6 +528,10 @@ struct Engine {
                 rrt_status s = capture_sweep(Iprev, inv_cdt);
                 if (s != RRT_E_STATE) return s;
             }
+        }
+        if (pr->eager_sweeps == 1 && pr->autotune && !pr->tuned) {
+            rrt_status s = autotune(inv_cdt);
+            if (s) return s;
         }
         ++pr->eager_sweeps;
         return sweep_queue(Iprev, inv_cdt);
@@ -794,7 +906,11 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
         pr->Gc = 0;
         const char *env = std::getenv("RRT_TRACE_GC");
         const int want = env ? std::atoi(env) : 0;
-        if ((want == 1 || want == 2 || want == 4) && fits(want)) pr->Gc = want;
+        pr->lds_lim = lim;
+        if ((want == 1 || want == 2 || want == 4) && fits(want)) {
+            pr->Gc = want;
+            pr->gc_forced = true;
+        }
         for (int gc = 4; !pr->Gc && gc >= 1; gc /= 2)
             if (fits(gc)) pr->Gc = gc;
         const size_t need_boost = pr->prec == RRT_FP64 ? rrt::boost_lds<double>(pr->K, pr->G)
@@ -1204,6 +1320,44 @@ rrt_status rrt_ray_trace(rrt_problem *pr, const double *S_tilde, const double *c
     });
     if (s) return s;
     return download_real(pr, I_lab, pr->d_Ilab, n);
+}
+
+rrt_status rrt_set_autotune(rrt_problem *pr, int enable)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    pr->autotune = enable != 0;
+    return RRT_OK;
+}
+
+rrt_status rrt_set_variants(rrt_problem *pr, int trace_groups, int s6_variant)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    bool ok_gc = trace_groups == 0;
+    dispatch(pr, [&](auto &e) {
+        for (int gc : e.gc_candidates()) ok_gc = ok_gc || gc == trace_groups;
+        return RRT_OK;
+    });
+    if (!ok_gc) return fail(RRT_E_INVALID, "groups per ray-trace workgroup must divide G and fit the LDS (1, 2 or 4)");
+    bool ok_s6 = s6_variant == -1;
+    dispatch(pr, [&](auto &e) {
+        for (int v : e.s6_candidates()) ok_s6 = ok_s6 || v == s6_variant;
+        return RRT_OK;
+    });
+    if (!ok_s6) return fail(RRT_E_INVALID, "S6 variant not available for this shape and precision");
+    clear_graphs(pr);
+    if (trace_groups) pr->Gc = trace_groups;
+    pr->s6 = s6_variant;
+    pr->autotune = false;
+    return RRT_OK;
+}
+
+rrt_status rrt_get_variants(const rrt_problem *pr, int *trace_groups, int *s6_variant, int *tuned)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    if (trace_groups) *trace_groups = pr->Gc;
+    if (s6_variant) *s6_variant = pr->s6;
+    if (tuned) *tuned = pr->tuned ? 1 : 0;
+    return RRT_OK;
 }
 
 rrt_status rrt_set_graphs(rrt_problem *pr, int enable)

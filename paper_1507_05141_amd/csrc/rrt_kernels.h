@@ -128,15 +128,16 @@ template <typename real> size_t boost_lds(int K, int G);
 template <typename real> size_t unboost_lds(int K, int G);
 template <typename real> void launch_remap_plan(const PlanArgs<real> &a, hipStream_t st);
 template <typename real> void launch_chilab(const ChiLabArgs<real> &a, hipStream_t st);
-// S6 on the matrix cores (FP32) for NL <= 64; false when the shape is not covered (then use a library product)
-bool launch_do2sh_f32(long R, int K, int NL, const float *A, const float *B, float *C, hipStream_t st);
+// S6 on the matrix cores (FP32) for NL <= 64; false when the shape is not covered (then use a library
+// product).  rt: 16-row tiles per wave (1, 2 or 4; 0 = the default for NL)
+bool launch_do2sh_f32(long R, int K, int NL, const float *A, const float *B, float *C, hipStream_t st, int rt = 0);
 size_t do2sh_lds(int NL);
 // mixed precision (FP16 matrix cores on hi + lo operand pairs, FP32 accumulation), NL <= 256:
 // S6 with the FP16 tables WYt[NL rounded up to 16][K rounded up to 32] and S2 with the FP16
 // tables Y[K rounded up to 16][NL rounded up to 32] (hi and lo parts, zero padding); false when
 // the shape is not covered
 bool launch_do2sh_f16(long R, int K, int NL, const float *A, const _Float16 *WYh, const _Float16 *WYl, float *C,
-                      hipStream_t st);
+                      hipStream_t st, int rt = 0);
 bool launch_sh2do_f16(long R, int K, int NL, const float *S, const _Float16 *Yh, const _Float16 *Yl, float *C,
                       hipStream_t st);
 template <typename real> void launch_source(const SourceArgs<real> &a, hipStream_t st);

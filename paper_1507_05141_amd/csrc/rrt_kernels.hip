@@ -1720,7 +1720,7 @@ void launch_unboost(const UnboostArgs<real> &a, hipStream_t st)
 }
 size_t do2sh_lds(int NL) { return sizeof(float) * 64 * (size_t)(((NL + 15) / 16) * 16 + 4); }
 
-bool launch_do2sh_f32(long R, int K, int NL, const float *A, const float *B, float *C, hipStream_t st)
+bool launch_do2sh_f32(long R, int K, int NL, const float *A, const float *B, float *C, hipStream_t st, int rt)
 {
     const dim3 block(256);
     const size_t sm = do2sh_lds(NL);
@@ -1733,14 +1733,21 @@ bool launch_do2sh_f32(long R, int K, int NL, const float *A, const float *B, flo
                            C);                                                                               \
         return true;                                                                                          \
     }
-    if (NL <= 16) RRT_DO2SH32(1, 4)
-    if (NL <= 64) RRT_DO2SH32(4, 2)
+    if (NL <= 16) {
+        if (rt == 1) RRT_DO2SH32(1, 1)
+        if (rt == 2) RRT_DO2SH32(1, 2)
+        if (rt == 0 || rt == 4) RRT_DO2SH32(1, 4)
+    } else if (NL <= 64) {
+        if (rt == 1) RRT_DO2SH32(4, 1)
+        if (rt == 0 || rt == 2) RRT_DO2SH32(4, 2)
+        if (rt == 4) RRT_DO2SH32(4, 4)
+    }
 #undef RRT_DO2SH32
     return false;
 }
 
 bool launch_do2sh_f16(long R, int K, int NL, const float *A, const _Float16 *WYh, const _Float16 *WYl, float *C,
-                      hipStream_t st)
+                      hipStream_t st, int rt)
 {
     const int Kp = (K + 31) / 32 * 32;
     const dim3 block(256);
@@ -1753,9 +1760,17 @@ bool launch_do2sh_f16(long R, int K, int NL, const float *A, const _Float16 *WYh
                            NL, A, WYh, WYl, C);                                                             \
         return true;                                                                                         \
     }
-    if (NL <= 16) RRT_DO2SH16(1, 4)
-    if (NL <= 64) RRT_DO2SH16(4, 2)
-    if (NL <= 256) RRT_DO2SH16(16, 1)
+    if (NL <= 16) {
+        if (rt == 1) RRT_DO2SH16(1, 1)
+        if (rt == 2) RRT_DO2SH16(1, 2)
+        if (rt == 0 || rt == 4) RRT_DO2SH16(1, 4)
+    } else if (NL <= 64) {
+        if (rt == 1) RRT_DO2SH16(4, 1)
+        if (rt == 0 || rt == 2) RRT_DO2SH16(4, 2)
+        if (rt == 4) RRT_DO2SH16(4, 4)
+    } else if (NL <= 256) {
+        if (rt == 0 || rt == 1) RRT_DO2SH16(16, 1)
+    }
 #undef RRT_DO2SH16
     return false;
 }
@@ -1895,15 +1910,23 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_unboost<float>),
                          reinterpret_cast<const void *>(&k_unboost<double>),
                          reinterpret_cast<const void *>(&k_source_compton<float>),
+                         reinterpret_cast<const void *>(&k_do2sh_f16<1, 1>),
+                         reinterpret_cast<const void *>(&k_do2sh_f16<1, 2>),
                          reinterpret_cast<const void *>(&k_do2sh_f16<1, 4>),
+                         reinterpret_cast<const void *>(&k_do2sh_f16<4, 1>),
                          reinterpret_cast<const void *>(&k_do2sh_f16<4, 2>),
+                         reinterpret_cast<const void *>(&k_do2sh_f16<4, 4>),
                          reinterpret_cast<const void *>(&k_do2sh_f16<16, 1>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<1>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<2>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<4>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<8>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32<1, 1>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32<1, 2>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<1, 4>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32<4, 1>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<4, 2>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32<4, 4>),
                          reinterpret_cast<const void *>(&k_source_compton<double>)};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
