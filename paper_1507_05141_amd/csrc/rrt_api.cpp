@@ -433,7 +433,7 @@ struct Engine {
                 return RRT_OK;
             }
         }
-        if (!pr->gc_forced) {
+        if (!pr->gc_forced && gc_candidates().size() > 1) {
             const auto c = gc_candidates();
             float best = INFINITY;
             int pick = pr->Gc;
@@ -444,7 +444,7 @@ struct Engine {
             }
             pr->Gc = pick;
         }
-        {
+        if (s6_candidates().size() > 1) {
             const auto c = s6_candidates();
             float best = INFINITY;
             int pick = pr->s6;

@@ -1423,6 +1423,111 @@ __global__ void __launch_bounds__(256) k_source_compton(SourceArgs<real> a)
     }
 }
 
+// Compton source on the matrix cores (FP32, G <= 32, L <= 15): for each l the
+// group-to-group product S_l = A_l I_l is a 32 x 32 (j x i) by 32 x (2l + 1)
+// (i x q) product, one v_mfma_f32_32x32x2f32 chain of K = 32.  Wave w takes the
+// angular orders l = w, w + 4, w + 8, w + 12 and holds their A_l in registers
+// for the whole launch; the workgroup walks points (persistent), staging a
+// point's SH intensities in LDS while the next point's are loaded into
+// registers, and gathers the products in LDS for 16-byte scaled stores.
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+constexpr int kComptonMfmaThreads = 256;
+
+__global__ void __launch_bounds__(kComptonMfmaThreads, 2) k_source_compton_mfma(SourceArgs<float> a, int lmax)
+{
+    using P4 = Pack<float, 4>;
+    extern __shared__ unsigned char smem_raw[];
+    const int G = a.G, NL = a.NL, GN = G * NL, GN4 = GN >> 2;
+    float *sI = reinterpret_cast<float *>(smem_raw);     // [G][NL] intensities of the point
+    float *sS = sI + GN;                                   // [G][NL] products of the point
+    float *sF = sS + GN;                                   // [G] sigma / chi_j (0 where chi_j = 0)
+    float *sT = sF + G;                                    // [G] thermal term of q = 0
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int n = lane & 31, kh = lane >> 5;               // B / C column, K half
+    // A_l[m][k] for this wave's orders: lane holds m = n, k = 2 ks + kh
+    float Areg[4][16];
+#pragma unroll
+    for (int t = 0; t < 4; ++t) {
+        const int l = wave + 4 * t;
+#pragma unroll
+        for (int ks = 0; ks < 16; ++ks) {
+            const int k = 2 * ks + kh;
+            Areg[t][ks] = (l <= lmax && n < G && k < G) ? a.A[((long)l * G + n) * G + k] : 0.0f;
+        }
+    }
+    constexpr int kPre = 8;                                // 16-byte loads per thread and point (G NL <= 8192)
+    P4 pre[kPre];
+    float pchi = 0.0f, pkap = 0.0f, pbnu = 0.0f, psig = 0.0f;
+    auto fetch = [&](long p) {
+        const P4 *src = reinterpret_cast<const P4 *>(a.Ilm + p * GN);
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const int i = tid + u * kComptonMfmaThreads;
+            if (i < GN4) pre[u] = src[i];
+        }
+        if (tid < G) {
+            pchi = a.chi0[p * G + tid];
+            pkap = a.kappa[p * G + tid];
+            pbnu = a.bnu[p * G + tid];
+            psig = a.sigma[p];
+        }
+    };
+    long p = blockIdx.x;
+    if (p < a.P) fetch(p);
+    for (; p < a.P; p += gridDim.x) {
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const int i = tid + u * kComptonMfmaThreads;
+            if (i < GN4) reinterpret_cast<P4 *>(sI)[i] = pre[u];
+        }
+        if (tid < G) {
+            const bool on = pchi > 0.0f;
+            sF[tid] = on ? psig / pchi : 0.0f;
+            sT[tid] = on ? 3.5449077018110318f * pkap * pbnu / pchi : 0.0f;
+        }
+        if (p + gridDim.x < a.P) fetch(p + gridDim.x);
+        __syncthreads();
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int l = wave + 4 * t;
+            if (l > lmax) break;
+            const int q0 = l * l, nq = 2 * l + 1;
+            f32x16 acc;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks) {
+                if (2 * ks >= G) break;
+                const int k = 2 * ks + kh;
+                const float b = (k < G && n < nq) ? sI[k * NL + q0 + n] : 0.0f;
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(Areg[t][ks], b, acc, 0, 0, 0);
+            }
+            // element (m, n) sits in register r of lane n + 32 ((m / 4) % 2), r = 4 (m / 8) + m % 4
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int m = 8 * (r >> 2) + 4 * kh + (r & 3);
+                if (m < G && n < nq) sS[m * NL + q0 + n] = acc[r];
+            }
+        }
+        __syncthreads();
+        // S[j][q] = sigma / chi_j (A I)[j][q], plus the thermal term at q = 0
+        float *dst = a.S + p * GN;
+#pragma unroll
+        for (int u = 0; u < kPre; ++u) {
+            const int i = tid + u * kComptonMfmaThreads;
+            if (i < GN4) {
+                const int j = (i * 4) / NL, q = i * 4 - j * NL;
+                const float f = sF[j];
+                P4 v = reinterpret_cast<const P4 *>(sS)[i];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) v.v[c] *= f;
+                if (q == 0) v.v[0] += sT[j];
+                reinterpret_cast<P4 *>(dst)[i] = v;
+            }
+        }
+    }
+}
+
 // chi0 = kappa + sigma * s_g
 template <typename real>
 __global__ void k_chi0(long P, int G, const real *__restrict__ kappa, const real *__restrict__ sigma,
@@ -1794,6 +1899,15 @@ template <typename real>
 void launch_source(const SourceArgs<real> &a, hipStream_t st)
 {
     if (a.compton) {
+        int lmax = 0;
+        while ((lmax + 1) * (lmax + 1) < a.NL) ++lmax;
+        if (sizeof(real) == 4 && a.G <= 32 && lmax <= 15 && (a.G * a.NL) % 4 == 0) {
+            const unsigned nb = (unsigned)std::min<long>(a.P, 2048);
+            hipLaunchKernelGGL(k_source_compton_mfma, dim3(nb), dim3(kComptonMfmaThreads),
+                               sizeof(float) * (2 * (size_t)a.G * a.NL + 2 * (size_t)a.G), st,
+                               *reinterpret_cast<const SourceArgs<float> *>(&a), lmax);
+            return;
+        }
         const unsigned nb = (unsigned)(8 * ((a.P + 7) / 8));
         hipLaunchKernelGGL(k_source_compton<real>, dim3(nb), dim3(256), sizeof(real) * (size_t)a.G * a.NL, st, a);
     } else {
@@ -1921,6 +2035,7 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_sh2do_f16<2>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<4>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<8>),
+                         reinterpret_cast<const void *>(&k_source_compton_mfma),
                          reinterpret_cast<const void *>(&k_do2sh_f32<1, 1>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<1, 2>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<1, 4>),
