@@ -1425,13 +1425,13 @@ __global__ void __launch_bounds__(256) k_source_compton(SourceArgs<real> a)
 
 // Compton source on the matrix cores (FP32, G <= 32, L <= 15): for each l the
 // group-to-group product S_l = A_l I_l is a 32 x 32 (j x i) by 32 x (2l + 1)
-// (i x q) product, one v_mfma_f32_32x32x2f32 chain of K = 32.  Wave w takes the
-// angular orders l = w, w + 4, w + 8, w + 12 and holds their A_l in registers
-// for the whole launch; the workgroup walks points (persistent), staging a
-// point's SH intensities in LDS while the next point's are loaded into
-// registers, and gathers the products in LDS for 16-byte scaled stores.
+// (i x q) product, one v_mfma_f32_32x32x2f32 chain of K = 32.  Wave w of eight
+// takes the angular orders l = w and w + 8 and holds their A_l in registers for
+// the whole launch; the workgroup walks points (persistent), staging a point's
+// SH intensities in LDS while the next point's are loaded into registers, and
+// gathers the products in LDS for 16-byte scaled stores.
 typedef float f32x16 __attribute__((ext_vector_type(16)));
-constexpr int kComptonMfmaThreads = 256;
+constexpr int kComptonMfmaThreads = 512;
 
 __global__ void __launch_bounds__(kComptonMfmaThreads, 2) k_source_compton_mfma(SourceArgs<float> a, int lmax)
 {
@@ -1445,17 +1445,19 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, 2) k_source_compton_mfma(
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = lane & 31, kh = lane >> 5;               // B / C column, K half
     // A_l[m][k] for this wave's orders: lane holds m = n, k = 2 ks + kh
-    float Areg[4][16];
+    float Areg[2][16];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) {
-        const int l = wave + 4 * t;
+    for (int t = 0; t < 2; ++t) {
+        const int l = wave + 8 * t;
 #pragma unroll
         for (int ks = 0; ks < 16; ++ks) {
             const int k = 2 * ks + kh;
             Areg[t][ks] = (l <= lmax && n < G && k < G) ? a.A[((long)l * G + n) * G + k] : 0.0f;
         }
     }
-    constexpr int kPre = 8;                                // 16-byte loads per thread and point (G NL <= 8192)
+    // the table must have arrived before the loop (keeps the loop free of waits on it)
+    __builtin_amdgcn_s_waitcnt(0);
+    constexpr int kPre = 4;                                // 16-byte loads per thread and point (G NL <= 8192)
     P4 pre[kPre];
     float pchi = 0.0f, pkap = 0.0f, pbnu = 0.0f, psig = 0.0f;
     auto fetch = [&](long p) {
@@ -1488,25 +1490,32 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, 2) k_source_compton_mfma(
         if (p + gridDim.x < a.P) fetch(p + gridDim.x);
         __syncthreads();
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int l = wave + 4 * t;
+        for (int t = 0; t < 2; ++t) {
+            const int l = wave + 8 * t;
             if (l > lmax) break;
             const int q0 = l * l, nq = 2 * l + 1;
+            // B operand: rows k >= G and columns n >= nq read real (finite) entries that
+            // meet zero A columns or land in unused output columns, so no lane branches
+            const float *col = sI + q0 + min(n, nq - 1);
+            float b[16];
+#pragma unroll
+            for (int ks = 0; ks < 16; ++ks) b[ks] = col[min(2 * ks + kh, G - 1) * NL];
+            // all sixteen reads issued before the first product (one wait instead of sixteen)
+            asm volatile("" : "+v"(b[0]), "+v"(b[1]), "+v"(b[2]), "+v"(b[3]), "+v"(b[4]), "+v"(b[5]), "+v"(b[6]),
+                         "+v"(b[7]), "+v"(b[8]), "+v"(b[9]), "+v"(b[10]), "+v"(b[11]), "+v"(b[12]), "+v"(b[13]),
+                         "+v"(b[14]), "+v"(b[15]));
             f32x16 acc;
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 #pragma unroll
-            for (int ks = 0; ks < 16; ++ks) {
-                if (2 * ks >= G) break;
-                const int k = 2 * ks + kh;
-                const float b = (k < G && n < nq) ? sI[k * NL + q0 + n] : 0.0f;
-                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(Areg[t][ks], b, acc, 0, 0, 0);
-            }
+            for (int ks = 0; ks < 16; ++ks) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(Areg[t][ks], b[ks], acc, 0, 0, 0);
             // element (m, n) sits in register r of lane n + 32 ((m / 4) % 2), r = 4 (m / 8) + m % 4
+            if (n < nq) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int m = 8 * (r >> 2) + 4 * kh + (r & 3);
-                if (m < G && n < nq) sS[m * NL + q0 + n] = acc[r];
+                for (int r = 0; r < 16; ++r) {
+                    const int m = 8 * (r >> 2) + 4 * kh + (r & 3);
+                    if (m < G) sS[m * NL + q0 + n] = acc[r];
+                }
             }
         }
         __syncthreads();
