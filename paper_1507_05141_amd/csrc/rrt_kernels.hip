@@ -1428,22 +1428,25 @@ __global__ void __launch_bounds__(256) k_source_compton(SourceArgs<real> a)
 // (i x q) product, one v_mfma_f32_32x32x2f32 chain of K = 32.  Wave w of eight
 // takes the angular orders l = w and w + 8 and holds their A_l in registers for
 // the whole launch; the workgroup walks points (persistent), staging a point's
-// SH intensities in LDS while the next point's are loaded into registers, and
-// gathers the products in LDS for 16-byte scaled stores.
+// SH intensities in LDS while the next point's are loaded into registers.  The
+// products overwrite the intensities in LDS (a wave writes only the columns of
+// its own orders, after it has read them) and leave as 16-byte scaled stores.
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kComptonMfmaThreads = 512;
 
-__global__ void __launch_bounds__(kComptonMfmaThreads, 2) k_source_compton_mfma(SourceArgs<float> a, int lmax)
+__global__ void __launch_bounds__(kComptonMfmaThreads, 4) k_source_compton_mfma(SourceArgs<float> a, int lmax)
 {
     using P4 = Pack<float, 4>;
+    constexpr int RS = 256;                                // LDS row stride (the largest NL), 32 rows
     extern __shared__ unsigned char smem_raw[];
-    const int G = a.G, NL = a.NL, GN = G * NL, GN4 = GN >> 2;
-    float *sI = reinterpret_cast<float *>(smem_raw);     // [G][NL] intensities of the point
-    float *sS = sI + GN;                                   // [G][NL] products of the point
-    float *sF = sS + GN;                                   // [G] sigma / chi_j (0 where chi_j = 0)
+    const int G = a.G, NL = a.NL, GN = G * NL, GN4 = GN >> 2, NL4 = NL >> 2;
+    float *sI = reinterpret_cast<float *>(smem_raw);     // [32][RS] intensities, then products, of the point
+    float *sF = sI + 32 * RS;                              // [G] sigma / chi_j (0 where chi_j = 0)
     float *sT = sF + G;                                    // [G] thermal term of q = 0
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = lane & 31, kh = lane >> 5;               // B / C column, K half
+    // rows G..31 stay zero: they meet zero columns of A
+    for (int i = G * RS + tid; i < 32 * RS; i += kComptonMfmaThreads) sI[i] = 0.0f;
     // A_l[m][k] for this wave's orders: lane holds m = n, k = 2 ks + kh
     float Areg[2][16];
 #pragma unroll
@@ -1480,7 +1483,10 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, 2) k_source_compton_mfma(
 #pragma unroll
         for (int u = 0; u < kPre; ++u) {
             const int i = tid + u * kComptonMfmaThreads;
-            if (i < GN4) reinterpret_cast<P4 *>(sI)[i] = pre[u];
+            if (i < GN4) {
+                const int j = i / NL4, q = (i - j * NL4) * 4;
+                *reinterpret_cast<P4 *>(sI + j * RS + q) = pre[u];
+            }
         }
         if (tid < G) {
             const bool on = pchi > 0.0f;
@@ -1494,12 +1500,11 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, 2) k_source_compton_mfma(
             const int l = wave + 8 * t;
             if (l > lmax) break;
             const int q0 = l * l, nq = 2 * l + 1;
-            // B operand: rows k >= G and columns n >= nq read real (finite) entries that
-            // meet zero A columns or land in unused output columns, so no lane branches
-            const float *col = sI + q0 + min(n, nq - 1);
+            // B operand: columns n >= nq repeat the last column (their outputs are not kept)
+            const float *col = sI + kh * RS + q0 + min(n, nq - 1);
             float b[16];
 #pragma unroll
-            for (int ks = 0; ks < 16; ++ks) b[ks] = col[min(2 * ks + kh, G - 1) * NL];
+            for (int ks = 0; ks < 16; ++ks) b[ks] = col[2 * ks * RS];
             // all sixteen reads issued before the first product (one wait instead of sixteen)
             asm volatile("" : "+v"(b[0]), "+v"(b[1]), "+v"(b[2]), "+v"(b[3]), "+v"(b[4]), "+v"(b[5]), "+v"(b[6]),
                          "+v"(b[7]), "+v"(b[8]), "+v"(b[9]), "+v"(b[10]), "+v"(b[11]), "+v"(b[12]), "+v"(b[13]),
@@ -1509,12 +1514,13 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, 2) k_source_compton_mfma(
             for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 #pragma unroll
             for (int ks = 0; ks < 16; ++ks) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(Areg[t][ks], b[ks], acc, 0, 0, 0);
-            // element (m, n) sits in register r of lane n + 32 ((m / 4) % 2), r = 4 (m / 8) + m % 4
+            // element (m, n) sits in register r of lane n + 32 ((m / 4) % 2), r = 4 (m / 8) + m % 4;
+            // it overwrites the intensity it replaces (this wave's own columns, already read)
             if (n < nq) {
 #pragma unroll
                 for (int r = 0; r < 16; ++r) {
                     const int m = 8 * (r >> 2) + 4 * kh + (r & 3);
-                    if (m < G) sS[m * NL + q0 + n] = acc[r];
+                    if (m < G) sI[m * RS + q0 + n] = acc[r];
                 }
             }
         }
@@ -1525,15 +1531,16 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, 2) k_source_compton_mfma(
         for (int u = 0; u < kPre; ++u) {
             const int i = tid + u * kComptonMfmaThreads;
             if (i < GN4) {
-                const int j = (i * 4) / NL, q = i * 4 - j * NL;
+                const int j = i / NL4, q = (i - j * NL4) * 4;
                 const float f = sF[j];
-                P4 v = reinterpret_cast<const P4 *>(sS)[i];
+                P4 v = *reinterpret_cast<const P4 *>(sI + j * RS + q);
 #pragma unroll
                 for (int c = 0; c < 4; ++c) v.v[c] *= f;
                 if (q == 0) v.v[0] += sT[j];
                 reinterpret_cast<P4 *>(dst)[i] = v;
             }
         }
+        __syncthreads();                                   // the next point overwrites the table and factors
     }
 }
 
@@ -1910,10 +1917,10 @@ void launch_source(const SourceArgs<real> &a, hipStream_t st)
     if (a.compton) {
         int lmax = 0;
         while ((lmax + 1) * (lmax + 1) < a.NL) ++lmax;
-        if (sizeof(real) == 4 && a.G <= 32 && lmax <= 15 && (a.G * a.NL) % 4 == 0) {
+        if (sizeof(real) == 4 && a.G <= 32 && lmax <= 15 && a.NL % 4 == 0) {
             const unsigned nb = (unsigned)std::min<long>(a.P, 2048);
             hipLaunchKernelGGL(k_source_compton_mfma, dim3(nb), dim3(kComptonMfmaThreads),
-                               sizeof(float) * (2 * (size_t)a.G * a.NL + 2 * (size_t)a.G), st,
+                               sizeof(float) * (32 * 256 + 2 * (size_t)a.G), st,
                                *reinterpret_cast<const SourceArgs<float> *>(&a), lmax);
             return;
         }
