@@ -102,20 +102,40 @@ def serving_bench(args):
     as a Poisson stream at 0.8 x the FP32 capacity, in FP32 and in mixed precision."""
     from paper_1507_05141_amd import binding as B
     from paper_1507_05141_amd import serving as SV
-    budget = 64 << 30
+    if args.mix == "full":
+        # every grid, group count and SH order of the batched workload, up to 64^3 x 32 x L = 15
+        mix = dict(sizes=(16, 24, 32, 48, 64), groups=(4, 8, 16, 32), lmaxes=(3, 7, 15))
+        budget = 240 << 30
+        workload = "request mix: n in {16,24,32,48,64}, G in {4,8,16,32}, L in {3,7,15}, Thomson/Compton"
+        # Compton requests at n_e sigma_T near 10 do not converge (the FP64 oracle neither): a
+        # request gives up after 150 Lambda iterations (converged ones need at most ~90)
+        max_iter = 150
+    else:
+        mix = {}
+        budget = 64 << 30
+        workload = "request mix: n in {16,24,32}, G in {4,8,16}, L in {3,7}, Thomson/Compton"
+        max_iter = 300
     SV.serve(SV.poisson_requests(4, rate=0.0, seed=1), precision=B.FP32, budget_bytes=budget)     # warm-up
     SV.serve(SV.poisson_requests(4, rate=0.0, seed=1), precision=B.MIXED, budget_bytes=budget)
-    burst = SV.poisson_requests(args.requests, rate=0.0, seed=5)
+    burst = SV.poisson_requests(args.requests, rate=0.0, seed=5, **mix)
     cap = {}
-    for name, prec, graphs in (("fp32_eager", B.FP32, False), ("fp32", B.FP32, True), ("mixed", B.MIXED, True)):
-        recs, wall = SV.serve(burst, precision=prec, budget_bytes=budget, graphs=graphs)
+    runs = (("fp32_eager", B.FP32, False), ("fp32", B.FP32, True), ("mixed", B.MIXED, True))
+    if args.mix == "full":
+        runs = runs[1:]
+    def progress(done, total):
+        if done % 8 == 0 or done == total:
+            print(f"  {done}/{total} requests finished", file=sys.stderr, flush=True)
+
+    for name, prec, graphs in runs:
+        recs, wall = SV.serve(burst, precision=prec, budget_bytes=budget, graphs=graphs, progress=progress,
+                              max_iter=max_iter)
         cap[name] = SV.summary(recs, wall)
         print(f"capacity {name}: {cap[name]['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
     rate = 0.8 * cap["fp32"]["solves_per_s"]
-    stream = SV.poisson_requests(args.requests, rate=rate, seed=5)
+    stream = SV.poisson_requests(args.requests, rate=rate, seed=5, **mix)
     res = {}
     for name, prec in (("fp32", B.FP32), ("mixed", B.MIXED)):
-        recs, wall = SV.serve(stream, precision=prec, budget_bytes=budget)
+        recs, wall = SV.serve(stream, precision=prec, budget_bytes=budget, progress=progress, max_iter=max_iter)
         res[name] = SV.summary(recs, wall)
         print(f"stream {name}: p50 {res[name]['p50_ms']:.1f} ms p99 {res[name]['p99_ms']:.1f} ms", file=sys.stderr,
               flush=True)
@@ -123,8 +143,9 @@ def serving_bench(args):
             "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
             "dtype": "f32+f16mfma", "data": "synthetic",
             "p50_ms": res["mixed"]["p50_ms"], "p99_ms": res["mixed"]["p99_ms"],
-            "config": {"workload": "request mix: n in {16,24,32}, G in {4,8,16}, L in {3,7}, Thomson/Compton",
-                       "requests": args.requests, "arrival_rate_per_s": rate, "tol": 1e-6, "hbm_budget_bytes": budget},
+            "config": {"workload": workload,
+                       "requests": args.requests, "arrival_rate_per_s": rate, "tol": 1e-6, "max_iter": max_iter,
+                       "hbm_budget_bytes": budget},
             "capacity": cap, "stream": res}
 
 
@@ -142,6 +163,8 @@ def main():
     ap.add_argument("--serving", action="store_true",
                     help="continuous batching of a stream of solve requests instead of sweeps: solves/s, p50/p99 latency")
     ap.add_argument("--requests", type=int, default=48, help="requests in the --serving stream")
+    ap.add_argument("--mix", choices=["small", "full"], default="small",
+                    help="--serving request mix: small (n <= 32, G <= 16, L <= 7) or full (n <= 64, G <= 32, L <= 15)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")

@@ -64,12 +64,13 @@ def poisson_requests(count, rate, seed, **mix):
 
 
 def serve(requests, precision=B.FP32, budget_bytes=64 << 30, tol=1e-6, max_iter=300, use_ng=True, keep=None,
-          graphs=True):
+          graphs=True, progress=None):
     """Run the request stream; returns per-request records and the run's wall time.
 
     keep(i, problem) -> dict, if given, is called on each finished problem
     before it is destroyed (e.g. to read its moments).  graphs=False runs every
-    sweep eagerly instead of replaying captured sweeps."""
+    sweep eagerly instead of replaying captured sweeps.  progress(done, total),
+    if given, is called whenever a request finishes or is rejected."""
     batch = B.Batch(budget_bytes)
     pending = list(range(len(requests)))           # not yet admitted, in arrival order
     running = {}                                    # request -> Problem
@@ -99,6 +100,8 @@ def serve(requests, precision=B.FP32, budget_bytes=64 << 30, tol=1e-6, max_iter=
                     pending.pop(0)
                     recs[i] = {"arrival": requests[i]["arrival"], "rejected": True, "latency": now() - requests[i]["arrival"],
                                "iters": 0, "converged": False, **requests[i]["meta"]}
+                    if progress is not None:
+                        progress(sum(r is not None and "latency" in r for r in recs), len(requests))
                     continue
                 pending.pop(0)
                 running[i] = pr
@@ -123,6 +126,8 @@ def serve(requests, precision=B.FP32, budget_bytes=64 << 30, tol=1e-6, max_iter=
                     recs[i].update(keep(i, pr))
                 pr.close()
                 used -= reserved.pop(i)
+                if progress is not None:
+                    progress(sum(r is not None and "latency" in r for r in recs), len(requests))
     finally:
         for pr in running.values():
             pr.close()
@@ -131,8 +136,12 @@ def serve(requests, precision=B.FP32, budget_bytes=64 << 30, tol=1e-6, max_iter=
 
 
 def summary(recs, wall):
-    lat = np.array([r["latency"] for r in recs])
-    return {"requests": len(recs), "solves_per_s": len(recs) / wall, "wall_s": wall,
+    """Solves per second, latency percentiles and iteration counts of the served
+    (not rejected) requests."""
+    done = [r for r in recs if not r.get("rejected")]
+    lat = np.array([r["latency"] for r in done]) if done else np.zeros(1)
+    return {"requests": len(recs), "rejected": len(recs) - len(done), "solves_per_s": len(done) / wall, "wall_s": wall,
             "p50_ms": float(np.percentile(lat, 50) * 1e3), "p99_ms": float(np.percentile(lat, 99) * 1e3),
-            "mean_iters": float(np.mean([r["iters"] for r in recs])),
-            "all_converged": bool(all(r["converged"] for r in recs))}
+            "mean_iters": float(np.mean([r["iters"] for r in done])) if done else 0.0,
+            "not_converged": sum(not r["converged"] for r in done),
+            "all_converged": bool(all(r["converged"] for r in done))}
