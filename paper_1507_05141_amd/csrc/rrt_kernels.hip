@@ -1216,8 +1216,8 @@ __device__ __forceinline__ float quad_max(float m)
 // S6 mixed: Ilm[r][q] = sum_j I0[r][j] WYt[q][j]; WYt = hi, lo FP16 tables [NT*16][Kp], Kp = K up to 32.
 // A workgroup of 4 waves takes 64 RT rows (a wave RT tiles of 16 rows); the table is
 // staged in LDS per chunk of 64 ordinates ([NT*16][64 + 8] per part).
-template <int NT, int RT>
-__global__ void __launch_bounds__(256) k_do2sh_f16(long R, int K, int Kp, int NL, const float *__restrict__ A,
+template <int NT, int RT, int W = 4>
+__global__ void __launch_bounds__(64 * W) k_do2sh_f16(long R, int K, int Kp, int NL, const float *__restrict__ A,
                                                    const _Float16 *__restrict__ WYh, const _Float16 *__restrict__ WYl,
                                                    float *__restrict__ C)
 {
@@ -1225,7 +1225,7 @@ __global__ void __launch_bounds__(256) k_do2sh_f16(long R, int K, int Kp, int NL
     extern __shared__ unsigned char smem_raw[];
     _Float16 *Th = reinterpret_cast<_Float16 *>(smem_raw), *Tl = Th + NC * LS;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
-    const long r0 = (long)xcd_item(gridDim.x) * (64 * RT) + wave * (16 * RT);
+    const long r0 = (long)xcd_item(gridDim.x) * (16 * W * RT) + wave * (16 * RT);
     const bool vec = (K & 3) == 0;
     const float *Arow[RT];
 #pragma unroll
@@ -1302,8 +1302,8 @@ __global__ void __launch_bounds__(256) k_do2sh_f16(long R, int K, int Kp, int NL
 // S2 mixed: S0[r][j] = sum_q S[r][q] Y[j][q]; Y = hi, lo FP16 tables [Kt][NLp] (Kt = K up to 16,
 // NLp = NL up to 32, NB = NLp / 32 blocks); one scale per row.  A workgroup of 4 waves takes 64
 // rows; the table is staged in LDS per chunk of 64 ordinates ([64][NLp + 8] per part).
-template <int NB>
-__global__ void __launch_bounds__(256) k_sh2do_f16(long R, int K, int NL, const float *__restrict__ S,
+template <int NB, int W = 4>
+__global__ void __launch_bounds__(64 * W) k_sh2do_f16(long R, int K, int NL, const float *__restrict__ S,
                                                    const _Float16 *__restrict__ Yh, const _Float16 *__restrict__ Yl,
                                                    float *__restrict__ C)
 {
@@ -1311,7 +1311,7 @@ __global__ void __launch_bounds__(256) k_sh2do_f16(long R, int K, int NL, const 
     extern __shared__ unsigned char smem_raw[];
     _Float16 *Th = reinterpret_cast<_Float16 *>(smem_raw), *Tl = Th + JC * LS;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
-    const long r0 = (long)xcd_item(gridDim.x) * 64 + wave * 16;
+    const long r0 = (long)xcd_item(gridDim.x) * (16 * W) + wave * 16;
     const int Kt = (K + 15) / 16 * 16;
     const float *__restrict__ Srow = S + min(r0 + lr, R - 1) * (long)NL;
     float v[NB][8];
@@ -1890,7 +1890,15 @@ bool launch_do2sh_f16(long R, int K, int NL, const float *A, const _Float16 *WYh
         if (rt == 0 || rt == 2) RRT_DO2SH16(4, 2)
         if (rt == 4) RRT_DO2SH16(4, 4)
     } else if (NL <= 256) {
-        if (rt == 0 || rt == 1) RRT_DO2SH16(16, 1)
+        // eight waves share each staged table chunk
+        if (rt == 0 || rt == 1) {
+            const long nb = (R + 127) / 128;
+            if (nb > 0x7fffffffL) return false;
+            const size_t sm = 2 * sizeof(_Float16) * (size_t)(16 * 16) * 72;
+            hipLaunchKernelGGL((k_do2sh_f16<16, 1, 8>), dim3((unsigned)(8 * ((nb + 7) / 8))), dim3(512), sm, st, R, K,
+                               Kp, NL, A, WYh, WYl, C);
+            return true;
+        }
     }
 #undef RRT_DO2SH16
     return false;
@@ -1906,7 +1914,13 @@ bool launch_sh2do_f16(long R, int K, int NL, const float *S, const _Float16 *Yh,
     if (NL <= 32) hipLaunchKernelGGL(k_sh2do_f16<1>, grid, block, sm(1), st, R, K, NL, S, Yh, Yl, C);
     else if (NL <= 64) hipLaunchKernelGGL(k_sh2do_f16<2>, grid, block, sm(2), st, R, K, NL, S, Yh, Yl, C);
     else if (NL <= 128) hipLaunchKernelGGL(k_sh2do_f16<4>, grid, block, sm(4), st, R, K, NL, S, Yh, Yl, C);
-    else if (NL <= 256) hipLaunchKernelGGL(k_sh2do_f16<8>, grid, block, sm(8), st, R, K, NL, S, Yh, Yl, C);
+    else if (NL <= 256) {
+        // eight waves share each staged table chunk
+        const long nb8 = (R + 127) / 128;
+        if (nb8 > 0x7fffffffL) return false;
+        hipLaunchKernelGGL((k_sh2do_f16<8, 8>), dim3((unsigned)(8 * ((nb8 + 7) / 8))), dim3(512), sm(8), st, R, K, NL, S,
+                           Yh, Yl, C);
+    }
     else return false;
     return true;
 }
@@ -2046,11 +2060,11 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_do2sh_f16<4, 1>),
                          reinterpret_cast<const void *>(&k_do2sh_f16<4, 2>),
                          reinterpret_cast<const void *>(&k_do2sh_f16<4, 4>),
-                         reinterpret_cast<const void *>(&k_do2sh_f16<16, 1>),
+                         reinterpret_cast<const void *>(&k_do2sh_f16<16, 1, 8>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<1>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<2>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<4>),
-                         reinterpret_cast<const void *>(&k_sh2do_f16<8>),
+                         reinterpret_cast<const void *>(&k_sh2do_f16<8, 8>),
                          reinterpret_cast<const void *>(&k_source_compton_mfma),
                          reinterpret_cast<const void *>(&k_do2sh_f32<1, 1>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<1, 2>),

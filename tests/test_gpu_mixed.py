@@ -46,7 +46,7 @@ def moment_errors(got, ref, decades=None):
 
 
 @pytest.mark.parametrize("case", ["thomson_log", "high_gamma_L7", "grey_extinction_8g", "compton_log_keV",
-                                  "lmax0_min_z"])
+                                  "lmax0_min_z", "compton_L15"])
 def test_mixed_sweep_against_oracle(case):
     spec = custom_spec(**CASES[case])
     o = oracle.Oracle(spec)
