@@ -461,25 +461,33 @@ struct Engine {
         return RRT_OK;
     }
 
-    // S1: source from d_Ilm into S
-    void source(void *S)
+    // S1: source from d_Ilm into S; with Sold, the residual's row sums against it in the
+    // same pass where the kernel allows (returns whether it did)
+    bool source(void *S, const void *Sold = nullptr)
     {
         rrt::SourceArgs<real> s;
         s.P = pr->P; s.G = pr->G; s.NL = pr->NL; s.compton = pr->scatter == RRT_COMPTON;
         s.chi0 = R(pr->d_chi0); s.sigma = R(pr->d_sigma); s.kappa = R(pr->d_kappa); s.bnu = R(pr->d_bnu);
         s.A = R(pr->d_A); s.Ilm = R(pr->d_Ilm); s.S = R(S);
         prof_begin(pr, KI_SOURCE);
-        rrt::launch_source<real>(s, pr->stream);
+        const bool fused = Sold && rrt::launch_source_resid<real>(s, static_cast<const real *>(Sold), pr->d_partial,
+                                                                  pr->stream);
+        if (!fused) rrt::launch_source<real>(s, pr->stream);
         prof_end(pr, KI_SOURCE);
+        return fused;
     }
 
     // S8: max over groups of ||a - b|| / ||a||
     // S8, queued: per-group sums into the pinned host buffer (read after the stream is synchronized)
-    rrt_status residual_launch(const void *a, const void *b)
+    // rows_ready: the per-row sums are already in d_partial (fused into the source step)
+    rrt_status residual_launch(const void *a, const void *b, bool rows_ready = false)
     {
         prof_begin(pr, KI_REDUCE);
-        rrt::launch_resid<real>(pr->P, pr->G, pr->NL, static_cast<const real *>(a), static_cast<const real *>(b),
-                                pr->d_partial, pr->nblk_red, pr->d_red, pr->stream);
+        if (rows_ready)
+            rrt::launch_resid_groups<real>(pr->P, pr->G, pr->d_partial, pr->d_red, pr->stream);
+        else
+            rrt::launch_resid<real>(pr->P, pr->G, pr->NL, static_cast<const real *>(a), static_cast<const real *>(b),
+                                    pr->d_partial, pr->nblk_red, pr->d_red, pr->stream);
         prof_end(pr, KI_REDUCE);
         rrt_status s = check_launch();
         if (s) return s;
@@ -569,9 +577,9 @@ struct Engine {
         if (s) return s;
         trace(pr->d_St, pr->d_Ilab, inv_cdt, false);
         if ((s = fold(pr->d_Ilab))) return s;
-        source(pr->d_Snew);
+        const bool fused = source(pr->d_Snew, pr->d_S);
         if ((s = check_launch())) return s;
-        s = residual_launch(pr->d_Snew, pr->d_S);
+        s = residual_launch(pr->d_Snew, pr->d_S, fused);
         if (s) return s;
         std::swap(pr->d_S, pr->d_Snew);
         return RRT_OK;

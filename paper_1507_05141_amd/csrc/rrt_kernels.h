@@ -141,6 +141,10 @@ bool launch_do2sh_f16(long R, int K, int NL, const float *A, const _Float16 *WYh
 bool launch_sh2do_f16(long R, int K, int NL, const float *S, const _Float16 *Yh, const _Float16 *Yl, float *C,
                       hipStream_t st);
 template <typename real> void launch_source(const SourceArgs<real> &a, hipStream_t st);
+// Thomson source with the residual's per-row sums against Sold (rows[2 r], rows[2 r + 1]) in the
+// same pass; false (nothing launched) for Compton or NL not dividing 64
+template <typename real> bool launch_source_resid(const SourceArgs<real> &a, const real *Sold, double *rows, hipStream_t st);
+template <typename real> void launch_resid_groups(long P, int G, const double *rows, double *out, hipStream_t st);
 template <typename real> void launch_chi0(long P, int G, const real *kappa, const real *sigma, const real *sg, real *chi0, hipStream_t st);
 template <typename real> void launch_moments_lab(long P, int G, int K, const double *dir, const real *I, double *J, double *H, double *Kt, hipStream_t st);
 template <typename real> void launch_moments_co(long PG, int NL, int lmax, const real *Ilm, double *J, double *H, double *Kt, hipStream_t st);

@@ -1390,6 +1390,50 @@ __global__ void __launch_bounds__(256) k_source(SourceArgs<real> a)
     a.S[idx] = v;
 }
 
+// Thomson source fused with the residual's row sums (NL dividing 64): a wave
+// takes 64 / NL (point, group) rows, computes their new source coefficients,
+// and reduces sum (S_new - S_old)^2 and sum S_new^2 of each row in FP64 across
+// the row's lanes; rows[2 r], rows[2 r + 1] receive them (the per-group totals
+// follow in k_resid_groups)
+template <typename real>
+__global__ void __launch_bounds__(256) k_source_resid(SourceArgs<real> a, const real *__restrict__ Sold, double *rows)
+{
+    const int G = a.G, NL = a.NL, RW = 64 / NL;
+    const long PG = a.P * G;
+    const int lane = threadIdx.x & 63, sub = lane / NL, q = lane - sub * NL;
+    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long nwaves = ((long)gridDim.x * blockDim.x) >> 6;
+    int l = (int)sqrtf((float)q);
+    while (l * l > q) --l;
+    while ((l + 1) * (l + 1) <= q) ++l;
+    const real cl = (l == 0) ? real(1) : (l == 2 ? real(0.1) : real(0));   // chi_l/(2l+1), Thomson
+    for (long r0 = wave * RW; r0 < PG; r0 += nwaves * RW) {
+        const long r = r0 + sub;
+        double dd = 0.0, aa = 0.0;
+        if (r < PG) {
+            const long idx = r * NL + q, p = r / G;
+            const real chi = a.chi0[r];
+            real v = 0;
+            if (chi > real(0)) {
+                v = a.sigma[p] / chi * cl * a.Ilm[idx];
+                if (q == 0) v += real(3.5449077018110318) * a.kappa[r] * a.bnu[r] / chi;   // sqrt(4 pi) kappa B / chi
+            }
+            a.S[idx] = v;
+            const double u = (double)v, d = u - (double)Sold[idx];
+            dd = d * d;
+            aa = u * u;
+        }
+        for (int off = NL >> 1; off > 0; off >>= 1) {
+            dd += __shfl_xor(dd, off, 64);
+            aa += __shfl_xor(aa, off, 64);
+        }
+        if (q == 0 && r < PG) {
+            rows[2 * r] = dd;
+            rows[2 * r + 1] = aa;
+        }
+    }
+}
+
 // Compton: one workgroup per point; its SH intensities I[i][q] (all groups) are
 // staged in LDS and S[j][q] = sigma/chi_j sum_i A_l(q)[j][i] I[i][q] + T_q
 template <typename real>
@@ -1960,6 +2004,20 @@ void launch_moments_co(long PG, int NL, int lmax, const real *Ilm, double *J, do
     hipLaunchKernelGGL(k_moments_co<real>, dim3(blocks_for(PG, 256)), dim3(256), 0, st, PG, NL, lmax, Ilm, J, H, Kt);
 }
 template <typename real>
+bool launch_source_resid(const SourceArgs<real> &a, const real *Sold, double *rows, hipStream_t st)
+{
+    if (a.compton || a.NL > 64 || 64 % a.NL != 0) return false;
+    const long waves = (a.P * a.G + 64 / a.NL - 1) / (64 / a.NL);
+    const unsigned nb = (unsigned)std::min<long>((waves + 3) / 4, 16384);
+    hipLaunchKernelGGL(k_source_resid<real>, dim3(nb), dim3(256), 0, st, a, Sold, rows);
+    return true;
+}
+template <typename real>
+void launch_resid_groups(long P, int G, const double *rows, double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_resid_groups, dim3(2 * G), dim3(256), 0, st, P, G, rows, out);
+}
+template <typename real>
 void launch_resid(long P, int G, int NL, const real *a, const real *b, double *rows, int nblk, double *out, hipStream_t st)
 {
     (void)nblk;
@@ -2090,6 +2148,8 @@ hipError_t set_lds_limits(size_t bytes)
     template void launch_chilab<real>(const ChiLabArgs<real> &, hipStream_t);                                   \
     template void launch_remap_plan<real>(const PlanArgs<real> &, hipStream_t);                                   \
     template void launch_source<real>(const SourceArgs<real> &, hipStream_t);                                   \
+    template bool launch_source_resid<real>(const SourceArgs<real> &, const real *, double *, hipStream_t);     \
+    template void launch_resid_groups<real>(long, int, const double *, double *, hipStream_t);                  \
     template void launch_chi0<real>(long, int, const real *, const real *, const real *, real *, hipStream_t);  \
     template void launch_moments_lab<real>(long, int, int, const double *, const real *, double *, double *,    \
                                            double *, hipStream_t);                                              \
