@@ -625,13 +625,17 @@ def _rk_scalar(I, dt, kap, B):
     return I + d1 + d2 + d3 + d4
 
 
+@pytest.mark.parametrize("kap", [0.8, 2560.0], ids=["mild", "stiff"])
 @pytest.mark.parametrize("scheme", ["rk4", "euler"])
-def test_interior_follows_the_scalar_time_recursion(scheme):
+def test_interior_follows_the_scalar_time_recursion(scheme, kap):
     """Deep inside a uniform medium the implicit solve of each stage reduces to
     I = (kappa B + I_prev/(c dt))/(kappa + 1/(c dt)); boundary influence is
-    damped by exp(-dz/(c dt)) per plane."""
+    damped by exp(-dz/(c dt)) per plane.  The stiff case (kappa c dt = 20) pins
+    the four-stage scheme's amplification of stiff modes: per step the
+    deviation from kappa B grows by G(20) = 3.675 (G -> 9 as kappa c dt grows),
+    where the single implicit stage damps it by 1/21."""
     n, nz = 3, 20
-    kap, sig, B = 0.8, 0.5, 2.0
+    sig, B = 0.5, 2.0
     o = oracle.Oracle(spec_uniform(n=n, nz=nz, nmu=4, nphi=8, lmax=3, kappa=kap, sigma=sig, B=B))
     dt = 0.5 / 64
     I0 = np.full(o.lab_shape(), 0.3)
@@ -641,6 +645,38 @@ def test_interior_follows_the_scalar_time_recursion(scheme):
         s = _rk_scalar(s, dt, kap, B) if scheme == "rk4" else _stage(s, dt, kap, B)
     planes = I.reshape(o.K, nz, n * n)[:, 6:nz - 6]
     assert np.allclose(planes, s, rtol=1e-12)
+    if kap > 100:
+        z = kap * dt
+        g = (s - B) / (0.3 - B)
+        expect = (1.0 / (1.0 + z)) ** 3 if scheme == "euler" else _rk_scalar(1.0, dt, kap, 0.0) ** 3
+        assert np.isclose(g, expect, rtol=1e-10)
+        if scheme == "rk4":
+            assert abs(_rk_scalar(1.0, dt, kap, 0.0) - 3.67536) < 1e-4
+
+
+def test_scattering_pulse_follows_the_diffusion_solution():
+    """An isotropic Gaussian pulse (width 0.09) in a purely scattering slab two
+    optical depths per cell thick spreads as the diffusion equation's Gaussian
+    with D = c/(3 sigma) (the paper's optically thick test, Eq. 16), and keeps
+    its photon number (backward Euler steps; the four-stage scheme amplifies
+    the stiff modes of such a medium at this step, see the scalar recursion)."""
+    n, nz = 2, 64
+    sig, w = 2.0 * (nz - 1), 0.09
+    z = np.arange(nz) / (nz - 1)
+    o = oracle.Oracle(spec_uniform(n=n, nz=nz, nmu=4, nphi=8, lmax=3, kappa=0.0, sigma=sig, B=0.0))
+    prof = 100 * np.exp(-((z - 0.5) / w) ** 2)
+    I0 = np.zeros(o.lab_shape())
+    I0[:] = np.repeat(prof, n * n)[None, :, None]
+    dt, nsteps = 0.05, 16
+    I, _ = o.advance(I0, dt, nsteps=nsteps, scheme="euler", tol=1e-9, max_iter=400, use_ng=True)
+    J = o.moments_lab(I)[0][:, 0].reshape(nz, n * n)
+    assert np.allclose(J, J[:, :1], rtol=1e-12)           # x, y independent
+    J = J[:, 0]
+    D, t = 1.0 / (3 * sig), dt * nsteps
+    Jd = 100 * w / np.sqrt(w ** 2 + 4 * D * t) * np.exp(-(z - 0.5) ** 2 / (w ** 2 + 4 * D * t))
+    main = Jd > 0.1 * Jd.max()
+    assert np.max(np.abs(J - Jd)[main]) < 0.02 * Jd.max()
+    assert abs(J.sum() / prof.sum() - 1) < 1e-4
 
 
 def test_backward_euler_front_moves_at_c():
