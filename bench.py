@@ -35,6 +35,7 @@ def algorithmic(kernel, spec, esz, time_dependent):
     G = len(spec["edges"]) - 1 if spec.get("edges") is not None else 1
     K = spec["nmu"] * spec["nphi"]
     NL = (spec["lmax"] + 1) ** 2
+    fused = spec.get("scatter", "thomson") != "compton" and 64 % NL == 0
     do, sh = n * G * K, n * G * NL
     table = {
         # S~ read, I written
@@ -47,9 +48,11 @@ def algorithmic(kernel, spec, esz, time_dependent):
         "unboost": ("hbm", 2 * esz * do),
         # comoving ordinate values read, SH intensity written
         "do2sh": ("hbm", esz * (do + sh)),
-        # SH read and written (Thomson: diagonal in SH)
-        "source": ("hbm", esz * 2 * sh),
-        "reduce": ("hbm", esz * 2 * sh),
+        # SH intensity read, new source written, and (Thomson, where the residual's row sums are
+        # taken in the same pass) the old source read
+        "source": ("hbm", esz * (3 if fused else 2) * sh),
+        # the residual: both sources read, or only the per-row sums where fused into the source
+        "reduce": ("hbm", 16 * n * G if fused else esz * 2 * sh),
     }
     return table[kernel]
 

@@ -166,11 +166,18 @@ size_t rrt_footprint_bytes(const rrt_grid *grid, const rrt_groups *groups, const
    planes fit the LDS) and the ordinate -> SH product (S6; -1 the default for
    the shape, 0 the library product (FP32 only), 1, 2 or 4 the matrix-core
    kernel with that many 16-row tiles per wave, for (L+1)^2 <= 64 in FP32 and
-   mixed precision).  With autotuning on (the default) each candidate is timed
+   mixed precision).  trace_groups -1 (G > 1) traces one group per workgroup
+   on group-major planes: the lab source is transposed to [k][g][p] before the
+   trace and the intensity back after it, so that the trace reads and writes
+   whole planes of one group contiguously (for planes too large for more than
+   one group in LDS); a per-group extinction is then kept transposed too (one
+   more ordinate-size array).  With autotuning on (the default) each candidate is timed
    on the problem's own buffers at the start of its second sweep and the
    fastest kept; the choice is remembered per problem shape for the rest of
-   the process.  The first sweep always uses the defaults.  Variants differ
-   only in the order of floating-point sums.  rrt_set_variants fixes them
+   the process (the group-major trace is a candidate where a transposed
+   extinction exists: planes that fit one group per workgroup only).  The first
+   sweep always uses the defaults.  Variants differ only in the order of
+   floating-point sums.  rrt_set_variants fixes them
    (trace_groups 0 keeps the current one) and turns autotuning off; it
    returns RRT_E_INVALID for a variant the shape or precision does not have.
    RRT_TRACE_GC in the environment at creation fixes the groups per workgroup. */

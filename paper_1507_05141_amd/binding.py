@@ -270,7 +270,8 @@ class Problem:
 
     def set_variants(self, trace_groups=0, s6=-1):
         """Fix the kernel variants (turns autotuning off): trace_groups groups per
-        ray-trace workgroup (0 keeps the current), s6 the ordinate -> SH product
+        ray-trace workgroup (0 keeps the current; -1 one group on group-major
+        planes, the lab arrays transposed around the trace), s6 the ordinate -> SH product
         (-1 the default for the shape, 0 the library product, 1/2/4 the
         matrix-core kernel with that many 16-row tiles per wave)."""
         _check(lib().rrt_set_variants(self._h, int(trace_groups), int(s6)))

@@ -82,6 +82,8 @@ struct rrt_problem {
     double *d_beta = nullptr, *d_gam = nullptr;
     void *d_chilab = nullptr;
     void *d_plan = nullptr;                         // remap entries: [p][k] boost, then [p][j] inverse
+    void *d_chilabT = nullptr;                      // per-group lab extinction on group-major planes [k][g][p]
+    bool gmajor = false;                            // trace on group-major planes (one group per workgroup)
     int grey_chi = 0;
     void *d_bc[2] = {nullptr, nullptr};
     // state and work arrays
@@ -330,18 +332,28 @@ struct Engine {
     void trace(const void *St, void *I, double inv_cdt, bool chi_array)
     {
         prof_begin(pr, KI_TRACE);
-        trace_launch(St, I, inv_cdt, chi_array);
+        trace_launch(St, I, inv_cdt, chi_array, false);
         prof_end(pr, KI_TRACE);
     }
-    void trace_launch(const void *St, void *I, double inv_cdt, bool chi_array)
+    void trace_launch(const void *St, void *I, double inv_cdt, bool chi_array, bool gmajor)
     {
         rrt::TraceArgs<real> t;
-        t.nx = pr->nx; t.ny = pr->ny; t.nz = pr->nz; t.G = pr->G; t.K = pr->K; t.Gc = pr->Gc; t.P = pr->P;
+        t.nx = pr->nx; t.ny = pr->ny; t.nz = pr->nz; t.G = pr->G; t.K = pr->K; t.Gc = gmajor ? 1 : pr->Gc; t.P = pr->P;
         t.geo = pr->d_geo; t.dir = pr->d_dir; t.St = static_cast<const real *>(St); t.Xt = R(pr->d_Xt);
-        t.chilab = R(pr->d_chilab); t.chi_grey = pr->grey_chi;
+        t.chilab = R(gmajor && !pr->grey_chi ? pr->d_chilabT : pr->d_chilab); t.chi_grey = pr->grey_chi;
         t.inv_cdt = (real)inv_cdt; t.bc_bot = R(pr->d_bc[0]); t.bc_top = R(pr->d_bc[1]); t.I = R(I);
+        t.gmajor = gmajor;
         rrt::launch_trace<real>(t, chi_array, pr->stream);
     }
+    // S4 on group-major planes: S~ (in d_St) is transposed into d_Ilab, traced into d_St,
+    // and the intensity transposed back into d_Ilab (both transposes timed with the trace)
+    void trace_gmajor_launch(double inv_cdt)
+    {
+        rrt::launch_transpose_lab<real>(R(pr->d_St), R(pr->d_Ilab), pr->P, pr->G, pr->K, true, pr->stream);
+        trace_launch(pr->d_Ilab, pr->d_St, inv_cdt, false, true);
+        rrt::launch_transpose_lab<real>(R(pr->d_St), R(pr->d_Ilab), pr->P, pr->G, pr->K, false, pr->stream);
+    }
+    bool gmajor_ready() const { return pr->G > 1 && (pr->grey_chi || pr->d_chilabT); }
 
     // S5 + S6: lab intensity -> comoving ordinates -> comoving SH intensity (into d_Ilm)
     rrt_status fold(const void *Ilab)
@@ -428,21 +440,34 @@ struct Engine {
             std::lock_guard<std::mutex> lk(g_tune_mu);
             auto it = g_tuned.find(key);
             if (it != g_tuned.end()) {
-                if (!pr->gc_forced) pr->Gc = it->second.first;
+                if (!pr->gc_forced) {
+                    pr->Gc = it->second.first & 7;
+                    pr->gmajor = (it->second.first >> 3) && gmajor_ready();
+                    if (pr->gmajor) pr->Gc = 1;
+                }
                 pr->s6 = it->second.second;
                 return RRT_OK;
             }
         }
-        if (!pr->gc_forced && gc_candidates().size() > 1) {
+        const bool try_gm = gmajor_ready() && !pr->gc_forced;
+        if (!pr->gc_forced && (gc_candidates().size() > 1 || try_gm)) {
             const auto c = gc_candidates();
             float best = INFINITY;
             int pick = pr->Gc;
+            bool pick_gm = false;
             for (int gc : c) {
                 pr->Gc = gc;
-                const float t = time_ms([&] { trace_launch(pr->d_St, pr->d_Ilab, inv_cdt, false); });
+                const float t = time_ms([&] { trace_launch(pr->d_St, pr->d_Ilab, inv_cdt, false, false); });
                 if (t < best) { best = t; pick = gc; }
             }
+            if (try_gm) {
+                // group-major planes with both transposes (d_St and d_Ilab hold scratch afterwards: the
+                // sweep about to run recomputes both)
+                const float t = time_ms([&] { trace_gmajor_launch(inv_cdt); });
+                if (t < best) { best = t; pick = 1; pick_gm = true; }
+            }
             pr->Gc = pick;
+            pr->gmajor = pick_gm;
         }
         if (s6_candidates().size() > 1) {
             const auto c = s6_candidates();
@@ -457,7 +482,7 @@ struct Engine {
         rrt_status s = check_launch();
         if (s) return s;
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tuned[key] = {pr->Gc, pr->s6};
+        g_tuned[key] = {pr->Gc + (pr->gmajor ? 8 : 0), pr->s6};
         return RRT_OK;
     }
 
@@ -575,7 +600,13 @@ struct Engine {
     {
         rrt_status s = to_lab(pr->d_S, Iprev, inv_cdt);
         if (s) return s;
-        trace(pr->d_St, pr->d_Ilab, inv_cdt, false);
+        if (pr->gmajor) {
+            prof_begin(pr, KI_TRACE);
+            trace_gmajor_launch(inv_cdt);
+            prof_end(pr, KI_TRACE);
+        } else {
+            trace(pr->d_St, pr->d_Ilab, inv_cdt, false);
+        }
         if ((s = fold(pr->d_Ilab))) return s;
         const bool fused = source(pr->d_Snew, pr->d_S);
         if ((s = check_launch())) return s;
@@ -777,6 +808,23 @@ rrt_status dispatch(rrt_problem *pr, F &&f)
     return f(e);
 }
 
+// the per-group lab extinction transposed for group-major ray traces (allocated on first
+// need, recomputed with every medium); nothing to do for an extinction shared by all groups
+rrt_status ensure_chilab_gmajor(rrt_problem *pr)
+{
+    if (pr->grey_chi || pr->G < 2) return RRT_OK;
+    rrt_status s = pr_alloc(pr, &pr->d_chilabT, (size_t)pr->K * pr->P * pr->G * pr->esz);
+    if (s) return s;
+    if (pr->prec == RRT_FP64)
+        rrt::launch_transpose_lab<double>((const double *)pr->d_chilab, (double *)pr->d_chilabT, pr->P, pr->G, pr->K,
+                                          true, pr->stream);
+    else
+        rrt::launch_transpose_lab<float>((const float *)pr->d_chilab, (float *)pr->d_chilabT, pr->P, pr->G, pr->K,
+                                         true, pr->stream);
+    HIPCHK(hipGetLastError());
+    return RRT_OK;
+}
+
 rrt_status check_sizes(const rrt_grid *g, const rrt_groups *gr, const rrt_angles *a, rrt_scatter sc, int prec)
 {
     if (!g || !gr || !a) return fail(RRT_E_INVALID, "NULL grid/groups/angles");
@@ -850,7 +898,7 @@ void rrt_destroy(rrt_problem *pr)
     if (pr->blas) (void)rocblas_destroy_handle(pr->blas);
     void *bufs[] = {pr->d_dir, pr->d_mu, pr->d_lnc, pr->d_nu3, pr->d_inv_nu3, pr->d_inv_dc, pr->d_geo, pr->d_Yt, pr->d_WY,
                     pr->d_Y16, pr->d_WYt16,
-                    pr->d_A, pr->d_sg, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_gam, pr->d_chi0, pr->d_chilab, pr->d_plan, pr->d_bc[0], pr->d_bc[1],
+                    pr->d_A, pr->d_sg, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_gam, pr->d_chi0, pr->d_chilab, pr->d_plan, pr->d_chilabT, pr->d_bc[0], pr->d_bc[1],
                     pr->d_S, pr->d_Snew, pr->d_Ilm, pr->d_co, pr->d_St, pr->d_Xt, pr->d_Ilab, pr->d_I, pr->d_Iin,
                     pr->d_acc, pr->d_chain[0], pr->d_chain[1], pr->d_chain[2], pr->d_chain[3], pr->d_partial, pr->d_red};
     for (void *b : bufs)
@@ -1159,6 +1207,10 @@ rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *si
         rrt::launch_chilab<real>(c, pr->stream);
     };
     if (pr->prec == RRT_FP64) chilab(0.0); else chilab(0.0f);
+    // group-major copy of a per-group extinction where the trace may use it: planes that
+    // leave LDS for one group per workgroup only, or a copy kept from an earlier medium
+    if (!pr->grey_chi && pr->G > 1 && (pr->Gc == 1 || pr->d_chilabT || pr->gmajor))
+        if ((s = ensure_chilab_gmajor(pr))) return s;
     // remap plan of the velocity field
     if (beta) {
         const size_t esz = pr->prec == RRT_FP64 ? sizeof(rrt::RemapEntry<double>) : sizeof(rrt::RemapEntry<float>);
@@ -1342,10 +1394,17 @@ rrt_status rrt_set_variants(rrt_problem *pr, int trace_groups, int s6_variant)
     if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
     bool ok_gc = trace_groups == 0;
     dispatch(pr, [&](auto &e) {
-        for (int gc : e.gc_candidates()) ok_gc = ok_gc || gc == trace_groups;
+        for (int gc : e.gc_candidates()) ok_gc = ok_gc || gc == trace_groups || (trace_groups == -1 && gc == 1);
         return RRT_OK;
     });
-    if (!ok_gc) return fail(RRT_E_INVALID, "groups per ray-trace workgroup must divide G and fit the LDS (1, 2 or 4)");
+    if (trace_groups == -1 && pr->G < 2) ok_gc = false;
+    if (!ok_gc)
+        return fail(RRT_E_INVALID, "groups per ray-trace workgroup must divide G and fit the LDS (1, 2 or 4; -1: one "
+                                   "group on group-major planes, G > 1)");
+    if (trace_groups == -1 && pr->medium_set) {
+        rrt_status s = ensure_chilab_gmajor(pr);
+        if (s) return s;
+    }
     bool ok_s6 = s6_variant == -1;
     dispatch(pr, [&](auto &e) {
         for (int v : e.s6_candidates()) ok_s6 = ok_s6 || v == s6_variant;
@@ -1353,7 +1412,10 @@ rrt_status rrt_set_variants(rrt_problem *pr, int trace_groups, int s6_variant)
     });
     if (!ok_s6) return fail(RRT_E_INVALID, "S6 variant not available for this shape and precision");
     clear_graphs(pr);
-    if (trace_groups) pr->Gc = trace_groups;
+    if (trace_groups) {
+        pr->gmajor = trace_groups == -1;
+        pr->Gc = pr->gmajor ? 1 : trace_groups;
+    }
     pr->s6 = s6_variant;
     pr->autotune = false;
     return RRT_OK;
@@ -1362,7 +1424,7 @@ rrt_status rrt_set_variants(rrt_problem *pr, int trace_groups, int s6_variant)
 rrt_status rrt_get_variants(const rrt_problem *pr, int *trace_groups, int *s6_variant, int *tuned)
 {
     if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
-    if (trace_groups) *trace_groups = pr->Gc;
+    if (trace_groups) *trace_groups = pr->gmajor ? -1 : pr->Gc;
     if (s6_variant) *s6_variant = pr->s6;
     if (tuned) *tuned = pr->tuned ? 1 : 0;
     return RRT_OK;

@@ -48,6 +48,7 @@ template <typename real> struct TraceArgs {
     real inv_cdt;               // 1/(c dt) of the implicit time step, 0 when steady
     const real *bc_bot, *bc_top;  // [k][ny][nx][g] or NULL
     real *I;                    // [k][p][g]
+    int gmajor;                 // St, Xt, a per-group chilab and I are [k][g][p] instead (Gc = 1)
 };
 
 // Remap of one ordinate at one moving point, fixed by the medium (velocity
@@ -121,6 +122,9 @@ template <typename real> struct SourceArgs {
 };
 
 template <typename real> void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st);
+// lab ordinate arrays between [k][p][g] (point-major) and [k][g][p] (group-major)
+template <typename real> void launch_transpose_lab(const real *in, real *out, long P, int G, int K, bool to_gmajor,
+                                                   hipStream_t st);
 template <typename real> void launch_boost(const BoostArgs<real> &a, hipStream_t st);
 template <typename real> void launch_unboost(const UnboostArgs<real> &a, hipStream_t st);
 template <typename real> size_t trace_lds(int nx, int ny, int Gc, int chi_per_point);
@@ -141,7 +145,7 @@ bool launch_do2sh_f16(long R, int K, int NL, const float *A, const _Float16 *WYh
 bool launch_sh2do_f16(long R, int K, int NL, const float *S, const _Float16 *Yh, const _Float16 *Yl, float *C,
                       hipStream_t st);
 template <typename real> void launch_source(const SourceArgs<real> &a, hipStream_t st);
-// Thomson source with the residual's per-row sums against Sold (rows[2 r], rows[2 r + 1]) in the
+// Thomson source with the residual's per-row sums against Sold (rows[g P + p], rows[(G + g) P + p]) in the
 // same pass; false (nothing launched) for Compton or NL not dividing 64
 template <typename real> bool launch_source_resid(const SourceArgs<real> &a, const real *Sold, double *rows, hipStream_t st);
 template <typename real> void launch_resid_groups(long P, int G, const double *rows, double *out, hipStream_t st);

@@ -349,14 +349,22 @@ struct TraceIdx {
 // global -> registers: S~ and chi (raw) of plane m for this thread's points.
 // Threads past the end of the plane load its last point (never stored), so
 // the loads are unconditional and stay in flight until the values are stored.
+// planes of S~ and chi~ kept in LDS (the stencil's four) and intensity planes.
+// (A fifth slot and a second intensity plane, for one barrier per plane instead
+// of two, made the 32^3 trace 1.7x slower: 143 KB of LDS against 96 KB.)
+constexpr int kRing = 4;
+constexpr int kIBuf = 1;
+
+// plane m of S~ and chi~ into registers; ps = stride between points (G, or 1 on group-major planes)
 template <typename real, int XMODE, int GC, int MAXPT>
 __device__ __forceinline__ void trace_fetch(PlaneRegs<real, GC, MAXPT> &r, const real *__restrict__ Sk,
-                                            const real *__restrict__ Xk, int G, int PL, int m)
+                                            const real *__restrict__ Xk, int ps, int PL, int m)
 {
     using P = Pack<real, GC>;
 #pragma unroll
     for (int c = 0; c < MAXPT; ++c) {
-        const int pidx = m * PL + min((int)threadIdx.x + c * kTraceThreads, PL - 1), o = pidx * G;
+        const int pidx = m * PL + min((int)threadIdx.x + c * kTraceThreads, PL - 1);
+        const long o = (long)pidx * ps;
         r.s[c] = *reinterpret_cast<const P *>(Sk + o);
         if (XMODE == kChiGrey) r.x[c].v[0] = Xk[pidx];
         else r.x[c] = *reinterpret_cast<const P *>(Xk + o);
@@ -382,7 +390,8 @@ __device__ __forceinline__ void trace_store(const PlaneRegs<real, GC, MAXPT> &r,
 {
     constexpr bool xg = XMODE == kChiGrey;
     using P = Pack<real, GC>;
-    P *Sd = reinterpret_cast<P *>(Sr + (t & 3) * q.PS * GC);
+    const int slot = t % kRing;
+    P *Sd = reinterpret_cast<P *>(Sr + slot * q.PS * GC);
 #pragma unroll
     for (int c = 0; c < MAXPT; ++c) {
         const int pe = threadIdx.x + c * kTraceThreads;
@@ -391,12 +400,12 @@ __device__ __forceinline__ void trace_store(const PlaneRegs<real, GC, MAXPT> &r,
             plane_ij(pe, q.nx, q.rnx, i, j);
             lds_put(Sd, q, i, j, r.s[c]);
             if (xg) {
-                lds_put(Xr + (t & 3) * q.PS, q, i, j, r.x[c].v[0] + add);
+                lds_put(Xr + slot * q.PS, q, i, j, r.x[c].v[0] + add);
             } else {
                 P x = r.x[c];
 #pragma unroll
                 for (int n = 0; n < GC; ++n) x.v[n] += add;
-                lds_put(reinterpret_cast<P *>(Xr + (t & 3) * q.PS * GC), q, i, j, x);
+                lds_put(reinterpret_cast<P *>(Xr + slot * q.PS * GC), q, i, j, x);
             }
         }
     }
@@ -430,10 +439,12 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
     const TraceIdx q{nx, ny, PL, nx + 1, (nx + 1) * (ny + 1), 1.0f / (float)nx};
     const int XE = q.PS * XG;
     real *Sr = reinterpret_cast<real *>(smem_raw);
-    real *Xr = Sr + 4 * q.PS * GC;
-    P *Ir = reinterpret_cast<P *>(Xr + 4 * XE);
+    real *Xr = Sr + kRing * q.PS * GC;
+    P *Ir = reinterpret_cast<P *>(Xr + kRing * XE);   // kIBuf planes of PS points
     const OrdGeom gm = a.geo[k];
-    const long slab = (long)k * a.P * G + g0;        // start of this ordinate's lab slab (+ chunk)
+    // start of this ordinate's lab slab (+ chunk) and the stride between points
+    const long slab = a.gmajor ? ((long)k * G + g0) * a.P : (long)k * a.P * G + g0;
+    const int ps = a.gmajor ? 1 : G;
     const real *__restrict__ Sk = a.St + slab;
     const real *__restrict__ Xk = XMODE == kChiArray ? a.Xt + slab
                                 : (XMODE == kChiGrey ? a.chilab + (long)k * a.P : a.chilab + slab);
@@ -459,7 +470,7 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
 
     const real add = XMODE == kChiArray ? real(0) : a.inv_cdt;   // the stand-alone chi~ already holds it
     for (int t = 0; t < nz && t < 3; ++t) {
-        trace_fetch<real, XMODE, GC, MAXPT>(rg, Sk, Xk, G, PL, gm.up ? t : nz - 1 - t);
+        trace_fetch<real, XMODE, GC, MAXPT>(rg, Sk, Xk, ps, PL, gm.up ? t : nz - 1 - t);
         trace_store<real, XMODE, GC, MAXPT>(rg, Sr, Xr, q, t, add);
     }
     {
@@ -479,7 +490,7 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
                 for (int n = 0; n < GC; ++n) v.v[n] = real(0);
             }
             lds_put(Ir, q, i, j, v);
-            *reinterpret_cast<P *>(Ik + (m0 * PL + pe) * G) = v;
+            *reinterpret_cast<P *>(Ik + (long)(m0 * PL + pe) * ps) = v;
         }
     }
     __syncthreads();
@@ -495,22 +506,25 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
     }
     const int RS = q.RS;
     for (int t = 1; t < nz; ++t) {
-        if (t + 2 < nz) trace_fetch<real, XMODE, GC, MAXPT>(rg, Sk, Xk, G, PL, gm.up ? t + 2 : nz - 3 - t);
+        if (t + 2 < nz) trace_fetch<real, XMODE, GC, MAXPT>(rg, Sk, Xk, ps, PL, gm.up ? t + 2 : nz - 3 - t);
         const int m = gm.up ? t : nz - 1 - t;
         const bool has_d = t <= nz - 2, has_uu = t >= 2;
-        const P *Spl = reinterpret_cast<const P *>(Sr + (t & 3) * q.PS * GC);
-        const P *Sul = reinterpret_cast<const P *>(Sr + ((t - 1) & 3) * q.PS * GC);
-        const P *Suul = reinterpret_cast<const P *>(Sr + ((t - 2) & 3) * q.PS * GC);
-        const P *Sdl = reinterpret_cast<const P *>(Sr + ((t + 1) & 3) * q.PS * GC);
-        const PX *Xpl = reinterpret_cast<const PX *>(Xr + (t & 3) * XE);
-        const PX *Xul = reinterpret_cast<const PX *>(Xr + ((t - 1) & 3) * XE);
-        const PX *Xuul = reinterpret_cast<const PX *>(Xr + ((t - 2) & 3) * XE);
-        const PX *Xdl = reinterpret_cast<const PX *>(Xr + ((t + 1) & 3) * XE);
+        const int sp0 = t % kRing, su0 = (t + kRing - 1) % kRing, suu0 = (t + kRing - 2) % kRing,
+                  sd0 = (t + 1) % kRing;
+        const P *Spl = reinterpret_cast<const P *>(Sr + sp0 * q.PS * GC);
+        const P *Sul = reinterpret_cast<const P *>(Sr + su0 * q.PS * GC);
+        const P *Suul = reinterpret_cast<const P *>(Sr + suu0 * q.PS * GC);
+        const P *Sdl = reinterpret_cast<const P *>(Sr + sd0 * q.PS * GC);
+        const PX *Xpl = reinterpret_cast<const PX *>(Xr + sp0 * XE);
+        const PX *Xul = reinterpret_cast<const PX *>(Xr + su0 * XE);
+        const PX *Xuul = reinterpret_cast<const PX *>(Xr + suu0 * XE);
+        const PX *Xdl = reinterpret_cast<const PX *>(Xr + sd0 * XE);
+        const P *Iul = Ir;
         P res[MAXPT];
 #pragma unroll
         for (int c = 0; c < MAXPT; ++c) {
             const int cp = self[c], cu = cell[c][1], cd = cell[c][2], cuu = cell[c][0];
-            const P Sp = Spl[cp], Su = bil(Sul, cu, RS, wts[1]), Iu = bil(Ir, cu, RS, wts[1]);
+            const P Sp = Spl[cp], Su = bil(Sul, cu, RS, wts[1]), Iu = bil(Iul, cu, RS, wts[1]);
             P Sd, Suu;
             PX Xd, Xuu;
             const PX Xp = Xpl[cp], Xu = bil(Xul, cu, RS, wts[1]);
@@ -537,7 +551,7 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
                 const real Cp = fmin(fmax(sp - tp * real(1.0 / 3.0), lo), hi);
                 res[c].v[n] = Iu.v[n] * gd.ex + bezier_integral(gd.E0, gd.E1, gd.E2, gd.E3, su, Cu, Cp, sp);
             }
-            if (tid + c * T < PL) *reinterpret_cast<P *>(Ik + (m * PL + tid + c * T) * G) = res[c];
+            if (tid + c * T < PL) *reinterpret_cast<P *>(Ik + (long)(m * PL + tid + c * T) * ps) = res[c];
         }
         __syncthreads();
         // every read of plane t - 1 is done: the intensity plane and the slot of
@@ -1393,8 +1407,8 @@ __global__ void __launch_bounds__(256) k_source(SourceArgs<real> a)
 // Thomson source fused with the residual's row sums (NL dividing 64): a wave
 // takes 64 / NL (point, group) rows, computes their new source coefficients,
 // and reduces sum (S_new - S_old)^2 and sum S_new^2 of each row in FP64 across
-// the row's lanes; rows[2 r], rows[2 r + 1] receive them (the per-group totals
-// follow in k_resid_groups)
+// the row's lanes; rows[g P + p] and rows[(G + g) P + p] receive them (the
+// per-group totals follow in k_resid_groups)
 template <typename real>
 __global__ void __launch_bounds__(256) k_source_resid(SourceArgs<real> a, const real *__restrict__ Sold, double *rows)
 {
@@ -1428,8 +1442,9 @@ __global__ void __launch_bounds__(256) k_source_resid(SourceArgs<real> a, const 
             aa += __shfl_xor(aa, off, 64);
         }
         if (q == 0 && r < PG) {
-            rows[2 * r] = dd;
-            rows[2 * r + 1] = aa;
+            const long pp = r / G, g = r - pp * G;
+            rows[g * a.P + pp] = dd;
+            rows[(G + g) * a.P + pp] = aa;
         }
     }
 }
@@ -1680,12 +1695,13 @@ __device__ __forceinline__ double block_sum(double v, double *sh)
 // per (point, group) row of NL SH terms: sum (a-b)^2 and sum a^2; one wave per
 // row (lanes stride the row, then a shuffle reduction), rows strided over waves
 template <typename real>
-__global__ void __launch_bounds__(256) k_resid_rows(long PG, int NL, const real *__restrict__ a,
+__global__ void __launch_bounds__(256) k_resid_rows(long P, int G, int NL, const real *__restrict__ a,
                                                     const real *__restrict__ b, double *rows)
 {
     const int lane = threadIdx.x & 63;
     const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const long nwaves = ((long)gridDim.x * blockDim.x) >> 6;
+    const long PG = P * G;
     for (long r = wave; r < PG; r += nwaves) {
         const real *x = a + r * NL, *y = b + r * NL;
         double dd = 0, aa = 0;
@@ -1700,19 +1716,21 @@ __global__ void __launch_bounds__(256) k_resid_rows(long PG, int NL, const real 
             aa += __shfl_xor(aa, off, 64);
         }
         if (lane == 0) {
-            rows[2 * r] = dd;
-            rows[2 * r + 1] = aa;
+            const long pp = r / G, g = r - pp * G;
+            rows[g * P + pp] = dd;
+            rows[(G + g) * P + pp] = aa;
         }
     }
 }
 
-// out[2g + c] = sum over points of rows[2 (p G + g) + c]; one block per (g, c)
+// out[2g + c] = sum over points of rows[(c G + g) P + p]; one block per (g, c)
 __global__ void __launch_bounds__(256) k_resid_groups(long P, int G, const double *__restrict__ rows, double *out)
 {
     __shared__ double sh[256];
     const int g = blockIdx.x >> 1, c = blockIdx.x & 1;
     double v = 0;
-    for (long p = threadIdx.x; p < P; p += blockDim.x) v += rows[2 * (p * G + g) + c];
+    const double *__restrict__ x = rows + (c * (long)G + g) * P;
+    for (long p = threadIdx.x; p < P; p += blockDim.x) v += x[p];
     v = block_sum(v, sh);
     if (threadIdx.x == 0) out[2 * g + c] = v;
 }
@@ -1820,7 +1838,47 @@ static inline unsigned blocks_for(long n, int bs) { return (unsigned)((n + bs - 
 template <typename real>
 size_t trace_lds(int nx, int ny, int Gc, int chi_per_point)
 {
-    return sizeof(real) * (size_t)(nx + 1) * (ny + 1) * (5 * (size_t)Gc + 4 * (chi_per_point ? 1 : (size_t)Gc));
+    return sizeof(real) * (size_t)(nx + 1) * (ny + 1) *
+           ((kRing + kIBuf) * (size_t)Gc + kRing * (chi_per_point ? 1 : (size_t)Gc));
+}
+// lab ordinate arrays [k][p][g] <-> [k][g][p], through an LDS tile of 64 points x
+// up to 32 groups (both sides read and written in contiguous runs)
+template <typename real>
+__global__ void __launch_bounds__(256) k_transpose_lab(const real *__restrict__ in, real *__restrict__ out, long P,
+                                                       int G, int to_gmajor)
+{
+    __shared__ real tile[64][33];
+    const long k = blockIdx.y, p0 = (long)blockIdx.x * 64;
+    const int np = (int)min(64L, P - p0);
+    for (int g0 = 0; g0 < G; g0 += 32) {
+        const int gn = min(32, G - g0), n = np * gn;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            if (to_gmajor) {
+                const int pp = i / gn, gg = i - pp * gn;
+                tile[pp][gg] = in[(k * P + p0 + pp) * G + g0 + gg];
+            } else {
+                const int gg = i / np, pp = i - gg * np;
+                tile[pp][gg] = in[(k * G + g0 + gg) * P + p0 + pp];
+            }
+        }
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += blockDim.x) {
+            if (to_gmajor) {
+                const int gg = i / np, pp = i - gg * np;
+                out[(k * G + g0 + gg) * P + p0 + pp] = tile[pp][gg];
+            } else {
+                const int pp = i / gn, gg = i - pp * gn;
+                out[(k * P + p0 + pp) * G + g0 + gg] = tile[pp][gg];
+            }
+        }
+        __syncthreads();
+    }
+}
+template <typename real>
+void launch_transpose_lab(const real *in, real *out, long P, int G, int K, bool to_gmajor, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_transpose_lab<real>, dim3((unsigned)((P + 63) / 64), (unsigned)K), dim3(256), 0, st, in, out,
+                       P, G, (int)to_gmajor);
 }
 template <typename real>
 void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st)
@@ -2022,7 +2080,7 @@ void launch_resid(long P, int G, int NL, const real *a, const real *b, double *r
 {
     (void)nblk;
     const unsigned nb = (unsigned)std::min<long>((P * G + 3) / 4, 8192);   // 4 waves per block, one row each
-    hipLaunchKernelGGL(k_resid_rows<real>, dim3(nb), dim3(256), 0, st, P * G, NL, a, b, rows);
+    hipLaunchKernelGGL(k_resid_rows<real>, dim3(nb), dim3(256), 0, st, P, G, NL, a, b, rows);
     hipLaunchKernelGGL(k_resid_groups, dim3(2 * G), dim3(256), 0, st, P, G, rows, out);
 }
 template <typename real>
@@ -2143,6 +2201,7 @@ hipError_t set_lds_limits(size_t bytes)
     template void launch_boost<real>(const BoostArgs<real> &, hipStream_t);                                     \
     template void launch_unboost<real>(const UnboostArgs<real> &, hipStream_t);                                 \
     template size_t trace_lds<real>(int, int, int, int);                                                       \
+    template void launch_transpose_lab<real>(const real *, real *, long, int, int, bool, hipStream_t);          \
     template size_t boost_lds<real>(int, int);                                                                 \
     template size_t unboost_lds<real>(int, int);                                                               \
     template void launch_chilab<real>(const ChiLabArgs<real> &, hipStream_t);                                   \

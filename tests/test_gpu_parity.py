@@ -143,6 +143,35 @@ def test_ray_trace_variants_parity(gc, grey_kappa, monkeypatch):
     g.close()
 
 
+@pytest.mark.parametrize("prec", [B.FP32, B.FP64], ids=["fp32", "fp64"])
+@pytest.mark.parametrize("grey_kappa", [True, False], ids=["grey_chi", "group_chi"])
+def test_group_major_trace_parity(grey_kappa, prec):
+    """The ray trace on group-major planes (source transposed before, intensity
+    after; a per-group extinction kept transposed) on one time-dependent sweep,
+    then again after a new medium."""
+    spec = custom_spec(9, 5, 7, G=4, seed=23, grey_kappa=grey_kappa, gamma_max=8.0)
+    o, g = _both(spec, prec)
+    g.set_variants(trace_groups=-1)
+    assert g.variants()["trace_groups"] == -1
+    rs = np.random.default_rng(24)
+    for rep in range(2):
+        S = o.initial_source() * (1 + 0.2 * rs.uniform(size=o.sh_shape()))
+        Iprev = rs.uniform(0.0, 1.0, o.lab_shape())
+        ref_I, ref_Ilm, ref_S, _ = o.sweep(S, I_prev=Iprev, inv_cdt=3.0)
+        g.set_source_sh(S)
+        g.set_intensity(Iprev)
+        g.sweep(dt_stage=1.0 / 3.0)
+        close_by_group(g.sweep_intensity(), ref_I, TOL[prec], 2, f"I_lab group-major {rep}")
+        close_by_group(g.source_sh(), ref_S, TOL[prec], 1, f"S_new group-major {rep}")
+        # a new medium: the transposed extinction is recomputed
+        spec = custom_spec(9, 5, 7, G=4, seed=25 + rep, grey_kappa=grey_kappa, gamma_max=6.0)
+        o = oracle.Oracle(spec)
+        g.set_medium(spec["kappa"], spec["sigma"], spec["bnu"], spec.get("beta"))
+        for face, key in ((0, "bc_bot"), (1, "bc_top")):
+            g.set_boundary(face, spec.get(key))
+    g.close()
+
+
 @pytest.mark.parametrize("prec", [B.FP64, B.FP32], ids=["fp64", "fp32"])
 def test_time_dependent_sweep_parity(prec):
     spec = custom_spec(7, 6, 5, G=4, seed=12)

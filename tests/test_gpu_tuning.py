@@ -45,7 +45,7 @@ def test_s6_variants_mixed(case, s6):
     _sweep_against_oracle(case, B.MIXED, 1, s6)
 
 
-@pytest.mark.parametrize("gc", [1, 2, 4], ids=["gc1", "gc2", "gc4"])
+@pytest.mark.parametrize("gc", [1, 2, 4, -1], ids=["gc1", "gc2", "gc4", "group_major"])
 def test_trace_group_variants(gc):
     print(f"trace groups {gc}", flush=True)
     _sweep_against_oracle("grey_extinction_8g", B.FP32, gc, -1)
