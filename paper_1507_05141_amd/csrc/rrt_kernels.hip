@@ -1874,9 +1874,79 @@ __global__ void __launch_bounds__(256) k_transpose_lab(const real *__restrict__ 
         __syncthreads();
     }
 }
+// the same with 16-byte loads and stores (G and P multiples of 4): a tile of 128
+// points x up to 32 groups, every lane's loads in flight before the LDS writes
+template <typename real>
+__global__ void __launch_bounds__(256) k_transpose_lab4(const real *__restrict__ in, real *__restrict__ out, long P,
+                                                        int G, int to_gmajor)
+{
+    using P4 = Pack<real, 4>;
+    constexpr int TP = 128, TS = 33;
+    __shared__ real tile[TP * TS];
+    const long k = blockIdx.y, p0 = (long)blockIdx.x * TP;
+    const int np = (int)min((long)TP, P - p0);             // a multiple of 4
+    for (int g0 = 0; g0 < G; g0 += 32) {
+        const int gn = min(32, G - g0), gn4 = gn >> 2, np4 = np >> 2;
+        const int n4 = np * gn4;                            // 16-byte pieces of the tile
+        P4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int f = threadIdx.x + u * 256;
+            if (f < n4) {
+                if (to_gmajor) {
+                    const int pp = f / gn4, g4 = f - pp * gn4;
+                    v[u] = *reinterpret_cast<const P4 *>(in + (k * P + p0 + pp) * G + g0 + 4 * g4);
+                } else {
+                    const int gg = f / np4, p4 = f - gg * np4;
+                    v[u] = *reinterpret_cast<const P4 *>(in + (k * G + g0 + gg) * P + p0 + 4 * p4);
+                }
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int f = threadIdx.x + u * 256;
+            if (f < n4) {
+                if (to_gmajor) {
+                    const int pp = f / gn4, g4 = f - pp * gn4;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) tile[pp * TS + 4 * g4 + i] = v[u].v[i];
+                } else {
+                    const int gg = f / np4, p4 = f - gg * np4;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) tile[(4 * p4 + i) * TS + gg] = v[u].v[i];
+                }
+            }
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int f = threadIdx.x + u * 256;
+            if (f < n4) {
+                P4 w;
+                if (to_gmajor) {
+                    const int gg = f / np4, p4 = f - gg * np4;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) w.v[i] = tile[(4 * p4 + i) * TS + gg];
+                    *reinterpret_cast<P4 *>(out + (k * G + g0 + gg) * P + p0 + 4 * p4) = w;
+                } else {
+                    const int pp = f / gn4, g4 = f - pp * gn4;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) w.v[i] = tile[pp * TS + 4 * g4 + i];
+                    *reinterpret_cast<P4 *>(out + (k * P + p0 + pp) * G + g0 + 4 * g4) = w;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
 template <typename real>
 void launch_transpose_lab(const real *in, real *out, long P, int G, int K, bool to_gmajor, hipStream_t st)
 {
+    if (G % 4 == 0 && P % 4 == 0) {
+        hipLaunchKernelGGL(k_transpose_lab4<real>, dim3((unsigned)((P + 127) / 128), (unsigned)K), dim3(256), 0, st, in,
+                           out, P, G, (int)to_gmajor);
+        return;
+    }
     hipLaunchKernelGGL(k_transpose_lab<real>, dim3((unsigned)((P + 63) / 64), (unsigned)K), dim3(256), 0, st, in, out,
                        P, G, (int)to_gmajor);
 }
