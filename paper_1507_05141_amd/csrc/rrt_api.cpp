@@ -833,6 +833,9 @@ rrt_status check_sizes(const rrt_grid *g, const rrt_groups *gr, const rrt_angles
     if (a->lmax < 0 || a->n_mu < 2 || a->n_phi < 1) return fail(RRT_E_INVALID, "bad angular sizes");
     if (a->n_mu % 2) return fail(RRT_E_INVALID, "n_mu must be even (no horizontal ordinate)");
     if ((long)a->n_mu * a->n_phi > 65535) return fail(RRT_E_INVALID, "at most 65535 ordinates");
+    // the remap plan packs the ring (10 bits), azimuth (10 bits) and group shift (12 bits) in one word
+    if (a->n_mu > 1022 || a->n_phi > 1024) return fail(RRT_E_INVALID, "at most 1022 polar and 1024 azimuthal nodes");
+    if (gr->ngroups > 2046) return fail(RRT_E_INVALID, "at most 2046 groups");
     if (a->n_mu < a->lmax + 1 || a->n_phi < 2 * a->lmax + 1)
         return fail(RRT_E_INVALID, "ordinate mesh too coarse for lmax (need n_mu >= lmax+1, n_phi >= 2 lmax+1)");
     if (prec != RRT_FP64 && prec != RRT_FP32 && prec != RRT_MIXED) return fail(RRT_E_INVALID, "unknown precision");
@@ -1220,6 +1223,7 @@ rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *si
             rrt::PlanArgs<real> a;
             a.P = (long)P; a.K = pr->K; a.nmu = pr->nmu; a.nphi = pr->nphi; a.fi = pr->fi;
             a.dir = pr->d_dir; a.mu = pr->d_mu; a.beta = pr->d_beta; a.gam = pr->d_gam;
+            a.chilab = static_cast<const real *>(pr->d_chilab); a.chi_grey = pr->grey_chi;
             a.boost = static_cast<rrt::RemapEntry<real> *>(pr->d_plan);
             a.unboost = a.boost + P * pr->K;
             rrt::launch_remap_plan<real>(a, pr->stream);

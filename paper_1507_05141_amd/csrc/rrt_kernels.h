@@ -52,19 +52,23 @@ template <typename real> struct TraceArgs {
 };
 
 // Remap of one ordinate at one moving point, fixed by the medium (velocity
-// field) and computed once per medium: the four bilinear angle taps of the
-// direction in the other frame (ring a0 = (ab & 0xffff) - 1 with a1 = a0 + 1,
-// azimuth b0 = ab >> 16 with b1 = b0 + 1 mod nphi; rings -1 and nmu are the
-// poles) with their weights w, and the frequency shift: for a single group
-// u = D^4 (to the lab) or D'^-4 (to the comoving frame); for groups uniform in
-// ln(nu), position shift s and the two weights u, v with the nu^3 ratios
-// (s = kAllGhost when every target lies beyond the groups); otherwise the
-// ln(nu) shift u + v split into a high and a low part.
+// field) and computed once per medium.  Word `abs` packs the four bilinear
+// angle taps of the direction in the other frame (ring a0 = (abs & 1023) - 1
+// with a1 = a0 + 1, azimuth b0 = (abs >> 10) & 1023 with b1 = b0 + 1 mod nphi;
+// rings -1 and nmu are the poles) and, for groups uniform in ln(nu), the
+// position shift s = abs >> 20 (signed; kPackedGhost when every target lies
+// beyond the groups); w are the tap weights.  Frequency: for a single group
+// u = D^4 (to the lab) or D'^-4 (to the comoving frame); for uniform groups the
+// two weights u, v with the nu^3 ratios; otherwise the ln(nu) shift u + v split
+// into a high and a low part.  kap: the lab extinction of the ordinate at the
+// point where it is the same for every group (boost entries only).
 template <typename real> struct alignas(16) RemapEntry {
-    int ab, s;
+    int abs;
+    real kap;
     real w[4];
     real u, v;
 };
+constexpr int kPackedGhost = -2048;       // s field of abs: every target beyond the groups
 constexpr int kAllGhost = -(1 << 30);
 
 template <typename real> struct PlanArgs {
@@ -73,6 +77,8 @@ template <typename real> struct PlanArgs {
     FreqInfo fi;
     const double *dir, *mu;      // [K][4], [nmu]
     const double *beta, *gam;    // [P][3], [P]
+    const real *chilab;          // [k][p] when chi_grey (copied into the boost entries)
+    int chi_grey;
     RemapEntry<real> *boost;     // [p][k]: comoving taps of lab ordinate k
     RemapEntry<real> *unboost;   // [p][j]: lab taps of comoving ordinate j
 };

@@ -726,7 +726,7 @@ __device__ __forceinline__ RemapEntry<real> remap_entry(const double *mu, int nm
 {
     const AngleTaps t = angle_taps<real>(mu, nmu, nphi, nt);
     RemapEntry<real> e{};
-    e.ab = (t.a0 + 1) | (t.b0 << 16);
+    e.abs = (t.a0 + 1) | (t.b0 << 10);
     const double um = 1.0 - t.wmu, up = 1.0 - t.wphi;
     e.w[0] = (real)(um * up); e.w[1] = (real)(um * t.wphi);
     e.w[2] = (real)(t.wmu * up); e.w[3] = (real)(t.wmu * t.wphi);
@@ -742,7 +742,9 @@ __device__ __forceinline__ void entry_freq(RemapEntry<real> &e, const FreqInfo &
     } else if (fi.uniform) {
         // positions of the target frequencies nu/D (boost) or D' nu (inverse)
         const double lr = (double)log((real)D) * fi.inv_delta;
-        uniform_shift<real>(inverse ? lr : -lr, fi.delta, fi.G, e.s, e.u, e.v);
+        int sh;
+        uniform_shift<real>(inverse ? lr : -lr, fi.delta, fi.G, sh, e.u, e.v);
+        e.abs |= (sh == kAllGhost ? kPackedGhost : sh) * (1 << 20);
     } else {
         const double x = inverse ? log(D) : -log(D);
         e.u = (real)x;
@@ -770,6 +772,7 @@ __global__ void __launch_bounds__(256) k_remap_plan(PlanArgs<real> a)
             for (int c = 0; c < 3; ++c) n0[c] = D * (n[c] - f * b[c]);
             RemapEntry<real> e = remap_entry<real>(a.mu, a.nmu, a.nphi, n0);
             entry_freq(e, a.fi, D, false);
+            if (a.chi_grey) e.kap = a.chilab[(long)k * a.P + p];
             a.boost[i] = e;
         }
         {
@@ -785,11 +788,18 @@ __global__ void __launch_bounds__(256) k_remap_plan(PlanArgs<real> a)
     }
 }
 
+// the frequency position shift packed in an entry (kAllGhost: every target beyond the groups)
+__device__ __forceinline__ int entry_shift(int abs)
+{
+    const int sh = abs >> 20;
+    return sh == kPackedGhost ? kAllGhost : sh;
+}
+
 // the four table columns of an entry's angle taps
 template <typename real>
-__device__ __forceinline__ Taps4<real> entry_taps(int ab, const real w[4], int K, int nmu, int nphi)
+__device__ __forceinline__ Taps4<real> entry_taps(int abs, const real w[4], int K, int nmu, int nphi)
 {
-    const int a0 = (ab & 0xffff) - 1, b0 = ab >> 16;
+    const int a0 = (abs & 1023) - 1, b0 = (abs >> 10) & 1023;
     const int b1 = b0 + 1 == nphi ? 0 : b0 + 1;
     auto col = [&](int ring, int b) { return ring < 0 ? K : (ring >= nmu ? K + 1 : ring * nphi + b); };
     Taps4<real> t;
@@ -868,7 +878,7 @@ __global__ void __launch_bounds__(kRemapThreads, 4) k_boost(BoostArgs<real> a)
         const int km = kb + lane;
         if (km < K) {
             if (moving) e = a.plan[p * K + km];
-            if (a.chi_grey) kap = a.chilab[(long)km * a.P + p];
+            else if (a.chi_grey) kap = a.chilab[(long)km * a.P + p];
         }
     };
     auto fetch_inputs = [&](int kb, int nit, int base) {
@@ -913,12 +923,12 @@ __global__ void __launch_bounds__(kRemapThreads, 4) k_boost(BoostArgs<real> a)
                 const int item = base + 64 * u + lane;
                 // every lane takes part in the shuffles (their source lanes are all active)
                 const int kk = min((int)(((float)item + 0.5f) * rNC), nk - 1), g0 = (item - kk * NC) * W;
-                const real kp = __shfl(kap, kk, 64);
+                const real kp = __shfl(moving ? e.kap : kap, kk, 64);
                 int ab = 0, sh = 0;
                 real w[4] = {0, 0, 0, 0}, eu = 0, ev = 0;
                 if (moving) {
-                    ab = __shfl(e.ab, kk, 64);
-                    sh = __shfl(e.s, kk, 64);
+                    ab = __shfl(e.abs, kk, 64);
+                    sh = entry_shift(ab);
 #pragma unroll
                     for (int i = 0; i < 4; ++i) w[i] = __shfl(e.w[i], kk, 64);
                     eu = __shfl(e.u, kk, 64);
@@ -1051,17 +1061,18 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_un
     __syncthreads();
     for (int j = tid; j < K; j += T) {
         if (j != tid) e = a.plan[p * K + j];
-        const Taps4<real> tp = entry_taps(e.ab, e.w, K, a.nmu, a.nphi);
+        const Taps4<real> tp = entry_taps(e.abs, e.w, K, a.nmu, a.nphi);
         if (a.fi.grey) {
             out[j] = tap_row(F + KS, tp) * e.u;
         } else if (a.fi.uniform) {
-            if (e.s == kAllGhost) {
+            const int sh = entry_shift(e.abs);
+            if (sh == kAllGhost) {
                 for (int g = 0; g < G; ++g) out[g * K + j] = real(0);
             } else {
                 auto A = [&](int gp) -> real { return tap_row(F + (min(max(gp, -1), G) + 1) * KS, tp); };
-                real acur = A(e.s);
+                real acur = A(sh);
                 for (int g = 0; g < G; ++g) {
-                    const real anext = A(g + e.s + 1);
+                    const real anext = A(g + sh + 1);
                     out[g * K + j] = e.u * acur + e.v * anext;
                     acur = anext;
                 }
