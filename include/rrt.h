@@ -171,7 +171,8 @@ size_t rrt_footprint_bytes(const rrt_grid *grid, const rrt_groups *groups, const
    trace and the intensity back after it, so that the trace reads and writes
    whole planes of one group contiguously (for planes too large for more than
    one group in LDS); a per-group extinction is then kept transposed too (one
-   more ordinate-size array).  With autotuning on (the default) each candidate is timed
+   more ordinate-size array).  It is the default where only one group per
+   workgroup fits the LDS and G >= 8.  With autotuning on (the default) each candidate is timed
    on the problem's own buffers at the start of its second sweep and the
    fastest kept; the choice is remembered per problem shape for the rest of
    the process (the group-major trace is a candidate where a transposed

@@ -125,6 +125,7 @@ struct rrt_problem {
     int s6 = -1;
     bool autotune = true, tuned = false;
     bool gc_forced = false;                         // groups per workgroup fixed by the environment
+    bool variants_fixed = false;                    // fixed by rrt_set_variants
     size_t lds_lim = 0;
     // kernel timing
     bool prof = false;
@@ -865,7 +866,11 @@ size_t footprint(const rrt_grid *g, const rrt_groups *gr, const rrt_angles *a, i
     const size_t NL = (size_t)(a->lmax + 1) * (a->lmax + 1);
     size_t sh = P * G * NL * esz, dob = P * G * K * esz;
     size_t total = 3 * sh + 4 * dob;                 // S, Snew, Ilm; comoving ordinates, St, Ilab, I
-    total += P * K * esz;                            // lab extinction (one group; G times more if non-grey)
+    total += dob;                                    // lab extinction (per group: an upper bound)
+    // its group-major copy, where the ray trace's planes leave LDS for one group per workgroup
+    const size_t tl2 = (prec == RRT_FP64 ? rrt::trace_lds<double>(g->nx, g->ny, 2, 0)
+                                          : rrt::trace_lds<float>(g->nx, g->ny, 2, 0));
+    if (G >= 8 && tl2 > kMaxLds) total += dob;
     if (time_dep) total += 2 * dob;                  // stage input, accumulator
     if (use_ng) total += 4 * sh;                     // Ng chain
     total += P * (3 * G + 1) * esz + 4 * P * 8;     // fields, chi0, beta, Gamma
@@ -1214,6 +1219,9 @@ rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *si
     // leave LDS for one group per workgroup only, or a copy kept from an earlier medium
     if (!pr->grey_chi && pr->G > 1 && (pr->Gc == 1 || pr->d_chilabT || pr->gmajor))
         if ((s = ensure_chilab_gmajor(pr))) return s;
+    // default: group-major planes where one group per workgroup is all the LDS holds and a
+    // point's groups span whole 32-byte sectors (G >= 8); the autotuner may revise it
+    if (!pr->variants_fixed && !pr->gc_forced) pr->gmajor = pr->Gc == 1 && pr->G >= 8;
     // remap plan of the velocity field
     if (beta) {
         const size_t esz = pr->prec == RRT_FP64 ? sizeof(rrt::RemapEntry<double>) : sizeof(rrt::RemapEntry<float>);
@@ -1422,6 +1430,7 @@ rrt_status rrt_set_variants(rrt_problem *pr, int trace_groups, int s6_variant)
     }
     pr->s6 = s6_variant;
     pr->autotune = false;
+    pr->variants_fixed = true;
     return RRT_OK;
 }
 

@@ -64,25 +64,29 @@ def poisson_requests(count, rate, seed, **mix):
 
 
 def serve(requests, precision=B.FP32, budget_bytes=64 << 30, tol=1e-6, max_iter=300, use_ng=True, keep=None,
-          graphs=True, progress=None):
+          graphs=True, progress=None, autotune=False):
     """Run the request stream; returns per-request records and the run's wall time.
 
     keep(i, problem) -> dict, if given, is called on each finished problem
     before it is destroyed (e.g. to read its moments).  graphs=False runs every
     sweep eagerly instead of replaying captured sweeps.  progress(done, total),
-    if given, is called whenever a request finishes or is rejected."""
+    if given, is called whenever a request finishes or is rejected.  Requests
+    run the library's default kernel variants unless autotune is set (timing
+    candidates inside a request would add to its latency and, with other
+    requests sharing the GPU, measure contention as much as the kernels)."""
     batch = B.Batch(budget_bytes)
     pending = list(range(len(requests)))           # not yet admitted, in arrival order
     running = {}                                    # request -> Problem
     reserved = {}                                   # request -> bytes counted at admission
     used = 0
+    blocked = False                                 # the head request did not fit: wait for a retirement
     recs = [None] * len(requests)
     t0 = time.perf_counter()
     now = lambda: time.perf_counter() - t0
     try:
         while pending or running:
             # admit arrived requests in order while the budget allows
-            while pending and requests[pending[0]]["arrival"] <= now():
+            while pending and not blocked and requests[pending[0]]["arrival"] <= now():
                 i = pending[0]
                 spec = requests[i]["spec"]
                 need = B.footprint_bytes(spec, precision, time_dependent=False, use_ng=use_ng)
@@ -92,9 +96,12 @@ def serve(requests, precision=B.FP32, budget_bytes=64 << 30, tol=1e-6, max_iter=
                 pr = B.Problem.from_spec(spec, precision=precision)
                 if not graphs:
                     pr.set_graphs(False)
+                if not autotune:
+                    pr.set_autotune(False)
                 if not batch.admit(pr, tol=tol, max_iter=max_iter, use_ng=use_ng):
                     pr.close()
                     if running:
+                        blocked = True
                         break
                     # larger than the whole budget: rejected
                     pending.pop(0)
@@ -126,6 +133,7 @@ def serve(requests, precision=B.FP32, budget_bytes=64 << 30, tol=1e-6, max_iter=
                     recs[i].update(keep(i, pr))
                 pr.close()
                 used -= reserved.pop(i)
+                blocked = False
                 if progress is not None:
                     progress(sum(r is not None and "latency" in r for r in recs), len(requests))
     finally:

@@ -73,7 +73,7 @@ def test_autotune_picks_a_candidate_and_reuses_it():
         a.sweep()
     va = a.variants()
     print("tuned", va, flush=True)
-    assert va["tuned"] and va["trace_groups"] in (1, 2, 4) and va["s6"] in (0, 1, 2, 4)
+    assert va["tuned"] and va["trace_groups"] in (1, 2, 4, -1) and va["s6"] in (0, 1, 2, 4)
     b = B.Problem.from_spec(spec, precision=B.FP32)
     for _ in range(2):
         b.sweep()
