@@ -2054,24 +2054,24 @@ bool launch_do2sh_f16(long R, int K, int NL, const float *A, const _Float16 *WYh
                       hipStream_t st, int rt)
 {
     const int Kp = (K + 31) / 32 * 32;
-    const dim3 block(256);
-#define RRT_DO2SH16(NT, RT)                                                                                  \
+    // W waves share each staged table chunk (sixteen where the registers allow)
+#define RRT_DO2SH16(NT, RT, W)                                                                               \
     {                                                                                                        \
-        const long nb = (R + 64 * RT - 1) / (64 * RT);                                                       \
+        const long nb = (R + 16 * W * RT - 1) / (16 * W * RT);                                               \
         if (nb > 0x7fffffffL) return false;                                                                 \
         const size_t sm = 2 * sizeof(_Float16) * (size_t)(NT * 16) * 72;                                    \
-        hipLaunchKernelGGL((k_do2sh_f16<NT, RT>), dim3((unsigned)(8 * ((nb + 7) / 8))), block, sm, st, R, K, Kp, \
-                           NL, A, WYh, WYl, C);                                                             \
+        hipLaunchKernelGGL((k_do2sh_f16<NT, RT, W>), dim3((unsigned)(8 * ((nb + 7) / 8))), dim3(64 * W), sm, st, R, \
+                           K, Kp, NL, A, WYh, WYl, C);                                                      \
         return true;                                                                                         \
     }
     if (NL <= 16) {
-        if (rt == 1) RRT_DO2SH16(1, 1)
-        if (rt == 2) RRT_DO2SH16(1, 2)
-        if (rt == 0 || rt == 4) RRT_DO2SH16(1, 4)
+        if (rt == 1) RRT_DO2SH16(1, 1, 16)
+        if (rt == 2) RRT_DO2SH16(1, 2, 16)
+        if (rt == 0 || rt == 4) RRT_DO2SH16(1, 4, 16)
     } else if (NL <= 64) {
-        if (rt == 1) RRT_DO2SH16(4, 1)
-        if (rt == 0 || rt == 2) RRT_DO2SH16(4, 2)
-        if (rt == 4) RRT_DO2SH16(4, 4)
+        if (rt == 1) RRT_DO2SH16(4, 1, 16)
+        if (rt == 0 || rt == 2) RRT_DO2SH16(4, 2, 16)
+        if (rt == 4) RRT_DO2SH16(4, 4, 4)
     } else if (NL <= 256) {
         // eight waves share each staged table chunk
         if (rt == 0 || rt == 1) {
@@ -2094,8 +2094,11 @@ bool launch_sh2do_f16(long R, int K, int NL, const float *S, const _Float16 *Yh,
     if (nb > 0x7fffffffL) return false;
     const dim3 grid((unsigned)(8 * ((nb + 7) / 8))), block(256);
     auto sm = [](int NB) { return 2 * sizeof(_Float16) * 64 * (size_t)(NB * 32 + 8); };
-    if (NL <= 32) hipLaunchKernelGGL(k_sh2do_f16<1>, grid, block, sm(1), st, R, K, NL, S, Yh, Yl, C);
-    else if (NL <= 64) hipLaunchKernelGGL(k_sh2do_f16<2>, grid, block, sm(2), st, R, K, NL, S, Yh, Yl, C);
+    // sixteen waves (256 rows) share each staged table chunk where the rows are short
+    const long nb16 = (R + 255) / 256;
+    const dim3 grid16((unsigned)(8 * ((nb16 + 7) / 8))), block16(1024);
+    if (NL <= 32) hipLaunchKernelGGL((k_sh2do_f16<1, 16>), grid16, block16, sm(1), st, R, K, NL, S, Yh, Yl, C);
+    else if (NL <= 64) hipLaunchKernelGGL((k_sh2do_f16<2, 16>), grid16, block16, sm(2), st, R, K, NL, S, Yh, Yl, C);
     else if (NL <= 128) hipLaunchKernelGGL(k_sh2do_f16<4>, grid, block, sm(4), st, R, K, NL, S, Yh, Yl, C);
     else if (NL <= 256) {
         // eight waves share each staged table chunk
@@ -2251,15 +2254,15 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_unboost<float>),
                          reinterpret_cast<const void *>(&k_unboost<double>),
                          reinterpret_cast<const void *>(&k_source_compton<float>),
-                         reinterpret_cast<const void *>(&k_do2sh_f16<1, 1>),
-                         reinterpret_cast<const void *>(&k_do2sh_f16<1, 2>),
-                         reinterpret_cast<const void *>(&k_do2sh_f16<1, 4>),
-                         reinterpret_cast<const void *>(&k_do2sh_f16<4, 1>),
-                         reinterpret_cast<const void *>(&k_do2sh_f16<4, 2>),
-                         reinterpret_cast<const void *>(&k_do2sh_f16<4, 4>),
+                         reinterpret_cast<const void *>(&k_do2sh_f16<1, 1, 16>),
+                         reinterpret_cast<const void *>(&k_do2sh_f16<1, 2, 16>),
+                         reinterpret_cast<const void *>(&k_do2sh_f16<1, 4, 16>),
+                         reinterpret_cast<const void *>(&k_do2sh_f16<4, 1, 16>),
+                         reinterpret_cast<const void *>(&k_do2sh_f16<4, 2, 16>),
+                         reinterpret_cast<const void *>(&k_do2sh_f16<4, 4, 4>),
                          reinterpret_cast<const void *>(&k_do2sh_f16<16, 1, 8>),
-                         reinterpret_cast<const void *>(&k_sh2do_f16<1>),
-                         reinterpret_cast<const void *>(&k_sh2do_f16<2>),
+                         reinterpret_cast<const void *>(&k_sh2do_f16<1, 16>),
+                         reinterpret_cast<const void *>(&k_sh2do_f16<2, 16>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<4>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<8, 8>),
                          reinterpret_cast<const void *>(&k_source_compton_mfma),
