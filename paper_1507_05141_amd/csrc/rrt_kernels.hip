@@ -1119,15 +1119,15 @@ __global__ void __launch_bounds__(256) k_chilab(ChiLabArgs<real> a)
 // ---------------------------------------------------------------------------
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-template <int NT, int RT>
-__global__ void __launch_bounds__(256) k_do2sh_f32(long R, int K, int NL, const float *__restrict__ A,
-                                                   const float *__restrict__ B, float *__restrict__ C)
+template <int NT, int RT, int W = 4>
+__global__ void __launch_bounds__(64 * W) k_do2sh_f32(long R, int K, int NL, const float *__restrict__ A,
+                                                      const float *__restrict__ B, float *__restrict__ C)
 {
     constexpr int KC = 64, NC = NT * 16, NLP = NC + 4;
     extern __shared__ unsigned char smem_raw[];
     float *Bs = reinterpret_cast<float *>(smem_raw);                   // [KC][NLP]
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
-    const long r0 = (long)xcd_item(gridDim.x) * (64 * RT) + wave * (16 * RT);
+    const long r0 = (long)xcd_item(gridDim.x) * (16 * W * RT) + wave * (16 * RT);
     const float *Arow[RT];
 #pragma unroll
     for (int t = 0; t < RT; ++t) Arow[t] = A + min(r0 + 16 * t + lr, R - 1) * (long)K;
@@ -2026,25 +2026,25 @@ size_t do2sh_lds(int NL) { return sizeof(float) * 64 * (size_t)(((NL + 15) / 16)
 
 bool launch_do2sh_f32(long R, int K, int NL, const float *A, const float *B, float *C, hipStream_t st, int rt)
 {
-    const dim3 block(256);
     const size_t sm = do2sh_lds(NL);
     // NL up to 64 (L <= 7); at L = 15 the library product is faster (measured on MI355X)
-#define RRT_DO2SH32(NT, RT)                                                                                   \
+    // W waves share each staged table chunk (sixteen where the registers allow)
+#define RRT_DO2SH32(NT, RT, W)                                                                                \
     {                                                                                                         \
-        const long nb = (R + 64 * RT - 1) / (64 * RT);                                                        \
+        const long nb = (R + 16 * W * RT - 1) / (16 * W * RT);                                                \
         if (nb > 0x7fffffffL) return false;                                                                  \
-        hipLaunchKernelGGL((k_do2sh_f32<NT, RT>), dim3((unsigned)(8 * ((nb + 7) / 8))), block, sm, st, R, K, NL, A, B, \
-                           C);                                                                               \
+        hipLaunchKernelGGL((k_do2sh_f32<NT, RT, W>), dim3((unsigned)(8 * ((nb + 7) / 8))), dim3(64 * W), sm, st, R, \
+                           K, NL, A, B, C);                                                                  \
         return true;                                                                                          \
     }
     if (NL <= 16) {
-        if (rt == 1) RRT_DO2SH32(1, 1)
-        if (rt == 2) RRT_DO2SH32(1, 2)
-        if (rt == 0 || rt == 4) RRT_DO2SH32(1, 4)
+        if (rt == 1) RRT_DO2SH32(1, 1, 16)
+        if (rt == 2) RRT_DO2SH32(1, 2, 16)
+        if (rt == 0 || rt == 4) RRT_DO2SH32(1, 4, 16)
     } else if (NL <= 64) {
-        if (rt == 1) RRT_DO2SH32(4, 1)
-        if (rt == 0 || rt == 2) RRT_DO2SH32(4, 2)
-        if (rt == 4) RRT_DO2SH32(4, 4)
+        if (rt == 1) RRT_DO2SH32(4, 1, 16)
+        if (rt == 0 || rt == 2) RRT_DO2SH32(4, 2, 16)
+        if (rt == 4) RRT_DO2SH32(4, 4, 4)
     }
 #undef RRT_DO2SH32
     return false;
@@ -2266,12 +2266,12 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_sh2do_f16<4>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<8, 8>),
                          reinterpret_cast<const void *>(&k_source_compton_mfma),
-                         reinterpret_cast<const void *>(&k_do2sh_f32<1, 1>),
-                         reinterpret_cast<const void *>(&k_do2sh_f32<1, 2>),
-                         reinterpret_cast<const void *>(&k_do2sh_f32<1, 4>),
-                         reinterpret_cast<const void *>(&k_do2sh_f32<4, 1>),
-                         reinterpret_cast<const void *>(&k_do2sh_f32<4, 2>),
-                         reinterpret_cast<const void *>(&k_do2sh_f32<4, 4>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32<1, 1, 16>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32<1, 2, 16>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32<1, 4, 16>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32<4, 1, 16>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32<4, 2, 16>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32<4, 4, 4>),
                          reinterpret_cast<const void *>(&k_source_compton<double>)};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
