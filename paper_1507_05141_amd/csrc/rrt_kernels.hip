@@ -844,41 +844,56 @@ __device__ __forceinline__ void stage_rows(const real *__restrict__ src, real *F
 // invariant S0/nu^3 at the comoving direction n0 (Eq. 8) and frequency nu/D
 // (Eq. 7) of that ray, times nu^3; then the implicit time terms of Eqs. 5-6
 // with the lab extinction chi_lab precomputed per medium.  Output S~[k][p][g].
-// Each wave takes 64 ordinates: lane l loads the remap entry of ordinate
-// kb + l, then the lanes run over (ordinate, run of W groups) items, W = 4 when
-// G allows 16-byte runs, fetching their ordinate's entry from the lane that
+// A workgroup takes NPT neighbouring points (NPT = 2 where a point's groups
+// fill 64 bytes, so that the stage inputs and outputs of one ordinate are read
+// and written as whole 128-byte lines; half-line runs scattered over the
+// ordinate slabs move at about half the rate).  Each wave takes 64 / NPT
+// ordinates: lane l loads the remap entry of ordinate kb + l / NPT at point
+// l % NPT, then the lanes run over (ordinate, point, run of W groups) items,
+// W = 4 when G allows 16-byte runs, fetching their entry from the lane that
 // loaded it; consecutive lanes so write consecutive groups of one ordinate.
 // The entries and the time-term inputs of a lane's first four items are
-// loaded before the table is staged.
+// loaded before the tables are staged.
 // ---------------------------------------------------------------------------
-template <typename real>
+template <typename real, int NPT>
 __global__ void __launch_bounds__(kRemapThreads, 4) k_boost(BoostArgs<real> a)
 {
     using P4 = Pack<real, 4>;
     extern __shared__ unsigned char smem_raw[];
-    const long p = xcd_item(a.P);
-    if (p >= a.P) return;
+    const long p0 = xcd_item((a.P + NPT - 1) / NPT) * NPT;
+    if (p0 >= a.P) return;
     const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x, KS = table_stride(K);
-    const int lane = tid & 63, wave = tid >> 6;
+    const int lane = tid & 63, wave = tid >> 6, nwaves = T >> 6;
+    const int TS = (G + 2) * KS;                        // one point's table
     double *fbuf = reinterpret_cast<double *>(smem_raw);                // [4G]
-    real *F = reinterpret_cast<real *>(fbuf + 4 * G);                   // [G+2][KS]
+    real *F0 = reinterpret_cast<real *>(fbuf + 4 * G);                  // [NPT][G+2][KS]
 
     const FreqL fl = stage_freq(a.fi, fbuf);
-    double b[3];
-    const bool moving = load_beta(a.beta, p, b);
+    bool mv[NPT];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+        double b[3];
+        mv[q] = p0 + q < a.P && load_beta(a.beta, p0 + q, b);
+    }
     const int W = (G & 3) == 0 ? 4 : 1;                // groups per lane item
-    const int NC = G / W;                               // items per ordinate
-    const float rNC = 1.0f / (float)NC;
-    const int kb0 = wave * 64;
+    const int NC = G / W;                               // items per ordinate and point
+    const int IC = NPT * NC;                            // items per ordinate
+    const float rIC = 1.0f / (float)IC;
+    constexpr int OB = 64 / NPT;                        // ordinates per wave block
+    const int kb0 = wave * OB;
+    // this lane's entry: ordinate kb + lane / NPT at point p0 + lane % NPT
+    const int lq = lane % NPT;
+    const long lp = p0 + lq;
+    const bool lmv = mv[lq];
 
     RemapEntry<real> e{};
     real kap = 0;
     P4 pre[4];
     auto fetch_ordinates = [&](int kb) {
-        const int km = kb + lane;
-        if (km < K) {
-            if (moving) e = a.plan[p * K + km];
-            else if (a.chi_grey) kap = a.chilab[(long)km * a.P + p];
+        const int km = kb + lane / NPT;
+        if (km < K && lp < a.P) {
+            if (lmv) e = a.plan[lp * K + km];
+            else if (a.chi_grey) kap = a.chilab[(long)km * a.P + lp];
         }
     };
     auto fetch_inputs = [&](int kb, int nit, int base) {
@@ -887,58 +902,71 @@ __global__ void __launch_bounds__(kRemapThreads, 4) k_boost(BoostArgs<real> a)
             const int item = base + 64 * u + lane;
             pre[u] = P4{};
             if (a.Iprev && item < nit) {
-                const int kk = (int)(((float)item + 0.5f) * rNC), g0 = (item - kk * NC) * W;
-                const long o = ((long)(kb + kk) * a.P + p) * G + g0;
-                if (W == 4) pre[u] = *reinterpret_cast<const P4 *>(a.Iprev + o);
-                else pre[u].v[0] = a.Iprev[o];
+                const int kk = (int)(((float)item + 0.5f) * rIC), rem = item - kk * IC, q = rem / NC;
+                const int g0 = (rem - q * NC) * W;
+                if (p0 + q < a.P) {
+                    const long o = ((long)(kb + kk) * a.P + p0 + q) * G + g0;
+                    if (W == 4) pre[u] = *reinterpret_cast<const P4 *>(a.Iprev + o);
+                    else pre[u].v[0] = a.Iprev[o];
+                }
             }
         }
     };
     if (kb0 < K) {
         fetch_ordinates(kb0);
-        fetch_inputs(kb0, min(64, K - kb0) * NC, 0);
+        fetch_inputs(kb0, min(OB, K - kb0) * IC, 0);
     }
 
-    const real *__restrict__ src = a.S0 + (long)p * G * K;
-    if ((K & 3) == 0) {
-        stage_rows(src, F, G, K, KS);
-    } else {
-        for (int g = 0; g < G; ++g)
-            for (int j = tid; j < K; j += T) F[(g + 1) * KS + j] = src[g * K + j];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+        if (p0 + q >= a.P) break;
+        const real *__restrict__ src = a.S0 + (p0 + q) * G * K;
+        real *F = F0 + q * TS;
+        if ((K & 3) == 0) {
+            stage_rows(src, F, G, K, KS);
+        } else {
+            for (int g = 0; g < G; ++g)
+                for (int j = tid; j < K; j += T) F[(g + 1) * KS + j] = src[g * K + j];
+        }
+        if (mv[q]) table_ghosts(F, G, KS);
     }
-    if (moving) table_ghosts(F, G, KS);
     __syncthreads();
-    if (moving) {
-        table_poles(F, G, K, KS, a.nmu, a.nphi);
+    bool anymv = false;
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) anymv = anymv || mv[q];
+    if (anymv) {
+#pragma unroll
+        for (int q = 0; q < NPT; ++q)
+            if (mv[q]) table_poles(F0 + q * TS, G, K, KS, a.nmu, a.nphi);
         __syncthreads();
     }
     const real icdt = a.inv_cdt;
-    for (int kb = kb0; kb < K; kb += T) {
-        const int nk = min(64, K - kb), nit = nk * NC;
+    for (int kb = kb0; kb < K; kb += nwaves * OB) {
+        const int nk = min(OB, K - kb), nit = nk * IC;
         if (kb != kb0) fetch_ordinates(kb);
+        const real kapv = lmv ? e.kap : kap;
         for (int base = 0; base < nit; base += 256) {
             if (kb != kb0 || base != 0) fetch_inputs(kb, nit, base);
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int item = base + 64 * u + lane;
                 // every lane takes part in the shuffles (their source lanes are all active)
-                const int kk = min((int)(((float)item + 0.5f) * rNC), nk - 1), g0 = (item - kk * NC) * W;
-                const real kp = __shfl(moving ? e.kap : kap, kk, 64);
-                int ab = 0, sh = 0;
-                real w[4] = {0, 0, 0, 0}, eu = 0, ev = 0;
-                if (moving) {
-                    ab = __shfl(e.abs, kk, 64);
-                    sh = entry_shift(ab);
+                const int kk = min((int)(((float)item + 0.5f) * rIC), nk - 1), rem = item - kk * IC;
+                const int q = min(rem / NC, NPT - 1), g0 = (rem - q * NC) * W;
+                const int srcl = kk * NPT + q;
+                const real kp = __shfl(kapv, srcl, 64);
+                const int ab = __shfl(e.abs, srcl, 64);
+                const int sh = entry_shift(ab);
+                real w[4];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) w[i] = __shfl(e.w[i], kk, 64);
-                    eu = __shfl(e.u, kk, 64);
-                    ev = __shfl(e.v, kk, 64);
-                }
-                if (item >= nit) continue;
+                for (int i = 0; i < 4; ++i) w[i] = __shfl(e.w[i], srcl, 64);
+                const real eu = __shfl(e.u, srcl, 64), ev = __shfl(e.v, srcl, 64);
+                if (item >= nit || p0 + q >= a.P) continue;
+                const real *F = F0 + q * TS;
                 const int k = kb + kk;
-                const long o = ((long)k * a.P + p) * G + g0;
+                const long o = ((long)k * a.P + p0 + q) * G + g0;
                 real out[4] = {0, 0, 0, 0};
-                if (!moving) {
+                if (!mv[q]) {
 #pragma unroll
                     for (int i = 0; i < 4; ++i)
                         if (i < W) out[i] = F[(g0 + i + 1) * KS + k];
@@ -2013,8 +2041,16 @@ void launch_chilab(const ChiLabArgs<real> &a, hipStream_t st)
 template <typename real>
 void launch_boost(const BoostArgs<real> &a, hipStream_t st)
 {
+    // two points per workgroup where a point's groups fill 64 bytes and both tables fit
+    const size_t one = boost_lds<real>(a.K, a.fi.G), two = one + sizeof(real) * (a.fi.G + 2) * (size_t)((a.K + 2) | 1);
+    if (a.fi.G * sizeof(real) == 64 && two <= 160 * 1024) {
+        const long items = (a.P + 1) / 2;
+        const unsigned nb = (unsigned)(8 * ((items + 7) / 8));
+        hipLaunchKernelGGL((k_boost<real, 2>), dim3(nb), dim3(kRemapThreads), two, st, a);
+        return;
+    }
     const unsigned nb = (unsigned)(8 * ((a.P + 7) / 8));
-    hipLaunchKernelGGL(k_boost<real>, dim3(nb), dim3(kRemapThreads), boost_lds<real>(a.K, a.fi.G), st, a);
+    hipLaunchKernelGGL((k_boost<real, 1>), dim3(nb), dim3(kRemapThreads), one, st, a);
 }
 template <typename real>
 void launch_unboost(const UnboostArgs<real> &a, hipStream_t st)
@@ -2249,8 +2285,10 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_trace<double, kChiArray, 4, 1>),
                          reinterpret_cast<const void *>(&k_trace<double, kChiArray, 4, 2>),
                          reinterpret_cast<const void *>(&k_trace<double, kChiArray, 4, 4>),
-                         reinterpret_cast<const void *>(&k_boost<float>),
-                         reinterpret_cast<const void *>(&k_boost<double>),
+                         reinterpret_cast<const void *>(&k_boost<float, 1>),
+                         reinterpret_cast<const void *>(&k_boost<float, 2>),
+                         reinterpret_cast<const void *>(&k_boost<double, 1>),
+                         reinterpret_cast<const void *>(&k_boost<double, 2>),
                          reinterpret_cast<const void *>(&k_unboost<float>),
                          reinterpret_cast<const void *>(&k_unboost<double>),
                          reinterpret_cast<const void *>(&k_source_compton<float>),
