@@ -1026,42 +1026,57 @@ __global__ void __launch_bounds__(kRemapThreads, 4) k_boost(BoostArgs<real> a)
 // the comoving value of ordinate j is the remap of the invariant I/nu^3 at the
 // lab direction and frequency D' nu of that comoving ray.  Output I0[p][g][j].
 // ---------------------------------------------------------------------------
-template <typename real>
+// NPT neighbouring points per workgroup (2 where a point's groups fill 64
+// bytes: the staging then reads whole 128-byte lines of each ordinate).
+template <typename real, int NPT>
 __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_unboost(UnboostArgs<real> a)
 {
     extern __shared__ unsigned char smem_raw[];
-    const long p = xcd_item(a.P);
-    if (p >= a.P) return;
+    const long p0 = xcd_item((a.P + NPT - 1) / NPT) * NPT;
+    if (p0 >= a.P) return;
     const int G = a.fi.G, K = a.K, T = blockDim.x, tid = threadIdx.x, KS = table_stride(K);
+    const int TS = (G + 2) * KS;
     double *fbuf = reinterpret_cast<double *>(smem_raw);                // [4G]
-    real *F = reinterpret_cast<real *>(fbuf + 4 * G);                   // [G+2][KS]
+    real *F0 = reinterpret_cast<real *>(fbuf + 4 * G);                  // [NPT][G+2][KS]
+    const int np = (int)min((long)NPT, a.P - p0);
 
     const FreqL fl = stage_freq(a.fi, fbuf);
-    double b[3];
-    const bool moving = load_beta(a.beta, p, b);
+    bool mv[NPT];
+#pragma unroll
+    for (int q = 0; q < NPT; ++q) {
+        double b[3];
+        mv[q] = q < np && load_beta(a.beta, p0 + q, b);
+    }
+    // the first (point, ordinate) pair's entry, before staging
     RemapEntry<real> e{};
-    if (moving && tid < K) e = a.plan[p * K + tid];     // the first ordinate's entry, before staging
+    {
+        const int q = tid / K, j = tid - q * K;
+        if (q < np && mv[q]) e = a.plan[(p0 + q) * K + j];
+    }
     if ((G & 3) == 0) {
-        // 16-byte loads, four groups of one ordinate per lane, written down a
+        // 16-byte loads, four groups of one (ordinate, point) per lane, written down a
         // table column; four loads per lane in flight
         using P4 = Pack<real, 4>;
-        const int G4 = G >> 2, n4 = K * G4;
-        const float rG4 = 1.0f / (float)G4;
+        const int G4 = G >> 2, IC = NPT * G4, n4 = K * IC;
+        const float rIC = 1.0f / (float)IC;
         for (int i0 = tid; i0 < n4; i0 += 4 * T) {
             P4 v[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int idx = i0 + u * T;
-                if (idx < n4) {
-                    const int k = (int)(((float)idx + 0.5f) * rG4), g = (idx - k * G4) * 4;
-                    v[u] = *reinterpret_cast<const P4 *>(a.Ilab + ((long)k * a.P + p) * G + g);
+                const int k = (int)(((float)idx + 0.5f) * rIC), rem = idx - k * IC, q = rem / G4;
+                if (idx < n4 && q < np) {
+                    const int g = (rem - q * G4) * 4;
+                    v[u] = *reinterpret_cast<const P4 *>(a.Ilab + ((long)k * a.P + p0 + q) * G + g);
                 }
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int idx = i0 + u * T;
-                if (idx < n4) {
-                    const int k = (int)(((float)idx + 0.5f) * rG4), g = (idx - k * G4) * 4;
+                const int k = (int)(((float)idx + 0.5f) * rIC), rem = idx - k * IC, q = rem / G4;
+                if (idx < n4 && q < np) {
+                    const int g = (rem - q * G4) * 4;
+                    real *F = F0 + q * TS;
                     F[(g + 1) * KS + k] = v[u].v[0];
                     F[(g + 2) * KS + k] = v[u].v[1];
                     F[(g + 3) * KS + k] = v[u].v[2];
@@ -1070,25 +1085,30 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_un
             }
         }
     } else {
-        const float rG = 1.0f / (float)G;
-        for (int idx = tid; idx < K * G; idx += T) {
-            const int k = (int)(((float)idx + 0.5f) * rG), g = idx - k * G;
-            F[(g + 1) * KS + k] = a.Ilab[((long)k * a.P + p) * G + g];
+        const int IC = NPT * G;
+        const float rIC = 1.0f / (float)IC;
+        for (int idx = tid; idx < K * IC; idx += T) {
+            const int k = (int)(((float)idx + 0.5f) * rIC), rem = idx - k * IC, q = rem / G, g = rem - q * G;
+            if (q < np) F0[q * TS + (g + 1) * KS + k] = a.Ilab[((long)k * a.P + p0 + q) * G + g];
         }
     }
-    real *__restrict__ out = a.I0 + (long)p * G * K;
-    if (!moving) {
-        __syncthreads();
-        for (int g = 0; g < G; ++g)
-            for (int j = tid; j < K; j += T) out[g * K + j] = F[(g + 1) * KS + j];
-        return;
-    }
-    table_ghosts(F, G, KS);
+#pragma unroll
+    for (int q = 0; q < NPT; ++q)
+        if (mv[q]) table_ghosts(F0 + q * TS, G, KS);
     __syncthreads();
-    table_poles(F, G, K, KS, a.nmu, a.nphi);
+#pragma unroll
+    for (int q = 0; q < NPT; ++q)
+        if (mv[q]) table_poles(F0 + q * TS, G, K, KS, a.nmu, a.nphi);
     __syncthreads();
-    for (int j = tid; j < K; j += T) {
-        if (j != tid) e = a.plan[p * K + j];
+    for (int idx = tid; idx < np * K; idx += T) {
+        const int q = idx / K, j = idx - q * K;
+        const real *F = F0 + q * TS;
+        real *__restrict__ out = a.I0 + (p0 + q) * G * K;
+        if (!mv[q]) {
+            for (int g = 0; g < G; ++g) out[g * K + j] = F[(g + 1) * KS + j];
+            continue;
+        }
+        if (idx != tid) e = a.plan[(p0 + q) * K + j];
         const Taps4<real> tp = entry_taps(e.abs, e.w, K, a.nmu, a.nphi);
         if (a.fi.grey) {
             out[j] = tap_row(F + KS, tp) * e.u;
@@ -2055,8 +2075,16 @@ void launch_boost(const BoostArgs<real> &a, hipStream_t st)
 template <typename real>
 void launch_unboost(const UnboostArgs<real> &a, hipStream_t st)
 {
+    // two points per workgroup where a point's groups fill 64 bytes and both tables fit
+    const size_t one = unboost_lds<real>(a.K, a.fi.G), two = one + sizeof(real) * (a.fi.G + 2) * (size_t)((a.K + 2) | 1);
+    if (a.fi.G * sizeof(real) == 64 && two <= 160 * 1024) {
+        const long items = (a.P + 1) / 2;
+        const unsigned nb = (unsigned)(8 * ((items + 7) / 8));
+        hipLaunchKernelGGL((k_unboost<real, 2>), dim3(nb), dim3(kRemapThreads), two, st, a);
+        return;
+    }
     const unsigned nb = (unsigned)(8 * ((a.P + 7) / 8));
-    hipLaunchKernelGGL(k_unboost<real>, dim3(nb), dim3(kRemapThreads), unboost_lds<real>(a.K, a.fi.G), st, a);
+    hipLaunchKernelGGL((k_unboost<real, 1>), dim3(nb), dim3(kRemapThreads), one, st, a);
 }
 size_t do2sh_lds(int NL) { return sizeof(float) * 64 * (size_t)(((NL + 15) / 16) * 16 + 4); }
 
@@ -2289,8 +2317,10 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_boost<float, 2>),
                          reinterpret_cast<const void *>(&k_boost<double, 1>),
                          reinterpret_cast<const void *>(&k_boost<double, 2>),
-                         reinterpret_cast<const void *>(&k_unboost<float>),
-                         reinterpret_cast<const void *>(&k_unboost<double>),
+                         reinterpret_cast<const void *>(&k_unboost<float, 1>),
+                         reinterpret_cast<const void *>(&k_unboost<float, 2>),
+                         reinterpret_cast<const void *>(&k_unboost<double, 1>),
+                         reinterpret_cast<const void *>(&k_unboost<double, 2>),
                          reinterpret_cast<const void *>(&k_source_compton<float>),
                          reinterpret_cast<const void *>(&k_do2sh_f16<1, 1, 16>),
                          reinterpret_cast<const void *>(&k_do2sh_f16<1, 2, 16>),
