@@ -1508,6 +1508,61 @@ __global__ void __launch_bounds__(256) k_source_resid(SourceArgs<real> a, const 
     }
 }
 
+// the same with four coefficients per lane (16-byte loads and stores; NL a multiple of 4 with
+// NL / 4 dividing 64): a wave takes 256 / NL rows
+template <typename real>
+__global__ void __launch_bounds__(256) k_source_resid4(SourceArgs<real> a, const real *__restrict__ Sold, double *rows)
+{
+    using P4 = Pack<real, 4>;
+    const int G = a.G, NL = a.NL, LR = NL >> 2, RW = 64 / LR;
+    const long PG = a.P * G;
+    const int lane = threadIdx.x & 63, sub = lane / LR, q0 = (lane - sub * LR) * 4;
+    const long wave = ((long)blockIdx.x * blockDim.x + threadIdx.x) >> 6;
+    const long nwaves = ((long)gridDim.x * blockDim.x) >> 6;
+    real cl[4];
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const int q = q0 + c;
+        int l = (int)sqrtf((float)q);
+        while (l * l > q) --l;
+        while ((l + 1) * (l + 1) <= q) ++l;
+        cl[c] = (l == 0) ? real(1) : (l == 2 ? real(0.1) : real(0));   // chi_l/(2l+1), Thomson
+    }
+    for (long r0 = wave * RW; r0 < PG; r0 += nwaves * RW) {
+        const long r = r0 + sub;
+        double dd = 0.0, aa = 0.0;
+        if (r < PG) {
+            const long idx = r * NL + q0, p = r / G;
+            const real chi = a.chi0[r];
+            const P4 in = *reinterpret_cast<const P4 *>(a.Ilm + idx);
+            const P4 old = *reinterpret_cast<const P4 *>(Sold + idx);
+            P4 v{};
+            if (chi > real(0)) {
+                const real f = a.sigma[p] / chi;
+#pragma unroll
+                for (int c = 0; c < 4; ++c) v.v[c] = f * cl[c] * in.v[c];
+                if (q0 == 0) v.v[0] += real(3.5449077018110318) * a.kappa[r] * a.bnu[r] / chi;
+            }
+            *reinterpret_cast<P4 *>(a.S + idx) = v;
+#pragma unroll
+            for (int c = 0; c < 4; ++c) {
+                const double u = (double)v.v[c], d = u - (double)old.v[c];
+                dd += d * d;
+                aa += u * u;
+            }
+        }
+        for (int off = LR >> 1; off > 0; off >>= 1) {
+            dd += __shfl_xor(dd, off, 64);
+            aa += __shfl_xor(aa, off, 64);
+        }
+        if (q0 == 0 && r < PG) {
+            const long pp = r / G, g = r - pp * G;
+            rows[g * a.P + pp] = dd;
+            rows[(G + g) * a.P + pp] = aa;
+        }
+    }
+}
+
 // Compton: one workgroup per point; its SH intensities I[i][q] (all groups) are
 // staged in LDS and S[j][q] = sigma/chi_j sum_i A_l(q)[j][i] I[i][q] + T_q
 template <typename real>
@@ -2212,7 +2267,15 @@ void launch_moments_co(long PG, int NL, int lmax, const real *Ilm, double *J, do
 template <typename real>
 bool launch_source_resid(const SourceArgs<real> &a, const real *Sold, double *rows, hipStream_t st)
 {
-    if (a.compton || a.NL > 64 || 64 % a.NL != 0) return false;
+    if (a.compton) return false;
+    if (a.NL % 4 == 0 && a.NL <= 256 && 256 % a.NL == 0) {
+        const int rw = 256 / a.NL;                       // rows per wave
+        const long waves = (a.P * a.G + rw - 1) / rw;
+        const unsigned nb = (unsigned)std::min<long>((waves + 3) / 4, 16384);
+        hipLaunchKernelGGL(k_source_resid4<real>, dim3(nb), dim3(256), 0, st, a, Sold, rows);
+        return true;
+    }
+    if (a.NL > 64 || 64 % a.NL != 0) return false;
     const long waves = (a.P * a.G + 64 / a.NL - 1) / (64 / a.NL);
     const unsigned nb = (unsigned)std::min<long>((waves + 3) / 4, 16384);
     hipLaunchKernelGGL(k_source_resid<real>, dim3(nb), dim3(256), 0, st, a, Sold, rows);

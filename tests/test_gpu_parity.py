@@ -76,6 +76,8 @@ CASES = {
     "grey_extinction_8g": dict(nx=7, ny=6, nz=7, G=8, grey_kappa=True, seed=8, gamma_max=10.0),
     # 16 groups (64 bytes per point in FP32: two points per frame-transform workgroup), odd point count
     "thomson_16g_odd_points": dict(nx=5, ny=3, nz=5, G=16, seed=10, gamma_max=6.0),
+    # L = 15 Thomson (the fused source and residual on 256-term rows)
+    "thomson_L15": dict(nx=4, ny=3, nz=3, G=2, lmax=15, nmu=16, nphi=32, seed=11),
     # L = 15 (256 SH terms, 16 x 32 ordinates): the widest SH products and Compton source
     "compton_L15": dict(nx=4, ny=4, nz=3, G=4, lmax=15, nmu=16, nphi=32, scatter="compton", seed=9,
                         edges=np.exp(np.linspace(np.log(1.0), np.log(150.0), 5)), mec2=W.MEC2_KEV),
