@@ -587,6 +587,17 @@ static void bezier_weights(double h, double *ex, double w[4])
     w[3] = E[0] - 3.0 * E[1] + 3.0 * E[2] - E[3];
 }
 
+/* An upwind displacement within rounding of a whole number of cells is that
+   whole number: a ray in a grid plane (n_x = cos(pi/2) evaluates to ~6e-17)
+   then interpolates nothing across it.  Otherwise a tap weight of ~1e-15
+   would give a vacuum neighbour a depth of ~1e-15 instead of 0, and the
+   slope limiter treats zero and positive depths differently. */
+static double snap_cells(double o)
+{
+    double r = nearbyint(o);
+    return fabs(o - r) < 1e-9 ? r : o;
+}
+
 /* For every lab ordinate and group, march the z planes from the inflow face:
    I_p = I_u e^{-h} + Bezier integral of S~ over the segment from the upwind
    point u on the previous plane (back-traced a distance dz/|mu| along -n and
@@ -603,7 +614,7 @@ void or_trace(const or_problem *pr, const double *St, const double *Xt, double *
             ordinate_dir(pr, k, n);
             double mu = n[2];
             double ds = dz / fabs(mu);
-            double ox = -ds * n[0] / dx, oy = -ds * n[1] / dy;
+            double ox = snap_cells(-ds * n[0] / dx), oy = snap_cells(-ds * n[1] / dy);
             long o = ((long)k * G + g) * P;
             const double *S = St + o, *X = Xt + o;
             double *Ik = I + o;

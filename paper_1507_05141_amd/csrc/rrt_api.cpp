@@ -1047,7 +1047,12 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
             rrt::OrdGeom &gm = geo[k];
             gm.ds = dz / std::fabs(n[2]);
             gm.up = n[2] > 0 ? 1 : 0;
-            const double ox = -gm.ds * n[0] / dx, oy = -gm.ds * n[1] / dy;
+            // a displacement within rounding of whole cells (a ray in a grid plane,
+            // n_x = cos(pi/2) ~ 6e-17) is taken as whole: no tap weight of ~1e-15
+            // gives a vacuum neighbour a positive depth, which the slope limiter
+            // would treat differently from zero
+            auto snap = [](double o) { const double r = std::nearbyint(o); return std::fabs(o - r) < 1e-9 ? r : o; };
+            const double ox = snap(-gm.ds * n[0] / dx), oy = snap(-gm.ds * n[1] / dy);
             const double sh[3] = {2.0, 1.0, -1.0};
             for (int c = 0; c < 3; ++c) {
                 const double sx = sh[c] * ox, sy = sh[c] * oy;
