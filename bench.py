@@ -35,7 +35,8 @@ def algorithmic(kernel, spec, esz, time_dependent):
     G = len(spec["edges"]) - 1 if spec.get("edges") is not None else 1
     K = spec["nmu"] * spec["nphi"]
     NL = (spec["lmax"] + 1) ** 2
-    fused = spec.get("scatter", "thomson") != "compton" and 64 % NL == 0
+    fused = spec.get("scatter", "thomson") != "compton" and (
+        64 % NL == 0 or (NL % 4 == 0 and 256 % NL == 0))
     do, sh = n * G * K, n * G * NL
     table = {
         # S~ read, I written
@@ -152,6 +153,147 @@ def serving_bench(args):
             "capacity": cap, "stream": res}
 
 
+def validation_runs(args):
+    """The paper's validation problems (Sec. 4) at its own grid and ordinate
+    sizes, in FP32 on the library, each checked against the closed form the
+    paper compares with.  One JSON line per problem: wall time, sweeps,
+    updates per second and the measured deviations."""
+    import numpy as np
+    from paper_1507_05141_amd import binding as B
+    from paper_1507_05141_amd import workloads as W
+
+    def beam_J(nmu, nphi):
+        mu, wmu = np.polynomial.legendre.leggauss(nmu)
+        return mu[-1], wmu[-1] * 2 * np.pi / nphi / (4 * np.pi)
+
+    def run(spec, I0, how):
+        g = B.Problem.from_spec(spec, precision=B.FP32)
+        g.set_intensity(I0)
+        t0 = time.perf_counter()
+        info = how(g)
+        sec = time.perf_counter() - t0
+        J, H, _ = g.moments(B.FRAME_LAB)
+        I = g.intensity() if spec["nmu"] * spec["nphi"] * spec["nx"] * spec["nz"] <= (1 << 26) else None
+        g.close()
+        ups = spec["nx"] * spec["nz"] * spec["nmu"] * spec["nphi"]
+        return dict(seconds=round(sec, 3), sweeps=info["sweeps"], updates_per_s=info["sweeps"] * ups / sec), J, H, I
+
+    def advance(dt, nsteps, scheme, tol, max_iter, use_ng):
+        def how(g):
+            i = g.advance(dt, nsteps=nsteps, scheme=scheme, tol=tol, max_iter=max_iter, use_ng=use_ng)
+            return dict(sweeps=i["iters"])
+        return how
+
+    def steady(g):
+        i = g.solve(tol=1e-10, max_iter=5, use_ng=False)
+        return dict(sweeps=i["iters"])
+
+    def emit(rec):
+        print(json.dumps(rec), flush=True)
+
+    # searchlight beam, 512^2, (4, 8), one cell per step, t = 0.25 s
+    n = 512
+    mu, Jb = beam_J(4, 8)
+    dt = 1.0 / (n - 1)
+    nsteps = int(round(0.25 * W.SECOND / dt))
+    ct = nsteps * dt
+    prof = {}
+    for alpha_cm in (0.0, 1e-10):
+        spec, I0 = W.searchlight(n, alpha_cm=alpha_cm)
+        rec, J, _, _ = run(spec, I0, advance(dt, nsteps, B.SCHEME_RK4, 1e-10, 5, False))
+        J = J[:, 0].reshape(spec["nz"], n)
+        z = np.arange(spec["nz"]) / (spec["nz"] - 1)
+        xi = ((0.3 + z * np.sqrt(1 - mu * mu) / mu) % 1.0) * n
+        i0 = np.floor(xi).astype(int)
+        f = xi - i0
+        rows = np.arange(spec["nz"])
+        Jr = (1 - f) * J[rows, i0 % n] + f * J[rows, (i0 + 1) % n]
+        s = z / mu
+        att = np.exp(-alpha_cm * W.DOMAIN_CM * s)
+        rel = Jr / Jb / att
+        behind = s < ct - 0.25
+        prof[alpha_cm] = rel
+        emit(dict(problem="searchlight", alpha_per_cm=alpha_cm, grid=[n, n], ordinates=[4, 8], t_s=0.25, **rec,
+                  max_dev_behind_front=float(np.max(np.abs(rel[behind] - 1))),
+                  front_half_point_minus_ct=float(s[np.argmin(np.abs(rel - 0.5))] - ct), cell_path=1.0 / (n - 1) / mu))
+    emit(dict(problem="searchlight", check="front shape with / without absorption",
+              max_diff=float(np.max(np.abs(prof[1e-10] - prof[0.0])))))
+
+    # two beams and a shadow, 512^2, (4, 8), steady state
+    Js = {}
+    for beams in ((0,), (1,), (0, 1)):
+        spec, I0 = W.two_beam_shadow(n, beams=beams)
+        rec, J, _, _ = run(spec, I0, steady)
+        Js[beams] = J[:, 0].reshape(spec["nz"], n) / Jb
+    both, nz = Js[(0, 1)], spec["nz"]
+
+    def at(x, z):
+        return float(both[int(round(z * (nz - 1))), int(round(x * n)) % n])
+    emit(dict(problem="two_beam_shadow", grid=[n, n], ordinates=[4, 8], **rec,
+              superposition_dev=float(np.max(np.abs(both - Js[(0,)] - Js[(1,)]))),
+              J_over_beam={"lit_both(0.1,0.05)": at(0.1, 0.05), "above_shadows(0.5,0.9)": at(0.5, 0.9),
+                           "one_shadow(0.75,0.7)": at(0.75, 0.7), "one_shadow(0.25,0.7)": at(0.25, 0.7),
+                           "both_shadows(0.5,0.52)": at(0.5, 0.52)}))
+
+    # optically thin pulse, 128^2, (64, 128), t = 0.1 s: peak of J r against free streaming
+    spec, I0 = W.radiative_pulse(128, nmu=64, nphi=128)
+    n, nz = spec["nx"], spec["nz"]
+    dt = 1.0 / (nz - 1)
+    nsteps = int(round(0.1 * W.SECOND / dt))
+    rec, J, _, _ = run(spec, I0, advance(dt, nsteps, B.SCHEME_RK4, 1e-10, 5, False))
+    J = J[:, 0].reshape(nz, n)
+    t = nsteps * dt
+    mid = (nz - 1) // 2
+    r = np.arange(n // 2) / n
+    mq, wq = np.polynomial.legendre.leggauss(256)
+    ph = (np.arange(512) + 0.5) * np.pi / 256
+    M, PH = np.meshgrid(mq, ph, indexing="ij")
+    nxv, nzv = np.sqrt(1 - M ** 2) * np.cos(PH), M
+    exact = np.array([(wq[:, None] * 100 * np.exp(-((rr - t * nxv) ** 2 + (t * nzv) ** 2) / 0.09 ** 2)).sum()
+                      * (np.pi / 256) / (4 * np.pi) for rr in r])
+    emit(dict(problem="thin_pulse", grid=[n, nz], ordinates=[64, 128], t_s=0.1, **rec,
+              exact_peak_r=float(r[np.argmax(exact)]), exact_peak_J=float(exact.max()),
+              x_axis_peak_r=float(r[np.argmax(J[mid, n // 2:])]), x_axis_peak_J=float(J[mid, n // 2:].max()),
+              z_axis_peak_r=float(r[np.argmax(J[mid:mid + n // 2, n // 2])]),
+              z_axis_peak_J=float(J[mid:mid + n // 2, n // 2].max()), centre_J=float(J[mid, n // 2]),
+              exact_centre_J=float(exact[0])))
+
+    # optically thick pulse, 128^2, (32, 64), backward Euler, dt = 1/20 to t = 1 (c = 1)
+    spec, I0 = W.radiative_pulse(128, nmu=32, nphi=64, thick=True)
+    n, nz = spec["nx"], spec["nz"]
+    rec, J, _, _ = run(spec, I0, advance(0.05, 20, B.SCHEME_EULER, 1e-6, 400, True))
+    J = J[:, 0].reshape(nz, n)
+    x = np.arange(n) / n - 0.5
+    Dc, t, w = 1.0 / (3 * 300.0), 1.0, 0.09
+    Jd = 100 * w / np.sqrt(w ** 2 + 4 * Dc * t) * np.exp(-x ** 2 / (w ** 2 + 4 * Dc * t))
+    emit(dict(problem="thick_pulse", grid=[n, nz], ordinates=[32, 64], t_units=t, **rec,
+              max_dev_over_peak=float(np.max(np.abs(J[(nz - 1) // 2] - Jd)) / Jd.max())))
+
+    # relativistic beaming, 128^2, (32, 64), steady state, beta along x
+    nmu, nphi = 32, 64
+    mq = np.polynomial.legendre.leggauss(nmu)[0]
+    for bx in (0.0, 0.1, 0.5, 0.9, 0.99, 0.995):
+        spec, I0 = W.beaming_cylinder(128, nmu=nmu, nphi=nphi, beta=(bx, 0.0))
+        rec, J, H, I = run(spec, I0, steady)
+        n, nz = spec["nx"], spec["nz"]
+        I = I[:, :, 0].reshape(nmu * nphi, nz, n)
+        worst = 0.0
+        for a in range(nmu):
+            st = np.sqrt(1 - mq[a] ** 2)
+            for b in range(nphi):
+                cph = np.cos(2 * np.pi * b / nphi)
+                if cph <= 0:
+                    continue
+                ratio = ((1 + bx * st * cph) / (1 - bx * st * cph)) ** 3
+                A, Mr = I[a * nphi + b], I[a * nphi + (nphi // 2 - b) % nphi][:, (-np.arange(n)) % n]
+                lit = A > 1e-6 * A.max()
+                if lit.any():
+                    worst = max(worst, float(np.max(np.abs(A[lit] / (Mr[lit] * ratio) - 1))))
+        emit(dict(problem="beaming_cylinder", beta_x=bx, gamma=1 / np.sqrt(1 - bx * bx), grid=[n, nz],
+                  ordinates=[nmu, nphi], **rec, mirror_D3_ratio_max_dev=worst,
+                  flux_x_over_J=float(H[:, 0, 0].sum() / J[:, 0].sum())))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -168,6 +310,8 @@ def main():
     ap.add_argument("--requests", type=int, default=48, help="requests in the --serving stream")
     ap.add_argument("--mix", choices=["small", "full"], default="small",
                     help="--serving request mix: small (n <= 32, G <= 16, L <= 7) or full (n <= 64, G <= 32, L <= 15)")
+    ap.add_argument("--validation", action="store_true",
+                    help="run the paper's validation problems (Sec. 4) at its sizes instead of the sweep benchmark")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")
@@ -187,6 +331,9 @@ def main():
     torch.cuda.set_device(0)
     if args.serving:
         print(json.dumps(serving_bench(args)), flush=True)
+        return
+    if args.validation:
+        validation_runs(args)
         return
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda")

@@ -168,3 +168,117 @@ def random_medium(n=8, nz=None, ng=4, lmax=3, nmu=4, nphi=8, seed=11, scatter="t
                 bc_bot=gen.uniform(0.0, 1.0, (K, n, n, ng)) if with_bc else None,
                 bc_top=gen.uniform(0.0, 1.0, (K, n, n, ng)) if with_bc else None)
     return spec
+
+
+# ---------------------------------------------------------------------------
+# The paper's validation problems (Sec. 4), two-dimensional: ny = 1, symmetry
+# in y.  Lengths are in units of the paper's 1e10 cm domain side, so with c = 1
+# one time unit is 1/3 s; x is periodic and z has nz points on [0, 1].  Each
+# generator returns the problem description and the initial lab intensity
+# (K, P, 1).  Where light enters through the bottom face, the initial field
+# already holds the inflow on that face (the beam is on from t = 0): the
+# inflow-face values are prescribed data that no time step changes.
+# ---------------------------------------------------------------------------
+
+DOMAIN_CM = 1.0e10
+SECOND = 3.0            # c t for t = 1 s, in domain sides (c = 3e10 cm/s)
+
+
+def _plane(n, nz):
+    x = np.arange(n) / n
+    z = np.arange(nz) / (nz - 1)
+    Z, X = np.meshgrid(z, x, indexing="ij")
+    return X.ravel(), Z.ravel()
+
+
+def _two_d(n, nz, nmu, nphi, lmax, kappa, sigma, bnu, beta=None, bc_bot=None):
+    return dict(nx=n, ny=1, nz=nz, lx=1.0, ly=1.0 / n, lz=1.0, nmu=nmu, nphi=nphi, lmax=lmax,
+                edges=None, log_centres=True, scatter="thomson", mec2=MEC2_KEV,
+                kappa=np.asarray(kappa, float).reshape(-1, 1), sigma=np.asarray(sigma, float).ravel(),
+                bnu=np.asarray(bnu, float).reshape(-1, 1), beta=beta, kte=None, bc_bot=bc_bot, bc_top=None)
+
+
+def _inflow_start(spec):
+    """Zero field except the bottom-face inflow (K, P, 1)."""
+    K, n = spec["nmu"] * spec["nphi"], spec["nx"]
+    I0 = np.zeros((K, n * spec["nz"], 1))
+    I0[:, :n, 0] = spec["bc_bot"][:, 0, :, 0]
+    return I0
+
+
+def beam_ordinate(nmu, nphi, phi_index=0):
+    """Index k = a nphi + b of the upward ordinate with the largest mu (the
+    paper's 0.17 pi zenith angle for nmu = 4) and azimuth 2 pi b / nphi."""
+    return (nmu - 1) * nphi + phi_index
+
+
+def searchlight(n=512, nz=None, alpha_cm=0.0, nmu=4, nphi=8, lmax=1):
+    """Searchlight beam (Sec. 4.1): unit intensity enters through the bottom
+    face for 0.15 < x < 0.45 along the ordinate (0.17 pi, 0); uniform
+    absorption alpha (1e-10 / cm in the paper's second case), no scattering."""
+    nz = n if nz is None else nz
+    X, Z = _plane(n, nz)
+    P, K = X.size, nmu * nphi
+    bc = np.zeros((K, 1, n, 1))
+    x = np.arange(n) / n
+    bc[beam_ordinate(nmu, nphi), 0, (x > 0.15) & (x < 0.45), 0] = 1.0
+    spec = _two_d(n, nz, nmu, nphi, lmax, np.full(P, alpha_cm * DOMAIN_CM), np.zeros(P), np.zeros(P), bc_bot=bc)
+    return spec, _inflow_start(spec)
+
+
+def two_beam_shadow(n=512, nz=None, nmu=4, nphi=8, lmax=1, beams=(0, 1)):
+    """Two beams and a shadow (Sec. 4.2): plane-parallel unit intensity enters
+    through the whole bottom face along (0.17 pi, 0) and (0.17 pi, pi); an
+    absorbing cylinder of radius 0.15 about (x, z) = (0.5, 0.33), optical depth
+    100 across its diameter, in vacuum.  `beams` selects which of the two enter."""
+    nz = n if nz is None else nz
+    X, Z = _plane(n, nz)
+    P, K = X.size, nmu * nphi
+    kap = np.where((X - 0.5) ** 2 + (Z - 0.33) ** 2 <= 0.15 ** 2, 3.3e-8 * DOMAIN_CM, 0.0)
+    bc = np.zeros((K, 1, n, 1))
+    for b in beams:
+        bc[beam_ordinate(nmu, nphi, b * nphi // 2), 0, :, 0] = 1.0
+    spec = _two_d(n, nz, nmu, nphi, lmax, kap, np.zeros(P), np.zeros(P), bc_bot=bc)
+    return spec, _inflow_start(spec)
+
+
+def radiative_pulse(n=128, nz=None, nmu=64, nphi=128, lmax=1, thick=False, w_cm=9.0e8):
+    """Radiative pulse (Sec. 4.3): an isotropic initial intensity
+    100 exp(-(r/w)^2) about the domain centre in vacuum (thin), or
+    100 exp(-(x/w)^2) in a purely scattering medium of Thomson depth 300 across
+    the domain (thick, isotropic scattering: the Thomson kernel with L = 0).
+    Returns (problem, initial lab intensity)."""
+    nz = (n + 1) if nz is None else nz
+    X, Z = _plane(n, nz)
+    P, K = X.size, nmu * nphi
+    w = w_cm / DOMAIN_CM
+    dx, dz = X - 0.5, Z - 0.5
+    prof = 100.0 * np.exp(-(dx / w) ** 2) if thick else 100.0 * np.exp(-(dx ** 2 + dz ** 2) / w ** 2)
+    sig = np.full(P, 3.0e-8 * DOMAIN_CM if thick else 0.0)
+    spec = _two_d(n, nz, nmu, nphi, 0 if thick else lmax, np.zeros(P), sig, np.zeros(P))
+    I0 = np.broadcast_to(prof[None, :, None], (K, P, 1)).copy()
+    # vacuum inflow: no light enters through either face (upward ordinates at
+    # z = 0, downward ones at z = 1)
+    up = np.repeat(np.arange(nmu) >= nmu // 2, nphi)
+    I0[up, :n] = 0.0
+    I0[~up, P - n:] = 0.0
+    return spec, I0
+
+
+def beaming_cylinder(n=128, nz=None, nmu=32, nphi=64, lmax=1, beta=(0.0, 0.0), radius_cm=5.0e8,
+                     kappa=1e-9, emission=1.0):
+    """Relativistic beaming (Sec. 4.4): a cylinder of radius 5e8 cm about the
+    domain centre whose matter moves with beta = (vx/c, vz/c) and emits
+    isotropically in its own frame (emissivity kappa B = `emission`, with an
+    absorption coefficient small enough to leave the light unabsorbed); vacuum
+    at rest outside.  Returns (problem, zero initial lab intensity)."""
+    nz = (n + 1) if nz is None else nz
+    X, Z = _plane(n, nz)
+    P = X.size
+    inside = (X - 0.5) ** 2 + (Z - 0.5) ** 2 <= (radius_cm / DOMAIN_CM) ** 2
+    kap = np.where(inside, kappa, 0.0)
+    B = np.where(inside, emission / kappa, 0.0)
+    b = np.zeros((P, 3))
+    b[inside, 0], b[inside, 2] = beta[0], beta[1]
+    spec = _two_d(n, nz, nmu, nphi, lmax, kap, np.zeros(P), B, beta=b)
+    return spec, np.zeros((nmu * nphi, P, 1))
