@@ -771,3 +771,71 @@ def test_floored_residual_only_changes_negligible_groups():
     floor = 1e-20 * np.sqrt(np.sum(S_new[:, :2] ** 2, axis=(0, 2)).max())
     assert np.isclose(out[2], np.sqrt(np.sum((S_new[:, 2] - S_old[:, 2]) ** 2)) / floor, rtol=1e-12)
     assert np.isclose(out[3], np.sqrt(np.sum(S_old[:, 3] ** 2)) / floor, rtol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# the paper's two-dimensional validation problems (Sec. 4), small grids
+# ---------------------------------------------------------------------------
+
+def test_searchlight_attenuation_and_front_in_two_dimensions():
+    """Sec. 4.1 on a 48 x 48 plane with (4, 8) ordinates and the four-stage
+    scheme, one cell per step: behind the front J is the beam's J times
+    exp(-alpha s) (alpha = 1 per domain side), and the front's half point is
+    within two cell paths of c t."""
+    n = 48
+    spec, I0 = W.searchlight(n, alpha_cm=1e-10)
+    o = oracle.Oracle(spec)
+    dt = 1.0 / (n - 1)
+    nsteps = 28
+    I, _ = o.advance(I0, dt, nsteps=nsteps, scheme="rk4", tol=1e-12, max_iter=5)
+    J = o.moments_lab(I)[0][:, 0].reshape(n, n)
+    mu, wmu = np.polynomial.legendre.leggauss(4)
+    Jb = wmu[-1] * 2 * np.pi / 8 / (4 * np.pi)
+    z = np.arange(n) / (n - 1)
+    xi = ((0.3 + z * np.sqrt(1 - mu[-1] ** 2) / mu[-1]) % 1.0) * n
+    i0 = np.floor(xi).astype(int)
+    f = xi - i0
+    Jr = (1 - f) * J[np.arange(n), i0 % n] + f * J[np.arange(n), (i0 + 1) % n]
+    s = z / mu[-1]
+    rel = Jr / Jb / np.exp(-s)
+    ct = nsteps * dt
+    assert np.max(np.abs(rel[s < ct - 0.25] - 1)) < 2e-3
+    assert abs(s[np.argmin(np.abs(rel - 0.5))] - ct) < 2 * dt / mu[-1]
+
+
+def test_inconsistent_inflow_face_grows_ninefold_per_four_stage_step():
+    """Inflow-face values are fixed by the boundary in every stage, the z -> inf
+    mode of the four-stage combination: an initial field that disagrees with the
+    boundary there by d becomes d (1 - 9^m) after m steps, while one that agrees
+    stays bounded."""
+    spec, I0 = W.searchlight(16)
+    o = oracle.Oracle(spec)
+    I, _ = o.advance(np.zeros_like(I0), 0.05, nsteps=2, scheme="rk4", tol=1e-12, max_iter=5)
+    assert np.isclose(np.abs(I).max(), 80.0)
+    I, _ = o.advance(I0, 0.05, nsteps=2, scheme="rk4", tol=1e-12, max_iter=5)
+    assert np.abs(I).max() <= 1.0 + 1e-12
+
+
+@pytest.mark.parametrize("bx", [0.0, 0.9, 0.995])
+def test_moving_emitter_is_beamed_as_the_cube_of_the_doppler_factor(bx):
+    """Sec. 4.4: isotropic comoving emission from matter moving along x has the
+    lab emissivity D^3 eta_0 along n; on a grid and ordinate set symmetric under
+    x -> -x the intensity along (theta, phi) at x over that along (theta, pi - phi)
+    at -x is ((1 + beta sin(theta) cos(phi)) / (1 - beta sin(theta) cos(phi)))^3
+    (up to the 1e-9 absorption left in the emitter)."""
+    nmu, nphi, n = 8, 16, 24
+    spec, _ = W.beaming_cylinder(n, nmu=nmu, nphi=nphi, beta=(bx, 0.0), radius_cm=1.5e9)
+    o = oracle.Oracle(spec)
+    I = o.solve(tol=1e-12, max_iter=5, use_ng=False)["I_lab"][:, :, 0].reshape(nmu * nphi, spec["nz"], n)
+    worst = 0.0
+    for a in range(nmu):
+        st = np.sqrt(1 - o.mu[a] ** 2)
+        for b in range(nphi):
+            cph = np.cos(2 * np.pi * b / nphi)
+            if cph <= 0:
+                continue
+            ratio = ((1 + bx * st * cph) / (1 - bx * st * cph)) ** 3
+            A, M = I[a * nphi + b], I[a * nphi + (nphi // 2 - b) % nphi][:, (-np.arange(n)) % n]
+            lit = A > 1e-6 * A.max()
+            worst = max(worst, float(np.max(np.abs(A[lit] / (M[lit] * ratio) - 1))))
+    assert worst < 1e-8
