@@ -876,7 +876,7 @@ size_t footprint(const rrt_grid *g, const rrt_groups *gr, const rrt_angles *a, i
     total += P * (3 * G + 1) * esz + 4 * P * 8;     // fields, chi0, beta, Gamma
     total += 2 * P * K * 8 * esz;                    // remap plan of a moving medium (two entries per point and ordinate)
     total += 2 * (size_t)g->nx * g->ny * K * G * esz;  // boundaries
-    total += 16 * P * G + (1 << 20);                 // residual partial sums, tables
+    total += 16 * P * G + 16 * G * rrt::kResidSplit + (1 << 20);   // residual row and partial sums, tables
     return total;
 }
 
@@ -1140,7 +1140,8 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
     }
     pr->nblk_red = 1024;
     if ((s = pr_alloc(pr, (void **)&pr->d_partial,
-                       std::max((size_t)pr->nblk_red * std::max(2 * G, 5), 2 * (size_t)pr->P * G) * 8)) ||
+                       std::max((size_t)pr->nblk_red * std::max(2 * G, 5),
+                                2 * (size_t)pr->P * G + 2 * (size_t)G * rrt::kResidSplit) * 8)) ||
         (s = pr_alloc(pr, (void **)&pr->d_red, (size_t)std::max(2 * G, 5) * 8)))
         return bail(s);
     if (hipHostMalloc((void **)&pr->h_red, (size_t)std::max(2 * G, 5) * 8, hipHostMallocDefault) != hipSuccess) {

@@ -154,6 +154,8 @@ template <typename real> void launch_source(const SourceArgs<real> &a, hipStream
 // Thomson source with the residual's per-row sums against Sold (rows[g P + p], rows[(G + g) P + p]) in the
 // same pass; false (nothing launched) for Compton or NL not dividing 64
 template <typename real> bool launch_source_resid(const SourceArgs<real> &a, const real *Sold, double *rows, hipStream_t st);
+// rows holds 2 P G row sums followed by room for 2 G kResidSplit partial sums
+constexpr int kResidSplit = 64;
 template <typename real> void launch_resid_groups(long P, int G, const double *rows, double *out, hipStream_t st);
 template <typename real> void launch_chi0(long P, int G, const real *kappa, const real *sigma, const real *sg, real *chi0, hipStream_t st);
 template <typename real> void launch_moments_lab(long P, int G, int K, const double *dir, const real *I, double *J, double *H, double *Kt, hipStream_t st);

@@ -1467,7 +1467,7 @@ __global__ void __launch_bounds__(256) k_source(SourceArgs<real> a)
 // takes 64 / NL (point, group) rows, computes their new source coefficients,
 // and reduces sum (S_new - S_old)^2 and sum S_new^2 of each row in FP64 across
 // the row's lanes; rows[g P + p] and rows[(G + g) P + p] receive them (the
-// per-group totals follow in k_resid_groups)
+// per-group totals follow in k_resid_part / k_resid_fin)
 template <typename real>
 __global__ void __launch_bounds__(256) k_source_resid(SourceArgs<real> a, const real *__restrict__ Sold, double *rows)
 {
@@ -1837,16 +1837,42 @@ __global__ void __launch_bounds__(256) k_resid_rows(long P, int G, int NL, const
     }
 }
 
-// out[2g + c] = sum over points of rows[(c G + g) P + p]; one block per (g, c)
-__global__ void __launch_bounds__(256) k_resid_groups(long P, int G, const double *__restrict__ rows, double *out)
+// Per-group totals of the row sums, out[2g + c] = sum over points of
+// rows[(c G + g) P + p], in two passes with a fixed order: block (s, cg) sums
+// chunk s of row block cg into part[cg S + s] (two loads in flight per thread),
+// then one thread per row block adds its S partial sums in order.
+__global__ void __launch_bounds__(256) k_resid_part(long P, int S, const double *__restrict__ rows, double *part)
 {
     __shared__ double sh[256];
-    const int g = blockIdx.x >> 1, c = blockIdx.x & 1;
+    const int cg = blockIdx.y, s = blockIdx.x;
+    const long chunk = (P + S - 1) / S, b = (long)s * chunk, e = min(P, b + chunk);
+    const double *__restrict__ x = rows + (long)cg * P;
+    double v0 = 0, v1 = 0;
+    long p = b + threadIdx.x;
+    for (; p + 256 < e; p += 512) {
+        v0 += x[p];
+        v1 += x[p + 256];
+    }
+    if (p < e) v0 += x[p];
+    const double v = block_sum(v0 + v1, sh);
+    if (threadIdx.x == 0) part[(long)cg * S + s] = v;
+}
+__global__ void __launch_bounds__(64) k_resid_fin(int G, int S, const double *__restrict__ part, double *out)
+{
+    const int cg = blockIdx.x * blockDim.x + threadIdx.x;
+    if (cg >= 2 * G) return;
     double v = 0;
-    const double *__restrict__ x = rows + (c * (long)G + g) * P;
-    for (long p = threadIdx.x; p < P; p += blockDim.x) v += x[p];
-    v = block_sum(v, sh);
-    if (threadIdx.x == 0) out[2 * g + c] = v;
+    for (int s = 0; s < S; ++s) v += part[(long)cg * S + s];
+    const int c = cg / G, g = cg - c * G;
+    out[2 * g + c] = v;
+}
+static void launch_group_totals(long P, int G, const double *rows, double *out, hipStream_t st)
+{
+    // about 1024 blocks over the 2 G row blocks, chunks of at least 512 points
+    const long S = std::max<long>(1, std::min<long>({kResidSplit, (1024 + 2 * G - 1) / (2 * G), P / 512}));
+    double *part = const_cast<double *>(rows) + 2 * P * G;
+    hipLaunchKernelGGL(k_resid_part, dim3((unsigned)S, 2 * G), dim3(256), 0, st, P, (int)S, rows, part);
+    hipLaunchKernelGGL(k_resid_fin, dim3((2 * G + 63) / 64), dim3(64), 0, st, G, (int)S, part, out);
 }
 
 // five dot products for the Ng extrapolation from the chain s3 (oldest) .. s0
@@ -2284,7 +2310,7 @@ bool launch_source_resid(const SourceArgs<real> &a, const real *Sold, double *ro
 template <typename real>
 void launch_resid_groups(long P, int G, const double *rows, double *out, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_resid_groups, dim3(2 * G), dim3(256), 0, st, P, G, rows, out);
+    launch_group_totals(P, G, rows, out, st);
 }
 template <typename real>
 void launch_resid(long P, int G, int NL, const real *a, const real *b, double *rows, int nblk, double *out, hipStream_t st)
@@ -2292,7 +2318,7 @@ void launch_resid(long P, int G, int NL, const real *a, const real *b, double *r
     (void)nblk;
     const unsigned nb = (unsigned)std::min<long>((P * G + 3) / 4, 8192);   // 4 waves per block, one row each
     hipLaunchKernelGGL(k_resid_rows<real>, dim3(nb), dim3(256), 0, st, P, G, NL, a, b, rows);
-    hipLaunchKernelGGL(k_resid_groups, dim3(2 * G), dim3(256), 0, st, P, G, rows, out);
+    launch_group_totals(P, G, rows, out, st);
 }
 template <typename real>
 void launch_ng_dots(long n, int G, int NL, const double *red, double floor2, const real *s0, const real *s1,
