@@ -373,7 +373,7 @@ __device__ __forceinline__ void trace_fetch(PlaneRegs<real, GC, MAXPT> &r, const
 
 // write value v of point (i, j) into an LDS plane with its periodic halo
 template <typename T>
-__device__ __forceinline__ void lds_put(T *pl, const TraceIdx &q, int i, int j, const T &v)
+__device__ __forceinline__ void lds_put(T *pl, const TraceIdx &q, int i, int j, const T v)
 {
     pl[j * q.RS + i] = v;
     if (i == 0) pl[j * q.RS + q.nx] = v;
