@@ -1609,7 +1609,7 @@ constexpr int kComptonMfmaThreads = 512;
 
 __global__ void __launch_bounds__(kComptonMfmaThreads, 4) k_source_compton_mfma(SourceArgs<float> a, int lmax)
 {
-    using P4 = Pack<float, 4>;
+    typedef float P4 __attribute__((ext_vector_type(4)));
     constexpr int RS = 256;                                // LDS row stride (the largest NL), 32 rows
     extern __shared__ unsigned char smem_raw[];
     const int G = a.G, NL = a.NL, GN = G * NL, GN4 = GN >> 2, NL4 = NL >> 2;
@@ -1707,9 +1707,8 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, 4) k_source_compton_mfma(
                 const int j = i / NL4, q = (i - j * NL4) * 4;
                 const float f = sF[j];
                 P4 v = *reinterpret_cast<const P4 *>(sI + j * RS + q);
-#pragma unroll
-                for (int c = 0; c < 4; ++c) v.v[c] *= f;
-                if (q == 0) v.v[0] += sT[j];
+                v *= f;
+                if (q == 0) v.x += sT[j];
                 reinterpret_cast<P4 *>(dst)[i] = v;
             }
         }
