@@ -136,7 +136,14 @@ rrt_status rrt_solve(rrt_problem *pr, double tol, int max_iter, int use_ng, rrt_
 
 /* nsteps time steps of length dt from the intensity state: RRT_SCHEME_RK4 is
    the four implicit stages of Appendix A (dt/6, dt/3, dt/3, dt/6 and
-   Eq. A1), RRT_SCHEME_EULER one implicit stage.  Each stage is a solve to tol. */
+   Eq. A1), RRT_SCHEME_EULER one implicit stage.  Each stage is a solve to tol.
+   Every stage returns the boundary inflow on the inflow faces unchanged, so
+   the intensity state should already hold it there (upward ordinates on
+   z = 0, downward ones on z = lz): with RRT_SCHEME_RK4 a difference d between
+   the state and the boundary on those faces becomes d (1 - 9^m) after m
+   steps (the scheme's amplification of an infinitely stiff mode); with
+   RRT_SCHEME_EULER it is replaced by the boundary in one step.  The library
+   does not alter the caller's state. */
 rrt_status rrt_advance(rrt_problem *pr, double dt, int nsteps, int scheme, double tol,
                        int max_iter, int use_ng, rrt_info *info);
 
