@@ -140,7 +140,7 @@ rrt_status rrt_solve(rrt_problem *pr, double tol, int max_iter, int use_ng, rrt_
    Every stage returns the boundary inflow on the inflow faces unchanged, so
    the intensity state should already hold it there (upward ordinates on
    z = 0, downward ones on z = lz): with RRT_SCHEME_RK4 a difference d between
-   the state and the boundary on those faces becomes d (1 - 9^m) after m
+   the state and the boundary on those faces grows to d 9^m after m
    steps (the scheme's amplification of an infinitely stiff mode); with
    RRT_SCHEME_EULER it is replaced by the boundary in one step.  The library
    does not alter the caller's state. */

@@ -806,7 +806,8 @@ def test_searchlight_attenuation_and_front_in_two_dimensions():
 def test_inconsistent_inflow_face_grows_ninefold_per_four_stage_step():
     """Inflow-face values are fixed by the boundary in every stage, the z -> inf
     mode of the four-stage combination: an initial field that disagrees with the
-    boundary there by d becomes d (1 - 9^m) after m steps, while one that agrees
+    boundary there by d disagrees by d 9^m after m steps (the state is 1 - 9^m for
+    a unit beam from zero), while one that agrees
     stays bounded."""
     spec, I0 = W.searchlight(16)
     o = oracle.Oracle(spec)
