@@ -256,3 +256,25 @@ def test_beaming_is_the_cube_of_the_doppler_factor(prec):
         ahead.append(H[:, 0, 0].sum() / J[:, 0].sum())
     assert abs(ahead[0]) < 1e-6
     assert all(b > a for a, b in zip(ahead, ahead[1:])), ahead
+
+
+@pytest.mark.parametrize("problem", ["thick_pulse", "beaming_cylinder"])
+def test_validation_problems_in_mixed_precision(problem):
+    """Mixed precision (FP16 matrix-core SH <-> ordinate products with FP32
+    accumulation) against the FP64 oracle: J, H and K of the lab frame within
+    1e-3 of each moment's maximum.  The scattering pulse's steps stop at
+    residual 1e-5 (stage albedo 0.94: up to ~2e-4 from the fixed point)."""
+    print(f"{problem} mixed precision", flush=True)
+    if problem == "thick_pulse":
+        spec, I0 = W.radiative_pulse(16, nmu=4, nphi=8, thick=True)
+        run = _advance(0.05, 3, "euler", tol=1e-5, max_iter=400, use_ng=True, oracle_tol=1e-13)
+    else:
+        spec, I0 = W.beaming_cylinder(24, nmu=8, nphi=16, beta=(0.9, 0.3), radius_cm=1.5e9)
+        run = _steady()
+    o = oracle.Oracle(spec)
+    g = _problem(spec, I0, B.MIXED)
+    I_ref = run(o, I0, None)
+    run(None, None, g)
+    for name, got, ref in zip("JHK", g.moments(B.FRAME_LAB), o.moments_lab(I_ref)):
+        _close(got, ref, 1e-3, name)
+    g.close()
