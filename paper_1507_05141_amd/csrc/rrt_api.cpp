@@ -72,6 +72,7 @@ struct rrt_problem {
            *d_inv_dc = nullptr;
     rocblas_handle blas = nullptr;
     int Gc = 1;
+    int Gc_max = 1;                                 // the most groups per trace workgroup the LDS holds
     rrt::OrdGeom *d_geo = nullptr;
     void *d_Yt = nullptr, *d_WY = nullptr, *d_A = nullptr, *d_sg = nullptr;
     void *d_Y16 = nullptr, *d_WYt16 = nullptr;     // RRT_MIXED: FP16 SH tables, hi then lo part (zero padded)
@@ -977,6 +978,9 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
         }
         for (int gc = 4; !pr->Gc && gc >= 1; gc /= 2)
             if (fits(gc)) pr->Gc = gc;
+        pr->Gc_max = 0;
+        for (int gc = 4; !pr->Gc_max && gc >= 1; gc /= 2)
+            if (fits(gc)) pr->Gc_max = gc;
         const size_t need_boost = pr->prec == RRT_FP64 ? rrt::boost_lds<double>(pr->K, pr->G)
                                                        : rrt::boost_lds<float>(pr->K, pr->G);
         if (!pr->Gc || plane > rrt::kTraceMaxPlane)
@@ -1223,11 +1227,20 @@ rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *si
     if (pr->prec == RRT_FP64) chilab(0.0); else chilab(0.0f);
     // group-major copy of a per-group extinction where the trace may use it: planes that
     // leave LDS for one group per workgroup only, or a copy kept from an earlier medium
-    if (!pr->grey_chi && pr->G > 1 && (pr->Gc == 1 || pr->d_chilabT || pr->gmajor))
+    // default groups per trace workgroup for this medium: with a per-group extinction, four
+    // spill registers (1024-thread workgroups hold 128 per lane) and are slower than two on
+    // planes of 32 x 32 points and more, and than one on smaller planes (more workgroups);
+    // the autotuner may revise it
+    if (!pr->variants_fixed && !pr->gc_forced && !pr->tuned) {
+        int gc = pr->Gc_max;
+        if (!pr->grey_chi && pr->G > 1) gc = std::min(gc, (long)pr->nx * pr->ny >= 1024 ? 2 : 1);
+        pr->Gc = gc;
+    }
+    if (!pr->grey_chi && pr->G > 1 && (pr->Gc_max == 1 || pr->d_chilabT || pr->gmajor))
         if ((s = ensure_chilab_gmajor(pr))) return s;
     // default: group-major planes where one group per workgroup is all the LDS holds and a
     // point's groups span whole 32-byte sectors (G >= 8); the autotuner may revise it
-    if (!pr->variants_fixed && !pr->gc_forced) pr->gmajor = pr->Gc == 1 && pr->G >= 8;
+    if (!pr->variants_fixed && !pr->gc_forced) pr->gmajor = pr->Gc_max == 1 && pr->G >= 8;
     // remap plan of the velocity field
     if (beta) {
         const size_t esz = pr->prec == RRT_FP64 ? sizeof(rrt::RemapEntry<double>) : sizeof(rrt::RemapEntry<float>);
