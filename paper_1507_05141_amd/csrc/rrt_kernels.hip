@@ -90,6 +90,7 @@ struct StepDepth {
     real au, bu, nu;            // slope at u: left = uu -> u, right = the step
     bool okp, oku;
     real ex, E0, E1, E2, E3;    // e^{-hu} and the Bezier moments
+    real w0, w1, w2, w3;        // the Bernstein weights of S_u, C_u, C_p, S_p they give
 };
 
 template <typename real>
@@ -116,6 +117,10 @@ __device__ __forceinline__ StepDepth<real> step_depth(real hds, real Xuu, real X
         g.oku = huu > real(0) && hu > real(0);
     }
     bezier_moments(hu, g.ex, g.E0, g.E1, g.E2, g.E3);
+    g.w0 = g.E3;
+    g.w1 = real(3) * (g.E2 - g.E3);
+    g.w2 = real(3) * ((g.E1 - g.E2) - (g.E2 - g.E3));
+    g.w3 = (g.E0 - g.E3) - real(3) * (g.E1 - g.E2);
     return g;
 }
 
@@ -549,7 +554,11 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
                 const real lo = fmin(su, sp), hi = fmax(su, sp);
                 const real Cu = fmin(fmax(su + tu * real(1.0 / 3.0), lo), hi);
                 const real Cp = fmin(fmax(sp - tp * real(1.0 / 3.0), lo), hi);
-                res[c].v[n] = Iu.v[n] * gd.ex + bezier_integral(gd.E0, gd.E1, gd.E2, gd.E3, su, Cu, Cp, sp);
+                // a grey extinction shares the step's weights among the groups: the integral is
+                // then four products per group; otherwise the moment form (fewer operations
+                // for one group)
+                res[c].v[n] = xg ? Iu.v[n] * gd.ex + gd.w0 * su + gd.w1 * Cu + gd.w2 * Cp + gd.w3 * sp
+                                 : Iu.v[n] * gd.ex + bezier_integral(gd.E0, gd.E1, gd.E2, gd.E3, su, Cu, Cp, sp);
             }
             if (tid + c * T < PL) *reinterpret_cast<P *>(Ik + (long)(m * PL + tid + c * T) * ps) = res[c];
         }
