@@ -427,6 +427,13 @@ __device__ __forceinline__ Pack<real, N> bil(const Pack<real, N> *pl, int cell, 
     return r;
 }
 
+// x clamped to the interval between a and b (one median-of-three in FP32)
+__device__ __forceinline__ float clamp_between(float x, float a, float b) { return __builtin_amdgcn_fmed3f(x, a, b); }
+__device__ __forceinline__ double clamp_between(double x, double a, double b)
+{
+    return fmin(fmax(x, fmin(a, b)), fmax(a, b));
+}
+
 template <typename real, int XMODE, int GC, int MAXPT>
 __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
 {
@@ -551,9 +558,8 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
                 // step depth times the slopes at p and at u (secant where the outer neighbour is missing)
                 const real tp = has_d ? fb_slope(gd.np, gd.ap, gd.bp, gd.okp, dl, Sd.v[n] - sp) : dl;
                 const real tu = has_uu ? fb_slope(gd.nu, gd.au, gd.bu, gd.oku, su - Suu.v[n], dl) : dl;
-                const real lo = fmin(su, sp), hi = fmax(su, sp);
-                const real Cu = fmin(fmax(su + tu * real(1.0 / 3.0), lo), hi);
-                const real Cp = fmin(fmax(sp - tp * real(1.0 / 3.0), lo), hi);
+                const real Cu = clamp_between(su + tu * real(1.0 / 3.0), su, sp);
+                const real Cp = clamp_between(sp - tp * real(1.0 / 3.0), su, sp);
                 // a grey extinction shares the step's weights among the groups: the integral is
                 // then four products per group; otherwise the moment form (fewer operations
                 // for one group)
