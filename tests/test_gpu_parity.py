@@ -78,6 +78,10 @@ CASES = {
     "thomson_16g_odd_points": dict(nx=5, ny=3, nz=5, G=16, seed=10, gamma_max=6.0),
     # L = 15 Thomson (the fused source and residual on 256-term rows)
     "thomson_L15": dict(nx=4, ny=3, nz=3, G=2, lmax=15, nmu=16, nphi=32, seed=11),
+    # two-dimensional (ny = 1, as the paper's own tests) with a per-group extinction, and a
+    # single column (nx = ny = 1)
+    "two_d_groups": dict(nx=12, ny=1, nz=9, G=4, seed=12, gamma_max=6.0),
+    "one_column": dict(nx=1, ny=1, nz=16, G=2, seed=13, nmu=8, nphi=16),
     # L = 15 (256 SH terms, 16 x 32 ordinates): the widest SH products and Compton source
     "compton_L15": dict(nx=4, ny=4, nz=3, G=4, lmax=15, nmu=16, nphi=32, scatter="compton", seed=9,
                         edges=np.exp(np.linspace(np.log(1.0), np.log(150.0), 5)), mec2=W.MEC2_KEV),
