@@ -1250,6 +1250,88 @@ __global__ void __launch_bounds__(64 * W) k_do2sh_f32(long R, int K, int NL, con
         }
 }
 
+// The same product with the whole weight table resident in LDS (staged once
+// per workgroup, K rounded up to 64 rows of NLP floats): persistent workgroups
+// of sixteen waves walk blocks of 16 x 16 RT rows with no barrier inside, each
+// wave loading the next 64-ordinate chunk of its rows while the matrix cores
+// take the current one.
+template <int NT, int RT>
+__global__ void __launch_bounds__(1024) k_do2sh_f32r(long R, int K, int NL, const float *__restrict__ A,
+                                                     const float *__restrict__ B, float *__restrict__ C)
+{
+    constexpr int W = 16, KC = 64, NC = NT * 16, NLP = NC + 4;
+    extern __shared__ unsigned char smem_raw[];
+    float *Bs = reinterpret_cast<float *>(smem_raw);                   // [Kr][NLP]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
+    const int Kr = (K + KC - 1) / KC * KC;
+    for (int i = threadIdx.x; i < Kr * NC; i += blockDim.x) {
+        const int kk = i / NC, c = i - kk * NC;
+        Bs[kk * NLP + c] = (kk < K && c < NL) ? B[(long)kk * NL + c] : 0.f;
+    }
+    __syncthreads();
+    const bool vec = (K & 3) == 0;
+    const long nblk = (R + 16 * W * RT - 1) / (16 * W * RT);
+    for (long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
+        const long r0 = blk * (16 * W * RT) + wave * (16 * RT);
+        const float *Arow[RT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t) Arow[t] = A + min(r0 + 16 * t + lr, R - 1) * (long)K;
+        f32x4 acc[RT][NT];
+#pragma unroll
+        for (int t = 0; t < RT; ++t)
+#pragma unroll
+            for (int c = 0; c < NT; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+        f32x4 a[RT][4], an[RT][4];
+        auto load = [&](f32x4 (&dst)[RT][4], int kc) {
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int k = kc + 16 * t + 4 * lg;
+                    if (vec && k + 3 < K) {
+                        dst[rt][t] = *reinterpret_cast<const f32x4 *>(Arow[rt] + k);
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) dst[rt][t][i] = (k + i < K) ? Arow[rt][k + i] : 0.f;
+                    }
+                }
+        };
+        load(a, 0);
+        for (int kc = 0; kc < K; kc += KC) {
+            if (kc + KC < K) load(an, kc + KC);
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const float *brow = Bs + (kc + 16 * t + 4 * lg + s) * NLP + lr;
+#pragma unroll
+                    for (int c = 0; c < NT; ++c) {
+                        const float bv = brow[16 * c];
+#pragma unroll
+                        for (int rt = 0; rt < RT; ++rt)
+                            acc[rt][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][t][s], bv, acc[rt][c], 0, 0, 0);
+                    }
+                }
+            }
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) a[rt][t] = an[rt][t];
+        }
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                const int col = 16 * c + lr;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const long r = r0 + 16 * rt + 4 * lg + i;
+                    if (r < R && col < NL) C[r * NL + col] = acc[rt][c][i];
+                }
+            }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Mixed precision: the two SH <-> ordinate products on FP16 matrix cores
 // (v_mfma_f32_16x16x32_f16) with FP32 accumulation.  Both operands are split
@@ -2196,15 +2278,32 @@ bool launch_do2sh_f32(long R, int K, int NL, const float *A, const float *B, flo
                            K, NL, A, B, C);                                                                  \
         return true;                                                                                          \
     }
+    // rt 1 and 2 with the whole table resident in LDS where it fits: one persistent
+    // workgroup per CU
+#define RRT_DO2SH32R(NT, RT)                                                                                  \
+    {                                                                                                         \
+        const size_t smr = sizeof(float) * (size_t)((K + 63) / 64 * 64) * (NT * 16 + 4);                     \
+        if (smr <= 160 * 1024) {                                                                              \
+            const long nb = (R + 256 * RT - 1) / (256 * RT);                                                  \
+            hipLaunchKernelGGL((k_do2sh_f32r<NT, RT>), dim3((unsigned)std::min<long>(nb, 256)), dim3(1024), smr, st, R, \
+                               K, NL, A, B, C);                                                              \
+            return true;                                                                                      \
+        }                                                                                                     \
+    }
     if (NL <= 16) {
+        if (rt == 1) RRT_DO2SH32R(1, 1)
+        if (rt == 2) RRT_DO2SH32R(1, 2)
         if (rt == 1) RRT_DO2SH32(1, 1, 16)
         if (rt == 2) RRT_DO2SH32(1, 2, 16)
         if (rt == 0 || rt == 4) RRT_DO2SH32(1, 4, 16)
     } else if (NL <= 64) {
+        if (rt == 1) RRT_DO2SH32R(4, 1)
+        if (rt == 2) RRT_DO2SH32R(4, 2)
         if (rt == 1) RRT_DO2SH32(4, 1, 16)
         if (rt == 0 || rt == 2) RRT_DO2SH32(4, 2, 16)
         if (rt == 4) RRT_DO2SH32(4, 4, 4)
     }
+#undef RRT_DO2SH32R
 #undef RRT_DO2SH32
     return false;
 }
@@ -2443,6 +2542,10 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_do2sh_f32<4, 1, 16>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<4, 2, 16>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<4, 4, 4>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32r<1, 1>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32r<1, 2>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32r<4, 1>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32r<4, 2>),
                          reinterpret_cast<const void *>(&k_source_compton<double>)};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
