@@ -2290,15 +2290,17 @@ bool launch_do2sh_f32(long R, int K, int NL, const float *A, const float *B, flo
             return true;                                                                                      \
         }                                                                                                     \
     }
+    // (the defaults: resident, one row tile per wave for NL <= 16 and two up to 64, the
+    // fastest measured on MI355X at L = 3 and 7)
     if (NL <= 16) {
-        if (rt == 1) RRT_DO2SH32R(1, 1)
+        if (rt == 0 || rt == 1) RRT_DO2SH32R(1, 1)
         if (rt == 2) RRT_DO2SH32R(1, 2)
         if (rt == 1) RRT_DO2SH32(1, 1, 16)
         if (rt == 2) RRT_DO2SH32(1, 2, 16)
         if (rt == 0 || rt == 4) RRT_DO2SH32(1, 4, 16)
     } else if (NL <= 64) {
         if (rt == 1) RRT_DO2SH32R(4, 1)
-        if (rt == 2) RRT_DO2SH32R(4, 2)
+        if (rt == 0 || rt == 2) RRT_DO2SH32R(4, 2)
         if (rt == 1) RRT_DO2SH32(4, 1, 16)
         if (rt == 0 || rt == 2) RRT_DO2SH32(4, 2, 16)
         if (rt == 4) RRT_DO2SH32(4, 4, 4)
