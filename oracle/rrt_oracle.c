@@ -598,10 +598,46 @@ static double snap_cells(double o)
     return fabs(o - r) < 1e-9 ? r : o;
 }
 
-/* For every lab ordinate and group, march the z planes from the inflow face:
-   I_p = I_u e^{-h} + Bezier integral of S~ over the segment from the upwind
-   point u on the previous plane (back-traced a distance dz/|mu| along -n and
-   bilinearly interpolated, periodic in x and y) to the grid point p. */
+/* Number of equal pieces into which the path between two neighbouring z
+   planes is cut for ordinates of polar cosine mu: enough that no piece moves
+   the ray more than one cell horizontally, in any azimuth (a direction with a
+   single column is left out: every horizontal offset reaches the same point
+   there).  It depends on mu only, so every azimuth of a ring is treated alike. */
+static int trace_pieces(const or_problem *pr, double mu)
+{
+    double h = 0.0;
+    if (pr->nx > 1) h = pr->lx / pr->nx;
+    if (pr->ny > 1 && (h == 0.0 || pr->ly / pr->ny < h)) h = pr->ly / pr->ny;
+    if (h == 0.0) return 1;
+    double dz = pr->lz / (pr->nz - 1);
+    double c = dz * sqrt(fmax(0.0, 1.0 - mu * mu)) / (fabs(mu) * h);
+    int m = (int)ceil(c - 1e-9);
+    return m < 1 ? 1 : m;
+}
+
+/* Value at the point a fraction f of the way from grid plane A (at the
+   horizontal offset (ox, oy) cells from point (i, j)) to grid plane B (same
+   offset): bilinear in x and y, linear in z. */
+static double path_value(const double *A, const double *B, int nx, int ny, int i, int j, double ox, double oy,
+                         double f)
+{
+    double a = plane_interp(A, nx, ny, i, j, ox, oy);
+    if (f == 0.0) return a;
+    return (1.0 - f) * a + f * plane_interp(B, nx, ny, i, j, ox, oy);
+}
+
+/* For every lab ordinate and group, march the z planes from the inflow face.
+   For grid point p on plane m the ray is traced back a distance dz/|mu| to
+   the upwind point u on the previous plane, where the intensity I_u is
+   bilinear (periodic in x and y).  The path from u to p is cut into np equal
+   pieces (trace_pieces) at points q_0 = p, ..., q_np = u, where S~ and chi~
+   are bilinear in x and y and linear in z between the grid planes, and the
+   intensity is carried along the path piece by piece:
+   I(q_j) = I(q_{j+1}) e^{-h} + Bezier integral of S~ over the piece, the
+   control points taking their slopes from the neighbouring points q_{j+2}
+   and q_{j-1} (which extend one piece beyond u and beyond p when those
+   planes exist).  With np = 1 this is the plane-to-plane short
+   characteristic. */
 void or_trace(const or_problem *pr, const double *St, const double *Xt, double *I)
 {
     int nx = pr->nx, ny = pr->ny, nz = pr->nz, G = pr->ng, K = nord(pr);
@@ -613,12 +649,15 @@ void or_trace(const or_problem *pr, const double *St, const double *Xt, double *
             double n[3];
             ordinate_dir(pr, k, n);
             double mu = n[2];
-            double ds = dz / fabs(mu);
+            int np = trace_pieces(pr, mu);
+            double ds = dz / fabs(mu) / np;                  /* length of one piece */
             double ox = snap_cells(-ds * n[0] / dx), oy = snap_cells(-ds * n[1] / dy);
             long o = ((long)k * G + g) * P;
             const double *S = St + o, *X = Xt + o;
             double *Ik = I + o;
             const double *bc = (mu > 0.0) ? pr->bc_bot : pr->bc_top;
+            double *qs = (double *)malloc(sizeof(double) * (np + 3));
+            double *qx = (double *)malloc(sizeof(double) * (np + 3));
             for (int t = 0; t < nz; t++) {
                 int m = (mu > 0.0) ? t : nz - 1 - t;
                 int mu_ = (mu > 0.0) ? t - 1 : nz - t;       /* upwind plane          */
@@ -629,42 +668,69 @@ void or_trace(const or_problem *pr, const double *St, const double *Xt, double *
                         Ik[m * PL + e] = bc ? bc[((long)k * G + g) * PL + e] : 0.0;
                     continue;
                 }
+                int has_d = t <= nz - 2, has_uu = t >= 2;
                 for (int j = 0; j < ny; j++) {
                     for (int i = 0; i < nx; i++) {
                         long e = (long)j * nx + i;
-                        double Sp = S[m * PL + e], Xp = X[m * PL + e];
-                        double Su = plane_interp(S + mu_ * PL, nx, ny, i, j, ox, oy);
-                        double Xu = plane_interp(X + mu_ * PL, nx, ny, i, j, ox, oy);
-                        double Iu = plane_interp(Ik + mu_ * PL, nx, ny, i, j, ox, oy);
-                        double hu = ds * 0.5 * (Xu + Xp);
-                        double dSp = 0.0, dSu = 0.0;
-                        if (hu > 0.0) {
-                            double d1 = (Sp - Su) / hu;
-                            if (t <= nz - 2) {
-                                double Sd = plane_interp(S + md * PL, nx, ny, i, j, -ox, -oy);
-                                double Xd = plane_interp(X + md * PL, nx, ny, i, j, -ox, -oy);
-                                double hd = ds * 0.5 * (Xp + Xd);
-                                dSp = (hd > 0.0) ? fb_slope(d1, (Sd - Sp) / hd, hu, hd) : 0.0;
+                        /* path points q_c, c = -1 .. np + 1, stored at index c + 1 */
+                        for (int c = -1; c <= np + 1; c++) {
+                            double *vs = qs + c + 1, *vx = qx + c + 1;
+                            if (c == -1) {
+                                if (!has_d) { *vs = *vx = 0.0; continue; }
+                                double f = 1.0 / np;
+                                *vs = path_value(S + m * PL, S + md * PL, nx, ny, i, j, -ox, -oy, f);
+                                *vx = path_value(X + m * PL, X + md * PL, nx, ny, i, j, -ox, -oy, f);
+                            } else if (c <= np) {
+                                double f = (double)c / np;
+                                if (c == np) {          /* on the upwind plane */
+                                    *vs = plane_interp(S + mu_ * PL, nx, ny, i, j, c * ox, c * oy);
+                                    *vx = plane_interp(X + mu_ * PL, nx, ny, i, j, c * ox, c * oy);
+                                } else {
+                                    *vs = path_value(S + m * PL, S + mu_ * PL, nx, ny, i, j, c * ox, c * oy, f);
+                                    *vx = path_value(X + m * PL, X + mu_ * PL, nx, ny, i, j, c * ox, c * oy, f);
+                                }
                             } else {
-                                dSp = d1;
-                            }
-                            if (t >= 2) {
-                                double Suu = plane_interp(S + muu * PL, nx, ny, i, j, 2.0 * ox, 2.0 * oy);
-                                double Xuu = plane_interp(X + muu * PL, nx, ny, i, j, 2.0 * ox, 2.0 * oy);
-                                double huu = ds * 0.5 * (Xuu + Xu);
-                                dSu = (huu > 0.0) ? fb_slope((Su - Suu) / huu, d1, huu, hu) : 0.0;
-                            } else {
-                                dSu = d1;
+                                if (!has_uu) { *vs = *vx = 0.0; continue; }
+                                double f = 1.0 / np;
+                                *vs = path_value(S + mu_ * PL, S + muu * PL, nx, ny, i, j, c * ox, c * oy, f);
+                                *vx = path_value(X + mu_ * PL, X + muu * PL, nx, ny, i, j, c * ox, c * oy, f);
                             }
                         }
-                        double Cu = clampd(Su + hu * dSu / 3.0, Su, Sp);
-                        double Cp = clampd(Sp - hu * dSp / 3.0, Su, Sp);
-                        double ex, w[4];
-                        bezier_weights(hu, &ex, w);
-                        Ik[m * PL + e] = Iu * ex + w[0] * Su + w[1] * Cu + w[2] * Cp + w[3] * Sp;
+                        double Iv = plane_interp(Ik + mu_ * PL, nx, ny, i, j, np * ox, np * oy);
+                        for (int c = np - 1; c >= 0; c--) {
+                            /* piece from q_{c+1} (u) to q_c (p); neighbours q_{c+2}, q_{c-1} */
+                            double Su = qs[c + 2], Xu = qx[c + 2], Sp = qs[c + 1], Xp = qx[c + 1];
+                            int d_ok = c >= 1 || has_d, uu_ok = c + 2 <= np || has_uu;
+                            double hu = ds * 0.5 * (Xu + Xp);
+                            double dSp = 0.0, dSu = 0.0;
+                            if (hu > 0.0) {
+                                double d1 = (Sp - Su) / hu;
+                                if (d_ok) {
+                                    double Sd = qs[c], Xd = qx[c];
+                                    double hd = ds * 0.5 * (Xp + Xd);
+                                    dSp = (hd > 0.0) ? fb_slope(d1, (Sd - Sp) / hd, hu, hd) : 0.0;
+                                } else {
+                                    dSp = d1;
+                                }
+                                if (uu_ok) {
+                                    double Suu = qs[c + 3], Xuu = qx[c + 3];
+                                    double huu = ds * 0.5 * (Xuu + Xu);
+                                    dSu = (huu > 0.0) ? fb_slope((Su - Suu) / huu, d1, huu, hu) : 0.0;
+                                } else {
+                                    dSu = d1;
+                                }
+                            }
+                            double Cu = clampd(Su + hu * dSu / 3.0, Su, Sp);
+                            double Cp = clampd(Sp - hu * dSp / 3.0, Su, Sp);
+                            double ex, w[4];
+                            bezier_weights(hu, &ex, w);
+                            Iv = Iv * ex + w[0] * Su + w[1] * Cu + w[2] * Cp + w[3] * Sp;
+                        }
+                        Ik[m * PL + e] = Iv;
                     }
                 }
             }
+            free(qs); free(qx);
         }
     }
 }
