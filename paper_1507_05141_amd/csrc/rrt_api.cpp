@@ -14,6 +14,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <utility>
 #include <vector>
 
@@ -74,6 +75,8 @@ struct rrt_problem {
     int Gc = 1;
     int Gc_max = 1;                                 // the most groups per trace workgroup the LDS holds
     rrt::OrdGeom *d_geo = nullptr;
+    void *d_taps = nullptr;                         // rrt::PathTap<real> of every ordinate's path points
+    int *d_order = nullptr;                         // ordinates by decreasing number of path pieces
     void *d_Yt = nullptr, *d_WY = nullptr, *d_A = nullptr, *d_sg = nullptr;
     void *d_Y16 = nullptr, *d_WYt16 = nullptr;     // RRT_MIXED: FP16 SH tables, hi then lo part (zero padded)
     size_t y16_n = 0, wyt16_n = 0;                  // elements per part
@@ -341,7 +344,8 @@ struct Engine {
     {
         rrt::TraceArgs<real> t;
         t.nx = pr->nx; t.ny = pr->ny; t.nz = pr->nz; t.G = pr->G; t.K = pr->K; t.Gc = gmajor ? 1 : pr->Gc; t.P = pr->P;
-        t.geo = pr->d_geo; t.dir = pr->d_dir; t.St = static_cast<const real *>(St); t.Xt = R(pr->d_Xt);
+        t.geo = pr->d_geo; t.taps = static_cast<const rrt::PathTap<real> *>(pr->d_taps); t.order = pr->d_order;
+        t.dir = pr->d_dir; t.St = static_cast<const real *>(St); t.Xt = R(pr->d_Xt);
         t.chilab = R(gmajor && !pr->grey_chi ? pr->d_chilabT : pr->d_chilab); t.chi_grey = pr->grey_chi;
         t.inv_cdt = (real)inv_cdt; t.bc_bot = R(pr->d_bc[0]); t.bc_top = R(pr->d_bc[1]); t.I = R(I);
         t.gmajor = gmajor;
@@ -905,7 +909,7 @@ void rrt_destroy(rrt_problem *pr)
     clear_graphs(pr);
     if (pr->h_red) (void)hipHostFree(pr->h_red);
     if (pr->blas) (void)rocblas_destroy_handle(pr->blas);
-    void *bufs[] = {pr->d_dir, pr->d_mu, pr->d_lnc, pr->d_nu3, pr->d_inv_nu3, pr->d_inv_dc, pr->d_geo, pr->d_Yt, pr->d_WY,
+    void *bufs[] = {pr->d_dir, pr->d_mu, pr->d_lnc, pr->d_nu3, pr->d_inv_nu3, pr->d_inv_dc, pr->d_geo, pr->d_taps, pr->d_order, pr->d_Yt, pr->d_WY,
                     pr->d_Y16, pr->d_WYt16,
                     pr->d_A, pr->d_sg, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_gam, pr->d_chi0, pr->d_chilab, pr->d_plan, pr->d_chilabT, pr->d_bc[0], pr->d_bc[1],
                     pr->d_S, pr->d_Snew, pr->d_Ilm, pr->d_co, pr->d_St, pr->d_Xt, pr->d_Ilab, pr->d_I, pr->d_Iin,
@@ -1042,37 +1046,78 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
         if (e == hipSuccess) e = hipMemcpy(pr->d_WYt16, wyt16.data(), wyt16.size() * sizeof(_Float16), hipMemcpyHostToDevice);
         if (e != hipSuccess) return bail(fail(RRT_E_HBM, std::string("mixed-precision tables: ") + hipGetErrorString(e)));
     }
-    // ray-trace geometry per ordinate
+    // ray-trace geometry per ordinate: the path from the previous z plane is cut
+    // into the fewest equal pieces that move the ray at most one cell sideways
+    // (a single column or row in x or y is left out: every offset reaches the
+    // same point there); the count depends on mu only
     {
         const double dx = pr->lx / pr->nx, dy = pr->ly / pr->ny, dz = pr->lz / (pr->nz - 1);
+        double hmin = 0.0;
+        if (pr->nx > 1) hmin = dx;
+        if (pr->ny > 1 && (hmin == 0.0 || dy < hmin)) hmin = dy;
         std::vector<rrt::OrdGeom> geo(K);
+        std::vector<double> tix, tiy, tw;          // per tap: integer shift and four weights
         for (int k = 0; k < K; ++k) {
             const double *n = &pr->dir[4 * k];
             rrt::OrdGeom &gm = geo[k];
-            gm.ds = dz / std::fabs(n[2]);
+            const double amu = std::fabs(n[2]);
+            int npc = 1;
+            if (hmin > 0.0) {
+                const double cells = dz * std::sqrt(std::max(0.0, 1.0 - n[2] * n[2])) / (amu * hmin);
+                npc = std::max(1, (int)std::ceil(cells - 1e-9));
+            }
+            gm.npc = npc;
+            gm.ds = dz / amu / npc;
             gm.up = n[2] > 0 ? 1 : 0;
+            gm.tap0 = (int)tix.size();
             // a displacement within rounding of whole cells (a ray in a grid plane,
             // n_x = cos(pi/2) ~ 6e-17) is taken as whole: no tap weight of ~1e-15
             // gives a vacuum neighbour a positive depth, which the slope limiter
             // would treat differently from zero
             auto snap = [](double o) { const double r = std::nearbyint(o); return std::fabs(o - r) < 1e-9 ? r : o; };
             const double ox = snap(-gm.ds * n[0] / dx), oy = snap(-gm.ds * n[1] / dy);
-            const double sh[3] = {2.0, 1.0, -1.0};
-            for (int c = 0; c < 3; ++c) {
-                const double sx = sh[c] * ox, sy = sh[c] * oy;
+            for (int c = -1; c <= npc + 1; ++c) {
+                const double sx = c * ox, sy = c * oy;
                 const double fx0 = std::floor(sx), fy0 = std::floor(sy);
-                gm.fx[c] = sx - fx0;
-                gm.fy[c] = sy - fy0;
+                const double fx = sx - fx0, fy = sy - fy0;
                 long ix = (long)fx0 % pr->nx, iy = (long)fy0 % pr->ny;
                 if (ix < 0) ix += pr->nx;
                 if (iy < 0) iy += pr->ny;
-                gm.ix[c] = (int)ix;
-                gm.iy[c] = (int)iy;
+                tix.push_back((double)ix);
+                tiy.push_back((double)iy);
+                tw.push_back((1.0 - fx) * (1.0 - fy));
+                tw.push_back(fx * (1.0 - fy));
+                tw.push_back((1.0 - fx) * fy);
+                tw.push_back(fx * fy);
             }
         }
+        std::vector<int> order(K);
+        for (int k = 0; k < K; ++k) order[k] = k;
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return geo[x].npc > geo[y].npc; });
         s = pr_alloc(pr, (void **)&pr->d_geo, sizeof(rrt::OrdGeom) * K);
         if (s) return bail(s);
+        s = pr_alloc(pr, (void **)&pr->d_order, sizeof(int) * K);
+        if (s) return bail(s);
+        const size_t nt = tix.size();
+        auto fill_taps = [&](auto *tag, size_t esz) -> rrt_status {
+            using real = std::remove_pointer_t<decltype(tag)>;
+            std::vector<rrt::PathTap<real>> taps(nt);
+            for (size_t i = 0; i < nt; ++i) {
+                taps[i].ix = (int)tix[i];
+                taps[i].iy = (int)tiy[i];
+                for (int w = 0; w < 4; ++w) taps[i].w[w] = (real)tw[4 * i + w];
+            }
+            rrt_status st = pr_alloc(pr, &pr->d_taps, esz * nt);
+            if (st) return st;
+            if (hipMemcpy(pr->d_taps, taps.data(), esz * nt, hipMemcpyHostToDevice) != hipSuccess)
+                return fail(RRT_E_DEVICE, "geometry upload");
+            return RRT_OK;
+        };
+        s = pr->prec == RRT_FP64 ? fill_taps((double *)nullptr, sizeof(rrt::PathTap<double>))
+                                 : fill_taps((float *)nullptr, sizeof(rrt::PathTap<float>));
+        if (s) return bail(s);
         hipError_t e = hipMemcpy(pr->d_geo, geo.data(), sizeof(rrt::OrdGeom) * K, hipMemcpyHostToDevice);
+        if (e == hipSuccess) e = hipMemcpy(pr->d_order, order.data(), sizeof(int) * K, hipMemcpyHostToDevice);
         if (e != hipSuccess) return bail(fail(RRT_E_DEVICE, "geometry upload"));
     }
     // groups

@@ -8,15 +8,25 @@ constexpr int kTraceThreads = 1024;    // threads per ray-trace workgroup
 constexpr int kTraceMaxPlane = 4096;   // grid points of an x-y plane (at most): four per ray-trace thread
 constexpr int kRemapThreads = 512;  // threads per frame-transform workgroup (one lab ordinate each)
 
-// Per-ordinate geometry of the plane-to-plane short characteristic: path
-// length ds = dz/|mu| between planes, march direction, and the horizontal
-// back-trace offsets in cells for the second-upwind (2 * off), upwind (off)
-// and downwind (-off) planes: integer part (reduced modulo nx, ny) + fraction.
+// Per-ordinate geometry of the short characteristic.  The path from the
+// previous z plane to a grid point is cut into npc equal pieces of length ds
+// (dz/(|mu| npc)), npc being the fewest that move the ray at most one cell
+// sideways.  Path point c (0 = the grid point, npc = the upwind point on the
+// previous plane, -1 and npc + 1 one piece beyond either end) lies c ds back
+// along -n, at the horizontal offset of tap table entry tap0 + c + 1.
 struct OrdGeom {
     double ds;
     int up;
-    int ix[3], iy[3];
-    double fx[3], fy[3];
+    int npc;
+    int tap0;
+};
+
+// Bilinear tap of a horizontal offset in cells: integer part reduced modulo
+// nx, ny, and the weights of the (x, y), (x + 1, y), (x, y + 1), (x + 1, y + 1)
+// neighbours.
+template <typename real> struct PathTap {
+    int ix, iy;
+    real w[4];
 };
 
 // Group centres for the ln(nu) interpolation of the frame transforms.
@@ -40,6 +50,8 @@ template <typename real> struct TraceArgs {
     int nx, ny, nz, G, K, Gc;   // Gc groups per workgroup (divides G)
     long P;
     const OrdGeom *geo;
+    const PathTap<real> *taps;  // path taps of every ordinate (OrdGeom::tap0)
+    const int *order;           // ordinates by decreasing number of pieces (the costliest start first)
     const double *dir;          // [K][4]
     const real *St;             // S~ [k][p][g]
     const real *Xt;             // chi~ [k][p][g] (stand-alone trace only)

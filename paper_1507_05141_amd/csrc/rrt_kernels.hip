@@ -434,6 +434,64 @@ __device__ __forceinline__ double clamp_between(double x, double a, double b)
     return fmin(fmax(x, fmin(a, b)), fmax(a, b));
 }
 
+// LDS cell of the tap of point (i, j) at table offset t (periodic wrap; the
+// plane's halo serves the + 1 neighbours)
+template <typename real>
+__device__ __forceinline__ int tap_cell(const PathTap<real> &t, int i, int j, const TraceIdx &q)
+{
+    int i0 = i + t.ix; if (i0 >= q.nx) i0 -= q.nx;
+    int j0 = j + t.iy; if (j0 >= q.ny) j0 -= q.ny;
+    return j0 * q.RS + i0;
+}
+
+// value a fraction f of the way from a bilinear sample of plane A to one of
+// plane B at the same tap (linear in z along the path)
+template <typename real, int N>
+__device__ __forceinline__ Pack<real, N> bil_lerp(const Pack<real, N> *A, const Pack<real, N> *B, int cell, int RS,
+                                                  const real w[4], real f)
+{
+    const Pack<real, N> x = bil(A, cell, RS, w), y = bil(B, cell, RS, w);
+    Pack<real, N> r;
+#pragma unroll
+    for (int n = 0; n < N; ++n) r.v[n] = (real(1) - f) * x.v[n] + f * y.v[n];
+    return r;
+}
+
+// One cubic Bezier step u -> p over every group of the pack: the intensity
+// arriving from u is attenuated by e^{-h} and the integral of the source
+// added; slopes from the neighbours uu and d where they exist (has_uu,
+// has_d), else the secant.
+template <typename real, int XMODE, int GC>
+__device__ __forceinline__ void bezier_step(Pack<real, GC> &I, real hds, const Pack<real, GC> &Suu,
+                                            const Pack<real, GC> &Su, const Pack<real, GC> &Sp,
+                                            const Pack<real, GC> &Sd,
+                                            const Pack<real, XMODE == kChiGrey ? 1 : GC> &Xuu,
+                                            const Pack<real, XMODE == kChiGrey ? 1 : GC> &Xu,
+                                            const Pack<real, XMODE == kChiGrey ? 1 : GC> &Xp,
+                                            const Pack<real, XMODE == kChiGrey ? 1 : GC> &Xd, bool has_d, bool has_uu)
+{
+    constexpr bool xg = XMODE == kChiGrey;
+    constexpr int XG = xg ? 1 : GC;
+    StepDepth<real> gd;
+    if (xg) gd = step_depth(hds, Xuu.v[0], Xu.v[0], Xp.v[0], Xd.v[0], has_d, has_uu);
+#pragma unroll
+    for (int n = 0; n < GC; ++n) {
+        if (!xg) gd = step_depth(hds, Xuu.v[n % XG], Xu.v[n % XG], Xp.v[n % XG], Xd.v[n % XG], has_d, has_uu);
+        const real sp = Sp.v[n], su = Su.v[n];
+        const real dl = sp - su;
+        // step depth times the slopes at p and at u (secant where the outer neighbour is missing)
+        const real tp = has_d ? fb_slope(gd.np, gd.ap, gd.bp, gd.okp, dl, Sd.v[n] - sp) : dl;
+        const real tu = has_uu ? fb_slope(gd.nu, gd.au, gd.bu, gd.oku, su - Suu.v[n], dl) : dl;
+        const real Cu = clamp_between(su + tu * real(1.0 / 3.0), su, sp);
+        const real Cp = clamp_between(sp - tp * real(1.0 / 3.0), su, sp);
+        // a grey extinction shares the step's weights among the groups: the integral is
+        // then four products per group; otherwise the moment form (fewer operations
+        // for one group)
+        I.v[n] = xg ? I.v[n] * gd.ex + gd.w0 * su + gd.w1 * Cu + gd.w2 * Cp + gd.w3 * sp
+                    : I.v[n] * gd.ex + bezier_integral(gd.E0, gd.E1, gd.E2, gd.E3, su, Cu, Cp, sp);
+    }
+}
+
 template <typename real, int XMODE, int GC, int MAXPT>
 __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
 {
@@ -445,15 +503,23 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
     extern __shared__ unsigned char smem_raw[];
     const int nx = a.nx, ny = a.ny, nz = a.nz, PL = nx * ny, G = a.G;
     const int nch = G / GC;
-    const long wi = xcd_item((long)a.K * nch);
-    if (wi >= (long)a.K * nch) return;
-    const int k = (int)(wi / nch), g0 = (int)(wi - (long)k * nch) * GC;
+    // Block b runs on XCD b % 8.  Each XCD takes every eighth ordinate of the
+    // list ordered by decreasing cost, and all group chunks of an ordinate in a
+    // row (they share the cache lines of its points), so the XCDs get equal work
+    // and the longest marches start first.
+    const int xcd = blockIdx.x % 8;
+    const long slot = blockIdx.x / 8;
+    const int rank = 8 * (int)(slot / nch) + xcd;
+    if (rank >= a.K) return;
+    const int k = a.order[rank], g0 = (int)(slot % nch) * GC;
     const TraceIdx q{nx, ny, PL, nx + 1, (nx + 1) * (ny + 1), 1.0f / (float)nx};
     const int XE = q.PS * XG;
     real *Sr = reinterpret_cast<real *>(smem_raw);
     real *Xr = Sr + kRing * q.PS * GC;
     P *Ir = reinterpret_cast<P *>(Xr + kRing * XE);   // kIBuf planes of PS points
     const OrdGeom gm = a.geo[k];
+    const PathTap<real> *__restrict__ tp = a.taps + gm.tap0 + 1;   // tp[c]: path point c = -1 .. npc + 1
+    const int npc = gm.npc;
     // start of this ordinate's lab slab (+ chunk) and the stride between points
     const long slab = a.gmajor ? ((long)k * G + g0) * a.P : (long)k * a.P * G + g0;
     const int ps = a.gmajor ? 1 : G;
@@ -464,20 +530,17 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
     const int tid = threadIdx.x;
     PlaneRegs<real, GC, MAXPT> rg;
 
-    // LDS cell of each point and of its three bilinear tap cells (second
-    // upwind, upwind, downwind): the same on every plane
-    int self[MAXPT], cell[MAXPT][3];
+    // plane position of each point, its LDS cell and, for one piece per
+    // plane, the cells of its three bilinear taps (second upwind, upwind,
+    // downwind): the same on every plane
+    int pi[MAXPT], pj[MAXPT], self[MAXPT], cell[MAXPT][3];
 #pragma unroll
     for (int c = 0; c < MAXPT; ++c) {
-        int i, j;
-        plane_ij(min(tid + c * T, PL - 1), nx, q.rnx, i, j);
-        self[c] = j * q.RS + i;
-#pragma unroll
-        for (int s = 0; s < 3; ++s) {
-            int i0 = i + gm.ix[s]; if (i0 >= nx) i0 -= nx;
-            int j0 = j + gm.iy[s]; if (j0 >= ny) j0 -= ny;
-            cell[c][s] = j0 * q.RS + i0;
-        }
+        plane_ij(min(tid + c * T, PL - 1), nx, q.rnx, pi[c], pj[c]);
+        self[c] = pj[c] * q.RS + pi[c];
+        cell[c][0] = tap_cell(tp[2], pi[c], pj[c], q);
+        cell[c][1] = tap_cell(tp[1], pi[c], pj[c], q);
+        cell[c][2] = tap_cell(tp[-1], pi[c], pj[c], q);
     }
 
     const real add = XMODE == kChiArray ? real(0) : a.inv_cdt;   // the stand-alone chi~ already holds it
@@ -492,8 +555,6 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
         for (int c = 0; c < MAXPT; ++c) {
             const int pe = tid + c * T;
             if (pe >= PL) break;
-            int i, j;
-            plane_ij(pe, nx, q.rnx, i, j);
             P v;
             if (bc) {
                 v = *reinterpret_cast<const P *>(bc + ((long)k * PL + pe) * G + g0);
@@ -501,20 +562,19 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
 #pragma unroll
                 for (int n = 0; n < GC; ++n) v.v[n] = real(0);
             }
-            lds_put(Ir, q, i, j, v);
+            lds_put(Ir, q, pi[c], pj[c], v);
             *reinterpret_cast<P *>(Ik + (long)(m0 * PL + pe) * ps) = v;
         }
     }
     __syncthreads();
     const real hds = real(0.5) * (real)gm.ds;
+    const real inv_np = real(1) / (real)npc;
     real wts[3][4];
 #pragma unroll
-    for (int s = 0; s < 3; ++s) {
-        const real fx = (real)gm.fx[s], fy = (real)gm.fy[s];
-        wts[s][0] = (real(1) - fx) * (real(1) - fy);
-        wts[s][1] = fx * (real(1) - fy);
-        wts[s][2] = (real(1) - fx) * fy;
-        wts[s][3] = fx * fy;
+    for (int n = 0; n < 4; ++n) {
+        wts[0][n] = tp[2].w[n];
+        wts[1][n] = tp[1].w[n];
+        wts[2][n] = tp[-1].w[n];
     }
     const int RS = q.RS;
     for (int t = 1; t < nz; ++t) {
@@ -533,40 +593,94 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
         const PX *Xdl = reinterpret_cast<const PX *>(Xr + sd0 * XE);
         const P *Iul = Ir;
         P res[MAXPT];
+        if (npc == 1) {
+            // one piece: the plane-to-plane step, every tap on a grid plane
 #pragma unroll
-        for (int c = 0; c < MAXPT; ++c) {
-            const int cp = self[c], cu = cell[c][1], cd = cell[c][2], cuu = cell[c][0];
-            const P Sp = Spl[cp], Su = bil(Sul, cu, RS, wts[1]), Iu = bil(Iul, cu, RS, wts[1]);
-            P Sd, Suu;
-            PX Xd, Xuu;
-            const PX Xp = Xpl[cp], Xu = bil(Xul, cu, RS, wts[1]);
-            if (has_d) {
-                Sd = bil(Sdl, cd, RS, wts[2]);
-                Xd = bil(Xdl, cd, RS, wts[2]);
+            for (int c = 0; c < MAXPT; ++c) {
+                const int cp = self[c], cu = cell[c][1], cd = cell[c][2], cuu = cell[c][0];
+                const P Sp = Spl[cp], Su = bil(Sul, cu, RS, wts[1]);
+                P Iu = bil(Iul, cu, RS, wts[1]);
+                P Sd, Suu;
+                PX Xd, Xuu;
+                const PX Xp = Xpl[cp], Xu = bil(Xul, cu, RS, wts[1]);
+                if (has_d) {
+                    Sd = bil(Sdl, cd, RS, wts[2]);
+                    Xd = bil(Xdl, cd, RS, wts[2]);
+                }
+                if (has_uu) {
+                    Suu = bil(Suul, cuu, RS, wts[0]);
+                    Xuu = bil(Xuul, cuu, RS, wts[0]);
+                }
+                bezier_step<real, XMODE, GC>(Iu, hds, Suu, Su, Sp, Sd, Xuu, Xu, Xp, Xd, has_d, has_uu);
+                res[c] = Iu;
+                if (tid + c * T < PL) *reinterpret_cast<P *>(Ik + (long)(m * PL + tid + c * T) * ps) = res[c];
             }
-            if (has_uu) {
-                Suu = bil(Suul, cuu, RS, wts[0]);
-                Xuu = bil(Xuul, cuu, RS, wts[0]);
-            }
-            StepDepth<real> gd;
-            if (xg) gd = step_depth(hds, Xuu.v[0], Xu.v[0], Xp.v[0], Xd.v[0], has_d, has_uu);
+        } else {
+            // npc pieces: the intensity at the upwind point u = path point npc is
+            // carried to p = path point 0 piece by piece; S~ and chi~ at path
+            // point c lie between grid planes (bilinear on each, linear in z)
 #pragma unroll
-            for (int n = 0; n < GC; ++n) {
-                if (!xg) gd = step_depth(hds, Xuu.v[n % XG], Xu.v[n % XG], Xp.v[n % XG], Xd.v[n % XG], has_d, has_uu);
-                const real sp = Sp.v[n], su = Su.v[n];
-                const real dl = sp - su;
-                // step depth times the slopes at p and at u (secant where the outer neighbour is missing)
-                const real tp = has_d ? fb_slope(gd.np, gd.ap, gd.bp, gd.okp, dl, Sd.v[n] - sp) : dl;
-                const real tu = has_uu ? fb_slope(gd.nu, gd.au, gd.bu, gd.oku, su - Suu.v[n], dl) : dl;
-                const real Cu = clamp_between(su + tu * real(1.0 / 3.0), su, sp);
-                const real Cp = clamp_between(sp - tp * real(1.0 / 3.0), su, sp);
-                // a grey extinction shares the step's weights among the groups: the integral is
-                // then four products per group; otherwise the moment form (fewer operations
-                // for one group)
-                res[c].v[n] = xg ? Iu.v[n] * gd.ex + gd.w0 * su + gd.w1 * Cu + gd.w2 * Cp + gd.w3 * sp
-                                 : Iu.v[n] * gd.ex + bezier_integral(gd.E0, gd.E1, gd.E2, gd.E3, su, Cu, Cp, sp);
+            for (int c = 0; c < MAXPT; ++c) {
+                const int i = pi[c], j = pj[c];
+                P Suu, Su, Sp, Sd;
+                PX Xuu, Xu, Xp, Xd;
+                real w[4];
+                if (has_uu) {            // path point npc + 1: one piece beyond u
+                    const PathTap<real> tt = tp[npc + 1];
+#pragma unroll
+                    for (int n = 0; n < 4; ++n) w[n] = tt.w[n];
+                    const int cl = tap_cell(tt, i, j, q);
+                    Suu = bil_lerp(Sul, Suul, cl, RS, w, inv_np);
+                    Xuu = bil_lerp(Xul, Xuul, cl, RS, w, inv_np);
+                }
+                P I;
+                {                        // path point npc: u on the previous plane
+                    const PathTap<real> tt = tp[npc];
+#pragma unroll
+                    for (int n = 0; n < 4; ++n) w[n] = tt.w[n];
+                    const int cl = tap_cell(tt, i, j, q);
+                    Su = bil(Sul, cl, RS, w);
+                    Xu = bil(Xul, cl, RS, w);
+                    I = bil(Iul, cl, RS, w);
+                }
+                {                        // path point npc - 1 (>= 1)
+                    const PathTap<real> tt = tp[npc - 1];
+#pragma unroll
+                    for (int n = 0; n < 4; ++n) w[n] = tt.w[n];
+                    const int cl = tap_cell(tt, i, j, q);
+                    const real f = (real)(npc - 1) * inv_np;
+                    Sp = bil_lerp(Spl, Sul, cl, RS, w, f);
+                    Xp = bil_lerp(Xpl, Xul, cl, RS, w, f);
+                }
+                for (int pc = npc - 1; pc >= 0; --pc) {
+                    // piece from path point pc + 1 to pc; its downwind neighbour pc - 1
+                    const bool pd = pc >= 1 || has_d, puu = pc + 2 <= npc || has_uu;
+                    if (pc >= 2) {
+                        const PathTap<real> tt = tp[pc - 1];
+#pragma unroll
+                        for (int n = 0; n < 4; ++n) w[n] = tt.w[n];
+                        const int cl = tap_cell(tt, i, j, q);
+                        const real f = (real)(pc - 1) * inv_np;
+                        Sd = bil_lerp(Spl, Sul, cl, RS, w, f);
+                        Xd = bil_lerp(Xpl, Xul, cl, RS, w, f);
+                    } else if (pc == 1) {
+                        Sd = Spl[self[c]];
+                        Xd = Xpl[self[c]];
+                    } else if (has_d) {  // path point -1: one piece beyond p
+                        const PathTap<real> tt = tp[-1];
+#pragma unroll
+                        for (int n = 0; n < 4; ++n) w[n] = tt.w[n];
+                        const int cl = tap_cell(tt, i, j, q);
+                        Sd = bil_lerp(Spl, Sdl, cl, RS, w, inv_np);
+                        Xd = bil_lerp(Xpl, Xdl, cl, RS, w, inv_np);
+                    }
+                    bezier_step<real, XMODE, GC>(I, hds, Suu, Su, Sp, Sd, Xuu, Xu, Xp, Xd, pd, puu);
+                    Suu = Su; Su = Sp; Sp = Sd;
+                    Xuu = Xu; Xu = Xp; Xp = Xd;
+                }
+                res[c] = I;
+                if (tid + c * T < PL) *reinterpret_cast<P *>(Ik + (long)(m * PL + tid + c * T) * ps) = res[c];
             }
-            if (tid + c * T < PL) *reinterpret_cast<P *>(Ik + (long)(m * PL + tid + c * T) * ps) = res[c];
         }
         __syncthreads();
         // every read of plane t - 1 is done: the intensity plane and the slot of
@@ -575,9 +689,7 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
         for (int c = 0; c < MAXPT; ++c) {
             const int pe = tid + c * T;
             if (pe >= PL) break;
-            int i, j;
-            plane_ij(pe, nx, q.rnx, i, j);
-            lds_put(Ir, q, i, j, res[c]);
+            lds_put(Ir, q, pi[c], pj[c], res[c]);
         }
         if (t + 2 < nz) trace_store<real, XMODE, GC, MAXPT>(rg, Sr, Xr, q, t + 2, add);
         __syncthreads();
@@ -2190,8 +2302,7 @@ template <typename real>
 void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st)
 {
     const size_t sm = trace_lds<real>(a.nx, a.ny, a.Gc, !chi_array && a.chi_grey);
-    const long items = (long)a.K * (a.G / a.Gc);
-    const dim3 grid((unsigned)(8 * ((items + 7) / 8))), block(kTraceThreads);
+    const dim3 grid((unsigned)(8 * ((a.K + 7) / 8) * (a.G / a.Gc))), block(kTraceThreads);
     const int npt = (a.nx * a.ny + kTraceThreads - 1) / kTraceThreads;
 #define RRT_TRACE_CASE(GC, MP)                                                                       \
     if (a.Gc == GC && npt <= MP) {                                                                   \

@@ -182,6 +182,39 @@ def test_group_major_trace_parity(grey_kappa, prec, grid):
     g.close()
 
 
+@pytest.mark.parametrize("plane", [(40, 36), (64, 50)], ids=["two_points_per_thread", "four_points_per_thread"])
+@pytest.mark.parametrize("grey_kappa", [True, False], ids=["grey_chi", "group_chi"])
+def test_large_plane_trace_parity(plane, grey_kappa):
+    """Planes of more than 1024 and more than 2048 points (each ray-trace
+    thread then owns two or four points, as on the 48^3 and 64^3 grids), on a
+    time-dependent FP32 sweep, for every ray-trace variant the LDS holds
+    (groups per workgroup, and one group on group-major planes).  nz, the
+    ordinates and the groups are few so that the oracle stays fast; lz makes
+    the path between planes cross a few cells for the shallow ordinates."""
+    nx, ny = plane
+    spec = custom_spec(nx, ny, 4, G=4, lmax=1, nmu=4, nphi=8, seed=31, grey_kappa=grey_kappa, gamma_max=5.0)
+    spec["lz"] = 0.06
+    o, g = _both(spec, B.FP32)
+    rs = np.random.default_rng(32)
+    S = o.initial_source() * (1 + 0.2 * rs.uniform(size=o.sh_shape()))
+    Iprev = rs.uniform(0.0, 1.0, o.lab_shape())
+    ref_I = o.sweep(S, I_prev=Iprev, inv_cdt=3.0)[0]
+    ran = []
+    for gc in (1, 2, 4, -1):
+        try:
+            g.set_variants(trace_groups=gc)
+        except B.RRTError:
+            continue
+        ran.append(gc)
+        print(f"  trace groups {gc}", flush=True)
+        g.set_source_sh(S)
+        g.set_intensity(Iprev)
+        g.sweep(dt_stage=1.0 / 3.0)
+        close_by_group(g.sweep_intensity(), ref_I, TOL[B.FP32], 2, f"I_lab {plane} gc {gc}")
+    assert 1 in ran and -1 in ran
+    g.close()
+
+
 @pytest.mark.parametrize("prec", [B.FP64, B.FP32], ids=["fp64", "fp32"])
 def test_time_dependent_sweep_parity(prec):
     spec = custom_spec(7, 6, 5, G=4, seed=12)

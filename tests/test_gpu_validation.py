@@ -197,13 +197,14 @@ def test_two_beams_cross_without_interaction_and_cast_shadows():
 
 
 def test_thick_pulse_follows_the_diffusion_solution():
-    """Sec. 4.3.2 at 64 x 64 with (8, 16) ordinates: an isotropic pulse
+    """Sec. 3.3.2 at the paper's size, 128 x 128 with (32, 64) ordinates (an
+    optical depth of 2.3 per cell, as there): an isotropic pulse
     100 exp(-(x/w)^2) in a purely (isotropically) scattering medium of depth
     300 across the domain, backward-Euler steps of 1/20 to t = 1: J along x
     follows Eq. 16's Gaussian with D = c/(3 sigma) to 10 % of the peak and is
     independent of z away from the open faces."""
-    print("thick pulse 64^2", flush=True)
-    spec, I0 = W.radiative_pulse(64, nmu=8, nphi=16, thick=True)
+    print("thick pulse 128^2", flush=True)
+    spec, I0 = W.radiative_pulse(128, nmu=32, nphi=64, thick=True)
     g = _problem(spec, I0, B.FP32)
     dt, nsteps = 0.05, 20
     g.advance(dt, nsteps=nsteps, scheme=B.SCHEME_EULER, tol=1e-6, max_iter=400, use_ng=True)
