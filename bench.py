@@ -154,7 +154,7 @@ def serving_bench(args):
 
 
 def validation_runs(args):
-    """The paper's validation problems (Sec. 4) at its own grid and ordinate
+    """The paper's validation problems (Sec. 3) at its own grid and ordinate
     sizes, in FP32 on the library, each checked against the closed form the
     paper compares with.  One JSON line per problem: wall time, sweeps,
     updates per second and the measured deviations."""
@@ -311,7 +311,7 @@ def main():
     ap.add_argument("--mix", choices=["small", "full"], default="small",
                     help="--serving request mix: small (n <= 32, G <= 16, L <= 7) or full (n <= 64, G <= 32, L <= 15)")
     ap.add_argument("--validation", action="store_true",
-                    help="run the paper's validation problems (Sec. 4) at its sizes instead of the sweep benchmark")
+                    help="run the paper's validation problems (Sec. 3) at its sizes instead of the sweep benchmark")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="first run a plain 1 GiB device-to-device copy (reference for HBM byte counters)")

@@ -171,7 +171,7 @@ def random_medium(n=8, nz=None, ng=4, lmax=3, nmu=4, nphi=8, seed=11, scatter="t
 
 
 # ---------------------------------------------------------------------------
-# The paper's validation problems (Sec. 4), two-dimensional: ny = 1, symmetry
+# The paper's validation problems (Sec. 3), two-dimensional: ny = 1, symmetry
 # in y.  Lengths are in units of the paper's 1e10 cm domain side, so with c = 1
 # one time unit is 1/3 s; x is periodic and z has nz points on [0, 1].  Each
 # generator returns the problem description and the initial lab intensity
@@ -213,7 +213,7 @@ def beam_ordinate(nmu, nphi, phi_index=0):
 
 
 def searchlight(n=512, nz=None, alpha_cm=0.0, nmu=4, nphi=8, lmax=1):
-    """Searchlight beam (Sec. 4.1): unit intensity enters through the bottom
+    """Searchlight beam (Sec. 3.1): unit intensity enters through the bottom
     face for 0.15 < x < 0.45 along the ordinate (0.17 pi, 0); uniform
     absorption alpha (1e-10 / cm in the paper's second case), no scattering."""
     nz = n if nz is None else nz
@@ -227,7 +227,7 @@ def searchlight(n=512, nz=None, alpha_cm=0.0, nmu=4, nphi=8, lmax=1):
 
 
 def two_beam_shadow(n=512, nz=None, nmu=4, nphi=8, lmax=1, beams=(0, 1)):
-    """Two beams and a shadow (Sec. 4.2): plane-parallel unit intensity enters
+    """Two beams and a shadow (Sec. 3.2): plane-parallel unit intensity enters
     through the whole bottom face along (0.17 pi, 0) and (0.17 pi, pi); an
     absorbing cylinder of radius 0.15 about (x, z) = (0.5, 0.33), optical depth
     100 across its diameter, in vacuum.  `beams` selects which of the two enter."""
@@ -243,7 +243,7 @@ def two_beam_shadow(n=512, nz=None, nmu=4, nphi=8, lmax=1, beams=(0, 1)):
 
 
 def radiative_pulse(n=128, nz=None, nmu=64, nphi=128, lmax=1, thick=False, w_cm=9.0e8):
-    """Radiative pulse (Sec. 4.3): an isotropic initial intensity
+    """Radiative pulse (Sec. 3.3): an isotropic initial intensity
     100 exp(-(r/w)^2) about the domain centre in vacuum (thin), or
     100 exp(-(x/w)^2) in a purely scattering medium of Thomson depth 300 across
     the domain (thick, isotropic scattering: the Thomson kernel with L = 0).
@@ -267,7 +267,7 @@ def radiative_pulse(n=128, nz=None, nmu=64, nphi=128, lmax=1, thick=False, w_cm=
 
 def beaming_cylinder(n=128, nz=None, nmu=32, nphi=64, lmax=1, beta=(0.0, 0.0), radius_cm=5.0e8,
                      kappa=1e-9, emission=1.0):
-    """Relativistic beaming (Sec. 4.4): a cylinder of radius 5e8 cm about the
+    """Relativistic beaming (Sec. 3.4): a cylinder of radius 5e8 cm about the
     domain centre whose matter moves with beta = (vx/c, vz/c) and emits
     isotropically in its own frame (emissivity kappa B = `emission`, with an
     absorption coefficient small enough to leave the light unabsorbed); vacuum

@@ -914,11 +914,11 @@ def test_floored_residual_only_changes_negligible_groups():
 
 
 # ---------------------------------------------------------------------------
-# the paper's two-dimensional validation problems (Sec. 4), small grids
+# the paper's two-dimensional validation problems (Sec. 3), small grids
 # ---------------------------------------------------------------------------
 
 def test_searchlight_attenuation_and_front_in_two_dimensions():
-    """Sec. 4.1 on a 48 x 48 plane with (4, 8) ordinates and the four-stage
+    """Sec. 3.1 on a 48 x 48 plane with (4, 8) ordinates and the four-stage
     scheme, one cell per step: behind the front J is the beam's J times
     exp(-alpha s) (alpha = 1 per domain side), and the front's half point is
     within two cell paths of c t."""
@@ -1010,7 +1010,7 @@ def test_inconsistent_inflow_face_grows_ninefold_per_four_stage_step():
 
 @pytest.mark.parametrize("bx", [0.0, 0.9, 0.995])
 def test_moving_emitter_is_beamed_as_the_cube_of_the_doppler_factor(bx):
-    """Sec. 4.4: isotropic comoving emission from matter moving along x has the
+    """Sec. 3.4: isotropic comoving emission from matter moving along x has the
     lab emissivity D^3 eta_0 along n; on a grid and ordinate set symmetric under
     x -> -x the intensity along (theta, phi) at x over that along (theta, pi - phi)
     at -x is ((1 + beta sin(theta) cos(phi)) / (1 - beta sin(theta) cos(phi)))^3
