@@ -77,6 +77,7 @@ struct rrt_problem {
     rrt::OrdGeom *d_geo = nullptr;
     void *d_taps = nullptr;                         // rrt::PathTap<real> of every ordinate's path points
     int *d_order = nullptr;                         // ordinates by decreasing number of path pieces
+    int nmulti = 0;                                 // ordinates whose path takes more than one piece
     void *d_Yt = nullptr, *d_WY = nullptr, *d_A = nullptr, *d_sg = nullptr;
     void *d_Y16 = nullptr, *d_WYt16 = nullptr;     // RRT_MIXED: FP16 SH tables, hi then lo part (zero padded)
     size_t y16_n = 0, wyt16_n = 0;                  // elements per part
@@ -344,7 +345,7 @@ struct Engine {
     {
         rrt::TraceArgs<real> t;
         t.nx = pr->nx; t.ny = pr->ny; t.nz = pr->nz; t.G = pr->G; t.K = pr->K; t.Gc = gmajor ? 1 : pr->Gc; t.P = pr->P;
-        t.geo = pr->d_geo; t.taps = static_cast<const rrt::PathTap<real> *>(pr->d_taps); t.order = pr->d_order;
+        t.geo = pr->d_geo; t.taps = static_cast<const rrt::PathTap<real> *>(pr->d_taps); t.order = pr->d_order; t.nmulti = pr->nmulti;
         t.dir = pr->d_dir; t.St = static_cast<const real *>(St); t.Xt = R(pr->d_Xt);
         t.chilab = R(gmajor && !pr->grey_chi ? pr->d_chilabT : pr->d_chilab); t.chi_grey = pr->grey_chi;
         t.inv_cdt = (real)inv_cdt; t.bc_bot = R(pr->d_bc[0]); t.bc_top = R(pr->d_bc[1]); t.I = R(I);
@@ -1056,7 +1057,7 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
         if (pr->nx > 1) hmin = dx;
         if (pr->ny > 1 && (hmin == 0.0 || dy < hmin)) hmin = dy;
         std::vector<rrt::OrdGeom> geo(K);
-        std::vector<double> tix, tiy, tw;          // per tap: integer shift and four weights
+        std::vector<double> tix, tiy, tw;          // per tap: integer shift and eight weights
         for (int k = 0; k < K; ++k) {
             const double *n = &pr->dir[4 * k];
             rrt::OrdGeom &gm = geo[k];
@@ -1085,15 +1086,20 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
                 if (iy < 0) iy += pr->ny;
                 tix.push_back((double)ix);
                 tiy.push_back((double)iy);
-                tw.push_back((1.0 - fx) * (1.0 - fy));
-                tw.push_back(fx * (1.0 - fy));
-                tw.push_back((1.0 - fx) * fy);
-                tw.push_back(fx * fy);
+                // fraction of the plane spacing from the nearer plane: c / npc between
+                // the grid point's plane and the upwind one, 1 / npc one piece beyond
+                // either end, 0 on a grid plane
+                const double f = (c == -1 || c == npc + 1) ? 1.0 / npc : (c == 0 || c == npc) ? 0.0 : (double)c / npc;
+                const double w4[4] = {(1.0 - fx) * (1.0 - fy), fx * (1.0 - fy), (1.0 - fx) * fy, fx * fy};
+                for (int w = 0; w < 4; ++w) tw.push_back((1.0 - f) * w4[w]);
+                for (int w = 0; w < 4; ++w) tw.push_back(f * w4[w]);
             }
         }
         std::vector<int> order(K);
         for (int k = 0; k < K; ++k) order[k] = k;
         std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return geo[x].npc > geo[y].npc; });
+        pr->nmulti = 0;
+        for (int k = 0; k < K; ++k) pr->nmulti += geo[k].npc > 1;
         s = pr_alloc(pr, (void **)&pr->d_geo, sizeof(rrt::OrdGeom) * K);
         if (s) return bail(s);
         s = pr_alloc(pr, (void **)&pr->d_order, sizeof(int) * K);
@@ -1105,7 +1111,7 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
             for (size_t i = 0; i < nt; ++i) {
                 taps[i].ix = (int)tix[i];
                 taps[i].iy = (int)tiy[i];
-                for (int w = 0; w < 4; ++w) taps[i].w[w] = (real)tw[4 * i + w];
+                for (int w = 0; w < 8; ++w) taps[i].w[w] = (real)tw[8 * i + w];
             }
             rrt_status st = pr_alloc(pr, &pr->d_taps, esz * nt);
             if (st) return st;

@@ -21,12 +21,15 @@ struct OrdGeom {
     int tap0;
 };
 
-// Bilinear tap of a horizontal offset in cells: integer part reduced modulo
-// nx, ny, and the weights of the (x, y), (x + 1, y), (x, y + 1), (x + 1, y + 1)
-// neighbours.
+// Tap of a path point: the horizontal offset in cells (integer part reduced
+// modulo nx, ny) and eight weights, w[0..3] of the (x, y), (x + 1, y),
+// (x, y + 1), (x + 1, y + 1) neighbours on the nearer grid plane and w[4..7] of
+// the same neighbours on the farther one: the bilinear weights times 1 - f and
+// f, f being the path point's fraction of the plane spacing from the nearer
+// plane (0 on a grid plane).
 template <typename real> struct PathTap {
     int ix, iy;
-    real w[4];
+    real w[8];
 };
 
 // Group centres for the ln(nu) interpolation of the frame transforms.
@@ -52,6 +55,7 @@ template <typename real> struct TraceArgs {
     const OrdGeom *geo;
     const PathTap<real> *taps;  // path taps of every ordinate (OrdGeom::tap0)
     const int *order;           // ordinates by decreasing number of pieces (the costliest start first)
+    int nmulti;                 // how many of them take more than one piece
     const double *dir;          // [K][4]
     const real *St;             // S~ [k][p][g]
     const real *Xt;             // chi~ [k][p][g] (stand-alone trace only)

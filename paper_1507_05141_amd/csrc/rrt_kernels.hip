@@ -436,25 +436,55 @@ __device__ __forceinline__ double clamp_between(double x, double a, double b)
 
 // LDS cell of the tap of point (i, j) at table offset t (periodic wrap; the
 // plane's halo serves the + 1 neighbours)
-template <typename real>
-__device__ __forceinline__ int tap_cell(const PathTap<real> &t, int i, int j, const TraceIdx &q)
+template <typename T>
+__device__ __forceinline__ int tap_cell(const T &t, int i, int j, const TraceIdx &q)
 {
     int i0 = i + t.ix; if (i0 >= q.nx) i0 -= q.nx;
     int j0 = j + t.iy; if (j0 >= q.ny) j0 -= q.ny;
     return j0 * q.RS + i0;
 }
 
-// value a fraction f of the way from a bilinear sample of plane A to one of
-// plane B at the same tap (linear in z along the path)
+// value at a path point between grid planes A (the nearer) and B: bilinear
+// on each, linear in z, with the eight combined weights of its tap
 template <typename real, int N>
-__device__ __forceinline__ Pack<real, N> bil_lerp(const Pack<real, N> *A, const Pack<real, N> *B, int cell, int RS,
-                                                  const real w[4], real f)
+__device__ __forceinline__ Pack<real, N> bil2(const Pack<real, N> *A, const Pack<real, N> *B, int cell, int RS,
+                                              const real w[8])
 {
-    const Pack<real, N> x = bil(A, cell, RS, w), y = bil(B, cell, RS, w);
+    const Pack<real, N> a0 = A[cell], a1 = A[cell + 1], a2 = A[cell + RS], a3 = A[cell + RS + 1];
+    const Pack<real, N> b0 = B[cell], b1 = B[cell + 1], b2 = B[cell + RS], b3 = B[cell + RS + 1];
     Pack<real, N> r;
 #pragma unroll
-    for (int n = 0; n < N; ++n) r.v[n] = (real(1) - f) * x.v[n] + f * y.v[n];
+    for (int n = 0; n < N; ++n)
+        r.v[n] = w[0] * a0.v[n] + w[1] * a1.v[n] + w[2] * a2.v[n] + w[3] * a3.v[n] + w[4] * b0.v[n] +
+                 w[5] * b1.v[n] + w[6] * b2.v[n] + w[7] * b3.v[n];
     return r;
+}
+
+// Fritsch-Butland slope dS/dtau at a path point from its left segment (source
+// change dl over optical depth hl) and right segment (dr over hr), with the
+// depth coefficients of slope_coef: 3 (hl + hr) dl dr / (a dr + b dl), zero
+// unless dl dr > 0 and both depths are positive
+template <typename real>
+struct SlopeCoef {
+    real a, b, n;
+    bool ok;
+};
+template <typename real>
+__device__ __forceinline__ SlopeCoef<real> slope_coef(real hl, real hr)
+{
+    SlopeCoef<real> c;
+    c.a = hl * (hl + real(2) * hr);
+    c.b = hr * (real(2) * hl + hr);
+    c.n = real(3) * (hl + hr);
+    c.ok = hl > real(0) && hr > real(0);
+    return c;
+}
+template <typename real>
+__device__ __forceinline__ real fb_dtau(const SlopeCoef<real> &c, real dl, real dr)
+{
+    const real prod = dl * dr;
+    const real v = c.n * prod * fast_rcp(c.a * dr + c.b * dl);
+    return (c.ok && prod > real(0)) ? v : real(0);
 }
 
 // One cubic Bezier step u -> p over every group of the pack: the intensity
@@ -492,8 +522,8 @@ __device__ __forceinline__ void bezier_step(Pack<real, GC> &I, real hds, const P
     }
 }
 
-template <typename real, int XMODE, int GC, int MAXPT>
-__global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
+template <typename real, int XMODE, int GC, int MAXPT, bool MULTI>
+__global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a, int rank0, int nrank)
 {
     using P = Pack<real, GC>;
     using PX = Pack<real, XMODE == kChiGrey ? 1 : GC>;
@@ -510,15 +540,18 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
     const int xcd = blockIdx.x % 8;
     const long slot = blockIdx.x / 8;
     const int rank = 8 * (int)(slot / nch) + xcd;
-    if (rank >= a.K) return;
-    const int k = a.order[rank], g0 = (int)(slot % nch) * GC;
+    if (rank >= nrank) return;
+    const int k = a.order[rank0 + rank], g0 = (int)(slot % nch) * GC;
     const TraceIdx q{nx, ny, PL, nx + 1, (nx + 1) * (ny + 1), 1.0f / (float)nx};
     const int XE = q.PS * XG;
     real *Sr = reinterpret_cast<real *>(smem_raw);
     real *Xr = Sr + kRing * q.PS * GC;
     P *Ir = reinterpret_cast<P *>(Xr + kRing * XE);   // kIBuf planes of PS points
     const OrdGeom gm = a.geo[k];
-    const PathTap<real> *__restrict__ tp = a.taps + gm.tap0 + 1;   // tp[c]: path point c = -1 .. npc + 1
+    // tp[c]: path point c = -1 .. npc + 1, read through the constant address
+    // space so that the (uniform) taps load into scalar registers
+    const __attribute__((address_space(4))) PathTap<real> *tp =
+        (const __attribute__((address_space(4))) PathTap<real> *)(a.taps + gm.tap0 + 1);
     const int npc = gm.npc;
     // start of this ordinate's lab slab (+ chunk) and the stride between points
     const long slab = a.gmajor ? ((long)k * G + g0) * a.P : (long)k * a.P * G + g0;
@@ -568,13 +601,13 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
     }
     __syncthreads();
     const real hds = real(0.5) * (real)gm.ds;
-    const real inv_np = real(1) / (real)npc;
+    // one piece per plane: second upwind, upwind and downwind taps (each on a grid plane)
     real wts[3][4];
 #pragma unroll
     for (int n = 0; n < 4; ++n) {
-        wts[0][n] = tp[2].w[n];
+        wts[0][n] = tp[2].w[4 + n];
         wts[1][n] = tp[1].w[n];
-        wts[2][n] = tp[-1].w[n];
+        wts[2][n] = tp[-1].w[4 + n];
     }
     const int RS = q.RS;
     for (int t = 1; t < nz; ++t) {
@@ -593,7 +626,7 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
         const PX *Xdl = reinterpret_cast<const PX *>(Xr + sd0 * XE);
         const P *Iul = Ir;
         P res[MAXPT];
-        if (npc == 1) {
+        if (!MULTI) {
             // one piece: the plane-to-plane step, every tap on a grid plane
 #pragma unroll
             for (int c = 0; c < MAXPT; ++c) {
@@ -617,66 +650,108 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a)
             }
         } else {
             // npc pieces: the intensity at the upwind point u = path point npc is
-            // carried to p = path point 0 piece by piece; S~ and chi~ at path
-            // point c lie between grid planes (bilinear on each, linear in z)
+            // carried to p = path point 0 piece by piece.  Path point c lies
+            // between grid planes (bilinear on each, linear in z); the
+            // Fritsch-Butland slope at a path point serves the piece that ends
+            // there and the one that starts there.
 #pragma unroll
             for (int c = 0; c < MAXPT; ++c) {
                 const int i = pi[c], j = pj[c];
-                P Suu, Su, Sp, Sd;
-                PX Xuu, Xu, Xp, Xd;
-                real w[4];
-                if (has_uu) {            // path point npc + 1: one piece beyond u
-                    const PathTap<real> tt = tp[npc + 1];
+                P Sup2, Sup, Scur, Sdn;          // path points c + 2, c + 1, c, c - 1 of the walk
+                PX Xup2, Xup, Xcur, Xdn;
+                real w[8];
+                auto taps_of = [&](int pc) {
 #pragma unroll
-                    for (int n = 0; n < 4; ++n) w[n] = tt.w[n];
-                    const int cl = tap_cell(tt, i, j, q);
-                    Suu = bil_lerp(Sul, Suul, cl, RS, w, inv_np);
-                    Xuu = bil_lerp(Xul, Xuul, cl, RS, w, inv_np);
+                    for (int n = 0; n < 8; ++n) w[n] = tp[pc].w[n];
+                    return tap_cell(tp[pc], i, j, q);
+                };
+                if (has_uu) {                    // path point npc + 1: one piece beyond u
+                    const int cl = taps_of(npc + 1);
+                    Sup2 = bil2(Sul, Suul, cl, RS, w);
+                    Xup2 = bil2(Xul, Xuul, cl, RS, w);
                 }
                 P I;
-                {                        // path point npc: u on the previous plane
-                    const PathTap<real> tt = tp[npc];
-#pragma unroll
-                    for (int n = 0; n < 4; ++n) w[n] = tt.w[n];
-                    const int cl = tap_cell(tt, i, j, q);
-                    Su = bil(Sul, cl, RS, w);
-                    Xu = bil(Xul, cl, RS, w);
+                {                                // path point npc: u on the upwind plane
+                    const int cl = taps_of(npc);
+                    Sup = bil(Sul, cl, RS, w);
+                    Xup = bil(Xul, cl, RS, w);
                     I = bil(Iul, cl, RS, w);
                 }
-                {                        // path point npc - 1 (>= 1)
-                    const PathTap<real> tt = tp[npc - 1];
-#pragma unroll
-                    for (int n = 0; n < 4; ++n) w[n] = tt.w[n];
-                    const int cl = tap_cell(tt, i, j, q);
-                    const real f = (real)(npc - 1) * inv_np;
-                    Sp = bil_lerp(Spl, Sul, cl, RS, w, f);
-                    Xp = bil_lerp(Xpl, Xul, cl, RS, w, f);
+                {                                // path point npc - 1 (>= 1)
+                    const int cl = taps_of(npc - 1);
+                    Scur = bil2(Spl, Sul, cl, RS, w);
+                    Xcur = bil2(Xpl, Xul, cl, RS, w);
                 }
+                // depths of the piece before u and of the first piece (per group unless grey)
+                PX hup, hcur;
+#pragma unroll
+                for (int n = 0; n < XG; ++n) {
+                    hup.v[n] = hds * (Xup2.v[n] + Xup.v[n]);
+                    hcur.v[n] = hds * (Xcur.v[n] + Xup.v[n]);
+                }
+                // slope at u (dS/dtau); unused without the piece before it
+                P sup;
+                {
+                    SlopeCoef<real> sc;
+                    if (xg) sc = slope_coef(hup.v[0], hcur.v[0]);
+#pragma unroll
+                    for (int n = 0; n < GC; ++n) {
+                        if (!xg) sc = slope_coef(hup.v[n % XG], hcur.v[n % XG]);
+                        sup.v[n] = fb_dtau(sc, Sup.v[n] - Sup2.v[n], Scur.v[n] - Sup.v[n]);
+                    }
+                }
+#pragma unroll 1
                 for (int pc = npc - 1; pc >= 0; --pc) {
-                    // piece from path point pc + 1 to pc; its downwind neighbour pc - 1
+                    // piece from path point pc + 1 to pc; the next path point pc - 1
                     const bool pd = pc >= 1 || has_d, puu = pc + 2 <= npc || has_uu;
                     if (pc >= 2) {
-                        const PathTap<real> tt = tp[pc - 1];
-#pragma unroll
-                        for (int n = 0; n < 4; ++n) w[n] = tt.w[n];
-                        const int cl = tap_cell(tt, i, j, q);
-                        const real f = (real)(pc - 1) * inv_np;
-                        Sd = bil_lerp(Spl, Sul, cl, RS, w, f);
-                        Xd = bil_lerp(Xpl, Xul, cl, RS, w, f);
+                        const int cl = taps_of(pc - 1);
+                        Sdn = bil2(Spl, Sul, cl, RS, w);
+                        Xdn = bil2(Xpl, Xul, cl, RS, w);
                     } else if (pc == 1) {
-                        Sd = Spl[self[c]];
-                        Xd = Xpl[self[c]];
-                    } else if (has_d) {  // path point -1: one piece beyond p
-                        const PathTap<real> tt = tp[-1];
-#pragma unroll
-                        for (int n = 0; n < 4; ++n) w[n] = tt.w[n];
-                        const int cl = tap_cell(tt, i, j, q);
-                        Sd = bil_lerp(Spl, Sdl, cl, RS, w, inv_np);
-                        Xd = bil_lerp(Xpl, Xdl, cl, RS, w, inv_np);
+                        Sdn = Spl[self[c]];
+                        Xdn = Xpl[self[c]];
+                    } else if (has_d) {          // path point -1: one piece beyond p
+                        const int cl = taps_of(-1);
+                        Sdn = bil2(Spl, Sdl, cl, RS, w);
+                        Xdn = bil2(Xpl, Xdl, cl, RS, w);
                     }
-                    bezier_step<real, XMODE, GC>(I, hds, Suu, Su, Sp, Sd, Xuu, Xu, Xp, Xd, pd, puu);
-                    Suu = Su; Su = Sp; Sp = Sd;
-                    Xuu = Xu; Xu = Xp; Xp = Xd;
+                    PX hdn;
+#pragma unroll
+                    for (int n = 0; n < XG; ++n) hdn.v[n] = hds * (Xcur.v[n] + Xdn.v[n]);
+                    P scur;                       // slope at path point pc
+                    real ex = real(0), E0 = real(0), E1 = real(0), E2 = real(0), E3 = real(0);
+                    real bw0 = real(0), bw1 = real(0), bw2 = real(0), bw3 = real(0);
+                    SlopeCoef<real> sc;
+                    if (xg) {
+                        // a grey extinction shares the piece's Bernstein weights among the groups
+                        sc = slope_coef(hcur.v[0], hdn.v[0]);
+                        bezier_moments(hcur.v[0], ex, E0, E1, E2, E3);
+                        bw0 = E3;
+                        bw1 = real(3) * (E2 - E3);
+                        bw2 = real(3) * ((E1 - E2) - (E2 - E3));
+                        bw3 = (E0 - E3) - real(3) * (E1 - E2);
+                    }
+#pragma unroll
+                    for (int n = 0; n < GC; ++n) {
+                        if (!xg) {
+                            sc = slope_coef(hcur.v[n % XG], hdn.v[n % XG]);
+                            bezier_moments(hcur.v[n % XG], ex, E0, E1, E2, E3);
+                        }
+                        const real h = hcur.v[n % XG];
+                        const real su = Sup.v[n], sp = Scur.v[n];
+                        const real dl = sp - su;
+                        scur.v[n] = fb_dtau(sc, dl, Sdn.v[n] - sp);
+                        // step depth times the slopes at p and at u (secant where the outer neighbour is missing)
+                        const real tp_ = pd ? h * scur.v[n] : dl;
+                        const real tu_ = puu ? h * sup.v[n] : dl;
+                        const real Cu = clamp_between(su + tu_ * real(1.0 / 3.0), su, sp);
+                        const real Cp = clamp_between(sp - tp_ * real(1.0 / 3.0), su, sp);
+                        I.v[n] = xg ? I.v[n] * ex + bw0 * su + bw1 * Cu + bw2 * Cp + bw3 * sp
+                                    : I.v[n] * ex + bezier_integral(E0, E1, E2, E3, su, Cu, Cp, sp);
+                    }
+                    Sup = Scur; Scur = Sdn; sup = scur;
+                    Xcur = Xdn; hcur = hdn;
                 }
                 res[c] = I;
                 if (tid + c * T < PL) *reinterpret_cast<P *>(Ik + (long)(m * PL + tid + c * T) * ps) = res[c];
@@ -2302,25 +2377,39 @@ template <typename real>
 void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st)
 {
     const size_t sm = trace_lds<real>(a.nx, a.ny, a.Gc, !chi_array && a.chi_grey);
-    const dim3 grid((unsigned)(8 * ((a.K + 7) / 8) * (a.G / a.Gc))), block(kTraceThreads);
+    const int nch = a.G / a.Gc;
     const int npt = (a.nx * a.ny + kTraceThreads - 1) / kTraceThreads;
-#define RRT_TRACE_CASE(GC, MP)                                                                       \
-    if (a.Gc == GC && npt <= MP) {                                                                   \
-        if (chi_array) hipLaunchKernelGGL((k_trace<real, kChiArray, GC, MP>), grid, block, sm, st, a); \
-        else if (a.chi_grey) hipLaunchKernelGGL((k_trace<real, kChiGrey, GC, MP>), grid, block, sm, st, a); \
-        else hipLaunchKernelGGL((k_trace<real, kChiGroup, GC, MP>), grid, block, sm, st, a);          \
-        return;                                                                                      \
-    }
-    RRT_TRACE_CASE(1, 1)
-    RRT_TRACE_CASE(1, 2)
-    RRT_TRACE_CASE(1, 4)
-    RRT_TRACE_CASE(2, 1)
-    RRT_TRACE_CASE(2, 2)
-    RRT_TRACE_CASE(2, 4)
-    RRT_TRACE_CASE(4, 1)
-    RRT_TRACE_CASE(4, 2)
-    RRT_TRACE_CASE(4, 4)
+    // ordinates whose path takes several pieces first (a.order lists them first), then
+    // the single-piece ones; each launch gives every XCD every eighth ordinate
+    const int parts[2][2] = {{0, a.nmulti}, {a.nmulti, a.K - a.nmulti}};
+    for (int part = 0; part < 2; ++part) {
+        const int r0 = parts[part][0], nr = parts[part][1];
+        if (nr <= 0) continue;
+        const dim3 grid((unsigned)(8 * ((nr + 7) / 8) * nch)), block(kTraceThreads);
+#define RRT_TRACE_CASE(GC, MP)                                                                                   \
+        if (a.Gc == GC && npt <= MP) {                                                                           \
+            if (part == 0) {                                                                                     \
+                if (chi_array) hipLaunchKernelGGL((k_trace<real, kChiArray, GC, MP, true>), grid, block, sm, st, a, r0, nr); \
+                else if (a.chi_grey) hipLaunchKernelGGL((k_trace<real, kChiGrey, GC, MP, true>), grid, block, sm, st, a, r0, nr); \
+                else hipLaunchKernelGGL((k_trace<real, kChiGroup, GC, MP, true>), grid, block, sm, st, a, r0, nr); \
+            } else {                                                                                             \
+                if (chi_array) hipLaunchKernelGGL((k_trace<real, kChiArray, GC, MP, false>), grid, block, sm, st, a, r0, nr); \
+                else if (a.chi_grey) hipLaunchKernelGGL((k_trace<real, kChiGrey, GC, MP, false>), grid, block, sm, st, a, r0, nr); \
+                else hipLaunchKernelGGL((k_trace<real, kChiGroup, GC, MP, false>), grid, block, sm, st, a, r0, nr); \
+            }                                                                                                    \
+            continue;                                                                                            \
+        }
+        RRT_TRACE_CASE(1, 1)
+        RRT_TRACE_CASE(1, 2)
+        RRT_TRACE_CASE(1, 4)
+        RRT_TRACE_CASE(2, 1)
+        RRT_TRACE_CASE(2, 2)
+        RRT_TRACE_CASE(2, 4)
+        RRT_TRACE_CASE(4, 1)
+        RRT_TRACE_CASE(4, 2)
+        RRT_TRACE_CASE(4, 4)
 #undef RRT_TRACE_CASE
+    }
 }
 template <typename real>
 size_t boost_lds(int K, int G)
@@ -2574,60 +2663,114 @@ void launch_rk_stage(long n, const real *R, real *Iin, real *acc, real *In, int 
 
 hipError_t set_lds_limits(size_t bytes)
 {
-    const void *fns[] = {reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 1, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 1, 2>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 1, 4>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 2, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 2, 2>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 2, 4>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 4, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 4, 2>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 4, 4>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 1, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 1, 2>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 1, 4>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 2, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 2, 2>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 2, 4>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 4, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 4, 2>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 4, 4>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 1, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 1, 2>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 1, 4>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 2, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 2, 2>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 2, 4>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 4, 1>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 4, 2>),
-                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 4, 4>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 1, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 1, 2>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 1, 4>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 2, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 2, 2>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 2, 4>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 4, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 4, 2>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 4, 4>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 1, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 1, 2>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 1, 4>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 2, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 2, 2>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 2, 4>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 4, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 4, 2>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 4, 4>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 1, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 1, 2>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 1, 4>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 2, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 2, 2>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 2, 4>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 4, 1>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 4, 2>),
-                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 4, 4>),
+    const void *fns[] = {reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 1, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 1, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 1, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 1, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 1, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 1, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 2, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 2, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 2, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 2, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 2, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 2, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 4, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 4, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 4, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 4, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 4, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 4, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 1, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 1, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 1, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 1, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 1, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 1, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 2, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 2, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 2, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 2, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 2, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 2, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 4, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 4, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 4, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 4, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 4, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiGroup, 4, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 1, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 1, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 1, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 1, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 1, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 1, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 2, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 2, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 2, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 2, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 2, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 2, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 4, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 4, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 4, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 4, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 4, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<float, kChiArray, 4, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 1, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 1, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 1, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 1, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 1, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 1, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 2, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 2, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 2, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 2, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 2, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 2, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 4, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 4, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 4, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 4, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 4, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGrey, 4, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 1, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 1, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 1, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 1, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 1, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 1, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 2, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 2, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 2, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 2, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 2, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 2, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 4, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 4, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 4, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 4, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 4, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiGroup, 4, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 1, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 1, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 1, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 1, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 1, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 1, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 2, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 2, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 2, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 2, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 2, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 2, 4, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 4, 1, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 4, 1, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 4, 2, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 4, 2, false>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 4, 4, true>),
+                         reinterpret_cast<const void *>(&k_trace<double, kChiArray, 4, 4, false>),
                          reinterpret_cast<const void *>(&k_boost<float, 1>),
                          reinterpret_cast<const void *>(&k_boost<float, 2>),
                          reinterpret_cast<const void *>(&k_boost<double, 1>),
