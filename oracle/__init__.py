@@ -60,6 +60,7 @@ class _Problem(ctypes.Structure):
         ("kappa", _dp), ("sigma", _dp), ("bnu", _dp), ("beta", _dp),
         ("bc_bot", _dp), ("bc_top", _dp),
         ("mu", _dp), ("wmu", _dp), ("Y", _dp),
+        ("ntemp", ctypes.c_int), ("lt_nodes", _dp), ("kte", _dp),
     ]
 
 
@@ -110,6 +111,37 @@ def compton_cold(edges, centres, mec2, lmax):
     return s, p
 
 
+def compton_thermal(edges, centres, mec2, lmax, kT):
+    """Group-to-group Compton tables for electrons of temperature kT (units of
+    the edges), a Maxwell-Juttner average of the Klein-Nishina rate; kT = 0 is
+    the paper's electrons at rest."""
+    G = len(centres)
+    s = np.zeros(G)
+    p = np.zeros((lmax + 1, G, G))
+    _load().or_compton_thermal(G, _ptr(_f64(edges)), _ptr(_f64(centres)), ctypes.c_double(mec2), lmax,
+                               ctypes.c_double(kT), _ptr(s), _ptr(p))
+    return s, p
+
+
+def compton_thermal_moments(nu, mec2, kT):
+    """Unbinned averages of the thermal Compton rate at one frequency:
+    (total cross-section / sigma_T, mean nu1/nu - 1 of the scattered photons,
+    the total again from integrating the rate over all scattered directions)."""
+    out = np.zeros(3)
+    _load().or_compton_thermal_moments(ctypes.c_double(nu), ctypes.c_double(mec2), ctypes.c_double(kT), _ptr(out))
+    return out
+
+
+def temperature_nodes(kte):
+    """Node temperatures of the Compton tables for a temperature field: log10 T
+    on a grid of 8 nodes per decade covering the field's range."""
+    lt = np.log10(np.asarray(kte, dtype=np.float64))
+    lo = math.floor(8.0 * float(lt.min()) + 1e-9) / 8.0
+    hi = math.ceil(8.0 * float(lt.max()) - 1e-9) / 8.0
+    n = int(round((hi - lo) * 8.0)) + 1
+    return lo + np.arange(n) / 8.0
+
+
 # ---------------------------------------------------------------------------
 # problem
 # ---------------------------------------------------------------------------
@@ -135,7 +167,16 @@ class Oracle:
             self.centres = group_centres(self.edges, spec.get("log_centres", True))
         G, P, K = self.G, self.P, self.K
         self.compton = spec.get("scatter", "thomson") == "compton"
-        if self.compton:
+        self.kte = _f64(spec.get("kte")) if self.compton and spec.get("kte") is not None else None
+        self.lt_nodes = None
+        if self.compton and self.kte is not None:
+            if not np.all(self.kte > 0):
+                raise ValueError("electron temperatures must be positive")
+            self.lt_nodes = temperature_nodes(self.kte)
+            tabs = [compton_thermal(self.edges, self.centres, spec["mec2"], self.lmax, 10.0 ** t) for t in self.lt_nodes]
+            self.kn_s = np.ascontiguousarray(np.stack([t[0] for t in tabs]))
+            self.kn_p = np.ascontiguousarray(np.stack([t[1] for t in tabs]))
+        elif self.compton:
             self.kn_s, self.kn_p = compton_cold(self.edges, self.centres, spec["mec2"], self.lmax)
         else:
             self.kn_s, self.kn_p = None, None
@@ -159,6 +200,9 @@ class Oracle:
         s.kappa, s.sigma, s.bnu, s.beta = _ptr(self.kappa), _ptr(self.sigma), _ptr(self.bnu), _ptr(self.beta)
         s.bc_bot, s.bc_top = _ptr(self.bc_bot), _ptr(self.bc_top)
         s.mu, s.wmu, s.Y = _ptr(self.mu), _ptr(self.wmu), _ptr(self.Y)
+        s.ntemp = 0 if self.lt_nodes is None else len(self.lt_nodes)
+        s.lt_nodes = _ptr(None if self.lt_nodes is None else _f64(self.lt_nodes))
+        s.kte = _ptr(self.kte)
         self._ref = ctypes.byref(s)
 
     def _bc(self, a):

@@ -43,10 +43,10 @@ typedef struct {
     int grey;               /* 1: one frequency-integrated group */
     const double *edges;    /* [ng+1] */
     const double *centres;  /* [ng]   */
-    /* scattering: 0 = Thomson, 1 = Compton on electrons at rest */
+    /* scattering: 0 = Thomson, 1 = Compton */
     int compton;
-    const double *kn_s;     /* [ng]  sigma_KN(nu_i) / sigma_T          */
-    const double *kn_p;     /* [lmax+1][ng][ng]  Legendre moment p_l^{i->j} */
+    const double *kn_s;     /* [nt][ng]  sigma(nu_i; T_n) / sigma_T                    */
+    const double *kn_p;     /* [nt][lmax+1][ng][ng]  Legendre moment p_l^{i->j}(T_n)    */
     /* fields */
     const double *kappa;    /* [P][ng] */
     const double *sigma;    /* [P]     */
@@ -58,6 +58,12 @@ typedef struct {
     const double *mu;       /* [nmu] Gauss-Legendre nodes, ascending */
     const double *wmu;      /* [nmu] Gauss-Legendre weights          */
     const double *Y;        /* [K][NLM] real SH at the ordinates     */
+    /* electron temperature: ntemp = 0 for electrons at rest (one table);
+       else the tables above are given at ntemp nodes, log10 of the node
+       temperatures in lt_nodes (ascending), and kte [P] is the field */
+    int ntemp;
+    const double *lt_nodes;
+    const double *kte;
 } or_problem;
 
 static int nlm_of(int lmax) { return (lmax + 1) * (lmax + 1); }
@@ -248,19 +254,292 @@ int or_compton_cold(int ng, const double *edges, const double *centres, double m
     return 0;
 }
 
+/* Klein-Nishina total cross-section of a photon of energy x = h nu / (m_e c^2),
+   in units of r0^2, by the same 8-piece quadrature as or_compton_cold. */
+static double kn_total(double x, const double *gx, const double *gw, int ng)
+{
+    double tot = 0.0;
+    for (int piece = 0; piece < 8; piece++)
+        tot += kn_band_integral(x, 0, -1.0 + piece * 0.25, -1.0 + (piece + 1) * 0.25, gx, gw, ng);
+    return tot * 2.0 * M_PI;
+}
+
+/* Electrons of temperature kT (an isotropic Maxwell-Juttner distribution; not
+   part of the paper, whose electrons are at rest).  For an electron of speed
+   beta (Lorentz factor gam) moving at cosine mu_e to the incident photon
+   (direction z) and the scattered photon going out at (mu1, phi1) in the same
+   frame, with x = h nu / (m_e c^2):
+     nu1 = nu (1 - beta.Omega) / (1 - beta.Omega1 + (x / gam)(1 - mu1))
+   (energy-momentum conservation), and the scattered photons per unit solid
+   angle and unit photon path, per electron, are
+     R = (1 - beta.Omega) (dsigma/dOmega')_KN (nu1 / nu1')^2
+   with the rest-frame frequencies nu' = gam nu (1 - beta.Omega),
+   nu1' = gam nu1 (1 - beta.Omega1), the rest-frame scattering angle from the
+   invariant nu nu1 (1 - mu1) = nu' nu1' (1 - cos Theta'), the flux factor
+   (1 - beta.Omega) and the solid-angle Jacobian (nu1/nu1')^2 of the photon
+   aberration. */
+typedef struct {
+    double nu, x, beta, gam, mue, sine, cphi;
+} hot_state;
+
+static double hot_nu1(const hot_state *h, double mu1)
+{
+    double s1 = sqrt(fmax(0.0, 1.0 - mu1 * mu1));
+    double bo1 = h->beta * (h->sine * s1 * h->cphi + h->mue * mu1);
+    return h->nu * (1.0 - h->beta * h->mue) / (1.0 - bo1 + h->x / h->gam * (1.0 - mu1));
+}
+
+static double hot_rate(const hot_state *h, double mu1)
+{
+    double s1 = sqrt(fmax(0.0, 1.0 - mu1 * mu1));
+    double bo = h->beta * h->mue;
+    double bo1 = h->beta * (h->sine * s1 * h->cphi + h->mue * mu1);
+    double nu1 = h->nu * (1.0 - bo) / (1.0 - bo1 + h->x / h->gam * (1.0 - mu1));
+    double nup = h->gam * h->nu * (1.0 - bo), nu1p = h->gam * nu1 * (1.0 - bo1);
+    double omc = h->nu * nu1 * (1.0 - mu1) / (nup * nu1p);          /* 1 - cos Theta' */
+    double c = 1.0 - omc;
+    double r = nu1p / nup;
+    double dsdo = 0.5 * r * r * (1.0 / r + r - (1.0 - c * c));
+    double jac = nu1 / nu1p;
+    return (1.0 - bo) * dsdo * jac * jac;
+}
+
+/* roots in (-1, 1) of a + b mu + c sqrt(1 - mu^2) = 0: with mu = cos psi,
+   psi in (0, pi), the equation is R cos(psi - delta) = -a with
+   R = sqrt(b^2 + c^2), delta = atan2(c, b); without the square-root term it is
+   linear. */
+static int hot_roots(double a, double b, double c, double out[2])
+{
+    int n = 0;
+    if (c == 0.0) {
+        if (b != 0.0) {
+            double m = -a / b;
+            if (m > -1.0 && m < 1.0) out[n++] = m;
+        }
+        return n;
+    }
+    double R = sqrt(b * b + c * c), y = -a / R;
+    if (y < -1.0 || y > 1.0) return 0;
+    double delta = atan2(c, b), g = acos(y);
+    double cand[2] = {delta - g, delta + g};
+    for (int k = 0; k < 2; k++) {
+        double psi = cand[k];
+        if (psi > M_PI) psi -= 2.0 * M_PI;
+        if (psi < -M_PI) psi += 2.0 * M_PI;
+        if (psi > 0.0 && psi < M_PI) {
+            double m = cos(psi);
+            if (m > -1.0 && m < 1.0) out[n++] = m;
+        }
+    }
+    if (n == 2 && out[0] == out[1]) n = 1;
+    return n;
+}
+
+static int cmp_double(const void *a, const void *b)
+{
+    double x = *(const double *)a, y = *(const double *)b;
+    return (x > y) - (x < y);
+}
+
+/* Group-to-group Compton tables for electrons of temperature kT (units of the
+   edges; kT = 0: electrons at rest, the paper's kernel), same definitions as
+   or_compton_cold with the Klein-Nishina rate averaged over the electrons:
+     s[i]       = <R> integrated over all directions / sigma_T
+     p[l][i][j] = (2l+1)/2 integral of P_l(mu1) 4 pi <R>(mu1) / (s[i] sigma_T) over
+                  the mu1 where the scattered frequency lies in bin j,
+   <R>(mu1) the rate averaged over the electrons' momentum and direction and
+   over the azimuth of the scattered photon.  The averages are fixed
+   quadrature rules: momentum by 16-point Gauss-Legendre in t on [0, 6] with
+   (gam - 1) / Theta = t^2 (Theta = kT / m_e c^2; weight p gam t e^{-t^2}),
+   the electron's direction cosine by 16-point Gauss-Legendre, the scattered
+   azimuth by 12-point Gauss-Legendre on [0, pi] (the rate is even in it);
+   along mu1, every interval of [-1, 1] on which the scattered frequency stays
+   in one bin (split at the roots of nu1 = edge) takes 4 equal pieces of
+   48-point Gauss-Legendre, as the cold tables do.  At kT = 0 the average is
+   the single electron at rest.  Parity unpinned beyond the limits the tests
+   check (cold limit, normalisation, Thomson limit, mean energy exchange). */
+int or_compton_thermal(int ng, const double *edges, const double *centres, double mec2, int lmax, double kT,
+                       double *s, double *p)
+{
+    const int NQ = 48, NT = 16, NE = 16, NF = 12;
+    double gx[48], gw[48], tx[16], tw[16], ex[16], ew[16], fx[12], fw[12];
+    or_gauss_legendre(NQ, gx, gw);
+    or_gauss_legendre(NT, tx, tw);
+    or_gauss_legendre(NE, ex, ew);
+    or_gauss_legendre(NF, fx, fw);
+    double theta = kT / mec2;
+    int nt = theta > 0.0 ? NT : 1, ne = theta > 0.0 ? NE : 1, nf = theta > 0.0 ? NF : 1;
+    /* momentum nodes and normalised weights */
+    double gam_t[16], beta_t[16], wt_t[16], wsum = 0.0;
+    for (int a = 0; a < nt; a++) {
+        if (theta <= 0.0) { gam_t[a] = 1.0; beta_t[a] = 0.0; wt_t[a] = 1.0; wsum = 1.0; break; }
+        double t = 3.0 * (tx[a] + 1.0);                   /* [0, 6] */
+        double gam = 1.0 + theta * t * t;
+        double pm = sqrt(gam * gam - 1.0);
+        gam_t[a] = gam;
+        beta_t[a] = pm / gam;
+        wt_t[a] = 3.0 * tw[a] * pm * gam * t * exp(-t * t);
+        wsum += wt_t[a];
+    }
+    for (int a = 0; a < nt; a++) wt_t[a] /= wsum;
+    int L = lmax;
+    #pragma omp parallel for schedule(dynamic)
+    for (int i = 0; i < ng; i++) {
+        double nu = centres[i], x = nu / mec2;
+        double *acc = (double *)calloc((size_t)(L + 1) * ng, sizeof(double));
+        double *cut = (double *)malloc(sizeof(double) * (2 * (ng + 1) + 2));
+        double *Pl = (double *)malloc(sizeof(double) * (L + 1));
+        double sig = 0.0;                                   /* r0^2 units */
+        for (int a = 0; a < nt; a++)
+            for (int b = 0; b < ne; b++) {
+                double mue = theta > 0.0 ? ex[b] : 1.0, wmue = theta > 0.0 ? 0.5 * ew[b] : 1.0;
+                double beta = beta_t[a], gam = gam_t[a];
+                sig += wt_t[a] * wmue * (1.0 - beta * mue) * kn_total(gam * x * (1.0 - beta * mue), gx, gw, NQ);
+                for (int f = 0; f < nf; f++) {
+                    double phi = theta > 0.0 ? 0.5 * M_PI * (fx[f] + 1.0) : 0.0;
+                    double wphi = theta > 0.0 ? 0.5 * fw[f] : 1.0;      /* mean over [0, pi] */
+                    hot_state h = {nu, x, beta, gam, mue, sqrt(fmax(0.0, 1.0 - mue * mue)), cos(phi)};
+                    double w = wt_t[a] * wmue * wphi;
+                    int nc = 0;
+                    cut[nc++] = -1.0;
+                    cut[nc++] = 1.0;
+                    for (int e = 0; e <= ng; e++) {
+                        double E = edges[e];
+                        if (E <= 0.0) continue;
+                        double A = nu * (1.0 - beta * mue) - E * (1.0 + x / gam);
+                        double B = E * (x / gam - beta * mue);
+                        double C = -E * beta * h.sine * h.cphi;
+                        nc += hot_roots(A, B, C, cut + nc);
+                    }
+                    qsort(cut, nc, sizeof(double), cmp_double);
+                    for (int c = 0; c + 1 < nc; c++) {
+                        double lo = cut[c], hi = cut[c + 1];
+                        if (!(hi > lo)) continue;
+                        double nm = hot_nu1(&h, 0.5 * (lo + hi));
+                        if (nm < edges[0] || nm >= edges[ng]) continue;
+                        int j = 0;
+                        while (j < ng - 1 && nm >= edges[j + 1]) j++;
+                        for (int piece = 0; piece < 4; piece++) {
+                            double pa = lo + (hi - lo) * piece / 4.0, pb = lo + (hi - lo) * (piece + 1) / 4.0;
+                            double hh = 0.5 * (pb - pa), cc = 0.5 * (pb + pa);
+                            for (int q = 0; q < NQ; q++) {
+                                double mu1 = cc + hh * gx[q];
+                                double v = w * gw[q] * hh * hot_rate(&h, mu1);
+                                Pl[0] = 1.0;
+                                if (L >= 1) Pl[1] = mu1;
+                                for (int l = 2; l <= L; l++)
+                                    Pl[l] = ((2.0 * l - 1.0) * mu1 * Pl[l - 1] - (l - 1.0) * Pl[l - 2]) / l;
+                                for (int l = 0; l <= L; l++) acc[(long)l * ng + j] += v * Pl[l];
+                            }
+                        }
+                    }
+                }
+            }
+        s[i] = sig / (8.0 * M_PI / 3.0);
+        for (int l = 0; l <= L; l++)
+            for (int j = 0; j < ng; j++)
+                p[((long)l * ng + i) * ng + j] = (2.0 * l + 1.0) / 2.0 * 4.0 * M_PI / sig * acc[(long)l * ng + j];
+        free(acc);
+        free(cut);
+        free(Pl);
+    }
+    return 0;
+}
+
+/* Unbinned averages of the same thermal rate for one photon frequency nu:
+   out[0] = s (total / sigma_T), out[1] = mean of nu1/nu - 1 over the scattered
+   photons (the rate-weighted mean over all scattered directions). */
+int or_compton_thermal_moments(double nu, double mec2, double kT, double *out)
+{
+    const int NQ = 48, NT = 16, NE = 16, NF = 12;
+    double gx[48], gw[48], tx[16], tw[16], ex[16], ew[16], fx[12], fw[12];
+    or_gauss_legendre(NQ, gx, gw);
+    or_gauss_legendre(NT, tx, tw);
+    or_gauss_legendre(NE, ex, ew);
+    or_gauss_legendre(NF, fx, fw);
+    double theta = kT / mec2, x = nu / mec2;
+    int nt = theta > 0.0 ? NT : 1, ne = theta > 0.0 ? NE : 1, nf = theta > 0.0 ? NF : 1;
+    double wsum = 0.0, sig = 0.0, tot = 0.0, shift = 0.0;
+    for (int a = 0; a < nt; a++) {
+        double gam = 1.0, beta = 0.0, wt = 1.0;
+        if (theta > 0.0) {
+            double t = 3.0 * (tx[a] + 1.0);
+            gam = 1.0 + theta * t * t;
+            double pm = sqrt(gam * gam - 1.0);
+            beta = pm / gam;
+            wt = 3.0 * tw[a] * pm * gam * t * exp(-t * t);
+        }
+        wsum += wt;
+        for (int b = 0; b < ne; b++) {
+            double mue = theta > 0.0 ? ex[b] : 1.0, wmue = theta > 0.0 ? 0.5 * ew[b] : 1.0;
+            sig += wt * wmue * (1.0 - beta * mue) * kn_total(gam * x * (1.0 - beta * mue), gx, gw, NQ);
+            for (int f = 0; f < nf; f++) {
+                double phi = theta > 0.0 ? 0.5 * M_PI * (fx[f] + 1.0) : 0.0;
+                double wphi = theta > 0.0 ? 0.5 * fw[f] : 1.0;
+                hot_state h = {nu, x, beta, gam, mue, sqrt(fmax(0.0, 1.0 - mue * mue)), cos(phi)};
+                for (int piece = 0; piece < 8; piece++) {
+                    double pa = -1.0 + piece * 0.25, pb = pa + 0.25, hh = 0.125, cc = 0.5 * (pa + pb);
+                    for (int q = 0; q < NQ; q++) {
+                        double mu1 = cc + hh * gx[q];
+                        double v = wt * wmue * wphi * gw[q] * hh * hot_rate(&h, mu1) * 2.0 * M_PI;
+                        tot += v;
+                        shift += v * (hot_nu1(&h, mu1) / nu - 1.0);
+                    }
+                }
+            }
+        }
+    }
+    out[0] = sig / wsum / (8.0 * M_PI / 3.0);
+    out[1] = shift / tot;
+    out[2] = tot / wsum / (8.0 * M_PI / 3.0);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* S1: source function in SH space (Eqs. 10-12 and the multi-group kernel)   */
 /* ------------------------------------------------------------------------ */
 
+/* Electron-temperature bracket of point p: node n and weight w of node n + 1,
+   linear in log10 T between nodes and clamped to the node range (n = 0, w = 0
+   for electrons at rest). */
+static void temp_bracket(const or_problem *pr, long p, int *n, double *w)
+{
+    *n = 0;
+    *w = 0.0;
+    if (pr->ntemp < 2 || !pr->kte) return;
+    double lt = log10(pr->kte[p]);
+    const double *t = pr->lt_nodes;
+    int nt = pr->ntemp;
+    if (lt <= t[0]) return;
+    if (lt >= t[nt - 1]) { *n = nt - 2; *w = 1.0; return; }
+    int k = 0;
+    while (k < nt - 2 && lt >= t[k + 1]) k++;
+    *n = k;
+    *w = (lt - t[k]) / (t[k + 1] - t[k]);
+}
+
+/* scattering cross-section ratio s_g of point p (interpolated in log10 T) */
+static double kn_s_at(const or_problem *pr, long p, int g)
+{
+    int n;
+    double w;
+    temp_bracket(pr, p, &n, &w);
+    double v = pr->kn_s[(long)n * pr->ng + g];
+    if (w > 0.0) v = (1.0 - w) * v + w * pr->kn_s[(long)(n + 1) * pr->ng + g];
+    return v;
+}
+
 static double chi0_of(const or_problem *pr, long p, int g)
 {
-    double s = pr->compton ? pr->kn_s[g] : 1.0;
+    double s = pr->compton ? kn_s_at(pr, p, g) : 1.0;
     return pr->kappa[p * pr->ng + g] + pr->sigma[p] * s;
 }
 
 /* S_lm = omega chi_l/(2l+1) I_lm + T_lm with the Thomson Legendre moments
    chi_l = (1, 0, 1/2, 0, ...) of 3/4 (1 + cos^2), or, for Compton,
    S_lm^j = sigma/chi_j sum_i s_i (nu_j dnu_i)/(nu_i dnu_j) p_l^{i->j}/(2l+1) I_lm^i,
+   (with a temperature field, s_i p_l^{i->j} interpolated linearly in log10 T
+   between the node tables),
    plus the isotropic thermal term T_00 = sqrt(4 pi) kappa B / chi. */
 void or_source(const or_problem *pr, const double *I_lm, double *S_lm)
 {
@@ -283,12 +562,21 @@ void or_source(const or_problem *pr, const double *I_lm, double *S_lm)
                         double chil = (l == 0) ? 1.0 : (l == 2 ? 0.5 : 0.0);
                         v = pr->sigma[p] / chi * chil / (2.0 * l + 1.0) * I_lm[(p * G + j) * NL + q];
                     } else {
+                        /* A_l^{ji} at the node temperatures, linear in log10 T between them */
+                        int n;
+                        double wt;
+                        temp_bracket(pr, p, &n, &wt);
+                        long LG = (long)(pr->lmax + 1) * G * G;
                         for (int i = 0; i < G; i++) {
                             double dnu_i = pr->edges[i + 1] - pr->edges[i];
                             double dnu_j = pr->edges[j + 1] - pr->edges[j];
-                            double w = pr->kn_s[i] * (pr->centres[j] * dnu_i) / (pr->centres[i] * dnu_j)
-                                       * pr->kn_p[((long)l * G + i) * G + j] / (2.0 * l + 1.0);
-                            v += w * I_lm[(p * G + i) * NL + q];
+                            double f = (pr->centres[j] * dnu_i) / (pr->centres[i] * dnu_j) / (2.0 * l + 1.0);
+                            double a0 = pr->kn_s[(long)n * G + i] * pr->kn_p[n * LG + ((long)l * G + i) * G + j];
+                            double a = a0;
+                            if (wt > 0.0)
+                                a = (1.0 - wt) * a0 + wt * pr->kn_s[(long)(n + 1) * G + i]
+                                                       * pr->kn_p[(n + 1) * LG + ((long)l * G + i) * G + j];
+                            v += f * a * I_lm[(p * G + i) * NL + q];
                         }
                         v *= pr->sigma[p] / chi;
                     }

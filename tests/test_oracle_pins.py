@@ -266,6 +266,106 @@ def test_compton_source_reduces_to_thomson_at_low_energy():
 
 
 # ---------------------------------------------------------------------------
+# Compton scattering on hot electrons (a Maxwell-Juttner average of the
+# Klein-Nishina rate; not in the paper, whose electrons are at rest)
+# ---------------------------------------------------------------------------
+
+KEV_EDGES = np.exp(np.linspace(np.log(20.0), np.log(2000.0), 7))
+
+
+def test_thermal_compton_tables_reduce_to_the_cold_kernel():
+    """kT = 0 is the paper's kernel (electrons at rest, Eqs. 13-14) exactly;
+    at kT = 1e-12 keV the electrons' motion changes the tables by less than
+    1e-10."""
+    c = oracle.group_centres(KEV_EDGES, True)
+    s0, p0 = oracle.compton_cold(KEV_EDGES, c, W.MEC2_KEV, 3)
+    for kT, tol in ((0.0, 1e-14), (1e-12, 1e-10)):
+        s, p = oracle.compton_thermal(KEV_EDGES, c, W.MEC2_KEV, 3, kT)
+        assert np.abs(s - s0).max() < tol and np.abs(p - p0).max() < tol, kT
+
+
+def test_thermal_compton_rate_integrates_to_the_invariant_cross_section():
+    """Integrating the lab-frame rate of a moving electron over every
+    scattered direction gives (1 - beta.n) sigma_KN(nu') (the cross-section is
+    invariant; the flux factor counts the electrons met per unit photon path),
+    so both totals agree; and in the Thomson limit (h nu -> 0) the flux factor
+    averages to 1 over isotropic electrons at any temperature."""
+    for nu, kT in ((50.0, 10.0), (500.0, 100.0), (1e-4, 50.0)):
+        s, _, tot = oracle.compton_thermal_moments(nu, W.MEC2_KEV, kT)
+        assert abs(tot / s - 1) < 1e-7, (nu, kT)
+    for theta in (0.01, 0.1):
+        s, _, _ = oracle.compton_thermal_moments(1e-9, 1.0, theta)
+        assert abs(s - 1) < 1e-7
+
+
+def test_thermal_compton_mean_energy_exchange_nonrelativistic_limit():
+    """Mean fractional energy change per scattering (4 kT - h nu) / m_e c^2
+    for kT, h nu << m_e c^2 (Rybicki & Lightman, Eq. 7.36); the corrections are
+    of relative order kT/m_e c^2 and h nu/m_e c^2."""
+    for x, th in ((1e-4, 1e-4), (1e-4, 3e-4), (3e-4, 1e-4), (2e-5, 1e-5)):
+        shift = oracle.compton_thermal_moments(x * W.MEC2_KEV, W.MEC2_KEV, th * W.MEC2_KEV)[1]
+        assert abs(shift / (4 * th - x) - 1) < 20 * max(x, th), (x, th, shift)
+
+
+def test_thermal_compton_tables_conserve_photons_within_the_groups():
+    """Every photon scattered from a group whose reachable frequencies stay
+    inside the edges lands in some group: sum_j p_0^{i->j} = 1, and at most 1
+    near the ends of the range; s > 0."""
+    edges = np.exp(np.linspace(np.log(1e-3), np.log(1e3), 17))
+    c = oracle.group_centres(edges, True)
+    s, p = oracle.compton_thermal(edges, c, W.MEC2_KEV, 3, 10.0)
+    tot = p[0].sum(axis=1)
+    assert np.all(tot <= 1 + 1e-7) and np.all(s > 0)
+    assert np.abs(tot[4:10] - 1).max() < 1e-7
+
+
+def test_compton_source_with_a_uniform_node_temperature_uses_that_node():
+    """A uniform temperature field on one node temperature gives the source
+    of the tables at that temperature, and the extinction sigma s(T)."""
+    edges = KEV_EDGES
+    kte = 10.0 ** 1.25
+    base = dict(n=2, nz=2, lmax=3, kappa=0.3, sigma=1.7, B=0.8, edges=edges, mec2=W.MEC2_KEV, scatter="compton")
+    spec = spec_uniform(**base)
+    spec["kte"] = np.full(8, kte)
+    o = oracle.Oracle(spec)
+    assert np.allclose(o.lt_nodes, [1.25])
+    c = oracle.group_centres(edges, True)
+    s, p = oracle.compton_thermal(edges, c, W.MEC2_KEV, 3, kte)
+    I_lm = np.random.default_rng(8).normal(size=o.sh_shape())
+    S = o.source(I_lm)
+    G = len(c)
+    dnu = np.diff(edges)
+    chi = 0.3 + 1.7 * s
+    for l in range(4):
+        A = s[:, None] * (c[None, :] * dnu[:, None]) / (c[:, None] * dnu[None, :]) * p[l] / (2 * l + 1)  # [i][j]
+        for m in range(-l, l + 1):
+            q = l * l + l + m
+            ref = 1.7 / chi[None, :] * np.einsum("ij,pi->pj", A, I_lm[:, :, q])
+            if q == 0:
+                ref = ref + math.sqrt(4 * np.pi) * 0.3 * 0.8 / chi[None, :]
+            assert np.allclose(S[:, :, q], ref, rtol=1e-12, atol=1e-14)
+
+
+def test_compton_tables_interpolate_linearly_in_log_temperature():
+    """Between two node temperatures the source is the log10 T weighted mean
+    of the sources at the nodes (the tables enter linearly)."""
+    edges = KEV_EDGES
+    base = dict(n=2, nz=2, lmax=3, kappa=0.3, sigma=1.7, B=0.0, edges=edges, mec2=W.MEC2_KEV, scatter="compton")
+    lo, hi = 10.0 ** 1.25, 10.0 ** 1.375
+    spec = spec_uniform(**base)
+    spec["kte"] = np.array([lo, hi] + [10.0 ** 1.3] * 6)       # nodes 1.25, 1.375; 1.3 = 40 % of the way
+    o = oracle.Oracle(spec)
+    assert np.allclose(o.lt_nodes, [1.25, 1.375])
+    I_lm = np.random.default_rng(9).normal(size=o.sh_shape())
+    I_lm[:] = I_lm[:1]
+    S = o.source(I_lm)
+    chi = o.kappa + o.sigma[:, None] * (np.stack([o.kn_s[0], o.kn_s[1]]).T @ np.array([[1, 0, 0.6], [0, 1, 0.4]]))[:, [0, 1, 2, 2, 2, 2, 2, 2]].T
+    # the scattering part times chi / sigma is linear in the node tables
+    Ssc = S * (chi / 1.7)[:, :, None]
+    assert np.allclose(Ssc[2], 0.6 * Ssc[0] + 0.4 * Ssc[1], rtol=1e-12, atol=1e-14)
+
+
+# ---------------------------------------------------------------------------
 # Lorentz maps (Eqs. 7-8) and the invariants
 # ---------------------------------------------------------------------------
 
