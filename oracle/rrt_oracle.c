@@ -406,9 +406,10 @@ int or_compton_thermal(int ng, const double *edges, const double *centres, doubl
                     for (int e = 0; e <= ng; e++) {
                         double E = edges[e];
                         if (E <= 0.0) continue;
+                        /* nu1 = E: nu (1 - beta mu_e) = E (1 - beta.Omega1 + (x/gam)(1 - mu1)) */
                         double A = nu * (1.0 - beta * mue) - E * (1.0 + x / gam);
-                        double B = E * (x / gam - beta * mue);
-                        double C = -E * beta * h.sine * h.cphi;
+                        double B = E * (x / gam + beta * mue);
+                        double C = E * beta * h.sine * h.cphi;
                         nc += hot_roots(A, B, C, cut + nc);
                     }
                     qsort(cut, nc, sizeof(double), cmp_double);

@@ -319,6 +319,56 @@ def test_thermal_compton_tables_conserve_photons_within_the_groups():
     assert np.abs(tot[4:10] - 1).max() < 1e-7
 
 
+def test_thermal_compton_bin_fractions_by_brute_force():
+    """The scattered photons' split among the groups, checked on one incident
+    group at 100 keV against a brute-force integration written here: the same
+    electron and azimuth nodes, but along the scattering cosine a fine midpoint
+    rule that sorts each sample into its group (no band limits), for p_0 and
+    p_1 of every target group."""
+    edges = np.exp(np.linspace(np.log(1e-3), np.log(1e3), 13))
+    c = oracle.group_centres(edges, True)
+    mec2, kT, i = W.MEC2_KEV, 100.0, 10
+    s, p = oracle.compton_thermal(edges, c, mec2, 1, kT)
+    nu, x, th = c[i], c[i] / mec2, kT / mec2
+    tx, tw = np.polynomial.legendre.leggauss(16)
+    ex, ew = np.polynomial.legendre.leggauss(16)
+    fx, fw = np.polynomial.legendre.leggauss(12)
+    m = 50000
+    mu1 = -1 + (np.arange(m) + 0.5) * (2.0 / m)
+    s1 = np.sqrt(1 - mu1 ** 2)
+    acc = np.zeros((2, len(c)))
+    wsum = tot = 0.0
+    for a in range(16):
+        t = 3 * (tx[a] + 1)
+        gam = 1 + th * t * t
+        pm = math.sqrt(gam * gam - 1)
+        beta = pm / gam
+        wt = 3 * tw[a] * pm * gam * t * math.exp(-t * t)
+        wsum += wt
+        for b in range(16):
+            mue = ex[b]
+            for f in range(12):
+                cph = math.cos(0.5 * np.pi * (fx[f] + 1))
+                w = wt * 0.5 * ew[b] * 0.5 * fw[f]
+                # the scattering in the electron's rest frame, seen from the lab
+                bo, bo1 = beta * mue, beta * (math.sqrt(1 - mue * mue) * s1 * cph + mue * mu1)
+                nu1 = nu * (1 - bo) / (1 - bo1 + x / gam * (1 - mu1))
+                nup, nu1p = gam * nu * (1 - bo), gam * nu1 * (1 - bo1)
+                cos_r = 1 - nu * nu1 * (1 - mu1) / (nup * nu1p)
+                r = nu1p / nup
+                rate = (1 - bo) * 0.5 * r * r * (1 / r + r - (1 - cos_r ** 2)) * (nu1 / nu1p) ** 2
+                grp = np.searchsorted(edges, nu1, side="right") - 1
+                ok = (grp >= 0) & (grp < len(c))
+                v = w * rate * (2.0 / m)
+                tot += v.sum()
+                acc[0] += np.bincount(grp[ok], weights=v[ok], minlength=len(c))
+                acc[1] += np.bincount(grp[ok], weights=(v * mu1)[ok], minlength=len(c))
+    # normalised by the total over every direction (2 pi int R dmu1 = s sigma_T)
+    ref = np.array([0.5, 1.5])[:, None] * acc / (tot / 2.0)
+    assert abs(2 * np.pi * tot / wsum / (8 * np.pi / 3) / s[i] - 1) < 1e-6
+    assert np.abs(p[:, i, :] - ref).max() < 5e-4, (p[:, i, :], ref)
+
+
 def test_compton_source_with_a_uniform_node_temperature_uses_that_node():
     """A uniform temperature field on one node temperature gives the source
     of the tables at that temperature, and the extinction sigma s(T)."""
