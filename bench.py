@@ -347,8 +347,7 @@ def main():
         workload = "thomson_jet_32c_g16_l7_16x32"
     else:
         spec = W.compton_jet()
-        spec["kte"] = None
-        workload = "compton_jet_64c_g32_l15_16x32"
+        workload = "compton_jet_64c_g32_l15_16x32_kte10-100"
     prec = {"fp32": B.FP32, "fp64": B.FP64, "mixed": B.MIXED}[args.precision]
     esz = 8 if prec == B.FP64 else 4
     stream = torch.cuda.current_stream().cuda_stream

@@ -90,7 +90,8 @@ typedef struct rrt_problem rrt_problem;
 
 /* Create a problem: computes the ordinate set, the SH tables and, for Compton
    scattering, the Klein-Nishina group-to-group tables for electrons at rest
-   (Eqs. 13-14), and allocates the device arrays.  hip_stream: a hipStream_t on
+   (Sec. 2.3, Eqs. 13-14; built on the GPU in FP64), and allocates the device
+   arrays.  hip_stream: a hipStream_t on
    which all work is queued, or NULL for a stream owned by the library.
    Errors: RRT_E_INVALID (sizes, odd n_mu, mesh too coarse for lmax, bad edges),
    RRT_E_HBM (device memory), RRT_E_DEVICE. */
@@ -101,9 +102,17 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
 /* Comoving medium (Eq. 1 with chi = alpha + sigma): absorption kappa [P][G] >= 0,
    n_e sigma_T [P] >= 0 (scattering coefficient per unit length), thermal source
    function bnu [P][G] (emission kappa*B), flow velocity beta [P][3] with
-   |beta| < 1 or NULL for a static medium, electron temperature kte [P] which
-   must be NULL (electrons at rest, as in the paper's Compton kernel).
-   Errors: RRT_E_INVALID for NaN/negative/|beta|>=1/non-NULL kte. */
+   |beta| < 1 or NULL for a static medium, electron temperature kte [P] > 0 in
+   the units of the edges (Compton only) or NULL for electrons at rest (the
+   paper's kernel, Sec. 2.3).  With a temperature field the group-to-group
+   tables of the Klein-Nishina rate averaged over a Maxwell-Juttner electron
+   gas (an extension of Eqs. 13-14; not in the paper) are built on the GPU at
+   node temperatures log10 T_n = a + n/8 covering the field (a, b the field's
+   log10 range rounded out to eighths of a decade), and every point uses the
+   source tables A = s_i (nu_j dnu_i)/(nu_i dnu_j) p_l^{i->j}/(2l+1) and the
+   cross-section ratio s interpolated linearly in log10 T between its two
+   nodes.  Errors: RRT_E_INVALID for NaN/negative/|beta|>=1, for kte <= 0 or
+   kte with Thomson scattering; RRT_E_DEVICE if the tables fail. */
 rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *sigma,
                           const double *bnu, const double *beta, const double *kte);
 
@@ -116,6 +125,14 @@ rrt_status rrt_set_boundary(rrt_problem *pr, int face, const double *I_in);
    previous-time intensity of a time-dependent rrt_sweep, the first guess of
    rrt_solve); NULL sets it to zero. */
 rrt_status rrt_set_intensity(rrt_problem *pr, const double *I_lab);
+
+/* Compton tables in use (FP64 copies): ntemp node temperatures kT_nodes
+   [ntemp] (a single node 0 for electrons at rest), cross-section ratios
+   s [ntemp][G] (sigma(nu_i; T)/sigma_T) and source tables A
+   [ntemp][lmax+1][G][G] (row j, column i: A_l^{ji} = s_i (nu_j dnu_i) /
+   (nu_i dnu_j) p_l^{i->j} / (2l+1), Sec. 2.3).  Any output may be NULL (e.g.
+   to query ntemp first).  Errors: RRT_E_STATE for Thomson problems. */
+rrt_status rrt_get_compton_tables(const rrt_problem *pr, int *ntemp, double *kT_nodes, double *s, double *A);
 
 /* Comoving SH source S [P][G][NLM] used by the next rrt_sweep. */
 rrt_status rrt_set_source_sh(rrt_problem *pr, const double *S_lm);

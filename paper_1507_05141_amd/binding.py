@@ -76,6 +76,7 @@ def lib():
             "rrt_get_intensity_sh": [P, _dp],
             "rrt_get_intensity": [P, _dp],
             "rrt_get_sweep_intensity": [P, _dp],
+            "rrt_get_compton_tables": [P, ctypes.POINTER(I), _dp, _dp, _dp],
             "rrt_ray_trace": [P, _dp, _dp, _dp],
             "rrt_set_profiling": [P, I],
             "rrt_set_graphs": [P, I],
@@ -161,7 +162,8 @@ class Problem:
     def from_spec(cls, spec, precision=FP32, stream=None):
         """Create a problem and upload its medium and boundaries from a workload dict."""
         pr = cls(spec, precision, stream)
-        pr.set_medium(spec["kappa"], spec["sigma"], spec["bnu"], spec.get("beta"), None)
+        kte = spec.get("kte") if spec.get("scatter", "thomson") == "compton" else None
+        pr.set_medium(spec["kappa"], spec["sigma"], spec["bnu"], spec.get("beta"), kte)
         if spec.get("bc_bot") is not None:
             pr.set_boundary(0, spec["bc_bot"])
         if spec.get("bc_top") is not None:
@@ -256,6 +258,17 @@ class Problem:
 
     def sweep_intensity(self):
         return self._get(lib().rrt_get_sweep_intensity, self.lab_shape())
+
+    def compton_tables(self):
+        """(node temperatures [nt], s [nt][G], A [nt][lmax+1][G][G]) in use."""
+        nt = ctypes.c_int(0)
+        _check(lib().rrt_get_compton_tables(self._h, ctypes.byref(nt), None, None, None))
+        n = nt.value
+        nl = self.spec["lmax"] + 1
+        kT, s, A = np.zeros(n), np.zeros((n, self.G)), np.zeros((n, nl, self.G, self.G))
+        _check(lib().rrt_get_compton_tables(self._h, ctypes.byref(nt), kT.ctypes.data_as(_dp), s.ctypes.data_as(_dp),
+                                            A.ctypes.data_as(_dp)))
+        return kT, s, A
 
     def ray_trace(self, S_tilde, chi_tilde):
         s, sp = _in(S_tilde)

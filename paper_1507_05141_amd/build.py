@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librrt.so")
-SOURCES = ["csrc/rrt_kernels.hip", "csrc/rrt_api.cpp", "csrc/rrt_tables.cpp"]
+SOURCES = ["csrc/rrt_kernels.hip", "csrc/rrt_compton.hip", "csrc/rrt_api.cpp", "csrc/rrt_tables.cpp"]
 LIBS = ["-L/opt/rocm/lib", "-lrocblas"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -67,7 +67,16 @@ struct rrt_problem {
     bool own_stream = false;
     // host tables
     std::vector<double> mu, wmu, edges, centres, Y, dir;
-    std::vector<double> kn_s, kn_A, kn_p;
+    // Compton tables (FP64 host copies) at the temperature nodes kT_nodes (units of
+    // the edges; the single node 0 is the paper's electrons at rest): kn_s [nt][G],
+    // kn_A [nt][lmax+1][G][G] (row j, column i)
+    std::vector<double> kn_s, kn_A;
+    std::vector<double> kT_nodes;
+    std::vector<double> lt_nodes;                   // log10 of kT_nodes (temperature field set)
+    int *d_tnode = nullptr;                         // per point: lower temperature node
+    void *d_twt = nullptr;                          // per point: weight of the upper node
+    size_t tab_bytes = 0;                           // bytes of d_A + d_sg
+    size_t temp_bytes = 0;                          // bytes of d_tnode + d_twt
     // device tables
     double *d_dir = nullptr, *d_mu = nullptr, *d_lnc = nullptr, *d_nu3 = nullptr, *d_inv_nu3 = nullptr,
            *d_inv_dc = nullptr;
@@ -501,6 +510,7 @@ struct Engine {
         s.P = pr->P; s.G = pr->G; s.NL = pr->NL; s.compton = pr->scatter == RRT_COMPTON;
         s.chi0 = R(pr->d_chi0); s.sigma = R(pr->d_sigma); s.kappa = R(pr->d_kappa); s.bnu = R(pr->d_bnu);
         s.A = R(pr->d_A); s.Ilm = R(pr->d_Ilm); s.S = R(S);
+        s.tnode = pr->d_tnode; s.twt = R(pr->d_twt);
         prof_begin(pr, KI_SOURCE);
         const bool fused = Sold && rrt::launch_source_resid<real>(s, static_cast<const real *>(Sold), pr->d_partial,
                                                                   pr->stream);
@@ -883,6 +893,7 @@ size_t footprint(const rrt_grid *g, const rrt_groups *gr, const rrt_angles *a, i
     total += 2 * P * K * 8 * esz;                    // remap plan of a moving medium (two entries per point and ordinate)
     total += 2 * (size_t)g->nx * g->ny * K * G * esz;  // boundaries
     total += 16 * P * G + 16 * G * rrt::kResidSplit + (1 << 20);   // residual row and partial sums, tables
+    total += P * (4 + esz) + 25 * (size_t)(a->lmax + 1) * G * G * esz;  // electron-temperature brackets, node tables
     return total;
 }
 
@@ -902,6 +913,41 @@ size_t rrt_footprint_bytes(const rrt_grid *grid, const rrt_groups *groups, const
     return footprint(grid, groups, angles, precision, time_dependent, use_ng);
 }
 
+// Compton tables at the node temperatures kT (units of the edges; {0}: electrons at
+// rest), built on the GPU in FP64; the source tables A = s_i (nu_j dnu_i)/(nu_i dnu_j)
+// p_l^{i->j}/(2l+1) and s are uploaded in the working precision
+static rrt_status build_compton_tables(rrt_problem *pr, const std::vector<double> &kT)
+{
+    if (pr->kT_nodes == kT && pr->d_A) return RRT_OK;
+    const int G = pr->G, L = pr->lmax, nt = (int)kT.size();
+    std::vector<double> sv, pv;
+    const int e = rrt::compton_tables_gpu(G, pr->edges.data(), pr->centres.data(), pr->mec2, L, nt, kT.data(), sv, pv,
+                                          pr->stream);
+    if (e != 0) return fail(RRT_E_DEVICE, std::string("Compton tables: ") + hipGetErrorString((hipError_t)e));
+    std::vector<double> A((size_t)nt * (L + 1) * G * G, 0.0);
+    for (int n = 0; n < nt; ++n)
+        for (int l = 0; l <= L; ++l)
+            for (int i = 0; i < G; ++i)
+                for (int j = 0; j < G; ++j) {
+                    const double dnu_i = pr->edges[i + 1] - pr->edges[i], dnu_j = pr->edges[j + 1] - pr->edges[j];
+                    const double pl = pv[(((size_t)n * (L + 1) + l) * G + i) * G + j];
+                    A[(((size_t)n * (L + 1) + l) * G + j) * G + i] =
+                        sv[(size_t)n * G + i] * (pr->centres[j] * dnu_i) / (pr->centres[i] * dnu_j) * pl / (2.0 * l + 1.0);
+                }
+    // replace the device tables
+    pr->dev_bytes -= std::min(pr->dev_bytes, pr->tab_bytes);
+    dev_free(pr->d_A);
+    dev_free(pr->d_sg);
+    pr->tab_bytes = 0;
+    rrt_status s;
+    if ((s = alloc_upload_real(pr, &pr->d_A, A)) || (s = alloc_upload_real(pr, &pr->d_sg, sv))) return s;
+    pr->tab_bytes = (A.size() + sv.size()) * pr->esz;
+    pr->kn_s = sv;
+    pr->kn_A = A;
+    pr->kT_nodes = kT;
+    return RRT_OK;
+}
+
 void rrt_destroy(rrt_problem *pr)
 {
     if (!pr) return;
@@ -912,7 +958,7 @@ void rrt_destroy(rrt_problem *pr)
     if (pr->blas) (void)rocblas_destroy_handle(pr->blas);
     void *bufs[] = {pr->d_dir, pr->d_mu, pr->d_lnc, pr->d_nu3, pr->d_inv_nu3, pr->d_inv_dc, pr->d_geo, pr->d_taps, pr->d_order, pr->d_Yt, pr->d_WY,
                     pr->d_Y16, pr->d_WYt16,
-                    pr->d_A, pr->d_sg, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_gam, pr->d_chi0, pr->d_chilab, pr->d_plan, pr->d_chilabT, pr->d_bc[0], pr->d_bc[1],
+                    pr->d_A, pr->d_sg, pr->d_tnode, pr->d_twt, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_gam, pr->d_chi0, pr->d_chilab, pr->d_plan, pr->d_chilabT, pr->d_bc[0], pr->d_bc[1],
                     pr->d_S, pr->d_Snew, pr->d_Ilm, pr->d_co, pr->d_St, pr->d_Xt, pr->d_Ilab, pr->d_I, pr->d_Iin,
                     pr->d_acc, pr->d_chain[0], pr->d_chain[1], pr->d_chain[2], pr->d_chain[3], pr->d_partial, pr->d_red};
     for (void *b : bufs)
@@ -925,6 +971,18 @@ void rrt_destroy(rrt_problem *pr)
     for (auto e : pr->pool) (void)hipEventDestroy(e);
     if (pr->own_stream && pr->stream) (void)hipStreamDestroy(pr->stream);
     delete pr;
+}
+
+rrt_status rrt_get_compton_tables(const rrt_problem *pr, int *ntemp, double *kT_nodes, double *s, double *A)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    if (pr->scatter != RRT_COMPTON) return fail(RRT_E_STATE, "not a Compton problem");
+    const size_t nt = pr->kT_nodes.size();
+    if (ntemp) *ntemp = (int)nt;
+    if (kT_nodes) std::copy(pr->kT_nodes.begin(), pr->kT_nodes.end(), kT_nodes);
+    if (s) std::copy(pr->kn_s.begin(), pr->kn_s.end(), s);
+    if (A) std::copy(pr->kn_A.begin(), pr->kn_A.end(), A);
+    return RRT_OK;
 }
 
 rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_angles *angles, rrt_scatter scatter,
@@ -1175,9 +1233,8 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
         pr->fi.inv_nu3 = pr->d_inv_nu3;
     }
     if (scatter == RRT_COMPTON) {
-        rrt::compton_tables(G, pr->edges.data(), pr->centres.data(), pr->mec2, pr->lmax, pr->kn_s, pr->kn_A, pr->kn_p);
-        if ((s = alloc_upload_real(pr, &pr->d_A, pr->kn_A)) || (s = alloc_upload_real(pr, &pr->d_sg, pr->kn_s)))
-            return bail(s);
+        s = build_compton_tables(pr, std::vector<double>{0.0});
+        if (s) return bail(s);
     }
     // state arrays
     const size_t shb = sh_elems(pr) * pr->esz, dob = do_elems(pr) * pr->esz;
@@ -1213,9 +1270,13 @@ rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *si
 {
     if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
     if (!kappa || !sigma || !bnu) return fail(RRT_E_INVALID, "kappa, sigma and bnu are required");
-    if (kte) return fail(RRT_E_INVALID, "electron temperature fields are not supported: electrons at rest only");
-    clear_graphs(pr);
     const size_t P = pr->P, G = pr->G;
+    if (kte && pr->scatter != RRT_COMPTON)
+        return fail(RRT_E_INVALID, "an electron temperature field applies to Compton scattering only");
+    if (kte)
+        for (size_t i = 0; i < P; ++i)
+            if (!std::isfinite(kte[i]) || !(kte[i] > 0.0)) return fail(RRT_E_INVALID, "kte must be finite and > 0");
+    clear_graphs(pr);
     for (size_t i = 0; i < P * G; ++i) {
         if (!std::isfinite(kappa[i]) || kappa[i] < 0) return fail(RRT_E_INVALID, "kappa must be finite and >= 0");
         if (!std::isfinite(bnu[i])) return fail(RRT_E_INVALID, "bnu must be finite");
@@ -1266,10 +1327,63 @@ rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *si
         pr->d_chilab = nullptr;
         if ((s = pr_alloc(pr, &pr->d_chilab, nchi * pr->esz))) return s;
     }
+    // electron temperature: tables on log10 T nodes 1/8 decade apart covering the field,
+    // each point between two nodes (linear in log10 T)
+    if (pr->scatter == RRT_COMPTON) {
+        std::vector<double> nodes{0.0};
+        std::vector<double> lt;
+        if (kte) {
+            double lo = INFINITY, hi = -INFINITY;
+            for (size_t i = 0; i < P; ++i) {
+                const double v = std::log10(kte[i]);
+                lo = std::min(lo, v);
+                hi = std::max(hi, v);
+            }
+            const double a = std::floor(8.0 * lo + 1e-9) / 8.0, b = std::ceil(8.0 * hi - 1e-9) / 8.0;
+            const int nt = (int)std::lround((b - a) * 8.0) + 1;
+            nodes.assign(nt, 0.0);
+            lt.assign(nt, 0.0);
+            for (int n = 0; n < nt; ++n) {
+                lt[n] = a + n / 8.0;
+                nodes[n] = std::pow(10.0, lt[n]);
+            }
+        }
+        if ((s = build_compton_tables(pr, nodes))) return s;
+        pr->lt_nodes = lt;
+        dev_free(*reinterpret_cast<void **>(&pr->d_tnode));
+        dev_free(pr->d_twt);
+        pr->dev_bytes -= std::min(pr->dev_bytes, pr->temp_bytes);
+        pr->temp_bytes = 0;
+        if (kte && lt.size() >= 2) {
+            const int nt = (int)lt.size();
+            std::vector<int> tn(P);
+            std::vector<double> tw(P);
+            for (size_t i = 0; i < P; ++i) {
+                const double v = std::log10(kte[i]);
+                int n = 0;
+                double w = 0.0;
+                if (v >= lt[nt - 1]) {
+                    n = nt - 2;
+                    w = 1.0;
+                } else if (v > lt[0]) {
+                    while (n < nt - 2 && v >= lt[n + 1]) ++n;
+                    w = (v - lt[n]) / (lt[n + 1] - lt[n]);
+                }
+                tn[i] = n;
+                tw[i] = w;
+            }
+            if ((s = dev_alloc((void **)&pr->d_tnode, P * sizeof(int))) || (s = dev_alloc(&pr->d_twt, P * pr->esz))) return s;
+            pr->temp_bytes = P * (sizeof(int) + pr->esz);
+            pr->dev_bytes += pr->temp_bytes;
+            HIPCHK(hipMemcpyAsync(pr->d_tnode, tn.data(), P * sizeof(int), hipMemcpyHostToDevice, pr->stream));
+            if ((s = upload_real(pr, pr->d_twt, tw.data(), P))) return s;
+        }
+    }
     auto chilab = [&](auto tag) {
         using real = decltype(tag);
         rrt::launch_chi0<real>((long)P, (int)G, (const real *)pr->d_kappa, (const real *)pr->d_sigma,
-                               (const real *)pr->d_sg, (real *)pr->d_chi0, pr->stream);
+                               (const real *)pr->d_sg, pr->d_tnode, (const real *)pr->d_twt, (real *)pr->d_chi0,
+                               pr->stream);
         rrt::ChiLabArgs<real> c;
         c.P = (long)P; c.K = pr->K; c.fi = pr->fi; c.chi_grey = pr->grey_chi; c.dir = pr->d_dir;
         c.chi0 = (const real *)pr->d_chi0; c.beta = pr->d_beta; c.gam = pr->d_gam; c.out = (real *)pr->d_chilab;

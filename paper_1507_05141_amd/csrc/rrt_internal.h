@@ -6,7 +6,11 @@ namespace rrt {
 
 void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w);
 void real_sh(int lmax, double mu, double phi, double *Y);
-void compton_tables(int G, const double *edges, const double *centres, double mec2, int lmax,
-                    std::vector<double> &s, std::vector<double> &A, std::vector<double> &p);
+// Compton group-to-group tables at nt node temperatures kT (units of the edges; 0 =
+// electrons at rest), computed on the GPU in FP64 on the given HIP stream:
+// s [nt][G] (cross-section / sigma_T) and p [nt][lmax+1][G][G] (Legendre moments
+// p_l^{i->j}); returns a hipError_t value (0 on success)
+int compton_tables_gpu(int G, const double *edges, const double *centres, double mec2, int lmax, int nt,
+                       const double *kT, std::vector<double> &s, std::vector<double> &p, void *stream);
 
 }  // namespace rrt

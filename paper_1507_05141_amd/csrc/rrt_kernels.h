@@ -136,11 +136,16 @@ template <typename real> struct UnboostArgs {
     real *I0;                   // [p][g][j]
 };
 
+// Compton source tables A [nt][lmax+1][G][G] (row j, column i) at nt node
+// temperatures; with nt > 1 point p interpolates linearly between nodes
+// tnode[p] and tnode[p] + 1 with weight twt[p] on the upper one.
 template <typename real> struct SourceArgs {
     long P;
     int G, NL, compton;
     const real *chi0, *sigma, *kappa, *bnu, *A, *Ilm;
     real *S;
+    const int *tnode;           // [P] or NULL (one table)
+    const real *twt;            // [P] or NULL
 };
 
 template <typename real> void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st);
@@ -173,7 +178,9 @@ template <typename real> bool launch_source_resid(const SourceArgs<real> &a, con
 // rows holds 2 P G row sums followed by room for 2 G kResidSplit partial sums
 constexpr int kResidSplit = 64;
 template <typename real> void launch_resid_groups(long P, int G, const double *rows, double *out, hipStream_t st);
-template <typename real> void launch_chi0(long P, int G, const real *kappa, const real *sigma, const real *sg, real *chi0, hipStream_t st);
+// chi0 = kappa + sigma s_g, with s [nt][G] interpolated per point as the source tables (tnode / twt NULL: node 0)
+template <typename real> void launch_chi0(long P, int G, const real *kappa, const real *sigma, const real *sg,
+                                          const int *tnode, const real *twt, real *chi0, hipStream_t st);
 template <typename real> void launch_moments_lab(long P, int G, int K, const double *dir, const real *I, double *J, double *H, double *Kt, hipStream_t st);
 template <typename real> void launch_moments_co(long PG, int NL, int lmax, const real *Ilm, double *J, double *H, double *Kt, hipStream_t st);
 template <typename real> void launch_resid(long P, int G, int NL, const real *a, const real *b, double *partial, int nblk, double *out, hipStream_t st);

@@ -1849,6 +1849,15 @@ __global__ void __launch_bounds__(256) k_source_resid4(SourceArgs<real> a, const
 
 // Compton: one workgroup per point; its SH intensities I[i][q] (all groups) are
 // staged in LDS and S[j][q] = sigma/chi_j sum_i A_l(q)[j][i] I[i][q] + T_q
+// SH order of an expansion with nl terms
+__device__ __forceinline__ int lmax_of(int nl)
+{
+    int l = (int)sqrtf((float)nl) - 1;
+    while ((l + 1) * (l + 1) < nl) ++l;
+    while (l > 0 && l * l >= nl) --l;
+    return l;
+}
+
 template <typename real>
 __global__ void __launch_bounds__(256) k_source_compton(SourceArgs<real> a)
 {
@@ -1870,9 +1879,17 @@ __global__ void __launch_bounds__(256) k_source_compton(SourceArgs<real> a)
         const real chi = a.chi0[p * G + j];
         real v = 0;
         if (chi > real(0)) {
-            const real *__restrict__ Arow = a.A + ((long)l * G + j) * G;
+            const long LGG = (long)(a.NL > 0 ? lmax_of(a.NL) + 1 : 1) * G * G;
+            const long n = a.tnode ? a.tnode[p] : 0;
+            const real w = a.tnode ? a.twt[p] : real(0);
+            const real *__restrict__ Arow = a.A + n * LGG + ((long)l * G + j) * G;
             real acc = 0;
-            for (int i = 0; i < G; ++i) acc += Arow[i] * sI[i * NL + q];
+            if (w > real(0)) {
+                const real *__restrict__ Brow = Arow + LGG;
+                for (int i = 0; i < G; ++i) acc += ((real(1) - w) * Arow[i] + w * Brow[i]) * sI[i * NL + q];
+            } else {
+                for (int i = 0; i < G; ++i) acc += Arow[i] * sI[i * NL + q];
+            }
             v = sig / chi * acc;
             if (q == 0) v += real(3.5449077018110318) * a.kappa[p * G + j] * a.bnu[p * G + j] / chi;
         }
@@ -1891,7 +1908,8 @@ __global__ void __launch_bounds__(256) k_source_compton(SourceArgs<real> a)
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kComptonMfmaThreads = 512;
 
-__global__ void __launch_bounds__(kComptonMfmaThreads, 4) k_source_compton_mfma(SourceArgs<float> a, int lmax)
+template <bool TEMP>
+__global__ void __launch_bounds__(kComptonMfmaThreads, TEMP ? 2 : 4) k_source_compton_mfma(SourceArgs<float> a, int lmax)
 {
     typedef float P4 __attribute__((ext_vector_type(4)));
     constexpr int RS = 256;                                // LDS row stride (the largest NL), 32 rows
@@ -1904,19 +1922,33 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, 4) k_source_compton_mfma(
     const int n = lane & 31, kh = lane >> 5;               // B / C column, K half
     // rows G..31 stay zero: they meet zero columns of A
     for (int i = G * RS + tid; i < 32 * RS; i += kComptonMfmaThreads) sI[i] = 0.0f;
-    // A_l[m][k] for this wave's orders: lane holds m = n, k = 2 ks + kh
-    float Areg[2][16];
+    // A_l[m][k] for this wave's orders: lane holds m = n, k = 2 ks + kh.  With
+    // temperature nodes the lane holds the lower node's table (A0) and the
+    // difference to the upper one (Ad) of the bracket in use, reloaded when a
+    // point's bracket differs (points come in order, and a smooth temperature
+    // field changes bracket rarely); a point's table is A0 + w Ad.
+    const long LGG = (long)(lmax + 1) * G * G;
+    float A0[2][16], Ad[2][TEMP ? 16 : 1];
+    int cur = -1;
+    float w = 0.0f;
+    auto load_tables = [&](int node) {
 #pragma unroll
-    for (int t = 0; t < 2; ++t) {
-        const int l = wave + 8 * t;
+        for (int t = 0; t < 2; ++t) {
+            const int l = wave + 8 * t;
 #pragma unroll
-        for (int ks = 0; ks < 16; ++ks) {
-            const int k = 2 * ks + kh;
-            Areg[t][ks] = (l <= lmax && n < G && k < G) ? a.A[((long)l * G + n) * G + k] : 0.0f;
+            for (int ks = 0; ks < 16; ++ks) {
+                const int k = 2 * ks + kh;
+                const bool in = l <= lmax && n < G && k < G;
+                const long o = node * LGG + ((long)l * G + n) * G + k;
+                A0[t][ks] = in ? a.A[o] : 0.0f;
+                if (TEMP) Ad[t][ks] = in ? a.A[o + LGG] - A0[t][ks] : 0.0f;
+            }
         }
-    }
-    // the table must have arrived before the loop (keeps the loop free of waits on it)
-    __builtin_amdgcn_s_waitcnt(0);
+        cur = node;
+    };
+    // contiguous points per workgroup
+    const long chunk = (a.P + gridDim.x - 1) / gridDim.x;
+    const long pbeg = (long)blockIdx.x * chunk, pend = min(a.P, pbeg + chunk);
     constexpr int kPre = 4;                                // 16-byte loads per thread and point (G NL <= 8192)
     P4 pre[kPre];
     float pchi = 0.0f, pkap = 0.0f, pbnu = 0.0f, psig = 0.0f;
@@ -1934,9 +1966,14 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, 4) k_source_compton_mfma(
             psig = a.sigma[p];
         }
     };
-    long p = blockIdx.x;
-    if (p < a.P) fetch(p);
-    for (; p < a.P; p += gridDim.x) {
+    long p = pbeg;
+    if (p < pend) fetch(p);
+    for (; p < pend; ++p) {
+        {
+            const int node = TEMP ? a.tnode[p] : 0;
+            if (TEMP) w = a.twt[p];
+            if (node != cur) load_tables(node);
+        }
 #pragma unroll
         for (int u = 0; u < kPre; ++u) {
             const int i = tid + u * kComptonMfmaThreads;
@@ -1950,7 +1987,7 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, 4) k_source_compton_mfma(
             sF[tid] = on ? psig / pchi : 0.0f;
             sT[tid] = on ? 3.5449077018110318f * pkap * pbnu / pchi : 0.0f;
         }
-        if (p + gridDim.x < a.P) fetch(p + gridDim.x);
+        if (p + 1 < pend) fetch(p + 1);
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
@@ -1970,7 +2007,9 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, 4) k_source_compton_mfma(
 #pragma unroll
             for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
 #pragma unroll
-            for (int ks = 0; ks < 16; ++ks) acc = __builtin_amdgcn_mfma_f32_32x32x2f32(Areg[t][ks], b[ks], acc, 0, 0, 0);
+            for (int ks = 0; ks < 16; ++ks)
+                acc = __builtin_amdgcn_mfma_f32_32x32x2f32(TEMP ? A0[t][ks] + w * Ad[t][ks % (TEMP ? 16 : 1)] : A0[t][ks],
+                                                           b[ks], acc, 0, 0, 0);
             // element (m, n) sits in register r of lane n + 32 ((m / 4) % 2), r = 4 (m / 8) + m % 4;
             // it overwrites the intensity it replaces (this wave's own columns, already read)
             if (n < nq) {
@@ -2003,13 +2042,25 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, 4) k_source_compton_mfma(
 // chi0 = kappa + sigma * s_g
 template <typename real>
 __global__ void k_chi0(long P, int G, const real *__restrict__ kappa, const real *__restrict__ sigma,
-                       const real *__restrict__ sg, real *__restrict__ chi0)
+                       const real *__restrict__ sg, const int *__restrict__ tnode, const real *__restrict__ twt,
+                       real *__restrict__ chi0)
 {
     const long idx = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= P * G) return;
     const long p = idx / G;
     const int g = (int)(idx - p * G);
-    chi0[idx] = kappa[idx] + sigma[p] * (sg ? sg[g] : real(1));
+    real s = real(1);
+    if (sg) {
+        if (tnode) {
+            const long n = tnode[p];
+            const real w = twt[p];
+            s = sg[n * G + g];
+            if (w > real(0)) s = (real(1) - w) * s + w * sg[(n + 1) * G + g];
+        } else {
+            s = sg[g];
+        }
+    }
+    chi0[idx] = kappa[idx] + sigma[p] * s;
 }
 
 // ---------------------------------------------------------------------------
@@ -2579,9 +2630,12 @@ void launch_source(const SourceArgs<real> &a, hipStream_t st)
         while ((lmax + 1) * (lmax + 1) < a.NL) ++lmax;
         if (sizeof(real) == 4 && a.G <= 32 && lmax <= 15 && a.NL % 4 == 0) {
             const unsigned nb = (unsigned)std::min<long>(a.P, 2048);
-            hipLaunchKernelGGL(k_source_compton_mfma, dim3(nb), dim3(kComptonMfmaThreads),
-                               sizeof(float) * (32 * 256 + 2 * (size_t)a.G), st,
-                               *reinterpret_cast<const SourceArgs<float> *>(&a), lmax);
+            const SourceArgs<float> &af = *reinterpret_cast<const SourceArgs<float> *>(&a);
+            const size_t sm = sizeof(float) * (32 * 256 + 2 * (size_t)a.G);
+            if (a.tnode)
+                hipLaunchKernelGGL(k_source_compton_mfma<true>, dim3(nb), dim3(kComptonMfmaThreads), sm, st, af, lmax);
+            else
+                hipLaunchKernelGGL(k_source_compton_mfma<false>, dim3(nb), dim3(kComptonMfmaThreads), sm, st, af, lmax);
             return;
         }
         const unsigned nb = (unsigned)(8 * ((a.P + 7) / 8));
@@ -2591,9 +2645,11 @@ void launch_source(const SourceArgs<real> &a, hipStream_t st)
     }
 }
 template <typename real>
-void launch_chi0(long P, int G, const real *kappa, const real *sigma, const real *sg, real *chi0, hipStream_t st)
+void launch_chi0(long P, int G, const real *kappa, const real *sigma, const real *sg, const int *tnode, const real *twt,
+                 real *chi0, hipStream_t st)
 {
-    hipLaunchKernelGGL(k_chi0<real>, dim3(blocks_for(P * G, 256)), dim3(256), 0, st, P, G, kappa, sigma, sg, chi0);
+    hipLaunchKernelGGL(k_chi0<real>, dim3(blocks_for(P * G, 256)), dim3(256), 0, st, P, G, kappa, sigma, sg, tnode,
+                       twt, chi0);
 }
 template <typename real>
 void launch_moments_lab(long P, int G, int K, const double *dir, const real *I, double *J, double *H, double *Kt, hipStream_t st)
@@ -2791,7 +2847,8 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_sh2do_f16<2, 16>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<4>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<8, 8>),
-                         reinterpret_cast<const void *>(&k_source_compton_mfma),
+                         reinterpret_cast<const void *>(&k_source_compton_mfma<false>),
+                         reinterpret_cast<const void *>(&k_source_compton_mfma<true>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<1, 1, 16>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<1, 2, 16>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<1, 4, 16>),
@@ -2823,7 +2880,8 @@ hipError_t set_lds_limits(size_t bytes)
     template void launch_source<real>(const SourceArgs<real> &, hipStream_t);                                   \
     template bool launch_source_resid<real>(const SourceArgs<real> &, const real *, double *, hipStream_t);     \
     template void launch_resid_groups<real>(long, int, const double *, double *, hipStream_t);                  \
-    template void launch_chi0<real>(long, int, const real *, const real *, const real *, real *, hipStream_t);  \
+    template void launch_chi0<real>(long, int, const real *, const real *, const real *, const int *, const real *,   \
+                                    real *, hipStream_t);  \
     template void launch_moments_lab<real>(long, int, int, const double *, const real *, double *, double *,    \
                                            double *, hipStream_t);                                              \
     template void launch_moments_co<real>(long, int, int, const real *, double *, double *, double *,           \

@@ -1,7 +1,6 @@
-// Host-side FP64 tables of the library: ordinate quadrature, real spherical
-// harmonics on the ordinates and the Klein-Nishina group-to-group tables.
-// Built once per problem (rrt_create); uploaded to the device in the working
-// precision.
+// Host-side FP64 tables of the library: ordinate quadrature and real
+// spherical harmonics on the ordinates.  Built once per problem (rrt_create);
+// uploaded to the device in the working precision.
 #include "rrt_internal.h"
 
 #include <cmath>
@@ -83,91 +82,6 @@ void real_sh(int lmax, double mu, double phi, double *Y)
             } else {
                 Y[l * l + l + m] = p * cm;
                 Y[l * l + l - m] = p * sm;
-            }
-        }
-    }
-}
-
-// Klein-Nishina dsigma/dOmega / r0^2 with the scattered-to-incident frequency
-// ratio entering squared (the textbook Klein-Nishina formula).
-static double kn_cross(double x, double mu)
-{
-    const double r = 1.0 / (1.0 + x * (1.0 - mu));
-    return 0.5 * r * r * (r + 1.0 / r - (1.0 - mu * mu));
-}
-
-static double legendre(int l, double t)
-{
-    double a = 1.0, b = t;
-    if (l == 0) return a;
-    for (int k = 2; k <= l; ++k) {
-        double c = ((2 * k - 1) * t * b - (k - 1) * a) / k;
-        a = b;
-        b = c;
-    }
-    return b;
-}
-
-// Composite 24-point Gauss-Legendre (16 panels) of kn_cross(x, mu) P_l(mu) for
-// l = 0..lmax over [lo, hi]; out[l] accumulates.
-static void kn_moments(double x, double lo, double hi, int lmax, const std::vector<double> &gx,
-                       const std::vector<double> &gw, double *out)
-{
-    const int panels = 16;
-    const double h = (hi - lo) / panels;
-    for (int pnl = 0; pnl < panels; ++pnl) {
-        const double a = lo + pnl * h, c = a + 0.5 * h;
-        for (size_t i = 0; i < gx.size(); ++i) {
-            const double mu = c + 0.5 * h * gx[i];
-            const double f = kn_cross(x, mu) * gw[i] * 0.5 * h;
-            double p0 = 1.0, p1 = mu;
-            out[0] += f;
-            if (lmax >= 1) out[1] += f * mu;
-            for (int l = 2; l <= lmax; ++l) {
-                double p2 = ((2 * l - 1) * mu * p1 - (l - 1) * p0) / l;
-                out[l] += f * p2;
-                p0 = p1;
-                p1 = p2;
-            }
-        }
-    }
-}
-
-// Multi-group Compton scattering on electrons at rest with photons at the bin
-// centres.  s[i] = sigma_KN(nu_i)/sigma_T; the source coefficient of Legendre
-// order l from group i into group j is
-//   A[l][j][i] = s_i (nu_j dnu_i)/(nu_i dnu_j) p_l^{i->j} / (2l+1),
-// where p^{i->j}(mu) = 4 pi dsigma/dOmega(nu_i, mu) / sigma_KN(nu_i) on the
-// scattering cosines whose scattered frequency nu_i/(1 + x_i (1 - mu)) lies in
-// bin j, and p_l = (2l+1)/2 int p P_l dmu.
-void compton_tables(int G, const double *edges, const double *centres, double mec2, int lmax,
-                    std::vector<double> &s, std::vector<double> &A, std::vector<double> &p_out)
-{
-    std::vector<double> gx, gw;
-    gauss_legendre(24, gx, gw);
-    s.assign(G, 0.0);
-    A.assign((size_t)(lmax + 1) * G * G, 0.0);
-    p_out.assign((size_t)(lmax + 1) * G * G, 0.0);
-    std::vector<double> mom(lmax + 1);
-    for (int i = 0; i < G; ++i) {
-        const double nu = centres[i], x = nu / mec2;
-        std::fill(mom.begin(), mom.end(), 0.0);
-        kn_moments(x, -1.0, 1.0, 0, gx, gw, mom.data());
-        const double sig = 2.0 * kPi * mom[0];           // r0^2 units
-        s[i] = sig / (8.0 * kPi / 3.0);
-        for (int j = 0; j < G; ++j) {
-            // cosine of the scattering angle that lands exactly on a frequency
-            auto mu_of = [&](double e) { return e > 0.0 ? 1.0 - (nu / e - 1.0) / x : -2.0; };
-            double lo = std::fmax(-1.0, mu_of(edges[j]));
-            double hi = std::fmin(1.0, mu_of(edges[j + 1]));
-            if (!(hi > lo)) continue;
-            std::fill(mom.begin(), mom.end(), 0.0);
-            kn_moments(x, lo, hi, lmax, gx, gw, mom.data());
-            for (int l = 0; l <= lmax; ++l) {
-                const double pl = (2.0 * l + 1.0) * 0.5 * 4.0 * kPi / sig * mom[l];
-                p_out[((size_t)l * G + i) * G + j] = pl;
-                const double dnu_i = edges[i + 1] - edges[i], dnu_j = edges[j + 1] - edges[j];
-                A[((size_t)l * G + j) * G + i] = s[i] * (centres[j] * dnu_i) / (centres[i] * dnu_j) * pl / (2.0 * l + 1.0);
             }
         }
     }

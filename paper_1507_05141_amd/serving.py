@@ -40,7 +40,6 @@ def request_spec(gen, sizes=(16, 24, 32), groups=(4, 8, 16), lmaxes=(3, 7)):
         kind = "thomson"
     else:
         spec = W.compton_jet(n=n, ng=G, lmax=L, nmu=nmu, nphi=nphi, gamma_max=gmax, seed=seed, e_hi=200.0)
-        spec["kte"] = None
         kind = "compton"
     spec["sigma"] = np.full(n ** 3, sig)
     meta = {"n": n, "G": G, "lmax": L, "gamma_max": gmax, "sigma": sig, "scatter": kind}
