@@ -126,6 +126,15 @@ rrt_status rrt_set_boundary(rrt_problem *pr, int face, const double *I_in);
    rrt_solve); NULL sets it to zero. */
 rrt_status rrt_set_intensity(rrt_problem *pr, const double *I_lab);
 
+/* Frequency-integrated moments of the same fields as rrt_get_moments, reduced
+   on the device in FP64 (X_tot = sum_g dnu_g X_g with the group widths, 1 for
+   a grey group; Sec. 4 and the abstract: the Eddington tensor is what the
+   method hands on), and the Eddington tensor f = K_tot / J_tot (0 where
+   J_tot = 0): out [P][16] = J, H (x, y, z), K (xx, yy, zz, xy, xz, yz),
+   f (same order).  Uses the problem's own moment buffer (no allocation).
+   Errors: RRT_E_INVALID for NULL or an unknown frame. */
+rrt_status rrt_get_moments_integrated(rrt_problem *pr, rrt_frame frame, double *out);
+
 /* Compton tables in use (FP64 copies): ntemp node temperatures kT_nodes
    [ntemp] (a single node 0 for electrons at rest), cross-section ratios
    s [ntemp][G] (sigma(nu_i; T)/sigma_T) and source tables A
@@ -167,7 +176,9 @@ rrt_status rrt_advance(rrt_problem *pr, double dt, int nsteps, int scheme, doubl
 /* Moments per point and group: lab frame by ordinate quadrature of the
    intensity state, comoving frame from the l <= 2 SH coefficients of the last
    comoving intensity: J = int I/4pi, H = int n I/4pi, K = int n n I/4pi; the
-   Eddington tensor is K/J.  Reduced in FP64.  Any output pointer may be NULL. */
+   Eddington tensor is K/J.  Reduced in FP64 into the problem's moment buffer
+   (allocated with the problem and counted in its device bytes: no allocation
+   per call).  Any output pointer may be NULL. */
 rrt_status rrt_get_moments(rrt_problem *pr, rrt_frame frame, double *J, double *H, double *K);
 
 rrt_status rrt_get_source_sh(rrt_problem *pr, double *S_lm);        /* [P][G][NLM] */

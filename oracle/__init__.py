@@ -296,6 +296,18 @@ class Oracle:
         _load().or_moments_comoving(self._ref, _ptr(I_lm), _ptr(J), _ptr(H), _ptr(Kt))
         return J, H, Kt
 
+    def integrated(self, J, H, Kt):
+        """Frequency integrals X_tot = sum_g dnu_g X_g of per-group moments (a grey
+        group counts once) and the Eddington tensor f = K_tot / J_tot (0 where
+        J_tot = 0)."""
+        dnu = np.ones(1) if self.grey else np.diff(self.edges)
+        Jt = np.einsum("pg,g->p", J, dnu)
+        Ht = np.einsum("pgc,g->pc", H, dnu)
+        Kt_ = np.einsum("pgc,g->pc", Kt, dnu)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            f = np.where(Jt[:, None] != 0, Kt_ / np.where(Jt[:, None] != 0, Jt[:, None], 1.0), 0.0)
+        return Jt, Ht, Kt_, f
+
     def sweep(self, S_lm, I_prev=None, inv_cdt=0.0):
         """One source iteration: SH->DO, boost + time terms, ray trace, inverse
         boost, DO->SH, new source, residual.  Returns (I_lab, I_lm, S_new, r)."""

@@ -77,6 +77,7 @@ def lib():
             "rrt_get_intensity": [P, _dp],
             "rrt_get_sweep_intensity": [P, _dp],
             "rrt_get_compton_tables": [P, ctypes.POINTER(I), _dp, _dp, _dp],
+            "rrt_get_moments_integrated": [P, I, _dp],
             "rrt_ray_trace": [P, _dp, _dp, _dp],
             "rrt_set_profiling": [P, I],
             "rrt_set_graphs": [P, I],
@@ -241,6 +242,12 @@ class Problem:
         K = np.zeros((self.P, self.G, 6))
         _check(lib().rrt_get_moments(self._h, frame, J.ctypes.data_as(_dp), H.ctypes.data_as(_dp), K.ctypes.data_as(_dp)))
         return J, H, K
+
+    def moments_integrated(self, frame=FRAME_LAB):
+        """Frequency-integrated J [P], H [P][3], K [P][6] and f = K/J [P][6]."""
+        out = np.zeros((self.P, 16))
+        _check(lib().rrt_get_moments_integrated(self._h, frame, out.ctypes.data_as(_dp)))
+        return out[:, 0], out[:, 1:4], out[:, 4:10], out[:, 10:16]
 
     def _get(self, fn, shape):
         out = np.zeros(shape)

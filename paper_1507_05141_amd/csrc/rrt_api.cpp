@@ -74,6 +74,7 @@ struct rrt_problem {
     std::vector<double> kT_nodes;
     std::vector<double> lt_nodes;                   // log10 of kT_nodes (temperature field set)
     int *d_tnode = nullptr;                         // per point: lower temperature node
+    int *d_torder = nullptr;                        // the points ordered by their lower node
     void *d_twt = nullptr;                          // per point: weight of the upper node
     size_t tab_bytes = 0;                           // bytes of d_A + d_sg
     size_t temp_bytes = 0;                          // bytes of d_tnode + d_twt
@@ -106,6 +107,8 @@ struct rrt_problem {
     void *d_Iin = nullptr, *d_acc = nullptr;
     void *d_chain[4] = {nullptr, nullptr, nullptr, nullptr};
     double *d_partial = nullptr, *d_red = nullptr;
+    double *d_mom = nullptr;                        // moments: J, H, K per group, then per point J, H, K, f integrated
+    double *d_dnu = nullptr;                        // group widths (1 for a grey group)
     double *h_red = nullptr;                        // pinned host copy of the per-group residual sums
     int nblk_red = 0;
     bool medium_set = false;
@@ -510,7 +513,7 @@ struct Engine {
         s.P = pr->P; s.G = pr->G; s.NL = pr->NL; s.compton = pr->scatter == RRT_COMPTON;
         s.chi0 = R(pr->d_chi0); s.sigma = R(pr->d_sigma); s.kappa = R(pr->d_kappa); s.bnu = R(pr->d_bnu);
         s.A = R(pr->d_A); s.Ilm = R(pr->d_Ilm); s.S = R(S);
-        s.tnode = pr->d_tnode; s.twt = R(pr->d_twt);
+        s.tnode = pr->d_tnode; s.twt = R(pr->d_twt); s.torder = pr->d_torder;
         prof_begin(pr, KI_SOURCE);
         const bool fused = Sold && rrt::launch_source_resid<real>(s, static_cast<const real *>(Sold), pr->d_partial,
                                                                   pr->stream);
@@ -736,36 +739,44 @@ struct Engine {
         return s ? s : pr->sv.st;
     }
 
-    rrt_status moments(rrt_frame frame, double *J, double *H, double *Kt)
+    // moments of the lab intensity state or the comoving SH intensity into the problem's
+    // moment buffer (per group J, H, K, then the frequency-integrated ones)
+    rrt_status moments_launch(rrt_frame frame)
     {
         const size_t pg = (size_t)pr->P * pr->G;
-        double *dJ = nullptr, *dH = nullptr, *dK = nullptr;
-        rrt_status s;
-        if ((s = dev_alloc((void **)&dJ, pg * 8)) || (s = dev_alloc((void **)&dH, pg * 24)) ||
-            (s = dev_alloc((void **)&dK, pg * 48))) {
-            if (dJ) (void)hipFree(dJ);
-            if (dH) (void)hipFree(dH);
-            return s;
-        }
+        double *dJ = pr->d_mom, *dH = dJ + pg, *dK = dH + 3 * pg;
         prof_begin(pr, KI_MOMENTS);
         if (frame == RRT_FRAME_LAB)
             rrt::launch_moments_lab<real>(pr->P, pr->G, pr->K, pr->d_dir, R(pr->d_I), dJ, dH, dK, pr->stream);
         else
             rrt::launch_moments_co<real>((long)pg, pr->NL, pr->lmax, R(pr->d_Ilm), dJ, dH, dK, pr->stream);
+        rrt::launch_moments_integrate(pr->P, pr->G, pr->d_dnu, dJ, dH, dK, dK + 6 * pg, pr->stream);
         prof_end(pr, KI_MOMENTS);
-        s = check_launch();
-        if (!s) {
-            hipError_t e = hipSuccess;
-            if (J && e == hipSuccess) e = hipMemcpyAsync(J, dJ, pg * 8, hipMemcpyDeviceToHost, pr->stream);
-            if (H && e == hipSuccess) e = hipMemcpyAsync(H, dH, pg * 24, hipMemcpyDeviceToHost, pr->stream);
-            if (Kt && e == hipSuccess) e = hipMemcpyAsync(Kt, dK, pg * 48, hipMemcpyDeviceToHost, pr->stream);
-            if (e == hipSuccess) e = hipStreamSynchronize(pr->stream);
-            if (e != hipSuccess) s = fail(RRT_E_DEVICE, std::string("moments download: ") + hipGetErrorString(e));
-        }
-        (void)hipFree(dJ);
-        (void)hipFree(dH);
-        (void)hipFree(dK);
-        return s;
+        return check_launch();
+    }
+    rrt_status moments(rrt_frame frame, double *J, double *H, double *Kt)
+    {
+        const size_t pg = (size_t)pr->P * pr->G;
+        rrt_status s = moments_launch(frame);
+        if (s) return s;
+        const double *dJ = pr->d_mom, *dH = dJ + pg, *dK = dH + 3 * pg;
+        hipError_t e = hipSuccess;
+        if (J && e == hipSuccess) e = hipMemcpyAsync(J, dJ, pg * 8, hipMemcpyDeviceToHost, pr->stream);
+        if (H && e == hipSuccess) e = hipMemcpyAsync(H, dH, pg * 24, hipMemcpyDeviceToHost, pr->stream);
+        if (Kt && e == hipSuccess) e = hipMemcpyAsync(Kt, dK, pg * 48, hipMemcpyDeviceToHost, pr->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(pr->stream);
+        if (e != hipSuccess) return fail(RRT_E_DEVICE, std::string("moments download: ") + hipGetErrorString(e));
+        return RRT_OK;
+    }
+    rrt_status moments_integrated(rrt_frame frame, double *out)
+    {
+        const size_t pg = (size_t)pr->P * pr->G;
+        rrt_status s = moments_launch(frame);
+        if (s) return s;
+        hipError_t e = hipMemcpyAsync(out, pr->d_mom + 10 * pg, (size_t)pr->P * 16 * 8, hipMemcpyDeviceToHost, pr->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(pr->stream);
+        if (e != hipSuccess) return fail(RRT_E_DEVICE, std::string("moments download: ") + hipGetErrorString(e));
+        return RRT_OK;
     }
 
     rrt_status advance(double dt, int nsteps, int scheme, double tol, int max_iter, int use_ng, int *iters, double *res)
@@ -893,7 +904,8 @@ size_t footprint(const rrt_grid *g, const rrt_groups *gr, const rrt_angles *a, i
     total += 2 * P * K * 8 * esz;                    // remap plan of a moving medium (two entries per point and ordinate)
     total += 2 * (size_t)g->nx * g->ny * K * G * esz;  // boundaries
     total += 16 * P * G + 16 * G * rrt::kResidSplit + (1 << 20);   // residual row and partial sums, tables
-    total += P * (4 + esz) + 25 * (size_t)(a->lmax + 1) * G * G * esz;  // electron-temperature brackets, node tables
+    total += P * (8 + esz) + 25 * (size_t)(a->lmax + 1) * G * G * esz;  // electron-temperature brackets, node tables
+    total += (P * G * 10 + P * 16) * 8;              // moment buffer
     return total;
 }
 
@@ -958,9 +970,9 @@ void rrt_destroy(rrt_problem *pr)
     if (pr->blas) (void)rocblas_destroy_handle(pr->blas);
     void *bufs[] = {pr->d_dir, pr->d_mu, pr->d_lnc, pr->d_nu3, pr->d_inv_nu3, pr->d_inv_dc, pr->d_geo, pr->d_taps, pr->d_order, pr->d_Yt, pr->d_WY,
                     pr->d_Y16, pr->d_WYt16,
-                    pr->d_A, pr->d_sg, pr->d_tnode, pr->d_twt, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_gam, pr->d_chi0, pr->d_chilab, pr->d_plan, pr->d_chilabT, pr->d_bc[0], pr->d_bc[1],
+                    pr->d_A, pr->d_sg, pr->d_tnode, pr->d_twt, pr->d_torder, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_gam, pr->d_chi0, pr->d_chilab, pr->d_plan, pr->d_chilabT, pr->d_bc[0], pr->d_bc[1],
                     pr->d_S, pr->d_Snew, pr->d_Ilm, pr->d_co, pr->d_St, pr->d_Xt, pr->d_Ilab, pr->d_I, pr->d_Iin,
-                    pr->d_acc, pr->d_chain[0], pr->d_chain[1], pr->d_chain[2], pr->d_chain[3], pr->d_partial, pr->d_red};
+                    pr->d_acc, pr->d_chain[0], pr->d_chain[1], pr->d_chain[2], pr->d_chain[3], pr->d_partial, pr->d_red, pr->d_mom, pr->d_dnu};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (int i = 0; i < KI_N; ++i)
@@ -1254,8 +1266,15 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
     if ((s = pr_alloc(pr, (void **)&pr->d_partial,
                        std::max((size_t)pr->nblk_red * std::max(2 * G, 5),
                                 2 * (size_t)pr->P * G + 2 * (size_t)G * rrt::kResidSplit) * 8)) ||
-        (s = pr_alloc(pr, (void **)&pr->d_red, (size_t)std::max(2 * G, 5) * 8)))
+        (s = pr_alloc(pr, (void **)&pr->d_red, (size_t)std::max(2 * G, 5) * 8)) ||
+        (s = pr_alloc(pr, (void **)&pr->d_mom, ((size_t)pr->P * G * 10 + (size_t)pr->P * 16) * 8)))
         return bail(s);
+    {
+        std::vector<double> dnu(G, 1.0);
+        if (!pr->grey)
+            for (int g = 0; g < G; ++g) dnu[g] = pr->edges[g + 1] - pr->edges[g];
+        if ((s = upload_double(pr, (void **)&pr->d_dnu, dnu))) return bail(s);
+    }
     if (hipHostMalloc((void **)&pr->h_red, (size_t)std::max(2 * G, 5) * 8, hipHostMallocDefault) != hipSuccess) {
         pr->h_red = nullptr;
         return bail(fail(RRT_E_HOST_OOM, "pinned residual buffer"));
@@ -1351,6 +1370,7 @@ rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *si
         if ((s = build_compton_tables(pr, nodes))) return s;
         pr->lt_nodes = lt;
         dev_free(*reinterpret_cast<void **>(&pr->d_tnode));
+        dev_free(*reinterpret_cast<void **>(&pr->d_torder));
         dev_free(pr->d_twt);
         pr->dev_bytes -= std::min(pr->dev_bytes, pr->temp_bytes);
         pr->temp_bytes = 0;
@@ -1372,10 +1392,18 @@ rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *si
                 tn[i] = n;
                 tw[i] = w;
             }
-            if ((s = dev_alloc((void **)&pr->d_tnode, P * sizeof(int))) || (s = dev_alloc(&pr->d_twt, P * pr->esz))) return s;
-            pr->temp_bytes = P * (sizeof(int) + pr->esz);
+            // the points ordered by bracket (counting sort, stable)
+            std::vector<int> order(P), start(nt + 1, 0);
+            for (size_t i = 0; i < P; ++i) ++start[tn[i] + 1];
+            for (int n = 0; n < nt; ++n) start[n + 1] += start[n];
+            for (size_t i = 0; i < P; ++i) order[start[tn[i]]++] = (int)i;
+            if ((s = dev_alloc((void **)&pr->d_tnode, P * sizeof(int))) || (s = dev_alloc(&pr->d_twt, P * pr->esz)) ||
+                (s = dev_alloc((void **)&pr->d_torder, P * sizeof(int))))
+                return s;
+            pr->temp_bytes = P * (2 * sizeof(int) + pr->esz);
             pr->dev_bytes += pr->temp_bytes;
             HIPCHK(hipMemcpyAsync(pr->d_tnode, tn.data(), P * sizeof(int), hipMemcpyHostToDevice, pr->stream));
+            HIPCHK(hipMemcpyAsync(pr->d_torder, order.data(), P * sizeof(int), hipMemcpyHostToDevice, pr->stream));
             if ((s = upload_real(pr, pr->d_twt, tw.data(), P))) return s;
         }
     }
@@ -1534,6 +1562,13 @@ rrt_status rrt_get_moments(rrt_problem *pr, rrt_frame frame, double *J, double *
     if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
     if (frame != RRT_FRAME_LAB && frame != RRT_FRAME_COMOVING) return fail(RRT_E_INVALID, "unknown frame");
     return dispatch(pr, [&](auto &e) { return e.moments(frame, J, H, K); });
+}
+
+rrt_status rrt_get_moments_integrated(rrt_problem *pr, rrt_frame frame, double *out)
+{
+    if (!pr || !out) return fail(RRT_E_INVALID, "NULL argument");
+    if (frame != RRT_FRAME_LAB && frame != RRT_FRAME_COMOVING) return fail(RRT_E_INVALID, "unknown frame");
+    return dispatch(pr, [&](auto &e) { return e.moments_integrated(frame, out); });
 }
 
 rrt_status rrt_get_source_sh(rrt_problem *pr, double *S_lm)

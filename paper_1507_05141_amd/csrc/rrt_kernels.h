@@ -146,6 +146,7 @@ template <typename real> struct SourceArgs {
     real *S;
     const int *tnode;           // [P] or NULL (one table)
     const real *twt;            // [P] or NULL
+    const int *torder;          // [P] the points ordered by tnode (with tnode), or NULL
 };
 
 template <typename real> void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st);
@@ -182,6 +183,8 @@ template <typename real> void launch_resid_groups(long P, int G, const double *r
 template <typename real> void launch_chi0(long P, int G, const real *kappa, const real *sigma, const real *sg,
                                           const int *tnode, const real *twt, real *chi0, hipStream_t st);
 template <typename real> void launch_moments_lab(long P, int G, int K, const double *dir, const real *I, double *J, double *H, double *Kt, hipStream_t st);
+void launch_moments_integrate(long P, int G, const double *dnu, const double *J, const double *H, const double *Kt,
+                              double *out, hipStream_t st);
 template <typename real> void launch_moments_co(long PG, int NL, int lmax, const real *Ilm, double *J, double *H, double *Kt, hipStream_t st);
 template <typename real> void launch_resid(long P, int G, int NL, const real *a, const real *b, double *partial, int nblk, double *out, hipStream_t st);
 // Ng dot products, each group weighted by 1/||s0_g||^2 from the residual sums red (floor2 as there)

@@ -1946,13 +1946,16 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, TEMP ? 2 : 4) k_source_co
         }
         cur = node;
     };
-    // contiguous points per workgroup
+    // contiguous points per workgroup; with temperature nodes in the order of
+    // their bracket, so that a workgroup reloads its tables rarely
     const long chunk = (a.P + gridDim.x - 1) / gridDim.x;
     const long pbeg = (long)blockIdx.x * chunk, pend = min(a.P, pbeg + chunk);
     constexpr int kPre = 4;                                // 16-byte loads per thread and point (G NL <= 8192)
     P4 pre[kPre];
     float pchi = 0.0f, pkap = 0.0f, pbnu = 0.0f, psig = 0.0f;
-    auto fetch = [&](long p) {
+    auto point = [&](long idx) -> long { return TEMP ? (long)a.torder[idx] : idx; };
+    auto fetch = [&](long idx) {
+        const long p = point(idx);
         const P4 *src = reinterpret_cast<const P4 *>(a.Ilm + p * GN);
 #pragma unroll
         for (int u = 0; u < kPre; ++u) {
@@ -1966,9 +1969,9 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, TEMP ? 2 : 4) k_source_co
             psig = a.sigma[p];
         }
     };
-    long p = pbeg;
-    if (p < pend) fetch(p);
-    for (; p < pend; ++p) {
+    if (pbeg < pend) fetch(pbeg);
+    for (long idx = pbeg; idx < pend; ++idx) {
+        const long p = point(idx);
         {
             const int node = TEMP ? a.tnode[p] : 0;
             if (TEMP) w = a.twt[p];
@@ -1987,7 +1990,7 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, TEMP ? 2 : 4) k_source_co
             sF[tid] = on ? psig / pchi : 0.0f;
             sT[tid] = on ? 3.5449077018110318f * pkap * pbnu / pchi : 0.0f;
         }
-        if (p + 1 < pend) fetch(p + 1);
+        if (idx + 1 < pend) fetch(idx + 1);
         __syncthreads();
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
@@ -2656,6 +2659,36 @@ void launch_moments_lab(long P, int G, int K, const double *dir, const real *I, 
 {
     hipLaunchKernelGGL(k_moments_lab<real>, dim3(blocks_for(P * G, 256)), dim3(256), 0, st, P, G, K, dir, I, J, H, Kt);
 }
+// Frequency-integrated moments per point (FP64): X_tot = sum_g dnu_g X_g over the
+// per-group J [P][G], H [P][G][3], K [P][G][6], and the Eddington tensor
+// f = K_tot / J_tot (0 where J_tot = 0); out [P][16] = J, H (3), K (6), f (6)
+__global__ void __launch_bounds__(256) k_moments_integrate(long P, int G, const double *__restrict__ dnu,
+                                                           const double *__restrict__ J, const double *__restrict__ H,
+                                                           const double *__restrict__ Kt, double *__restrict__ out)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    double j = 0.0, h[3] = {0.0, 0.0, 0.0}, k[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int g = 0; g < G; ++g) {
+        const double w = dnu[g];
+        const long o = p * G + g;
+        j += w * J[o];
+        for (int c = 0; c < 3; ++c) h[c] += w * H[3 * o + c];
+        for (int c = 0; c < 6; ++c) k[c] += w * Kt[6 * o + c];
+    }
+    double *r = out + 16 * p;
+    r[0] = j;
+    for (int c = 0; c < 3; ++c) r[1 + c] = h[c];
+    for (int c = 0; c < 6; ++c) r[4 + c] = k[c];
+    for (int c = 0; c < 6; ++c) r[10 + c] = j != 0.0 ? k[c] / j : 0.0;
+}
+
+void launch_moments_integrate(long P, int G, const double *dnu, const double *J, const double *H, const double *Kt,
+                              double *out, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_moments_integrate, dim3(blocks_for(P, 256)), dim3(256), 0, st, P, G, dnu, J, H, Kt, out);
+}
+
 template <typename real>
 void launch_moments_co(long PG, int NL, int lmax, const real *Ilm, double *J, double *H, double *Kt, hipStream_t st)
 {

@@ -299,6 +299,29 @@ def test_full_size_thomson_jet_sweep_fp32():
     g.close()
 
 
+@pytest.mark.parametrize("prec", [B.FP64, B.FP32], ids=["fp64", "fp32"])
+def test_frequency_integrated_moments_parity(prec):
+    """Frequency-integrated J, H, K and f = K/J, reduced on the device in FP64,
+    in both frames, after one time-dependent sweep of a moving multi-group
+    medium, against the oracle's integrals of its own moments."""
+    spec = custom_spec(6, 5, 4, G=5, seed=51)
+    o, g = _both(spec, prec)
+    rs = np.random.default_rng(52)
+    Iprev = rs.uniform(0.0, 1.0, o.lab_shape())
+    S = o.initial_source(Iprev)
+    ref_I, ref_Ilm, _, _ = o.sweep(S, Iprev, 4.0)
+    g.set_intensity(ref_I)                          # the lab moments read the intensity state
+    g.set_source_sh(S)
+    g.sweep(0.0)
+    tol = 10 * TOL[prec]
+    for frame, ref in ((B.FRAME_LAB, o.integrated(*o.moments_lab(ref_I))),
+                       (B.FRAME_COMOVING, o.integrated(*o.moments_comoving(g.intensity_sh())))):
+        got = g.moments_integrated(frame)
+        for a, b, name in zip(got, ref, ("J", "H", "K", "f")):
+            assert np.abs(a - b).max() <= tol * np.abs(b).max(), (frame, name)
+    g.close()
+
+
 @pytest.mark.parametrize("thermal", [False, True], ids=["electrons_at_rest", "thermal_electrons"])
 def test_compton_tables_built_on_the_gpu_match_the_oracle(thermal):
     """The library builds its group-to-group tables on the GPU (FP64, its own

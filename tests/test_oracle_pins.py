@@ -606,6 +606,20 @@ def test_residual_closed_form():
     assert r[3] == 0.0 and np.isinf(r[4])
 
 
+def test_frequency_integrated_moments_of_an_isotropic_spectrum():
+    """An isotropic field with group values c_g: J_tot = sum dnu_g c_g (the
+    group widths), H_tot = 0, K_tot = J_tot / 3 on the diagonal, so the
+    frequency-integrated Eddington tensor is 1/3 times the identity."""
+    edges = 10.0 ** np.linspace(-1, 1, 6)
+    o = oracle.Oracle(spec_uniform(n=2, nz=2, nmu=8, nphi=16, lmax=3, kappa=1.0, edges=edges))
+    cg = np.array([0.5, 2.0, 1.5, 0.25, 3.0])
+    I_lab = np.broadcast_to(cg[None, None, :], o.lab_shape()).copy()
+    Jt, Ht, Kt, f = o.integrated(*o.moments_lab(I_lab))
+    assert np.allclose(Jt, np.sum(np.diff(edges) * cg), rtol=1e-13)
+    assert np.abs(Ht).max() < 1e-13
+    assert np.allclose(f, [1 / 3, 1 / 3, 1 / 3, 0, 0, 0], atol=1e-13)
+
+
 def test_comoving_moments_of_a_quadratic_field_match_closed_forms():
     """At rest, a field I(n) = a + b.n + n.C.n with a symmetric C (non-zero
     off-diagonal terms) has J = a + tr C / 3, H = b / 3 and
