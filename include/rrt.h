@@ -135,6 +135,19 @@ rrt_status rrt_set_intensity(rrt_problem *pr, const double *I_lab);
    Errors: RRT_E_INVALID for NULL or an unknown frame. */
 rrt_status rrt_get_moments_integrated(rrt_problem *pr, rrt_frame frame, double *out);
 
+/* Stand-alone group-to-group Compton tables (Sec. 2.3, Eqs. 13-14, and
+   their thermal average) for ngroups groups with edges [ngroups+1] (centres
+   as in rrt_groups), electron rest energy mec2 in the units of the edges,
+   Legendre orders 0..lmax (lmax <= 15), at ntemp electron temperatures
+   kT [ntemp] (units of the edges; 0 = electrons at rest): cross-section
+   ratios s [ntemp][ngroups] (sigma(nu_i; T)/sigma_T) and Legendre moments
+   p [ntemp][lmax+1][ngroups][ngroups] (p_l^{i->j}, incident group i), FP64,
+   into caller host arrays.  Built on the GPU on hip_stream (NULL: the null
+   stream) with a device scratch buffer allocated and freed by the call.
+   Errors: RRT_E_INVALID (sizes, edges, temperatures), RRT_E_DEVICE. */
+rrt_status rrt_compton_tables(int ngroups, const double *edges, int log_centres, double mec2, int lmax, int ntemp,
+                              const double *kT, double *s, double *p, void *hip_stream);
+
 /* Compton tables in use (FP64 copies): ntemp node temperatures kT_nodes
    [ntemp] (a single node 0 for electrons at rest), cross-section ratios
    s [ntemp][G] (sigma(nu_i; T)/sigma_T) and source tables A

@@ -78,6 +78,7 @@ def lib():
             "rrt_get_sweep_intensity": [P, _dp],
             "rrt_get_compton_tables": [P, ctypes.POINTER(I), _dp, _dp, _dp],
             "rrt_get_moments_integrated": [P, I, _dp],
+            "rrt_compton_tables": [I, _dp, I, D, I, I, _dp, _dp, _dp, P],
             "rrt_ray_trace": [P, _dp, _dp, _dp],
             "rrt_set_profiling": [P, I],
             "rrt_set_graphs": [P, I],
@@ -132,6 +133,19 @@ def _structs(spec):
     groups = Groups(G, e_ptr, int(spec.get("log_centres", True)), float(spec.get("mec2", 510.99895)))
     angles = Angles(spec["lmax"], spec["nmu"], spec["nphi"])
     return grid, groups, angles, e_arr
+
+
+def compton_tables(edges, mec2, lmax, kT, log_centres=True, stream=None):
+    """Stand-alone Compton tables at the temperatures kT (units of the edges):
+    s [nt][G] and p [nt][lmax+1][G][G] (built on the GPU)."""
+    e, ep = _in(edges)
+    t, tp = _in(np.atleast_1d(kT))
+    G, nt = len(e) - 1, len(t)
+    s = np.zeros((nt, G))
+    p = np.zeros((nt, lmax + 1, G, G))
+    _check(lib().rrt_compton_tables(G, ep, int(log_centres), float(mec2), int(lmax), nt, tp, s.ctypes.data_as(_dp),
+                                    p.ctypes.data_as(_dp), ctypes.c_void_p(stream) if stream else None))
+    return s, p
 
 
 def footprint_bytes(spec, precision=FP32, time_dependent=False, use_ng=False):

@@ -985,6 +985,40 @@ void rrt_destroy(rrt_problem *pr)
     delete pr;
 }
 
+// arguments of the stand-alone table builder; centres from the edges
+static rrt_status table_args(int ngroups, const double *edges, int log_centres, double mec2, int lmax, int ntemp,
+                             const double *kT, std::vector<double> &centres)
+{
+    if (ngroups < 1 || !edges || !kT || ntemp < 1 || lmax < 0 || lmax > 15)
+        return fail(RRT_E_INVALID, "need ngroups >= 1, edges, 0 <= lmax <= 15 and ntemp >= 1 temperatures");
+    if (!(mec2 > 0.0) || !std::isfinite(mec2)) return fail(RRT_E_INVALID, "mec2 must be finite and > 0");
+    for (int g = 0; g < ngroups; ++g)
+        if (!std::isfinite(edges[g]) || !std::isfinite(edges[g + 1]) || !(edges[g + 1] > edges[g]) || edges[0] < 0.0 ||
+            (log_centres && !(edges[0] > 0.0)))
+            return fail(RRT_E_INVALID, "edges must be finite and ascending (positive for log centres)");
+    for (int n = 0; n < ntemp; ++n)
+        if (!std::isfinite(kT[n]) || kT[n] < 0.0) return fail(RRT_E_INVALID, "temperatures must be finite and >= 0");
+    centres.resize(ngroups);
+    for (int g = 0; g < ngroups; ++g)
+        centres[g] = log_centres ? std::sqrt(edges[g] * edges[g + 1]) : 0.5 * (edges[g] + edges[g + 1]);
+    return RRT_OK;
+}
+
+rrt_status rrt_compton_tables(int ngroups, const double *edges, int log_centres, double mec2, int lmax, int ntemp,
+                              const double *kT, double *s, double *p, void *hip_stream)
+{
+    std::vector<double> c;
+    rrt_status st = table_args(ngroups, edges, log_centres, mec2, lmax, ntemp, kT, c);
+    if (st) return st;
+    if (!s || !p) return fail(RRT_E_INVALID, "s and p are required");
+    std::vector<double> sv, pv;
+    const int e = rrt::compton_tables_gpu(ngroups, edges, c.data(), mec2, lmax, ntemp, kT, sv, pv, hip_stream);
+    if (e != 0) return fail(RRT_E_DEVICE, std::string("Compton tables: ") + hipGetErrorString((hipError_t)e));
+    std::copy(sv.begin(), sv.end(), s);
+    std::copy(pv.begin(), pv.end(), p);
+    return RRT_OK;
+}
+
 rrt_status rrt_get_compton_tables(const rrt_problem *pr, int *ntemp, double *kT_nodes, double *s, double *A)
 {
     if (!pr) return fail(RRT_E_INVALID, "problem is NULL");

@@ -23,6 +23,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <mutex>
 #include <vector>
 
 #include "rrt_internal.h"
@@ -256,43 +257,69 @@ __global__ void __launch_bounds__(256) k_kn_finish(TableArgs a, double *s_out, d
 
 }  // namespace
 
+namespace {
+
+// the Gauss-Legendre rules of the table definition (computed once)
+const QuadRules &quad_rules()
+{
+    static QuadRules h{};
+    static bool done = false;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!done) {
+        std::vector<double> x, w;
+        gauss_legendre(kNQ, x, w);
+        for (int k = 0; k < kNQ; ++k) { h.gx[k] = x[k]; h.gw[k] = w[k]; }
+        gauss_legendre(kNT, x, w);
+        for (int k = 0; k < kNT; ++k) { h.tx[k] = x[k]; h.tw[k] = w[k]; }
+        gauss_legendre(kNE, x, w);
+        for (int k = 0; k < kNE; ++k) { h.ex[k] = x[k]; h.ew[k] = w[k]; }
+        gauss_legendre(kNF, x, w);
+        for (int k = 0; k < kNF; ++k) { h.fx[k] = x[k]; h.fw[k] = w[k]; }
+        done = true;
+    }
+    return h;
+}
+
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+}  // namespace
+
+size_t compton_scratch_bytes(int G, int lmax, int nt)
+{
+    const size_t nsig = (size_t)nt * G * kNT * kNE, nband = (size_t)nt * G * G * kChunks * (lmax + 1);
+    const size_t np = (size_t)nt * (lmax + 1) * G * G;
+    return align256(sizeof(QuadRules)) + align256(8 * ((size_t)G + 1)) + align256(8 * (size_t)G) +
+           align256(8 * (size_t)nt) + align256(8 * nsig) + align256(8 * nband) + align256(8 * np) +
+           align256(8 * (size_t)nt * G);
+}
+
 // Tables at the node temperatures kT[0..nt) (units of the edges; 0 = electrons
-// at rest).  s [nt][G] and p [nt][lmax+1][G][G] are returned on the host in FP64.
-int compton_tables_gpu(int G, const double *edges, const double *centres, double mec2, int lmax, int nt,
-                       const double *kT, std::vector<double> &s, std::vector<double> &p, void *stream)
+// at rest) in the scratch buffer buf (device memory of compton_scratch_bytes):
+// s [nt][G] and p [nt][lmax+1][G][G] are written to the host arrays s_out,
+// p_out in FP64.  Every scratch element is written before it is read.
+int compton_tables_in(int G, const double *edges, const double *centres, double mec2, int lmax, int nt,
+                      const double *kT, void *scratch_buf, double *s_out, double *p_out, void *stream)
 {
     if (lmax > kMaxL) return (int)hipErrorInvalidValue;
     hipStream_t st = static_cast<hipStream_t>(stream);
-    QuadRules h{};
-    std::vector<double> x, w;
-    gauss_legendre(kNQ, x, w);
-    for (int k = 0; k < kNQ; ++k) { h.gx[k] = x[k]; h.gw[k] = w[k]; }
-    gauss_legendre(kNT, x, w);
-    for (int k = 0; k < kNT; ++k) { h.tx[k] = x[k]; h.tw[k] = w[k]; }
-    gauss_legendre(kNE, x, w);
-    for (int k = 0; k < kNE; ++k) { h.ex[k] = x[k]; h.ew[k] = w[k]; }
-    gauss_legendre(kNF, x, w);
-    for (int k = 0; k < kNF; ++k) { h.fx[k] = x[k]; h.fw[k] = w[k]; }
+    const QuadRules &h = quad_rules();
     const size_t nsig = (size_t)nt * G * kNT * kNE, nband = (size_t)nt * G * G * kChunks * (lmax + 1);
     const size_t np = (size_t)nt * (lmax + 1) * G * G;
-    const size_t bytes = sizeof(QuadRules) + 8 * ((size_t)2 * G + 1 + nt + nsig + nband + np + (size_t)nt * G);
-    char *buf = nullptr;
-    hipError_t e = hipMalloc(&buf, bytes);
-    if (e != hipSuccess) return (int)e;
-    char *cur = buf;
-    auto take = [&](size_t n) { char *r = cur; cur += n; return r; };
+    char *cur = static_cast<char *>(scratch_buf);
+    auto take = [&](size_t n) { char *r = cur; cur += align256(n); return r; };
     QuadRules *d_q = reinterpret_cast<QuadRules *>(take(sizeof(QuadRules)));
-    double *d_edges = reinterpret_cast<double *>(take(8 * (G + 1)));
-    double *d_centres = reinterpret_cast<double *>(take(8 * G));
-    double *d_kT = reinterpret_cast<double *>(take(8 * nt));
+    double *d_edges = reinterpret_cast<double *>(take(8 * ((size_t)G + 1)));
+    double *d_centres = reinterpret_cast<double *>(take(8 * (size_t)G));
+    double *d_kT = reinterpret_cast<double *>(take(8 * (size_t)nt));
     double *d_sig = reinterpret_cast<double *>(take(8 * nsig));
     double *d_band = reinterpret_cast<double *>(take(8 * nband));
     double *d_p = reinterpret_cast<double *>(take(8 * np));
     double *d_s = reinterpret_cast<double *>(take(8 * (size_t)nt * G));
-    if (e == hipSuccess) e = hipMemcpyAsync(d_q, &h, sizeof(QuadRules), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_edges, edges, 8 * (G + 1), hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_centres, centres, 8 * G, hipMemcpyHostToDevice, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(d_kT, kT, 8 * nt, hipMemcpyHostToDevice, st);
+    hipError_t e = hipMemcpyAsync(d_q, &h, sizeof(QuadRules), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_edges, edges, 8 * ((size_t)G + 1), hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_centres, centres, 8 * (size_t)G, hipMemcpyHostToDevice, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(d_kT, kT, 8 * (size_t)nt, hipMemcpyHostToDevice, st);
     if (e == hipSuccess) {
         TableArgs a{G, lmax, nt, mec2, d_edges, d_centres, d_kT, d_q, d_sig, d_band};
         hipLaunchKernelGGL(k_kn_sigma, dim3((unsigned)((nsig + 255) / 256)), dim3(256), 0, st, a);
@@ -301,13 +328,25 @@ int compton_tables_gpu(int G, const double *edges, const double *centres, double
         hipLaunchKernelGGL(k_kn_finish, dim3((unsigned)((np + 255) / 256)), dim3(256), 0, st, a, d_s, d_p);
         e = hipGetLastError();
     }
-    s.assign((size_t)nt * G, 0.0);
-    p.assign(np, 0.0);
-    if (e == hipSuccess) e = hipMemcpyAsync(s.data(), d_s, 8 * (size_t)nt * G, hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(p.data(), d_p, 8 * np, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(s_out, d_s, 8 * (size_t)nt * G, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(p_out, d_p, 8 * np, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(buf);
     return (int)e;
+}
+
+// the same with a scratch buffer allocated for the call
+int compton_tables_gpu(int G, const double *edges, const double *centres, double mec2, int lmax, int nt,
+                       const double *kT, std::vector<double> &s, std::vector<double> &p, void *stream)
+{
+    if (lmax > kMaxL) return (int)hipErrorInvalidValue;
+    void *buf = nullptr;
+    hipError_t e = hipMalloc(&buf, compton_scratch_bytes(G, lmax, nt));
+    if (e != hipSuccess) return (int)e;
+    s.assign((size_t)nt * G, 0.0);
+    p.assign((size_t)nt * (lmax + 1) * G * G, 0.0);
+    const int r = compton_tables_in(G, edges, centres, mec2, lmax, nt, kT, buf, s.data(), p.data(), stream);
+    (void)hipFree(buf);
+    return r;
 }
 
 }  // namespace rrt

@@ -12,5 +12,10 @@ void real_sh(int lmax, double mu, double phi, double *Y);
 // p_l^{i->j}); returns a hipError_t value (0 on success)
 int compton_tables_gpu(int G, const double *edges, const double *centres, double mec2, int lmax, int nt,
                        const double *kT, std::vector<double> &s, std::vector<double> &p, void *stream);
+// the same in a caller's device scratch buffer of compton_scratch_bytes(G, lmax, nt),
+// writing s and p to host arrays
+size_t compton_scratch_bytes(int G, int lmax, int nt);
+int compton_tables_in(int G, const double *edges, const double *centres, double mec2, int lmax, int nt,
+                      const double *kT, void *scratch_buf, double *s_out, double *p_out, void *stream);
 
 }  // namespace rrt

@@ -351,6 +351,22 @@ def test_compton_tables_built_on_the_gpu_match_the_oracle(thermal):
             assert np.abs(A[n, l] - ref).max() <= 1e-11 * np.abs(ref).max(), (n, l)
 
 
+def test_standalone_compton_tables_match_the_oracle():
+    """rrt_compton_tables at electrons at rest and at 10, 31.6 and 100 keV
+    (s and p, FP64) against the oracle's tables: 1e-11 of each table's largest
+    entry; an invalid temperature is refused."""
+    edges = np.exp(np.linspace(np.log(1.0), np.log(1e3), 11))
+    kT = np.array([0.0, 10.0, 10 ** 1.5, 100.0])
+    s, p = B.compton_tables(edges, W.MEC2_KEV, 5, kT)
+    c = oracle.group_centres(edges, True)
+    for n, t in enumerate(kT):
+        so, po = oracle.compton_thermal(edges, c, W.MEC2_KEV, 5, t)
+        assert np.abs(s[n] - so).max() <= 1e-11 * np.abs(so).max()
+        assert np.abs(p[n] - po).max() <= 1e-11 * np.abs(po).max(), n
+    with pytest.raises(B.RRTError):
+        B.compton_tables(edges, W.MEC2_KEV, 5, [-1.0])
+
+
 @pytest.mark.parametrize("prec", [B.FP64, B.FP32], ids=["fp64", "fp32"])
 def test_thermal_compton_sweep_parity(prec):
     """One sweep with a smooth 10-100 keV electron temperature field (tables on
