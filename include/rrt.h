@@ -148,6 +148,16 @@ rrt_status rrt_get_moments_integrated(rrt_problem *pr, rrt_frame frame, double *
 rrt_status rrt_compton_tables(int ngroups, const double *edges, int log_centres, double mec2, int lmax, int ntemp,
                               const double *kT, double *s, double *p, void *hip_stream);
 
+/* rrt_compton_tables without any device allocation, for callers that cannot
+   allocate (code under HIP graph capture, tight serving loops, harnesses that
+   forbid hipMalloc): the scratch is a static device array of 32 MiB per GPU,
+   kept until the process ends, instead of a buffer allocated per call.  Same
+   arguments, kernels and results.  Sizes whose scratch exceeds 32 MiB
+   (about nt G^2 (lmax+1) 128 bytes) are refused with RRT_E_INVALID.  The array
+   is shared by every call on a GPU: calls that overlap on one GPU race. */
+rrt_status rrt_compton_tables_noalloc(int ngroups, const double *edges, int log_centres, double mec2, int lmax,
+                                      int ntemp, const double *kT, double *s, double *p, void *hip_stream);
+
 /* Compton tables in use (FP64 copies): ntemp node temperatures kT_nodes
    [ntemp] (a single node 0 for electrons at rest), cross-section ratios
    s [ntemp][G] (sigma(nu_i; T)/sigma_T) and source tables A

@@ -987,7 +987,7 @@ void rrt_destroy(rrt_problem *pr)
 
 // arguments of the stand-alone table builder; centres from the edges
 static rrt_status table_args(int ngroups, const double *edges, int log_centres, double mec2, int lmax, int ntemp,
-                             const double *kT, std::vector<double> &centres)
+                             const double *kT, double *centres)
 {
     if (ngroups < 1 || !edges || !kT || ntemp < 1 || lmax < 0 || lmax > 15)
         return fail(RRT_E_INVALID, "need ngroups >= 1, edges, 0 <= lmax <= 15 and ntemp >= 1 temperatures");
@@ -998,7 +998,6 @@ static rrt_status table_args(int ngroups, const double *edges, int log_centres, 
             return fail(RRT_E_INVALID, "edges must be finite and ascending (positive for log centres)");
     for (int n = 0; n < ntemp; ++n)
         if (!std::isfinite(kT[n]) || kT[n] < 0.0) return fail(RRT_E_INVALID, "temperatures must be finite and >= 0");
-    centres.resize(ngroups);
     for (int g = 0; g < ngroups; ++g)
         centres[g] = log_centres ? std::sqrt(edges[g] * edges[g + 1]) : 0.5 * (edges[g] + edges[g + 1]);
     return RRT_OK;
@@ -1007,8 +1006,8 @@ static rrt_status table_args(int ngroups, const double *edges, int log_centres, 
 rrt_status rrt_compton_tables(int ngroups, const double *edges, int log_centres, double mec2, int lmax, int ntemp,
                               const double *kT, double *s, double *p, void *hip_stream)
 {
-    std::vector<double> c;
-    rrt_status st = table_args(ngroups, edges, log_centres, mec2, lmax, ntemp, kT, c);
+    std::vector<double> c(std::max(ngroups, 1));
+    rrt_status st = table_args(ngroups, edges, log_centres, mec2, lmax, ntemp, kT, c.data());
     if (st) return st;
     if (!s || !p) return fail(RRT_E_INVALID, "s and p are required");
     std::vector<double> sv, pv;
@@ -1016,6 +1015,25 @@ rrt_status rrt_compton_tables(int ngroups, const double *edges, int log_centres,
     if (e != 0) return fail(RRT_E_DEVICE, std::string("Compton tables: ") + hipGetErrorString((hipError_t)e));
     std::copy(sv.begin(), sv.end(), s);
     std::copy(pv.begin(), pv.end(), p);
+    return RRT_OK;
+}
+
+rrt_status rrt_compton_tables_noalloc(int ngroups, const double *edges, int log_centres, double mec2, int lmax,
+                                      int ntemp, const double *kT, double *s, double *p, void *hip_stream)
+{
+    constexpr int kMaxGroups = 1024;
+    double c[kMaxGroups];
+    if (ngroups > kMaxGroups) return fail(RRT_E_INVALID, "at most 1024 groups");
+    rrt_status st = table_args(ngroups, edges, log_centres, mec2, lmax, ntemp, kT, c);
+    if (st) return st;
+    if (!s || !p) return fail(RRT_E_INVALID, "s and p are required");
+    const size_t need = rrt::compton_scratch_bytes(ngroups, lmax, ntemp), have = rrt::compton_static_scratch_bytes();
+    if (need > have)
+        return fail(RRT_E_INVALID, "tables of " + std::to_string(ngroups) + " groups, lmax " + std::to_string(lmax) +
+                                       " at " + std::to_string(ntemp) + " temperatures need " + std::to_string(need) +
+                                       " bytes of scratch; the allocation-free builder has " + std::to_string(have));
+    const int e = rrt::compton_tables_static(ngroups, edges, c, mec2, lmax, ntemp, kT, s, p, hip_stream);
+    if (e != 0) return fail(RRT_E_DEVICE, std::string("Compton tables: ") + hipGetErrorString((hipError_t)e));
     return RRT_OK;
 }
 

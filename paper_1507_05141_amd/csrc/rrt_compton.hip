@@ -267,15 +267,10 @@ const QuadRules &quad_rules()
     static std::mutex mu;
     std::lock_guard<std::mutex> lock(mu);
     if (!done) {
-        std::vector<double> x, w;
-        gauss_legendre(kNQ, x, w);
-        for (int k = 0; k < kNQ; ++k) { h.gx[k] = x[k]; h.gw[k] = w[k]; }
-        gauss_legendre(kNT, x, w);
-        for (int k = 0; k < kNT; ++k) { h.tx[k] = x[k]; h.tw[k] = w[k]; }
-        gauss_legendre(kNE, x, w);
-        for (int k = 0; k < kNE; ++k) { h.ex[k] = x[k]; h.ew[k] = w[k]; }
-        gauss_legendre(kNF, x, w);
-        for (int k = 0; k < kNF; ++k) { h.fx[k] = x[k]; h.fw[k] = w[k]; }
+        gauss_legendre(kNQ, h.gx, h.gw);
+        gauss_legendre(kNT, h.tx, h.tw);
+        gauss_legendre(kNE, h.ex, h.ew);
+        gauss_legendre(kNF, h.fx, h.fw);
         done = true;
     }
     return h;
@@ -347,6 +342,53 @@ int compton_tables_gpu(int G, const double *edges, const double *centres, double
     const int r = compton_tables_in(G, edges, centres, mec2, lmax, nt, kT, buf, s.data(), p.data(), stream);
     (void)hipFree(buf);
     return r;
+}
+
+// Scratch of the allocation-free table builder: a file-scope device array, one
+// copy per GPU the library runs on, held until the process ends.  Host code
+// reaches it only through the address hipGetSymbolAddress returns on each
+// device (the array's name is a host-side stand-in there).  Calls on one GPU
+// share it: calls that overlap on one GPU race.
+constexpr size_t kStaticScratchBytes = (size_t)32 << 20;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+size_t compton_static_scratch_bytes() { return kStaticScratchBytes; }
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+
+// this device's address of the scratch array, looked up once per device with
+// that device current
+hipError_t static_scratch(void **out)
+{
+    static std::mutex mu;
+    static void *ptr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (!ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        ptr[dev] = p;
+    }
+    *out = ptr[dev];
+    return hipSuccess;
+}
+
+}  // namespace
+
+int compton_tables_static(int G, const double *edges, const double *centres, double mec2, int lmax, int nt,
+                          const double *kT, double *s_out, double *p_out, void *stream)
+{
+    if (lmax > kMaxL || compton_scratch_bytes(G, lmax, nt) > kStaticScratchBytes) return (int)hipErrorInvalidValue;
+    void *buf = nullptr;
+    const hipError_t e = static_scratch(&buf);
+    if (e != hipSuccess) return (int)e;
+    return compton_tables_in(G, edges, centres, mec2, lmax, nt, kT, buf, s_out, p_out, stream);
 }
 
 }  // namespace rrt

@@ -17,6 +17,11 @@ void gauss_legendre(int n, std::vector<double> &x, std::vector<double> &w)
 {
     x.assign(n, 0.0);
     w.assign(n, 0.0);
+    gauss_legendre(n, x.data(), w.data());
+}
+
+void gauss_legendre(int n, double *x, double *w)
+{
     for (int i = 1; i <= n; ++i) {
         double t = std::cos(kPi * (4.0 * i - 1.0) / (4.0 * n + 2.0));
         double dpn = 1.0;
