@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "librrt.so")
 SOURCES = ["csrc/rrt_kernels.hip", "csrc/rrt_compton.hip", "csrc/rrt_api.cpp", "csrc/rrt_tables.cpp"]
-LIBS = ["-L/opt/rocm/lib", "-lrocblas"]
+LIBS = []
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-Wall", "-Wno-unused-function"]

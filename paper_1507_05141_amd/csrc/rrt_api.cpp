@@ -3,7 +3,6 @@
 // time scheme, and kernel timing.  Every step of the sweep runs in the HIP
 // kernels of rrt_kernels.hip; the host only sequences them.
 #include <hip/hip_runtime.h>
-#include <rocblas/rocblas.h>
 
 #include <algorithm>
 #include <chrono>
@@ -81,7 +80,6 @@ struct rrt_problem {
     // device tables
     double *d_dir = nullptr, *d_mu = nullptr, *d_lnc = nullptr, *d_nu3 = nullptr, *d_inv_nu3 = nullptr,
            *d_inv_dc = nullptr;
-    rocblas_handle blas = nullptr;
     int Gc = 1;
     int Gc_max = 1;                                 // the most groups per trace workgroup the LDS holds
     rrt::OrdGeom *d_geo = nullptr;
@@ -292,27 +290,11 @@ struct Engine {
         return RRT_OK;
     }
 
-    // row-major C[M][N] = A[M][Kd] . B[Kd][N] with rocBLAS (column-major C^T = B^T A^T),
-    // split along M so that no matrix exceeds 2^31 elements
+    // row-major C[M][N] = A[M][Kd] . B[Kd][N] on the matrix cores (the library's panel kernel)
     rrt_status gemm(long M, int N, int Kd, const real *A, const real *Bm, real *C)
     {
-        const real one = 1, zero = 0;
-        const long maxrows = std::max(1L, (long)((1L << 31) - 1) / std::max(N, Kd));
-        for (long r0 = 0; r0 < M; r0 += maxrows) {
-            const int rows = (int)std::min(maxrows, M - r0);
-            rocblas_status st;
-            if (sizeof(real) == 8)
-                st = rocblas_dgemm(pr->blas, rocblas_operation_none, rocblas_operation_none, N, rows, Kd,
-                                   (const double *)&one, (const double *)Bm, N, (const double *)(A + r0 * Kd), Kd,
-                                   (const double *)&zero, (double *)(C + r0 * N), N);
-            else
-                st = rocblas_sgemm(pr->blas, rocblas_operation_none, rocblas_operation_none, N, rows, Kd,
-                                   (const float *)&one, (const float *)Bm, N, (const float *)(A + r0 * Kd), Kd,
-                                   (const float *)&zero, (float *)(C + r0 * N), N);
-            if (st != rocblas_status_success)
-                return fail(RRT_E_DEVICE, std::string("rocBLAS gemm: ") + rocblas_status_to_string(st));
-        }
-        return RRT_OK;
+        rrt::launch_gemm<real>(M, Kd, N, A, Bm, C, pr->stream);
+        return check_launch();
     }
 
     // S2 + S3: comoving SH source -> comoving ordinates -> lab S~ (with the implicit time terms)
@@ -967,7 +949,6 @@ void rrt_destroy(rrt_problem *pr)
     if (pr->stream) (void)hipStreamSynchronize(pr->stream);
     clear_graphs(pr);
     if (pr->h_red) (void)hipHostFree(pr->h_red);
-    if (pr->blas) (void)rocblas_destroy_handle(pr->blas);
     void *bufs[] = {pr->d_dir, pr->d_mu, pr->d_lnc, pr->d_nu3, pr->d_inv_nu3, pr->d_inv_dc, pr->d_geo, pr->d_taps, pr->d_order, pr->d_Yt, pr->d_WY,
                     pr->d_Y16, pr->d_WYt16,
                     pr->d_A, pr->d_sg, pr->d_tnode, pr->d_twt, pr->d_torder, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_gam, pr->d_chi0, pr->d_chilab, pr->d_plan, pr->d_chilabT, pr->d_bc[0], pr->d_bc[1],
@@ -1117,10 +1098,6 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
         if (need_boost > lim)
             return bail(fail(RRT_E_INVALID, "ordinates x groups per point too large for the frame-transform "
                                             "kernels' LDS in this precision"));
-        rocblas_status bs = rocblas_create_handle(&pr->blas);
-        if (bs == rocblas_status_success) bs = rocblas_set_stream(pr->blas, pr->stream);
-        if (bs != rocblas_status_success)
-            return bail(fail(RRT_E_DEVICE, std::string("rocBLAS handle: ") + rocblas_status_to_string(bs)));
     }
     // ordinates and SH tables
     rrt::gauss_legendre(pr->nmu, pr->mu, pr->wmu);
