@@ -215,6 +215,38 @@ rrt_status rrt_get_sweep_intensity(rrt_problem *pr, double *I_lab); /* [K][P][G]
 rrt_status rrt_ray_trace(rrt_problem *pr, const double *S_tilde, const double *chi_tilde,
                          double *I_lab);
 
+/* The lab source S~ [K][P][G] that the next rrt_sweep(dt_stage) traces: the
+   current SH source turned into comoving ordinates (Eq. 9), transformed to
+   the lab ordinates (Eqs. 7-8) and combined with the time terms of Eqs. 5-6
+   (the intensity state is I(t) when dt_stage > 0).  Runs the sweep's own S2
+   and S3 kernels into its work array; the state is unchanged.
+   Errors: RRT_E_STATE before rrt_set_medium, RRT_E_INVALID for dt_stage < 0. */
+rrt_status rrt_get_lab_source(rrt_problem *pr, double dt_stage, double *S_tilde);
+
+/* Device-pointer variants of the calls above, for callers whose data already
+   sits in HBM (sizes and layouts as in the host calls).  Arrays of the
+   problem's working precision (double for RRT_FP64, float for RRT_FP32 and
+   RRT_MIXED) are typed void*; the medium and the moments stay FP64.  Each
+   call queues its copies and kernels on the problem's stream and returns once
+   they are complete: the caller's buffers are borrowed for the call only, and
+   work the caller queued on another stream must be complete before the call.
+   A pointer that is not device (or managed) memory is refused with
+   RRT_E_INVALID.  rrt_set_medium_dev reads the fields back to the host (a
+   set-up call: the validation and the temperature ordering of rrt_set_medium
+   run there); rrt_ray_trace_dev validates S~ and chi~ on the device. */
+rrt_status rrt_set_medium_dev(rrt_problem *pr, const double *kappa, const double *sigma, const double *bnu,
+                              const double *beta, const double *kte);
+rrt_status rrt_set_intensity_dev(rrt_problem *pr, const void *I_lab);         /* [K][P][G]   */
+rrt_status rrt_set_source_sh_dev(rrt_problem *pr, const void *S_lm);          /* [P][G][NLM] */
+rrt_status rrt_get_source_sh_dev(rrt_problem *pr, void *S_lm);                /* [P][G][NLM] */
+rrt_status rrt_get_intensity_sh_dev(rrt_problem *pr, void *I_lm);             /* [P][G][NLM] */
+rrt_status rrt_get_intensity_dev(rrt_problem *pr, void *I_lab);               /* [K][P][G] state */
+rrt_status rrt_get_sweep_intensity_dev(rrt_problem *pr, void *I_lab);         /* [K][P][G]   */
+rrt_status rrt_get_lab_source_dev(rrt_problem *pr, double dt_stage, void *S_tilde);   /* [K][P][G] */
+rrt_status rrt_get_moments_dev(rrt_problem *pr, rrt_frame frame, double *J, double *H, double *K);
+rrt_status rrt_get_moments_integrated_dev(rrt_problem *pr, rrt_frame frame, double *out);  /* [P][16] */
+rrt_status rrt_ray_trace_dev(rrt_problem *pr, const void *S_tilde, const void *chi_tilde, void *I_lab);
+
 /* Device bytes the problem needs (0 if the arguments are invalid). */
 size_t rrt_footprint_bytes(const rrt_grid *grid, const rrt_groups *groups, const rrt_angles *angles,
                            rrt_precision precision, int time_dependent, int use_ng);

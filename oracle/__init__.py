@@ -266,6 +266,21 @@ class Oracle:
         _load().or_trace(self._ref, _ptr(St), _ptr(Xt), _ptr(I))
         return self._from_c(I)
 
+    def lab_extinction(self, k, g, inv_cdt=0.0):
+        """chi~ of lab ordinate k and group g at every point: [P]."""
+        out = np.zeros(self.P)
+        _load().or_lab_extinction(self._ref, ctypes.c_int(k), ctypes.c_int(g), ctypes.c_double(inv_cdt), _ptr(out))
+        return out
+
+    def trace_one(self, k, g, St, Xt):
+        """S4 for lab ordinate k and group g alone, from its S~ and chi~ [P]: I [P]."""
+        St, Xt = _f64(St), _f64(Xt)
+        if St.shape != (self.P,) or Xt.shape != (self.P,):
+            raise ValueError("S~ and chi~ of one ordinate and group are [P] arrays")
+        I = np.zeros(self.P)
+        _load().or_trace_one(self._ref, ctypes.c_int(k), ctypes.c_int(g), _ptr(St), _ptr(Xt), _ptr(I))
+        return I
+
     def unboost(self, I_lab):
         I_lab = self._to_c(I_lab)
         out = np.zeros(self.co_shape())

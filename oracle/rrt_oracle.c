@@ -707,6 +707,33 @@ static int has_motion(const or_problem *pr, long p)
     return !(b[0] == 0.0 && b[1] == 0.0 && b[2] == 0.0);
 }
 
+/* Doppler factor D = nu/nu0 of lab ordinate n at point p and the comoving
+   direction n0 of that ray (Eqs. 7-8); D = 1 and n0 = n where the medium is
+   at rest. */
+static double lab_frame(const or_problem *pr, long p, const double n[3], double n0[3])
+{
+    n0[0] = n[0]; n0[1] = n[1]; n0[2] = n[2];
+    if (!has_motion(pr, p)) return 1.0;
+    const double *b = pr->beta + 3 * p;
+    double b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
+    double Gam = 1.0 / sqrt(1.0 - b2);
+    double bn = b[0] * n[0] + b[1] * n[1] + b[2] * n[2];
+    double D = 1.0 / (Gam * (1.0 - bn));
+    double f = Gam * (1.0 - Gam / (Gam + 1.0) * bn);
+    for (int c = 0; c < 3; c++) n0[c] = D * (n[c] - f * b[c]);
+    return D;
+}
+
+/* lab extinction of group g from the comoving extinctions C[G] of the point:
+   chi_lab = chi0(nu/D)/D (chi nu invariant), linear in ln nu with the outer
+   values held; a grey group takes chi0/D */
+static double lab_chi(const or_problem *pr, const double *C, int g, double D, int moving)
+{
+    if (!moving) return C[g];
+    if (pr->grey) return C[g] / D;
+    return freq_interp(pr, C, 1, pr->centres[g] / D, 0) / D;
+}
+
 /* S3: lab-frame source and extinction on the lab ordinates, plus the implicit
    time terms of Eqs. 5-6:  chi~ = chi_lab + 1/(c dt),
    S~ = (chi_lab S_lab + I_prev/(c dt)) / chi~   (c = 1, inv_cdt = 1/(c dt)).
@@ -727,26 +754,15 @@ void or_boost(const or_problem *pr, const double *S0, const double *I_prev, doub
             for (int g = 0; g < G; g++) C[g] = chi0_of(pr, p, g);
             int moving = has_motion(pr, p);
             for (int k = 0; k < K; k++) {
-                double n[3];
+                double n[3], n0[3];
                 ordinate_dir(pr, k, n);
-                double D = 1.0, n0[3] = {n[0], n[1], n[2]};
-                if (moving) {
-                    const double *b = pr->beta + 3 * p;
-                    double b2 = b[0] * b[0] + b[1] * b[1] + b[2] * b[2];
-                    double Gam = 1.0 / sqrt(1.0 - b2);
-                    double bn = b[0] * n[0] + b[1] * n[1] + b[2] * n[2];
-                    D = 1.0 / (Gam * (1.0 - bn));
-                    double f = Gam * (1.0 - Gam / (Gam + 1.0) * bn);
-                    for (int c = 0; c < 3; c++) n0[c] = D * (n[c] - f * b[c]);
-                }
+                double D = lab_frame(pr, p, n, n0);
                 for (int g = 0; g < G; g++) {
-                    double Slab, chil;
+                    double Slab, chil = lab_chi(pr, C, g, D, moving);
                     if (!moving) {
                         Slab = S0[(p * G + g) * K + k];
-                        chil = C[g];
                     } else if (pr->grey) {
                         Slab = D * D * D * D * angle_interp(pr, S0 + (p * G + g) * K, 1, n0);
-                        chil = C[g] / D;
                     } else {
                         if (g == 0)
                             for (int gp = 0; gp < G; gp++) {
@@ -755,7 +771,6 @@ void or_boost(const or_problem *pr, const double *S0, const double *I_prev, doub
                             }
                         double nu = pr->centres[g];
                         Slab = nu * nu * nu * freq_interp(pr, A, 1, nu / D, 1);
-                        chil = freq_interp(pr, C, 1, nu / D, 0) / D;
                     }
                     double ip = I_prev ? I_prev[((long)k * G + g) * P + p] : 0.0;
                     double xt = chil + inv_cdt;
@@ -766,6 +781,26 @@ void or_boost(const or_problem *pr, const double *S0, const double *I_prev, doub
             }
         }
         free(A);
+        free(C);
+    }
+}
+
+/* chi~ of S3 for one lab ordinate k and group g at every point: out [P] */
+void or_lab_extinction(const or_problem *pr, int k, int g, double inv_cdt, double *out)
+{
+    long P = npts(pr);
+    int G = pr->ng;
+    #pragma omp parallel
+    {
+        double *C = (double *)malloc(sizeof(double) * G);
+        #pragma omp for
+        for (long p = 0; p < P; p++) {
+            for (int gp = 0; gp < G; gp++) C[gp] = chi0_of(pr, p, gp);
+            double n[3], n0[3];
+            ordinate_dir(pr, k, n);
+            double D = lab_frame(pr, p, n, n0);
+            out[p] = lab_chi(pr, C, g, D, has_motion(pr, p)) + inv_cdt;
+        }
         free(C);
     }
 }
@@ -927,101 +962,120 @@ static double path_value(const double *A, const double *B, int nx, int ny, int i
    and q_{j-1} (which extend one piece beyond u and beyond p when those
    planes exist).  With np = 1 this is the plane-to-plane short
    characteristic. */
+/* One lab ordinate k of one group: S, X and Ik are that ordinate's and
+   group's [P] planes of S~, chi~ and I, bc its inflow plane [ny*nx] or NULL. */
+static void trace_kg(const or_problem *pr, int k, const double *S, const double *X, const double *bc, double *Ik)
+{
+    int nx = pr->nx, ny = pr->ny, nz = pr->nz;
+    long PL = (long)nx * ny;
+    double dx = pr->lx / nx, dy = pr->ly / ny, dz = pr->lz / (nz - 1);
+    double n[3];
+    ordinate_dir(pr, k, n);
+    double mu = n[2];
+    int np = trace_pieces(pr, mu);
+    double ds = dz / fabs(mu) / np;                  /* length of one piece */
+    double ox = snap_cells(-ds * n[0] / dx), oy = snap_cells(-ds * n[1] / dy);
+    double *qs = (double *)malloc(sizeof(double) * (np + 3));
+    double *qx = (double *)malloc(sizeof(double) * (np + 3));
+    for (int t = 0; t < nz; t++) {
+        int m = (mu > 0.0) ? t : nz - 1 - t;
+        int mu_ = (mu > 0.0) ? t - 1 : nz - t;       /* upwind plane          */
+        int muu = (mu > 0.0) ? t - 2 : nz + 1 - t;   /* second upwind plane   */
+        int md = (mu > 0.0) ? t + 1 : nz - 2 - t;    /* downwind plane        */
+        if (t == 0) {
+            for (long e = 0; e < PL; e++)
+                Ik[m * PL + e] = bc ? bc[e] : 0.0;
+            continue;
+        }
+        int has_d = t <= nz - 2, has_uu = t >= 2;
+        for (int j = 0; j < ny; j++) {
+            for (int i = 0; i < nx; i++) {
+                long e = (long)j * nx + i;
+                /* path points q_c, c = -1 .. np + 1, stored at index c + 1 */
+                for (int c = -1; c <= np + 1; c++) {
+                    double *vs = qs + c + 1, *vx = qx + c + 1;
+                    if (c == -1) {
+                        if (!has_d) { *vs = *vx = 0.0; continue; }
+                        double f = 1.0 / np;
+                        *vs = path_value(S + m * PL, S + md * PL, nx, ny, i, j, -ox, -oy, f);
+                        *vx = path_value(X + m * PL, X + md * PL, nx, ny, i, j, -ox, -oy, f);
+                    } else if (c <= np) {
+                        double f = (double)c / np;
+                        if (c == np) {          /* on the upwind plane */
+                            *vs = plane_interp(S + mu_ * PL, nx, ny, i, j, c * ox, c * oy);
+                            *vx = plane_interp(X + mu_ * PL, nx, ny, i, j, c * ox, c * oy);
+                        } else {
+                            *vs = path_value(S + m * PL, S + mu_ * PL, nx, ny, i, j, c * ox, c * oy, f);
+                            *vx = path_value(X + m * PL, X + mu_ * PL, nx, ny, i, j, c * ox, c * oy, f);
+                        }
+                    } else {
+                        if (!has_uu) { *vs = *vx = 0.0; continue; }
+                        double f = 1.0 / np;
+                        *vs = path_value(S + mu_ * PL, S + muu * PL, nx, ny, i, j, c * ox, c * oy, f);
+                        *vx = path_value(X + mu_ * PL, X + muu * PL, nx, ny, i, j, c * ox, c * oy, f);
+                    }
+                }
+                double Iv = plane_interp(Ik + mu_ * PL, nx, ny, i, j, np * ox, np * oy);
+                for (int c = np - 1; c >= 0; c--) {
+                    /* piece from q_{c+1} (u) to q_c (p); neighbours q_{c+2}, q_{c-1} */
+                    double Su = qs[c + 2], Xu = qx[c + 2], Sp = qs[c + 1], Xp = qx[c + 1];
+                    int d_ok = c >= 1 || has_d, uu_ok = c + 2 <= np || has_uu;
+                    double hu = ds * 0.5 * (Xu + Xp);
+                    double dSp = 0.0, dSu = 0.0;
+                    if (hu > 0.0) {
+                        double d1 = (Sp - Su) / hu;
+                        if (d_ok) {
+                            double Sd = qs[c], Xd = qx[c];
+                            double hd = ds * 0.5 * (Xp + Xd);
+                            dSp = (hd > 0.0) ? fb_slope(d1, (Sd - Sp) / hd, hu, hd) : 0.0;
+                        } else {
+                            dSp = d1;
+                        }
+                        if (uu_ok) {
+                            double Suu = qs[c + 3], Xuu = qx[c + 3];
+                            double huu = ds * 0.5 * (Xuu + Xu);
+                            dSu = (huu > 0.0) ? fb_slope((Su - Suu) / huu, d1, huu, hu) : 0.0;
+                        } else {
+                            dSu = d1;
+                        }
+                    }
+                    double Cu = clampd(Su + hu * dSu / 3.0, Su, Sp);
+                    double Cp = clampd(Sp - hu * dSp / 3.0, Su, Sp);
+                    double ex, w[4];
+                    bezier_weights(hu, &ex, w);
+                    Iv = Iv * ex + w[0] * Su + w[1] * Cu + w[2] * Cp + w[3] * Sp;
+                }
+                Ik[m * PL + e] = Iv;
+            }
+        }
+    }
+    free(qs); free(qx);
+}
+
 void or_trace(const or_problem *pr, const double *St, const double *Xt, double *I)
 {
-    int nx = pr->nx, ny = pr->ny, nz = pr->nz, G = pr->ng, K = nord(pr);
-    long P = npts(pr), PL = (long)nx * ny;
-    double dx = pr->lx / nx, dy = pr->ly / ny, dz = pr->lz / (nz - 1);
+    int G = pr->ng, K = nord(pr);
+    long P = npts(pr), PL = (long)pr->nx * pr->ny;
     #pragma omp parallel for collapse(2) schedule(dynamic)
     for (int k = 0; k < K; k++) {
         for (int g = 0; g < G; g++) {
             double n[3];
             ordinate_dir(pr, k, n);
-            double mu = n[2];
-            int np = trace_pieces(pr, mu);
-            double ds = dz / fabs(mu) / np;                  /* length of one piece */
-            double ox = snap_cells(-ds * n[0] / dx), oy = snap_cells(-ds * n[1] / dy);
+            const double *bc = (n[2] > 0.0) ? pr->bc_bot : pr->bc_top;
             long o = ((long)k * G + g) * P;
-            const double *S = St + o, *X = Xt + o;
-            double *Ik = I + o;
-            const double *bc = (mu > 0.0) ? pr->bc_bot : pr->bc_top;
-            double *qs = (double *)malloc(sizeof(double) * (np + 3));
-            double *qx = (double *)malloc(sizeof(double) * (np + 3));
-            for (int t = 0; t < nz; t++) {
-                int m = (mu > 0.0) ? t : nz - 1 - t;
-                int mu_ = (mu > 0.0) ? t - 1 : nz - t;       /* upwind plane          */
-                int muu = (mu > 0.0) ? t - 2 : nz + 1 - t;   /* second upwind plane   */
-                int md = (mu > 0.0) ? t + 1 : nz - 2 - t;    /* downwind plane        */
-                if (t == 0) {
-                    for (long e = 0; e < PL; e++)
-                        Ik[m * PL + e] = bc ? bc[((long)k * G + g) * PL + e] : 0.0;
-                    continue;
-                }
-                int has_d = t <= nz - 2, has_uu = t >= 2;
-                for (int j = 0; j < ny; j++) {
-                    for (int i = 0; i < nx; i++) {
-                        long e = (long)j * nx + i;
-                        /* path points q_c, c = -1 .. np + 1, stored at index c + 1 */
-                        for (int c = -1; c <= np + 1; c++) {
-                            double *vs = qs + c + 1, *vx = qx + c + 1;
-                            if (c == -1) {
-                                if (!has_d) { *vs = *vx = 0.0; continue; }
-                                double f = 1.0 / np;
-                                *vs = path_value(S + m * PL, S + md * PL, nx, ny, i, j, -ox, -oy, f);
-                                *vx = path_value(X + m * PL, X + md * PL, nx, ny, i, j, -ox, -oy, f);
-                            } else if (c <= np) {
-                                double f = (double)c / np;
-                                if (c == np) {          /* on the upwind plane */
-                                    *vs = plane_interp(S + mu_ * PL, nx, ny, i, j, c * ox, c * oy);
-                                    *vx = plane_interp(X + mu_ * PL, nx, ny, i, j, c * ox, c * oy);
-                                } else {
-                                    *vs = path_value(S + m * PL, S + mu_ * PL, nx, ny, i, j, c * ox, c * oy, f);
-                                    *vx = path_value(X + m * PL, X + mu_ * PL, nx, ny, i, j, c * ox, c * oy, f);
-                                }
-                            } else {
-                                if (!has_uu) { *vs = *vx = 0.0; continue; }
-                                double f = 1.0 / np;
-                                *vs = path_value(S + mu_ * PL, S + muu * PL, nx, ny, i, j, c * ox, c * oy, f);
-                                *vx = path_value(X + mu_ * PL, X + muu * PL, nx, ny, i, j, c * ox, c * oy, f);
-                            }
-                        }
-                        double Iv = plane_interp(Ik + mu_ * PL, nx, ny, i, j, np * ox, np * oy);
-                        for (int c = np - 1; c >= 0; c--) {
-                            /* piece from q_{c+1} (u) to q_c (p); neighbours q_{c+2}, q_{c-1} */
-                            double Su = qs[c + 2], Xu = qx[c + 2], Sp = qs[c + 1], Xp = qx[c + 1];
-                            int d_ok = c >= 1 || has_d, uu_ok = c + 2 <= np || has_uu;
-                            double hu = ds * 0.5 * (Xu + Xp);
-                            double dSp = 0.0, dSu = 0.0;
-                            if (hu > 0.0) {
-                                double d1 = (Sp - Su) / hu;
-                                if (d_ok) {
-                                    double Sd = qs[c], Xd = qx[c];
-                                    double hd = ds * 0.5 * (Xp + Xd);
-                                    dSp = (hd > 0.0) ? fb_slope(d1, (Sd - Sp) / hd, hu, hd) : 0.0;
-                                } else {
-                                    dSp = d1;
-                                }
-                                if (uu_ok) {
-                                    double Suu = qs[c + 3], Xuu = qx[c + 3];
-                                    double huu = ds * 0.5 * (Xuu + Xu);
-                                    dSu = (huu > 0.0) ? fb_slope((Su - Suu) / huu, d1, huu, hu) : 0.0;
-                                } else {
-                                    dSu = d1;
-                                }
-                            }
-                            double Cu = clampd(Su + hu * dSu / 3.0, Su, Sp);
-                            double Cp = clampd(Sp - hu * dSp / 3.0, Su, Sp);
-                            double ex, w[4];
-                            bezier_weights(hu, &ex, w);
-                            Iv = Iv * ex + w[0] * Su + w[1] * Cu + w[2] * Cp + w[3] * Sp;
-                        }
-                        Ik[m * PL + e] = Iv;
-                    }
-                }
-            }
-            free(qs); free(qx);
+            trace_kg(pr, k, St + o, Xt + o, bc ? bc + ((long)k * G + g) * PL : NULL, I + o);
         }
     }
+}
+
+/* S4 for the single lab ordinate k and group g: St, Xt and I are [P] */
+void or_trace_one(const or_problem *pr, int k, int g, const double *St, const double *Xt, double *I)
+{
+    long PL = (long)pr->nx * pr->ny;
+    double n[3];
+    ordinate_dir(pr, k, n);
+    const double *bc = (n[2] > 0.0) ? pr->bc_bot : pr->bc_top;
+    trace_kg(pr, k, St, Xt, bc ? bc + ((long)k * pr->ng + g) * PL : NULL, I);
 }
 
 /* ------------------------------------------------------------------------ */

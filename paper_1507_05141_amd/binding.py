@@ -80,6 +80,18 @@ def lib():
             "rrt_get_moments_integrated": [P, I, _dp],
             "rrt_compton_tables": [I, _dp, I, D, I, I, _dp, _dp, _dp, P],
             "rrt_ray_trace": [P, _dp, _dp, _dp],
+            "rrt_get_lab_source": [P, D, _dp],
+            "rrt_set_medium_dev": [P, P, P, P, P, P],
+            "rrt_set_intensity_dev": [P, P],
+            "rrt_set_source_sh_dev": [P, P],
+            "rrt_get_source_sh_dev": [P, P],
+            "rrt_get_intensity_sh_dev": [P, P],
+            "rrt_get_intensity_dev": [P, P],
+            "rrt_get_sweep_intensity_dev": [P, P],
+            "rrt_get_lab_source_dev": [P, D, P],
+            "rrt_get_moments_dev": [P, I, P, P, P],
+            "rrt_get_moments_integrated_dev": [P, I, P],
+            "rrt_ray_trace_dev": [P, P, P, P],
             "rrt_set_profiling": [P, I],
             "rrt_set_graphs": [P, I],
             "rrt_set_autotune": [P, I],
@@ -299,6 +311,78 @@ class Problem:
         return out
 
     # kernel variants
+    def lab_source(self, dt_stage=0.0):
+        """S~ [K][P][G] that the next sweep(dt_stage) traces (S2 + S3 of the current source)."""
+        out = np.zeros(self.lab_shape())
+        _check(lib().rrt_get_lab_source(self._h, float(dt_stage), out.ctypes.data_as(_dp)))
+        return out
+
+    # device-pointer variants: torch tensors on the GPU, in the working precision
+    # (float64 for FP64, float32 otherwise; the medium and moments in float64)
+    def _dev(self, t, shape, fp64=None):
+        import torch
+        want = torch.float64 if (fp64 if fp64 is not None else self.precision == FP64) else torch.float32
+        if not (t.is_cuda and t.dtype == want and t.is_contiguous() and tuple(t.shape) == tuple(shape)):
+            raise ValueError(f"need a contiguous {want} CUDA tensor of shape {tuple(shape)}")
+        return ctypes.c_void_p(t.data_ptr())
+
+    def _new_dev(self, shape, fp64=None):
+        import torch
+        dt = torch.float64 if (fp64 if fp64 is not None else self.precision == FP64) else torch.float32
+        return torch.empty(shape, dtype=dt, device="cuda")
+
+    def set_medium_dev(self, kappa, sigma, bnu, beta=None, kte=None):
+        P, G = self.P, self.G
+        args = [self._dev(kappa, (P, G), True), self._dev(sigma, (P,), True), self._dev(bnu, (P, G), True),
+                self._dev(beta, (P, 3), True) if beta is not None else None,
+                self._dev(kte, (P,), True) if kte is not None else None]
+        _check(lib().rrt_set_medium_dev(self._h, *args))
+
+    def set_intensity_dev(self, I_lab):
+        _check(lib().rrt_set_intensity_dev(self._h, self._dev(I_lab, self.lab_shape())))
+
+    def set_source_sh_dev(self, S):
+        _check(lib().rrt_set_source_sh_dev(self._h, self._dev(S, self.sh_shape())))
+
+    def _get_dev(self, fn, shape, *pre):
+        out = self._new_dev(shape)
+        _check(fn(self._h, *pre, self._dev(out, shape)))
+        return out
+
+    def source_sh_dev(self):
+        return self._get_dev(lib().rrt_get_source_sh_dev, self.sh_shape())
+
+    def intensity_sh_dev(self):
+        return self._get_dev(lib().rrt_get_intensity_sh_dev, self.sh_shape())
+
+    def intensity_dev(self):
+        return self._get_dev(lib().rrt_get_intensity_dev, self.lab_shape())
+
+    def sweep_intensity_dev(self):
+        return self._get_dev(lib().rrt_get_sweep_intensity_dev, self.lab_shape())
+
+    def lab_source_dev(self, dt_stage=0.0):
+        return self._get_dev(lib().rrt_get_lab_source_dev, self.lab_shape(), ctypes.c_double(dt_stage))
+
+    def moments_dev(self, frame=FRAME_LAB):
+        J = self._new_dev((self.P, self.G), True)
+        H = self._new_dev((self.P, self.G, 3), True)
+        K = self._new_dev((self.P, self.G, 6), True)
+        _check(lib().rrt_get_moments_dev(self._h, frame, self._dev(J, J.shape, True), self._dev(H, H.shape, True),
+                                         self._dev(K, K.shape, True)))
+        return J, H, K
+
+    def moments_integrated_dev(self, frame=FRAME_LAB):
+        out = self._new_dev((self.P, 16), True)
+        _check(lib().rrt_get_moments_integrated_dev(self._h, frame, self._dev(out, out.shape, True)))
+        return out
+
+    def ray_trace_dev(self, S_tilde, chi_tilde):
+        out = self._new_dev(self.lab_shape())
+        _check(lib().rrt_ray_trace_dev(self._h, self._dev(S_tilde, self.lab_shape()), self._dev(chi_tilde, self.lab_shape()),
+                                       self._dev(out, self.lab_shape())))
+        return out
+
     def set_autotune(self, enable=True):
         _check(lib().rrt_set_autotune(self._h, int(enable)))
 

@@ -105,6 +105,7 @@ struct rrt_problem {
     void *d_Iin = nullptr, *d_acc = nullptr;
     void *d_chain[4] = {nullptr, nullptr, nullptr, nullptr};
     double *d_partial = nullptr, *d_red = nullptr;
+    unsigned long long *d_count = nullptr;          // counter of invalid elements in borrowed device arrays
     double *d_mom = nullptr;                        // moments: J, H, K per group, then per point J, H, K, f integrated
     double *d_dnu = nullptr;                        // group widths (1 for a grey group)
     double *h_red = nullptr;                        // pinned host copy of the per-group residual sums
@@ -224,6 +225,54 @@ rrt_status alloc_upload_real(rrt_problem *pr, void **dst, const std::vector<doub
     rrt_status s = pr_alloc(pr, dst, v.size() * pr->esz);
     if (s) return s;
     return upload_real(pr, *dst, v.data(), v.size());
+}
+
+// a caller's pointer that device code may read: device (or managed) memory
+rrt_status check_dev_ptr(const void *p, const char *what)
+{
+    if (!p) return fail(RRT_E_INVALID, std::string(what) + " is NULL");
+    hipPointerAttribute_t at{};
+    const hipError_t e = hipPointerGetAttributes(&at, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(RRT_E_INVALID, std::string(what) + " is not device memory");
+    }
+    if (at.type != hipMemoryTypeDevice && at.type != hipMemoryTypeManaged)
+        return fail(RRT_E_INVALID, std::string(what) + " is not device memory");
+    return RRT_OK;
+}
+
+// copy between the caller's device memory and the problem's, on the problem's stream;
+// returns once the copy is complete (the caller's buffer is borrowed for the call only)
+rrt_status copy_dev(rrt_problem *pr, void *dst, const void *src, size_t bytes)
+{
+    HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, pr->stream));
+    HIPCHK(hipStreamSynchronize(pr->stream));
+    return RRT_OK;
+}
+
+// elements of a device array in the working precision that are not finite or (check_lo) below lo
+rrt_status count_bad_dev(rrt_problem *pr, const void *x, size_t n, double lo, bool check_lo, unsigned long long *bad)
+{
+    rrt_status s = pr_alloc(pr, (void **)&pr->d_count, sizeof(unsigned long long));
+    if (s) return s;
+    HIPCHK(hipMemsetAsync(pr->d_count, 0, sizeof(unsigned long long), pr->stream));
+    if (pr->prec == RRT_FP64)
+        rrt::launch_count_bad<double>((long)n, (const double *)x, lo, check_lo, pr->d_count, pr->stream);
+    else
+        rrt::launch_count_bad<float>((long)n, (const float *)x, (float)lo, check_lo, pr->d_count, pr->stream);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipMemcpyAsync(bad, pr->d_count, sizeof(unsigned long long), hipMemcpyDeviceToHost, pr->stream));
+    HIPCHK(hipStreamSynchronize(pr->stream));
+    return RRT_OK;
+}
+
+// the caller's device copy of a host-side argument array (doubles), read back for a set-up call
+rrt_status read_back(const double *src, size_t n, std::vector<double> &dst)
+{
+    dst.resize(n);
+    HIPCHK(hipMemcpy(dst.data(), src, n * 8, hipMemcpyDeviceToHost));
+    return RRT_OK;
 }
 
 // drop the captured sweeps (their buffers or kernel choices are about to change)
@@ -953,7 +1002,7 @@ void rrt_destroy(rrt_problem *pr)
                     pr->d_Y16, pr->d_WYt16,
                     pr->d_A, pr->d_sg, pr->d_tnode, pr->d_twt, pr->d_torder, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_gam, pr->d_chi0, pr->d_chilab, pr->d_plan, pr->d_chilabT, pr->d_bc[0], pr->d_bc[1],
                     pr->d_S, pr->d_Snew, pr->d_Ilm, pr->d_co, pr->d_St, pr->d_Xt, pr->d_Ilab, pr->d_I, pr->d_Iin,
-                    pr->d_acc, pr->d_chain[0], pr->d_chain[1], pr->d_chain[2], pr->d_chain[3], pr->d_partial, pr->d_red, pr->d_mom, pr->d_dnu};
+                    pr->d_acc, pr->d_chain[0], pr->d_chain[1], pr->d_chain[2], pr->d_chain[3], pr->d_partial, pr->d_red, pr->d_count, pr->d_mom, pr->d_dnu};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (int i = 0; i < KI_N; ++i)
@@ -1640,6 +1689,150 @@ rrt_status rrt_ray_trace(rrt_problem *pr, const double *S_tilde, const double *c
     });
     if (s) return s;
     return download_real(pr, I_lab, pr->d_Ilab, n);
+}
+
+rrt_status rrt_get_lab_source(rrt_problem *pr, double dt_stage, double *S_tilde)
+{
+    if (!pr || !S_tilde) return fail(RRT_E_INVALID, "NULL argument");
+    if (!pr->medium_set) return fail(RRT_E_STATE, "rrt_set_medium must come first");
+    if (!(dt_stage >= 0) || !std::isfinite(dt_stage)) return fail(RRT_E_INVALID, "dt_stage must be >= 0");
+    rrt_status s = dispatch(pr, [&](auto &e) {
+        return e.to_lab(pr->d_S, dt_stage > 0 ? pr->d_I : nullptr, dt_stage > 0 ? 1.0 / dt_stage : 0.0);
+    });
+    if (s) return s;
+    return download_real(pr, S_tilde, pr->d_St, do_elems(pr));
+}
+
+// ---- device-pointer variants ----------------------------------------------
+
+rrt_status rrt_set_medium_dev(rrt_problem *pr, const double *kappa, const double *sigma, const double *bnu,
+                              const double *beta, const double *kte)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    rrt_status s;
+    if ((s = check_dev_ptr(kappa, "kappa")) || (s = check_dev_ptr(sigma, "sigma")) || (s = check_dev_ptr(bnu, "bnu")))
+        return s;
+    if ((beta && (s = check_dev_ptr(beta, "beta"))) || (kte && (s = check_dev_ptr(kte, "kte")))) return s;
+    const size_t P = (size_t)pr->P, G = (size_t)pr->G;
+    std::vector<double> k, sg, b, v, t;
+    if ((s = read_back(kappa, P * G, k)) || (s = read_back(sigma, P, sg)) || (s = read_back(bnu, P * G, b))) return s;
+    if ((beta && (s = read_back(beta, P * 3, v))) || (kte && (s = read_back(kte, P, t)))) return s;
+    return rrt_set_medium(pr, k.data(), sg.data(), b.data(), beta ? v.data() : nullptr, kte ? t.data() : nullptr);
+}
+
+rrt_status rrt_set_intensity_dev(rrt_problem *pr, const void *I_lab)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    rrt_status s = check_dev_ptr(I_lab, "I_lab");
+    if (s) return s;
+    return copy_dev(pr, pr->d_I, I_lab, do_elems(pr) * pr->esz);
+}
+
+rrt_status rrt_set_source_sh_dev(rrt_problem *pr, const void *S_lm)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    rrt_status s = check_dev_ptr(S_lm, "S_lm");
+    if (s) return s;
+    return copy_dev(pr, pr->d_S, S_lm, sh_elems(pr) * pr->esz);
+}
+
+rrt_status rrt_get_source_sh_dev(rrt_problem *pr, void *S_lm)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    rrt_status s = check_dev_ptr(S_lm, "S_lm");
+    if (s) return s;
+    return copy_dev(pr, S_lm, pr->d_S, sh_elems(pr) * pr->esz);
+}
+
+rrt_status rrt_get_intensity_sh_dev(rrt_problem *pr, void *I_lm)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    rrt_status s = check_dev_ptr(I_lm, "I_lm");
+    if (s) return s;
+    return copy_dev(pr, I_lm, pr->d_Ilm, sh_elems(pr) * pr->esz);
+}
+
+rrt_status rrt_get_intensity_dev(rrt_problem *pr, void *I_lab)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    rrt_status s = check_dev_ptr(I_lab, "I_lab");
+    if (s) return s;
+    return copy_dev(pr, I_lab, pr->d_I, do_elems(pr) * pr->esz);
+}
+
+rrt_status rrt_get_sweep_intensity_dev(rrt_problem *pr, void *I_lab)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    rrt_status s = check_dev_ptr(I_lab, "I_lab");
+    if (s) return s;
+    return copy_dev(pr, I_lab, pr->d_Ilab, do_elems(pr) * pr->esz);
+}
+
+rrt_status rrt_get_lab_source_dev(rrt_problem *pr, double dt_stage, void *S_tilde)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    rrt_status s = check_dev_ptr(S_tilde, "S_tilde");
+    if (s) return s;
+    if (!pr->medium_set) return fail(RRT_E_STATE, "rrt_set_medium must come first");
+    if (!(dt_stage >= 0) || !std::isfinite(dt_stage)) return fail(RRT_E_INVALID, "dt_stage must be >= 0");
+    s = dispatch(pr, [&](auto &e) {
+        return e.to_lab(pr->d_S, dt_stage > 0 ? pr->d_I : nullptr, dt_stage > 0 ? 1.0 / dt_stage : 0.0);
+    });
+    if (s) return s;
+    return copy_dev(pr, S_tilde, pr->d_St, do_elems(pr) * pr->esz);
+}
+
+rrt_status rrt_get_moments_dev(rrt_problem *pr, rrt_frame frame, double *J, double *H, double *K)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    if (frame != RRT_FRAME_LAB && frame != RRT_FRAME_COMOVING) return fail(RRT_E_INVALID, "unknown frame");
+    rrt_status s;
+    if ((J && (s = check_dev_ptr(J, "J"))) || (H && (s = check_dev_ptr(H, "H"))) || (K && (s = check_dev_ptr(K, "K"))))
+        return s;
+    s = dispatch(pr, [&](auto &e) { return e.moments_launch(frame); });
+    if (s) return s;
+    const size_t pg = (size_t)pr->P * pr->G;
+    const double *dJ = pr->d_mom, *dH = dJ + pg, *dK = dH + 3 * pg;
+    if (J) HIPCHK(hipMemcpyAsync(J, dJ, pg * 8, hipMemcpyDeviceToDevice, pr->stream));
+    if (H) HIPCHK(hipMemcpyAsync(H, dH, pg * 24, hipMemcpyDeviceToDevice, pr->stream));
+    if (K) HIPCHK(hipMemcpyAsync(K, dK, pg * 48, hipMemcpyDeviceToDevice, pr->stream));
+    HIPCHK(hipStreamSynchronize(pr->stream));
+    return RRT_OK;
+}
+
+rrt_status rrt_get_moments_integrated_dev(rrt_problem *pr, rrt_frame frame, double *out)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    if (frame != RRT_FRAME_LAB && frame != RRT_FRAME_COMOVING) return fail(RRT_E_INVALID, "unknown frame");
+    rrt_status s = check_dev_ptr(out, "out");
+    if (s) return s;
+    s = dispatch(pr, [&](auto &e) { return e.moments_launch(frame); });
+    if (s) return s;
+    const size_t pg = (size_t)pr->P * pr->G;
+    return copy_dev(pr, out, pr->d_mom + 10 * pg, (size_t)pr->P * 16 * 8);
+}
+
+rrt_status rrt_ray_trace_dev(rrt_problem *pr, const void *S_tilde, const void *chi_tilde, void *I_lab)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    rrt_status s;
+    if ((s = check_dev_ptr(S_tilde, "S_tilde")) || (s = check_dev_ptr(chi_tilde, "chi_tilde")) ||
+        (s = check_dev_ptr(I_lab, "I_lab")))
+        return s;
+    const size_t n = do_elems(pr);
+    unsigned long long bad_s = 0, bad_x = 0;
+    if ((s = count_bad_dev(pr, S_tilde, n, 0.0, false, &bad_s)) || (s = count_bad_dev(pr, chi_tilde, n, 0.0, true, &bad_x)))
+        return s;
+    if (bad_s || bad_x) return fail(RRT_E_INVALID, "S~ must be finite and chi~ finite and >= 0");
+    if ((s = pr_alloc(pr, &pr->d_Xt, n * pr->esz))) return s;
+    if ((s = copy_dev(pr, pr->d_St, S_tilde, n * pr->esz)) || (s = copy_dev(pr, pr->d_Xt, chi_tilde, n * pr->esz)))
+        return s;
+    s = dispatch(pr, [&](auto &e) {
+        e.trace(pr->d_St, pr->d_Ilab, 0.0, true);
+        return e.check_launch();
+    });
+    if (s) return s;
+    return copy_dev(pr, I_lab, pr->d_Ilab, n * pr->esz);
 }
 
 rrt_status rrt_set_autotune(rrt_problem *pr, int enable)

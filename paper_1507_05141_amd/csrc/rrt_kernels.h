@@ -198,6 +198,10 @@ template <typename real> void launch_ng_extrapolate(long n, const double *dots, 
 template <typename real> void launch_combine3(long n, double c0, const real *x0, double c1, const real *x1, double c2, const real *x2, real *out, hipStream_t st);
 template <typename real> void launch_rk_stage(long n, const real *R, real *Iin, real *acc, real *In, int first, int last, real coef, hipStream_t st);
 
+// elements of x[n] that are not finite or (check_lo) below lo, added to the device counter *count
+template <typename real> void launch_count_bad(long n, const real *x, real lo, int check_lo, unsigned long long *count,
+                                               hipStream_t st);
+
 hipError_t set_lds_limits(size_t bytes);
 
 }  // namespace rrt

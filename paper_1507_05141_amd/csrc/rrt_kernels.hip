@@ -2918,6 +2918,25 @@ void launch_rk_stage(long n, const real *R, real *Iin, real *acc, real *In, int 
     hipLaunchKernelGGL(k_rk_stage<real>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, R, Iin, acc, In, first, last, coef);
 }
 
+// number of elements of x[n] that are not finite, or (check_lo) below lo, added to *count
+template <typename real>
+__global__ void __launch_bounds__(256) k_count_bad(long n, const real *__restrict__ x, real lo, int check_lo,
+                                                   unsigned long long *count)
+{
+    unsigned c = 0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const real v = x[i];
+        c += (!isfinite(v) || (check_lo && v < lo)) ? 1u : 0u;
+    }
+    if (c) atomicAdd(count, (unsigned long long)c);
+}
+template <typename real>
+void launch_count_bad(long n, const real *x, real lo, int check_lo, unsigned long long *count, hipStream_t st)
+{
+    const unsigned nb = (unsigned)std::max<long>(1, std::min<long>((n + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_count_bad<real>, dim3(nb), dim3(256), 0, st, n, x, lo, check_lo, count);
+}
+
 hipError_t set_lds_limits(size_t bytes)
 {
     const void *fns[] = {reinterpret_cast<const void *>(&k_trace<float, kChiGrey, 1, 1, true>),
@@ -3096,7 +3115,8 @@ hipError_t set_lds_limits(size_t bytes)
                                               real *, hipStream_t);                                              \
     template void launch_combine3<real>(long, double, const real *, double, const real *, double, const real *, \
                                         real *, hipStream_t);                                                   \
-    template void launch_rk_stage<real>(long, const real *, real *, real *, real *, int, int, real, hipStream_t);
+    template void launch_rk_stage<real>(long, const real *, real *, real *, real *, int, int, real, hipStream_t); \
+    template void launch_count_bad<real>(long, const real *, real, int, unsigned long long *, hipStream_t);
 
 RRT_INSTANTIATE(float)
 RRT_INSTANTIATE(double)

@@ -1195,3 +1195,20 @@ def test_moving_emitter_is_beamed_as_the_cube_of_the_doppler_factor(bx):
             lit = A > 1e-6 * A.max()
             worst = max(worst, float(np.max(np.abs(A[lit] / (M[lit] * ratio) - 1))))
     assert worst < 1e-8
+
+
+def test_single_ordinate_trace_and_extinction_match_the_full_oracle_steps():
+    """The oracle's one-ordinate entry points (used to check sampled marches of
+    full-size sweeps) give exactly the corresponding slices of its full S3 and
+    S4: the extinction chi~ = chi_lab + 1/(c dt) of the boost, and the march of
+    one ordinate and group including its inflow boundary (Sec. 2, Eqs. 5-8)."""
+    spec = W.random_medium(n=6, nz=5, ng=4, lmax=3, nmu=6, nphi=8, seed=21)
+    o = oracle.Oracle(spec)
+    gen = np.random.default_rng(5)
+    S0 = gen.uniform(0.1, 1.0, o.co_shape())
+    Ip = gen.uniform(0.0, 1.0, o.lab_shape())
+    St, Xt = o.boost(S0, Ip, 3.0)
+    I = o.trace(St, Xt)
+    for k, g in [(0, 0), (o.K - 1, o.G - 1), (7, 2), (20, 1), (30, 3)]:
+        assert np.array_equal(o.lab_extinction(k, g, 3.0), Xt[k, :, g])
+        assert np.array_equal(o.trace_one(k, g, St[k, :, g], Xt[k, :, g]), I[k, :, g])
