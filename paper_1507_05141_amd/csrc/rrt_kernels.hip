@@ -25,16 +25,19 @@ __device__ __forceinline__ double fast_rcp(double x) { return 1.0 / x; }
 // E_3 = (6/h^3) P(4, h), P the regularised lower incomplete gamma function:
 // for h < hs by its positive series P(4, h) = h^4 e^{-h} sum_k h^k/(k+4)!, else
 // as 1 - e^{-h}(1 + h + h^2/2 + h^3/6) (at most ~4 bits of cancellation).
-// Both branches are evaluated and selected, so a wave never diverges.
+// The series is evaluated only when some lane of the wave needs it, and then
+// selected per lane, so a wave never diverges.
 template <typename real> struct BezTraits;
 template <> struct BezTraits<double> {
     static constexpr double hs = 1.5;
     static constexpr int nt = 18;      // last term < 1e-16 of the first at h = hs
+    static constexpr double tau_cut = 80.0;    // e^-80 ~ 2e-35
     __device__ static double ex(double h) { return exp(-h); }
 };
 template <> struct BezTraits<float> {
     static constexpr float hs = 1.5f;
     static constexpr int nt = 10;      // last term < 4e-8 of the first at h = hs
+    static constexpr float tau_cut = 40.0f;    // e^-40 ~ 4e-18
     __device__ static float ex(float h) { return __expf(-h); }
 };
 
@@ -59,11 +62,16 @@ __device__ __forceinline__ void bezier_moments(real h, real &ex, real &E0, real 
 {
     using T = BezTraits<real>;
     ex = T::ex(h);
-    const real e3s = real(6) * h * ex * GammaSeries<real, 0, T::nt>::eval(h);
     const real ih = fast_rcp(h);
     const real poly = ((h * real(1.0 / 6.0) + real(0.5)) * h + real(1)) * h + real(1);
-    const real e3l = real(6) * (real(1) - ex * poly) * (ih * ih * ih);
-    E3 = (h < T::hs) ? e3s : e3l;
+    E3 = real(6) * (real(1) - ex * poly) * (ih * ih * ih);
+    // the series only where some lane of the wave needs it (a wave-uniform
+    // branch: optically thick steps, e.g. under a time term, skip it)
+    if (__any(h < T::hs)) {
+        asm volatile("");       // not speculated: the branch is what saves the work
+        const real e3s = real(6) * h * ex * GammaSeries<real, 0, T::nt>::eval(h);
+        E3 = (h < T::hs) ? e3s : E3;
+    }
     E2 = h * real(1.0 / 3.0) * (E3 + ex);
     E1 = h * real(0.5) * (E2 + ex);
     E0 = h * (E1 + ex);
@@ -601,6 +609,17 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a, int 
     }
     __syncthreads();
     const real hds = real(0.5) * (real)gm.ds;
+    // Under a time term every piece is at least 2 hds / (c dt) deep (chi~ >= 1/(c dt)):
+    // what enters the path more than tau_cut before p arrives attenuated below
+    // e^-tau_cut, under the working precision's resolution, so the walk starts at
+    // path point c0, the nearest at least that deep, with I = S~ there (c0 = npc:
+    // the whole path).  An extinction array may be thin: no cut.
+    int c0 = npc;
+    if (MULTI && XMODE != kChiArray && add > real(0)) {
+        const real tmin = real(2) * hds * add;
+        if (tmin * (real)npc > BezTraits<real>::tau_cut)
+            c0 = max(1, min(npc, (int)ceil(BezTraits<real>::tau_cut / tmin)));
+    }
     // one piece per plane: second upwind, upwind and downwind taps (each on a grid plane)
     real wts[3][4];
 #pragma unroll
@@ -656,31 +675,56 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a, int 
             // there and the one that starts there.
 #pragma unroll
             for (int c = 0; c < MAXPT; ++c) {
-                const int i = pi[c], j = pj[c];
+                // cells left before the periodic wrap in x and y
+                const int rx = nx - pi[c], ry = ny - pj[c];
                 P Sup2, Sup, Scur, Sdn;          // path points c + 2, c + 1, c, c - 1 of the walk
                 PX Xup2, Xup, Xcur, Xdn;
                 real w[8];
+                // the tap cell of path point pc: the point's own cell moved by the (uniform)
+                // offset, wrapped where it passes the plane's edge (as tap_cell)
                 auto taps_of = [&](int pc) {
 #pragma unroll
                     for (int n = 0; n < 8; ++n) w[n] = tp[pc].w[n];
-                    return tap_cell(tp[pc], i, j, q);
+                    const int ix = tp[pc].ix, iy = tp[pc].iy;
+                    int cl = self[c] + (ix + iy * RS);
+                    if (ix >= rx) cl -= nx;
+                    if (iy >= ry) cl -= ny * RS;
+                    return cl;
                 };
-                if (has_uu) {                    // path point npc + 1: one piece beyond u
-                    const int cl = taps_of(npc + 1);
-                    Sup2 = bil2(Sul, Suul, cl, RS, w);
-                    Xup2 = bil2(Xul, Xuul, cl, RS, w);
-                }
                 P I;
-                {                                // path point npc: u on the upwind plane
-                    const int cl = taps_of(npc);
+                if (c0 == npc) {
+                    if (has_uu) {                // path point npc + 1: one piece beyond u
+                        const int cl = taps_of(npc + 1);
+                        Sup2 = bil2(Sul, Suul, cl, RS, w);
+                        Xup2 = bil2(Xul, Xuul, cl, RS, w);
+                    }
+                    const int cl = taps_of(npc);  // path point npc: u on the upwind plane
                     Sup = bil(Sul, cl, RS, w);
                     Xup = bil(Xul, cl, RS, w);
                     I = bil(Iul, cl, RS, w);
+                } else {
+                    // the walk starts inside the path (c0 < npc): path points c0 + 1 and
+                    // c0 between the planes (c0 + 1 on the upwind plane when it is npc)
+                    int cl = taps_of(c0 + 1);
+                    if (c0 + 1 == npc) {
+                        Sup2 = bil(Sul, cl, RS, w);
+                        Xup2 = bil(Xul, cl, RS, w);
+                    } else {
+                        Sup2 = bil2(Spl, Sul, cl, RS, w);
+                        Xup2 = bil2(Xpl, Xul, cl, RS, w);
+                    }
+                    cl = taps_of(c0);
+                    Sup = bil2(Spl, Sul, cl, RS, w);
+                    Xup = bil2(Xpl, Xul, cl, RS, w);
+                    I = Sup;
                 }
-                {                                // path point npc - 1 (>= 1)
-                    const int cl = taps_of(npc - 1);
+                if (c0 >= 2) {                   // path point c0 - 1
+                    const int cl = taps_of(c0 - 1);
                     Scur = bil2(Spl, Sul, cl, RS, w);
                     Xcur = bil2(Xpl, Xul, cl, RS, w);
+                } else {
+                    Scur = Spl[self[c]];
+                    Xcur = Xpl[self[c]];
                 }
                 // depths of the piece before u and of the first piece (per group unless grey)
                 PX hup, hcur;
@@ -701,7 +745,7 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a, int 
                     }
                 }
 #pragma unroll 1
-                for (int pc = npc - 1; pc >= 0; --pc) {
+                for (int pc = c0 - 1; pc >= 0; --pc) {
                     // piece from path point pc + 1 to pc; the next path point pc - 1
                     const bool pd = pc >= 1 || has_d, puu = pc + 2 <= npc || has_uu;
                     if (pc >= 2) {
