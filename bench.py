@@ -159,6 +159,91 @@ def serving_bench(args):
             "capacity": cap, "stream": res}
 
 
+def vet_bytes(P):
+    """Method bytes of one step of the VET hand-off, per kernel: the flux update
+    reads J, f (6), H (3), chi_F and the momentum exchange (3) and writes H and
+    the exchange; the energy update reads H (3), J, kappa_E, B and the energy
+    exchange and writes J and the exchange (FP64)."""
+    return {"vet_flux": 8 * P * (1 + 6 + 3 + 3 + 1 + 3 + 3), "vet_energy": 8 * P * (3 + 1 + 1 + 1 + 1 + 1 + 1)}
+
+
+def vet_bench(args):
+    """The variable-Eddington-tensor hand-off: nsteps FP64 steps of the
+    frequency-integrated moment equations closed with the Eddington tensor of
+    an anisotropic lab intensity state, on the 64^3 grid of the Compton jet
+    (launch-bound: 262144 points) and on a 64 x 64 x 4096 grid (16.8 M
+    points, streaming-bound; x-y planes of the size the ray trace holds); the
+    roofline of the dominant kernel on the larger grid."""
+    import numpy as np
+    import torch
+
+    from paper_1507_05141_amd import binding as B
+    out = {"metric": "VET moment-update point-steps/s", "unit": "point-steps/s", "n_gpus": 1,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic"}
+    runs = {}
+    for n in (64, 4096):
+        P = 64 * 64 * n
+        spec = dict(nx=64, ny=64, nz=n, lx=1.0, ly=1.0, lz=n / 64.0, nmu=2, nphi=4, lmax=1, edges=None, log_centres=True,
+                    scatter="thomson", kappa=np.full((P, 1), 0.5), sigma=np.full(P, 1.0), bnu=np.full((P, 1), 1.0),
+                    beta=None, kte=None, bc_bot=None, bc_top=None)
+        pr = B.Problem.from_spec(spec, precision=B.FP32, stream=torch.cuda.current_stream().cuda_stream)
+        gen = torch.Generator(device="cuda").manual_seed(7)
+        I = torch.rand((pr.K, P, 1), generator=gen, device="cuda") + 0.1
+        I[0] *= 4.0                                                   # anisotropic: one bright ordinate
+        pr.set_intensity_dev(I)
+        del I
+        cu = lambda lo, hi, shape: lo + (hi - lo) * torch.rand(shape, generator=gen, device="cuda", dtype=torch.float64)
+        kap, chi, Bf = cu(0.0, 2.0, (P,)), cu(0.5, 3.0, (P,)), cu(0.0, 1.0, (P,))
+        J, H, G = cu(0.2, 1.0, (P,)), cu(-0.1, 0.1, (P, 3)), torch.empty((P, 4), dtype=torch.float64, device="cuda")
+        dt = 0.5 / 64
+        steps = max(args.steps, 1) * (20 if n == 64 else 2)
+        pr.vet_step_dev(dt, steps, kap, chi, Bf, J, H, G)            # warm-up
+        torch.cuda.synchronize()
+        pr.set_profiling(True)
+        t0 = time.perf_counter()
+        pr.vet_step_dev(dt, steps, kap, chi, Bf, J, H, G)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kern = {}
+        for k in ("vet_flux", "vet_energy"):
+            c, ms = pr.kernel_time(k)
+            kern[k] = {"launches": c, "avg_ms": ms / c}
+        pr.set_profiling(False)
+        pr.close()
+        b = vet_bytes(P)
+        runs[n] = {"grid": [64, 64, n], "steps": steps, "ms_per_step": el / steps * 1e3, "value": P * steps / el,
+                   "kernels": kern,
+                   "kernel_rooflines": {k: {"bound": "hbm", "achieved_GBps": b[k] / (v["avg_ms"] * 1e-3) / 1e9,
+                                            "frac": b[k] / (v["avg_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBS}
+                                        for k, v in kern.items()}}
+        print(f"  VET 64 x 64 x {n}: {el / steps * 1e3:.3f} ms per step", file=sys.stderr, flush=True)
+    big = runs[4096]
+    PB = 64 * 64 * 4096
+    dom = max(big["kernels"], key=lambda k: big["kernels"][k]["avg_ms"])
+    ach = vet_bytes(PB)[dom] / (big["kernels"][dom]["avg_ms"] * 1e-3) / 1e9
+    out.update(value=big["value"], steps=big["steps"], warmup=big["steps"], ms_per_step=big["ms_per_step"],
+               config={"workload": "vet_handoff_64x64x4096", "grid": big["grid"], "transport_grid_64c": runs[64]},
+               roofline={"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                         "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                         "algorithmic_bytes_per_launch": vet_bytes(PB)[dom],
+                         "avg_launch_ms": big["kernels"][dom]["avg_ms"]},
+               kernels=big["kernels"], kernel_rooflines=big["kernel_rooflines"])
+    if not args.no_cpu_baseline:
+        from oracle.vet import vet_step as ovet
+        n, steps = 64, 4
+        P = n ** 3
+        rs = np.random.default_rng(1)
+        f = np.zeros((P, 6))
+        f[:, :3] = rs.uniform(0.2, 0.5, (P, 3))
+        t0 = time.perf_counter()
+        ovet((n, n, n, 1.0, 1.0, 1.0), f, rs.uniform(0, 2, P), rs.uniform(0.5, 3, P), rs.uniform(0, 1, P),
+             rs.uniform(0.2, 1, P), rs.uniform(-0.1, 0.1, (P, 3)), 0.5 / n, steps)
+        el = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": P * steps / el, "unit": "point-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{steps} steps of the NumPy oracle on 64^3 ({el:.1f} s)"}
+    return out
+
+
 def validation_runs(args):
     """The paper's validation problems (Sec. 3) at its own grid and ordinate
     sizes, in FP32 on the library, each checked against the closed form the
@@ -316,6 +401,8 @@ def main():
     ap.add_argument("--requests", type=int, default=48, help="requests in the --serving stream")
     ap.add_argument("--mix", choices=["small", "full"], default="small",
                     help="--serving request mix: small (n <= 32, G <= 16, L <= 7) or full (n <= 64, G <= 32, L <= 15)")
+    ap.add_argument("--vet", action="store_true",
+                    help="time the variable-Eddington-tensor hand-off (moment update closed with the transport's f)")
     ap.add_argument("--validation", action="store_true",
                     help="run the paper's validation problems (Sec. 3) at its sizes instead of the sweep benchmark")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -337,6 +424,9 @@ def main():
     torch.cuda.set_device(0)
     if args.serving:
         print(json.dumps(serving_bench(args)), flush=True)
+        return
+    if args.vet:
+        print(json.dumps(vet_bench(args)), flush=True)
         return
     if args.validation:
         validation_runs(args)

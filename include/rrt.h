@@ -247,6 +247,34 @@ rrt_status rrt_get_moments_dev(rrt_problem *pr, rrt_frame frame, double *J, doub
 rrt_status rrt_get_moments_integrated_dev(rrt_problem *pr, rrt_frame frame, double *out);  /* [P][16] */
 rrt_status rrt_ray_trace_dev(rrt_problem *pr, const void *S_tilde, const void *chi_tilde, void *I_lab);
 
+/* Variable-Eddington-tensor hand-off (Sec. 4: the tensor from the transfer
+   solution, instead of an approximate closure, in a radiation-hydrodynamics
+   update).  The Eddington tensor f of the lab intensity state (as
+   rrt_get_moments_integrated with RRT_FRAME_LAB; 0 where J = 0) closes the
+   frequency-integrated moment equations
+       dJ/dt + div H = kappa_E (B - J),   dH/dt + div (f J) = -chi_F H
+   (c = 1, angle-averaged moments as everywhere here), advanced nsteps steps
+   of dt by a forward-backward scheme (not in the paper): H from J^n, then J
+   from H^{n+1}, the local terms implicit; central differences on the
+   problem's grid, periodic in x and y, one-sided (first order) on the two z
+   faces.  f is taken once per call.  The hydrodynamics side gives the energy
+   exchange coefficient kappa_E [P] >= 0, the flux extinction chi_F [P] >= 0
+   and the emission B [P]; J [P] and H [P][3] are advanced in place; G [P][4]
+   (may be NULL) receives the exchange with the gas over the call,
+   sum dt kappa_E (J^{n+1} - B) and sum dt chi_F H^{n+1}.  Stable for dt up
+   to 2 h / sqrt(3) with h the smallest grid spacing (f has eigenvalues in
+   [0, 1]).  FP64 in every precision; the work buffer (17 doubles per point)
+   is allocated on first use and counted in rrt_device_bytes.  rrt_vet_step
+   takes host arrays; rrt_vet_step_dev device arrays (validated on the device,
+   borrowed for the call as the other *_dev calls).  Kernel times: "vet_flux",
+   "vet_energy".  Errors: RRT_E_STATE before rrt_set_medium, RRT_E_INVALID for
+   dt <= 0, nsteps < 0, negative or non-finite coefficients, non-finite B, J
+   or H. */
+rrt_status rrt_vet_step(rrt_problem *pr, double dt, int nsteps, const double *kappa_E, const double *chi_F,
+                        const double *B, double *J, double *H, double *G);
+rrt_status rrt_vet_step_dev(rrt_problem *pr, double dt, int nsteps, const double *kappa_E, const double *chi_F,
+                            const double *B, double *J, double *H, double *G);
+
 /* Device bytes the problem needs (0 if the arguments are invalid). */
 size_t rrt_footprint_bytes(const rrt_grid *grid, const rrt_groups *groups, const rrt_angles *angles,
                            rrt_precision precision, int time_dependent, int use_ng);
@@ -292,7 +320,8 @@ rrt_status rrt_graph_count(const rrt_problem *pr, int *count);
    bracketed by HIP events on the problem's stream; rrt_kernel_time returns
    the number of launches and their summed duration (ms) for one kernel name
    ("trace", "sh2do", "boost", "unboost", "do2sh", "source", "reduce",
-   "moments", "rk") since the last reset, synchronising the stream. */
+   "moments", "rk", "vet_flux", "vet_energy") since the last reset,
+   synchronising the stream. */
 rrt_status rrt_set_profiling(rrt_problem *pr, int enable);
 rrt_status rrt_kernel_time(rrt_problem *pr, const char *kernel, int *launches, double *ms);
 

@@ -92,6 +92,8 @@ def lib():
             "rrt_get_moments_dev": [P, I, P, P, P],
             "rrt_get_moments_integrated_dev": [P, I, P],
             "rrt_ray_trace_dev": [P, P, P, P],
+            "rrt_vet_step": [P, D, I, _dp, _dp, _dp, _dp, _dp, _dp],
+            "rrt_vet_step_dev": [P, D, I, P, P, P, P, P, P],
             "rrt_set_profiling": [P, I],
             "rrt_set_graphs": [P, I],
             "rrt_set_autotune": [P, I],
@@ -382,6 +384,29 @@ class Problem:
         _check(lib().rrt_ray_trace_dev(self._h, self._dev(S_tilde, self.lab_shape()), self._dev(chi_tilde, self.lab_shape()),
                                        self._dev(out, self.lab_shape())))
         return out
+
+    # variable-Eddington-tensor hand-off
+    def vet_step(self, dt, nsteps, kappa_E, chi_F, B, J, H):
+        """nsteps steps of the moment equations closed with the state's Eddington
+        tensor: returns (J [P], H [P][3], G [P][4])."""
+        P = self.P
+        k, kp = _in(np.broadcast_to(kappa_E, (P,)))
+        c, cp = _in(np.broadcast_to(chi_F, (P,)))
+        b, bp = _in(np.broadcast_to(B, (P,)))
+        J = np.array(np.broadcast_to(J, (P,)), dtype=np.float64)
+        H = np.array(np.broadcast_to(H, (P, 3)), dtype=np.float64)
+        G = np.zeros((P, 4))
+        _check(lib().rrt_vet_step(self._h, float(dt), int(nsteps), kp, cp, bp, J.ctypes.data_as(_dp),
+                                  H.ctypes.data_as(_dp), G.ctypes.data_as(_dp)))
+        return J, H, G
+
+    def vet_step_dev(self, dt, nsteps, kappa_E, chi_F, B, J, H, G=None):
+        """The same on float64 CUDA tensors, J and H (and G) updated in place."""
+        P = self.P
+        _check(lib().rrt_vet_step_dev(self._h, float(dt), int(nsteps), self._dev(kappa_E, (P,), True),
+                                      self._dev(chi_F, (P,), True), self._dev(B, (P,), True),
+                                      self._dev(J, (P,), True), self._dev(H, (P, 3), True),
+                                      self._dev(G, (P, 4), True) if G is not None else None))
 
     def set_autotune(self, enable=True):
         _check(lib().rrt_set_autotune(self._h, int(enable)))

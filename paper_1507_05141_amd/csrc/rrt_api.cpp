@@ -38,8 +38,8 @@ rrt_status fail(rrt_status s, const std::string &m)
             return fail(RRT_E_DEVICE, std::string(#call) + ": " + hipGetErrorString(e_));  \
     } while (0)
 
-enum KId { KI_TRACE, KI_SH2DO, KI_BOOST, KI_UNBOOST, KI_DO2SH, KI_SOURCE, KI_REDUCE, KI_MOMENTS, KI_RK, KI_N };
-const char *kNames[KI_N] = {"trace", "sh2do", "boost", "unboost", "do2sh", "source", "reduce", "moments", "rk"};
+enum KId { KI_TRACE, KI_SH2DO, KI_BOOST, KI_UNBOOST, KI_DO2SH, KI_SOURCE, KI_REDUCE, KI_MOMENTS, KI_RK, KI_VET_FLUX, KI_VET_ENERGY, KI_N };
+const char *kNames[KI_N] = {"trace", "sh2do", "boost", "unboost", "do2sh", "source", "reduce", "moments", "rk", "vet_flux", "vet_energy"};
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr size_t kMaxLds = 160 * 1024;
@@ -106,6 +106,7 @@ struct rrt_problem {
     void *d_chain[4] = {nullptr, nullptr, nullptr, nullptr};
     double *d_partial = nullptr, *d_red = nullptr;
     unsigned long long *d_count = nullptr;          // counter of invalid elements in borrowed device arrays
+    double *d_vet = nullptr;                        // VET hand-off: f [6][P], then kappa, chi, B, J, H [3], G [4] per point
     double *d_mom = nullptr;                        // moments: J, H, K per group, then per point J, H, K, f integrated
     double *d_dnu = nullptr;                        // group widths (1 for a grey group)
     double *h_red = nullptr;                        // pinned host copy of the per-group residual sums
@@ -251,13 +252,15 @@ rrt_status copy_dev(rrt_problem *pr, void *dst, const void *src, size_t bytes)
     return RRT_OK;
 }
 
-// elements of a device array in the working precision that are not finite or (check_lo) below lo
-rrt_status count_bad_dev(rrt_problem *pr, const void *x, size_t n, double lo, bool check_lo, unsigned long long *bad)
+// elements of a device array (FP64 when fp64, else the working precision) that are not finite
+// or (check_lo) below lo
+rrt_status count_bad_dev(rrt_problem *pr, const void *x, size_t n, double lo, bool check_lo, unsigned long long *bad,
+                         bool fp64 = false)
 {
     rrt_status s = pr_alloc(pr, (void **)&pr->d_count, sizeof(unsigned long long));
     if (s) return s;
     HIPCHK(hipMemsetAsync(pr->d_count, 0, sizeof(unsigned long long), pr->stream));
-    if (pr->prec == RRT_FP64)
+    if (fp64 || pr->prec == RRT_FP64)
         rrt::launch_count_bad<double>((long)n, (const double *)x, lo, check_lo, pr->d_count, pr->stream);
     else
         rrt::launch_count_bad<float>((long)n, (const float *)x, (float)lo, check_lo, pr->d_count, pr->stream);
@@ -1002,7 +1005,7 @@ void rrt_destroy(rrt_problem *pr)
                     pr->d_Y16, pr->d_WYt16,
                     pr->d_A, pr->d_sg, pr->d_tnode, pr->d_twt, pr->d_torder, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_gam, pr->d_chi0, pr->d_chilab, pr->d_plan, pr->d_chilabT, pr->d_bc[0], pr->d_bc[1],
                     pr->d_S, pr->d_Snew, pr->d_Ilm, pr->d_co, pr->d_St, pr->d_Xt, pr->d_Ilab, pr->d_I, pr->d_Iin,
-                    pr->d_acc, pr->d_chain[0], pr->d_chain[1], pr->d_chain[2], pr->d_chain[3], pr->d_partial, pr->d_red, pr->d_count, pr->d_mom, pr->d_dnu};
+                    pr->d_acc, pr->d_chain[0], pr->d_chain[1], pr->d_chain[2], pr->d_chain[3], pr->d_partial, pr->d_red, pr->d_count, pr->d_vet, pr->d_mom, pr->d_dnu};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     for (int i = 0; i < KI_N; ++i)
@@ -1833,6 +1836,93 @@ rrt_status rrt_ray_trace_dev(rrt_problem *pr, const void *S_tilde, const void *c
     });
     if (s) return s;
     return copy_dev(pr, I_lab, pr->d_Ilab, n * pr->esz);
+}
+
+// ---- variable-Eddington-tensor hand-off --------------------------------------
+
+// Eddington tensor of the lab intensity state into d_vet, then nsteps steps on the
+// device arrays (G zeroed first); returns after the stream completes
+static rrt_status vet_run(rrt_problem *pr, double dt, int nsteps, const double *kap, const double *chi,
+                          const double *B, double *J, double *H, double *G)
+{
+    const long P = pr->P;
+    rrt_status s = dispatch(pr, [&](auto &e) { return e.moments_launch(RRT_FRAME_LAB); });
+    if (s) return s;
+    rrt::launch_vet_f(P, pr->d_mom + (size_t)10 * P * pr->G, pr->d_vet, pr->stream);
+    HIPCHK(hipMemsetAsync(G, 0, (size_t)P * 4 * 8, pr->stream));
+    rrt::VetArgs a;
+    a.nx = pr->nx; a.ny = pr->ny; a.nz = pr->nz; a.P = P;
+    const double dx = pr->lx / pr->nx, dy = pr->ly / pr->ny, dz = pr->nz > 1 ? pr->lz / (pr->nz - 1) : 1.0;
+    a.idx2 = 0.5 / dx; a.idy2 = 0.5 / dy; a.idz2 = 0.5 / dz; a.idz = 1.0 / dz;
+    a.dt = dt; a.f = pr->d_vet; a.kap = kap; a.chi = chi; a.B = B; a.J = J; a.H = H; a.G = G;
+    for (int n = 0; n < nsteps; ++n) {
+        prof_begin(pr, KI_VET_FLUX);
+        rrt::launch_vet_flux(a, pr->stream);
+        prof_end(pr, KI_VET_FLUX);
+        prof_begin(pr, KI_VET_ENERGY);
+        rrt::launch_vet_energy(a, pr->stream);
+        prof_end(pr, KI_VET_ENERGY);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(pr->stream));
+    return RRT_OK;
+}
+
+static rrt_status vet_args(rrt_problem *pr, double dt, int nsteps)
+{
+    if (!pr) return fail(RRT_E_INVALID, "problem is NULL");
+    if (!pr->medium_set) return fail(RRT_E_STATE, "rrt_set_medium must come first");
+    if (!(dt > 0) || !std::isfinite(dt) || nsteps < 0) return fail(RRT_E_INVALID, "need dt > 0 and nsteps >= 0");
+    return pr_alloc(pr, (void **)&pr->d_vet, (size_t)pr->P * 17 * 8);
+}
+
+rrt_status rrt_vet_step(rrt_problem *pr, double dt, int nsteps, const double *kappa_E, const double *chi_F,
+                        const double *B, double *J, double *H, double *G)
+{
+    rrt_status s = vet_args(pr, dt, nsteps);
+    if (s) return s;
+    if (!kappa_E || !chi_F || !B || !J || !H) return fail(RRT_E_INVALID, "NULL argument");
+    const size_t P = (size_t)pr->P;
+    for (size_t p = 0; p < P; ++p) {
+        if (!(kappa_E[p] >= 0) || !std::isfinite(kappa_E[p]) || !(chi_F[p] >= 0) || !std::isfinite(chi_F[p]))
+            return fail(RRT_E_INVALID, "kappa_E and chi_F must be finite and >= 0");
+        if (!std::isfinite(B[p]) || !std::isfinite(J[p]) || !std::isfinite(H[3 * p]) || !std::isfinite(H[3 * p + 1]) ||
+            !std::isfinite(H[3 * p + 2]))
+            return fail(RRT_E_INVALID, "B, J and H must be finite");
+    }
+    double *dk = pr->d_vet + 6 * P, *dc = dk + P, *db = dc + P, *dj = db + P, *dh = dj + P, *dg = dh + 3 * P;
+    HIPCHK(hipMemcpyAsync(dk, kappa_E, P * 8, hipMemcpyHostToDevice, pr->stream));
+    HIPCHK(hipMemcpyAsync(dc, chi_F, P * 8, hipMemcpyHostToDevice, pr->stream));
+    HIPCHK(hipMemcpyAsync(db, B, P * 8, hipMemcpyHostToDevice, pr->stream));
+    HIPCHK(hipMemcpyAsync(dj, J, P * 8, hipMemcpyHostToDevice, pr->stream));
+    HIPCHK(hipMemcpyAsync(dh, H, P * 24, hipMemcpyHostToDevice, pr->stream));
+    if ((s = vet_run(pr, dt, nsteps, dk, dc, db, dj, dh, dg))) return s;
+    HIPCHK(hipMemcpyAsync(J, dj, P * 8, hipMemcpyDeviceToHost, pr->stream));
+    HIPCHK(hipMemcpyAsync(H, dh, P * 24, hipMemcpyDeviceToHost, pr->stream));
+    if (G) HIPCHK(hipMemcpyAsync(G, dg, P * 32, hipMemcpyDeviceToHost, pr->stream));
+    HIPCHK(hipStreamSynchronize(pr->stream));
+    return RRT_OK;
+}
+
+rrt_status rrt_vet_step_dev(rrt_problem *pr, double dt, int nsteps, const double *kappa_E, const double *chi_F,
+                            const double *B, double *J, double *H, double *G)
+{
+    rrt_status s = vet_args(pr, dt, nsteps);
+    if (s) return s;
+    if ((s = check_dev_ptr(kappa_E, "kappa_E")) || (s = check_dev_ptr(chi_F, "chi_F")) || (s = check_dev_ptr(B, "B")) ||
+        (s = check_dev_ptr(J, "J")) || (s = check_dev_ptr(H, "H")) || (G && (s = check_dev_ptr(G, "G"))))
+        return s;
+    const size_t P = (size_t)pr->P;
+    unsigned long long bad[5] = {0, 0, 0, 0, 0};
+    if ((s = count_bad_dev(pr, kappa_E, P, 0.0, true, &bad[0], true)) ||
+        (s = count_bad_dev(pr, chi_F, P, 0.0, true, &bad[1], true)) ||
+        (s = count_bad_dev(pr, B, P, 0.0, false, &bad[2], true)) ||
+        (s = count_bad_dev(pr, J, P, 0.0, false, &bad[3], true)) ||
+        (s = count_bad_dev(pr, H, 3 * P, 0.0, false, &bad[4], true)))
+        return s;
+    if (bad[0] || bad[1]) return fail(RRT_E_INVALID, "kappa_E and chi_F must be finite and >= 0");
+    if (bad[2] || bad[3] || bad[4]) return fail(RRT_E_INVALID, "B, J and H must be finite");
+    return vet_run(pr, dt, nsteps, kappa_E, chi_F, B, J, H, G ? G : pr->d_vet + 13 * P);
 }
 
 rrt_status rrt_set_autotune(rrt_problem *pr, int enable)

@@ -198,6 +198,19 @@ template <typename real> void launch_ng_extrapolate(long n, const double *dots, 
 template <typename real> void launch_combine3(long n, double c0, const real *x0, double c1, const real *x1, double c2, const real *x2, real *out, hipStream_t st);
 template <typename real> void launch_rk_stage(long n, const real *R, real *Iin, real *acc, real *In, int first, int last, real coef, hipStream_t st);
 
+// variable-Eddington-tensor hand-off (FP64): one step of the closed moment equations
+struct VetArgs {
+    int nx, ny, nz;
+    long P;
+    double idx2, idy2, idz2, idz;       // 1/(2 dx), 1/(2 dy), 1/(2 dz), 1/dz
+    double dt;
+    const double *f;                    // Eddington tensor, SoA [6][P]: xx, yy, zz, xy, xz, yz
+    const double *kap, *chi, *B;        // [P] energy exchange, flux extinction, emission
+    double *J, *H, *G;                  // [P], [P][3], [P][4]: updated in place
+};
+void launch_vet_f(long P, const double *mom, double *f, hipStream_t st);
+void launch_vet_flux(const VetArgs &a, hipStream_t st);       // H^{n+1} and the momentum exchange
+void launch_vet_energy(const VetArgs &a, hipStream_t st);     // then J^{n+1} and the energy exchange
 // elements of x[n] that are not finite or (check_lo) below lo, added to the device counter *count
 template <typename real> void launch_count_bad(long n, const real *x, real lo, int check_lo, unsigned long long *count,
                                                hipStream_t st);

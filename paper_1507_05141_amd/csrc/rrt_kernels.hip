@@ -2962,6 +2962,102 @@ void launch_rk_stage(long n, const real *R, real *Iin, real *acc, real *In, int 
     hipLaunchKernelGGL(k_rk_stage<real>, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, R, Iin, acc, In, first, last, coef);
 }
 
+// ---------------------------------------------------------------------------
+// Variable-Eddington-tensor hand-off: the frequency-integrated moment equations
+// dJ/dt + div H = kappa_E (B - J), dH/dt + div(f J) = -chi_F H closed with the
+// transport's Eddington tensor f, advanced by the forward-backward scheme (H
+// from J^n, then J from H^{n+1}; the local terms implicit).  Central
+// differences, periodic in x and y, one-sided on the z faces; one thread per
+// point, neighbours through the caches (each array is streamed once per step).
+// ---------------------------------------------------------------------------
+struct VetNbr {
+    long xp, xm, yp, ym, zp, zm;
+    double sz;      // 1/(2 dz) inside, 1/dz on a z face, 0 with one z plane
+};
+__device__ __forceinline__ VetNbr vet_nbr(const VetArgs &a, long p)
+{
+    const long PL = (long)a.nx * a.ny;
+    const int z = (int)(p / PL);
+    const long r = p - (long)z * PL;
+    const int y = (int)(r / a.nx), x = (int)(r - (long)y * a.nx);
+    VetNbr n;
+    n.xp = p + (x + 1 == a.nx ? 1 - a.nx : 1);
+    n.xm = p + (x == 0 ? a.nx - 1 : -1);
+    n.yp = p + (y + 1 == a.ny ? (long)(1 - a.ny) * a.nx : a.nx);
+    n.ym = p + (y == 0 ? (long)(a.ny - 1) * a.nx : -a.nx);
+    if (a.nz == 1) {
+        n.zp = n.zm = p;
+        n.sz = 0.0;
+    } else if (z == 0) {
+        n.zp = p + PL; n.zm = p; n.sz = a.idz;
+    } else if (z == a.nz - 1) {
+        n.zp = p; n.zm = p - PL; n.sz = a.idz;
+    } else {
+        n.zp = p + PL; n.zm = p - PL; n.sz = a.idz2;
+    }
+    return n;
+}
+
+// H^{n+1} and the momentum exchange; f in SoA order [6][P] (xx, yy, zz, xy, xz, yz)
+__global__ void __launch_bounds__(256) k_vet_flux(VetArgs a)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.P) return;
+    const VetNbr n = vet_nbr(a, p);
+    const double *f = a.f;
+    const long P = a.P;
+    auto fJ = [&](int c, long q) { return f[c * P + q] * a.J[q]; };
+    // column of f_ab for row a: (x, y, z) derivative directions
+    const int col[3][3] = {{0, 3, 4}, {3, 1, 5}, {4, 5, 2}};
+    const double dt = a.dt, den = 1.0 + dt * a.chi[p];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+        const double div = (fJ(col[r][0], n.xp) - fJ(col[r][0], n.xm)) * a.idx2 +
+                           (fJ(col[r][1], n.yp) - fJ(col[r][1], n.ym)) * a.idy2 +
+                           (fJ(col[r][2], n.zp) - fJ(col[r][2], n.zm)) * n.sz;
+        const double h = (a.H[3 * p + r] - dt * div) / den;
+        a.H[3 * p + r] = h;
+        a.G[4 * p + 1 + r] += dt * a.chi[p] * h;
+    }
+}
+
+// J^{n+1} from H^{n+1} and the energy exchange
+__global__ void __launch_bounds__(256) k_vet_energy(VetArgs a)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= a.P) return;
+    const VetNbr n = vet_nbr(a, p);
+    const double *H = a.H;
+    const double divH = (H[3 * n.xp] - H[3 * n.xm]) * a.idx2 + (H[3 * n.yp + 1] - H[3 * n.ym + 1]) * a.idy2 +
+                        (H[3 * n.zp + 2] - H[3 * n.zm + 2]) * n.sz;
+    const double dt = a.dt, k = a.kap[p], b = a.B[p];
+    const double j = (a.J[p] - dt * divH + dt * k * b) / (1.0 + dt * k);
+    a.J[p] = j;
+    a.G[4 * p] += dt * k * (j - b);
+}
+
+// f of the integrated moments ([P][16], columns 10..15) into SoA [6][P]
+__global__ void __launch_bounds__(256) k_vet_f(long P, const double *__restrict__ mom, double *__restrict__ f)
+{
+    const long p = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) f[c * P + p] = mom[16 * p + 10 + c];
+}
+
+void launch_vet_f(long P, const double *mom, double *f, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_vet_f, dim3((unsigned)((P + 255) / 256)), dim3(256), 0, st, P, mom, f);
+}
+void launch_vet_flux(const VetArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_vet_flux, dim3((unsigned)((a.P + 255) / 256)), dim3(256), 0, st, a);
+}
+void launch_vet_energy(const VetArgs &a, hipStream_t st)
+{
+    hipLaunchKernelGGL(k_vet_energy, dim3((unsigned)((a.P + 255) / 256)), dim3(256), 0, st, a);
+}
+
 // number of elements of x[n] that are not finite, or (check_lo) below lo, added to *count
 template <typename real>
 __global__ void __launch_bounds__(256) k_count_bad(long n, const real *__restrict__ x, real lo, int check_lo,
