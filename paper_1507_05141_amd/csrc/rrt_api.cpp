@@ -365,7 +365,7 @@ struct Engine {
         rrt::BoostArgs<real> b;
         b.P = pr->P; b.K = pr->K; b.nmu = pr->nmu; b.nphi = pr->nphi; b.fi = pr->fi;
         b.dir = pr->d_dir; b.mu = pr->d_mu; b.plan = plan(0); b.S0 = R(pr->d_co); b.Iprev = static_cast<const real *>(Iprev);
-        b.inv_cdt = (real)inv_cdt; b.chilab = R(pr->d_chilab); b.chi_grey = pr->grey_chi;
+        b.inv_cdt = (real)inv_cdt; b.chilab = R(pr->d_chilab); b.chi0 = R(pr->d_chi0); b.chi_grey = pr->grey_chi;
         b.beta = pr->d_beta; b.gam = pr->d_gam; b.St = R(pr->d_St);
         prof_begin(pr, KI_BOOST);
         rrt::launch_boost<real>(b, pr->stream);

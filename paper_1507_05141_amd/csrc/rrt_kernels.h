@@ -109,6 +109,8 @@ template <typename real> struct BoostArgs {
     const real *Iprev;          // [k][p][g] or NULL
     real inv_cdt;
     const real *chilab;         // [k][p] (chi_grey) or [k][p][g]
+    const real *chi0;           // [p][g] comoving extinction (per-group chi on log-uniform groups:
+                                // chi_lab rebuilt from the plan's frequency position, chilab unread)
     int chi_grey;
     const double *beta, *gam;
     real *St;                   // [k][p][g]

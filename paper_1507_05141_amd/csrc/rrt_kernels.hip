@@ -1019,6 +1019,9 @@ __global__ void __launch_bounds__(256) k_remap_plan(PlanArgs<real> a)
             RemapEntry<real> e = remap_entry<real>(a.mu, a.nmu, a.nphi, n0);
             entry_freq(e, a.fi, D, false);
             if (a.chi_grey) e.kap = a.chilab[(long)k * a.P + p];
+            // a per-group extinction on log-uniform groups: the position y = -ln D / dln(nu) of the
+            // target frequencies nu/D in group spacings, from which the boost rebuilds chi_lab
+            else if (a.fi.uniform) e.kap = (real)(-(double)log((real)D) * a.fi.inv_delta);
             a.boost[i] = e;
         }
         {
@@ -1163,6 +1166,15 @@ __global__ void __launch_bounds__(kRemapThreads, 4) k_boost(BoostArgs<real> a)
         fetch_inputs(kb0, min(OB, K - kb0) * IC, 0);
     }
 
+    // per-group lab extinction rebuilt from the points' comoving one (staged here) and the
+    // plan's frequency position: chi_lab = chi0(nu/D)/D, linear in ln(nu), outer values held
+    const bool chi_fly = !a.chi_grey && a.fi.uniform && a.chi0 != nullptr;
+    real *C0 = F0 + NPT * TS;                           // [NPT][G]
+    if (chi_fly)
+        for (int i = tid; i < NPT * G; i += T) {
+            const int q = i / G;
+            C0[i] = p0 + q < a.P ? a.chi0[(p0 + q) * G + (i - q * G)] : real(0);
+        }
 #pragma unroll
     for (int q = 0; q < NPT; ++q) {
         if (p0 + q >= a.P) break;
@@ -1251,9 +1263,31 @@ __global__ void __launch_bounds__(kRemapThreads, 4) k_boost(BoostArgs<real> a)
                     }
                 }
                 // implicit time terms and the store
+                real cx[4];
+                if (a.chi_grey) {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) cx[i] = kp;
+                } else if (chi_fly) {
+                    const real *C = C0 + q * G;
+                    if (!mv[q]) {
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) cx[i] = i < W ? C[g0 + i] : real(0);
+                    } else {
+                        const real sf = floor(kp), f = kp - sf, invD = exp(kp * (real)a.fi.delta);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int i0 = g0 + i + (int)sf;
+                            const int lo = min(max(i0, 0), G - 1), hi = min(max(i0 + 1, 0), G - 1);
+                            cx[i] = invD * ((real(1) - f) * C[lo] + f * C[hi]);
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) cx[i] = i < W ? a.chilab[o + i] : real(0);
+                }
 #pragma unroll
                 for (int i = 0; i < 4; ++i)
-                    if (i < W) out[i] = time_terms(a.chi_grey ? kp : a.chilab[o + i], out[i], pre[u].v[i], icdt);
+                    if (i < W) out[i] = time_terms(cx[i], out[i], pre[u].v[i], icdt);
                 if (W == 4) {
                     P4 v;
                     v.v[0] = out[0]; v.v[1] = out[1]; v.v[2] = out[2]; v.v[3] = out[3];
@@ -2648,7 +2682,7 @@ void launch_trace(const TraceArgs<real> &a, bool chi_array, hipStream_t st)
 template <typename real>
 size_t boost_lds(int K, int G)
 {
-    return sizeof(double) * 4 * (size_t)G + sizeof(real) * (G + 2) * (size_t)((K + 2) | 1);
+    return sizeof(double) * 4 * (size_t)G + sizeof(real) * ((G + 2) * (size_t)((K + 2) | 1) + G);
 }
 template <typename real>
 size_t unboost_lds(int K, int G)
@@ -2673,7 +2707,8 @@ template <typename real>
 void launch_boost(const BoostArgs<real> &a, hipStream_t st)
 {
     // two points per workgroup where a point's groups fill 64 bytes and both tables fit
-    const size_t one = boost_lds<real>(a.K, a.fi.G), two = one + sizeof(real) * (a.fi.G + 2) * (size_t)((a.K + 2) | 1);
+    const size_t one = boost_lds<real>(a.K, a.fi.G),
+                 two = one + sizeof(real) * ((a.fi.G + 2) * (size_t)((a.K + 2) | 1) + a.fi.G);
     if (a.fi.G * sizeof(real) == 64 && two <= 160 * 1024) {
         const long items = (a.P + 1) / 2;
         const unsigned nb = (unsigned)(8 * ((items + 7) / 8));
