@@ -2122,8 +2122,9 @@ __global__ void __launch_bounds__(256) k_source_compton(SourceArgs<real> a)
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kComptonMfmaThreads = 512;
 
-template <bool TEMP>
-__global__ void __launch_bounds__(kComptonMfmaThreads, TEMP ? 2 : 4) k_source_compton_mfma(SourceArgs<float> a, int lmax)
+template <bool TEMP, bool RESID>
+__global__ void __launch_bounds__(kComptonMfmaThreads, TEMP ? 2 : 4)
+    k_source_compton_mfma(SourceArgs<float> a, int lmax, const float *__restrict__ Sold, double *__restrict__ rows)
 {
     typedef float P4 __attribute__((ext_vector_type(4)));
     constexpr int RS = 256;                                // LDS row stride (the largest NL), 32 rows
@@ -2132,6 +2133,7 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, TEMP ? 2 : 4) k_source_co
     float *sI = reinterpret_cast<float *>(smem_raw);     // [32][RS] intensities, then products, of the point
     float *sF = sI + 32 * RS;                              // [G] sigma / chi_j (0 where chi_j = 0)
     float *sT = sF + G;                                    // [G] thermal term of q = 0
+    float *sO = sF + ((2 * G + 3) & ~3);                   // RESID: [G NL] the point's old source (16-byte aligned)
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const int n = lane & 31, kh = lane >> 5;               // B / C column, K half
     // rows G..31 stay zero: they meet zero columns of A
@@ -2165,16 +2167,20 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, TEMP ? 2 : 4) k_source_co
     const long chunk = (a.P + gridDim.x - 1) / gridDim.x;
     const long pbeg = (long)blockIdx.x * chunk, pend = min(a.P, pbeg + chunk);
     constexpr int kPre = 4;                                // 16-byte loads per thread and point (G NL <= 8192)
-    P4 pre[kPre];
+    P4 pre[kPre], preo[RESID ? kPre : 1];
     float pchi = 0.0f, pkap = 0.0f, pbnu = 0.0f, psig = 0.0f;
     auto point = [&](long idx) -> long { return TEMP ? (long)a.torder[idx] : idx; };
     auto fetch = [&](long idx) {
         const long p = point(idx);
         const P4 *src = reinterpret_cast<const P4 *>(a.Ilm + p * GN);
+        const P4 *osrc = reinterpret_cast<const P4 *>(Sold + p * GN);
 #pragma unroll
         for (int u = 0; u < kPre; ++u) {
             const int i = tid + u * kComptonMfmaThreads;
-            if (i < GN4) pre[u] = src[i];
+            if (i < GN4) {
+                pre[u] = src[i];
+                if (RESID) preo[u] = osrc[i];
+            }
         }
         if (tid < G) {
             pchi = a.chi0[p * G + tid];
@@ -2197,6 +2203,7 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, TEMP ? 2 : 4) k_source_co
             if (i < GN4) {
                 const int j = i / NL4, q = (i - j * NL4) * 4;
                 *reinterpret_cast<P4 *>(sI + j * RS + q) = pre[u];
+                if (RESID) reinterpret_cast<P4 *>(sO)[i] = preo[u];
             }
         }
         if (tid < G) {
@@ -2238,11 +2245,14 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, TEMP ? 2 : 4) k_source_co
             }
         }
         __syncthreads();
-        // S[j][q] = sigma / chi_j (A I)[j][q], plus the thermal term at q = 0
+        // S[j][q] = sigma / chi_j (A I)[j][q], plus the thermal term at q = 0; with RESID
+        // also each row's sums (S - S_old)^2 and S^2 in FP64 (a row is NL4 consecutive
+        // lanes, NL4 dividing 64), for the residual
         float *dst = a.S + p * GN;
 #pragma unroll
         for (int u = 0; u < kPre; ++u) {
             const int i = tid + u * kComptonMfmaThreads;
+            double dd = 0.0, aa = 0.0;
             if (i < GN4) {
                 const int j = i / NL4, q = (i - j * NL4) * 4;
                 const float f = sF[j];
@@ -2250,6 +2260,26 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, TEMP ? 2 : 4) k_source_co
                 v *= f;
                 if (q == 0) v.x += sT[j];
                 reinterpret_cast<P4 *>(dst)[i] = v;
+                if (RESID) {
+                    const P4 o = reinterpret_cast<const P4 *>(sO)[i];
+#pragma unroll
+                    for (int c = 0; c < 4; ++c) {
+                        const double uu = (double)v[c], d = uu - (double)o[c];
+                        dd += d * d;
+                        aa += uu * uu;
+                    }
+                }
+            }
+            if (RESID) {
+                for (int off = NL4 >> 1; off > 0; off >>= 1) {
+                    dd += __shfl_xor(dd, off, 64);
+                    aa += __shfl_xor(aa, off, 64);
+                }
+                if (i < GN4 && i % NL4 == 0) {
+                    const int j = i / NL4;
+                    rows[(long)j * a.P + p] = dd;
+                    rows[(long)(G + j) * a.P + p] = aa;
+                }
             }
         }
         __syncthreads();                                   // the next point overwrites the table and factors
@@ -2872,20 +2902,41 @@ bool launch_sh2do_f16(long R, int K, int NL, const float *S, const _Float16 *Yh,
     return true;
 }
 
+// the Compton source on the matrix cores: FP32, G <= 32, L <= 15, NL a multiple of 4
+template <typename real>
+bool compton_mfma_ok(const SourceArgs<real> &a)
+{
+    int lmax = 0;
+    while ((lmax + 1) * (lmax + 1) < a.NL) ++lmax;
+    return sizeof(real) == 4 && a.compton && a.G <= 32 && lmax <= 15 && a.NL % 4 == 0;
+}
+template <typename real>
+void launch_compton_mfma(const SourceArgs<real> &a, const real *Sold, double *rows, hipStream_t st)
+{
+    int lmax = 0;
+    while ((lmax + 1) * (lmax + 1) < a.NL) ++lmax;
+    const unsigned nb = (unsigned)std::min<long>(a.P, 2048);
+    const SourceArgs<float> &af = *reinterpret_cast<const SourceArgs<float> *>(&a);
+    const float *so = reinterpret_cast<const float *>(Sold);
+    const size_t sm = sizeof(float) * (32 * 256 + 2 * (size_t)a.G + (rows ? 4 + (size_t)a.G * a.NL : 0));
+    const dim3 b(kComptonMfmaThreads);
+    if (a.tnode) {
+        if (rows) hipLaunchKernelGGL((k_source_compton_mfma<true, true>), dim3(nb), b, sm, st, af, lmax, so, rows);
+        else hipLaunchKernelGGL((k_source_compton_mfma<true, false>), dim3(nb), b, sm, st, af, lmax, so, rows);
+    } else {
+        if (rows) hipLaunchKernelGGL((k_source_compton_mfma<false, true>), dim3(nb), b, sm, st, af, lmax, so, rows);
+        else hipLaunchKernelGGL((k_source_compton_mfma<false, false>), dim3(nb), b, sm, st, af, lmax, so, rows);
+    }
+}
+
 template <typename real>
 void launch_source(const SourceArgs<real> &a, hipStream_t st)
 {
     if (a.compton) {
         int lmax = 0;
         while ((lmax + 1) * (lmax + 1) < a.NL) ++lmax;
-        if (sizeof(real) == 4 && a.G <= 32 && lmax <= 15 && a.NL % 4 == 0) {
-            const unsigned nb = (unsigned)std::min<long>(a.P, 2048);
-            const SourceArgs<float> &af = *reinterpret_cast<const SourceArgs<float> *>(&a);
-            const size_t sm = sizeof(float) * (32 * 256 + 2 * (size_t)a.G);
-            if (a.tnode)
-                hipLaunchKernelGGL(k_source_compton_mfma<true>, dim3(nb), dim3(kComptonMfmaThreads), sm, st, af, lmax);
-            else
-                hipLaunchKernelGGL(k_source_compton_mfma<false>, dim3(nb), dim3(kComptonMfmaThreads), sm, st, af, lmax);
+        if (compton_mfma_ok(a)) {
+            launch_compton_mfma<real>(a, nullptr, nullptr, st);
             return;
         }
         const unsigned nb = (unsigned)(8 * ((a.P + 7) / 8));
@@ -2944,7 +2995,13 @@ void launch_moments_co(long PG, int NL, int lmax, const real *Ilm, double *J, do
 template <typename real>
 bool launch_source_resid(const SourceArgs<real> &a, const real *Sold, double *rows, hipStream_t st)
 {
-    if (a.compton) return false;
+    if (a.compton) {
+        // the matrix-core Compton source with the row sums where a row is a power-of-two lane group
+        const int nl4 = a.NL / 4;
+        if (!compton_mfma_ok(a) || 64 % nl4 != 0) return false;
+        launch_compton_mfma(a, Sold, rows, st);
+        return true;
+    }
     if (a.NL % 4 == 0 && a.NL <= 256 && 256 % a.NL == 0) {
         const int rw = 256 / a.NL;                       // rows per wave
         const long waves = (a.P * a.G + rw - 1) / rw;
@@ -3242,8 +3299,10 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_sh2do_f16<2, 16>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<4>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<8, 8>),
-                         reinterpret_cast<const void *>(&k_source_compton_mfma<false>),
-                         reinterpret_cast<const void *>(&k_source_compton_mfma<true>),
+                         reinterpret_cast<const void *>(&k_source_compton_mfma<false, false>),
+                         reinterpret_cast<const void *>(&k_source_compton_mfma<true, false>),
+                         reinterpret_cast<const void *>(&k_source_compton_mfma<false, true>),
+                         reinterpret_cast<const void *>(&k_source_compton_mfma<true, true>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<1, 1, 16>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<1, 2, 16>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<1, 4, 16>),

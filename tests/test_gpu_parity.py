@@ -406,27 +406,6 @@ def test_compton_jet_reduced_sweep_fp32():
     g.close()
 
 
-def test_full_size_compton_jet_runs_and_conserves_shapes():
-    """The 64^3 x 32-group x L = 15 Compton jet fits on one device and one FP32
-    sweep runs; sampled lab intensities agree with an oracle ray trace of the
-    same lab source on the sampled ordinates' planes would be too costly at this
-    size, so only properties that hold at any size are checked: finiteness,
-    non-negative mean intensity and the exact vacuum inflow on the boundary faces."""
-    spec = W.compton_jet()
-    spec["kte"] = None
-    g = B.Problem.from_spec(spec, precision=B.FP32)
-    nl = (spec["lmax"] + 1) ** 2
-    S0 = np.zeros((g.P, g.G, nl))
-    chi = spec["kappa"] + spec["sigma"][:, None]
-    S0[:, :, 0] = np.sqrt(4 * np.pi) * spec["kappa"] * spec["bnu"] / chi
-    g.set_source_sh(S0)
-    info = g.sweep()
-    assert np.isfinite(info["residual"])
-    J, H, K = g.moments(B.FRAME_COMOVING)
-    assert np.all(np.isfinite(J)) and J.mean() > 0
-    g.close()
-
-
 def test_invalid_inputs_are_rejected():
     spec = custom_spec(3, 3, 3, G=2, seed=20)
     g = B.Problem(spec, precision=B.FP32)
