@@ -1475,7 +1475,9 @@ template <> struct Mfma16<double> {
     __device__ static int row(int lg, int r) { return lg + 4 * r; }
 };
 
-template <typename real, int NT, int RT, int W, int KC, int BV>
+// TR (FP32, N a multiple of 4): each 16 x 16 tile is computed transposed (the
+// operands swapped), so that a lane holds four consecutive columns of one row
+template <typename real, int NT, int RT, int W, int KC, int BV, bool TR>
 __global__ void __launch_bounds__(64 * W) k_gemm_panel(long R, int Kd, int N, const real *__restrict__ A,
                                                        const real *__restrict__ B, real *__restrict__ C)
 {
@@ -1562,13 +1564,32 @@ __global__ void __launch_bounds__(64 * W) k_gemm_panel(long R, int Kd, int N, co
                 for (int c = 0; c < NT; ++c) {
                     const real bv = brow[16 * c];
 #pragma unroll
-                    for (int rt = 0; rt < RT; ++rt) acc[rt][c] = M::step(ac[rt][t][s], bv, acc[rt][c]);
+                    for (int rt = 0; rt < RT; ++rt)
+                        acc[rt][c] = TR ? M::step(bv, ac[rt][t][s], acc[rt][c]) : M::step(ac[rt][t][s], bv, acc[rt][c]);
                 }
             }
         }
         if (more) stage(buf ^ 1);                    // every wave finished the other buffer before the last barrier
         __syncthreads();
         buf ^= 1;
+    }
+    if (TR) {
+        // transposed tiles: lane (lr, lg) holds columns 16 c + 4 lg .. + 3 of row 16 rt + lr,
+        // stored as one 16-byte vector (N a multiple of 4)
+#pragma unroll
+        for (int rt = 0; rt < RT; ++rt) {
+            const long r = r0 + 16 * rt + lr;
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                const int col = c0 + 16 * c + 4 * lg;
+                if (r < R && col < N) {
+                    v4 v;
+                    v.x = acc[rt][c][0]; v.y = acc[rt][c][1]; v.z = acc[rt][c][2]; v.w = acc[rt][c][3];
+                    *reinterpret_cast<v4 *>(C + r * N + col) = v;
+                }
+            }
+        }
+        return;
     }
 #pragma unroll
     for (int rt = 0; rt < RT; ++rt)
@@ -2764,6 +2785,72 @@ void launch_unboost(const UnboostArgs<real> &a, hipStream_t st)
 }
 size_t do2sh_lds(int NL) { return sizeof(float) * 64 * (size_t)(((NL + 15) / 16) * 16 + 4); }
 
+// FP32 product with a short inner dimension (Kd <= 64, the S2 product of L <= 7):
+// the whole table B [Kd][N] (N = 128, 256 or 512) resident in LDS in one
+// persistent workgroup of 16 waves per CU.  Wave w computes 16 rows of a block
+// and 16 NT columns of group w % CQ (CQ = N / 16 NT); each 16 x 16 tile is
+// computed transposed (operands swapped) so that a lane holds four
+// consecutive columns of one row and stores them as one 16-byte vector; the
+// next block's A rows are loaded during the current products.
+template <int NT>
+__global__ void __launch_bounds__(1024) k_gemm_short_k(long R, int Kd, int N, const float *__restrict__ A,
+                                                       const float *__restrict__ B, float *__restrict__ C)
+{
+    constexpr int KR = 64, NC = 16 * NT;
+    extern __shared__ unsigned char smem_raw[];
+    float *Bs = reinterpret_cast<float *>(smem_raw);                   // [KR][N + 4]
+    const int NP = N + 4;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
+    for (int i = threadIdx.x; i < KR * N; i += blockDim.x) {
+        const int kk = i / N, c = i - kk * N;
+        Bs[kk * NP + c] = kk < Kd ? B[(long)kk * N + c] : 0.f;
+    }
+    __syncthreads();
+    const int CQ = N / NC, RW = 16 / CQ, rq = wave / CQ, cq = wave - rq * CQ;
+    const long nblk = (R + 16 * RW - 1) / (16 * RW);
+    const bool vec = (Kd & 3) == 0;
+    f32x4 a[4], an[4];
+    auto load = [&](f32x4 (&dst)[4], long blk) {
+        const float *Ar = A + min(blk * (16 * RW) + rq * 16 + lr, R - 1) * (long)Kd;
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            const int k = 16 * t + 4 * lg;
+            if (vec && k + 3 < Kd) {
+                dst[t] = *reinterpret_cast<const f32x4 *>(Ar + k);
+            } else {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) dst[t][i] = (k + i < Kd) ? Ar[k + i] : 0.f;
+            }
+        }
+    };
+    long blk = blockIdx.x;
+    if (blk < nblk) load(a, blk);
+    for (; blk < nblk; blk += gridDim.x) {
+        if (blk + gridDim.x < nblk) load(an, blk + gridDim.x);
+        f32x4 acc[NT];
+#pragma unroll
+        for (int c = 0; c < NT; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 4; ++t) {
+            if (16 * t >= Kd) break;
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const float *brow = Bs + (16 * t + 4 * lg + s) * NP + cq * NC + lr;
+#pragma unroll
+                for (int c = 0; c < NT; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(brow[16 * c], a[t][s], acc[c], 0, 0, 0);
+            }
+        }
+        const long r = blk * (16 * RW) + rq * 16 + lr;
+        if (r < R) {
+#pragma unroll
+            for (int c = 0; c < NT; ++c)
+                *reinterpret_cast<f32x4 *>(C + r * N + cq * NC + 16 * c + 4 * lg) = acc[c];
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) a[t] = an[t];
+    }
+}
+
 template <typename real>
 void launch_gemm(long R, int Kd, int N, const real *A, const real *B, real *C, hipStream_t st)
 {
@@ -2775,15 +2862,27 @@ void launch_gemm(long R, int Kd, int N, const real *A, const real *B, real *C, h
         const unsigned nby = (unsigned)((N + 16 * NT - 1) / (16 * NT));                                       \
         const size_t sm = 2 * sizeof(real) * (size_t)KC * (16 * NT + (sizeof(real) == 4 ? 4 : 2));            \
         const dim3 grid((unsigned)(8 * ((nb + 7) / 8)), nby);                                                \
-        if (N % 4 == 0)                                                                                      \
-            hipLaunchKernelGGL((k_gemm_panel<real, NT, RT, W, KC, 4>), grid, dim3(64 * W), sm, st, R, Kd, N, A, B, C); \
+        if (N % 4 == 0 && sizeof(real) == 4 && N > Kd)                                                       \
+            hipLaunchKernelGGL((k_gemm_panel<real, NT, RT, W, KC, 4, true>), grid, dim3(64 * W), sm, st, R, Kd, N, A, \
+                               B, C);                                                                        \
+        else if (N % 4 == 0)                                                                                 \
+            hipLaunchKernelGGL((k_gemm_panel<real, NT, RT, W, KC, 4, false>), grid, dim3(64 * W), sm, st, R, Kd, N, \
+                               A, B, C);                                                                     \
         else                                                                                                 \
-            hipLaunchKernelGGL((k_gemm_panel<real, NT, RT, W, KC, 1>), grid, dim3(64 * W), sm, st, R, Kd, N, A, B, C); \
+            hipLaunchKernelGGL((k_gemm_panel<real, NT, RT, W, KC, 1, false>), grid, dim3(64 * W), sm, st, R, Kd, N, A, \
+                               B, C);                                                                        \
         return;                                                                                              \
     }
     // (tile shapes: the fastest of a sweep on MI355X at 2^23 rows: 78 % of the FP32
     // matrix peak with 256 columns and 512 inner, 71 % with 512 columns and 256 inner)
     if constexpr (sizeof(real) == 4) {
+        if (Kd <= 64 && (N == 128 || N == 256 || N == 512)) {
+            const size_t smr = sizeof(float) * 64 * (size_t)(N + 4);
+            const long nblk = (R + 16 * (16 / (N / 128)) - 1) / (16 * (16 / (N / 128)));
+            hipLaunchKernelGGL((k_gemm_short_k<8>), dim3((unsigned)std::min<long>(nblk, 256)), dim3(1024), smr, st, R,
+                               Kd, N, A, B, C);
+            return;
+        }
         if (N <= 32) RRT_GEMM(2, 4, 4, 16)
         if (N <= 128) RRT_GEMM(8, 2, 4, 16)
         if (N <= 256) RRT_GEMM(16, 2, 8, 16)
@@ -3313,6 +3412,7 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_do2sh_f32r<1, 2>),
                          reinterpret_cast<const void *>(&k_do2sh_f32r<4, 1>),
                          reinterpret_cast<const void *>(&k_do2sh_f32r<4, 2>),
+                         reinterpret_cast<const void *>(&k_gemm_short_k<8>),
                          reinterpret_cast<const void *>(&k_source_compton<double>)};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
