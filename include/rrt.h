@@ -111,7 +111,9 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
    log10 range rounded out to eighths of a decade), and every point uses the
    source tables A = s_i (nu_j dnu_i)/(nu_i dnu_j) p_l^{i->j}/(2l+1) and the
    cross-section ratio s interpolated linearly in log10 T between its two
-   nodes.  Errors: RRT_E_INVALID for NaN/negative/|beta|>=1, for kte <= 0 or
+   nodes.  Tables built once are kept for the process, keyed by the groups,
+   mec2, lmax and node temperatures, so problems sharing them skip the build.
+   Errors: RRT_E_INVALID for NaN/negative/|beta|>=1, for kte <= 0 or
    kte with Thomson scattering; RRT_E_DEVICE if the tables fail. */
 rrt_status rrt_set_medium(rrt_problem *pr, const double *kappa, const double *sigma,
                           const double *bnu, const double *beta, const double *kte);

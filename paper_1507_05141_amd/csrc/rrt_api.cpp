@@ -11,6 +11,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <map>
+#include <tuple>
 #include <mutex>
 #include <string>
 #include <type_traits>
@@ -962,14 +963,46 @@ size_t rrt_footprint_bytes(const rrt_grid *grid, const rrt_groups *groups, const
 // Compton tables at the node temperatures kT (units of the edges; {0}: electrons at
 // rest), built on the GPU in FP64; the source tables A = s_i (nu_j dnu_i)/(nu_i dnu_j)
 // p_l^{i->j}/(2l+1) and s are uploaded in the working precision
+// Compton tables already built in this process, keyed by everything they depend on
+// (groups, centres, rest energy, order, node temperatures): problems of a served
+// mix share group sets and node grids, and a table build costs tens of ms
+struct TableKey {
+    int G, L;
+    double mec2;
+    std::vector<double> edges, centres, kT;
+    bool operator<(const TableKey &o) const
+    {
+        return std::tie(G, L, mec2, edges, centres, kT) < std::tie(o.G, o.L, o.mec2, o.edges, o.centres, o.kT);
+    }
+};
+static std::mutex g_tab_mu;
+static std::map<TableKey, std::pair<std::vector<double>, std::vector<double>>> g_tables;
+constexpr size_t kMaxCachedTables = 64;
+
 static rrt_status build_compton_tables(rrt_problem *pr, const std::vector<double> &kT)
 {
     if (pr->kT_nodes == kT && pr->d_A) return RRT_OK;
     const int G = pr->G, L = pr->lmax, nt = (int)kT.size();
     std::vector<double> sv, pv;
-    const int e = rrt::compton_tables_gpu(G, pr->edges.data(), pr->centres.data(), pr->mec2, L, nt, kT.data(), sv, pv,
-                                          pr->stream);
-    if (e != 0) return fail(RRT_E_DEVICE, std::string("Compton tables: ") + hipGetErrorString((hipError_t)e));
+    const TableKey key{G, L, pr->mec2, pr->edges, pr->centres, kT};
+    bool hit = false;
+    {
+        std::lock_guard<std::mutex> lk(g_tab_mu);
+        auto it = g_tables.find(key);
+        if (it != g_tables.end()) {
+            sv = it->second.first;
+            pv = it->second.second;
+            hit = true;
+        }
+    }
+    if (!hit) {
+        const int e = rrt::compton_tables_gpu(G, pr->edges.data(), pr->centres.data(), pr->mec2, L, nt, kT.data(), sv,
+                                              pv, pr->stream);
+        if (e != 0) return fail(RRT_E_DEVICE, std::string("Compton tables: ") + hipGetErrorString((hipError_t)e));
+        std::lock_guard<std::mutex> lk(g_tab_mu);
+        if (g_tables.size() >= kMaxCachedTables) g_tables.clear();
+        g_tables[key] = {sv, pv};
+    }
     std::vector<double> A((size_t)nt * (L + 1) * G * G, 0.0);
     for (int n = 0; n < nt; ++n)
         for (int l = 0; l <= L; ++l)
