@@ -40,7 +40,12 @@ def algorithmic(kernel, spec, esz, time_dependent, precision="fp32"):
     K = spec["nmu"] * spec["nphi"]
     NL = (spec["lmax"] + 1) ** 2
     compton = spec.get("scatter", "thomson") == "compton"
-    fused = not compton and (64 % NL == 0 or (NL % 4 == 0 and 256 % NL == 0))
+    # the residual's row sums are formed in the source pass: Thomson with NL dividing 64 or 256,
+    # Compton on the matrix cores (FP32, G <= 32, L <= 15, NL / 4 dividing 64)
+    if compton:
+        fused = precision != "fp64" and G <= 32 and spec["lmax"] <= 15 and NL % 4 == 0 and 64 % (NL // 4) == 0
+    else:
+        fused = 64 % NL == 0 or (NL % 4 == 0 and 256 % NL == 0)
     grey_chi = not compton and spec.get("kappa") is not None and bool((spec["kappa"] == spec["kappa"][:, :1]).all())
     do, sh = n * G * K, n * G * NL
     mfma_peak = 2500.0 if precision == "mixed" else FP32_PEAK_TFLOPS
@@ -54,8 +59,8 @@ def algorithmic(kernel, spec, esz, time_dependent, precision="fp32"):
         # lab intensity read, comoving SH intensity written (through the backward product)
         "unboost": ("hbm", esz * (do + sh)),
         "do2sh": ("mfma", 2.0 * NL * do, mfma_peak),
-        # SH intensity read, new source written, and (Thomson, where the residual's row sums are
-        # taken in the same pass) the old source read
+        # SH intensity read, new source written, and (where the residual's row sums are taken in
+        # the same pass) the old source read
         "source": ("hbm", esz * (3 if fused else 2) * sh),
         # the residual: both sources read, or only the per-row sums where fused into the source
         "reduce": ("hbm", 16 * n * G if fused else esz * 2 * sh),
