@@ -352,11 +352,12 @@ def test_compton_tables_built_on_the_gpu_match_the_oracle(thermal):
 
 
 def test_standalone_compton_tables_match_the_oracle():
-    """rrt_compton_tables at electrons at rest and at 10, 31.6 and 100 keV
-    (s and p, FP64) against the oracle's tables: 1e-11 of each table's largest
-    entry; an invalid temperature is refused."""
+    """rrt_compton_tables at electrons at rest and at 10, 31.6, 100 and 511 keV
+    (the last relativistic, Theta = 1) (s and p, FP64) against the oracle's
+    tables: 1e-11 of each table's largest entry; an invalid temperature is
+    refused."""
     edges = np.exp(np.linspace(np.log(1.0), np.log(1e3), 11))
-    kT = np.array([0.0, 10.0, 10 ** 1.5, 100.0])
+    kT = np.array([0.0, 10.0, 10 ** 1.5, 100.0, W.MEC2_KEV])
     s, p = B.compton_tables(edges, W.MEC2_KEV, 5, kT)
     c = oracle.group_centres(edges, True)
     for n, t in enumerate(kT):
