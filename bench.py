@@ -395,8 +395,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--precision", choices=["fp32", "fp64", "mixed"], default="fp32",
-                    help="mixed: FP32 with the SH <-> ordinate products on FP16 matrix cores")
+    ap.add_argument("--precision", choices=["fp32", "fp64", "mixed"], default=None,
+                    help="mixed: FP32 with the SH <-> ordinate products on FP16 matrix cores (the default for "
+                         "the Compton jet, which is specified with 16-bit matrix-core transforms and FP32 "
+                         "accumulation); fp32 the default for the Thomson jet")
     ap.add_argument("--workload", choices=["thomson_jet", "compton_jet"], default="compton_jet",
                     help="compton_jet (default): 64^3, 32 groups, L=15, electron temperature 10-100 keV; "
                          "thomson_jet: 32^3, 16 groups, L=7")
@@ -449,6 +451,8 @@ def main():
     else:
         spec = W.compton_jet()
         workload = "compton_jet_64c_g32_l15_16x32_kte10-100"
+    if args.precision is None:
+        args.precision = "mixed" if args.workload == "compton_jet" else "fp32"
     prec = {"fp32": B.FP32, "fp64": B.FP64, "mixed": B.MIXED}[args.precision]
     esz = 8 if prec == B.FP64 else 4
     stream = torch.cuda.current_stream().cuda_stream
@@ -515,6 +519,8 @@ def main():
                    "lmax": spec["lmax"], "ordinates": [spec["nmu"], spec["nphi"]], "scatter": spec["scatter"],
                    "gamma_max": 10.0, "updates_per_sweep": updates,
                    "electron_temperature_keV": [10.0, 100.0] if spec.get("kte") is not None else None,
+                   "sh_products": {"mixed": "FP16 matrix cores (hi/lo operand pairs), FP32 accumulation",
+                                   "fp32": "FP32 matrix cores", "fp64": "FP64 matrix cores"}[args.precision],
                    "stage": "steady" if not dt_stage else f"time step dt = {dt:.6g}, stage dt/6 (four-stage scheme)"},
         "roofline": roof,
         "kernels": kern,

@@ -18,7 +18,9 @@ compared with it:
 The samples include the last point, ordinate and group, so every index range
 of the arrays (more than 2^31 elements) is reached.  Tolerance 1e-5 of the
 group maximum as in the reduced-size parity tests (groups much fainter than a
-neighbour within 8 groups are held to 1e-5 of 1/100 of that neighbour).
+neighbour within 8 groups are held to 1e-5 of 1/100 of that neighbour) in
+FP32; 1e-4 in mixed precision (the SH <-> ordinate products on FP16 matrix
+cores with hi/lo operand pairs, about 22 significant bits).
 """
 import numpy as np
 import pytest
@@ -30,10 +32,10 @@ from paper_1507_05141_amd import workloads as W
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-RTOL = 1e-5
+RTOL = {B.FP32: 1e-5, B.MIXED: 1e-4}
 
 
-def close_by_group(got, ref, gaxis, what, reach=8):
+def close_by_group(got, ref, gaxis, what, rtol, reach=8):
     g = np.moveaxis(got, gaxis, 0).reshape(got.shape[gaxis], -1)
     r = np.moveaxis(ref, gaxis, 0).reshape(ref.shape[gaxis], -1)
     own = np.abs(r).max(axis=1)
@@ -42,7 +44,7 @@ def close_by_group(got, ref, gaxis, what, reach=8):
         scale = max(own[i], 1e-2 * own[max(0, i - reach):i + reach + 1].max())
         err = np.max(np.abs(g[i] - r[i]))
         worst = max(worst, err / scale if scale > 0 else err)
-        assert err <= RTOL * scale + 1e-300, f"{what} group {i}: max err {err:.3e} vs scale {scale:.3e}"
+        assert err <= rtol * scale + 1e-300, f"{what} group {i}: max err {err:.3e} vs scale {scale:.3e}"
     return worst
 
 
@@ -56,14 +58,16 @@ def point_oracle(spec, p):
     return oracle.Oracle(sub)
 
 
-def test_full_size_compton_jet_sampled_parity():
+@pytest.mark.parametrize("prec", [B.FP32, B.MIXED], ids=["fp32", "mixed"])
+def test_full_size_compton_jet_sampled_parity(prec):
     spec = W.compton_jet()
+    rtol = RTOL[prec]
     n, G, K = spec["nx"], len(spec["edges"]) - 1, spec["nmu"] * spec["nphi"]
     P = n ** 3
     NL = (spec["lmax"] + 1) ** 2
     stream = torch.cuda.current_stream().cuda_stream
-    print(f"case compton_jet {n}^3 G={G} K={K} L={spec['lmax']} fp32", flush=True)
-    g = B.Problem.from_spec(spec, precision=B.FP32, stream=stream)
+    print(f"case compton_jet {n}^3 G={G} K={K} L={spec['lmax']} precision {prec}", flush=True)
+    g = B.Problem.from_spec(spec, precision=prec, stream=stream)
     dt_stage = 0.5 / n / 6.0
     inv_cdt = 1.0 / dt_stage
     bnu = torch.from_numpy(spec["bnu"]).to("cuda", torch.float32)
@@ -110,11 +114,11 @@ def test_full_size_compton_jet_sampled_parity():
     for i, p in enumerate(points):
         o1 = point_oracle(spec, p)
         ref_St, _ = o1.boost(o1.sh2do(S_old_p[i][None]), np.broadcast_to(Ip_p[i], (K, 1, G)), inv_cdt)
-        w1 = close_by_group(St_p[:, i:i + 1, :], ref_St, 2, f"S~ at point {p}")
+        w1 = close_by_group(St_p[:, i:i + 1, :], ref_St, 2, f"S~ at point {p}", rtol)
         ref_Ilm = o1.fold(cut(I_p[:, i:i + 1, :]))
-        w2 = close_by_group(Ilm_p[i][None], ref_Ilm, 1, f"I_lm at point {p}")
+        w2 = close_by_group(Ilm_p[i][None], ref_Ilm, 1, f"I_lm at point {p}", rtol)
         ref_S = o1.source(cut(Ilm_p[i][None]))
-        w3 = close_by_group(S_new_p[i][None], ref_S, 1, f"S_new at point {p}")
+        w3 = close_by_group(S_new_p[i][None], ref_S, 1, f"S_new at point {p}", rtol)
         print(f"point {p}: S~ {w1:.1e}, fold {w2:.1e}, source {w3:.1e} (worst error / scale)", flush=True)
 
     o = oracle.Oracle(spec)
@@ -123,4 +127,4 @@ def test_full_size_compton_jet_sampled_parity():
         ref = o.trace_one(k, gg, s_m, x_m)
         err = np.abs(i_m - ref).max() / np.abs(ref).max()
         print(f"march ordinate {k} group {gg}: max error {err:.2e} of its maximum {np.abs(ref).max():.2e}", flush=True)
-        assert err <= RTOL
+        assert err <= rtol
