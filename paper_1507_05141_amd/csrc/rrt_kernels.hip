@@ -1922,9 +1922,7 @@ __global__ void __launch_bounds__(64 * W) k_sh2do_f16(long R, int K, int NL, con
     f16x8 ah[NB], al[NB];
 #pragma unroll
     for (int b = 0; b < NB; ++b) split_f16x8(v[b], sc, ah[b], al[b]);
-    float ri[4];
-#pragma unroll
-    for (int i = 0; i < 4; ++i) ri[i] = __shfl(inv, 4 * lg + i, 64);
+    const bool kvec = (K & 3) == 0;
     for (int jc = 0; jc < Kt; jc += JC) {
         __syncthreads();
         for (int i = threadIdx.x; i < JC * (NLp / 8); i += blockDim.x) {
@@ -1942,18 +1940,26 @@ __global__ void __launch_bounds__(64 * W) k_sh2do_f16(long R, int K, int NL, con
         for (int c = 0; c < JC / 16; ++c) {
             const int j0 = jc + 16 * c;
             if (j0 >= Kt) break;
+            // the tile transposed (table as the first operand): lane (lr, lg) gets ordinates
+            // j0 + 4 lg .. + 3 of row r0 + lr, rescaled by that row's own factor and stored
+            // as one 16-byte vector
             f32x4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int b = 0; b < NB; ++b) {
                 const int o = (16 * c + lr) * LS + 32 * b + 8 * lg;
-                acc = mfma3(ah[b], al[b], *reinterpret_cast<const f16x8 *>(Th + o), *reinterpret_cast<const f16x8 *>(Tl + o),
-                            acc);
+                acc = mfma3(*reinterpret_cast<const f16x8 *>(Th + o), *reinterpret_cast<const f16x8 *>(Tl + o), ah[b],
+                            al[b], acc);
             }
-            const int col = j0 + lr;
+            const int col = j0 + 4 * lg;
+            const long r = r0 + lr;
+            if (r < R) {
+                if (kvec && col + 3 < K) {
+                    *reinterpret_cast<f32x4 *>(C + r * K + col) = acc * inv;
+                } else {
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const long r = r0 + 4 * lg + i;
-                if (r < R && col < K) C[r * K + col] = acc[i] * ri[i];
+                    for (int i = 0; i < 4; ++i)
+                        if (col + i < K) C[r * K + col + i] = acc[i] * inv;
+                }
             }
         }
     }
