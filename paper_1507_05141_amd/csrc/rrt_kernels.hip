@@ -368,38 +368,49 @@ struct TraceIdx {
 constexpr int kRing = 4;
 constexpr int kIBuf = 1;
 
+// a thread's points, computed once: plane index e (clamped to the last point, for
+// unconditional loads), its offset e ps in a lab plane, its LDS cell and whether it
+// also fills the halo column (i = 0) or row (j = 0)
+template <int MAXPT>
+struct PointSlots {
+    int e[MAXPT], eo[MAXPT], cell[MAXPT];
+    bool i0[MAXPT], j0[MAXPT], in[MAXPT];
+};
+
 // plane m of S~ and chi~ into registers; ps = stride between points (G, or 1 on group-major planes)
 template <typename real, int XMODE, int GC, int MAXPT>
 __device__ __forceinline__ void trace_fetch(PlaneRegs<real, GC, MAXPT> &r, const real *__restrict__ Sk,
-                                            const real *__restrict__ Xk, int ps, int PL, int m)
+                                            const real *__restrict__ Xk, int ps, int PL, int m,
+                                            const PointSlots<MAXPT> &ps_)
 {
     using P = Pack<real, GC>;
+    const real *__restrict__ Sp = Sk + (long)m * PL * ps;           // the plane's start (uniform)
+    const real *__restrict__ Xp = XMODE == kChiGrey ? Xk + (long)m * PL : Xk + (long)m * PL * ps;
 #pragma unroll
     for (int c = 0; c < MAXPT; ++c) {
-        const int pidx = m * PL + min((int)threadIdx.x + c * kTraceThreads, PL - 1);
-        const long o = (long)pidx * ps;
-        r.s[c] = *reinterpret_cast<const P *>(Sk + o);
-        if (XMODE == kChiGrey) r.x[c].v[0] = Xk[pidx];
-        else r.x[c] = *reinterpret_cast<const P *>(Xk + o);
+        r.s[c] = *reinterpret_cast<const P *>(Sp + ps_.eo[c]);
+        if (XMODE == kChiGrey) r.x[c].v[0] = Xp[ps_.e[c]];
+        else r.x[c] = *reinterpret_cast<const P *>(Xp + ps_.eo[c]);
     }
 }
 
-// write value v of point (i, j) into an LDS plane with its periodic halo
+// value v of a point into an LDS plane at its cell, and into the periodic halo
+// column / row where the point is at i = 0 / j = 0
 template <typename T>
-__device__ __forceinline__ void lds_put(T *pl, const TraceIdx &q, int i, int j, const T v)
+__device__ __forceinline__ void lds_put_at(T *pl, const TraceIdx &q, int cell, bool i0, bool j0, const T v)
 {
-    pl[j * q.RS + i] = v;
-    if (i == 0) pl[j * q.RS + q.nx] = v;
-    if (j == 0) {
-        pl[q.ny * q.RS + i] = v;
-        if (i == 0) pl[q.ny * q.RS + q.nx] = v;
+    pl[cell] = v;
+    if (i0) pl[cell + q.nx] = v;
+    if (j0) {
+        pl[cell + q.ny * q.RS] = v;
+        if (i0) pl[cell + q.ny * q.RS + q.nx] = v;
     }
 }
 
 // registers -> the LDS ring slot of plane t; chi~ = chi + add (the time term)
 template <typename real, int XMODE, int GC, int MAXPT>
 __device__ __forceinline__ void trace_store(const PlaneRegs<real, GC, MAXPT> &r, real *Sr, real *Xr,
-                                            const TraceIdx &q, int t, real add)
+                                            const TraceIdx &q, int t, real add, const PointSlots<MAXPT> &ps_)
 {
     constexpr bool xg = XMODE == kChiGrey;
     using P = Pack<real, GC>;
@@ -407,18 +418,15 @@ __device__ __forceinline__ void trace_store(const PlaneRegs<real, GC, MAXPT> &r,
     P *Sd = reinterpret_cast<P *>(Sr + slot * q.PS * GC);
 #pragma unroll
     for (int c = 0; c < MAXPT; ++c) {
-        const int pe = threadIdx.x + c * kTraceThreads;
-        if (pe < q.PL) {
-            int i, j;
-            plane_ij(pe, q.nx, q.rnx, i, j);
-            lds_put(Sd, q, i, j, r.s[c]);
+        if (ps_.in[c]) {
+            lds_put_at(Sd, q, ps_.cell[c], ps_.i0[c], ps_.j0[c], r.s[c]);
             if (xg) {
-                lds_put(Xr + slot * q.PS, q, i, j, r.x[c].v[0] + add);
+                lds_put_at(Xr + slot * q.PS, q, ps_.cell[c], ps_.i0[c], ps_.j0[c], r.x[c].v[0] + add);
             } else {
                 P x = r.x[c];
 #pragma unroll
                 for (int n = 0; n < GC; ++n) x.v[n] += add;
-                lds_put(reinterpret_cast<P *>(Xr + slot * q.PS * GC), q, i, j, x);
+                lds_put_at(reinterpret_cast<P *>(Xr + slot * q.PS * GC), q, ps_.cell[c], ps_.i0[c], ps_.j0[c], x);
             }
         }
     }
@@ -575,19 +583,27 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a, int 
     // plane, the cells of its three bilinear taps (second upwind, upwind,
     // downwind): the same on every plane
     int pi[MAXPT], pj[MAXPT], self[MAXPT], cell[MAXPT][3];
+    PointSlots<MAXPT> pts;
 #pragma unroll
     for (int c = 0; c < MAXPT; ++c) {
-        plane_ij(min(tid + c * T, PL - 1), nx, q.rnx, pi[c], pj[c]);
+        const int e = min(tid + c * T, PL - 1);
+        plane_ij(e, nx, q.rnx, pi[c], pj[c]);
         self[c] = pj[c] * q.RS + pi[c];
         cell[c][0] = tap_cell(tp[2], pi[c], pj[c], q);
         cell[c][1] = tap_cell(tp[1], pi[c], pj[c], q);
         cell[c][2] = tap_cell(tp[-1], pi[c], pj[c], q);
+        pts.e[c] = e;
+        pts.eo[c] = e * ps;
+        pts.cell[c] = self[c];
+        pts.i0[c] = pi[c] == 0;
+        pts.j0[c] = pj[c] == 0;
+        pts.in[c] = tid + c * T < PL;
     }
 
     const real add = XMODE == kChiArray ? real(0) : a.inv_cdt;   // the stand-alone chi~ already holds it
     for (int t = 0; t < nz && t < 3; ++t) {
-        trace_fetch<real, XMODE, GC, MAXPT>(rg, Sk, Xk, ps, PL, gm.up ? t : nz - 1 - t);
-        trace_store<real, XMODE, GC, MAXPT>(rg, Sr, Xr, q, t, add);
+        trace_fetch<real, XMODE, GC, MAXPT>(rg, Sk, Xk, ps, PL, gm.up ? t : nz - 1 - t, pts);
+        trace_store<real, XMODE, GC, MAXPT>(rg, Sr, Xr, q, t, add, pts);
     }
     {
         const int m0 = gm.up ? 0 : nz - 1;
@@ -603,8 +619,8 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a, int 
 #pragma unroll
                 for (int n = 0; n < GC; ++n) v.v[n] = real(0);
             }
-            lds_put(Ir, q, pi[c], pj[c], v);
-            *reinterpret_cast<P *>(Ik + (long)(m0 * PL + pe) * ps) = v;
+            lds_put_at(Ir, q, pts.cell[c], pts.i0[c], pts.j0[c], v);
+            *reinterpret_cast<P *>(Ik + (long)m0 * PL * ps + pts.eo[c]) = v;
         }
     }
     __syncthreads();
@@ -630,8 +646,9 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a, int 
     }
     const int RS = q.RS;
     for (int t = 1; t < nz; ++t) {
-        if (t + 2 < nz) trace_fetch<real, XMODE, GC, MAXPT>(rg, Sk, Xk, ps, PL, gm.up ? t + 2 : nz - 3 - t);
+        if (t + 2 < nz) trace_fetch<real, XMODE, GC, MAXPT>(rg, Sk, Xk, ps, PL, gm.up ? t + 2 : nz - 3 - t, pts);
         const int m = gm.up ? t : nz - 1 - t;
+        real *__restrict__ Iplane = Ik + (long)m * PL * ps;            // this plane's intensities (uniform)
         const bool has_d = t <= nz - 2, has_uu = t >= 2;
         const int sp0 = t % kRing, su0 = (t + kRing - 1) % kRing, suu0 = (t + kRing - 2) % kRing,
                   sd0 = (t + 1) % kRing;
@@ -665,7 +682,7 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a, int 
                 }
                 bezier_step<real, XMODE, GC>(Iu, hds, Suu, Su, Sp, Sd, Xuu, Xu, Xp, Xd, has_d, has_uu);
                 res[c] = Iu;
-                if (tid + c * T < PL) *reinterpret_cast<P *>(Ik + (long)(m * PL + tid + c * T) * ps) = res[c];
+                if (pts.in[c]) *reinterpret_cast<P *>(Iplane + pts.eo[c]) = res[c];
             }
         } else {
             // npc pieces: the intensity at the upwind point u = path point npc is
@@ -798,19 +815,16 @@ __global__ void __launch_bounds__(kTraceThreads) k_trace(TraceArgs<real> a, int 
                     Xcur = Xdn; hcur = hdn;
                 }
                 res[c] = I;
-                if (tid + c * T < PL) *reinterpret_cast<P *>(Ik + (long)(m * PL + tid + c * T) * ps) = res[c];
+                if (pts.in[c]) *reinterpret_cast<P *>(Iplane + pts.eo[c]) = res[c];
             }
         }
         __syncthreads();
         // every read of plane t - 1 is done: the intensity plane and the slot of
         // plane t - 2 can be overwritten
 #pragma unroll
-        for (int c = 0; c < MAXPT; ++c) {
-            const int pe = tid + c * T;
-            if (pe >= PL) break;
-            lds_put(Ir, q, pi[c], pj[c], res[c]);
-        }
-        if (t + 2 < nz) trace_store<real, XMODE, GC, MAXPT>(rg, Sr, Xr, q, t + 2, add);
+        for (int c = 0; c < MAXPT; ++c)
+            if (pts.in[c]) lds_put_at(Ir, q, pts.cell[c], pts.i0[c], pts.j0[c], res[c]);
+        if (t + 2 < nz) trace_store<real, XMODE, GC, MAXPT>(rg, Sr, Xr, q, t + 2, add, pts);
         __syncthreads();
     }
 }
