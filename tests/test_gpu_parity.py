@@ -162,15 +162,18 @@ def test_ray_trace_variants_parity(gc, grey_kappa, monkeypatch):
     g.close()
 
 
-@pytest.mark.parametrize("grid", [(9, 5, 7), (8, 5, 6)], ids=["odd_points", "points_multiple_of_4"])
+@pytest.mark.parametrize("shape", [((9, 5, 7), 4, 4, 8), ((8, 5, 6), 4, 4, 8), ((9, 5, 7), 8, 8, 16)],
+                         ids=["odd_points", "points_multiple_of_4", "eight_groups_128_ordinates"])
 @pytest.mark.parametrize("prec", [B.FP32, B.FP64], ids=["fp32", "fp64"])
 @pytest.mark.parametrize("grey_kappa", [True, False], ids=["grey_chi", "group_chi"])
-def test_group_major_trace_parity(grey_kappa, prec, grid):
+def test_group_major_trace_parity(grey_kappa, prec, shape):
     """The ray trace on group-major planes (source transposed before, intensity
     after; a per-group extinction kept transposed) on one time-dependent sweep,
     then again after a new medium.  Point counts that are multiples of 4 take
-    the 16-byte transposes (here two tiles, the second partial)."""
-    spec = custom_spec(*grid, G=4, seed=23, grey_kappa=grey_kappa, gamma_max=8.0)
+    the 16-byte transposes (here two tiles, the second partial); the third case
+    has two 4-group runs per point and 128 ordinates."""
+    grid, G, nmu, nphi = shape
+    spec = custom_spec(*grid, G=G, nmu=nmu, nphi=nphi, seed=23, grey_kappa=grey_kappa, gamma_max=8.0)
     o, g = _both(spec, prec)
     g.set_variants(trace_groups=-1)
     assert g.variants()["trace_groups"] == -1
@@ -185,7 +188,7 @@ def test_group_major_trace_parity(grey_kappa, prec, grid):
         close_by_group(g.sweep_intensity(), ref_I, TOL[prec], 2, f"I_lab group-major {rep}")
         close_by_group(g.source_sh(), ref_S, TOL[prec], 1, f"S_new group-major {rep}")
         # a new medium: the transposed extinction is recomputed
-        spec = custom_spec(*grid, G=4, seed=25 + rep, grey_kappa=grey_kappa, gamma_max=6.0)
+        spec = custom_spec(*grid, G=G, nmu=nmu, nphi=nphi, seed=25 + rep, grey_kappa=grey_kappa, gamma_max=6.0)
         o = oracle.Oracle(spec)
         g.set_medium(spec["kappa"], spec["sigma"], spec["bnu"], spec.get("beta"))
         for face, key in ((0, "bc_bot"), (1, "bc_top")):
