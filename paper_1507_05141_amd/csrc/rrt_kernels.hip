@@ -1906,31 +1906,67 @@ __global__ void __launch_bounds__(64 * W) k_do2sh_f16(long R, int K, int Kp, int
 }
 
 // S2 mixed: S0[r][j] = sum_q S[r][q] Y[j][q]; Y = hi, lo FP16 tables [Kt][NLp] (Kt = K up to 16,
-// NLp = NL up to 32, NB = NLp / 32 blocks); one scale per row.  A workgroup of 4 waves takes 64
-// rows; the table is staged in LDS per chunk of 64 ordinates ([64][NLp + 8] per part).
+// NLp = NL up to 32, NB = NLp / 32 blocks); one scale per row.  A workgroup of W waves takes
+// 16 W rows; the table is staged in LDS per chunk of 64 ordinates ([64][NLp + 8] per part), the
+// next chunk loaded into registers while the current one's products run.
 template <int NB, int W = 4>
 __global__ void __launch_bounds__(64 * W) k_sh2do_f16(long R, int K, int NL, const float *__restrict__ S,
                                                    const _Float16 *__restrict__ Yh, const _Float16 *__restrict__ Yl,
                                                    float *__restrict__ C)
 {
     constexpr int NLp = NB * 32, LS = NLp + 8, JC = 64;
+    constexpr int NIT = JC * (NLp / 8), PF = (NIT + 64 * W - 1) / (64 * W);   // 16-byte table pieces
     extern __shared__ unsigned char smem_raw[];
     _Float16 *Th = reinterpret_cast<_Float16 *>(smem_raw), *Tl = Th + JC * LS;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
     const long r0 = (long)xcd_item(gridDim.x) * (16 * W) + wave * 16;
     const int Kt = (K + 15) / 16 * 16;
+    f16x8 ph[PF], pl[PF];
+    auto fetch = [&](int jc) {
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int i = threadIdx.x + u * 64 * W, row = i / (NLp / 8), q8 = (i - row * (NLp / 8)) * 8;
+            ph[u] = f16x8{};
+            pl[u] = f16x8{};
+            if (i < NIT && jc + row < Kt) {
+                ph[u] = *reinterpret_cast<const f16x8 *>(Yh + (long)(jc + row) * NLp + q8);
+                pl[u] = *reinterpret_cast<const f16x8 *>(Yl + (long)(jc + row) * NLp + q8);
+            }
+        }
+    };
+    fetch(0);
     const float *__restrict__ Srow = S + min(r0 + lr, R - 1) * (long)NL;
     float v[NB][8];
     float m = 0.f;
+    if ((NL & 7) == 0) {
+        // whole 8-value runs (rows 32-byte aligned): two 16-byte loads each
 #pragma unroll
-    for (int b = 0; b < NB; ++b) {
+        for (int b = 0; b < NB; ++b) {
+            const int q = 32 * b + 8 * lg;
+            f32x4 x = {0.f, 0.f, 0.f, 0.f}, y = {0.f, 0.f, 0.f, 0.f};
+            if (q < NL) {
+                x = *reinterpret_cast<const f32x4 *>(Srow + q);
+                y = *reinterpret_cast<const f32x4 *>(Srow + q + 4);
+            }
 #pragma unroll
-        for (int i = 0; i < 8; ++i) {
-            const int q = 32 * b + 8 * lg + i;
-            v[b][i] = q < NL ? Srow[q] : 0.f;
-            m = fmaxf(m, fabsf(v[b][i]));
+            for (int i = 0; i < 4; ++i) {
+                v[b][i] = x[i];
+                v[b][4 + i] = y[i];
+            }
         }
+    } else {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int q = 32 * b + 8 * lg + i;
+                v[b][i] = q < NL ? Srow[q] : 0.f;
+            }
     }
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(v[b][i]));
     float sc, inv;
     fp16_scale(quad_max(m), sc, inv);
     f16x8 ah[NB], al[NB];
@@ -1939,17 +1975,16 @@ __global__ void __launch_bounds__(64 * W) k_sh2do_f16(long R, int K, int NL, con
     const bool kvec = (K & 3) == 0;
     for (int jc = 0; jc < Kt; jc += JC) {
         __syncthreads();
-        for (int i = threadIdx.x; i < JC * (NLp / 8); i += blockDim.x) {
-            const int row = i / (NLp / 8), q8 = (i - row * (NLp / 8)) * 8;
-            f16x8 h = {}, l = {};
-            if (jc + row < Kt) {
-                h = *reinterpret_cast<const f16x8 *>(Yh + (long)(jc + row) * NLp + q8);
-                l = *reinterpret_cast<const f16x8 *>(Yl + (long)(jc + row) * NLp + q8);
+#pragma unroll
+        for (int u = 0; u < PF; ++u) {
+            const int i = threadIdx.x + u * 64 * W, row = i / (NLp / 8), q8 = (i - row * (NLp / 8)) * 8;
+            if (i < NIT) {
+                *reinterpret_cast<f16x8 *>(Th + row * LS + q8) = ph[u];
+                *reinterpret_cast<f16x8 *>(Tl + row * LS + q8) = pl[u];
             }
-            *reinterpret_cast<f16x8 *>(Th + row * LS + q8) = h;
-            *reinterpret_cast<f16x8 *>(Tl + row * LS + q8) = l;
         }
         __syncthreads();
+        if (jc + JC < Kt) fetch(jc + JC);
 #pragma unroll
         for (int c = 0; c < JC / 16; ++c) {
             const int j0 = jc + 16 * c;
