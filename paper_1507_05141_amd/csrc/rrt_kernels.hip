@@ -2322,9 +2322,48 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, TEMP ? 2 : 4)
         }
         __syncthreads();
         // S[j][q] = sigma / chi_j (A I)[j][q], plus the thermal term at q = 0; with RESID
-        // also each row's sums (S - S_old)^2 and S^2 in FP64 (a row is NL4 consecutive
-        // lanes, NL4 dividing 64), for the residual
+        // also each row's sums (S - S_old)^2 and S^2 in FP64, for the residual
         float *dst = a.S + p * GN;
+        if (NL4 % kPre == 0) {
+            // a row is NL4 / 4 consecutive lanes, each with four of its 16-byte pieces
+            // (the lanes of a row store 256-byte runs), so that the row sums take
+            // log2(NL4 / 4) cross-lane steps once per point
+            const int tpr = NL4 / kPre, j = tid / tpr, t = tid - j * tpr;
+            double dd = 0.0, aa = 0.0;
+            if (j < G) {
+                const float f = sF[j];
+#pragma unroll
+                for (int u = 0; u < kPre; ++u) {
+                    const int q4 = t + tpr * u, i = j * NL4 + q4;
+                    P4 v = *reinterpret_cast<const P4 *>(sI + j * RS + 4 * q4);
+                    v *= f;
+                    if (q4 == 0) v.x += sT[j];
+                    reinterpret_cast<P4 *>(dst)[i] = v;
+                    if (RESID) {
+                        const P4 o = reinterpret_cast<const P4 *>(sO)[i];
+#pragma unroll
+                        for (int c = 0; c < 4; ++c) {
+                            const double uu = (double)v[c], d = uu - (double)o[c];
+                            dd += d * d;
+                            aa += uu * uu;
+                        }
+                    }
+                }
+            }
+            if (RESID) {
+                for (int off = tpr >> 1; off > 0; off >>= 1) {
+                    dd += __shfl_xor(dd, off, 64);
+                    aa += __shfl_xor(aa, off, 64);
+                }
+                if (j < G && t == 0) {
+                    rows[(long)j * a.P + p] = dd;
+                    rows[(long)(G + j) * a.P + p] = aa;
+                }
+            }
+            __syncthreads();                               // the next point overwrites the table and factors
+            continue;
+        }
+        // a row is NL4 consecutive lanes, NL4 dividing 64
 #pragma unroll
         for (int u = 0; u < kPre; ++u) {
             const int i = tid + u * kComptonMfmaThreads;
