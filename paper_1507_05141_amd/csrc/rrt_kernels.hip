@@ -960,6 +960,11 @@ __device__ __forceinline__ void general_remap(const real *F, int KS, const FreqI
     }
 }
 
+// 2^(y dl2): the frequency factor 1/D of the lab extinction (dl2 = the group spacing in
+// log2(nu)); the hardware base-2 exponential in FP32
+__device__ __forceinline__ float exp_dl(float y, float dl2) { return __builtin_amdgcn_exp2f(y * dl2); }
+__device__ __forceinline__ double exp_dl(double y, double dl2) { return exp2(y * dl2); }
+
 // S~ = (chi S + I_prev/(c dt)) / (chi + 1/(c dt)); in steady state S (or 0 where chi = 0)
 __device__ __forceinline__ float time_terms(float chi, float S, float ip, float icdt)
 {
@@ -1213,6 +1218,7 @@ __global__ void __launch_bounds__(kRemapThreads, 4) k_boost(BoostArgs<real> a)
         __syncthreads();
     }
     const real icdt = a.inv_cdt;
+    const real dl2 = (real)(a.fi.delta * 1.4426950408889634);   // the group spacing in log2(nu)
     for (int kb = kb0; kb < K; kb += nwaves * OB) {
         const int nk = min(OB, K - kb), nit = nk * IC;
         if (kb != kb0) fetch_ordinates(kb);
@@ -1287,13 +1293,14 @@ __global__ void __launch_bounds__(kRemapThreads, 4) k_boost(BoostArgs<real> a)
 #pragma unroll
                         for (int i = 0; i < 4; ++i) cx[i] = i < W ? C[g0 + i] : real(0);
                     } else {
-                        const real sf = floor(kp), f = kp - sf, invD = exp(kp * (real)a.fi.delta);
+                        // the W + 1 comoving values the item's groups interpolate between
+                        const real sf = floor(kp), f = kp - sf, invD = exp_dl(kp, dl2);
+                        const int i0 = g0 + (int)sf;
+                        real cv[5];
 #pragma unroll
-                        for (int i = 0; i < 4; ++i) {
-                            const int i0 = g0 + i + (int)sf;
-                            const int lo = min(max(i0, 0), G - 1), hi = min(max(i0 + 1, 0), G - 1);
-                            cx[i] = invD * ((real(1) - f) * C[lo] + f * C[hi]);
-                        }
+                        for (int i = 0; i < 5; ++i) cv[i] = i <= W ? C[min(max(i0 + i, 0), G - 1)] : real(0);
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) cx[i] = invD * (cv[i] + f * (cv[i + 1] - cv[i]));
                     }
                 } else {
 #pragma unroll
