@@ -2196,9 +2196,10 @@ __global__ void __launch_bounds__(256) k_source_compton(SourceArgs<real> a)
 
 // Compton source on the matrix cores (FP32, G <= 32, L <= 15): for each l the
 // group-to-group product S_l = A_l I_l is a 32 x 32 (j x i) by 32 x (2l + 1)
-// (i x q) product, one v_mfma_f32_32x32x2f32 chain of K = 32.  Wave w of eight
-// takes the angular orders l = w and w + 8 and holds their A_l in registers for
-// the whole launch; the workgroup walks points (persistent), staging a point's
+// (i x q) product.  Wave w of eight takes the angular orders l = w and w + 8
+// and holds their A_l in registers for the whole launch: order w (at most 15
+// columns) as two 16-row v_mfma_f32_16x16x4f32 chains of K = 32 (16 columns),
+// order w + 8 as one v_mfma_f32_32x32x2f32 chain (32 columns); the workgroup walks points (persistent), staging a point's
 // SH intensities in LDS while the next point's are loaded into registers.  The
 // products overwrite the intensities in LDS (a wave writes only the columns of
 // its own orders, after it has read them) and leave as 16-byte scaled stores.
@@ -2221,8 +2222,9 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, TEMP ? 2 : 4)
     const int n = lane & 31, kh = lane >> 5;               // B / C column, K half
     // rows G..31 stay zero: they meet zero columns of A
     for (int i = G * RS + tid; i < 32 * RS; i += kComptonMfmaThreads) sI[i] = 0.0f;
-    // A_l[m][k] for this wave's orders: lane holds m = n, k = 2 ks + kh.  With
-    // temperature nodes the lane holds the lower node's table (A0) and the
+    // A_l[m][k] for this wave's orders: for order w + 8 (32 x 32 x 2) lane holds
+    // m = n, k = 2 ks + kh in element ks; for order w (16 x 16 x 4) element e holds
+    // m = 16 (e / 8) + lane % 16, k = 4 (e % 8) + lane / 16.  With temperature nodes the lane holds the lower node's table (A0) and the
     // difference to the upper one (Ad) of the bracket in use, reloaded when a
     // point's bracket differs (points come in order, and a smooth temperature
     // field changes bracket rarely); a point's table is A0 + w Ad.
@@ -2236,9 +2238,10 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, TEMP ? 2 : 4)
             const int l = wave + 8 * t;
 #pragma unroll
             for (int ks = 0; ks < 16; ++ks) {
-                const int k = 2 * ks + kh;
-                const bool in = l <= lmax && n < G && k < G;
-                const long o = node * LGG + ((long)l * G + n) * G + k;
+                const int m = t ? n : 16 * (ks >> 3) + (lane & 15);
+                const int k = t ? 2 * ks + kh : 4 * (ks & 7) + (lane >> 4);
+                const bool in = l <= lmax && m < G && k < G;
+                const long o = node * LGG + ((long)l * G + m) * G + k;
                 A0[t][ks] = in ? a.A[o] : 0.0f;
                 if (TEMP) Ad[t][ks] = in ? a.A[o + LGG] - A0[t][ks] : 0.0f;
             }
@@ -2296,8 +2299,36 @@ __global__ void __launch_bounds__(kComptonMfmaThreads, TEMP ? 2 : 4)
         }
         if (idx + 1 < pend) fetch(idx + 1);
         __syncthreads();
+        // order w: two 16 x 16 x 4 chains (rows 0-15, 16-31) over 16 columns
+        if (wave <= lmax) {
+            const int l = wave, q0 = l * l, nq = 2 * l + 1;
+            const int cn = lane & 15, kg = lane >> 4;
+            const float *col = sI + q0 + min(cn, nq - 1);
+            float b[8];
 #pragma unroll
-        for (int t = 0; t < 2; ++t) {
+            for (int ks = 0; ks < 8; ++ks) b[ks] = col[(4 * ks + kg) * RS];
+            asm volatile("" : "+v"(b[0]), "+v"(b[1]), "+v"(b[2]), "+v"(b[3]), "+v"(b[4]), "+v"(b[5]), "+v"(b[6]),
+                         "+v"(b[7]));
+            f32x4 lo = {0.f, 0.f, 0.f, 0.f}, hi = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int ks = 0; ks < 8; ++ks) {
+                lo = __builtin_amdgcn_mfma_f32_16x16x4f32(TEMP ? A0[0][ks] + w * Ad[0][ks % (TEMP ? 16 : 1)] : A0[0][ks],
+                                                          b[ks], lo, 0, 0, 0);
+                hi = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                    TEMP ? A0[0][8 + ks] + w * Ad[0][(8 + ks) % (TEMP ? 16 : 1)] : A0[0][8 + ks], b[ks], hi, 0, 0, 0);
+            }
+            // register r of lane l holds row 4 (l / 16) + r of column l % 16 (+ 16 for hi)
+            if (cn < nq) {
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int m = 4 * kg + r;
+                    if (m < G) sI[m * RS + q0 + cn] = lo[r];
+                    if (m + 16 < G) sI[(m + 16) * RS + q0 + cn] = hi[r];
+                }
+            }
+        }
+#pragma unroll
+        for (int t = 1; t < 2; ++t) {
             const int l = wave + 8 * t;
             if (l > lmax) break;
             const int q0 = l * l, nq = 2 * l + 1;
