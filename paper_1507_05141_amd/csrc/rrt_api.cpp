@@ -1210,8 +1210,11 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
         return bail(s);
     if (pr->prec == RRT_MIXED) {
         // FP16 hi + lo tables in the layouts of the matrix-core operands: Y16[K up to 16][NL up
-        // to 32] (forward product) and WYt16[NL up to 16][K up to 32] (backward), zero padded
-        const int Kt = (K + 15) / 16 * 16, NLp = (NL + 31) / 32 * 32, NLr = (NL + 15) / 16 * 16, Kp = (K + 31) / 32 * 32;
+        // to the forward kernel's row width: 32, 64, 128 or 256] and WYt16[NL up to the backward
+        // kernel's column count: 16, 64 or 256][K up to 32], zero padded
+        const int Kt = (K + 15) / 16 * 16, Kp = (K + 31) / 32 * 32;
+        const int NLp = NL <= 32 ? 32 : NL <= 64 ? 64 : NL <= 128 ? 128 : 256;
+        const int NLr = NL <= 16 ? 16 : NL <= 64 ? 64 : 256;
         pr->y16_n = (size_t)Kt * NLp;
         pr->wyt16_n = (size_t)NLr * Kp;
         std::vector<_Float16> y16(2 * pr->y16_n, (_Float16)0.0f), wyt16(2 * pr->wyt16_n, (_Float16)0.0f);

@@ -93,6 +93,11 @@ CASES = {
     # single column (nx = ny = 1)
     "two_d_groups": dict(nx=12, ny=1, nz=9, G=4, seed=12, gamma_max=6.0),
     "one_column": dict(nx=1, ny=1, nz=16, G=2, seed=13, nmu=8, nphi=16),
+    # SH orders whose term counts are not the matrix-core tiles' widths (25, 81, 144 terms)
+    "thomson_L4": dict(nx=4, ny=4, nz=3, G=3, lmax=4, nmu=8, nphi=16, seed=14),
+    "thomson_L8": dict(nx=4, ny=3, nz=3, G=2, lmax=8, nmu=10, nphi=18, seed=15),
+    "compton_L11": dict(nx=3, ny=3, nz=3, G=4, lmax=11, nmu=12, nphi=24, scatter="compton", seed=16,
+                        edges=np.exp(np.linspace(np.log(1.0), np.log(150.0), 5)), mec2=W.MEC2_KEV),
     # L = 15 (256 SH terms, 16 x 32 ordinates): the widest SH products and Compton source
     "compton_L15": dict(nx=4, ny=4, nz=3, G=4, lmax=15, nmu=16, nphi=32, scatter="compton", seed=9,
                         edges=np.exp(np.linspace(np.log(1.0), np.log(150.0), 5)), mec2=W.MEC2_KEV),
