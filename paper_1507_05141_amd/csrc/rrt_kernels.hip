@@ -1912,6 +1912,104 @@ __global__ void __launch_bounds__(64 * W) k_do2sh_f16(long R, int K, int Kp, int
         }
 }
 
+// S6 mixed for NT 16-column tiles in one workgroup of W waves (16 W rows): the
+// table goes from global memory straight into LDS (global_load_lds, 16 bytes per
+// lane) in chunks of 32 ordinates, double buffered, so that the next chunk's table
+// and the rows' next 32 values load during the current chunk's products (one
+// barrier per chunk).  A chunk is 2 NT blocks of 1 KB (hi, then lo part; column
+// tile c): row r of a block (column 16 c + r of the output) at 64 r bytes, its
+// ordinates 8 s .. 8 s + 7 in 16-byte slot s ^ ((r >> 2) & 3), so that the 16
+// rows a lane group reads fall on distinct banks.  Kp a multiple of 32; the
+// tables hold 16 NT rows.
+template <int NT, int W>
+__global__ void __launch_bounds__(64 * W) k_do2sh_f16_dma(long R, int K, int Kp, int NL, const float *__restrict__ A,
+                                                       const _Float16 *__restrict__ WYh,
+                                                       const _Float16 *__restrict__ WYl, float *__restrict__ C)
+{
+    constexpr int NB = 2 * NT, BPW = NB / W;                         // 1 KB blocks per chunk, per wave
+    static_assert(NB % W == 0, "whole blocks per wave");
+    extern __shared__ unsigned char smem_raw[];
+    _Float16 *buf = reinterpret_cast<_Float16 *>(smem_raw);         // [2][NB][512]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
+    const long r0 = (long)xcd_item(gridDim.x) * (16 * W) + wave * 16;
+    const bool vec = (K & 3) == 0;
+    const float *__restrict__ Arow = A + min(r0 + lr, R - 1) * (long)K;
+    // the piece this lane moves: row dr of a block, into slot lane & 3 (ordinates 8 ds ..)
+    const int dr = lane >> 2, ds = (lane & 3) ^ ((dr >> 2) & 3);
+    auto dma = [&](int kc, int b) {
+        _Float16 *dst = buf + (size_t)b * NB * 512;
+#pragma unroll
+        for (int u = 0; u < BPW; ++u) {
+            const int blk = wave * BPW + u, part = blk / NT, c = blk - part * NT;
+            const _Float16 *src = (part ? WYl : WYh) + (long)(16 * c + dr) * Kp + kc + 8 * ds;
+            __builtin_amdgcn_global_load_lds((const void *)src,
+                                             (__attribute__((address_space(3))) void *)(dst + blk * 512), 16, 0, 0);
+        }
+    };
+    float nv[8];
+    auto load_rows = [&](int kc) {
+        const int k = kc + 8 * lg;
+        if (vec && k + 7 < K) {
+            const f32x4 x = *reinterpret_cast<const f32x4 *>(Arow + k);
+            const f32x4 y = *reinterpret_cast<const f32x4 *>(Arow + k + 4);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                nv[i] = x[i];
+                nv[4 + i] = y[i];
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 8; ++i) nv[i] = (k + i < K) ? Arow[k + i] : 0.f;
+        }
+    };
+    const int ro = lr * 32 + 8 * (lg ^ ((lr >> 2) & 3));            // this lane's operand slot, in halfs
+    f32x4 acc[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nch = Kp / 32;
+    dma(0, 0);
+    load_rows(0);
+    for (int ci = 0; ci < nch; ++ci) {
+        float v[8];
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = nv[i];
+        __builtin_amdgcn_s_waitcnt(0);                  // this wave's pieces of the chunk and its values have landed
+        __syncthreads();                                // every wave's: the chunk is whole, the other buffer free
+        if (ci + 1 < nch) {
+            dma(32 * (ci + 1), (ci + 1) & 1);
+            load_rows(32 * (ci + 1));
+        }
+        const _Float16 *Tb = buf + (size_t)(ci & 1) * NB * 512;
+        float m = 0.f;
+#pragma unroll
+        for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(v[i]));
+        float sc, inv;
+        fp16_scale(quad_max(m), sc, inv);
+        f16x8 ah, al;
+        split_f16x8(v, sc, ah, al);
+        // inverse scales of the output rows 4 lg + i of this tile
+        float ri[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) ri[i] = __shfl(inv, 4 * lg + i, 64);
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            const f32x4 p = mfma3(ah, al, *reinterpret_cast<const f16x8 *>(Tb + c * 512 + ro),
+                                  *reinterpret_cast<const f16x8 *>(Tb + (NT + c) * 512 + ro), f32x4{0.f, 0.f, 0.f, 0.f});
+#pragma unroll
+            for (int i = 0; i < 4; ++i) acc[c][i] += p[i] * ri[i];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+        const int col = 16 * c + lr;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const long r = r0 + 4 * lg + i;
+            if (r < R && col < NL) C[r * NL + col] = acc[c][i];
+        }
+    }
+}
+
 // S2 mixed: S0[r][j] = sum_q S[r][q] Y[j][q]; Y = hi, lo FP16 tables [Kt][NLp] (Kt = K up to 16,
 // NLp = NL up to 32, NB = NLp / 32 blocks); one scale per row.  A workgroup of W waves takes
 // 16 W rows; the table is staged in LDS per chunk of 64 ordinates ([64][NLp + 8] per part), the
@@ -3099,9 +3197,9 @@ bool launch_do2sh_f16(long R, int K, int NL, const float *A, const _Float16 *WYh
         if (rt == 0 || rt == 1) {
             const long nb = (R + 127) / 128;
             if (nb > 0x7fffffffL) return false;
-            const size_t sm = 2 * sizeof(_Float16) * (size_t)(16 * 16) * 72;
-            hipLaunchKernelGGL((k_do2sh_f16<16, 1, 8>), dim3((unsigned)(8 * ((nb + 7) / 8))), dim3(512), sm, st, R, K,
-                               Kp, NL, A, WYh, WYl, C);
+            const size_t sm = 2 * sizeof(_Float16) * 2 * 16 * 512;          // two chunks of 32 1 KB blocks
+            hipLaunchKernelGGL((k_do2sh_f16_dma<16, 8>), dim3((unsigned)(8 * ((nb + 7) / 8))), dim3(512), sm, st, R,
+                               K, Kp, NL, A, WYh, WYl, C);
             return true;
         }
     }
@@ -3525,11 +3623,11 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_do2sh_f16<4, 1, 16>),
                          reinterpret_cast<const void *>(&k_do2sh_f16<4, 2, 16>),
                          reinterpret_cast<const void *>(&k_do2sh_f16<4, 4, 4>),
-                         reinterpret_cast<const void *>(&k_do2sh_f16<16, 1, 8>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<1, 16>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<2, 16>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<4>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<8, 8>),
+                         reinterpret_cast<const void *>(&k_do2sh_f16_dma<16, 8>),
                          reinterpret_cast<const void *>(&k_source_compton_mfma<false, false>),
                          reinterpret_cast<const void *>(&k_source_compton_mfma<true, false>),
                          reinterpret_cast<const void *>(&k_source_compton_mfma<false, true>),
