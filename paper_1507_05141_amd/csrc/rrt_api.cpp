@@ -1209,10 +1209,10 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
         (s = alloc_upload_real(pr, &pr->d_Yt, Yt)) || (s = alloc_upload_real(pr, &pr->d_WY, WY)))
         return bail(s);
     if (pr->prec == RRT_MIXED) {
-        // FP16 hi + lo tables in the layouts of the matrix-core operands: Y16[K up to 16][NL up
+        // FP16 hi + lo tables in the layouts of the matrix-core operands: Y16[K up to 32][NL up
         // to the forward kernel's row width: 32, 64, 128 or 256] and WYt16[NL up to the backward
         // kernel's column count: 16, 64 or 256][K up to 32], zero padded
-        const int Kt = (K + 15) / 16 * 16, Kp = (K + 31) / 32 * 32;
+        const int Kt = (K + 31) / 32 * 32, Kp = (K + 31) / 32 * 32;
         const int NLp = NL <= 32 ? 32 : NL <= 64 ? 64 : NL <= 128 ? 128 : 256;
         const int NLr = NL <= 16 ? 16 : NL <= 64 ? 64 : 256;
         pr->y16_n = (size_t)Kt * NLp;

@@ -2119,6 +2119,105 @@ __global__ void __launch_bounds__(64 * W) k_sh2do_f16(long R, int K, int NL, con
     }
 }
 
+// S2 mixed for NB 32-term SH blocks (NLp = 32 NB) in one workgroup of W waves (16 W rows),
+// the table moving from global memory straight into LDS (global_load_lds) in double-
+// buffered chunks of 32 ordinates: per part (hi, lo), ordinate tile c (16 ordinates) and
+// SH block b one 1 KB block of 16 ordinates x 32 terms, laid out as in k_do2sh_f16_dma
+// (ordinate r at 64 r bytes, terms 8 s .. 8 s + 7 in slot s ^ ((r >> 2) & 3)).  The
+// tables hold a multiple of 32 ordinates; tiles past Kt (K up to 16) are skipped.
+template <int NB, int W>
+__global__ void __launch_bounds__(64 * W) k_sh2do_f16_dma(long R, int K, int NL, const float *__restrict__ S,
+                                                       const _Float16 *__restrict__ Yh,
+                                                       const _Float16 *__restrict__ Yl, float *__restrict__ C)
+{
+    constexpr int NLp = NB * 32, TPC = 2, NBLK = 2 * TPC * NB, BPW = NBLK / W;
+    static_assert(NBLK % W == 0, "whole blocks per wave");
+    extern __shared__ unsigned char smem_raw[];
+    _Float16 *buf = reinterpret_cast<_Float16 *>(smem_raw);         // [2][NBLK][512]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
+    const long r0 = (long)xcd_item(gridDim.x) * (16 * W) + wave * 16;
+    const int Kt = (K + 15) / 16 * 16, nch = (Kt + 31) / 32;
+    const int dr = lane >> 2, ds = (lane & 3) ^ ((dr >> 2) & 3);
+    auto dma = [&](int jc, int bsel) {
+        _Float16 *dst = buf + (size_t)bsel * NBLK * 512;
+#pragma unroll
+        for (int u = 0; u < BPW; ++u) {
+            const int blk = wave * BPW + u, part = blk / (TPC * NB), c = (blk / NB) % TPC, b = blk % NB;
+            const _Float16 *src = (part ? Yl : Yh) + (long)(jc + 16 * c + dr) * NLp + 32 * b + 8 * ds;
+            __builtin_amdgcn_global_load_lds((const void *)src,
+                                             (__attribute__((address_space(3))) void *)(dst + blk * 512), 16, 0, 0);
+        }
+    };
+    dma(0, 0);
+    const float *__restrict__ Srow = S + min(r0 + lr, R - 1) * (long)NL;
+    float v[NB][8];
+    if ((NL & 7) == 0) {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int q = 32 * b + 8 * lg;
+            f32x4 x = {0.f, 0.f, 0.f, 0.f}, y = {0.f, 0.f, 0.f, 0.f};
+            if (q < NL) {
+                x = *reinterpret_cast<const f32x4 *>(Srow + q);
+                y = *reinterpret_cast<const f32x4 *>(Srow + q + 4);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                v[b][i] = x[i];
+                v[b][4 + i] = y[i];
+            }
+        }
+    } else {
+#pragma unroll
+        for (int b = 0; b < NB; ++b)
+#pragma unroll
+            for (int i = 0; i < 8; ++i) {
+                const int q = 32 * b + 8 * lg + i;
+                v[b][i] = q < NL ? Srow[q] : 0.f;
+            }
+    }
+    float m = 0.f;
+#pragma unroll
+    for (int b = 0; b < NB; ++b)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(v[b][i]));
+    float sc, inv;
+    fp16_scale(quad_max(m), sc, inv);
+    f16x8 ah[NB], al[NB];
+#pragma unroll
+    for (int b = 0; b < NB; ++b) split_f16x8(v[b], sc, ah[b], al[b]);
+    const int ro = lr * 32 + 8 * (lg ^ ((lr >> 2) & 3));
+    const bool kvec = (K & 3) == 0;
+    const long r = r0 + lr;
+    for (int ci = 0; ci < nch; ++ci) {
+        __builtin_amdgcn_s_waitcnt(0);                  // this wave's pieces of the chunk have landed
+        __syncthreads();                                // every wave's: the chunk is whole, the other buffer free
+        if (ci + 1 < nch) dma(32 * (ci + 1), (ci + 1) & 1);
+        const _Float16 *Tb = buf + (size_t)(ci & 1) * NBLK * 512;
+#pragma unroll
+        for (int c = 0; c < TPC; ++c) {
+            const int j0 = 32 * ci + 16 * c;
+            if (j0 >= Kt) break;
+            // the tile transposed (table as the first operand): lane (lr, lg) gets ordinates
+            // j0 + 4 lg .. + 3 of row r0 + lr, rescaled by that row's own factor
+            f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int b = 0; b < NB; ++b)
+                acc = mfma3(*reinterpret_cast<const f16x8 *>(Tb + (c * NB + b) * 512 + ro),
+                            *reinterpret_cast<const f16x8 *>(Tb + ((TPC + c) * NB + b) * 512 + ro), ah[b], al[b], acc);
+            const int col = j0 + 4 * lg;
+            if (r < R) {
+                if (kvec && col + 3 < K) {
+                    *reinterpret_cast<f32x4 *>(C + r * K + col) = acc * inv;
+                } else {
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (col + i < K) C[r * K + col + i] = acc[i] * inv;
+                }
+            }
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // S1: source function in SH space
 // ---------------------------------------------------------------------------
@@ -3224,8 +3323,8 @@ bool launch_sh2do_f16(long R, int K, int NL, const float *S, const _Float16 *Yh,
         // eight waves share each staged table chunk
         const long nb8 = (R + 127) / 128;
         if (nb8 > 0x7fffffffL) return false;
-        hipLaunchKernelGGL((k_sh2do_f16<8, 8>), dim3((unsigned)(8 * ((nb8 + 7) / 8))), dim3(512), sm(8), st, R, K, NL, S,
-                           Yh, Yl, C);
+        hipLaunchKernelGGL((k_sh2do_f16_dma<8, 8>), dim3((unsigned)(8 * ((nb8 + 7) / 8))), dim3(512),
+                           2 * sizeof(_Float16) * 32 * 512, st, R, K, NL, S, Yh, Yl, C);
     }
     else return false;
     return true;
@@ -3626,7 +3725,7 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_sh2do_f16<1, 16>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<2, 16>),
                          reinterpret_cast<const void *>(&k_sh2do_f16<4>),
-                         reinterpret_cast<const void *>(&k_sh2do_f16<8, 8>),
+                         reinterpret_cast<const void *>(&k_sh2do_f16_dma<8, 8>),
                          reinterpret_cast<const void *>(&k_do2sh_f16_dma<16, 8>),
                          reinterpret_cast<const void *>(&k_source_compton_mfma<false, false>),
                          reinterpret_cast<const void *>(&k_source_compton_mfma<true, false>),
