@@ -251,6 +251,38 @@ def test_time_dependent_sweep_parity(prec):
     g.close()
 
 
+@pytest.mark.parametrize("prec", [B.FP64, B.FP32], ids=["fp64", "fp32"])
+def test_depth_cut_with_a_bright_upwind_slab(prec):
+    """The multi-piece walk's depth cut at its worst: a short time step (pieces of
+    at least ~14 optical depths of the time term, so the FP32 walk starts two or
+    three pieces upwind, the FP64 one four) and a stage-start intensity a thousand
+    times brighter in the slab x < 0.3 than elsewhere, which the shallow ordinates
+    cross before reaching the dim points.  The oracle walks every piece; FP64 is
+    held to 1e-9 of each element (down to 1e-6 of its group's maximum), FP32 to
+    the usual 1e-5 of the group scale."""
+    spec = custom_spec(12, 12, 6, G=2, nmu=8, nphi=16, seed=31, gamma_max=2.0)
+    o, g = _both(spec, prec)
+    rs = np.random.default_rng(32)
+    I_prev = rs.uniform(1e-3, 2e-3, o.lab_shape())
+    x = (np.arange(o.P) % spec["nx"] + 0.5) / spec["nx"]
+    I_prev[:, x < 0.3, :] *= 1000.0
+    S = o.initial_source(I_prev)
+    dt = 1.0 / 200.0
+    ref_I, _, ref_S, _ = o.sweep(S, I_prev, 1.0 / dt)
+    g.set_intensity(I_prev)
+    g.set_source_sh(S)
+    g.sweep(dt)
+    got = g.sweep_intensity()
+    close_by_group(got, ref_I, TOL[prec], 2, "I_lab")
+    close_by_group(g.source_sh(), ref_S, TOL[prec], 1, "S_new")
+    if prec == B.FP64:
+        big = np.abs(ref_I) >= 1e-6 * np.abs(ref_I).max(axis=(0, 1), keepdims=True)
+        rel = np.abs(got - ref_I)[big] / np.abs(ref_I)[big]
+        print(f"worst element error {rel.max():.2e} relative to the element", flush=True)
+        assert rel.max() <= 1e-9
+    g.close()
+
+
 def _close_moments(got, ref, rtol, what):
     J, H, K = got
     Jr, Hr, Kr = ref
