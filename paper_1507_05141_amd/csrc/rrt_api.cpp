@@ -88,6 +88,7 @@ struct rrt_problem {
     int *d_order = nullptr;                         // ordinates by decreasing number of path pieces
     int nmulti = 0;                                 // ordinates whose path takes more than one piece
     void *d_Yt = nullptr, *d_WY = nullptr, *d_A = nullptr, *d_sg = nullptr;
+    void *d_Y = nullptr, *d_WYt = nullptr;          // RRT_FP32: the SH tables transposed (the products' k contiguous)
     void *d_Y16 = nullptr, *d_WYt16 = nullptr;     // RRT_MIXED: FP16 SH tables, hi then lo part (zero padded)
     size_t y16_n = 0, wyt16_n = 0;                  // elements per part
     rrt::FreqInfo fi{};
@@ -344,8 +345,11 @@ struct Engine {
     }
 
     // row-major C[M][N] = A[M][Kd] . B[Kd][N] on the matrix cores (the library's panel kernel)
-    rrt_status gemm(long M, int N, int Kd, const real *A, const real *Bm, real *C)
+    rrt_status gemm(long M, int N, int Kd, const real *A, const real *Bm, real *C, const void *Bt = nullptr)
     {
+        if (sizeof(real) == 4 && Kd > 64 &&
+            rrt::launch_gemm_dma(M, Kd, N, (const float *)A, (const float *)Bt, (float *)C, pr->stream))
+            return check_launch();
         rrt::launch_gemm<real>(M, Kd, N, A, Bm, C, pr->stream);
         return check_launch();
     }
@@ -360,7 +364,7 @@ struct Engine {
                                                            y16 + pr->y16_n, (float *)pr->d_co, pr->stream))
             s = check_launch();
         else
-            s = gemm(pr->P * pr->G, pr->K, pr->NL, static_cast<const real *>(S), R(pr->d_Yt), R(pr->d_co));
+            s = gemm(pr->P * pr->G, pr->K, pr->NL, static_cast<const real *>(S), R(pr->d_Yt), R(pr->d_co), pr->d_Y);
         prof_end(pr, KI_SH2DO);
         if (s) return s;
         rrt::BoostArgs<real> b;
@@ -438,7 +442,7 @@ struct Engine {
             rrt::launch_do2sh_f32(pr->P * pr->G, pr->K, pr->NL, (const float *)pr->d_co, (const float *)pr->d_WY,
                                   (float *)pr->d_Ilm, pr->stream, rt))
             return check_launch();
-        return gemm(pr->P * pr->G, pr->NL, pr->K, R(pr->d_co), R(pr->d_WY), R(pr->d_Ilm));
+        return gemm(pr->P * pr->G, pr->NL, pr->K, R(pr->d_co), R(pr->d_WY), R(pr->d_Ilm), pr->d_WYt);
     }
 
     // --- autotuning of the kernel variants ---------------------------------
@@ -1034,7 +1038,7 @@ void rrt_destroy(rrt_problem *pr)
     if (pr->stream) (void)hipStreamSynchronize(pr->stream);
     clear_graphs(pr);
     if (pr->h_red) (void)hipHostFree(pr->h_red);
-    void *bufs[] = {pr->d_dir, pr->d_mu, pr->d_lnc, pr->d_nu3, pr->d_inv_nu3, pr->d_inv_dc, pr->d_geo, pr->d_taps, pr->d_order, pr->d_Yt, pr->d_WY,
+    void *bufs[] = {pr->d_dir, pr->d_mu, pr->d_lnc, pr->d_nu3, pr->d_inv_nu3, pr->d_inv_dc, pr->d_geo, pr->d_taps, pr->d_order, pr->d_Yt, pr->d_WY, pr->d_Y, pr->d_WYt,
                     pr->d_Y16, pr->d_WYt16,
                     pr->d_A, pr->d_sg, pr->d_tnode, pr->d_twt, pr->d_torder, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_gam, pr->d_chi0, pr->d_chilab, pr->d_plan, pr->d_chilabT, pr->d_bc[0], pr->d_bc[1],
                     pr->d_S, pr->d_Snew, pr->d_Ilm, pr->d_co, pr->d_St, pr->d_Xt, pr->d_Ilab, pr->d_I, pr->d_Iin,
@@ -1208,6 +1212,13 @@ rrt_status rrt_create(const rrt_grid *grid, const rrt_groups *groups, const rrt_
     if ((s = upload_double(pr, (void **)&pr->d_dir, pr->dir)) || (s = upload_double(pr, (void **)&pr->d_mu, pr->mu)) ||
         (s = alloc_upload_real(pr, &pr->d_Yt, Yt)) || (s = alloc_upload_real(pr, &pr->d_WY, WY)))
         return bail(s);
+    if (pr->prec == RRT_FP32) {
+        // Y[k][q] (the forward product's B transposed) and WYt[q][k] (the backward one's)
+        std::vector<double> WYt((size_t)NL * K);
+        for (int k = 0; k < K; ++k)
+            for (int q = 0; q < NL; ++q) WYt[(size_t)q * K + k] = WY[(size_t)k * NL + q];
+        if ((s = alloc_upload_real(pr, &pr->d_Y, pr->Y)) || (s = alloc_upload_real(pr, &pr->d_WYt, WYt))) return bail(s);
+    }
     if (pr->prec == RRT_MIXED) {
         // FP16 hi + lo tables in the layouts of the matrix-core operands: Y16[K up to 32][NL up
         // to the forward kernel's row width: 32, 64, 128 or 256] and WYt16[NL up to the backward

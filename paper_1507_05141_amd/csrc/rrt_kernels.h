@@ -166,6 +166,9 @@ template <typename real> void launch_chilab(const ChiLabArgs<real> &a, hipStream
 // product).  rt: 16-row tiles per wave (1, 2 or 4; 0 = the default for NL)
 // row-major C[R][N] = A[R][Kd] B[Kd][N] on the matrix cores (FP32 or FP64), any sizes
 template <typename real> void launch_gemm(long R, int Kd, int N, const real *A, const real *B, real *C, hipStream_t st);
+// FP32 C[R][N] = A[R][Kd] B[Kd][N] from B's transpose Bt[N][Kd] (k contiguous) on the matrix
+// cores; false (nothing queued) unless Bt is given, Kd is a multiple of 16 and N >= 16
+bool launch_gemm_dma(long R, int Kd, int N, const float *A, const float *Bt, float *C, hipStream_t st);
 bool launch_do2sh_f32(long R, int K, int NL, const float *A, const float *B, float *C, hipStream_t st, int rt = 0);
 size_t do2sh_lds(int NL);
 // mixed precision (FP16 matrix cores on hi + lo operand pairs, FP32 accumulation), NL <= 256:

@@ -3184,6 +3184,115 @@ __global__ void __launch_bounds__(1024) k_gemm_short_k(long R, int Kd, int N, co
     }
 }
 
+// FP32 C[R][N] = A[R][Kd] B[Kd][N] with B given transposed (Bt[N][Kd], k contiguous)
+// and Kd a multiple of 16 KS: a wave owns 16 rows and the NT column tiles of the
+// workgroup's block (grid.y); B moves from global memory straight into LDS
+// (global_load_lds, 16 bytes = four k of one column per lane) in double-buffered
+// chunks of 16 KS k, one 1 KB block per 16 k and column tile with column r at 64 r
+// bytes and its k 4 s .. 4 s + 3 in slot s ^ ((r >> 2) & 3), so that one 16-byte read
+// gives a lane the B values of four matrix-core steps.  One 16-row tile per wave
+// keeps the accumulators at 4 NT registers, and four waves fit a SIMD.  TR: the
+// tiles computed transposed (a lane holds four consecutive columns of one row; N a
+// multiple of 4).
+template <int NT, int W, int KS, bool TR>
+__global__ void __launch_bounds__(64 * W) k_gemm_dma(long R, int Kd, int N, const float *__restrict__ A,
+                                                   const float *__restrict__ Bt, float *__restrict__ C)
+{
+    constexpr int NC = 16 * NT, KC = 16 * KS, NBK = NT * KS, BPW = (NBK + W - 1) / W;
+    extern __shared__ unsigned char smem_raw[];
+    float *buf = reinterpret_cast<float *>(smem_raw);                // [2][KS][NT][256]
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, lr = lane & 15, lg = lane >> 4;
+    const long r0 = (long)xcd_item(gridDim.x) * (16 * W) + wave * 16;
+    const int c0 = blockIdx.y * NC;
+    const float *__restrict__ Arow = A + min(r0 + lr, R - 1) * (long)Kd + 4 * lg;
+    const int dc = lane >> 2, ds = (lane & 3) ^ ((dc >> 2) & 3);
+    auto dma = [&](int kc, int b) {
+#pragma unroll
+        for (int u = 0; u < BPW; ++u) {
+            const int blk = wave * BPW + u, sub = blk / NT, c = blk - sub * NT;
+            if (blk < NBK) {
+                const int col = min(c0 + 16 * c + dc, N - 1);
+                __builtin_amdgcn_global_load_lds((const void *)(Bt + (long)col * Kd + kc + 16 * sub + 4 * ds),
+                                                 (__attribute__((address_space(3))) void *)(buf + (b * NBK + blk) * 256),
+                                                 16, 0, 0);
+            }
+        }
+    };
+    const int ro = lr * 16 + 4 * (lg ^ ((lr >> 2) & 3));
+    f32x4 acc[NT];
+#pragma unroll
+    for (int c = 0; c < NT; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
+    const int nch = Kd / KC;
+    dma(0, 0);
+    f32x4 an[KS];
+#pragma unroll
+    for (int u = 0; u < KS; ++u) an[u] = *reinterpret_cast<const f32x4 *>(Arow + 16 * u);
+    for (int ci = 0; ci < nch; ++ci) {
+        f32x4 a[KS];
+#pragma unroll
+        for (int u = 0; u < KS; ++u) a[u] = an[u];
+        __builtin_amdgcn_s_waitcnt(0);                  // this wave's pieces of the chunk and its A values have landed
+        __syncthreads();                                // every wave's: the chunk is whole, the other buffer free
+        if (ci + 1 < nch) {
+            dma(KC * (ci + 1), (ci + 1) & 1);
+#pragma unroll
+            for (int u = 0; u < KS; ++u) an[u] = *reinterpret_cast<const f32x4 *>(Arow + KC * (ci + 1) + 16 * u);
+        }
+        const float *Tb = buf + (ci & 1) * NBK * 256;
+#pragma unroll
+        for (int u = 0; u < KS; ++u)
+#pragma unroll
+            for (int c = 0; c < NT; ++c) {
+                const f32x4 b = *reinterpret_cast<const f32x4 *>(Tb + (u * NT + c) * 256 + ro);
+#pragma unroll
+                for (int s2 = 0; s2 < 4; ++s2)
+                    acc[c] = TR ? __builtin_amdgcn_mfma_f32_16x16x4f32(b[s2], a[u][s2], acc[c], 0, 0, 0)
+                                : __builtin_amdgcn_mfma_f32_16x16x4f32(a[u][s2], b[s2], acc[c], 0, 0, 0);
+            }
+    }
+    if (TR) {
+        const long r = r0 + lr;
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+            const int col = c0 + 16 * c + 4 * lg;
+            if (r < R && col < N) *reinterpret_cast<f32x4 *>(C + r * N + col) = acc[c];
+        }
+        return;
+    }
+#pragma unroll
+    for (int c = 0; c < NT; ++c) {
+        const int col = c0 + 16 * c + lr;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const long r = r0 + 4 * lg + i;
+            if (r < R && col < N) C[r * N + col] = acc[c][i];
+        }
+    }
+}
+bool launch_gemm_dma(long R, int Kd, int N, const float *A, const float *Bt, float *C, hipStream_t st)
+{
+    if (!Bt || Kd % 16 || N < 16) return false;
+    constexpr int NT = 16;
+    const unsigned nby = (unsigned)((N + 16 * NT - 1) / (16 * NT));
+    const size_t sm = 2 * sizeof(float) * NT * 256;
+    // (measured on MI355X at 2^23 rows: transposed tiles, 512 columns of 256 k, fastest with
+    // eight waves; 256 columns of 512 k with sixteen, each chunk of B then serving 256 rows)
+    if (N % 4 == 0 && N > Kd) {
+        constexpr int W = 8;
+        const long nb = (R + 16 * W - 1) / (16 * W);
+        if (nb > 0x7fffffffL) return false;
+        hipLaunchKernelGGL((k_gemm_dma<NT, W, 1, true>), dim3((unsigned)(8 * ((nb + 7) / 8)), nby), dim3(64 * W), sm,
+                           st, R, Kd, N, A, Bt, C);
+    } else {
+        constexpr int W = 16;
+        const long nb = (R + 16 * W - 1) / (16 * W);
+        if (nb > 0x7fffffffL) return false;
+        hipLaunchKernelGGL((k_gemm_dma<NT, W, 1, false>), dim3((unsigned)(8 * ((nb + 7) / 8)), nby), dim3(64 * W), sm,
+                           st, R, Kd, N, A, Bt, C);
+    }
+    return true;
+}
+
 template <typename real>
 void launch_gemm(long R, int Kd, int N, const real *A, const real *B, real *C, hipStream_t st)
 {
@@ -3731,6 +3840,7 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_sh2do_f16<4>),
                          reinterpret_cast<const void *>(&k_sh2do_f16_dma<8, 8>),
                          reinterpret_cast<const void *>(&k_do2sh_f16_dma<16, 8>),
+
                          reinterpret_cast<const void *>(&k_source_compton_mfma<false, false>),
                          reinterpret_cast<const void *>(&k_source_compton_mfma<true, false>),
                          reinterpret_cast<const void *>(&k_source_compton_mfma<false, true>),
