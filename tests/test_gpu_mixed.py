@@ -42,7 +42,8 @@ def moment_errors(got, ref):
 
 
 @pytest.mark.parametrize("case", ["thomson_log", "high_gamma_L7", "grey_extinction_8g", "compton_log_keV",
-                                  "lmax0_min_z", "compton_L15", "thomson_L4", "thomson_L8", "compton_L11"])
+                                  "lmax0_min_z", "compton_L15", "thomson_L4", "thomson_L8", "compton_L11",
+                                  "thomson_L11_312_ordinates"])
 def test_mixed_sweep_against_oracle(case):
     spec = custom_spec(**CASES[case])
     o = oracle.Oracle(spec)

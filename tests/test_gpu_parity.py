@@ -98,6 +98,8 @@ CASES = {
     "thomson_L8": dict(nx=4, ny=3, nz=3, G=2, lmax=8, nmu=10, nphi=18, seed=15),
     "compton_L11": dict(nx=3, ny=3, nz=3, G=4, lmax=11, nmu=12, nphi=24, scatter="compton", seed=16,
                         edges=np.exp(np.linspace(np.log(1.0), np.log(150.0), 5)), mec2=W.MEC2_KEV),
+    # 312 ordinates (not a multiple of 32: a partial last table chunk in the products)
+    "thomson_L11_312_ordinates": dict(nx=3, ny=3, nz=3, G=3, lmax=11, nmu=12, nphi=26, seed=17),
     # L = 15 (256 SH terms, 16 x 32 ordinates): the widest SH products and Compton source
     "compton_L15": dict(nx=4, ny=4, nz=3, G=4, lmax=15, nmu=16, nphi=32, scatter="compton", seed=9,
                         edges=np.exp(np.linspace(np.log(1.0), np.log(150.0), 5)), mec2=W.MEC2_KEV),
