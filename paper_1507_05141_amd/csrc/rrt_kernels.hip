@@ -343,6 +343,25 @@ template <typename real, int N>
 struct alignas(sizeof(real) * N) Pack {
     real v[N];
 };
+// a store that does not keep its lines in the caches, for lab-frame arrays that the
+// next step reads back only after far more data than the caches hold (measured at
+// 64^3: the boost's S~ 13.6 -> 13.3 ms, the transpose back to point-major planes 7.0
+// -> 6.2 ms, the inverse transform 8.65 -> 8.5 ms; the SH -> ordinate product and
+// the ray trace gain nothing or lose)
+template <typename real, int N>
+__device__ __forceinline__ void store_stream(real *dst, const Pack<real, N> &w)
+{
+    if constexpr (N == 1) {
+        __builtin_nontemporal_store(w.v[0], dst);
+    } else {
+        typedef real vN __attribute__((ext_vector_type(N)));
+        vN x;
+#pragma unroll
+        for (int i = 0; i < N; ++i) x[i] = w.v[i];
+        __builtin_nontemporal_store(x, reinterpret_cast<vN *>(dst));
+    }
+}
+
 
 template <typename real, int GC, int MAXPT>
 struct PlaneRegs {
@@ -1316,7 +1335,7 @@ __global__ void __launch_bounds__(kRemapThreads, 4) k_boost(BoostArgs<real> a)
                 if (W == 4) {
                     P4 v;
                     v.v[0] = out[0]; v.v[1] = out[1]; v.v[2] = out[2]; v.v[3] = out[3];
-                    *reinterpret_cast<P4 *>(a.St + o) = v;
+                    store_stream(a.St + o, v);
                 } else {
                     a.St[o] = out[0];
                 }
@@ -1426,7 +1445,7 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_un
                 real acur = A(sh);
                 for (int g = 0; g < G; ++g) {
                     const real anext = A(g + sh + 1);
-                    out[g * K + j] = e.u * acur + e.v * anext;
+                    __builtin_nontemporal_store(e.u * acur + e.v * anext, out + g * K + j);
                     acur = anext;
                 }
             }
@@ -2949,6 +2968,7 @@ __global__ void __launch_bounds__(256) k_transpose_lab(const real *__restrict__ 
         __syncthreads();
     }
 }
+
 // the same with 16-byte loads and stores (G and P multiples of 4): a tile of 128
 // points x up to 32 groups, every lane's loads in flight before the LDS writes
 template <typename real>
@@ -3007,7 +3027,7 @@ __global__ void __launch_bounds__(256) k_transpose_lab4(const real *__restrict__
                     const int pp = f / gn4, g4 = f - pp * gn4;
 #pragma unroll
                     for (int i = 0; i < 4; ++i) w.v[i] = tile[pp * TS + 4 * g4 + i];
-                    *reinterpret_cast<P4 *>(out + (k * P + p0 + pp) * G + g0 + 4 * g4) = w;
+                    store_stream(out + (k * P + p0 + pp) * G + g0 + 4 * g4, w);
                 }
             }
         }
