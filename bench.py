@@ -135,7 +135,7 @@ def serving_bench(args):
     # shape autotunes its kernel variants and builds its Compton tables (both kept for the
     # process), which would otherwise land in whichever timed pass meets the shape first
     for prec in (B.FP32, B.MIXED):
-        SV.serve(burst, precision=prec, budget_bytes=budget, max_iter=max_iter)
+        SV.serve(burst, precision=prec, budget_bytes=budget, max_iter=max_iter, release_pool=False)
     cap = {}
     runs = (("fp32_eager", B.FP32, False), ("fp32", B.FP32, True), ("mixed", B.MIXED, True))
     if args.mix == "full":
@@ -146,17 +146,19 @@ def serving_bench(args):
 
     for name, prec, graphs in runs:
         recs, wall = SV.serve(burst, precision=prec, budget_bytes=budget, graphs=graphs, progress=progress,
-                              max_iter=max_iter)
+                              max_iter=max_iter, release_pool=False)
         cap[name] = SV.summary(recs, wall)
         print(f"capacity {name}: {cap[name]['solves_per_s']:.2f} solves/s", file=sys.stderr, flush=True)
     rate = 0.8 * cap["fp32"]["solves_per_s"]
     stream = SV.poisson_requests(args.requests, rate=rate, seed=5, **mix)
     res = {}
     for name, prec in (("fp32", B.FP32), ("mixed", B.MIXED)):
-        recs, wall = SV.serve(stream, precision=prec, budget_bytes=budget, progress=progress, max_iter=max_iter)
+        recs, wall = SV.serve(stream, precision=prec, budget_bytes=budget, progress=progress, max_iter=max_iter,
+                              release_pool=False)
         res[name] = SV.summary(recs, wall)
         print(f"stream {name}: p50 {res[name]['p50_ms']:.1f} ms p99 {res[name]['p99_ms']:.1f} ms", file=sys.stderr,
               flush=True)
+    B.set_device_pool(0)
     return {"metric": "solves/s (continuous batching, all requests at once)", "value": cap["mixed"]["solves_per_s"],
             "unit": "solves/s", "n_gpus": 1, "higher_is_better": True, "vs_baseline": None,
             "dtype": "f32+f16mfma", "data": "synthetic",

@@ -338,6 +338,19 @@ const char *rrt_last_error(void);
    time-stepping arrays are first needed). */
 size_t rrt_device_bytes(const rrt_problem *pr);
 
+/* Keep up to max_bytes of the device memory that rrt_destroy frees, for reuse
+   by later problems that allocate blocks of the same sizes (exact sizes, per
+   device; the oldest blocks are freed first beyond the limit).  For serving
+   many problems: freeing device memory synchronises the whole device, so
+   every retirement would otherwise stall the other problems' streams.  0, the
+   default, frees at once; lowering the limit frees the excess now (and 0
+   everything held).  A block enters the pool only after its problem's
+   stream is idle.  When an allocation fails the pool is emptied and the
+   allocation tried again.  Process-wide and thread-safe; memory held in the
+   pool is in no problem's rrt_device_bytes.  *held (may be NULL) receives the
+   bytes held after the call. */
+rrt_status rrt_set_device_pool(size_t max_bytes, size_t *held);
+
 /* ---------------------------------------------------------------------------
    Batches: steady-state solves of independent problems sharing the GPU.
    Each admitted problem runs the Lambda iteration with Ng acceleration of

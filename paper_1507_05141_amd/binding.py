@@ -120,6 +120,8 @@ def lib():
         L.rrt_footprint_bytes.restype = ctypes.c_size_t
         L.rrt_device_bytes.argtypes = [P]
         L.rrt_device_bytes.restype = ctypes.c_size_t
+        L.rrt_set_device_pool.argtypes = [ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+        L.rrt_set_device_pool.restype = I
         L.rrt_batch_destroy.argtypes = [P]
         L.rrt_batch_destroy.restype = None
         _lib = L
@@ -147,6 +149,15 @@ def _structs(spec):
     groups = Groups(G, e_ptr, int(spec.get("log_centres", True)), float(spec.get("mec2", 510.99895)))
     angles = Angles(spec["lmax"], spec["nmu"], spec["nphi"])
     return grid, groups, angles, e_arr
+
+
+def set_device_pool(max_bytes):
+    """Keep up to max_bytes of the device memory destroyed problems free, for reuse
+    by later problems of the same sizes (rrt_set_device_pool); 0 frees it all.
+    Returns the bytes held."""
+    held = ctypes.c_size_t(0)
+    _check(lib().rrt_set_device_pool(int(max_bytes), ctypes.byref(held)))
+    return held.value
 
 
 def compton_tables(edges, mec2, lmax, kT, log_centres=True, stream=None):

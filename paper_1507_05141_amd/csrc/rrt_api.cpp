@@ -159,20 +159,111 @@ namespace {
 size_t sh_elems(const rrt_problem *p) { return (size_t)p->P * p->G * p->NL; }
 size_t do_elems(const rrt_problem *p) { return (size_t)p->P * p->G * p->K; }
 
+// Process-wide pool of device blocks that destroyed problems freed (rrt_set_device_pool):
+// blocks wait, per (device, size), for a later allocation of the same size.
+struct DevPool {
+    std::mutex mu;
+    size_t max_bytes = 0, held = 0;
+    std::map<std::pair<int, size_t>, std::vector<void *>> free;   // (device, bytes) -> blocks
+    std::vector<std::tuple<int, size_t, void *>> order;            // pooled blocks, oldest first
+    std::map<void *, std::pair<int, size_t>> sizes;                // every block dev_alloc made
+};
+DevPool &dev_pool()
+{
+    static DevPool p;
+    return p;
+}
+// take the pooled blocks beyond `keep` bytes (oldest first) out of the pool; the caller frees them
+std::vector<void *> pool_take_excess(DevPool &dp, size_t keep)
+{
+    std::vector<void *> out;
+    size_t i = 0;
+    for (; i < dp.order.size() && dp.held > keep; ++i) {
+        const auto &t = dp.order[i];
+        auto &v = dp.free[{std::get<0>(t), std::get<1>(t)}];
+        auto it = std::find(v.begin(), v.end(), std::get<2>(t));
+        if (it == v.end()) continue;                // already reused
+        v.erase(it);
+        dp.held -= std::get<1>(t);
+        dp.sizes.erase(std::get<2>(t));
+        out.push_back(std::get<2>(t));
+    }
+    dp.order.erase(dp.order.begin(), dp.order.begin() + i);
+    return out;
+}
+
 rrt_status dev_alloc(void **ptr, size_t bytes)
 {
     if (*ptr) return RRT_OK;
-    hipError_t e = hipMalloc(ptr, bytes ? bytes : 1);
+    bytes = bytes ? bytes : 1;
+    int dev = 0;
+    (void)hipGetDevice(&dev);
+    DevPool &dp = dev_pool();
+    {
+        std::lock_guard<std::mutex> lk(dp.mu);
+        auto it = dp.free.find({dev, bytes});
+        if (it != dp.free.end() && !it->second.empty()) {
+            *ptr = it->second.back();
+            it->second.pop_back();
+            dp.held -= bytes;
+            return RRT_OK;
+        }
+    }
+    hipError_t e = hipMalloc(ptr, bytes);
+    if (e == hipErrorOutOfMemory || e == hipErrorMemoryAllocation) {
+        // the pool may hold what this allocation needs: empty it and try once more
+        (void)hipGetLastError();
+        std::vector<void *> out;
+        {
+            std::lock_guard<std::mutex> lk(dp.mu);
+            out = pool_take_excess(dp, 0);
+        }
+        for (void *b : out) (void)hipFree(b);
+        if (!out.empty()) e = hipMalloc(ptr, bytes);
+    }
     if (e != hipSuccess) {
         *ptr = nullptr;
         return fail(RRT_E_HBM, std::string("hipMalloc of ") + std::to_string(bytes) + " bytes: " + hipGetErrorString(e));
     }
+    std::lock_guard<std::mutex> lk(dp.mu);
+    dp.sizes[*ptr] = {dev, bytes};
     return RRT_OK;
+}
+
+// a block whose users have all finished (its problem's stream is idle): into the pool
+// while it has room, else freed
+void dev_release(void *p)
+{
+    if (!p) return;
+    DevPool &dp = dev_pool();
+    std::vector<void *> out;
+    {
+        std::lock_guard<std::mutex> lk(dp.mu);
+        auto it = dp.sizes.find(p);
+        if (it != dp.sizes.end() && dp.max_bytes > 0 && it->second.second <= dp.max_bytes) {
+            dp.free[it->second].push_back(p);
+            dp.order.emplace_back(it->second.first, it->second.second, p);
+            dp.held += it->second.second;
+            out = pool_take_excess(dp, dp.max_bytes);
+            p = nullptr;
+        } else if (it != dp.sizes.end()) {
+            dp.sizes.erase(it);
+        }
+    }
+    if (p) (void)hipFree(p);
+    for (void *b : out) (void)hipFree(b);
 }
 
 void dev_free(void *&p)
 {
-    if (p) (void)hipFree(p);
+    if (p) {
+        {
+            DevPool &dp = dev_pool();
+            std::lock_guard<std::mutex> lk(dp.mu);
+            dp.sizes.erase(p);
+        }
+        (void)hipFree(p);
+    }
     p = nullptr;
 }
 
@@ -1043,8 +1134,7 @@ void rrt_destroy(rrt_problem *pr)
                     pr->d_A, pr->d_sg, pr->d_tnode, pr->d_twt, pr->d_torder, pr->d_kappa, pr->d_sigma, pr->d_bnu, pr->d_beta, pr->d_gam, pr->d_chi0, pr->d_chilab, pr->d_plan, pr->d_chilabT, pr->d_bc[0], pr->d_bc[1],
                     pr->d_S, pr->d_Snew, pr->d_Ilm, pr->d_co, pr->d_St, pr->d_Xt, pr->d_Ilab, pr->d_I, pr->d_Iin,
                     pr->d_acc, pr->d_chain[0], pr->d_chain[1], pr->d_chain[2], pr->d_chain[3], pr->d_partial, pr->d_red, pr->d_count, pr->d_vet, pr->d_mom, pr->d_dnu};
-    for (void *b : bufs)
-        if (b) (void)hipFree(b);
+    for (void *b : bufs) dev_release(b);          // the stream is idle (synchronised above)
     for (int i = 0; i < KI_N; ++i)
         for (auto &e : pr->pending[i]) {
             (void)hipEventDestroy(e.first);
@@ -2096,6 +2186,20 @@ void batch_finish(rrt_problem *pr)
 }  // namespace
 
 extern "C" {
+
+rrt_status rrt_set_device_pool(size_t max_bytes, size_t *held)
+{
+    DevPool &dp = dev_pool();
+    std::vector<void *> out;
+    {
+        std::lock_guard<std::mutex> lk(dp.mu);
+        dp.max_bytes = max_bytes;
+        out = pool_take_excess(dp, max_bytes);
+        if (held) *held = dp.held;
+    }
+    for (void *b : out) (void)hipFree(b);
+    return RRT_OK;
+}
 
 size_t rrt_device_bytes(const rrt_problem *pr) { return pr ? pr->dev_bytes : 0; }
 

@@ -63,7 +63,7 @@ def poisson_requests(count, rate, seed, **mix):
 
 
 def serve(requests, precision=B.FP32, budget_bytes=64 << 30, tol=1e-6, max_iter=300, use_ng=True, keep=None,
-          graphs=True, progress=None, autotune=False):
+          graphs=True, progress=None, autotune=False, pool_bytes=None, release_pool=True):
     """Run the request stream; returns per-request records and the run's wall time.
 
     keep(i, problem) -> dict, if given, is called on each finished problem
@@ -72,7 +72,15 @@ def serve(requests, precision=B.FP32, budget_bytes=64 << 30, tol=1e-6, max_iter=
     if given, is called whenever a request finishes or is rejected.  Requests
     run the library's default kernel variants unless autotune is set (timing
     candidates inside a request would add to its latency and, with other
-    requests sharing the GPU, measure contention as much as the kernels)."""
+    requests sharing the GPU, measure contention as much as the kernels).
+
+    Device memory that retired requests free is kept for the next requests of
+    the same sizes (rrt_set_device_pool, up to pool_bytes, default a quarter of the budget):
+    freeing device memory would synchronise the device and stall the running
+    requests at every retirement; release_pool empties the pool on return."""
+    # a quarter of the budget by default: the pool's blocks are not in the budget, so a pool as
+    # large as a near-full budget would leave allocations to fail and empty it
+    B.set_device_pool(budget_bytes // 4 if pool_bytes is None else pool_bytes)
     batch = B.Batch(budget_bytes)
     pending = list(range(len(requests)))           # not yet admitted, in arrival order
     running = {}                                    # request -> Problem
@@ -139,6 +147,8 @@ def serve(requests, precision=B.FP32, budget_bytes=64 << 30, tol=1e-6, max_iter=
         for pr in running.values():
             pr.close()
         batch.close()
+        if release_pool:
+            B.set_device_pool(0)
     return recs, now()
 
 

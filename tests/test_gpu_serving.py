@@ -51,6 +51,38 @@ def test_batch_results_equal_alone(prec):
     batch.close()
 
 
+@pytest.mark.parametrize("prec", [B.FP32, B.MIXED], ids=["fp32", "mixed"])
+def test_device_pool_reuses_freed_blocks(prec):
+    """rrt_set_device_pool: a destroyed problem's blocks wait in the pool, the next
+    problem of the same shape takes them, its solve equals a solve in fresh
+    memory bit for bit, and a limit of 0 frees everything held."""
+    sp = _uneven_specs()[2]
+    assert B.set_device_pool(0) == 0
+    g = B.Problem.from_spec(sp, precision=prec)
+    ref = g.solve(tol=1e-6, max_iter=300, use_ng=True)
+    ref_m = g.moments(B.FRAME_LAB)
+    g.close()
+    try:
+        B.set_device_pool(1 << 30)
+        g = B.Problem.from_spec(sp, precision=prec)
+        g.solve(tol=1e-6, max_iter=300, use_ng=True)
+        size = g.device_bytes()
+        g.close()
+        held = B.set_device_pool(1 << 30)
+        print(f"pool holds {held} bytes after one problem of {size}", flush=True)
+        assert held > 0
+        g = B.Problem.from_spec(sp, precision=prec)
+        assert B.set_device_pool(1 << 30) < held            # its blocks came from the pool
+        info = g.solve(tol=1e-6, max_iter=300, use_ng=True)
+        assert info["iters"] == ref["iters"]
+        for a, b in zip(ref_m, g.moments(B.FRAME_LAB)):
+            assert np.array_equal(a, b)
+        g.close()
+        assert B.set_device_pool(1000) <= 1000              # lowering the limit frees the excess
+    finally:
+        assert B.set_device_pool(0) == 0
+
+
 def test_batch_admission_respects_budget():
     sp = W.thomson_jet(n=8, ng=4, lmax=3, nmu=4, nphi=8, seed=2)
     a = B.Problem.from_spec(sp)
