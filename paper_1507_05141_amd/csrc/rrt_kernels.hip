@@ -1828,13 +1828,13 @@ __global__ void __launch_bounds__(1024) k_do2sh_f32r(long R, int K, int NL, cons
 // ---------------------------------------------------------------------------
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
-// power of two s taking m > 0 into [2^14, 2^15) (FP16 keeps full precision
-// down to 2^-28 m); m = 0 or tiny gives a bounded scale
-__device__ __forceinline__ void fp16_scale(float m, float &s, float &inv)
+// power of two s taking m > 0 into [2^top, 2^(top + 1)) (at top = 14 FP16 keeps
+// full precision down to 2^-28 m); m = 0 or tiny gives a bounded scale
+__device__ __forceinline__ void fp16_scale(float m, float &s, float &inv, int top = 14)
 {
     const int e = max(((__float_as_int(m) >> 23) & 0xff) - 127, -100);
-    s = ldexpf(1.0f, 14 - e);
-    inv = ldexpf(1.0f, e - 14);
+    s = ldexpf(1.0f, top - e);
+    inv = ldexpf(1.0f, e - top);
 }
 
 // hi + lo FP16 pair of v * s
@@ -1956,7 +1956,12 @@ __global__ void __launch_bounds__(64 * W) k_do2sh_f16(long R, int K, int Kp, int
 // tile c): row r of a block (column 16 c + r of the output) at 64 r bytes, its
 // ordinates 8 s .. 8 s + 7 in 16-byte slot s ^ ((r >> 2) & 3), so that the 16
 // rows a lane group reads fall on distinct banks.  Kp a multiple of 32; the
-// tables hold 16 NT rows.
+// tables hold 16 NT rows.  Each row keeps one power-of-two scale that puts its
+// largest value so far near 2^8 (FP16 holds up to 65504): a chunk that would pass
+// 2^15 under it rescales the row and its sums first, so the products accumulate
+// in the matrix-core accumulators and the scale is taken out once at the end.
+// What FP16's subnormal floor (2^-24) then drops is below 2^-32 of the row's
+// largest value.
 template <int NT, int W>
 __global__ void __launch_bounds__(64 * W) k_do2sh_f16_dma(long R, int K, int Kp, int NL, const float *__restrict__ A,
                                                        const _Float16 *__restrict__ WYh,
@@ -2003,6 +2008,7 @@ __global__ void __launch_bounds__(64 * W) k_do2sh_f16_dma(long R, int K, int Kp,
 #pragma unroll
     for (int c = 0; c < NT; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
     const int nch = Kp / 32;
+    float srow = 0.f, irow = 0.f;                       // the row's scale (0 while its values are all 0)
     dma(0, 0);
     load_rows(0);
     for (int ci = 0; ci < nch; ++ci) {
@@ -2019,29 +2025,43 @@ __global__ void __launch_bounds__(64 * W) k_do2sh_f16_dma(long R, int K, int Kp,
         float m = 0.f;
 #pragma unroll
         for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(v[i]));
-        float sc, inv;
-        fp16_scale(quad_max(m), sc, inv);
-        f16x8 ah, al;
-        split_f16x8(v, sc, ah, al);
-        // inverse scales of the output rows 4 lg + i of this tile
-        float ri[4];
+        m = quad_max(m);
+        const bool grow = m * srow >= 32768.f || (srow == 0.f && m > 0.f);
+        if (__ballot(grow) != 0) {                      // wave-uniform: some row of this tile takes a new scale
+            float f = 1.f;
+            if (grow) {
+                float sn, in;
+                fp16_scale(m, sn, in, 8);
+                if (srow != 0.f) f = sn * irow;         // a power of two: the sums rescale exactly
+                srow = sn;
+                irow = in;
+            }
+            float fr[4];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) ri[i] = __shfl(inv, 4 * lg + i, 64);
+            for (int i = 0; i < 4; ++i) fr[i] = __shfl(f, 4 * lg + i, 64);
 #pragma unroll
-        for (int c = 0; c < NT; ++c) {
-            const f32x4 p = mfma3(ah, al, *reinterpret_cast<const f16x8 *>(Tb + c * 512 + ro),
-                                  *reinterpret_cast<const f16x8 *>(Tb + (NT + c) * 512 + ro), f32x4{0.f, 0.f, 0.f, 0.f});
+            for (int c = 0; c < NT; ++c)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) acc[c][i] += p[i] * ri[i];
+                for (int i = 0; i < 4; ++i) acc[c][i] *= fr[i];
         }
+        f16x8 ah, al;
+        split_f16x8(v, srow, ah, al);
+#pragma unroll
+        for (int c = 0; c < NT; ++c)
+            acc[c] = mfma3(ah, al, *reinterpret_cast<const f16x8 *>(Tb + c * 512 + ro),
+                           *reinterpret_cast<const f16x8 *>(Tb + (NT + c) * 512 + ro), acc[c]);
     }
+    // inverse scales of the output rows 4 lg + i of this tile
+    float ri[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ri[i] = __shfl(irow, 4 * lg + i, 64);
 #pragma unroll
     for (int c = 0; c < NT; ++c) {
         const int col = 16 * c + lr;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const long r = r0 + 4 * lg + i;
-            if (r < R && col < NL) C[r * NL + col] = acc[c][i];
+            if (r < R && col < NL) C[r * NL + col] = acc[c][i] * ri[i];
         }
     }
 }
