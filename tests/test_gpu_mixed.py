@@ -92,3 +92,47 @@ def test_mixed_converged_moments(name):
     for frame, e in (("lab", lab), ("comoving", co)):
         for k in ("J", "H", "K", "f"):
             assert e[k] <= TARGET, f"{name} {frame} {k}: {e[k]:.3e}"
+
+
+@pytest.mark.parametrize("emit", [True, False], ids=["faint_emission", "no_emission"])
+def test_mixed_fold_of_rows_spanning_many_decades(emit):
+    """The mixed ordinate -> SH product (L = 15, 16 x 32 ordinates) keeps one
+    power-of-two scale per (point, group) row, set by the first block of 32
+    ordinates with a nonzero value and lowered when a later block outgrows it.
+    A beam exp(25 mu) entering through the bottom face of a nearly transparent
+    medium at rest makes every row grow by more than nine decades from the
+    downward to the upward rings (the ordinate order, one ring per block);
+    without emission the downward rings are exactly zero, so the scale starts
+    late.  The library's SH intensity is compared row by row with the FP64
+    oracle's fold (Eq. 9 projection; the identity frame change at rest) of the
+    library's own lab intensity, to 1e-4 of the row's largest coefficient."""
+    n, ng, K = 6, 2, 512
+    spec = W.random_medium(n=n, ng=ng, lmax=15, nmu=16, nphi=32, seed=5)
+    P = n ** 3
+    spec["beta"] = np.zeros((P, 3))
+    spec["kappa"] = np.full((P, ng), 1e-3)
+    spec["sigma"] = np.full(P, 1e-3)
+    spec["bnu"] = np.full((P, ng), 1e-6 if emit else 0.0)
+    o = oracle.Oracle(spec)
+    mu = np.repeat(o.mu, spec["nphi"])
+    beam = np.where(mu > 0, np.exp(25.0 * mu), 0.0)
+    spec["bc_bot"] = np.broadcast_to(beam[:, None, None, None] * np.array([1.0, 1e-3]), (K, n, n, ng)).copy()
+    spec["bc_top"] = np.zeros((K, n, n, ng))
+    print(f"fold of rows spanning many decades, emission {emit}", flush=True)
+    g = B.Problem.from_spec(spec, precision=B.MIXED)
+    g.set_source_sh(oracle.Oracle(spec).initial_source())
+    g.sweep()
+    I_lab = g.sweep_intensity()
+    got = g.intensity_sh()
+    g.close()
+    # the input has the structure the test is about
+    blocks = np.abs(np.moveaxis(I_lab, 0, -1).reshape(-1, 16, 32)).max(axis=2)
+    first = np.array([b[b > 0][0] for b in blocks])
+    assert np.all(blocks.max(axis=1) > 1e9 * first)
+    if not emit:
+        assert np.all(blocks[:, :8] == 0.0)
+    ref = oracle.Oracle(spec).fold(I_lab)
+    r = ref.reshape(-1, ref.shape[-1])
+    e = np.abs(got.reshape(r.shape) - r).max(axis=1) / np.abs(r).max(axis=1)
+    print(f"worst row error {e.max():.2e} of the row's largest coefficient", flush=True)
+    assert e.max() <= 1e-4
