@@ -1733,8 +1733,11 @@ __global__ void __launch_bounds__(64 * W) k_do2sh_f32(long R, int K, int NL, con
 // per workgroup, K rounded up to 64 rows of NLP floats): persistent workgroups
 // of sixteen waves walk blocks of 16 x 16 RT rows with no barrier inside, each
 // wave loading the next 64-ordinate chunk of its rows while the matrix cores
-// take the current one.
-template <int NT, int RT>
+// take the current one.  FULL (K a multiple of 64): every chunk is whole, the
+// loads take no branches, the last chunk of a block loads the first chunk of the
+// wave's next block, and the block's stores go out after the one wait for it (so
+// no load waits for them).
+template <int NT, int RT, bool FULL>
 __global__ void __launch_bounds__(1024) k_do2sh_f32r(long R, int K, int NL, const float *__restrict__ A,
                                                      const float *__restrict__ B, float *__restrict__ C)
 {
@@ -1750,6 +1753,77 @@ __global__ void __launch_bounds__(1024) k_do2sh_f32r(long R, int K, int NL, cons
     __syncthreads();
     const bool vec = (K & 3) == 0;
     const long nblk = (R + 16 * W * RT - 1) / (16 * W * RT);
+    if constexpr (FULL) {
+        auto rows_of = [&](long blk, const float *(&Ar)[RT]) {
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+                Ar[t] = A + min(blk * (16 * W * RT) + wave * (16 * RT) + 16 * t + lr, R - 1) * (long)K;
+        };
+        auto load = [&](f32x4 (&dst)[RT][4], const float *const (&Ar)[RT]) {
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) dst[rt][t] = *reinterpret_cast<const f32x4 *>(Ar[rt] + 16 * t + 4 * lg);
+        };
+        long blk = blockIdx.x;
+        if (blk >= nblk) return;
+        const float *Arow[RT], *Anext[RT], *src[RT];
+        rows_of(blk, Arow);
+        f32x4 a[RT][4], an[RT][4];
+        load(a, Arow);
+        __builtin_amdgcn_s_waitcnt(0xF70);              // vmcnt(0): the loop starts with no load in flight
+        for (; blk < nblk; blk += gridDim.x) {
+            // the wave's next block (past its last: the last again, loaded and not used)
+            rows_of(min(blk + (long)gridDim.x, nblk - 1), Anext);
+            f32x4 acc[RT][NT];
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+#pragma unroll
+                for (int c = 0; c < NT; ++c) acc[t][c] = f32x4{0.f, 0.f, 0.f, 0.f};
+            for (int kc = 0; kc < K; kc += KC) {
+                const bool last = kc + KC >= K;
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt) src[rt] = last ? Anext[rt] : Arow[rt] + kc + KC;
+                load(an, src);
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+#pragma unroll
+                    for (int s = 0; s < 4; ++s) {
+                        const float *brow = Bs + (kc + 16 * t + 4 * lg + s) * NLP + lr;
+#pragma unroll
+                        for (int c = 0; c < NT; ++c) {
+                            const float bv = brow[16 * c];
+#pragma unroll
+                            for (int rt = 0; rt < RT; ++rt)
+                                acc[rt][c] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[rt][t][s], bv, acc[rt][c], 0, 0, 0);
+                        }
+                    }
+                }
+                if (last) __builtin_amdgcn_s_waitcnt(0xF70);   // vmcnt(0): the next block's rows, not its stores
+#pragma unroll
+                for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) a[rt][t] = an[rt][t];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            const long r0 = blk * (16 * W * RT) + wave * (16 * RT);
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt)
+#pragma unroll
+                for (int c = 0; c < NT; ++c) {
+                    const int col = 16 * c + lr;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const long r = r0 + 16 * rt + 4 * lg + i;
+                        if (r < R && col < NL) C[r * NL + col] = acc[rt][c][i];
+                    }
+                }
+#pragma unroll
+            for (int rt = 0; rt < RT; ++rt) Arow[rt] = Anext[rt];
+        }
+        return;
+    }
     for (long blk = blockIdx.x; blk < nblk; blk += gridDim.x) {
         const long r0 = blk * (16 * W * RT) + wave * (16 * RT);
         const float *Arow[RT];
@@ -3177,8 +3251,9 @@ size_t do2sh_lds(int NL) { return sizeof(float) * 64 * (size_t)(((NL + 15) / 16)
 // and 16 NT columns of group w % CQ (CQ = N / 16 NT); each 16 x 16 tile is
 // computed transposed (operands swapped) so that a lane holds four
 // consecutive columns of one row and stores them as one 16-byte vector; the
-// next block's A rows are loaded during the current products.
-template <int NT>
+// next block's A rows are loaded during the current products.  KT > 0: Kd = 16 KT,
+// so every row piece is a whole 16-byte vector and the loads take no branches.
+template <int NT, int KT>
 __global__ void __launch_bounds__(1024) k_gemm_short_k(long R, int Kd, int N, const float *__restrict__ A,
                                                        const float *__restrict__ B, float *__restrict__ C)
 {
@@ -3194,16 +3269,17 @@ __global__ void __launch_bounds__(1024) k_gemm_short_k(long R, int Kd, int N, co
     __syncthreads();
     const int CQ = N / NC, RW = 16 / CQ, rq = wave / CQ, cq = wave - rq * CQ;
     const long nblk = (R + 16 * RW - 1) / (16 * RW);
-    const bool vec = (Kd & 3) == 0;
-    f32x4 a[4], an[4];
-    auto load = [&](f32x4 (&dst)[4], long blk) {
+    constexpr int TT = KT > 0 ? KT : 4;                 // 16-wide k tiles
+    f32x4 a[TT], an[TT];
+    auto load = [&](f32x4 (&dst)[TT], long blk) {
         const float *Ar = A + min(blk * (16 * RW) + rq * 16 + lr, R - 1) * (long)Kd;
+        if constexpr (KT > 0) {
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            const int k = 16 * t + 4 * lg;
-            if (vec && k + 3 < Kd) {
-                dst[t] = *reinterpret_cast<const f32x4 *>(Ar + k);
-            } else {
+            for (int t = 0; t < TT; ++t) dst[t] = *reinterpret_cast<const f32x4 *>(Ar + 16 * t + 4 * lg);
+        } else {
+#pragma unroll
+            for (int t = 0; t < TT; ++t) {
+                const int k = 16 * t + 4 * lg;
 #pragma unroll
                 for (int i = 0; i < 4; ++i) dst[t][i] = (k + i < Kd) ? Ar[k + i] : 0.f;
             }
@@ -3211,14 +3287,17 @@ __global__ void __launch_bounds__(1024) k_gemm_short_k(long R, int Kd, int N, co
     };
     long blk = blockIdx.x;
     if (blk < nblk) load(a, blk);
+    __builtin_amdgcn_s_waitcnt(0xF70);                  // vmcnt(0): the loop starts with no load in flight
     for (; blk < nblk; blk += gridDim.x) {
-        if (blk + gridDim.x < nblk) load(an, blk + gridDim.x);
+        // the next block's rows (past the last block: the last block again, not used)
+        load(an, min(blk + (long)gridDim.x, nblk - 1));
+        __builtin_amdgcn_sched_barrier(0);
         f32x4 acc[NT];
 #pragma unroll
         for (int c = 0; c < NT; ++c) acc[c] = f32x4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int t = 0; t < 4; ++t) {
-            if (16 * t >= Kd) break;
+        for (int t = 0; t < TT; ++t) {
+            if (KT == 0 && 16 * t >= Kd) break;
 #pragma unroll
             for (int s = 0; s < 4; ++s) {
                 const float *brow = Bs + (16 * t + 4 * lg + s) * NP + cq * NC + lr;
@@ -3226,14 +3305,19 @@ __global__ void __launch_bounds__(1024) k_gemm_short_k(long R, int Kd, int N, co
                 for (int c = 0; c < NT; ++c) acc[c] = __builtin_amdgcn_mfma_f32_16x16x4f32(brow[16 * c], a[t][s], acc[c], 0, 0, 0);
             }
         }
+        // take the next block's rows before this block's stores go out: the wait covers
+        // those rows and the stores of the block before, both issued a block of products
+        // earlier, and none of this block's stores
+        __builtin_amdgcn_s_waitcnt(0xF70);              // vmcnt(0)
+#pragma unroll
+        for (int t = 0; t < TT; ++t) a[t] = an[t];
+        __builtin_amdgcn_sched_barrier(0);
         const long r = blk * (16 * RW) + rq * 16 + lr;
         if (r < R) {
 #pragma unroll
             for (int c = 0; c < NT; ++c)
                 *reinterpret_cast<f32x4 *>(C + r * N + cq * NC + 16 * c + 4 * lg) = acc[c];
         }
-#pragma unroll
-        for (int t = 0; t < 4; ++t) a[t] = an[t];
     }
 }
 
@@ -3374,8 +3458,13 @@ void launch_gemm(long R, int Kd, int N, const real *A, const real *B, real *C, h
         if (Kd <= 64 && (N == 128 || N == 256 || N == 512)) {
             const size_t smr = sizeof(float) * 64 * (size_t)(N + 4);
             const long nblk = (R + 16 * (16 / (N / 128)) - 1) / (16 * (16 / (N / 128)));
-            hipLaunchKernelGGL((k_gemm_short_k<8>), dim3((unsigned)std::min<long>(nblk, 256)), dim3(1024), smr, st, R,
-                               Kd, N, A, B, C);
+            const dim3 grid((unsigned)std::min<long>(nblk, 256));
+            if (Kd == 64)
+                hipLaunchKernelGGL((k_gemm_short_k<8, 4>), grid, dim3(1024), smr, st, R, Kd, N, A, B, C);
+            else if (Kd == 16)
+                hipLaunchKernelGGL((k_gemm_short_k<8, 1>), grid, dim3(1024), smr, st, R, Kd, N, A, B, C);
+            else
+                hipLaunchKernelGGL((k_gemm_short_k<8, 0>), grid, dim3(1024), smr, st, R, Kd, N, A, B, C);
             return;
         }
         if (N <= 32) RRT_GEMM(2, 4, 4, 16)
@@ -3410,8 +3499,12 @@ bool launch_do2sh_f32(long R, int K, int NL, const float *A, const float *B, flo
         const size_t smr = sizeof(float) * (size_t)((K + 63) / 64 * 64) * (NT * 16 + 4);                     \
         if (smr <= 160 * 1024) {                                                                              \
             const long nb = (R + 256 * RT - 1) / (256 * RT);                                                  \
-            hipLaunchKernelGGL((k_do2sh_f32r<NT, RT>), dim3((unsigned)std::min<long>(nb, 256)), dim3(1024), smr, st, R, \
-                               K, NL, A, B, C);                                                              \
+            if (K % 64 == 0)                                                                                  \
+                hipLaunchKernelGGL((k_do2sh_f32r<NT, RT, true>), dim3((unsigned)std::min<long>(nb, 256)), dim3(1024), \
+                                   smr, st, R, K, NL, A, B, C);                                              \
+            else                                                                                              \
+                hipLaunchKernelGGL((k_do2sh_f32r<NT, RT, false>), dim3((unsigned)std::min<long>(nb, 256)), dim3(1024), \
+                                   smr, st, R, K, NL, A, B, C);                                              \
             return true;                                                                                      \
         }                                                                                                     \
     }
@@ -3904,11 +3997,17 @@ hipError_t set_lds_limits(size_t bytes)
                          reinterpret_cast<const void *>(&k_do2sh_f32<4, 1, 16>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<4, 2, 16>),
                          reinterpret_cast<const void *>(&k_do2sh_f32<4, 4, 4>),
-                         reinterpret_cast<const void *>(&k_do2sh_f32r<1, 1>),
-                         reinterpret_cast<const void *>(&k_do2sh_f32r<1, 2>),
-                         reinterpret_cast<const void *>(&k_do2sh_f32r<4, 1>),
-                         reinterpret_cast<const void *>(&k_do2sh_f32r<4, 2>),
-                         reinterpret_cast<const void *>(&k_gemm_short_k<8>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32r<1, 1, false>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32r<1, 1, true>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32r<1, 2, false>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32r<1, 2, true>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32r<4, 1, false>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32r<4, 1, true>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32r<4, 2, false>),
+                         reinterpret_cast<const void *>(&k_do2sh_f32r<4, 2, true>),
+                         reinterpret_cast<const void *>(&k_gemm_short_k<8, 0>),
+                         reinterpret_cast<const void *>(&k_gemm_short_k<8, 1>),
+                         reinterpret_cast<const void *>(&k_gemm_short_k<8, 4>),
                          reinterpret_cast<const void *>(&k_source_compton<double>)};
     for (const void *f : fns) {
         hipError_t e = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
