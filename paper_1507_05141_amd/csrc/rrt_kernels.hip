@@ -2416,6 +2416,26 @@ __global__ void __launch_bounds__(256) k_source_resid(SourceArgs<real> a, const 
     }
 }
 
+// sum of x over each row of 16 lanes, left in every lane of the row: four DPP moves
+// between registers (lane xor 1 and xor 2 within quads, then the mirrored lane of the
+// half row and of the row), no LDS traffic and no waits
+template <int CTRL>
+__device__ __forceinline__ double dpp_move(double x)
+{
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ double row16_sum(double x)
+{
+    x += dpp_move<0xB1>(x);                             // quad_perm [1, 0, 3, 2]
+    x += dpp_move<0x4E>(x);                             // quad_perm [2, 3, 0, 1]
+    x += dpp_move<0x141>(x);                            // row_half_mirror
+    x += dpp_move<0x140>(x);                            // row_mirror
+    return x;
+}
+
 // the same with four coefficients per lane (16-byte loads and stores; NL a multiple of 4 with
 // NL / 4 dividing 64): a wave takes 256 / NL rows
 template <typename real>
@@ -2459,9 +2479,14 @@ __global__ void __launch_bounds__(256) k_source_resid4(SourceArgs<real> a, const
                 aa += u * u;
             }
         }
-        for (int off = LR >> 1; off > 0; off >>= 1) {
-            dd += __shfl_xor(dd, off, 64);
-            aa += __shfl_xor(aa, off, 64);
+        if (LR == 16) {                                    // a row is one DPP row of 16 lanes
+            dd = row16_sum(dd);
+            aa = row16_sum(aa);
+        } else {
+            for (int off = LR >> 1; off > 0; off >>= 1) {
+                dd += __shfl_xor(dd, off, 64);
+                aa += __shfl_xor(aa, off, 64);
+            }
         }
         if (q0 == 0 && r < PG) {
             const long pp = r / G, g = r - pp * G;
@@ -2532,26 +2557,6 @@ __global__ void __launch_bounds__(256) k_source_compton(SourceArgs<real> a)
 // its own orders, after it has read them) and leave as 16-byte scaled stores.
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kComptonMfmaThreads = 512;
-
-// sum of x over each row of 16 lanes, left in every lane of the row: four DPP moves
-// between registers (lane xor 1 and xor 2 within quads, then the mirrored lane of the
-// half row and of the row), no LDS traffic and no waits
-template <int CTRL>
-__device__ __forceinline__ double dpp_move(double x)
-{
-    const long long b = __double_as_longlong(x);
-    const int lo = __builtin_amdgcn_mov_dpp((int)b, CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), CTRL, 0xF, 0xF, false);
-    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
-}
-__device__ __forceinline__ double row16_sum(double x)
-{
-    x += dpp_move<0xB1>(x);                             // quad_perm [1, 0, 3, 2]
-    x += dpp_move<0x4E>(x);                             // quad_perm [2, 3, 0, 1]
-    x += dpp_move<0x141>(x);                            // row_half_mirror
-    x += dpp_move<0x140>(x);                            // row_mirror
-    return x;
-}
 
 template <bool TEMP, bool RESID>
 __global__ void __launch_bounds__(kComptonMfmaThreads, TEMP ? 2 : 4)
