@@ -341,6 +341,27 @@ def test_full_size_thomson_jet_sweep_fp32():
     g.close()
 
 
+@pytest.mark.parametrize("lmax", [3, 5])
+def test_products_walking_many_row_blocks(lmax):
+    """At L <= 7 with 512 ordinates the SH <-> ordinate products run as one
+    persistent workgroup per compute unit that walks row blocks, loading the next
+    block's rows during the current one's products (S6 also across blocks).  On
+    a 16^3 x 40-group Thomson jet (163840 rows) every workgroup walks several
+    blocks: S2 ten of 64 rows (at L = 3 with whole 16-term rows, at L = 5 with
+    the guarded loads of 36 terms), S6 one to three of 256 or 512 rows.  One
+    FP32 sweep against the oracle, every output element."""
+    spec = W.thomson_jet(n=16, ng=40, lmax=lmax)
+    o, g = _both(spec, B.FP32)
+    S = o.initial_source()
+    ref_I, ref_Ilm, ref_S, _ = o.sweep(S, None, 0.0)
+    g.set_source_sh(S)
+    g.sweep()
+    close_by_group(g.sweep_intensity(), ref_I, 1e-5, 2, "I_lab")
+    close_by_group(g.intensity_sh(), ref_Ilm, 1e-5, 1, "I_lm")
+    close_by_group(g.source_sh(), ref_S, 1e-5, 1, "S_new")
+    g.close()
+
+
 @pytest.mark.parametrize("prec", [B.FP64, B.FP32], ids=["fp64", "fp32"])
 def test_frequency_integrated_moments_parity(prec):
     """Frequency-integrated J, H, K and f = K/J, reduced on the device in FP64,
