@@ -2099,9 +2099,12 @@ __global__ void __launch_bounds__(64 * W) k_do2sh_f16_dma(long R, int K, int Kp,
         float m = 0.f;
 #pragma unroll
         for (int i = 0; i < 8; ++i) m = fmaxf(m, fabsf(v[i]));
-        m = quad_max(m);
-        const bool grow = m * srow >= 32768.f || (srow == 0.f && m > 0.f);
-        if (__ballot(grow) != 0) {                      // wave-uniform: some row of this tile takes a new scale
+        // a row takes a new scale only if one of its four lanes' values asks for it, so
+        // the row maximum (two shuffles) is formed only when some lane does
+        const bool need = m * srow >= 32768.f || (srow == 0.f && m > 0.f);
+        if (__ballot(need) != 0) {                      // wave-uniform: some row of this tile takes a new scale
+            m = quad_max(m);
+            const bool grow = m * srow >= 32768.f || (srow == 0.f && m > 0.f);
             float f = 1.f;
             if (grow) {
                 float sn, in;
