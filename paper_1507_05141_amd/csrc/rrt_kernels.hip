@@ -1206,7 +1206,8 @@ __global__ void __launch_bounds__(kRemapThreads, 4) k_boost(BoostArgs<real> a)
             const int item = base + 64 * u + lane;
             pre[u] = P4{};
             if (a.Iprev && item < nit) {
-                const int kk = (int)(((float)item + 0.5f) * rIC), rem = item - kk * IC, q = rem / NC;
+                // (one point per workgroup: rem < NC, so q = 0 without the division)
+                const int kk = (int)(((float)item + 0.5f) * rIC), rem = item - __mul24(kk, IC), q = NPT == 1 ? 0 : rem / NC;
                 const int g0 = (rem - q * NC) * W;
                 if (p0 + q < a.P) {
                     const long o = ((long)(kb + kk) * a.P + p0 + q) * G + g0;
@@ -1265,8 +1266,8 @@ __global__ void __launch_bounds__(kRemapThreads, 4) k_boost(BoostArgs<real> a)
             for (int u = 0; u < 4; ++u) {
                 const int item = base + 64 * u + lane;
                 // every lane takes part in the shuffles (their source lanes are all active)
-                const int kk = min((int)(((float)item + 0.5f) * rIC), nk - 1), rem = item - kk * IC;
-                const int q = min(rem / NC, NPT - 1), g0 = (rem - q * NC) * W;
+                const int kk = min((int)(((float)item + 0.5f) * rIC), nk - 1), rem = item - __mul24(kk, IC);
+                const int q = NPT == 1 ? 0 : min(rem / NC, NPT - 1), g0 = (rem - q * NC) * W;
                 const int srcl = kk * NPT + q;
                 const real kp = __shfl(kapv, srcl, 64);
                 const int ab = __shfl(e.abs, srcl, 64);
@@ -1290,7 +1291,9 @@ __global__ void __launch_bounds__(kRemapThreads, 4) k_boost(BoostArgs<real> a)
                         out[0] = eu * tap_row(F + KS, tp);
                     } else if (a.fi.uniform) {
                         if (sh != kAllGhost) {
-                            auto A = [&](int gp) -> real { return tap_row(F + (min(max(gp, -1), G) + 1) * KS, tp); };
+                            auto A = [&](int gp) -> real {       // row index and stride < 2^24: the full-rate 24-bit product
+                                return tap_row(F + __umul24(min(max(gp, -1), G) + 1, KS), tp);
+                            };
                             real acur = A(g0 + sh);
 #pragma unroll
                             for (int i = 0; i < 4; ++i) {
@@ -1401,7 +1404,7 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_un
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int idx = i0 + u * T;
-                const int k = (int)(((float)idx + 0.5f) * rIC), rem = idx - k * IC, q = rem / G4;
+                const int k = (int)(((float)idx + 0.5f) * rIC), rem = idx - __mul24(k, IC), q = NPT == 1 ? 0 : rem / G4;
                 if (idx < n4 && q < np) {
                     const int g = (rem - q * G4) * 4;
                     v[u] = load_stream(a.Ilab + ((long)k * a.P + p0 + q) * G + g);
@@ -1410,7 +1413,7 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_un
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int idx = i0 + u * T;
-                const int k = (int)(((float)idx + 0.5f) * rIC), rem = idx - k * IC, q = rem / G4;
+                const int k = (int)(((float)idx + 0.5f) * rIC), rem = idx - __mul24(k, IC), q = NPT == 1 ? 0 : rem / G4;
                 if (idx < n4 && q < np) {
                     const int g = (rem - q * G4) * 4;
                     real *F = F0 + q * TS;
@@ -1438,7 +1441,7 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_un
         if (mv[q]) table_poles(F0 + q * TS, G, K, KS, a.nmu, a.nphi);
     __syncthreads();
     for (int idx = tid; idx < np * K; idx += T) {
-        const int q = idx / K, j = idx - q * K;
+        const int q = NPT == 1 ? 0 : idx / K, j = idx - q * K;   // one point per workgroup: idx < K
         const real *F = F0 + q * TS;
         real *__restrict__ out = a.I0 + (p0 + q) * G * K;
         if (!mv[q]) {
@@ -1454,7 +1457,9 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_un
             if (sh == kAllGhost) {
                 for (int g = 0; g < G; ++g) out[g * K + j] = real(0);
             } else {
-                auto A = [&](int gp) -> real { return tap_row(F + (min(max(gp, -1), G) + 1) * KS, tp); };
+                auto A = [&](int gp) -> real {   // row index and stride < 2^24: the full-rate 24-bit product
+                    return tap_row(F + __umul24(min(max(gp, -1), G) + 1, KS), tp);
+                };
                 real acur = A(sh);
                 for (int g = 0; g < G; ++g) {
                     const real anext = A(g + sh + 1);
