@@ -1112,6 +1112,13 @@ __device__ __forceinline__ Taps4<real> entry_taps(int abs, const real w[4], int 
     return t;
 }
 
+// x / d for 0 <= x < NPT d with NPT points per workgroup (1 or 2): no integer division
+template <int NPT>
+__device__ __forceinline__ int point_of(int x, int d)
+{
+    return NPT == 1 ? 0 : (NPT == 2 ? (int)(x >= d) : x / d);
+}
+
 // stage rows [g][j] of a point's ordinate values (n4 runs of four values,
 // K4 runs per row) into the table, four 16-byte loads per lane in flight
 template <typename real>
@@ -1207,7 +1214,7 @@ __global__ void __launch_bounds__(kRemapThreads, 4) k_boost(BoostArgs<real> a)
             pre[u] = P4{};
             if (a.Iprev && item < nit) {
                 // (one point per workgroup: rem < NC, so q = 0 without the division)
-                const int kk = (int)(((float)item + 0.5f) * rIC), rem = item - __mul24(kk, IC), q = NPT == 1 ? 0 : rem / NC;
+                const int kk = (int)(((float)item + 0.5f) * rIC), rem = item - __mul24(kk, IC), q = point_of<NPT>(rem, NC);
                 const int g0 = (rem - q * NC) * W;
                 if (p0 + q < a.P) {
                     const long o = ((long)(kb + kk) * a.P + p0 + q) * G + g0;
@@ -1267,7 +1274,8 @@ __global__ void __launch_bounds__(kRemapThreads, 4) k_boost(BoostArgs<real> a)
                 const int item = base + 64 * u + lane;
                 // every lane takes part in the shuffles (their source lanes are all active)
                 const int kk = min((int)(((float)item + 0.5f) * rIC), nk - 1), rem = item - __mul24(kk, IC);
-                const int q = NPT == 1 ? 0 : min(rem / NC, NPT - 1), g0 = (rem - q * NC) * W;
+                // (items past the last, clamped to the last ordinate, may have rem >= IC: point NPT - 1)
+                const int q = min(point_of<NPT>(rem, NC), NPT - 1), g0 = (rem - q * NC) * W;
                 const int srcl = kk * NPT + q;
                 const real kp = __shfl(kapv, srcl, 64);
                 const int ab = __shfl(e.abs, srcl, 64);
@@ -1404,7 +1412,7 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_un
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int idx = i0 + u * T;
-                const int k = (int)(((float)idx + 0.5f) * rIC), rem = idx - __mul24(k, IC), q = NPT == 1 ? 0 : rem / G4;
+                const int k = (int)(((float)idx + 0.5f) * rIC), rem = idx - __mul24(k, IC), q = point_of<NPT>(rem, G4);
                 if (idx < n4 && q < np) {
                     const int g = (rem - q * G4) * 4;
                     v[u] = load_stream(a.Ilab + ((long)k * a.P + p0 + q) * G + g);
@@ -1413,7 +1421,7 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_un
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
                 const int idx = i0 + u * T;
-                const int k = (int)(((float)idx + 0.5f) * rIC), rem = idx - __mul24(k, IC), q = NPT == 1 ? 0 : rem / G4;
+                const int k = (int)(((float)idx + 0.5f) * rIC), rem = idx - __mul24(k, IC), q = point_of<NPT>(rem, G4);
                 if (idx < n4 && q < np) {
                     const int g = (rem - q * G4) * 4;
                     real *F = F0 + q * TS;
@@ -1441,7 +1449,7 @@ __global__ void __launch_bounds__(kRemapThreads, sizeof(real) == 4 ? 8 : 4) k_un
         if (mv[q]) table_poles(F0 + q * TS, G, K, KS, a.nmu, a.nphi);
     __syncthreads();
     for (int idx = tid; idx < np * K; idx += T) {
-        const int q = NPT == 1 ? 0 : idx / K, j = idx - q * K;   // one point per workgroup: idx < K
+        const int q = point_of<NPT>(idx, K), j = idx - q * K;      // idx < NPT K
         const real *F = F0 + q * TS;
         real *__restrict__ out = a.I0 + (p0 + q) * G * K;
         if (!mv[q]) {
